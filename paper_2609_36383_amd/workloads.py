@@ -1,0 +1,199 @@
+"""Seeded synthetic workloads: run parameters and initial particle arrays.
+
+This module only draws inputs.  It holds none of the method's arithmetic (no
+deposit, shape, push or field solve), so both the GPU library and the independent
+CPU checker can be fed from it.
+
+Workloads (nondimensional units, kappa = sigma1 = sigma2 = rho0 = 1, q/m = -1,
+m = |q|, uniform immobile neutralizing background):
+
+  tsi1d     1D cold relativistic two-stream, 64 cells, L = 4 pi (k = 0.5), beams
+            u_x = +-1, 32 particles/cell/beam (4096), quiet start with a seeded 1e-3
+            weight perturbation at mode 1, dt = 0.1, 200 steps.
+  weibel2d  2D Weibel/filamentation, 128 x 128, dx = 0.2, beams u_z = +-0.5 with
+            Gaussian spread 0.01, 64 particles/cell (1,048,576), dt = 0.05, 500 steps.
+  mixed2d   2D two-stream/Weibel mixed, 512 x 512, dx = 0.2, beams u_x = +-1 with
+            spread 0.02, 256 particles/cell (67,108,864), dt = 0.05, 100 steps.
+  tsi1d_big 1D two-stream, 1024 cells, L = 64 pi, beams u_x = +-1, 1024 particles/
+            cell (1,048,576), 1e-3 weight perturbation at modes 1-8 with seeded
+            phases, dt = 0.1, 50 steps.
+  weibel3d  3D Weibel, 128^3, dx = 0.2, beams u_z = +-0.8 with spread 0.01,
+            32 particles/cell (67,108,864), dt = 0.05, 50 steps.
+
+Beam loading: 1D workloads use a quiet start (both beams share the positions
+x_j = lo + (j + 1/2) L / N_beam, weights carry the density perturbation).  2D and 3D
+workloads place ppc/2 symmetry-related pairs per cell at uniform random positions;
+the two members of a pair share the position and have opposite momenta
++-(u_d e + du), du ~ N(0, sigma^2 I), so the initial current and net momentum vanish.
+"""
+import math
+
+import numpy as np
+
+COMMON = dict(kappa=1.0, sigma1=1.0, sigma2=1.0)
+
+
+def _tol(fp32_bulk=False):
+    if fp32_bulk:
+        return dict(tol_outer_abs=1e-10, tol_outer_rel=1e-7, tol_inner_abs=1e-10, tol_inner_rel=1e-6)
+    return dict(tol_outer_abs=1e-14, tol_outer_rel=1e-12, tol_inner_abs=1e-14, tol_inner_rel=1e-12)
+
+
+WORKLOADS = {
+    "tsi1d": dict(kind="quiet1d", dim=1, n=(64,), dx=None, length=(4.0 * math.pi,), dt=0.1, steps=200,
+                  ppc=64, u_drift=1.0, eps=1e-3, modes=(1,), seed=1),
+    "weibel2d": dict(kind="pairs", dim=2, n=(128, 128), dx=0.2, dt=0.05, steps=500, ppc=64,
+                     drift_axis=2, u_drift=0.5, u_spread=0.01, seed=2),
+    "mixed2d": dict(kind="pairs", dim=2, n=(512, 512), dx=0.2, dt=0.05, steps=100, ppc=256,
+                    drift_axis=0, u_drift=1.0, u_spread=0.02, seed=3),
+    "tsi1d_big": dict(kind="quiet1d", dim=1, n=(1024,), dx=None, length=(64.0 * math.pi,), dt=0.1,
+                      steps=50, ppc=1024, u_drift=1.0, eps=1e-3, modes=tuple(range(1, 9)), seed=4),
+    "weibel3d": dict(kind="pairs", dim=3, n=(128, 128, 128), dx=0.2, dt=0.05, steps=50, ppc=32,
+                     drift_axis=2, u_drift=0.8, u_spread=0.01, seed=5),
+}
+
+
+def spec(name, **over):
+    """Workload description with optional overrides (e.g. a smaller n or ppc for tests)."""
+    w = dict(WORKLOADS[name])
+    w.update(over)
+    w["name"] = name
+    d = w["dim"]
+    if w["kind"] == "pairs":
+        w["length"] = tuple(w["n"][i] * w["dx"] for i in range(d))
+    w["lo"] = (0.0,) * d
+    w["n"] = tuple(int(v) for v in w["n"])
+    ncell = int(np.prod(w["n"]))
+    w["num_particles"] = ncell * int(w["ppc"])
+    return w
+
+
+def config_dict(w, fp32_bulk=False):
+    """Mesh, physics and solver settings of a workload as plain keyword values."""
+    d = dict(dim=w["dim"], n=tuple(w["n"]), lo=tuple(w["lo"]), length=tuple(w["length"]), dt=w["dt"])
+    d.update(COMMON)
+    d.update(_tol(fp32_bulk))
+    d.update(max_outer=80, max_inner=64, beta=1.0)
+    return d
+
+
+def particles(w):
+    """Initial arrays (x [d][N], u = p/(m kappa) [3][N], q [N]) of a workload."""
+    if w["kind"] == "quiet1d":
+        return _quiet1d(w)
+    return _pairs(w)
+
+
+def _quiet1d(w):
+    L = w["length"][0]
+    lo = w["lo"][0]
+    nb = w["n"][0] * w["ppc"] // 2
+    rng = np.random.default_rng(w["seed"])
+    theta = 2.0 * math.pi * rng.random(len(w["modes"]))
+    xj = lo + (np.arange(nb) + 0.5) * (L / nb)
+    u = np.zeros((3, 2 * nb))
+    u[0, :nb] = w["u_drift"]
+    u[0, nb:] = -w["u_drift"]
+    x = np.concatenate([xj, xj])[None, :]
+    if w.get("eig_gamma"):
+        return x, u, _eigen1d(w, xj, u)
+    pert = np.zeros(nb)
+    for mth, th in zip(w["modes"], theta):
+        pert += np.cos(2.0 * math.pi * mth / L * (xj - lo) + th)
+    wj = 0.5 * (L / nb) * (1.0 + w["eps"] * pert)
+    q = -np.concatenate([wj, wj])
+    return np.ascontiguousarray(x), u, q
+
+
+def _eigen1d(w, xj, u):
+    """Cold-fluid growing eigenmode of mode 1 for two equal electron beams (q/m = -1).
+
+    The caller supplies the growth rate ``eig_gamma`` and the field amplitude ``eig_E``
+    (E_x = eig_E sin(k x) after the field solve).  For beam s with drift s v0 and
+    w' = i Gamma - k s v0, linear cold-fluid theory gives the momentum perturbation
+    du = i (q/m) chi E / w' (chi = sinc(k dx / 2)^3 is the gathered-field factor) and
+    the relative density (weight) perturbation k (du / g0^3) / w'.  Modifies ``u`` in
+    place and returns the charges.
+    """
+    L = w["length"][0]
+    nb = xj.size
+    u0 = w["u_drift"]
+    g0 = math.sqrt(1.0 + u0 * u0)
+    v0 = u0 / g0
+    k = 2.0 * math.pi / L
+    z = 0.5 * k * L / w["n"][0]
+    chi = (math.sin(z) / z) ** 3
+    E1 = -1j * w["eig_E"]
+    phase = np.exp(1j * k * (xj - w["lo"][0]))
+    q = np.empty(2 * nb)
+    w0 = 0.5 * (L / nb)
+    for s, sl in ((1.0, slice(0, nb)), (-1.0, slice(nb, 2 * nb))):
+        wp = 1j * w["eig_gamma"] - k * s * v0
+        du = 1j * (-1.0) * chi * E1 / wp
+        dw = k * (du / g0 ** 3) / wp
+        u[0, sl] = s * u0 + np.real(du * phase)
+        q[sl] = -w0 * (1.0 + np.real(dw * phase))
+    return q
+
+
+def _pairs(w):
+    d = w["dim"]
+    n = w["n"]
+    ncell = int(np.prod(n))
+    npair = w["ppc"] // 2
+    dx = [w["length"][i] / n[i] for i in range(d)]
+    cellvol = float(np.prod(dx))
+    rng = np.random.default_rng(w["seed"])
+    cells = np.repeat(np.arange(ncell, dtype=np.int64), npair)
+    idx = []
+    rem = cells
+    for i in range(d):
+        idx.append(rem % n[i])
+        rem = rem // n[i]
+    xs = np.empty((d, 2 * cells.size))
+    for i in range(d):
+        pos = w["lo"][i] + (idx[i] + rng.random(cells.size)) * dx[i]
+        xs[i, 0::2] = pos
+        xs[i, 1::2] = pos
+    du = rng.normal(0.0, w["u_spread"], size=(3, cells.size))
+    du[w["drift_axis"]] += w["u_drift"]
+    u = np.empty((3, 2 * cells.size))
+    u[:, 0::2] = du
+    u[:, 1::2] = -du
+    q = np.full(2 * cells.size, -cellvol / w["ppc"])
+    return xs, u, q
+
+
+def random_fields(dim, n, length, seed, amp=1.0, modes=3):
+    """Smooth random periodic mesh arrays (sums of a few low Fourier modes), for tests.
+
+    Returns gradphi-like [d][Ng] and three [3][Ng] arrays drawn independently.
+    """
+    rng = np.random.default_rng(seed)
+    shape = tuple(n[i] for i in range(dim))
+    grids = np.meshgrid(*[np.arange(n[i]) * (length[i] / n[i]) for i in range(dim)], indexing="ij")
+
+    def one():
+        f = np.zeros(shape)
+        for _ in range(modes):
+            kk = [2.0 * math.pi * rng.integers(-2, 3) / length[i] for i in range(dim)]
+            ph = rng.random() * 2.0 * math.pi
+            arg = sum(kk[i] * grids[i] for i in range(dim)) + ph
+            f += amp * rng.normal() * np.cos(arg)
+        # node order: x fastest
+        return np.ascontiguousarray(np.transpose(f, axes=tuple(reversed(range(dim)))).ravel())
+
+    gphi = np.stack([one() for _ in range(dim)])
+    An = np.stack([one() for _ in range(3)])
+    Anp1 = np.stack([one() for _ in range(3)])
+    Uh = np.stack([one() for _ in range(3)])
+    return gphi, An, Anp1, Uh
+
+
+def random_particles(dim, n, length, num, seed, umax=1.0):
+    """Random positions in the box, momenta u in [-umax, umax]^3 and weights, for tests."""
+    rng = np.random.default_rng(seed)
+    x = np.stack([rng.random(num) * length[i] for i in range(dim)])
+    u = (2.0 * rng.random((3, num)) - 1.0) * umax
+    q = -(0.5 + rng.random(num)) * 0.01
+    return x, u, q

@@ -1,0 +1,155 @@
+"""Whole-step checks of the oracle: energy theorem, constraints, structural residuals,
+linear growth against closed-form theory, failure semantics and determinism."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle as O
+from oracle import closed_forms as CF
+from paper_2609_36383_amd import workloads as W
+
+
+def _run(w, steps, **cfg_over):
+    cfg = O.config_from_dict(W.config_dict(w), **cfg_over)
+    s = O.OracleSim(cfg)
+    x, u, q = W.particles(w)
+    s.load_particles(x, u, q)
+    s.initialize()
+    diags = [s.diagnostics()]
+    reps = []
+    for _ in range(steps):
+        st, r = s.step()
+        reps.append(r)
+        diags.append(s.diagnostics())
+    return s, diags, reps
+
+
+def test_tsi1d_eigenmode_growth_rate():
+    """Cold relativistic two-stream eigenmode: fitted rate over t in [0, 2] (the paper's
+    fit window) matches the finite-grid closed form."""
+    L, n = 4 * math.pi, 64
+    G = CF.gamma_two_stream(2 * math.pi / L, CF.v_of_u(1.0), L / n)
+    w = W.spec("tsi1d", eig_gamma=G, eig_E=0.01)
+    s, diags, reps = _run(w, 20)
+    cfg = s.cfg
+    ts, amps = [], []
+    s2 = O.OracleSim(cfg)
+    x, u, q = W.particles(w)
+    s2.load_particles(x, u, q)
+    s2.initialize()
+    ts.append(0.0)
+    amps.append(s2.mode_amplitude("E", 0, (1, 0, 0)))
+    for _ in range(20):
+        s2.step()
+        ts.append(s2.diagnostics()["t"])
+        amps.append(s2.mode_amplitude("E", 0, (1, 0, 0)))
+    rate = CF.fit_growth(ts, amps, 0.0, 2.0)
+    assert abs(rate / G - 1.0) < 5e-3
+    assert abs(amps[0] - 0.005) < 5e-5  # E_x = 0.01 sin(kx): positive-mode amplitude 0.005
+    assert max(d["energy_rel"] for d in diags) < 1e-11
+
+
+def test_tsi1d_energy_and_structure_50_steps():
+    w = W.spec("tsi1d")
+    s, diags, reps = _run(w, 50)
+    assert max(d["energy_rel"] for d in diags) < 1e-11  # 10x the nonlinear tolerance
+    assert max(d["gauss_rms"] for d in diags) < 1e-12
+    assert max(d["lorenz_rms"] for d in diags) < 1e-12
+    assert max(d["chain_rms"] for d in diags) < 1e-15
+    assert max(abs(d["work_residual"]) for d in diags) < 1e-15
+    assert max(d["vperp_rms"] for d in diags) == 0.0  # purely longitudinal
+    assert all(r["outer_iters"] < 20 for r in reps)
+    assert all(r["res_rms_ratio"] <= 1 and r["res_max_ratio"] <= 1 for r in reps)
+
+
+@pytest.mark.parametrize("name,over,steps", [
+    ("weibel2d", dict(n=(16, 16), ppc=8), 8),
+    ("mixed2d", dict(n=(16, 16), ppc=8), 8),
+    ("weibel3d", dict(n=(8, 8, 8), ppc=4), 4),
+])
+def test_small_multi_d_energy_and_structure(name, over, steps):
+    w = W.spec(name, **over)
+    s, diags, reps = _run(w, steps)
+    assert max(d["energy_rel"] for d in diags) < 1e-11
+    assert max(d["gauss_rms"] for d in diags) < 1e-11
+    assert max(d["lorenz_rms"] for d in diags) < 1e-11
+    assert max(d["chain_rms"] for d in diags) < 1e-15
+    assert max(abs(d["work_residual"]) for d in diags) < 1e-13
+
+
+def _state(s):
+    x, P, v = s.read_particles()
+    f = [s.read_field(k) for k in ("phi", "psi", "A", "U", "rho", "J")]
+    return [x, P, v] + f
+
+
+def _same(a, b):
+    return all(np.array_equal(p, q, equal_nan=True) for p, q in zip(a, b))
+
+
+def test_inner_failure_leaves_state_unchanged():
+    w = W.spec("weibel2d", n=(8, 8), ppc=4)
+    cfg = O.config_from_dict(W.config_dict(w))
+    s = O.OracleSim(cfg)
+    x, u, q = W.particles(w)
+    s.load_particles(x, u, q)
+    s.initialize()
+    s.step()
+    before = _state(s)
+    x0, P0, v0 = s.read_particles()
+    P0[1, 5] = np.nan
+    s.set_particle_state(x0, P0, v0)
+    before = _state(s)
+    st, rep = s.step(raise_on_error=False)
+    assert st == O.EINNER
+    assert _same(_state(s), before)
+
+
+def test_inner_limit_and_outer_limit():
+    w = W.spec("tsi1d")
+    base = W.config_dict(w)
+    # one inner iteration with an unreachable tolerance fails the inner solve
+    cfg = O.config_from_dict(base, max_inner=1, tol_inner_rel=0.0, tol_inner_abs=0.0)
+    s = O.OracleSim(cfg)
+    x, u, q = W.particles(w)
+    s.load_particles(x, u, q)
+    s.initialize()
+    before = _state(s)
+    st, _ = s.step(raise_on_error=False)
+    assert st == O.EINNER and _same(_state(s), before)
+    # one outer iteration cannot meet the outer tests
+    cfg = O.config_from_dict(base, max_outer=1)
+    s = O.OracleSim(cfg)
+    s.load_particles(x, u, q)
+    s.initialize()
+    before = _state(s)
+    st, rep = s.step(raise_on_error=False)
+    assert st == O.ENOCONV and rep["outer_iters"] == 1 and _same(_state(s), before)
+
+
+def test_invalid_config_rejected():
+    w = W.spec("tsi1d")
+    with pytest.raises(O.OracleError):
+        O.OracleSim(O.config_from_dict(W.config_dict(w), sigma1=2.0))  # sigma1 != kappa^2 sigma2
+    with pytest.raises(O.OracleError):
+        O.OracleSim(O.config_from_dict(W.config_dict(w), dt=0.0))
+
+
+def test_thread_count_does_not_change_results():
+    w = W.spec("weibel2d", n=(16, 16), ppc=8)
+    outs = []
+    for th in (1, 4):
+        s, diags, reps = _run(w, 3, threads=th)
+        outs.append(_state(s))
+    assert _same(outs[0], outs[1])
+
+
+def test_damped_outer_iteration_reaches_same_fixed_point():
+    w = W.spec("tsi1d")
+    s1, d1, r1 = _run(w, 5)
+    s2, d2, r2 = _run(w, 5, beta=0.7)
+    x1, P1, _ = s1.read_particles()
+    x2, P2, _ = s2.read_particles()
+    assert np.abs(x1 - x2).max() < 1e-10 and np.abs(P1 - P2).max() < 1e-10
+    assert sum(r["outer_iters"] for r in r2) > sum(r["outer_iters"] for r in r1)
