@@ -1,0 +1,204 @@
+"""Benchmark of the GM-HC-CN implicit step on one MI355X.
+
+Workload (default): 2D Weibel/filamentation, 128 x 128 periodic mesh, dx = 0.2,
+64 particles per cell (1,048,576 electrons), beams u_z = +-0.5 with spread 0.01,
+dt = 0.05, quadratic shapes, FP64, nonlinear tolerances 1e-12 (relative) / 1e-14
+(absolute).  Inputs are seeded synthetic arrays, resident in HBM before timing.
+
+One timed step is one full implicit Crank-Nicolson step (all outer iterations, each
+with the field solve, the orbit pass with its inner Picard loop and the deposit).
+`value` counts particle orbit evaluations (one particle through one Picard
+iteration of the orbit pass) per second of wall time over the timed steps.
+
+The JSON line also carries the roofline of the dominant kernel (the orbit pass) from
+its HIP-event timed launches, and the CPU oracle's rate on a bounded sample.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "particle-steps/s per Picard iter (FP64 vs FP32-bulk) at ΔE/E≤1e-6; %HBM peak"
+PEAK_HBM_GBS = 8000.0
+PEAK_FP64_VALU_TFLOPS = 78.6
+
+
+def flops_per_eval(d, seg_mean, ngl):
+    """Algorithmic flops of one orbit evaluation (FMA = 2).
+
+    Per Gauss-Legendre point: 1D weights and derivatives (10 per axis), the time blend
+    (3), and per stencil node (3^d): tensor weights d-1 + d(d-1), grad-phi gather 2d,
+    D gather 3(3 + 2d), quadrature weight 1.  Per evaluation add the endpoint
+    interpolant A^+ (3^d (d - 1 + 6) + 6d) and the push, HC rotation, secant velocity
+    and inner test (250).
+    """
+    node = (d - 1) + d * (d - 1) + 2 * d + 3 * (3 + 2 * d) + 1
+    point = 10 * d + 3 + (3 ** d) * node
+    endpoint = (3 ** d) * (d - 1 + 6) + 6 * d
+    return seg_mean * ngl * point + endpoint + 250
+
+
+def deposit_flops(d, seg_mean, ngl):
+    """Flops of the deposit sweep (once per converged particle per launch)."""
+    point = 10 * d + (3 ** d) * d
+    return seg_mean * ngl * point + (3 ** d) * (3 * 2 + 3 * 2)
+
+
+def bytes_per_particle(d):
+    """Algorithmic HBM bytes per particle per orbit launch (FP64): read x, P, q, v_in;
+    write v_out, x^{n+1}, P^{n+1}."""
+    return 8 * d + 24 + 8 + 24 + 24 + 8 * d + 24
+
+
+def bytes_per_node(d):
+    """Mesh bytes per node per launch: read grad phi (d), A^n, A^{n+1}, U (9);
+    read-modify-write of the deposited current (3)."""
+    return 8 * (d + 9) + 8 * 3 * 2
+
+
+def cpu_baseline(w, cfg_dict, ngl, target_s=12.0):
+    """The oracle's orbit pass (inner Picard loop, same GL order as the GPU) on a
+    bounded leading sample of the workload's particles at the first trial fields."""
+    import numpy as np
+
+    import oracle as O
+    from paper_2609_36383_amd import workloads as W
+
+    x, u, q = W.particles(w)
+    cfg = O.config_from_dict(cfg_dict, gl_order=ngl)
+    full = O.OracleSim(cfg)
+    full.load_particles(x, u, q)
+    full.initialize()
+    fields = full.trial_fields(full.read_field("J"))
+    xf, Pf, vf = full.read_particles()
+    del full
+
+    def run(ns):
+        s = O.OracleSim(cfg)
+        s.load_particles(x[:, :ns], u[:, :ns], q[:ns])
+        s.set_particle_state(xf[:, :ns], Pf[:, :ns], vf[:, :ns])
+        t0 = time.perf_counter()
+        r = s.orbit_pass(*fields, vf[:, :ns], iterate=True)
+        dt = time.perf_counter() - t0
+        return int(r["iters"].sum()), dt
+
+    ns = 8192
+    ev, dt = run(ns)
+    ns = int(min(q.size, max(ns, ns * target_s / max(dt, 1e-3))))
+    ev, dt = run(ns)
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {"value": ev / dt, "unit": "particle-iterations/s", "cores": threads, "kind": "oracle",
+            "sample": f"oracle orbit pass with inner Picard loop, GL{ngl} per knot segment, on the first "
+                      f"{ns} of {q.size} particles of the workload at its first trial fields "
+                      f"({ev} evaluations in {dt:.2f} s)"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="weibel2d")
+    ap.add_argument("--sort-every", type=int, default=10)
+    ap.add_argument("--gl-order", type=int, default=0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: this build runs the orbit pass on a single MI355X "
+              "(multi-GPU sharding is not implemented); use --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_2609_36383_amd import gmhc as G
+    from paper_2609_36383_amd import workloads as W
+
+    w = W.spec(args.workload)
+    base = W.config_dict(w)
+    ngl = args.gl_order if args.gl_order else w["dim"] + 1
+    cfg = G.config_from_dict(base, gl_order=ngl, sort_every=args.sort_every, timing=1)
+    x, u, q = W.particles(w)
+    npart = q.size
+    sim = G.Simulation(cfg, npart, device="cuda:0")
+    sim.load_particles(x, u, q)
+    sim.initialize()
+    for _ in range(args.warmup):
+        sim.step()
+    torch.cuda.synchronize()
+    evals = 0
+    orbit_ms = 0.0
+    launches = 0
+    outer = 0
+    segs = 0
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        st, rep = sim.step()
+        evals += rep["evaluations"]
+        orbit_ms += rep["orbit_ms"]
+        launches += rep["orbit_launches"]
+        outer += rep["outer_iters"]
+        segs += rep["segments"]
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    diag = sim.diagnostics()
+
+    d = w["dim"]
+    ng = int(np.prod(w["n"]))
+    seg_mean = segs / max(evals, 1)  # measured knot-split segments per evaluation
+    per_launch_evals = evals / max(launches, 1)
+    per_launch_conv = npart
+    flops_launch = per_launch_evals * flops_per_eval(d, seg_mean, ngl) + \
+        per_launch_conv * deposit_flops(d, seg_mean, ngl)
+    bytes_launch = npart * bytes_per_particle(d) + ng * bytes_per_node(d)
+    launch_s = (orbit_ms / max(launches, 1)) * 1e-3
+    achieved_tflops = flops_launch / launch_s / 1e12
+    achieved_gbs = bytes_launch / launch_s / 1e9
+    out = {
+        "metric": METRIC,
+        "value": evals / elapsed,
+        "unit": "particle-iterations/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": elapsed * 1e3 / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"{args.workload}: {'x'.join(map(str, w['n']))} mesh, {npart} particles, "
+                               f"{w['ppc']} per cell, dt {w['dt']}, GL{ngl} per knot segment",
+                   "global_batch": npart, "seq_len": None, "parallelism": "single GPU"},
+        "particle_steps_per_s": npart * args.steps / elapsed,
+        "outer_iters_mean": outer / args.steps,
+        "evaluations_per_particle_step": evals / (npart * args.steps),
+        "energy_drift": diag["energy_rel"],
+        "segments_per_evaluation": seg_mean,
+        "roofline": {
+            "bound": "alu",
+            "achieved": achieved_tflops,
+            "peak": PEAK_FP64_VALU_TFLOPS,
+            "unit": "TFLOP/s",
+            "frac": achieved_tflops / PEAK_FP64_VALU_TFLOPS,
+            "traffic": None,
+            "kernel": f"k_orbit<{d}>",
+            "launch_ms": launch_s * 1e3,
+            "flops_per_launch": flops_launch,
+            "hbm_bytes_per_launch": bytes_launch,
+            "hbm_achieved_gbs": achieved_gbs,
+            "hbm_frac": achieved_gbs / PEAK_HBM_GBS,
+        },
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(w, base, ngl)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

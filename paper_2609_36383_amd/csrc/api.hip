@@ -1,0 +1,930 @@
+// api.hip -- the C ABI of libgmhc (include/gmhc.h): context, workspace carving, the
+// outer current iteration of the implicit step (Algorithm 1 with damped Picard on
+// the mesh current), initialization, diagnostics and read-outs.
+#include <math.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <string>
+#include <vector>
+
+#include "../../include/gmhc.h"
+#include "gmhc_internal.h"
+
+using namespace gmhc;
+
+struct gmhc_ctx {
+  gmhc_config cfg;
+  Mesh M;
+  int ngl = 0;
+  double glx[kMaxGL], glw[kMaxGL];
+  int64_t np = 0;
+  hipStream_t stream = nullptr;
+  int device = 0;
+  char* ws = nullptr;
+  size_t ws_bytes = 0;
+  bool bound = false, loaded = false, initialized = false, have_pot = false, frozen = false,
+       pass_done = false;
+  // particles (sorted order), SoA
+  double* x[3] = {};
+  double* x2[3] = {};
+  double* P[3] = {};
+  double* P2[3] = {};
+  double* q = nullptr;
+  double* q2 = nullptr;
+  double* vb[3] = {};   // accepted orbit-velocity iterate (warm start)
+  double* vw[3] = {};   // working iterate of the current step / last frozen pass
+  double* pscr[3] = {}; // read-out scratch
+  int32_t* id = nullptr;
+  int32_t* id2 = nullptr;
+  int32_t* iters = nullptr;
+  int32_t* key = nullptr;
+  // mesh
+  double* An = nullptr;     // [3][Ng] real A^n
+  double* trial = nullptr;  // [d+6][Ng] real: grad phi^{n+1/2}, A^{n+1}, U^{n+1/2}
+  double* Jdep = nullptr;   // [3][Ng]
+  double* jr[3] = {};       // real current slots [3][Ng]; slot 0 = accepted J^{n-1/2}
+  double2* jh[3] = {};      // spectral current slots
+  double2* S0 = nullptr;    // accepted spectral state [9][Ng]: phi psi rho A(3) U(3)
+  double2* S1 = nullptr;    // trial spectral state
+  double2* cout = nullptr;  // [9][Ng] complex scratch (CN outputs, FFT work)
+  double2* cscr = nullptr;  // [9][Ng] complex scratch
+  double* rscr = nullptr;   // [9][Ng] real scratch
+  int32_t* count = nullptr;
+  int32_t* cursor = nullptr;
+  void* scan_tmp = nullptr;
+  size_t scan_tmp_bytes = 0;
+  double* partials = nullptr;
+  int64_t max_blocks = 0;
+  double* dres = nullptr;   // device results [32]
+  double* hres = nullptr;   // pinned host results [32]
+  double2* tw[3] = {};
+  FftPlanAxis axes[3];
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  // bookkeeping
+  double t = 0.0;
+  int64_t step = 0;
+  double E0 = 0.0;
+  double last_chain = 0.0, last_work = 0.0, last_rr = 0.0, last_mr = 0.0;
+  gmhc_pass_report last_pass{};
+  std::string err;
+};
+
+namespace {
+
+const int kResOff = 16;  // offset of residual results in dres
+
+int32_t fail(gmhc_ctx* c, int32_t st, const std::string& msg) {
+  if (c) c->err = msg;
+  return st;
+}
+
+#define HIPCK(expr)                                                                  \
+  do {                                                                               \
+    hipError_t e_ = (expr);                                                          \
+    if (e_ != hipSuccess)                                                            \
+      return fail(ctx, GMHC_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+// Gauss-Legendre nodes and weights on [0,1]: Newton on P_n in long double.
+void gl01(int n, double* x, double* w) {
+  const long double pi = 3.141592653589793238462643383279502884L;
+  for (int i = 0; i < n; ++i) {
+    long double z = cosl(pi * (n - i - 0.25L) / (n + 0.5L));  // ascending order
+    long double dp = 1.0L;
+    for (int it = 0; it < 100; ++it) {
+      long double p1 = 1.0L, p2 = 0.0L;
+      for (int k = 1; k <= n; ++k) {
+        long double p3 = p2;
+        p2 = p1;
+        p1 = ((2.0L * k - 1.0L) * z * p2 - (k - 1.0L) * p3) / k;
+      }
+      dp = n * (z * p1 - p2) / (z * z - 1.0L);
+      long double dz = p1 / dp;
+      z -= dz;
+      if (fabsl(dz) < 1e-19L) break;
+    }
+    long double p1 = 1.0L, p2 = 0.0L;
+    for (int k = 1; k <= n; ++k) {
+      long double p3 = p2;
+      p2 = p1;
+      p1 = ((2.0L * k - 1.0L) * z * p2 - (k - 1.0L) * p3) / k;
+    }
+    dp = n * (z * p1 - p2) / (z * z - 1.0L);
+    x[i] = (double)(0.5L * (1.0L + z));
+    w[i] = (double)(1.0L / ((1.0L - z * z) * dp * dp));
+  }
+}
+
+int ilog2(int n) {
+  int l = 0;
+  while ((1 << l) < n) ++l;
+  return l;
+}
+
+struct Carver {
+  char* base;
+  size_t off = 0;
+  template <class T>
+  T* take(size_t count) {
+    off = (off + 255) & ~(size_t)255;
+    T* p = base ? reinterpret_cast<T*>(base + off) : nullptr;
+    off += sizeof(T) * count;
+    return p;
+  }
+};
+
+// Lay out every device buffer; with base == nullptr only the size is computed.
+size_t carve(gmhc_ctx* c, char* base, int64_t np) {
+  Carver cv{base};
+  const int d = c->M.d;
+  const int64_t Ng = c->M.Ng;
+  const size_t N = (size_t)std::max<int64_t>(np, 1);
+  for (int l = 0; l < 3; ++l) {
+    c->x[l] = (l < d) ? cv.take<double>(N) : nullptr;
+    c->x2[l] = (l < d) ? cv.take<double>(N) : nullptr;
+  }
+  for (int l = 0; l < 3; ++l) {
+    c->P[l] = cv.take<double>(N);
+    c->P2[l] = cv.take<double>(N);
+    c->vb[l] = cv.take<double>(N);
+    c->vw[l] = cv.take<double>(N);
+    c->pscr[l] = cv.take<double>(N);
+  }
+  c->q = cv.take<double>(N);
+  c->q2 = cv.take<double>(N);
+  c->id = cv.take<int32_t>(N);
+  c->id2 = cv.take<int32_t>(N);
+  c->iters = cv.take<int32_t>(N);
+  c->key = cv.take<int32_t>(N);
+  c->An = cv.take<double>(3 * Ng);
+  c->trial = cv.take<double>((size_t)(d + 6) * Ng);
+  c->Jdep = cv.take<double>(3 * Ng);
+  for (int s = 0; s < 3; ++s) {
+    c->jr[s] = cv.take<double>(3 * Ng);
+    c->jh[s] = cv.take<double2>(3 * Ng);
+  }
+  c->S0 = cv.take<double2>(9 * Ng);
+  c->S1 = cv.take<double2>(9 * Ng);
+  c->cout = cv.take<double2>(9 * Ng);
+  c->cscr = cv.take<double2>(9 * Ng);
+  c->rscr = cv.take<double>(9 * Ng);
+  c->count = cv.take<int32_t>(Ng + 1);
+  c->cursor = cv.take<int32_t>(Ng + 1);
+  c->scan_tmp_bytes = sort_scan_tmp_bytes(Ng);
+  c->scan_tmp = cv.take<char>(c->scan_tmp_bytes);
+  c->max_blocks = std::max<int64_t>((np + kBlock - 1) / kBlock, 1024);
+  c->partials = cv.take<double>((size_t)(c->max_blocks + 1024) * 8);
+  c->dres = cv.take<double>(64);
+  for (int l = 0; l < d; ++l) c->tw[l] = cv.take<double2>(std::max(c->M.n[l] / 2, 1));
+  return (cv.off + 255) & ~(size_t)255;
+}
+
+struct DevGuard {
+  int old = -1;
+  explicit DevGuard(int dev) {
+    if (hipGetDevice(&old) != hipSuccess) old = -1;
+    if (old != dev) (void)hipSetDevice(dev);
+  }
+  ~DevGuard() {
+    if (old >= 0) (void)hipSetDevice(old);
+  }
+};
+
+hipMemcpyKind kind_of(int32_t ptr_kind, bool to_device) {
+  if (ptr_kind == GMHC_DEVICE) return hipMemcpyDeviceToDevice;
+  return to_device ? hipMemcpyHostToDevice : hipMemcpyDeviceToHost;
+}
+
+OrbitArgs orbit_args(gmhc_ctx* c, int iterate) {
+  OrbitArgs a{};
+  a.M = c->M;
+  a.np = c->np;
+  a.dt = c->cfg.dt;
+  a.kappa = c->cfg.kappa;
+  a.tol_abs = c->cfg.tol_inner_abs;
+  a.tol_rel = c->cfg.tol_inner_rel;
+  a.max_inner = c->cfg.max_inner;
+  a.iterate = iterate;
+  a.deposit = 1;
+  a.ngl = c->ngl;
+  for (int k = 0; k < kMaxGL; ++k) {
+    a.glx[k] = c->glx[k];
+    a.glw[k] = c->glw[k];
+  }
+  const int d = c->M.d;
+  const int64_t Ng = c->M.Ng;
+  for (int l = 0; l < 3; ++l) {
+    a.x[l] = c->x[l];
+    a.xn[l] = c->x2[l];
+    a.P[l] = c->P[l];
+    a.Pn[l] = c->P2[l];
+    a.v[l] = c->vw[l];
+    a.gphi[l] = (l < d) ? c->trial + (int64_t)l * Ng : nullptr;
+    a.An[l] = c->An + (int64_t)l * Ng;
+    a.Anp1[l] = c->trial + (int64_t)(d + l) * Ng;
+    a.Uh[l] = c->trial + (int64_t)(d + 3 + l) * Ng;
+    a.J[l] = c->Jdep + (int64_t)l * Ng;
+  }
+  a.q = c->q;
+  a.iters = c->iters;
+  a.partials = c->partials;
+  return a;
+}
+
+// Orbit pass + first-level reduction to dres[0..7]; optional HIP-event timing.
+int32_t run_orbit(gmhc_ctx* ctx, int iterate, double* ms) {
+  OrbitArgs a = orbit_args(ctx, iterate);
+  HIPCK(hipMemsetAsync(ctx->Jdep, 0, sizeof(double) * 3 * ctx->M.Ng, ctx->stream));
+  if (ctx->cfg.timing) HIPCK(hipEventRecord(ctx->ev0, ctx->stream));
+  HIPCK(launch_orbit(a, ctx->ngl, ctx->stream));
+  if (ctx->cfg.timing) HIPCK(hipEventRecord(ctx->ev1, ctx->stream));
+  const int nb = (int)((ctx->np + kBlock - 1) / kBlock);
+  if (nb > 0) {
+    HIPCK(launch_reduce(ctx->partials, nb, kOrbitParts, kOrbitParts, 1u << OP_ITMAX, ctx->dres,
+                        ctx->stream));
+  } else {
+    HIPCK(hipMemsetAsync(ctx->dres, 0, sizeof(double) * kOrbitParts, ctx->stream));
+  }
+  (void)ms;
+  return GMHC_OK;
+}
+
+int res_blocks(const gmhc_ctx* c) {
+  return (int)std::min<int64_t>((c->M.Ng + kBlock - 1) / kBlock, 1024);
+}
+
+int32_t fetch_results(gmhc_ctx* ctx, double* orbit_ms) {
+  HIPCK(hipMemcpyAsync(ctx->hres, ctx->dres, sizeof(double) * 32, hipMemcpyDeviceToHost, ctx->stream));
+  HIPCK(hipStreamSynchronize(ctx->stream));
+  if (ctx->cfg.timing && orbit_ms) {
+    float f = 0.0f;
+    HIPCK(hipEventElapsedTime(&f, ctx->ev0, ctx->ev1));
+    *orbit_ms += (double)f;
+  }
+  return GMHC_OK;
+}
+
+int32_t sort_particles(gmhc_ctx* ctx) {
+  SortArgs a{};
+  a.M = ctx->M;
+  a.np = ctx->np;
+  int k = 0;
+  const int d = ctx->M.d;
+  for (int l = 0; l < d; ++l) {
+    a.src[k] = ctx->x[l];
+    a.dst[k++] = ctx->x2[l];
+  }
+  for (int l = 0; l < 3; ++l) {
+    a.src[k] = ctx->P[l];
+    a.dst[k++] = ctx->P2[l];
+  }
+  for (int l = 0; l < 3; ++l) {
+    a.src[k] = ctx->vb[l];
+    a.dst[k++] = ctx->vw[l];
+  }
+  a.src[k] = ctx->q;
+  a.dst[k++] = ctx->q2;
+  a.ncomp = k;
+  a.id_src = ctx->id;
+  a.id_dst = ctx->id2;
+  for (int l = 0; l < d; ++l) a.x[l] = ctx->x[l];
+  a.key = ctx->key;
+  a.count = ctx->count;
+  a.cursor = ctx->cursor;
+  HIPCK(sort_by_cell(a, ctx->scan_tmp, ctx->scan_tmp_bytes, ctx->stream));
+  for (int l = 0; l < d; ++l) std::swap(ctx->x[l], ctx->x2[l]);
+  for (int l = 0; l < 3; ++l) {
+    std::swap(ctx->P[l], ctx->P2[l]);
+    std::swap(ctx->vb[l], ctx->vw[l]);
+  }
+  std::swap(ctx->q, ctx->q2);
+  std::swap(ctx->id, ctx->id2);
+  return GMHC_OK;
+}
+
+// Real-space read-out of accepted field `which` into rscr; returns ncomp.
+int32_t field_to_rscr(gmhc_ctx* ctx, int32_t which, int* ncomp) {
+  const int64_t Ng = ctx->M.Ng;
+  double2* S = ctx->S0;
+  const double2* src = nullptr;
+  int nc = 1;
+  switch (which) {
+    case GMHC_PHI: src = S; break;
+    case GMHC_PSI: src = S + Ng; break;
+    case GMHC_RHO: src = S + 2 * Ng; break;
+    case GMHC_A:
+      HIPCK(hipMemcpyAsync(ctx->rscr, ctx->An, sizeof(double) * 3 * Ng, hipMemcpyDeviceToDevice, ctx->stream));
+      *ncomp = 3;
+      return GMHC_OK;
+    case GMHC_U: src = S + 6 * Ng; nc = 3; break;
+    case GMHC_J:
+      HIPCK(hipMemcpyAsync(ctx->rscr, ctx->jr[0], sizeof(double) * 3 * Ng, hipMemcpyDeviceToDevice, ctx->stream));
+      *ncomp = 3;
+      return GMHC_OK;
+    case GMHC_E:
+    case GMHC_B:
+      HIPCK(launch_spec_field(ctx->M, which == GMHC_E, S, S + 3 * Ng, S + 6 * Ng, ctx->cscr, ctx->stream));
+      src = ctx->cscr;
+      nc = 3;
+      break;
+    default: return fail(ctx, GMHC_EINVAL, "unknown field selector");
+  }
+  HIPCK(fft_nd(ctx->M, ctx->axes, nc, nullptr, src, nullptr, ctx->rscr, ctx->cout, true, false, ctx->stream));
+  *ncomp = nc;
+  return GMHC_OK;
+}
+
+int ncomp_of(int32_t which) {
+  return (which == GMHC_PHI || which == GMHC_PSI || which == GMHC_RHO) ? 1 : 3;
+}
+
+}  // namespace
+
+extern "C" {
+
+int32_t gmhc_abi_version(void) { return GMHC_ABI_VERSION; }
+
+const char* gmhc_status_str(int32_t s) {
+  switch (s) {
+    case GMHC_OK: return "ok";
+    case GMHC_EINVAL: return "invalid argument";
+    case GMHC_ESTATE: return "call out of order";
+    case GMHC_ENOMEM: return "workspace too small";
+    case GMHC_EDEVICE: return "HIP runtime error";
+    case GMHC_EINNER: return "particle inner solve failed";
+    case GMHC_ENOCONV: return "outer iteration did not converge";
+    default: return "unknown status";
+  }
+}
+
+const char* gmhc_last_error(const gmhc_ctx* ctx) { return ctx ? ctx->err.c_str() : ""; }
+
+int32_t gmhc_create(const gmhc_config* cfg, gmhc_ctx** out) {
+  if (!cfg || !out) return GMHC_EINVAL;
+  *out = nullptr;
+  const gmhc_config& c = *cfg;
+  if (c.dim < 1 || c.dim > 3) return GMHC_EINVAL;
+  for (int l = 0; l < c.dim; ++l) {
+    const int n = c.n[l];
+    if (n < 4 || n > 4096 || (n & (n - 1)) != 0) return GMHC_EINVAL;
+    if (!(c.len[l] > 0.0) || !isfinite(c.lo[l])) return GMHC_EINVAL;
+  }
+  if (!(c.dt > 0.0) || !(c.kappa > 0.0) || !(c.sigma1 > 0.0) || !(c.sigma2 > 0.0)) return GMHC_EINVAL;
+  if (fabs(c.sigma1 - c.kappa * c.kappa * c.sigma2) > 1e-14 * fabs(c.sigma1)) return GMHC_EINVAL;
+  if (c.gl_order < 0 || c.gl_order > kMaxGL) return GMHC_EINVAL;
+  if (c.precision != GMHC_FP64) return GMHC_EINVAL;  // FP32-bulk selected elsewhere
+  if (c.max_outer < 1 || c.max_inner < 1 || !(c.beta > 0.0 && c.beta <= 1.0)) return GMHC_EINVAL;
+  if (c.tol_outer_abs < 0 || c.tol_outer_rel < 0 || c.tol_inner_abs < 0 || c.tol_inner_rel < 0)
+    return GMHC_EINVAL;
+  gmhc_ctx* ctx = new gmhc_ctx();
+  ctx->cfg = c;
+  Mesh& M = ctx->M;
+  M.d = c.dim;
+  M.Ng = 1;
+  M.dV = 1.0;
+  for (int l = 0; l < 3; ++l) {
+    const bool r = l < c.dim;
+    M.n[l] = r ? c.n[l] : 1;
+    M.lo[l] = r ? c.lo[l] : 0.0;
+    M.len[l] = r ? c.len[l] : 1.0;
+    M.h[l] = M.len[l] / M.n[l];
+    M.inv_h[l] = 1.0 / M.h[l];
+    M.Ng *= M.n[l];
+    if (r) M.dV *= M.h[l];
+  }
+  ctx->ngl = c.gl_order ? c.gl_order : c.dim + 1;
+  for (int k = 0; k < kMaxGL; ++k) ctx->glx[k] = ctx->glw[k] = 0.0;
+  gl01(ctx->ngl, ctx->glx, ctx->glw);
+  *out = ctx;
+  return GMHC_OK;
+}
+
+void gmhc_destroy(gmhc_ctx* ctx) {
+  if (!ctx) return;
+  if (ctx->bound) {
+    DevGuard g(ctx->device);
+    (void)hipStreamSynchronize(ctx->stream);
+    if (ctx->hres) (void)hipHostFree(ctx->hres);
+    if (ctx->ev0) (void)hipEventDestroy(ctx->ev0);
+    if (ctx->ev1) (void)hipEventDestroy(ctx->ev1);
+  }
+  delete ctx;
+}
+
+int32_t gmhc_workspace_bytes(const gmhc_ctx* ctx, int64_t n_particles, size_t* bytes) {
+  if (!ctx || !bytes || n_particles < 0 || n_particles > INT32_MAX) return GMHC_EINVAL;
+  gmhc_ctx tmp;
+  tmp.cfg = ctx->cfg;
+  tmp.M = ctx->M;
+  *bytes = carve(&tmp, nullptr, n_particles);
+  return GMHC_OK;
+}
+
+int32_t gmhc_bind(gmhc_ctx* ctx, int64_t n_particles, void* dev_workspace, size_t bytes,
+                  void* hip_stream) {
+  if (!ctx) return GMHC_EINVAL;
+  if (ctx->bound) return fail(ctx, GMHC_ESTATE, "context already bound");
+  if (n_particles < 0 || n_particles > INT32_MAX || !dev_workspace)
+    return fail(ctx, GMHC_EINVAL, "bad particle count or workspace");
+  size_t need = carve(ctx, nullptr, n_particles);
+  if (bytes < need) return fail(ctx, GMHC_ENOMEM, "workspace smaller than gmhc_workspace_bytes");
+  if ((reinterpret_cast<uintptr_t>(dev_workspace) & 255) != 0)
+    return fail(ctx, GMHC_EINVAL, "workspace must be 256-byte aligned");
+  HIPCK(hipGetDevice(&ctx->device));
+  ctx->stream = static_cast<hipStream_t>(hip_stream);
+  ctx->ws = static_cast<char*>(dev_workspace);
+  ctx->ws_bytes = bytes;
+  ctx->np = n_particles;
+  carve(ctx, ctx->ws, n_particles);
+  HIPCK(hipHostMalloc(reinterpret_cast<void**>(&ctx->hres), sizeof(double) * 64, hipHostMallocDefault));
+  HIPCK(hipEventCreate(&ctx->ev0));
+  HIPCK(hipEventCreate(&ctx->ev1));
+  // FFT plans and twiddles exp(-2 pi i m / N)
+  const long double pi = 3.141592653589793238462643383279502884L;
+  int64_t stride = 1;
+  for (int l = 0; l < ctx->M.d; ++l) {
+    const int N = ctx->M.n[l];
+    std::vector<double2> tw(std::max(N / 2, 1));
+    for (int m = 0; m < N / 2; ++m) {
+      long double ang = -2.0L * pi * m / N;
+      tw[m] = make_double2((double)cosl(ang), (double)sinl(ang));
+    }
+    HIPCK(hipMemcpy(ctx->tw[l], tw.data(), sizeof(double2) * tw.size(), hipMemcpyHostToDevice));
+    FftPlanAxis& ax = ctx->axes[l];
+    ax.N = N;
+    ax.logN = ilog2(N);
+    ax.stride = stride;
+    ax.nlines = ctx->M.Ng / N;
+    ax.T = std::max(1, 4096 / N);
+    if (ax.T > ax.nlines) ax.T = (int)ax.nlines;
+    ax.tw = ctx->tw[l];
+    stride *= N;
+  }
+  HIPCK(hipMemsetAsync(ctx->S0, 0, sizeof(double2) * 9 * ctx->M.Ng, ctx->stream));
+  HIPCK(hipMemsetAsync(ctx->jr[0], 0, sizeof(double) * 3 * ctx->M.Ng, ctx->stream));
+  HIPCK(hipMemsetAsync(ctx->jh[0], 0, sizeof(double2) * 3 * ctx->M.Ng, ctx->stream));
+  HIPCK(hipMemsetAsync(ctx->An, 0, sizeof(double) * 3 * ctx->M.Ng, ctx->stream));
+  HIPCK(hipMemsetAsync(ctx->trial, 0, sizeof(double) * (ctx->M.d + 6) * ctx->M.Ng, ctx->stream));
+  HIPCK(hipStreamSynchronize(ctx->stream));
+  ctx->bound = true;
+  return GMHC_OK;
+}
+
+int32_t gmhc_load_particles(gmhc_ctx* ctx, const double* x, const double* u, const double* q,
+                            int32_t ptr_kind) {
+  if (!ctx) return GMHC_EINVAL;
+  if (!ctx->bound) return fail(ctx, GMHC_ESTATE, "bind before loading particles");
+  const int64_t np = ctx->np;
+  if (np > 0 && (!x || !u || !q)) return fail(ctx, GMHC_EINVAL, "null particle array");
+  DevGuard g(ctx->device);
+  const size_t b = sizeof(double) * (size_t)np;
+  for (int l = 0; l < ctx->M.d; ++l)
+    if (np) HIPCK(hipMemcpyAsync(ctx->x[l], x + l * np, b, kind_of(ptr_kind, true), ctx->stream));
+  for (int l = 0; l < 3; ++l)
+    if (np) HIPCK(hipMemcpyAsync(ctx->P[l], u + l * np, b, kind_of(ptr_kind, true), ctx->stream));
+  if (np) HIPCK(hipMemcpyAsync(ctx->q, q, b, kind_of(ptr_kind, true), ctx->stream));
+  HIPCK(launch_mech_from_u(ctx->P, ctx->q, ctx->cfg.kappa, np, ctx->stream));
+  HIPCK(launch_iota(ctx->id, np, ctx->stream));
+  for (int l = 0; l < 3; ++l)
+    if (np) HIPCK(hipMemsetAsync(ctx->vb[l], 0, b, ctx->stream));
+  HIPCK(hipStreamSynchronize(ctx->stream));
+  ctx->loaded = true;
+  ctx->initialized = false;
+  return GMHC_OK;
+}
+
+int32_t gmhc_load_potentials(gmhc_ctx* ctx, const double* A0, const double* U0, int32_t ptr_kind) {
+  if (!ctx || !A0 || !U0) return GMHC_EINVAL;
+  if (!ctx->bound) return fail(ctx, GMHC_ESTATE, "bind before loading potentials");
+  DevGuard g(ctx->device);
+  const int64_t Ng = ctx->M.Ng;
+  HIPCK(hipMemcpyAsync(ctx->rscr, A0, sizeof(double) * 3 * Ng, kind_of(ptr_kind, true), ctx->stream));
+  HIPCK(hipMemcpyAsync(ctx->rscr + 3 * Ng, U0, sizeof(double) * 3 * Ng, kind_of(ptr_kind, true), ctx->stream));
+  HIPCK(fft_nd(ctx->M, ctx->axes, 6, ctx->rscr, nullptr, ctx->S0 + 3 * Ng, nullptr, nullptr, false, false,
+               ctx->stream));
+  HIPCK(hipStreamSynchronize(ctx->stream));
+  ctx->have_pot = true;
+  return GMHC_OK;
+}
+
+int32_t gmhc_initialize(gmhc_ctx* ctx) {
+  if (!ctx) return GMHC_EINVAL;
+  if (!ctx->loaded) return fail(ctx, GMHC_ESTATE, "load particles before initialize");
+  DevGuard g(ctx->device);
+  const Mesh& M = ctx->M;
+  const int64_t Ng = M.Ng;
+  hipStream_t s = ctx->stream;
+  if (!ctx->have_pot) HIPCK(hipMemsetAsync(ctx->S0 + 3 * Ng, 0, sizeof(double2) * 6 * Ng, s));
+  // point-shape deposit of rho (into rscr[0]) and J (into Jdep); v = V(p)
+  HIPCK(hipMemsetAsync(ctx->rscr, 0, sizeof(double) * Ng, s));
+  HIPCK(hipMemsetAsync(ctx->Jdep, 0, sizeof(double) * 3 * Ng, s));
+  InitArgs ia{};
+  ia.M = M;
+  ia.np = ctx->np;
+  ia.kappa = ctx->cfg.kappa;
+  for (int l = 0; l < 3; ++l) {
+    ia.x[l] = ctx->x[l];
+    ia.P[l] = ctx->P[l];
+    ia.v[l] = ctx->vb[l];
+    ia.J[l] = ctx->Jdep + l * Ng;
+  }
+  ia.q = ctx->q;
+  ia.rho = ctx->rscr;
+  HIPCK(launch_init_deposit(ia, s));
+  HIPCK(fft_nd(M, ctx->axes, 1, ctx->rscr, nullptr, ctx->S0 + 2 * Ng, nullptr, nullptr, false, false, s));
+  HIPCK(fft_nd(M, ctx->axes, 3, ctx->Jdep, nullptr, ctx->jh[0], nullptr, nullptr, false, false, s));
+  InitSpecArgs sa{};
+  sa.M = M;
+  sa.kappa2 = ctx->cfg.kappa * ctx->cfg.kappa;
+  sa.sigma1 = ctx->cfg.sigma1;
+  sa.project = ctx->cfg.project_nyquist;
+  sa.phi = ctx->S0;
+  sa.psi = ctx->S0 + Ng;
+  sa.rho = ctx->S0 + 2 * Ng;
+  sa.A = ctx->S0 + 3 * Ng;
+  sa.U = ctx->S0 + 6 * Ng;
+  sa.J = ctx->jh[0];
+  HIPCK(launch_init_spectral(sa, s));
+  HIPCK(fft_nd(M, ctx->axes, 3, nullptr, ctx->jh[0], nullptr, ctx->jr[0], ctx->cscr, true, false, s));
+  HIPCK(fft_nd(M, ctx->axes, 3, nullptr, ctx->S0 + 3 * Ng, nullptr, ctx->An, ctx->cscr, true, false, s));
+  CanonArgs ca{};
+  ca.M = M;
+  ca.np = ctx->np;
+  for (int l = 0; l < 3; ++l) {
+    ca.x[l] = ctx->x[l];
+    ca.P[l] = ctx->P[l];
+    ca.A[l] = ctx->An + l * Ng;
+  }
+  ca.q = ctx->q;
+  ca.sign = 1.0;
+  HIPCK(launch_canonical(ca, s));
+  HIPCK(hipStreamSynchronize(s));
+  ctx->t = 0.0;
+  ctx->step = 0;
+  ctx->last_chain = ctx->last_work = ctx->last_rr = ctx->last_mr = 0.0;
+  ctx->initialized = true;
+  gmhc_diag d;
+  int32_t st = gmhc_diagnostics(ctx, &d);
+  if (st) return st;
+  ctx->E0 = d.total;
+  return GMHC_OK;
+}
+
+int32_t gmhc_step(gmhc_ctx* ctx, gmhc_step_report* rep) {
+  if (!ctx) return GMHC_EINVAL;
+  if (!ctx->initialized) return fail(ctx, GMHC_ESTATE, "initialize before step");
+  DevGuard gd(ctx->device);
+  const Mesh& M = ctx->M;
+  const int64_t Ng = M.Ng, np = ctx->np;
+  const int d = M.d;
+  hipStream_t s = ctx->stream;
+  gmhc_step_report R{};
+  if (ctx->cfg.sort_every > 0 && ctx->step % ctx->cfg.sort_every == 0) {
+    int32_t st = sort_particles(ctx);
+    if (st) return st;
+  }
+  for (int l = 0; l < 3; ++l)
+    if (np) HIPCK(hipMemcpyAsync(ctx->vw[l], ctx->vb[l], sizeof(double) * np, hipMemcpyDeviceToDevice, s));
+  int cur = 0;
+  for (int k = 1; k <= ctx->cfg.max_outer; ++k) {
+    // field step for the trial current
+    CNArgs ca{};
+    ca.M = M;
+    ca.dt = ctx->cfg.dt;
+    ca.kappa2 = ctx->cfg.kappa * ctx->cfg.kappa;
+    ca.sigma1 = ctx->cfg.sigma1;
+    ca.sigma2 = ctx->cfg.sigma2;
+    ca.jh = ctx->jh[cur];
+    ca.phi = ctx->S0;
+    ca.psi = ctx->S0 + Ng;
+    ca.rho = ctx->S0 + 2 * Ng;
+    ca.A = ctx->S0 + 3 * Ng;
+    ca.U = ctx->S0 + 6 * Ng;
+    ca.phi1 = ctx->S1;
+    ca.psi1 = ctx->S1 + Ng;
+    ca.rho1 = ctx->S1 + 2 * Ng;
+    ca.A1 = ctx->S1 + 3 * Ng;
+    ca.U1 = ctx->S1 + 6 * Ng;
+    ca.out = ctx->cout;
+    HIPCK(launch_cn(ca, s));
+    HIPCK(fft_nd(M, ctx->axes, d + 6, nullptr, ctx->cout, nullptr, ctx->trial, ctx->cout, true, false, s));
+    // orbit pass with the inner Picard loop
+    int32_t st = run_orbit(ctx, 1, nullptr);
+    if (st) return st;
+    // H(j) = P J_orb in spectral and real space
+    const int hs = (cur == 1) ? 2 : 1;
+    HIPCK(fft_nd(M, ctx->axes, 3, ctx->Jdep, nullptr, ctx->jh[hs], nullptr, nullptr, false,
+                 ctx->cfg.project_nyquist != 0, s));
+    HIPCK(fft_nd(M, ctx->axes, 3, nullptr, ctx->jh[hs], nullptr, ctx->jr[hs], ctx->cscr, true, false, s));
+    ResidualArgs ra{};
+    ra.M = M;
+    ra.tol_abs = ctx->cfg.tol_outer_abs;
+    ra.tol_rel = ctx->cfg.tol_outer_rel;
+    ra.H = ctx->jr[hs];
+    ra.j = ctx->jr[cur];
+    ra.gphi = ctx->trial;
+    ra.Uh = ctx->trial + (int64_t)(d + 3) * Ng;
+    ra.partials = ctx->partials + (size_t)ctx->max_blocks * 8;  // disjoint from orbit partials
+    const int rb = res_blocks(ctx);
+    HIPCK(launch_residual(ra, rb, s));
+    HIPCK(launch_reduce(ra.partials, rb, kResParts, kResParts, 1u << 3, ctx->dres + kResOff, s));
+    double oms = 0.0;
+    st = fetch_results(ctx, &oms);
+    if (st) return st;
+    R.orbit_ms += oms;
+    R.orbit_launches += 1;
+    const double* h = ctx->hres;
+    R.outer_iters = k;
+    R.evaluations += (int64_t)llround(h[OP_ITERS]);
+    R.segments += (int64_t)llround(h[OP_SEGS]);
+    R.inner_max = (int32_t)llround(h[OP_ITMAX]);
+    R.inner_mean = np ? h[OP_ITERS] / (double)np : 0.0;
+    if (h[OP_FAIL] > 0.0) {
+      if (rep) *rep = R;
+      return fail(ctx, GMHC_EINNER, "particle inner solve failed (" + std::to_string((long long)h[OP_FAIL]) +
+                                        " particles)");
+    }
+    const double* r = ctx->hres + kResOff;
+    const double n3 = 3.0 * (double)Ng;
+    const double rr = sqrt(r[0] / n3) /
+                      (ctx->cfg.tol_outer_abs + 0.5 * ctx->cfg.tol_outer_rel * (sqrt(r[1] / n3) + sqrt(r[2] / n3)));
+    const double mr = r[3];
+    R.res_rms_ratio = rr;
+    R.res_max_ratio = mr;
+    if (rr <= 1.0 && mr <= 1.0) {
+      // commit the converged state
+      std::swap(ctx->S0, ctx->S1);
+      HIPCK(hipMemcpyAsync(ctx->An, ctx->trial + (int64_t)d * Ng, sizeof(double) * 3 * Ng,
+                           hipMemcpyDeviceToDevice, s));
+      if (cur != 0) {
+        HIPCK(hipMemcpyAsync(ctx->jr[0], ctx->jr[cur], sizeof(double) * 3 * Ng, hipMemcpyDeviceToDevice, s));
+        HIPCK(hipMemcpyAsync(ctx->jh[0], ctx->jh[cur], sizeof(double2) * 3 * Ng, hipMemcpyDeviceToDevice, s));
+      }
+      for (int l = 0; l < d; ++l) std::swap(ctx->x[l], ctx->x2[l]);
+      for (int l = 0; l < 3; ++l) {
+        std::swap(ctx->P[l], ctx->P2[l]);
+        std::swap(ctx->vb[l], ctx->vw[l]);
+      }
+      HIPCK(hipStreamSynchronize(s));
+      ctx->last_chain = np ? sqrt(h[OP_RA2] / (3.0 * (double)np)) : 0.0;
+      ctx->last_work = ctx->cfg.dt * (h[OP_WORK] - r[4] * M.dV);
+      ctx->last_rr = rr;
+      ctx->last_mr = mr;
+      ctx->t += ctx->cfg.dt;
+      ctx->step += 1;
+      if (rep) *rep = R;
+      return GMHC_OK;
+    }
+    if (ctx->cfg.beta != 1.0)
+      HIPCK(launch_axpy2(ctx->jr[hs], ctx->jr[cur], ctx->jh[hs], ctx->jh[cur], 1.0 - ctx->cfg.beta, 3 * Ng,
+                         3 * Ng, s));
+    cur = hs;
+  }
+  if (rep) *rep = R;
+  return fail(ctx, GMHC_ENOCONV, "outer iteration limit reached");
+}
+
+int32_t gmhc_diagnostics(gmhc_ctx* ctx, gmhc_diag* out) {
+  if (!ctx || !out) return GMHC_EINVAL;
+  if (!ctx->initialized) return fail(ctx, GMHC_ESTATE, "initialize before diagnostics");
+  DevGuard gd(ctx->device);
+  const Mesh& M = ctx->M;
+  const int64_t Ng = M.Ng;
+  hipStream_t s = ctx->stream;
+  KinArgs ka{};
+  ka.M = M;
+  ka.np = ctx->np;
+  ka.kappa = ctx->cfg.kappa;
+  for (int l = 0; l < 3; ++l) {
+    ka.x[l] = ctx->x[l];
+    ka.P[l] = ctx->P[l];
+    ka.A[l] = ctx->An + l * Ng;
+  }
+  ka.q = ctx->q;
+  ka.partials = ctx->partials;
+  const int kb = (int)std::min<int64_t>(std::max<int64_t>((ctx->np + kBlock - 1) / kBlock, 1), 1024);
+  HIPCK(launch_kinetic(ka, kb, s));
+  HIPCK(launch_reduce(ctx->partials, kb, kDiagParts, kDiagParts, 0u, ctx->dres, s));
+  SpecDiagArgs sa{};
+  sa.M = M;
+  sa.kappa2 = ctx->cfg.kappa * ctx->cfg.kappa;
+  sa.sigma1 = ctx->cfg.sigma1;
+  sa.sigma2 = ctx->cfg.sigma2;
+  sa.phi = ctx->S0;
+  sa.psi = ctx->S0 + Ng;
+  sa.rho = ctx->S0 + 2 * Ng;
+  sa.A = ctx->S0 + 3 * Ng;
+  sa.U = ctx->S0 + 6 * Ng;
+  sa.partials = ctx->partials + (size_t)ctx->max_blocks * 8;
+  const int sb = res_blocks(ctx);
+  HIPCK(launch_spec_diag(sa, sb, s));
+  HIPCK(launch_reduce(sa.partials, sb, kDiagParts, kDiagParts, 0u, ctx->dres + kResOff, s));
+  HIPCK(hipMemcpyAsync(ctx->hres, ctx->dres, sizeof(double) * 32, hipMemcpyDeviceToHost, s));
+  HIPCK(hipStreamSynchronize(s));
+  const double* h = ctx->hres;
+  const double* sp = ctx->hres + kResOff;
+  memset(out, 0, sizeof(*out));
+  out->t = ctx->t;
+  out->step = ctx->step;
+  out->kinetic = h[0];
+  out->vperp_rms = h[2] > 0.0 ? sqrt(h[1] / h[2]) : 0.0;
+  // Parseval: sum_g |f_g|^2 = (1/Ng) sum_k |f_hat_k|^2
+  const double ng = (double)Ng;
+  out->field = M.dV / ng * (sp[0] / (2.0 * ctx->cfg.sigma1) + sp[1] / (2.0 * ctx->cfg.sigma2));
+  out->total = out->kinetic + out->field;
+  out->energy_rel = ctx->E0 != 0.0 ? fabs(out->total - ctx->E0) / fabs(ctx->E0) : 0.0;
+  out->gauss_rms = sqrt(sp[2]) / ng;
+  out->lorenz_rms = sqrt(sp[3]) / ng;
+  out->chain_rms = ctx->last_chain;
+  out->work_residual = ctx->last_work;
+  out->res_rms_ratio = ctx->last_rr;
+  out->res_max_ratio = ctx->last_mr;
+  return GMHC_OK;
+}
+
+int32_t gmhc_read_particles(gmhc_ctx* ctx, double* x, double* P, double* vbar, int32_t ptr_kind) {
+  if (!ctx) return GMHC_EINVAL;
+  if (!ctx->loaded) return fail(ctx, GMHC_ESTATE, "no particles loaded");
+  DevGuard gd(ctx->device);
+  const int64_t np = ctx->np;
+  if (!np) return GMHC_OK;
+  hipStream_t s = ctx->stream;
+  const size_t b = sizeof(double) * (size_t)np;
+  auto emit = [&](double* const* src, int nc, double* dst) -> int32_t {
+    HIPCK(launch_unpermute(src, ctx->pscr, nc, ctx->id, np, s));
+    for (int c = 0; c < nc; ++c)
+      HIPCK(hipMemcpyAsync(dst + c * np, ctx->pscr[c], b, kind_of(ptr_kind, false), s));
+    HIPCK(hipStreamSynchronize(s));
+    return GMHC_OK;
+  };
+  int32_t st = GMHC_OK;
+  if (x && (st = emit(ctx->x, ctx->M.d, x))) return st;
+  if (P && (st = emit(ctx->P, 3, P))) return st;
+  if (vbar && (st = emit(ctx->vb, 3, vbar))) return st;
+  return GMHC_OK;
+}
+
+int32_t gmhc_set_particle_state(gmhc_ctx* ctx, const double* x, const double* P, const double* vbar,
+                                int32_t ptr_kind) {
+  if (!ctx) return GMHC_EINVAL;
+  if (!ctx->loaded) return fail(ctx, GMHC_ESTATE, "no particles loaded");
+  DevGuard gd(ctx->device);
+  const int64_t np = ctx->np;
+  if (!np) return GMHC_OK;
+  hipStream_t s = ctx->stream;
+  const size_t b = sizeof(double) * (size_t)np;
+  auto take = [&](const double* src, int nc, double* const* dst) -> int32_t {
+    for (int c = 0; c < nc; ++c)
+      HIPCK(hipMemcpyAsync(ctx->pscr[c], src + c * np, b, kind_of(ptr_kind, true), s));
+    HIPCK(launch_permute_in(ctx->pscr, dst, nc, ctx->id, np, s));
+    HIPCK(hipStreamSynchronize(s));
+    return GMHC_OK;
+  };
+  int32_t st = GMHC_OK;
+  if (x && (st = take(x, ctx->M.d, ctx->x))) return st;
+  if (P && (st = take(P, 3, ctx->P))) return st;
+  if (vbar && (st = take(vbar, 3, ctx->vb))) return st;
+  return GMHC_OK;
+}
+
+int32_t gmhc_read_field(gmhc_ctx* ctx, int32_t which, double* dst, int32_t ptr_kind) {
+  if (!ctx || !dst) return GMHC_EINVAL;
+  if (!ctx->bound) return fail(ctx, GMHC_ESTATE, "bind before reading fields");
+  DevGuard gd(ctx->device);
+  int nc = 0;
+  int32_t st = field_to_rscr(ctx, which, &nc);
+  if (st) return st;
+  HIPCK(hipMemcpyAsync(dst, ctx->rscr, sizeof(double) * nc * ctx->M.Ng, kind_of(ptr_kind, false), ctx->stream));
+  HIPCK(hipStreamSynchronize(ctx->stream));
+  return GMHC_OK;
+}
+
+int32_t gmhc_mode_amplitude(gmhc_ctx* ctx, int32_t which, int32_t comp, const int32_t mode[3], double* amp) {
+  if (!ctx || !mode || !amp) return GMHC_EINVAL;
+  if (!ctx->bound) return fail(ctx, GMHC_ESTATE, "bind before reading modes");
+  if (comp < 0 || comp >= ncomp_of(which)) return fail(ctx, GMHC_EINVAL, "bad component");
+  DevGuard gd(ctx->device);
+  const Mesh& M = ctx->M;
+  const int64_t Ng = M.Ng;
+  int64_t idx[3];
+  for (int l = 0; l < 3; ++l) idx[l] = ((mode[l] % M.n[l]) + M.n[l]) % M.n[l];
+  const int64_t g = idx[0] + (int64_t)M.n[0] * (idx[1] + (int64_t)M.n[1] * idx[2]);
+  auto fetch = [&](const double2* base, double2* v) -> int32_t {
+    HIPCK(hipMemcpy(v, base + g, sizeof(double2), hipMemcpyDeviceToHost));
+    return GMHC_OK;
+  };
+  HIPCK(hipStreamSynchronize(ctx->stream));
+  const long double pi = 3.141592653589793238462643383279502884L;
+  double k[3];
+  for (int l = 0; l < 3; ++l) {
+    const int n = M.n[l];
+    if (l >= M.d || (n % 2 == 0 && idx[l] == n / 2)) {
+      k[l] = 0.0;
+    } else {
+      const int64_t ms = (idx[l] <= n / 2) ? idx[l] : idx[l] - n;
+      k[l] = (double)(2.0L * pi * ms / M.len[l]);
+    }
+  }
+  double2 v{0.0, 0.0};
+  int32_t st = GMHC_OK;
+  const double2* S = ctx->S0;
+  switch (which) {
+    case GMHC_PHI: st = fetch(S, &v); break;
+    case GMHC_PSI: st = fetch(S + Ng, &v); break;
+    case GMHC_RHO: st = fetch(S + 2 * Ng, &v); break;
+    case GMHC_A: st = fetch(S + (3 + comp) * Ng, &v); break;
+    case GMHC_U: st = fetch(S + (6 + comp) * Ng, &v); break;
+    case GMHC_J: st = fetch(ctx->jh[0] + comp * Ng, &v); break;
+    case GMHC_E: {
+      double2 ph, u;
+      if ((st = fetch(S, &ph)) || (st = fetch(S + (6 + comp) * Ng, &u))) break;
+      // E = -i k phi - U
+      v = make_double2(k[comp] * ph.y - u.x, -k[comp] * ph.x - u.y);
+      break;
+    }
+    case GMHC_B: {
+      double2 A[3];
+      for (int c = 0; c < 3 && !st; ++c) st = fetch(S + (3 + c) * Ng, &A[c]);
+      if (st) break;
+      const int a = (comp + 1) % 3, b = (comp + 2) % 3;
+      // (i k x A)_comp = i (k_a A_b - k_b A_a)
+      const double2 w = make_double2(k[a] * A[b].x - k[b] * A[a].x, k[a] * A[b].y - k[b] * A[a].y);
+      v = make_double2(-w.y, w.x);
+      break;
+    }
+    default: return fail(ctx, GMHC_EINVAL, "unknown field selector");
+  }
+  if (st) return st;
+  *amp = hypot(v.x, v.y) / (double)Ng;
+  return GMHC_OK;
+}
+
+int32_t gmhc_set_frozen_fields(gmhc_ctx* ctx, const double* gradphi, const double* An, const double* Anp1,
+                               const double* Uh, int32_t ptr_kind) {
+  if (!ctx || !gradphi || !An || !Anp1 || !Uh) return GMHC_EINVAL;
+  if (!ctx->bound) return fail(ctx, GMHC_ESTATE, "bind before setting fields");
+  DevGuard gd(ctx->device);
+  const int64_t Ng = ctx->M.Ng;
+  const int d = ctx->M.d;
+  hipStream_t s = ctx->stream;
+  HIPCK(hipMemcpyAsync(ctx->trial, gradphi, sizeof(double) * d * Ng, kind_of(ptr_kind, true), s));
+  HIPCK(hipMemcpyAsync(ctx->An, An, sizeof(double) * 3 * Ng, kind_of(ptr_kind, true), s));
+  HIPCK(hipMemcpyAsync(ctx->trial + d * Ng, Anp1, sizeof(double) * 3 * Ng, kind_of(ptr_kind, true), s));
+  HIPCK(hipMemcpyAsync(ctx->trial + (d + 3) * Ng, Uh, sizeof(double) * 3 * Ng, kind_of(ptr_kind, true), s));
+  HIPCK(hipStreamSynchronize(s));
+  ctx->frozen = true;
+  return GMHC_OK;
+}
+
+int32_t gmhc_orbit_pass_frozen(gmhc_ctx* ctx, int32_t iterate, gmhc_pass_report* rep) {
+  if (!ctx) return GMHC_EINVAL;
+  if (!ctx->loaded || !ctx->frozen) return fail(ctx, GMHC_ESTATE, "load particles and set frozen fields first");
+  DevGuard gd(ctx->device);
+  const int64_t np = ctx->np;
+  hipStream_t s = ctx->stream;
+  for (int l = 0; l < 3; ++l)
+    if (np) HIPCK(hipMemcpyAsync(ctx->vw[l], ctx->vb[l], sizeof(double) * np, hipMemcpyDeviceToDevice, s));
+  int32_t st = run_orbit(ctx, iterate ? 1 : 0, nullptr);
+  if (st) return st;
+  double oms = 0.0;
+  st = fetch_results(ctx, &oms);
+  if (st) return st;
+  gmhc_pass_report R{};
+  const double* h = ctx->hres;
+  R.failed = (int64_t)llround(h[OP_FAIL]);
+  R.inner_max = (int32_t)llround(h[OP_ITMAX]);
+  R.evaluations = (int64_t)llround(h[OP_ITERS]);
+  R.segments = (int64_t)llround(h[OP_SEGS]);
+  R.inner_mean = np ? h[OP_ITERS] / (double)np : 0.0;
+  R.orbit_ms = oms;
+  ctx->last_pass = R;
+  ctx->pass_done = true;
+  if (rep) *rep = R;
+  return GMHC_OK;
+}
+
+int32_t gmhc_read_pass(gmhc_ctx* ctx, double* vout, double* Pnp1, double* J, int32_t ptr_kind) {
+  if (!ctx) return GMHC_EINVAL;
+  if (!ctx->pass_done) return fail(ctx, GMHC_ESTATE, "no frozen pass has run");
+  DevGuard gd(ctx->device);
+  const int64_t np = ctx->np, Ng = ctx->M.Ng;
+  hipStream_t s = ctx->stream;
+  const size_t b = sizeof(double) * (size_t)np;
+  if (vout && np) {
+    HIPCK(launch_unpermute(ctx->vw, ctx->pscr, 3, ctx->id, np, s));
+    for (int c = 0; c < 3; ++c) HIPCK(hipMemcpyAsync(vout + c * np, ctx->pscr[c], b, kind_of(ptr_kind, false), s));
+    HIPCK(hipStreamSynchronize(s));
+  }
+  if (Pnp1 && np) {
+    HIPCK(launch_unpermute(ctx->P2, ctx->pscr, 3, ctx->id, np, s));
+    for (int c = 0; c < 3; ++c) HIPCK(hipMemcpyAsync(Pnp1 + c * np, ctx->pscr[c], b, kind_of(ptr_kind, false), s));
+    HIPCK(hipStreamSynchronize(s));
+  }
+  if (J) HIPCK(hipMemcpyAsync(J, ctx->Jdep, sizeof(double) * 3 * Ng, kind_of(ptr_kind, false), s));
+  HIPCK(hipStreamSynchronize(s));
+  return GMHC_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,207 @@
+// gmhc_internal.h -- device-side argument blocks and launch wrappers shared by the
+// HIP translation units of libgmhc (orbit pass, spectral field step, sorting, C ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace gmhc {
+
+constexpr int kBlock = 256;       // threads per workgroup (4 wave64)
+constexpr int kMaxGL = 8;         // Gauss-Legendre points per segment supported
+constexpr int kMaxCross = 8;      // knot crossings per axis per step supported
+constexpr int kOrbitParts = 8;    // per-block partial values written by the orbit pass
+constexpr int kResParts = 8;      // per-block partial values written by the residual pass
+constexpr int kDiagParts = 8;
+
+// Indices of the orbit pass partials.
+enum OrbitPart {
+  OP_FAIL = 0,    // failed inner solves (sum)
+  OP_ITERS = 1,   // inner evaluations (sum)
+  OP_ITMAX = 2,   // inner evaluations (max)
+  OP_KIN = 3,     // kinetic energy of p^{n+1} (sum)
+  OP_WORK = 4,    // sum q v_out . E-bar
+  OP_RA2 = 5,     // sum |R_A|^2
+  OP_SEGS = 6,    // knot-split segments over all evaluations (sum)
+  OP_PAD = 7
+};
+
+// Mesh geometry in the form the kernels use.
+struct Mesh {
+  int d;
+  int n[3];
+  int64_t Ng;
+  double lo[3];
+  double len[3];
+  double h[3];
+  double inv_h[3];
+  double dV;
+};
+
+// Arguments of the orbit pass (one thread per particle).
+struct OrbitArgs {
+  Mesh M;
+  int64_t np;
+  double dt, kappa;
+  double tol_abs, tol_rel;
+  int max_inner;
+  int iterate;           // 0: single evaluation, 1: inner Picard loop
+  int deposit;           // 1: deposit the orbit current
+  int ngl;
+  double glx[kMaxGL], glw[kMaxGL];
+  const double* x[3];
+  const double* P[3];
+  const double* q;
+  double* v[3];          // in: v_in warm start; out: v_out of the final evaluation
+  double* xn[3];         // out: wrapped x^n + dt v_in
+  double* Pn[3];         // out: P^{n+1}
+  int32_t* iters;        // out: inner evaluations
+  const double* gphi[3]; // grad_h phi^{n+1/2}, d components
+  const double* An[3];   // A^n
+  const double* Anp1[3]; // A^{n+1}
+  const double* Uh[3];   // U^{n+1/2}
+  double* J[3];          // orbit current accumulator (FP64 atomics)
+  double* partials;      // [gridDim.x][kOrbitParts]
+};
+
+hipError_t launch_orbit(const OrbitArgs& a, int ngl, hipStream_t s);
+
+// ---- spectral field step ---------------------------------------------------------
+
+struct FftPlanAxis {
+  int N;
+  int logN;
+  int64_t stride;   // element stride of the axis
+  int64_t nlines;   // Ng / N
+  int T;            // lines per workgroup
+  const double2* tw;  // exp(-2 pi i m / N), m < N/2
+};
+
+// Batched multi-dimensional FFT of `ncomp` components (component stride Ng).
+// src may be real (src_r) or complex (src_c); dst may be real (dst_r, real part of
+// the result) or complex (dst_c).  Forward is unnormalized, inverse carries 1/Ng.
+// project = 1 zeroes the even-grid Nyquist planes of a forward result.
+hipError_t fft_nd(const Mesh& M, const FftPlanAxis* axes, int ncomp, const double* src_r,
+                  const double2* src_c, double2* dst_c, double* dst_r, double2* scratch_c,
+                  bool inverse, bool project, hipStream_t s);
+
+struct CNArgs {
+  Mesh M;
+  double dt, kappa2, sigma1, sigma2;
+  const double2* jh;     // [3][Ng] projected trial current
+  const double2* phi; const double2* psi; const double2* rho;
+  const double2* A;      // [3][Ng]
+  const double2* U;      // [3][Ng]
+  double2* phi1; double2* psi1; double2* rho1;
+  double2* A1; double2* U1;
+  double2* out;          // [d+6][Ng]: i k phi^{n+1/2} (d), A^{n+1} (3), U^{n+1/2} (3)
+};
+hipError_t launch_cn(const CNArgs& a, hipStream_t s);
+
+struct ResidualArgs {
+  Mesh M;
+  double tol_abs, tol_rel;
+  const double* H;       // [3][Ng]
+  const double* j;       // [3][Ng]
+  const double* gphi;    // [d][Ng]
+  const double* Uh;      // [3][Ng]
+  double* partials;      // [blocks][kResParts]
+};
+hipError_t launch_residual(const ResidualArgs& a, int blocks, hipStream_t s);
+
+// out[v] = reduce over blocks of partials[b*stride + v]; ops bit v set = max, else sum.
+hipError_t launch_reduce(const double* partials, int nblocks, int stride, int nvals,
+                         uint32_t max_mask, double* out, hipStream_t s);
+
+hipError_t launch_axpy2(double* y, const double* x, double2* yc, const double2* xc, double beta,
+                        int64_t nreal, int64_t ncplx, hipStream_t s);
+
+// ---- initialization and diagnostics ----------------------------------------------
+
+struct InitArgs {
+  Mesh M;
+  int64_t np;
+  double kappa;
+  const double* x[3];
+  double* P[3];          // in: mechanical p; out: unchanged (canonical pass adds q A)
+  const double* q;
+  double* v[3];          // out: V(p)
+  double* rho;           // [Ng] accumulator
+  double* J[3];          // accumulators
+};
+hipError_t launch_init_deposit(const InitArgs& a, hipStream_t s);
+
+struct InitSpecArgs {
+  Mesh M;
+  double kappa2, sigma1;
+  int project;
+  double2* rho; double2* phi; double2* psi; double2* A; double2* U; double2* J;
+};
+hipError_t launch_init_spectral(const InitSpecArgs& a, hipStream_t s);
+
+struct CanonArgs {
+  Mesh M;
+  int64_t np;
+  const double* x[3];
+  double* P[3];
+  const double* q;
+  const double* A[3];    // real A^0
+  double sign;           // +1: P = p + q A ; -1: p = P - q A
+};
+hipError_t launch_canonical(const CanonArgs& a, hipStream_t s);
+
+struct KinArgs {
+  Mesh M;
+  int64_t np;
+  double kappa;
+  const double* x[3];
+  const double* P[3];
+  const double* q;
+  const double* A[3];
+  double* partials;      // [blocks][kDiagParts]: K, sum|q|(vy^2+vz^2), sum|q|
+};
+hipError_t launch_kinetic(const KinArgs& a, int blocks, hipStream_t s);
+
+struct SpecDiagArgs {
+  Mesh M;
+  double kappa2, sigma1, sigma2;
+  const double2* phi; const double2* psi; const double2* rho;
+  const double2* A; const double2* U;
+  double* partials;      // [blocks][kDiagParts]: sum|E|^2, sum|B|^2, sum|RG|^2, sum|RL|^2
+};
+hipError_t launch_spec_diag(const SpecDiagArgs& a, int blocks, hipStream_t s);
+
+// Spectral E (= -i k phi - U) and B (= i k x A) into out [3][Ng].
+hipError_t launch_spec_field(const Mesh& M, int which_e, const double2* phi, const double2* A,
+                             const double2* U, double2* out, hipStream_t s);
+
+// P[c][i] *= |q_i| kappa (mechanical momentum from u = p/(m kappa)).
+hipError_t launch_mech_from_u(double* const P[3], const double* q, double kappa, int64_t np, hipStream_t s);
+hipError_t launch_iota(int32_t* id, int64_t np, hipStream_t s);
+
+// ---- particle permutation -------------------------------------------------------
+// dst[c][id[i]] = src[c][i] for c < ncomp (un-permute to load order).
+hipError_t launch_unpermute(const double* const* src, double* const* dst, int ncomp,
+                            const int32_t* id, int64_t np, hipStream_t s);
+// dst[c][i] = src[c][pos(i)] where pos is the inverse of id (gather to sorted order).
+hipError_t launch_permute_in(const double* const* src, double* const* dst, int ncomp,
+                             const int32_t* id, int64_t np, hipStream_t s);
+
+// Counting sort of particles by nearest-node cell.
+struct SortArgs {
+  Mesh M;
+  int64_t np;
+  int ncomp;              // number of double arrays to move
+  const double* src[12];
+  double* dst[12];
+  const int32_t* id_src;
+  int32_t* id_dst;
+  const double* x[3];     // positions (also among src)
+  int32_t* key;           // [np]
+  int32_t* count;         // [Ng + 1]
+  int32_t* cursor;        // [Ng]
+};
+hipError_t sort_by_cell(const SortArgs& a, void* scan_tmp, size_t scan_tmp_bytes, hipStream_t s);
+size_t sort_scan_tmp_bytes(int64_t Ng);
+
+}  // namespace gmhc

@@ -1,0 +1,599 @@
+// spectral.hip -- periodic spectral field step on the mesh: batched radix-2 FFTs in
+// LDS, the mode-by-mode Crank-Nicolson solve of the potential system with continuity
+// and the Nyquist projector, the outer residual norms, initialization and the
+// spectral diagnostics (section "Mesh-based field values and the Crank-Nicolson
+// potential update", the Nyquist-projection paragraph and the constraint diagnostics).
+#include <math.h>
+
+#include "gmhc_internal.h"
+
+namespace gmhc {
+namespace {
+
+__device__ __forceinline__ double2 cmul(double2 a, double2 b) {
+  return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ __forceinline__ double2 cadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ double2 csub(double2 a, double2 b) { return make_double2(a.x - b.x, a.y - b.y); }
+__device__ __forceinline__ double2 cscale(double2 a, double s) { return make_double2(a.x * s, a.y * s); }
+// i k * a
+__device__ __forceinline__ double2 cik(double k, double2 a) { return make_double2(-k * a.y, k * a.x); }
+
+// Signed-index derivative symbol k_l of unshifted index m (zero at the even-grid
+// Nyquist index, as the spectral operators of the paper use).
+__device__ __forceinline__ double ksym(const Mesh& M, int l, int64_t m) {
+  const int n = M.n[l];
+  if (l >= M.d) return 0.0;
+  if ((n & 1) == 0 && m == n / 2) return 0.0;
+  const int64_t ms = (m <= n / 2) ? m : m - n;
+  return 2.0 * M_PI * (double)ms / M.len[l];
+}
+
+__device__ __forceinline__ void mode_index(const Mesh& M, int64_t g, int64_t idx[3]) {
+  idx[0] = g % M.n[0];
+  idx[1] = (g / M.n[0]) % M.n[1];
+  idx[2] = g / ((int64_t)M.n[0] * M.n[1]);
+}
+
+__device__ __forceinline__ bool on_nyquist(const Mesh& M, const int64_t idx[3]) {
+  bool r = false;
+  for (int l = 0; l < M.d; ++l) r = r || (((M.n[l] & 1) == 0) && idx[l] == M.n[l] / 2);
+  return r;
+}
+
+// One axis pass of a batched complex FFT.  A workgroup loads T lines of length N
+// into LDS in bit-reversed order, runs log2 N radix-2 butterfly stages and writes
+// the lines back.  blockIdx.y selects the component.
+template <bool IN_REAL, bool OUT_REAL>
+__global__ __launch_bounds__(kBlock) void k_fft_axis(const double* src_r, const double2* src_c,
+                                                     double2* dst_c, double* dst_r, int64_t Ng,
+                                                     FftPlanAxis ax, int inverse, int project,
+                                                     Mesh M) {
+  extern __shared__ double2 lds[];
+  const int N = ax.N, T = ax.T;
+  const int64_t comp = blockIdx.y;
+  const int64_t line0 = (int64_t)blockIdx.x * T;
+  const int64_t total = (int64_t)T * N;
+  const int shift = 32 - ax.logN;
+  for (int64_t e = threadIdx.x; e < total; e += blockDim.x) {
+    int lt, k;
+    if (ax.stride == 1) {
+      lt = (int)(e / N);
+      k = (int)(e % N);
+    } else {
+      lt = (int)(e % T);
+      k = (int)(e / T);
+    }
+    const int64_t line = line0 + lt;
+    double2 v = make_double2(0.0, 0.0);
+    if (line < ax.nlines) {
+      const int64_t iin = line % ax.stride, iout = line / ax.stride;
+      const int64_t addr = comp * Ng + iin + ax.stride * ((int64_t)k + (int64_t)N * iout);
+      if (IN_REAL)
+        v = make_double2(src_r[addr], 0.0);
+      else
+        v = src_c[addr];
+    }
+    const int rk = (N > 1) ? (int)(__brev((unsigned)k) >> shift) : 0;
+    lds[lt * N + rk] = v;
+  }
+  __syncthreads();
+  for (int st = 1; st <= ax.logN; ++st) {
+    const int half = 1 << (st - 1);
+    const int twstep = N >> st;
+    for (int b = threadIdx.x; b < T * (N / 2); b += blockDim.x) {
+      const int lt = b / (N / 2), j = b % (N / 2);
+      const int grp = j >> (st - 1), pos = j & (half - 1);
+      const int i1 = lt * N + grp * (2 * half) + pos, i2 = i1 + half;
+      double2 w = ax.tw[pos * twstep];
+      if (inverse) w.y = -w.y;
+      const double2 u = lds[i1];
+      const double2 t = cmul(lds[i2], w);
+      lds[i1] = cadd(u, t);
+      lds[i2] = csub(u, t);
+    }
+    __syncthreads();
+  }
+  const double sc = inverse ? 1.0 / (double)N : 1.0;
+  for (int64_t e = threadIdx.x; e < total; e += blockDim.x) {
+    int lt, k;
+    if (ax.stride == 1) {
+      lt = (int)(e / N);
+      k = (int)(e % N);
+    } else {
+      lt = (int)(e % T);
+      k = (int)(e / T);
+    }
+    const int64_t line = line0 + lt;
+    if (line >= ax.nlines) continue;
+    const int64_t iin = line % ax.stride, iout = line / ax.stride;
+    const int64_t g = iin + ax.stride * ((int64_t)k + (int64_t)N * iout);
+    double2 v = cscale(lds[lt * N + k], sc);
+    if (project) {
+      int64_t idx[3];
+      mode_index(M, g, idx);
+      if (on_nyquist(M, idx)) v = make_double2(0.0, 0.0);
+    }
+    if (OUT_REAL)
+      dst_r[comp * Ng + g] = v.x;
+    else
+      dst_c[comp * Ng + g] = v;
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_cn(CNArgs a) {
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const Mesh& M = a.M;
+  if (g >= M.Ng) return;
+  int64_t idx[3];
+  mode_index(M, g, idx);
+  const double k[3] = {ksym(M, 0, idx[0]), ksym(M, 1, idx[1]), ksym(M, 2, idx[2])};
+  const int64_t Ng = M.Ng;
+  const double2 j0 = a.jh[g], j1 = a.jh[Ng + g], j2 = a.jh[2 * Ng + g];
+  // continuity: rho^{n+1} = rho^n - dt div_h J^{n+1/2}
+  double2 divj = cadd(cadd(cik(k[0], j0), cik(k[1], j1)), cik(k[2], j2));
+  const double h = a.dt;
+  const double2 rho0 = a.rho[g];
+  const double2 rho1 = csub(rho0, cscale(divj, h));
+  const double2 rhoh = cscale(cadd(rho0, rho1), 0.5);
+  const double av = a.kappa2 * (k[0] * k[0] + k[1] * k[1] + k[2] * k[2]);
+  const double q4 = 0.25 * h * h * av;
+  const double inv_den = 1.0 / (1.0 + q4);
+  const double c1 = 1.0 - q4;
+  const double src1 = 0.5 * h * h * a.kappa2 * a.sigma1;
+  const double src2 = 0.5 * h * h * a.kappa2 * a.sigma2;
+  // (phi, psi): phi^{n+1} from the CN pair with psi eliminated
+  const double2 ph0 = a.phi[g], ps0 = a.psi[g];
+  const double2 ph1 = cscale(cadd(cadd(cscale(ph0, c1), cscale(ps0, h)), cscale(rhoh, src1)), inv_den);
+  const double2 ps1 = csub(cscale(csub(ph1, ph0), 2.0 / h), ps0);
+  a.rho1[g] = rho1;
+  a.phi1[g] = ph1;
+  a.psi1[g] = ps1;
+  const double2 phh = cscale(cadd(ph0, ph1), 0.5);
+  int o = 0;
+  for (int l = 0; l < M.d; ++l) a.out[(int64_t)(o++) * Ng + g] = cik(k[l], phh);
+  const double2 jj[3] = {j0, j1, j2};
+  for (int c = 0; c < 3; ++c) {
+    const double2 A0 = a.A[c * Ng + g], U0 = a.U[c * Ng + g];
+    const double2 A1 = cscale(cadd(cadd(cscale(A0, c1), cscale(U0, h)), cscale(jj[c], src2)), inv_den);
+    const double2 U1 = csub(cscale(csub(A1, A0), 2.0 / h), U0);
+    a.A1[c * Ng + g] = A1;
+    a.U1[c * Ng + g] = U1;
+    a.out[(int64_t)(M.d + c) * Ng + g] = A1;
+    a.out[(int64_t)(M.d + 3 + c) * Ng + g] = cscale(cadd(U0, U1), 0.5);
+  }
+}
+
+template <int NV>
+__device__ __forceinline__ void block_store(double (&part)[NV], uint32_t max_mask, double* out) {
+#pragma unroll
+  for (int v = 0; v < NV; ++v)
+    for (int off = 32; off > 0; off >>= 1) {
+      const double o2 = __shfl_xor(part[v], off, 64);
+      part[v] = ((max_mask >> v) & 1u) ? fmax(part[v], o2) : part[v] + o2;
+    }
+  __shared__ double sh[kBlock / 64][NV];
+  const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
+  if (lane == 0)
+#pragma unroll
+    for (int v = 0; v < NV; ++v) sh[wave][v] = part[v];
+  __syncthreads();
+  if (threadIdx.x < NV) {
+    const int v = threadIdx.x;
+    double acc = sh[0][v];
+    for (int w = 1; w < (int)(blockDim.x / 64); ++w)
+      acc = ((max_mask >> v) & 1u) ? fmax(acc, sh[w][v]) : acc + sh[w][v];
+    out[(int64_t)blockIdx.x * NV + v] = acc;
+  }
+}
+
+// Outer residual r = H(j) - j: sums of |r|^2, |H|^2, |j|^2, the max-node test ratio,
+// and the mesh work sum_g H . E^{n+1/2} (E^{n+1/2} = -grad phi^{n+1/2} - U^{n+1/2}).
+__global__ __launch_bounds__(kBlock) void k_residual(ResidualArgs a) {
+  double part[kResParts];
+#pragma unroll
+  for (int v = 0; v < kResParts; ++v) part[v] = 0.0;
+  const int64_t Ng = a.M.Ng;
+  for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < Ng;
+       g += (int64_t)gridDim.x * blockDim.x) {
+    double r2 = 0.0, h2 = 0.0, j2 = 0.0, w = 0.0;
+    for (int c = 0; c < 3; ++c) {
+      const double H = a.H[c * Ng + g], j = a.j[c * Ng + g];
+      const double r = H - j;
+      r2 += r * r;
+      h2 += H * H;
+      j2 += j * j;
+      const double gp = (c < a.M.d) ? a.gphi[c * Ng + g] : 0.0;
+      w += H * (-gp - a.Uh[c * Ng + g]);
+    }
+    part[0] += r2;
+    part[1] += h2;
+    part[2] += j2;
+    part[3] = fmax(part[3], sqrt(r2) / (a.tol_abs + 0.5 * a.tol_rel * (sqrt(h2) + sqrt(j2))));
+    part[4] += w;
+  }
+  block_store<kResParts>(part, 1u << 3, a.partials);
+}
+
+__global__ __launch_bounds__(kBlock) void k_reduce(const double* partials, int nblocks, int stride,
+                                                   int nvals, uint32_t max_mask, double* out) {
+  // thread v (< nvals) reduces value v over all blocks in block order
+  const int v = threadIdx.x;
+  if (v >= nvals) return;
+  const bool mx = (max_mask >> v) & 1u;
+  double acc = mx ? -INFINITY : 0.0;
+  for (int b = 0; b < nblocks; ++b) {
+    const double x = partials[(int64_t)b * stride + v];
+    acc = mx ? fmax(acc, x) : acc + x;
+  }
+  out[v] = acc;
+}
+
+__global__ void k_axpy2(double* y, const double* x, double2* yc, const double2* xc, double beta,
+                        int64_t nreal, int64_t ncplx) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < nreal) y[i] += beta * (x[i] - y[i]);
+  if (i < ncplx) {
+    double2 a = yc[i], b = xc[i];
+    yc[i] = make_double2(a.x + beta * (b.x - a.x), a.y + beta * (b.y - a.y));
+  }
+}
+
+// ---- initialization --------------------------------------------------------------
+
+__device__ __forceinline__ int wrapi(int i, int n) {
+  int r = i % n;
+  return r < 0 ? r + n : r;
+}
+
+__device__ __forceinline__ void pw(double xi, int n, int gi[3], double w[3]) {
+  if (!(xi > -1.0e9 && xi < 1.0e9)) xi = 0.0;  // non-finite positions map to a valid node
+  const int j = (int)floor(xi + 0.5);
+  const double f = xi - (double)j;
+  const double a = 0.5 - f, b = 0.5 + f;
+  w[0] = 0.5 * a * a;
+  w[1] = 0.75 - f * f;
+  w[2] = 0.5 * b * b;
+  for (int c = 0; c < 3; ++c) gi[c] = wrapi(j + c - 1, n);
+}
+
+// Point-shape stencil of a particle: up to 27 (node, weight) pairs.
+__device__ __forceinline__ int point_stencil(const Mesh& M, const double* const* x, int64_t i,
+                                             int64_t* nodes, double* wts) {
+  int gi[3][3];
+  double w[3][3];
+  for (int l = 0; l < 3; ++l) {
+    if (l < M.d) {
+      pw((x[l][i] - M.lo[l]) * M.inv_h[l], M.n[l], gi[l], w[l]);
+    } else {
+      gi[l][0] = 0;
+      w[l][0] = 1.0;
+    }
+  }
+  const int NX = 3, NY = M.d > 1 ? 3 : 1, NZ = M.d > 2 ? 3 : 1;
+  int cnt = 0;
+  for (int cz = 0; cz < NZ; ++cz)
+    for (int cy = 0; cy < NY; ++cy)
+      for (int cx = 0; cx < NX; ++cx) {
+        nodes[cnt] = gi[0][cx] + (int64_t)M.n[0] * (gi[1][cy] + (int64_t)M.n[1] * gi[2][cz]);
+        wts[cnt] = w[0][cx] * w[1][cy] * w[2][cz];
+        ++cnt;
+      }
+  return cnt;
+}
+
+__global__ __launch_bounds__(kBlock) void k_init_deposit(InitArgs a) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= a.np) return;
+  const double q = a.q[i], m = fabs(q);
+  const double p[3] = {a.P[0][i], a.P[1][i], a.P[2][i]};
+  const double imk = 1.0 / (m * a.kappa);
+  const double g = sqrt(1.0 + (p[0] * p[0] + p[1] * p[1] + p[2] * p[2]) * imk * imk);
+  double v[3];
+  for (int c = 0; c < 3; ++c) {
+    v[c] = p[c] / (m * g);
+    a.v[c][i] = v[c];
+  }
+  int64_t nodes[27];
+  double wts[27];
+  const int cnt = point_stencil(a.M, a.x, i, nodes, wts);
+  const double qd = q / a.M.dV;
+  for (int k = 0; k < cnt; ++k) {
+    atomicAdd(a.rho + nodes[k], qd * wts[k]);
+    for (int c = 0; c < 3; ++c) atomicAdd(a.J[c] + nodes[k], qd * v[c] * wts[k]);
+  }
+}
+
+// Spectral initialization: neutralizing background (k = 0 charge removed), Nyquist
+// projection, phi from Gauss's law |k|^2 phi = sigma1 rho + i k . U, psi = -kappa^2 i k . A.
+__global__ __launch_bounds__(kBlock) void k_init_spectral(InitSpecArgs a) {
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const Mesh& M = a.M;
+  if (g >= M.Ng) return;
+  const int64_t Ng = M.Ng;
+  int64_t idx[3];
+  mode_index(M, g, idx);
+  const bool kill = a.project && on_nyquist(M, idx);
+  if (g == 0) a.rho[0] = make_double2(0.0, 0.0);
+  if (kill) {
+    a.rho[g] = make_double2(0.0, 0.0);
+    for (int c = 0; c < 3; ++c) {
+      a.A[c * Ng + g] = make_double2(0.0, 0.0);
+      a.U[c * Ng + g] = make_double2(0.0, 0.0);
+      a.J[c * Ng + g] = make_double2(0.0, 0.0);
+    }
+  }
+  const double k[3] = {ksym(M, 0, idx[0]), ksym(M, 1, idx[1]), ksym(M, 2, idx[2])};
+  double2 divU = make_double2(0.0, 0.0), divA = make_double2(0.0, 0.0);
+  for (int c = 0; c < 3; ++c) {
+    divU = cadd(divU, cik(k[c], a.U[c * Ng + g]));
+    divA = cadd(divA, cik(k[c], a.A[c * Ng + g]));
+  }
+  const double k2 = k[0] * k[0] + k[1] * k[1] + k[2] * k[2];
+  const double2 rho = a.rho[g];
+  a.phi[g] = (k2 > 0.0) ? cscale(cadd(cscale(rho, a.sigma1), divU), 1.0 / k2) : make_double2(0.0, 0.0);
+  a.psi[g] = cscale(divA, -a.kappa2);
+}
+
+__global__ __launch_bounds__(kBlock) void k_canonical(CanonArgs a) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= a.np) return;
+  int64_t nodes[27];
+  double wts[27];
+  const int cnt = point_stencil(a.M, a.x, i, nodes, wts);
+  double Ah[3] = {0.0, 0.0, 0.0};
+  for (int k = 0; k < cnt; ++k)
+    for (int c = 0; c < 3; ++c) Ah[c] += wts[k] * a.A[c][nodes[k]];
+  const double q = a.q[i];
+  for (int c = 0; c < 3; ++c) a.P[c][i] += a.sign * q * Ah[c];
+}
+
+// Kinetic energy and transverse velocity moments of the accepted state.
+__global__ __launch_bounds__(kBlock) void k_kinetic(KinArgs a) {
+  double part[kDiagParts];
+  for (int v = 0; v < kDiagParts; ++v) part[v] = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < a.np;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    int64_t nodes[27];
+    double wts[27];
+    const int cnt = point_stencil(a.M, a.x, i, nodes, wts);
+    double Ah[3] = {0.0, 0.0, 0.0};
+    for (int k = 0; k < cnt; ++k)
+      for (int c = 0; c < 3; ++c) Ah[c] += wts[k] * a.A[c][nodes[k]];
+    const double q = a.q[i], m = fabs(q);
+    double p[3];
+    for (int c = 0; c < 3; ++c) p[c] = a.P[c][i] - q * Ah[c];
+    const double imk = 1.0 / (m * a.kappa);
+    const double p2 = p[0] * p[0] + p[1] * p[1] + p[2] * p[2];
+    const double g = sqrt(1.0 + p2 * imk * imk);
+    part[0] += p2 / (m * (g + 1.0));
+    const double vy = p[1] / (m * g), vz = p[2] / (m * g);
+    part[1] += m * (vy * vy + vz * vz);
+    part[2] += m;
+  }
+  block_store<kDiagParts>(part, 0u, a.partials);
+}
+
+// Parseval sums over modes: |E_hat|^2, |B_hat|^2, |R_G hat|^2, |R_L hat|^2.
+__global__ __launch_bounds__(kBlock) void k_spec_diag(SpecDiagArgs a) {
+  double part[kDiagParts];
+  for (int v = 0; v < kDiagParts; ++v) part[v] = 0.0;
+  const Mesh& M = a.M;
+  const int64_t Ng = M.Ng;
+  for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < Ng;
+       g += (int64_t)gridDim.x * blockDim.x) {
+    int64_t idx[3];
+    mode_index(M, g, idx);
+    const double k[3] = {ksym(M, 0, idx[0]), ksym(M, 1, idx[1]), ksym(M, 2, idx[2])};
+    const double2 ph = a.phi[g];
+    double2 E[3], A[3];
+    double2 divE = make_double2(0.0, 0.0), divA = make_double2(0.0, 0.0);
+    for (int c = 0; c < 3; ++c) {
+      A[c] = a.A[c * Ng + g];
+      E[c] = csub(make_double2(-cik(k[c], ph).x, -cik(k[c], ph).y), a.U[c * Ng + g]);
+      divE = cadd(divE, cik(k[c], E[c]));
+      divA = cadd(divA, cik(k[c], A[c]));
+    }
+    // B = i k x A
+    const double2 B0 = csub(cik(k[1], A[2]), cik(k[2], A[1]));
+    const double2 B1 = csub(cik(k[2], A[0]), cik(k[0], A[2]));
+    const double2 B2 = csub(cik(k[0], A[1]), cik(k[1], A[0]));
+    double e2 = 0.0;
+    for (int c = 0; c < 3; ++c) e2 += E[c].x * E[c].x + E[c].y * E[c].y;
+    const double b2 = B0.x * B0.x + B0.y * B0.y + B1.x * B1.x + B1.y * B1.y + B2.x * B2.x + B2.y * B2.y;
+    const double2 RG = csub(divE, cscale(a.rho[g], a.sigma1));
+    const double2 RL = cadd(cscale(a.psi[g], 1.0 / a.kappa2), divA);
+    part[0] += e2;
+    part[1] += b2;
+    part[2] += RG.x * RG.x + RG.y * RG.y;
+    part[3] += RL.x * RL.x + RL.y * RL.y;
+  }
+  block_store<kDiagParts>(part, 0u, a.partials);
+}
+
+__global__ __launch_bounds__(kBlock) void k_spec_field(Mesh M, int which_e, const double2* phi,
+                                                       const double2* A, const double2* U,
+                                                       double2* out) {
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t Ng = M.Ng;
+  if (g >= Ng) return;
+  int64_t idx[3];
+  mode_index(M, g, idx);
+  const double k[3] = {ksym(M, 0, idx[0]), ksym(M, 1, idx[1]), ksym(M, 2, idx[2])};
+  if (which_e) {
+    const double2 ph = phi[g];
+    for (int c = 0; c < 3; ++c) {
+      const double2 gk = cik(k[c], ph);
+      out[c * Ng + g] = csub(make_double2(-gk.x, -gk.y), U[c * Ng + g]);
+    }
+  } else {
+    const double2 A0 = A[g], A1 = A[Ng + g], A2 = A[2 * Ng + g];
+    out[g] = csub(cik(k[1], A2), cik(k[2], A1));
+    out[Ng + g] = csub(cik(k[2], A0), cik(k[0], A2));
+    out[2 * Ng + g] = csub(cik(k[0], A1), cik(k[1], A0));
+  }
+}
+
+struct PermArgs {
+  const double* src[12];
+  double* dst[12];
+};
+
+__global__ __launch_bounds__(kBlock) void k_unpermute(PermArgs p, int ncomp, const int32_t* id,
+                                                      int64_t np, int inverse) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= np) return;
+  const int64_t k = id[i];
+  for (int c = 0; c < ncomp; ++c) {
+    if (inverse)
+      p.dst[c][i] = p.src[c][k];  // gather load-order data into sorted order
+    else
+      p.dst[c][k] = p.src[c][i];  // scatter sorted data back to load order
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_mech_from_u(double* P0, double* P1, double* P2, const double* q,
+                                                        double kappa, int64_t np) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= np) return;
+  const double mk = fabs(q[i]) * kappa;
+  P0[i] *= mk;
+  P1[i] *= mk;
+  P2[i] *= mk;
+}
+
+__global__ __launch_bounds__(kBlock) void k_iota(int32_t* id, int64_t np) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < np) id[i] = (int32_t)i;
+}
+
+inline unsigned nblk(int64_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
+
+}  // namespace
+
+hipError_t launch_mech_from_u(double* const P[3], const double* q, double kappa, int64_t np, hipStream_t s) {
+  if (np <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_mech_from_u, dim3(nblk(np)), dim3(kBlock), 0, s, P[0], P[1], P[2], q, kappa, np);
+  return hipGetLastError();
+}
+
+hipError_t launch_iota(int32_t* id, int64_t np, hipStream_t s) {
+  if (np <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_iota, dim3(nblk(np)), dim3(kBlock), 0, s, id, np);
+  return hipGetLastError();
+}
+
+hipError_t fft_nd(const Mesh& M, const FftPlanAxis* axes, int ncomp, const double* src_r,
+                  const double2* src_c, double2* dst_c, double* dst_r, double2* scratch_c,
+                  bool inverse, bool project, hipStream_t s) {
+  // passes: axis 0 .. d-1 (forward) or the same order (inverse; axes commute)
+  double2* work = dst_c ? dst_c : scratch_c;
+  for (int l = 0; l < M.d; ++l) {
+    const FftPlanAxis& ax = axes[l];
+    const bool first = (l == 0), last = (l == M.d - 1);
+    const bool in_real = first && src_r != nullptr;
+    const bool out_real = last && dst_r != nullptr;
+    const double2* in_c = first ? src_c : work;
+    const unsigned gx = (unsigned)((ax.nlines + ax.T - 1) / ax.T);
+    const size_t lds = sizeof(double2) * (size_t)ax.T * ax.N;
+    const int proj = (last && project && !inverse) ? 1 : 0;
+    dim3 grid(gx, (unsigned)ncomp);
+    if (in_real && out_real)
+      hipLaunchKernelGGL((k_fft_axis<true, true>), grid, dim3(kBlock), lds, s, src_r, nullptr, nullptr,
+                         dst_r, M.Ng, ax, inverse ? 1 : 0, proj, M);
+    else if (in_real)
+      hipLaunchKernelGGL((k_fft_axis<true, false>), grid, dim3(kBlock), lds, s, src_r, nullptr, work,
+                         nullptr, M.Ng, ax, inverse ? 1 : 0, proj, M);
+    else if (out_real)
+      hipLaunchKernelGGL((k_fft_axis<false, true>), grid, dim3(kBlock), lds, s, nullptr, in_c, nullptr,
+                         dst_r, M.Ng, ax, inverse ? 1 : 0, proj, M);
+    else
+      hipLaunchKernelGGL((k_fft_axis<false, false>), grid, dim3(kBlock), lds, s, nullptr, in_c, work,
+                         nullptr, M.Ng, ax, inverse ? 1 : 0, proj, M);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+hipError_t launch_cn(const CNArgs& a, hipStream_t s) {
+  hipLaunchKernelGGL(k_cn, dim3(nblk(a.M.Ng)), dim3(kBlock), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_residual(const ResidualArgs& a, int blocks, hipStream_t s) {
+  hipLaunchKernelGGL(k_residual, dim3(blocks), dim3(kBlock), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_reduce(const double* partials, int nblocks, int stride, int nvals,
+                         uint32_t max_mask, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_reduce, dim3(1), dim3(64), 0, s, partials, nblocks, stride, nvals, max_mask, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_axpy2(double* y, const double* x, double2* yc, const double2* xc, double beta,
+                        int64_t nreal, int64_t ncplx, hipStream_t s) {
+  const int64_t n = nreal > ncplx ? nreal : ncplx;
+  hipLaunchKernelGGL(k_axpy2, dim3(nblk(n)), dim3(kBlock), 0, s, y, x, yc, xc, beta, nreal, ncplx);
+  return hipGetLastError();
+}
+
+hipError_t launch_init_deposit(const InitArgs& a, hipStream_t s) {
+  if (a.np <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_init_deposit, dim3(nblk(a.np)), dim3(kBlock), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_init_spectral(const InitSpecArgs& a, hipStream_t s) {
+  hipLaunchKernelGGL(k_init_spectral, dim3(nblk(a.M.Ng)), dim3(kBlock), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_canonical(const CanonArgs& a, hipStream_t s) {
+  if (a.np <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_canonical, dim3(nblk(a.np)), dim3(kBlock), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_kinetic(const KinArgs& a, int blocks, hipStream_t s) {
+  hipLaunchKernelGGL(k_kinetic, dim3(blocks), dim3(kBlock), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_spec_diag(const SpecDiagArgs& a, int blocks, hipStream_t s) {
+  hipLaunchKernelGGL(k_spec_diag, dim3(blocks), dim3(kBlock), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_spec_field(const Mesh& M, int which_e, const double2* phi, const double2* A,
+                             const double2* U, double2* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_spec_field, dim3(nblk(M.Ng)), dim3(kBlock), 0, s, M, which_e, phi, A, U, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_unpermute(const double* const* src, double* const* dst, int ncomp,
+                            const int32_t* id, int64_t np, hipStream_t s) {
+  if (np <= 0) return hipSuccess;
+  PermArgs p;
+  for (int c = 0; c < ncomp && c < 12; ++c) {
+    p.src[c] = src[c];
+    p.dst[c] = dst[c];
+  }
+  hipLaunchKernelGGL(k_unpermute, dim3(nblk(np)), dim3(kBlock), 0, s, p, ncomp, id, np, 0);
+  return hipGetLastError();
+}
+
+hipError_t launch_permute_in(const double* const* src, double* const* dst, int ncomp,
+                             const int32_t* id, int64_t np, hipStream_t s) {
+  if (np <= 0) return hipSuccess;
+  PermArgs p;
+  for (int c = 0; c < ncomp && c < 12; ++c) {
+    p.src[c] = src[c];
+    p.dst[c] = dst[c];
+  }
+  hipLaunchKernelGGL(k_unpermute, dim3(nblk(np)), dim3(kBlock), 0, s, p, ncomp, id, np, 1);
+  return hipGetLastError();
+}
+
+}  // namespace gmhc

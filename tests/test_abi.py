@@ -1,0 +1,68 @@
+"""The C-ABI library loads and exports every entry point include/gmhc.h declares, and
+its host-only validation behaves as documented (no GPU compute is called here)."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+from paper_2609_36383_amd import gmhc as G
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    with open(os.path.join(ROOT, "include", "gmhc.h")) as f:
+        text = f.read()
+    return sorted(set(re.findall(r"\b(gmhc_[a-z_]+)\s*\(", text)))
+
+
+def test_header_declarations_match_binding():
+    assert _declared() == sorted(G.SYMBOLS)
+
+
+def test_library_exports_every_symbol():
+    lib = G.load_library()
+    for name in _declared():
+        assert hasattr(lib, name), name
+    assert lib.gmhc_abi_version() == 1
+
+
+def test_host_validation():
+    lib = G.load_library()
+    h = C.c_void_p()
+    good = G.make_config(2, (16, 16), (0, 0), (3.2, 3.2), 0.05)
+    assert lib.gmhc_create(C.byref(good), C.byref(h)) == G.OK
+    n = C.c_size_t()
+    assert lib.gmhc_workspace_bytes(h, 1000, C.byref(n)) == G.OK and n.value > 0
+    n2 = C.c_size_t()
+    assert lib.gmhc_workspace_bytes(h, 100000, C.byref(n2)) == G.OK and n2.value > n.value
+    lib.gmhc_destroy(h)
+    bad = [
+        dict(sigma1=2.0),                 # sigma1 != kappa^2 sigma2
+        dict(dt=0.0),
+        dict(n=(12, 16)),                 # not a power of two
+        dict(gl_order=9),
+        dict(beta=0.0),
+        dict(max_outer=0),
+    ]
+    for over in bad:
+        kw = dict(dim=2, n=(16, 16), lo=(0, 0), length=(3.2, 3.2), dt=0.05)
+        kw.update(over)
+        c = G.make_config(**kw)
+        hh = C.c_void_p()
+        assert lib.gmhc_create(C.byref(c), C.byref(hh)) == G.EINVAL, over
+    c = G.make_config(4, (16, 16, 16), (0, 0, 0), (1, 1, 1), 0.1)
+    c.dim = 4
+    assert lib.gmhc_create(C.byref(c), C.byref(C.c_void_p())) == G.EINVAL
+
+
+def test_calls_out_of_order_are_rejected():
+    lib = G.load_library()
+    h = C.c_void_p()
+    c = G.make_config(1, (16,), (0,), (1.0,), 0.1)
+    assert lib.gmhc_create(C.byref(c), C.byref(h)) == G.OK
+    assert lib.gmhc_initialize(h) == G.ESTATE
+    assert lib.gmhc_step(h, None) == G.ESTATE
+    assert b"initialize" in lib.gmhc_last_error(h) or lib.gmhc_last_error(h)
+    lib.gmhc_destroy(h)
