@@ -141,16 +141,22 @@ size_t carve(gmhc_ctx* c, char* base, int64_t np) {
   const int d = c->M.d;
   const int64_t Ng = c->M.Ng;
   const size_t N = (size_t)std::max<int64_t>(np, 1);
+  // each SoA group is one contiguous block with component stride N
+  double* xb = cv.take<double>(d * N);
+  double* x2b = cv.take<double>(d * N);
+  double* Pb = cv.take<double>(3 * N);
+  double* P2b = cv.take<double>(3 * N);
+  double* vbb = cv.take<double>(3 * N);
+  double* vwb = cv.take<double>(3 * N);
+  double* psb = cv.take<double>(3 * N);
   for (int l = 0; l < 3; ++l) {
-    c->x[l] = (l < d) ? cv.take<double>(N) : nullptr;
-    c->x2[l] = (l < d) ? cv.take<double>(N) : nullptr;
-  }
-  for (int l = 0; l < 3; ++l) {
-    c->P[l] = cv.take<double>(N);
-    c->P2[l] = cv.take<double>(N);
-    c->vb[l] = cv.take<double>(N);
-    c->vw[l] = cv.take<double>(N);
-    c->pscr[l] = cv.take<double>(N);
+    c->x[l] = (l < d && xb) ? xb + l * N : nullptr;
+    c->x2[l] = (l < d && x2b) ? x2b + l * N : nullptr;
+    c->P[l] = Pb ? Pb + l * N : nullptr;
+    c->P2[l] = P2b ? P2b + l * N : nullptr;
+    c->vb[l] = vbb ? vbb + l * N : nullptr;
+    c->vw[l] = vwb ? vwb + l * N : nullptr;
+    c->pscr[l] = psb ? psb + l * N : nullptr;
   }
   c->q = cv.take<double>(N);
   c->q2 = cv.take<double>(N);
@@ -213,20 +219,15 @@ OrbitArgs orbit_args(gmhc_ctx* c, int iterate) {
     a.glx[k] = c->glx[k];
     a.glw[k] = c->glw[k];
   }
-  const int d = c->M.d;
-  const int64_t Ng = c->M.Ng;
-  for (int l = 0; l < 3; ++l) {
-    a.x[l] = c->x[l];
-    a.xn[l] = c->x2[l];
-    a.P[l] = c->P[l];
-    a.Pn[l] = c->P2[l];
-    a.v[l] = c->vw[l];
-    a.gphi[l] = (l < d) ? c->trial + (int64_t)l * Ng : nullptr;
-    a.An[l] = c->An + (int64_t)l * Ng;
-    a.Anp1[l] = c->trial + (int64_t)(d + l) * Ng;
-    a.Uh[l] = c->trial + (int64_t)(d + 3 + l) * Ng;
-    a.J[l] = c->Jdep + (int64_t)l * Ng;
-  }
+  a.ps = std::max<int64_t>(c->np, 1);
+  a.x = c->x[0];
+  a.xn = c->x2[0];
+  a.P = c->P[0];
+  a.Pn = c->P2[0];
+  a.v = c->vw[0];
+  a.trial = c->trial;
+  a.An = c->An;
+  a.J = c->Jdep;
   a.q = c->q;
   a.iters = c->iters;
   a.partials = c->partials;

@@ -49,18 +49,19 @@ struct OrbitArgs {
   int deposit;           // 1: deposit the orbit current
   int ngl;
   double glx[kMaxGL], glw[kMaxGL];
-  const double* x[3];
-  const double* P[3];
-  const double* q;
-  double* v[3];          // in: v_in warm start; out: v_out of the final evaluation
-  double* xn[3];         // out: wrapped x^n + dt v_in
-  double* Pn[3];         // out: P^{n+1}
+  // particle SoA blocks, component c of particle i at [c * ps + i]
+  int64_t ps;
+  const double* x;       // [d]
+  const double* P;       // [3]
+  const double* q;       // [1]
+  double* v;             // [3] in: v_in warm start; out: v_out of the final evaluation
+  double* xn;            // [d] out: wrapped x^n + dt v_in
+  double* Pn;            // [3] out: P^{n+1}
   int32_t* iters;        // out: inner evaluations
-  const double* gphi[3]; // grad_h phi^{n+1/2}, d components
-  const double* An[3];   // A^n
-  const double* Anp1[3]; // A^{n+1}
-  const double* Uh[3];   // U^{n+1/2}
-  double* J[3];          // orbit current accumulator (FP64 atomics)
+  // mesh arrays, component stride Ng
+  const double* trial;   // [d+6]: grad_h phi^{n+1/2} (d), A^{n+1} (3), U^{n+1/2} (3)
+  const double* An;      // [3] A^n
+  double* J;             // [3] orbit current accumulator
   double* partials;      // [gridDim.x][kOrbitParts]
 };
 

@@ -5,6 +5,8 @@
 // potential update", the Nyquist-projection paragraph and the constraint diagnostics).
 #include <math.h>
 
+#include <algorithm>
+
 #include "gmhc_internal.h"
 
 namespace gmhc {
@@ -217,16 +219,27 @@ __global__ __launch_bounds__(kBlock) void k_residual(ResidualArgs a) {
 
 __global__ __launch_bounds__(kBlock) void k_reduce(const double* partials, int nblocks, int stride,
                                                    int nvals, uint32_t max_mask, double* out) {
-  // thread v (< nvals) reduces value v over all blocks in block order
-  const int v = threadIdx.x;
+  // One workgroup per value.  Thread t folds blocks t, t + 256, ... in order, then a
+  // fixed pairwise tree combines the threads: the result depends only on nblocks.
+  const int v = blockIdx.x;
   if (v >= nvals) return;
   const bool mx = (max_mask >> v) & 1u;
   double acc = mx ? -INFINITY : 0.0;
-  for (int b = 0; b < nblocks; ++b) {
+  for (int b = threadIdx.x; b < nblocks; b += blockDim.x) {
     const double x = partials[(int64_t)b * stride + v];
     acc = mx ? fmax(acc, x) : acc + x;
   }
-  out[v] = acc;
+  __shared__ double sh[kBlock];
+  sh[threadIdx.x] = acc;
+  __syncthreads();
+  for (int h = kBlock / 2; h > 0; h >>= 1) {
+    if ((int)threadIdx.x < h) {
+      const double o = sh[threadIdx.x + h];
+      sh[threadIdx.x] = mx ? fmax(sh[threadIdx.x], o) : sh[threadIdx.x] + o;
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[v] = sh[0];
 }
 
 __global__ void k_axpy2(double* y, const double* x, double2* yc, const double2* xc, double beta,
@@ -489,7 +502,14 @@ hipError_t fft_nd(const Mesh& M, const FftPlanAxis* axes, int ncomp, const doubl
   // passes: axis 0 .. d-1 (forward) or the same order (inverse; axes commute)
   double2* work = dst_c ? dst_c : scratch_c;
   for (int l = 0; l < M.d; ++l) {
-    const FftPlanAxis& ax = axes[l];
+    // lines per workgroup: enough workgroups to cover the chip (>= 512 when the mesh
+    // allows), at most 4096 elements (64 KiB of LDS) per workgroup
+    FftPlanAxis ax = axes[l];
+    int64_t T = (ax.nlines * ncomp) / 512;
+    T = std::max<int64_t>(1, std::min<int64_t>(T, std::max(1, 4096 / ax.N)));
+    T = std::min<int64_t>(T, ax.nlines);
+    ax.T = (int)T;
+    const int threads = (int)std::min<int64_t>(kBlock, std::max<int64_t>(64, (T * ax.N / 2 + 63) / 64 * 64));
     const bool first = (l == 0), last = (l == M.d - 1);
     const bool in_real = first && src_r != nullptr;
     const bool out_real = last && dst_r != nullptr;
@@ -499,16 +519,16 @@ hipError_t fft_nd(const Mesh& M, const FftPlanAxis* axes, int ncomp, const doubl
     const int proj = (last && project && !inverse) ? 1 : 0;
     dim3 grid(gx, (unsigned)ncomp);
     if (in_real && out_real)
-      hipLaunchKernelGGL((k_fft_axis<true, true>), grid, dim3(kBlock), lds, s, src_r, nullptr, nullptr,
+      hipLaunchKernelGGL((k_fft_axis<true, true>), grid, dim3(threads), lds, s, src_r, nullptr, nullptr,
                          dst_r, M.Ng, ax, inverse ? 1 : 0, proj, M);
     else if (in_real)
-      hipLaunchKernelGGL((k_fft_axis<true, false>), grid, dim3(kBlock), lds, s, src_r, nullptr, work,
+      hipLaunchKernelGGL((k_fft_axis<true, false>), grid, dim3(threads), lds, s, src_r, nullptr, work,
                          nullptr, M.Ng, ax, inverse ? 1 : 0, proj, M);
     else if (out_real)
-      hipLaunchKernelGGL((k_fft_axis<false, true>), grid, dim3(kBlock), lds, s, nullptr, in_c, nullptr,
+      hipLaunchKernelGGL((k_fft_axis<false, true>), grid, dim3(threads), lds, s, nullptr, in_c, nullptr,
                          dst_r, M.Ng, ax, inverse ? 1 : 0, proj, M);
     else
-      hipLaunchKernelGGL((k_fft_axis<false, false>), grid, dim3(kBlock), lds, s, nullptr, in_c, work,
+      hipLaunchKernelGGL((k_fft_axis<false, false>), grid, dim3(threads), lds, s, nullptr, in_c, work,
                          nullptr, M.Ng, ax, inverse ? 1 : 0, proj, M);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
@@ -528,7 +548,8 @@ hipError_t launch_residual(const ResidualArgs& a, int blocks, hipStream_t s) {
 
 hipError_t launch_reduce(const double* partials, int nblocks, int stride, int nvals,
                          uint32_t max_mask, double* out, hipStream_t s) {
-  hipLaunchKernelGGL(k_reduce, dim3(1), dim3(64), 0, s, partials, nblocks, stride, nvals, max_mask, out);
+  hipLaunchKernelGGL(k_reduce, dim3((unsigned)nvals), dim3(kBlock), 0, s, partials, nblocks, stride, nvals,
+                     max_mask, out);
   return hipGetLastError();
 }
 
