@@ -220,6 +220,7 @@ OrbitArgs orbit_args(gmhc_ctx* c, int iterate) {
     a.glw[k] = c->glw[k];
   }
   a.ps = std::max<int64_t>(c->np, 1);
+  a.precision = c->cfg.precision;
   a.x = c->x[0];
   a.xn = c->x2[0];
   a.P = c->P[0];

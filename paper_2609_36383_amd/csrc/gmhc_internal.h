@@ -49,14 +49,16 @@ struct OrbitArgs {
   int deposit;           // 1: deposit the orbit current
   int ngl;
   double glx[kMaxGL], glw[kMaxGL];
-  // particle SoA blocks, component c of particle i at [c * ps + i]
+  // particle SoA blocks, component c of particle i at [c * ps + i].  Positions are
+  // FP64; P, q and v are FP64, or FP32 in the FP32-bulk precision mode.
   int64_t ps;
+  int precision;         // GMHC_FP64 (0) or GMHC_FP32_BULK (1)
   const double* x;       // [d]
-  const double* P;       // [3]
-  const double* q;       // [1]
-  double* v;             // [3] in: v_in warm start; out: v_out of the final evaluation
+  const void* P;         // [3]
+  const void* q;         // [1]
+  void* v;               // [3] in: v_in warm start; out: v_out of the final evaluation
   double* xn;            // [d] out: wrapped x^n + dt v_in
-  double* Pn;            // [3] out: P^{n+1}
+  void* Pn;              // [3] out: P^{n+1}
   int32_t* iters;        // out: inner evaluations
   // mesh arrays, component stride Ng
   const double* trial;   // [d+6]: grad_h phi^{n+1/2} (d), A^{n+1} (3), U^{n+1/2} (3)

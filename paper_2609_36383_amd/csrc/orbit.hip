@@ -18,10 +18,16 @@
 // Memory layout on chip.  Particles arrive sorted by cell, so a workgroup's
 // particles sit in a small box of cells.  Each workgroup stages the mesh fields of
 // that box plus a halo of two nodes (stencil reach one node, orbit travel below one
-// cell) in LDS, and accumulates its current deposit in an LDS tile of the same box,
-// flushed to HBM with one atomic per tile node and component.  Orbits whose stencil
-// leaves the tile, and workgroups whose box does not fit, read and deposit through
-// global memory instead.
+// cell) in LDS, and accumulates its current deposit in an FP64 LDS tile of the same
+// box, flushed to HBM with one atomic per tile node and component.  Orbits whose
+// stencil leaves the tile, and workgroups whose box does not fit, read and deposit
+// through global memory instead.
+//
+// Arithmetic.  The bulk type R (double, or float in the FP32-bulk mode) carries the
+// particle state, the staged fields, the quadrature and the push; positions stay
+// FP64 and the orbit geometry is taken relative to the particle's nearest node, so
+// FP32 keeps sub-cell resolution.  The deposit tile, the current and every
+// reduction (kinetic energy, work, chain-rule residual) are FP64.
 #include <limits.h>
 #include <math.h>
 
@@ -40,37 +46,53 @@ __device__ __forceinline__ int wrapi(int i, int n) {
 
 __device__ __forceinline__ int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
-// Quadratic B-spline weights of nodes j-1, j, j+1 at offset f = xi - j in [-1/2, 1/2]
-// and their x-derivatives (inverse spacing ih).
-__device__ __forceinline__ void bw(double f, double w[3]) {
-  const double a = 0.5 - f, b = 0.5 + f;
-  w[0] = 0.5 * a * a;
-  w[1] = 0.75 - f * f;
-  w[2] = 0.5 * b * b;
+// Reciprocal and square roots: hardware estimates refined by Newton / Goldschmidt
+// steps to full FP64 precision; single hardware instructions in FP32.
+__device__ __forceinline__ double rcp_(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  double e = fma(-x, r, 1.0);
+  r = fma(r, e, r);
+  e = fma(-x, r, 1.0);
+  return fma(r, e, r);
 }
-__device__ __forceinline__ void bdw(double f, double ih, double dw[3]) {
-  dw[0] = (f - 0.5) * ih;
-  dw[1] = -2.0 * f * ih;
-  dw[2] = (0.5 + f) * ih;
-}
+__device__ __forceinline__ float rcp_(float x) { return __builtin_amdgcn_rcpf(x); }
 
-// Weight and x-derivative of the single node c (0, 1, 2 for j-1, j, j+1) at offset f.
-__device__ __forceinline__ double bw1(double f, int c) {
-  const double a = 0.5 - f, b = 0.5 + f;
-  return c == 0 ? 0.5 * a * a : (c == 1 ? 0.75 - f * f : 0.5 * b * b);
+// sqrt(a) and 1/sqrt(a) for a >= 1e-300 (normal, positive).
+__device__ __forceinline__ void sqrt_rsq(double a, double& s, double& rs) {
+  const double y = __builtin_amdgcn_rsq(a);
+  double g = a * y, h = 0.5 * y;
+  double r = fma(-g, h, 0.5);
+  g = fma(g, r, g);
+  h = fma(h, r, h);
+  r = fma(-g, h, 0.5);
+  g = fma(g, r, g);
+  h = fma(h, r, h);
+  const double d = fma(-g, g, a);
+  s = fma(d, h, g);
+  rs = 2.0 * h;
 }
-__device__ __forceinline__ double bdw1(double f, int c) { return c == 0 ? f - 0.5 : (c == 1 ? -2.0 * f : 0.5 + f); }
+__device__ __forceinline__ void sqrt_rsq(float a, float& s, float& rs) {
+  s = __builtin_amdgcn_sqrtf(a);
+  rs = __builtin_amdgcn_rsqf(a);
+}
+template <class R>
+__device__ __forceinline__ R sqrt_(R a) {
+  R s, rs;
+  sqrt_rsq(a, s, rs);
+  return s;
+}
 
 // Workgroup tile: box of unwrapped node coordinates [o, o + E) per axis (uniform).
 struct Tile {
   int o[3];
   int E[3];
   int nodes;
-  int ok;  // 1: fields staged in LDS
+  int ok;     // 1: fields staged in LDS
+  int joff;   // double offset of the current tile in the dynamic LDS block
 };
 
 // Fields of the staged tile: 0..D-1 grad phi, D..D+2 A^n, D+3..D+5 A^{n+1},
-// D+6..D+8 U^{n+1/2}; the current tile (3 components) follows the fields.
+// D+6..D+8 U^{n+1/2}; the FP64 current tile (3 components) follows the fields.
 template <int D>
 __device__ __forceinline__ constexpr int nfields() { return D + 9; }
 
@@ -82,44 +104,38 @@ __device__ __forceinline__ const double* gfield(const OrbitArgs& a, int f) {
   return a.trial + (int64_t)(f - 3) * Ng;
 }
 
-// Node-index addressing of one 3^D stencil, either into the LDS tile or into HBM.
-template <int D, bool LDS>
-struct Stencil {
-  int ix[3], iy[3], iz[3];  // per-axis contributions, summed per node
-  __device__ __forceinline__ void set(const Mesh& M, const Tile& t, const int jn[3]) {
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      if (LDS) {
-        ix[c] = jn[0] + c - 1 - t.o[0];
-        iy[c] = D > 1 ? t.E[0] * (jn[1] + c - 1 - t.o[1]) : 0;
-        iz[c] = D > 2 ? t.E[0] * t.E[1] * (jn[2] + c - 1 - t.o[2]) : 0;
-      } else {
-        ix[c] = wrapi(jn[0] + c - 1, M.n[0]);
-        iy[c] = D > 1 ? M.n[0] * wrapi(jn[1] + c - 1, M.n[1]) : 0;
-        iz[c] = D > 2 ? M.n[0] * M.n[1] * wrapi(jn[2] + c - 1, M.n[2]) : 0;
-      }
-    }
-  }
-  __device__ __forceinline__ int node(int cx, int cy, int cz) const { return ix[cx] + iy[cy] + iz[cz]; }
-  // offset of stencil row (cy, cz) computed directly (no indexing by a loop variable)
-  __device__ __forceinline__ int row(const Mesh& M, const Tile& t, const int jn[3], int cy, int cz) const {
-    if (LDS)
-      return (D > 1 ? t.E[0] * (jn[1] + cy - 1 - t.o[1]) : 0) +
-             (D > 2 ? t.E[0] * t.E[1] * (jn[2] + cz - 1 - t.o[2]) : 0);
-    return (D > 1 ? M.n[0] * wrapi(jn[1] + cy - 1, M.n[1]) : 0) +
-           (D > 2 ? M.n[0] * M.n[1] * wrapi(jn[2] + cz - 1, M.n[2]) : 0);
-  }
-};
-
-template <int D, bool LDS>
-__device__ __forceinline__ double ld(const OrbitArgs& a, const Tile& t, int f, int node) {
+template <int D, class R, bool LDS>
+__device__ __forceinline__ R ld(const OrbitArgs& a, const Tile& t, int f, int node) {
   if (LDS) {
-    HIP_DYNAMIC_SHARED(double, s_tile);
+    HIP_DYNAMIC_SHARED(double, s_dyn);
+    const R* s_tile = reinterpret_cast<const R*>(s_dyn);
     return s_tile[f * t.nodes + node];
   } else {
-    return gfield<D>(a, f)[node];
+    return (R)gfield<D>(a, f)[node];
   }
 }
+
+// Node index of stencil offsets (cx, cy, cz) around the absolute node jn: into the LDS
+// tile or into the periodic mesh.
+template <int D, bool LDS>
+struct Stencil {
+  int ix[3];
+  int base_y, base_z;  // unwrapped or tile-relative row coordinates of offset 0
+  const Mesh* M;
+  const Tile* t;
+  __device__ __forceinline__ Stencil(const Mesh& m, const Tile& tt, const int jn[3]) : M(&m), t(&tt) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) ix[c] = LDS ? jn[0] + c - 1 - tt.o[0] : wrapi(jn[0] + c - 1, m.n[0]);
+    base_y = LDS ? jn[1] - 1 - tt.o[1] : jn[1] - 1;
+    base_z = LDS ? jn[2] - 1 - tt.o[2] : jn[2] - 1;
+  }
+  __device__ __forceinline__ int row(int cy, int cz) const {
+    if (LDS)
+      return (D > 1 ? t->E[0] * (base_y + cy) : 0) + (D > 2 ? t->E[0] * t->E[1] * (base_z + cz) : 0);
+    return (D > 1 ? M->n[0] * wrapi(base_y + cy, M->n[1]) : 0) +
+           (D > 2 ? M->n[0] * M->n[1] * wrapi(base_z + cz, M->n[2]) : 0);
+  }
+};
 
 template <int D>
 __device__ __forceinline__ bool inside(const Tile& t, const int jn[3]) {
@@ -129,275 +145,340 @@ __device__ __forceinline__ bool inside(const Tile& t, const int jn[3]) {
   return r;
 }
 
-// Visit the knot-split segments [sa, sb] of the orbit xi(s) = xi0 + s dxi, s in [0,1].
-// Crossings of all axes are merged on the fly (each axis' crossings are monotone in s).
-template <int D, class F>
-__device__ __forceinline__ void for_each_segment(const double* xi0, const double* dxi, F&& f) {
-  double knot[3], next[3], stp[3];
+// Quadratic B-spline weights of nodes j-1, j, j+1 at local offset f in [-1/2, 1/2] and
+// their derivatives with respect to xi (times h they are d/dx).
+template <class R>
+__device__ __forceinline__ void bw(R f, R w[3], R dw[3]) {
+  const R a = R(0.5) - f, b = R(0.5) + f;
+  w[0] = R(0.5) * a * a;
+  w[1] = R(0.75) - f * f;
+  w[2] = R(0.5) * b * b;
+  dw[0] = -a;
+  dw[1] = R(-2.0) * f;
+  dw[2] = b;
+}
+// weight and derivative of the single stencil node c (0, 1, 2)
+template <class R>
+__device__ __forceinline__ void bw1(R f, int c, R& w, R& dw) {
+  const R t = f - R(c - 1);  // offset from node j + c - 1
+  const R at = fabs(t);
+  const R o = R(1.5) - at;
+  const R sg = t > R(0) ? R(1) : R(-1);
+  w = c == 1 ? R(0.75) - t * t : R(0.5) * o * o;
+  dw = c == 1 ? R(-2.0) * t : -sg * o;
+}
+
+// Orbit geometry relative to the particle's node j0: xi(s) = j0 + f0 + s del.
+// Visits the knot-split segments [sa, sb] of s in [0, 1]; each axis' crossings of the
+// half-integer knots are monotone in s and are merged on the fly.
+template <int D, class R, class F>
+__device__ __forceinline__ void for_each_segment(const R* f0, const R* del, F&& f) {
+  R knot[3], next[3], stp[3], rd[3];
 #pragma unroll
   for (int l = 0; l < D; ++l) {
-    if (dxi[l] > 0.0) {
-      knot[l] = floor(xi0[l] - 0.5) + 1.5;
-      stp[l] = 1.0;
-      next[l] = (knot[l] - xi0[l]) / dxi[l];
-    } else if (dxi[l] < 0.0) {
-      knot[l] = ceil(xi0[l] - 0.5) - 0.5;
-      stp[l] = -1.0;
-      next[l] = (knot[l] - xi0[l]) / dxi[l];
+    rd[l] = del[l] != R(0) ? rcp_(del[l]) : R(0);
+    if (del[l] > R(0)) {
+      knot[l] = floor(f0[l] - R(0.5)) + R(1.5);
+      stp[l] = R(1);
+      next[l] = (knot[l] - f0[l]) * rd[l];
+    } else if (del[l] < R(0)) {
+      knot[l] = ceil(f0[l] - R(0.5)) - R(0.5);
+      stp[l] = R(-1);
+      next[l] = (knot[l] - f0[l]) * rd[l];
     } else {
-      knot[l] = 0.0;
-      stp[l] = 0.0;
-      next[l] = 2.0;
+      knot[l] = R(0);
+      stp[l] = R(0);
+      next[l] = R(2);
     }
   }
-  double sa = 0.0;
+  R sa = R(0);
 #pragma unroll 1
   for (int it = 0; it <= D * kMaxCross; ++it) {
-    double sb = 1.0;
+    R sb = R(1);
 #pragma unroll
     for (int l = 0; l < D; ++l) sb = (next[l] < sb) ? next[l] : sb;
     if (sb > sa) f(sa, sb);
-    if (sb >= 1.0) break;
+    if (sb >= R(1)) break;
 #pragma unroll
     for (int l = 0; l < D; ++l)
       if (next[l] == sb) {
         knot[l] += stp[l];
-        next[l] = (knot[l] - xi0[l]) / dxi[l];
+        next[l] = (knot[l] - f0[l]) * rd[l];
       }
     sa = sb;
   }
 }
 
-template <int D>
-__device__ __forceinline__ void nearest(const double* xi, int jn[3]) {
-#pragma unroll
-  for (int l = 0; l < 3; ++l) jn[l] = (l < D) ? (int)floor(xi[l] + 0.5) : 0;
-}
-
-// Point interpolant sum_g F_g S_g(x) of A (field base fb = D: A^n, D+3: A^{n+1}).
-template <int D, bool LDS>
-__device__ __forceinline__ void interp3_at(const OrbitArgs& a, const Tile& t, int fb, const double* xi,
-                                           const int jn[3], double out[3]) {
-  double w[3][3];
+// Nearest node of the segment point s: relative offsets k and local offset at s = 0.
+template <int D, class R>
+__device__ __forceinline__ void seg_base(const int j0[3], const R* f0, const R* del, R sm, int jn[3], R fs[3]) {
 #pragma unroll
   for (int l = 0; l < 3; ++l) {
-    if (l < D)
-      bw(xi[l] - (double)jn[l], w[l]);
-    else
-      w[l][0] = 1.0;
+    if (l < D) {
+      const R xm = f0[l] + sm * del[l];
+      const int k = (int)floor(xm + R(0.5));
+      jn[l] = j0[l] + k;
+      fs[l] = f0[l] - R(k);
+    } else {
+      jn[l] = 0;
+      fs[l] = R(0);
+    }
   }
-  Stencil<D, LDS> st;
-  st.set(a.M, t, jn);
-  out[0] = out[1] = out[2] = 0.0;
+}
+
+template <int NGL>
+struct GL {
+  // compile-time point count; NGL == 0 runs the runtime count
+  __device__ static constexpr int n(int runtime) { return NGL > 0 ? NGL : runtime; }
+};
+
+// Point interpolant sum_g F_g S_g at node jn with local offsets f (field base fb).
+template <int D, class R, bool LDS>
+__device__ __forceinline__ void interp3_at(const OrbitArgs& a, const Tile& t, int fb, const int jn[3],
+                                           const R f[3], R out[3]) {
+  R w[3][3], dw[3][3];
+#pragma unroll
+  for (int l = 0; l < 3; ++l) {
+    if (l < D) {
+      bw(f[l], w[l], dw[l]);
+    } else {
+      w[l][0] = R(1);
+    }
+  }
+  Stencil<D, LDS> st(a.M, t, jn);
+  out[0] = out[1] = out[2] = R(0);
   constexpr int NY = D > 1 ? 3 : 1, NZ = D > 2 ? 3 : 1;
 #pragma unroll
   for (int cz = 0; cz < NZ; ++cz)
 #pragma unroll
     for (int cy = 0; cy < NY; ++cy) {
-      const double wyz = w[1][cy] * w[2][cz];
+      const R wyz = w[1][cy] * w[2][cz];
+      const int rowoff = st.row(cy, cz);
 #pragma unroll
       for (int cx = 0; cx < 3; ++cx) {
-        const double S = w[0][cx] * wyz;
-        const int g = st.node(cx, cy, cz);
+        const R S = w[0][cx] * wyz;
+        const int g = st.ix[cx] + rowoff;
 #pragma unroll
-        for (int c = 0; c < 3; ++c) out[c] += S * ld<D, LDS>(a, t, fb + c, g);
+        for (int c = 0; c < 3; ++c) out[c] += S * ld<D, R, LDS>(a, t, fb + c, g);
       }
     }
 }
 
-template <int D>
-__device__ __forceinline__ void interp3(const OrbitArgs& a, const Tile& t, int fb, const double* xi,
-                                        double out[3]) {
+template <int D, class R>
+__device__ __forceinline__ void interp3(const OrbitArgs& a, const Tile& t, int fb, const int j0[3], const R* fr,
+                                        R out[3]) {
   int jn[3];
-  nearest<D>(xi, jn);
+  R f[3];
+#pragma unroll
+  for (int l = 0; l < 3; ++l) {
+    if (l < D) {
+      const int k = (int)floor(fr[l] + R(0.5));
+      jn[l] = j0[l] + k;
+      f[l] = fr[l] - R(k);
+    } else {
+      jn[l] = 0;
+      f[l] = R(0);
+    }
+  }
   if (inside<D>(t, jn))
-    interp3_at<D, true>(a, t, fb, xi, jn, out);
+    interp3_at<D, R, true>(a, t, fb, jn, f, out);
   else
-    interp3_at<D, false>(a, t, fb, xi, jn, out);
+    interp3_at<D, R, false>(a, t, fb, jn, f, out);
 }
 
 // Quadrature of one knot segment for the gathers grad-phi-bar and D.
 //
-// The integrated weights of the stencil nodes of one x-row (fixed y, z offset) are
-// accumulated over the Gauss points first,
-//   S-bar_g = sum_q w_q S_g,  Xa_g = sum_q w_q (1-s_q) d_x S_g,  Xb_g = sum_q w_q s_q d_x S_g
-// (likewise Ya, Yb for d_y and Za, Zb for d_z), then contracted once with the node
-// values: grad-phi-bar += S-bar_g (grad phi)_g, D_l. += Xa_g A^n_{l,g} + Xb_g A^{n+1}_{l,g}.
-// This is the same quadrature summed in a different order: each field value is read
-// once per segment instead of once per Gauss point, and only one row of accumulators
-// is live at a time.
-template <int D, bool LDS>
-__device__ __forceinline__ void eval_segment(const OrbitArgs& a, const Tile& t, const double* xi0,
-                                             const double* dxi, const int jn[3], double sa, double sb,
-                                             double gp[3], double Dm[3][3]) {
-  const Mesh& M = a.M;
-  const double len = sb - sa;
-  Stencil<D, LDS> st;
-  st.set(M, t, jn);
-  constexpr int NR = (D > 1 ? 3 : 1) * (D > 2 ? 3 : 1);  // stencil rows
+// The integrated weights of the stencil nodes are accumulated over the Gauss points
+// first (per z-plane in 3D),
+//   S_g = sum_q w_q S_g(s_q),  X0_g = sum_q w_q (1-s_q) dS_g/dxi,  X1_g = sum_q w_q s_q dS_g/dxi
+// (likewise Y0, Y1 and Z0, Z1), then contracted once with the node values:
+//   grad-phi-bar += S_g (grad phi)_g,  D_l. += X0_g A^n_{l,g} + X1_g A^{n+1}_{l,g}.
+// This is the same quadrature summed in a different order; each field value is read
+// once per segment.  D is left in xi units and scaled by 1/h afterwards.
+template <int D, int NGL, class R, bool LDS>
+__device__ __forceinline__ void eval_segment(const OrbitArgs& a, const Tile& t, const R* gx, const R* gw,
+                                             const int jn[3], const R fs[3], const R* del, R sa, R sb,
+                                             R gp[3], R Dm[3][3]) {
+  const R len = sb - sa;
+  Stencil<D, LDS> st(a.M, t, jn);
+  constexpr int NY = D > 1 ? 3 : 1;
+  constexpr int NP = D > 2 ? 3 : 1;
 #pragma unroll 1
-  for (int r = 0; r < NR; ++r) {
-    const int cy = D > 1 ? r % 3 : 0, cz = D > 2 ? r / 3 : 0;
-    double Sb[3] = {0, 0, 0}, Xa[3] = {0, 0, 0}, Xb[3] = {0, 0, 0};
-    double Ya[3] = {0, 0, 0}, Yb[3] = {0, 0, 0}, Za[3] = {0, 0, 0}, Zb[3] = {0, 0, 0};
-#pragma unroll 1
-    for (int qp = 0; qp < a.ngl; ++qp) {
-      const double s = sa + len * a.glx[qp];
-      const double wq = len * a.glw[qp];
-      const double al = wq * (1.0 - s), be = wq * s;
-      double wx[3], dwx[3];
-      const double fx = xi0[0] + s * dxi[0] - (double)jn[0];
-      bw(fx, wx);
-      bdw(fx, M.inv_h[0], dwx);
-      // this row's node weight and derivative along the other axes
-      double wy = 1.0, dwy = 0.0, wz = 1.0, dwz = 0.0;
-      if (D > 1) {
-        const double fy = xi0[1] + s * dxi[1] - (double)jn[1];
-        wy = bw1(fy, cy);
-        dwy = bdw1(fy, cy) * M.inv_h[1];
-      }
-      if (D > 2) {
-        const double fz = xi0[2] + s * dxi[2] - (double)jn[2];
-        wz = bw1(fz, cz);
-        dwz = bdw1(fz, cz) * M.inv_h[2];
-      }
-      const double wyz = wy * wz;
-      const double sq = wq * wyz, xa = al * wyz, xb = be * wyz;
-      const double ya = al * dwy * wz, yb = be * dwy * wz;
-      const double za = al * wy * dwz, zb = be * wy * dwz;
+  for (int cz = 0; cz < NP; ++cz) {
+    R S[NY][3], X0[NY][3], X1[NY][3], Y0[NY][3], Y1[NY][3], Z0[NY][3], Z1[NY][3];
 #pragma unroll
-      for (int cx = 0; cx < 3; ++cx) {
-        Sb[cx] += wx[cx] * sq;
-        Xa[cx] += dwx[cx] * xa;
-        Xb[cx] += dwx[cx] * xb;
-        if (D > 1) {
-          Ya[cx] += wx[cx] * ya;
-          Yb[cx] += wx[cx] * yb;
-        }
-        if (D > 2) {
-          Za[cx] += wx[cx] * za;
-          Zb[cx] += wx[cx] * zb;
+    for (int b = 0; b < NY; ++b)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) S[b][c] = X0[b][c] = X1[b][c] = Y0[b][c] = Y1[b][c] = Z0[b][c] = Z1[b][c] = R(0);
+    const int nq = GL<NGL>::n(a.ngl);
+#pragma unroll
+    for (int q = 0; q < nq; ++q) {
+      const R s = sa + len * gx[q];
+      const R wq = len * gw[q];
+      const R b1 = wq * s, a1 = wq - b1;  // w_q s and w_q (1 - s)
+      R wx[3], dwx[3], wy[3] = {R(1), R(0), R(0)}, dwy[3] = {R(0), R(0), R(0)};
+      bw(fs[0] + s * del[0], wx, dwx);
+      if (D > 1) bw(fs[1] + s * del[1], wy, dwy);
+      R wz = R(1), dwz = R(0);
+      if (D > 2) bw1(fs[2] + s * del[2], cz, wz, dwz);
+      const R wqz = wq * wz, a1z = a1 * wz, b1z = b1 * wz;
+      const R a1d = a1 * dwz, b1d = b1 * dwz;
+#pragma unroll
+      for (int b = 0; b < NY; ++b) {
+        const R sw = wqz * wy[b], xw0 = a1z * wy[b], xw1 = b1z * wy[b];
+        const R yw0 = a1z * dwy[b], yw1 = b1z * dwy[b];
+        const R zw0 = a1d * wy[b], zw1 = b1d * wy[b];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          S[b][c] += sw * wx[c];
+          X0[b][c] += xw0 * dwx[c];
+          X1[b][c] += xw1 * dwx[c];
+          if (D > 1) {
+            Y0[b][c] += yw0 * wx[c];
+            Y1[b][c] += yw1 * wx[c];
+          }
+          if (D > 2) {
+            Z0[b][c] += zw0 * wx[c];
+            Z1[b][c] += zw1 * wx[c];
+          }
         }
       }
     }
-    const int rowoff = st.row(M, t, jn, cy, cz);
 #pragma unroll
-    for (int cx = 0; cx < 3; ++cx) {
-      const int g = st.ix[cx] + rowoff;
+    for (int b = 0; b < NY; ++b) {
+      const int rowoff = st.row(b, cz);
 #pragma unroll
-      for (int l = 0; l < D; ++l) gp[l] += Sb[cx] * ld<D, LDS>(a, t, l, g);
+      for (int c = 0; c < 3; ++c) {
+        const int g = st.ix[c] + rowoff;
 #pragma unroll
-      for (int l = 0; l < 3; ++l) {
-        const double a0 = ld<D, LDS>(a, t, D + l, g), a1 = ld<D, LDS>(a, t, D + 3 + l, g);
-        Dm[l][0] += Xa[cx] * a0 + Xb[cx] * a1;
-        if (D > 1) Dm[l][1] += Ya[cx] * a0 + Yb[cx] * a1;
-        if (D > 2) Dm[l][2] += Za[cx] * a0 + Zb[cx] * a1;
+        for (int l = 0; l < D; ++l) gp[l] += S[b][c] * ld<D, R, LDS>(a, t, l, g);
+#pragma unroll
+        for (int l = 0; l < 3; ++l) {
+          const R a0 = ld<D, R, LDS>(a, t, D + l, g), a1v = ld<D, R, LDS>(a, t, D + 3 + l, g);
+          Dm[l][0] += X0[b][c] * a0 + X1[b][c] * a1v;
+          if (D > 1) Dm[l][1] += Y0[b][c] * a0 + Y1[b][c] * a1v;
+          if (D > 2) Dm[l][2] += Z0[b][c] * a0 + Z1[b][c] * a1v;
+        }
       }
     }
   }
 }
 
+template <class R>
 struct EvalOut {
-  double vout[3];
-  double Pn1[3];
-  double pn1[3];
-  double Ap[3];
-  double gp[3];
-  double Dm[3][3];
+  R vout[3];
+  R Pn1[3];
+  R pn1[3];
+  R Ap[3];
+  R gp[3];
+  R Dm[3][3];
   int nseg;
 };
 
-__device__ __forceinline__ double gam(const double p[3], double inv_mk) {
-  const double ux = p[0] * inv_mk, uy = p[1] * inv_mk, uz = p[2] * inv_mk;
-  return sqrt(1.0 + ux * ux + uy * uy + uz * uz);
-}
+// Constants of one particle.
+template <class R>
+struct PConst {
+  R q, m, inv_mk, mk, tc, half_qdt;
+};
 
 // One orbit evaluation of one particle.
-template <int D>
-__device__ void evaluate(const OrbitArgs& a, const Tile& t, const double* xi0, const double P[3], double q,
-                         double m, const double Am[3], const double vin[3], EvalOut& o) {
+template <int D, int NGL, class R>
+__device__ void evaluate(const OrbitArgs& a, const Tile& t, const R* gx, const R* gw, const int j0[3], const R* f0,
+                         const R P[3], const PConst<R>& pc, const R Am[3], const R vin[3], EvalOut<R>& o) {
   const Mesh& M = a.M;
-  double dxi[3] = {0.0, 0.0, 0.0};
+  R del[3] = {R(0), R(0), R(0)};
 #pragma unroll
-  for (int l = 0; l < D; ++l) dxi[l] = a.dt * vin[l] * M.inv_h[l];
-  double gp[3] = {0.0, 0.0, 0.0};
-  double Dm[3][3];
+  for (int l = 0; l < D; ++l) del[l] = R(a.dt) * vin[l] * R(M.inv_h[l]);
+  R gp[3] = {R(0), R(0), R(0)};
+  R Dm[3][3];
 #pragma unroll
   for (int l = 0; l < 3; ++l)
 #pragma unroll
-    for (int j = 0; j < 3; ++j) Dm[l][j] = 0.0;
+    for (int j = 0; j < 3; ++j) Dm[l][j] = R(0);
   int nseg = 0;
-  for_each_segment<D>(xi0, dxi, [&](double sa, double sb) {
+  for_each_segment<D, R>(f0, del, [&](R sa, R sb) {
     ++nseg;
-    const double sm = 0.5 * (sa + sb);
-    double xm[3];
-#pragma unroll
-    for (int l = 0; l < D; ++l) xm[l] = xi0[l] + sm * dxi[l];
     int jn[3];
-    nearest<D>(xm, jn);
+    R fs[3];
+    seg_base<D, R>(j0, f0, del, R(0.5) * (sa + sb), jn, fs);
     if (inside<D>(t, jn))
-      eval_segment<D, true>(a, t, xi0, dxi, jn, sa, sb, gp, Dm);
+      eval_segment<D, NGL, R, true>(a, t, gx, gw, jn, fs, del, sa, sb, gp, Dm);
     else
-      eval_segment<D, false>(a, t, xi0, dxi, jn, sa, sb, gp, Dm);
+      eval_segment<D, NGL, R, false>(a, t, gx, gw, jn, fs, del, sa, sb, gp, Dm);
   });
+#pragma unroll
+  for (int j = 0; j < D; ++j) {
+    const R ih = R(M.inv_h[j]);
+#pragma unroll
+    for (int l = 0; l < 3; ++l) Dm[l][j] *= ih;
+  }
 
   // endpoint interpolant A^+ = A_h^{n+1}(x^n + dt v_in)
-  double xie[3] = {0.0, 0.0, 0.0};
+  R fe[3] = {R(0), R(0), R(0)};
 #pragma unroll
-  for (int l = 0; l < D; ++l) xie[l] = xi0[l] + dxi[l];
-  double Ap[3];
-  interp3<D>(a, t, D + 3, xie, Ap);
+  for (int l = 0; l < D; ++l) fe[l] = f0[l] + del[l];
+  R Ap[3];
+  interp3<D, R>(a, t, D + 3, j0, fe, Ap);
 
-  const double dt = a.dt, kappa = a.kappa;
-  double Aep[3], kick[3], pm[3];
+  const R q = pc.q;
+  R Aep[3], kick[3], pm[3];
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
-    Aep[c] = 0.5 * (Am[c] + Ap[c]);
-    double Dv = 0.0;
+    Aep[c] = R(0.5) * (Am[c] + Ap[c]);
+    R Dv = R(0);
 #pragma unroll
     for (int j = 0; j < D; ++j) Dv += Dm[c][j] * vin[j];
-    kick[c] = 0.5 * q * dt * (Dv - gp[c]);
+    kick[c] = pc.half_qdt * (Dv - gp[c]);
     pm[c] = P[c] - q * Aep[c] + kick[c];
   }
   // B_eff of the skew part K = D^T - D (D zero-padded to 3x3): (K23, -K13, K12)
-  const double Beff[3] = {Dm[2][1] - Dm[1][2], -(Dm[2][0] - Dm[0][2]), Dm[1][0] - Dm[0][1]};
+  const R Beff[3] = {Dm[2][1] - Dm[1][2], -(Dm[2][0] - Dm[0][2]), Dm[1][0] - Dm[0][1]};
   // normalized HC map
-  const double inv_mk = 1.0 / (m * kappa);
-  const double um[3] = {pm[0] * inv_mk, pm[1] * inv_mk, pm[2] * inv_mk};
-  const double tc = q * dt / (2.0 * m);
-  const double tau[3] = {tc * Beff[0], tc * Beff[1], tc * Beff[2]};
-  const double gm2 = 1.0 + um[0] * um[0] + um[1] * um[1] + um[2] * um[2];
-  const double tau2 = tau[0] * tau[0] + tau[1] * tau[1] + tau[2] * tau[2];
-  const double ut = um[0] * tau[0] + um[1] * tau[1] + um[2] * tau[2];
-  const double sig = gm2 - tau2;
-  const double X = tau2 + ut * ut;
-  const double R = sqrt(sig * sig + 4.0 * X);
-  const double g2 = (sig >= 0.0) ? 0.5 * (sig + R) : 2.0 * X / (R - sig);
-  const double ig = 1.0 / sqrt(g2);
-  const double tv[3] = {tau[0] * ig, tau[1] * ig, tau[2] * ig};
-  const double t2 = tv[0] * tv[0] + tv[1] * tv[1] + tv[2] * tv[2];
-  const double sf = 2.0 / (1.0 + t2);
-  const double sv[3] = {sf * tv[0], sf * tv[1], sf * tv[2]};
-  const double us[3] = {um[0] + (um[1] * tv[2] - um[2] * tv[1]), um[1] + (um[2] * tv[0] - um[0] * tv[2]),
-                        um[2] + (um[0] * tv[1] - um[1] * tv[0])};
-  const double up[3] = {um[0] + (us[1] * sv[2] - us[2] * sv[1]), um[1] + (us[2] * sv[0] - us[0] * sv[2]),
-                        um[2] + (us[0] * sv[1] - us[1] * sv[0])};
-  const double mk = m * kappa;
-  const double pp[3] = {mk * up[0], mk * up[1], mk * up[2]};
-  double pn[3], Pn1[3], pn1[3];
+  const R um[3] = {pm[0] * pc.inv_mk, pm[1] * pc.inv_mk, pm[2] * pc.inv_mk};
+  const R tau[3] = {pc.tc * Beff[0], pc.tc * Beff[1], pc.tc * Beff[2]};
+  const R um2 = um[0] * um[0] + um[1] * um[1] + um[2] * um[2];
+  const R tau2 = tau[0] * tau[0] + tau[1] * tau[1] + tau[2] * tau[2];
+  const R ut = um[0] * tau[0] + um[1] * tau[1] + um[2] * tau[2];
+  const R sig = R(1) + um2 - tau2;
+  const R X = tau2 + ut * ut;
+  R tv[3];
+  if (X > R(0)) {
+    const R Rr = sqrt_(sig * sig + R(4) * X);
+    const R g2 = (sig >= R(0)) ? R(0.5) * (sig + Rr) : R(2) * X * rcp_(Rr - sig);
+    R gh, ig;
+    sqrt_rsq(g2, gh, ig);
+    tv[0] = tau[0] * ig;
+    tv[1] = tau[1] * ig;
+    tv[2] = tau[2] * ig;
+  } else {
+    tv[0] = tv[1] = tv[2] = R(0);  // no magnetic generator: the rotation is the identity
+  }
+  const R t2 = tv[0] * tv[0] + tv[1] * tv[1] + tv[2] * tv[2];
+  const R sf = R(2) * rcp_(R(1) + t2);
+  const R sv[3] = {sf * tv[0], sf * tv[1], sf * tv[2]};
+  const R us[3] = {um[0] + (um[1] * tv[2] - um[2] * tv[1]), um[1] + (um[2] * tv[0] - um[0] * tv[2]),
+                   um[2] + (um[0] * tv[1] - um[1] * tv[0])};
+  const R up[3] = {um[0] + (us[1] * sv[2] - us[2] * sv[1]), um[1] + (us[2] * sv[0] - us[0] * sv[2]),
+                   um[2] + (us[0] * sv[1] - us[1] * sv[0])};
+  const R pp[3] = {pc.mk * up[0], pc.mk * up[1], pc.mk * up[2]};
+  R pn[3], Pn1[3], pn1[3];
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
     Pn1[c] = pp[c] + q * Aep[c] + kick[c];
     pn[c] = P[c] - q * Am[c];
     pn1[c] = Pn1[c] - q * Ap[c];
   }
-  // secant velocities and the orbit velocity
-  const double gm_ = gam(pm, inv_mk), gn = gam(pn, inv_mk), gn1 = gam(pn1, inv_mk), gp_ = gam(pp, inv_mk);
-  const double d1 = 1.0 / (m * (gm_ + gn)), d2 = 1.0 / (m * (gn1 + gp_));
+  // secant velocities V^dg and the orbit velocity
+  auto gam = [&](const R p[3]) {
+    const R ux = p[0] * pc.inv_mk, uy = p[1] * pc.inv_mk, uz = p[2] * pc.inv_mk;
+    return sqrt_(R(1) + ux * ux + uy * uy + uz * uz);
+  };
+  const R d1 = rcp_(pc.m * (gam(pm) + gam(pn)));
+  const R d2 = rcp_(pc.m * (gam(pn1) + gam(pp)));
   o.nseg = nseg;
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
-    o.vout[c] = 0.5 * ((pm[c] + pn[c]) * d1 + (pn1[c] + pp[c]) * d2);
+    o.vout[c] = R(0.5) * ((pm[c] + pn[c]) * d1 + (pn1[c] + pp[c]) * d2);
     o.Pn1[c] = Pn1[c];
     o.pn1[c] = pn1[c];
     o.Ap[c] = Ap[c];
@@ -407,73 +488,81 @@ __device__ void evaluate(const OrbitArgs& a, const Tile& t, const double* xi0, c
   }
 }
 
-// Deposit sweep of one segment, one stencil row at a time: S-bar over the row, U-bar
-// gather, current deposit (LDS tile or HBM atomics).
-template <int D, bool LDS>
-__device__ __forceinline__ void deposit_segment(const OrbitArgs& a, const Tile& t, const double* xi0,
-                                                const double* dxi, const int jn[3], double sa, double sb,
-                                                const double coef[3], bool do_dep, double Ub[3]) {
-  const double len = sb - sa;
-  Stencil<D, LDS> st;
-  st.set(a.M, t, jn);
-  HIP_DYNAMIC_SHARED(double, s_tile);
-  double* s_J = s_tile + nfields<D>() * t.nodes;
-  constexpr int NR = (D > 1 ? 3 : 1) * (D > 2 ? 3 : 1);
+// Deposit sweep of one segment: S-bar of the stencil, U-bar gather, current deposit
+// (FP64 LDS tile or FP64 HBM atomics).
+template <int D, int NGL, class R, bool LDS>
+__device__ __forceinline__ void deposit_segment(const OrbitArgs& a, const Tile& t, const R* gx, const R* gw,
+                                                const int jn[3], const R fs[3], const R* del, R sa, R sb,
+                                                const double coef[3], bool do_dep, R Ub[3]) {
+  const R len = sb - sa;
+  Stencil<D, LDS> st(a.M, t, jn);
+  HIP_DYNAMIC_SHARED(double, s_dyn);
+  double* s_J = s_dyn + t.joff;
+  constexpr int NY = D > 1 ? 3 : 1;
+  constexpr int NP = D > 2 ? 3 : 1;
 #pragma unroll 1
-  for (int r = 0; r < NR; ++r) {
-    const int cy = D > 1 ? r % 3 : 0, cz = D > 2 ? r / 3 : 0;
-    double acc[3] = {0.0, 0.0, 0.0};
-#pragma unroll 1
-    for (int qp = 0; qp < a.ngl; ++qp) {
-      const double s = sa + len * a.glx[qp];
-      const double wq = len * a.glw[qp];
-      double wx[3];
-      bw(xi0[0] + s * dxi[0] - (double)jn[0], wx);
-      double wyz = wq;
-      if (D > 1) wyz *= bw1(xi0[1] + s * dxi[1] - (double)jn[1], cy);
-      if (D > 2) wyz *= bw1(xi0[2] + s * dxi[2] - (double)jn[2], cz);
+  for (int cz = 0; cz < NP; ++cz) {
+    R S[NY][3];
 #pragma unroll
-      for (int cx = 0; cx < 3; ++cx) acc[cx] += wx[cx] * wyz;
+    for (int b = 0; b < NY; ++b)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) S[b][c] = R(0);
+    const int nq = GL<NGL>::n(a.ngl);
+#pragma unroll
+    for (int q = 0; q < nq; ++q) {
+      const R s = sa + len * gx[q];
+      const R wq = len * gw[q];
+      R wx[3], dwx[3], wy[3] = {R(1), R(0), R(0)}, dwy[3];
+      bw(fs[0] + s * del[0], wx, dwx);
+      if (D > 1) bw(fs[1] + s * del[1], wy, dwy);
+      R wz = R(1), dwz;
+      if (D > 2) bw1(fs[2] + s * del[2], cz, wz, dwz);
+      const R wqz = wq * wz;
+#pragma unroll
+      for (int b = 0; b < NY; ++b) {
+        const R sw = wqz * wy[b];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) S[b][c] += sw * wx[c];
+      }
     }
-    const int rowoff = st.row(a.M, t, jn, cy, cz);
 #pragma unroll
-    for (int cx = 0; cx < 3; ++cx) {
-      const int g = st.ix[cx] + rowoff;
-      const double Sb = acc[cx];
+    for (int b = 0; b < NY; ++b) {
+      const int rowoff = st.row(b, cz);
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
-        Ub[c] += Sb * ld<D, LDS>(a, t, D + 6 + c, g);
-        if (do_dep) {
-          if (LDS)
-            atomicAdd(s_J + c * t.nodes + g, coef[c] * Sb);
-          else
-            atomicAdd(a.J + (int64_t)c * a.M.Ng + g, coef[c] * Sb);
+        const int g = st.ix[c] + rowoff;
+        const R Sb = S[b][c];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+          Ub[k] += Sb * ld<D, R, LDS>(a, t, D + 6 + k, g);
+          if (do_dep) {
+            const double v = coef[k] * (double)Sb;
+            if (LDS)
+              atomicAdd(s_J + k * t.nodes + g, v);
+            else
+              atomicAdd(a.J + (int64_t)k * a.M.Ng + g, v);
+          }
         }
       }
     }
   }
 }
 
-// Deposit q v_out S-bar / dV along the orbit of v_in and gather U-bar.
-template <int D>
-__device__ void deposit_orbit(const OrbitArgs& a, const Tile& t, const double* xi0, const double vin[3],
-                              const double coef[3], bool do_dep, double Ub[3]) {
-  const Mesh& M = a.M;
-  double dxi[3] = {0.0, 0.0, 0.0};
+template <int D, int NGL, class R>
+__device__ void deposit_orbit(const OrbitArgs& a, const Tile& t, const R* gx, const R* gw, const int j0[3],
+                              const R* f0, const R vin[3], const double coef[3], bool do_dep, R Ub[3]) {
+  R del[3] = {R(0), R(0), R(0)};
 #pragma unroll
-  for (int l = 0; l < D; ++l) dxi[l] = a.dt * vin[l] * M.inv_h[l];
-  Ub[0] = Ub[1] = Ub[2] = 0.0;
-  for_each_segment<D>(xi0, dxi, [&](double sa, double sb) {
-    const double sm = 0.5 * (sa + sb);
-    double xm[3];
-#pragma unroll
-    for (int l = 0; l < D; ++l) xm[l] = xi0[l] + sm * dxi[l];
+  for (int l = 0; l < D; ++l) del[l] = R(a.dt) * vin[l] * R(a.M.inv_h[l]);
+  Ub[0] = Ub[1] = Ub[2] = R(0);
+  for_each_segment<D, R>(f0, del, [&](R sa, R sb) {
     int jn[3];
-    nearest<D>(xm, jn);
+    R fs[3];
+    seg_base<D, R>(j0, f0, del, R(0.5) * (sa + sb), jn, fs);
     if (inside<D>(t, jn))
-      deposit_segment<D, true>(a, t, xi0, dxi, jn, sa, sb, coef, do_dep, Ub);
+      deposit_segment<D, NGL, R, true>(a, t, gx, gw, jn, fs, del, sa, sb, coef, do_dep, Ub);
     else
-      deposit_segment<D, false>(a, t, xi0, dxi, jn, sa, sb, coef, do_dep, Ub);
+      deposit_segment<D, NGL, R, false>(a, t, gx, gw, jn, fs, del, sa, sb, coef, do_dep, Ub);
   });
 }
 
@@ -506,26 +595,41 @@ __device__ __forceinline__ int tile_to_global(const Mesh& M, const Tile& t, int 
   return wrapi(ux, M.n[0]) + M.n[0] * ((D > 1 ? wrapi(uy, M.n[1]) : 0) + M.n[1] * (D > 2 ? wrapi(uz, M.n[2]) : 0));
 }
 
-template <int D>
-__global__ __launch_bounds__(kBlock) void k_orbit(OrbitArgs a) {
+#ifndef GMHC_ORBIT_WAVES_PER_EU
+#define GMHC_ORBIT_WAVES_PER_EU 2
+#endif
+
+template <int D, int NGL, class R>
+__global__ __launch_bounds__(kBlock)
+__attribute__((amdgpu_waves_per_eu(GMHC_ORBIT_WAVES_PER_EU))) void k_orbit(OrbitArgs a) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const Mesh& M = a.M;
   const int64_t ps = a.ps;
-  HIP_DYNAMIC_SHARED(double, s_tile);
+  HIP_DYNAMIC_SHARED(double, s_dyn);
   __shared__ int s_mm[2 * (kBlock / 64)];
   constexpr int NF = nfields<D>();
+  const R* Pp = static_cast<const R*>(a.P);
+  const R* qp = static_cast<const R*>(a.q);
+  R* vp = static_cast<R*>(a.v);
+  R* Pnp = static_cast<R*>(a.Pn);
 
-  // ---- particle position and the workgroup's tile box
-  double x[3] = {0.0, 0.0, 0.0}, xi0[3] = {0.0, 0.0, 0.0};
+  // ---- particle position: nearest node j0 and offset f0 in [-1/2, 1/2)
+  double x[3] = {0.0, 0.0, 0.0};
+  int j0[3] = {0, 0, 0};
+  R f0[3] = {R(0), R(0), R(0)};
   bool valid = i < a.np;
   if (valid) {
 #pragma unroll
     for (int l = 0; l < D; ++l) {
       x[l] = a.x[l * ps + i];
-      xi0[l] = (x[l] - M.lo[l]) * M.inv_h[l];
-      valid = valid && isfinite(xi0[l]) && fabs(xi0[l]) < 1.0e8;
+      const double xi = (x[l] - M.lo[l]) * M.inv_h[l];
+      valid = valid && isfinite(xi) && fabs(xi) < 1.0e8;
+      const double jr = valid ? floor(xi + 0.5) : 0.0;
+      j0[l] = (int)jr;
+      f0[l] = valid ? (R)(xi - jr) : R(0);
     }
   }
+  // ---- the workgroup's tile box
   Tile t;
   int nodes = 1, ok = 1;
 #pragma unroll
@@ -535,8 +639,8 @@ __global__ __launch_bounds__(kBlock) void k_orbit(OrbitArgs a) {
   }
 #pragma unroll
   for (int l = 0; l < D; ++l) {
-    int lo = valid ? (int)floor(xi0[l] + 0.5) : INT_MAX;
-    int hi = valid ? (int)floor(xi0[l] + 0.5) : INT_MIN;
+    int lo = valid ? j0[l] : INT_MAX;
+    int hi = valid ? j0[l] : INT_MIN;
     block_minmax(lo, hi, s_mm);
     if (lo > hi) {  // no valid particle in this workgroup
       ok = 0;
@@ -547,83 +651,102 @@ __global__ __launch_bounds__(kBlock) void k_orbit(OrbitArgs a) {
       nodes = (e > 4096) ? (1 << 30) : nodes * e;
     }
   }
-  if (ok && (int64_t)nodes * (NF + 3) * (int64_t)sizeof(double) > kTileBytes) ok = 0;
+  // field tile in R, then the FP64 current tile at an 8-byte boundary
+  const int64_t fbytes = ((int64_t)nodes * NF * (int64_t)sizeof(R) + 7) / 8 * 8;
+  if (ok && fbytes + (int64_t)nodes * 3 * 8 > kTileBytes) ok = 0;
   t.nodes = uni(nodes);
   t.ok = uni(ok);
+  t.joff = uni((int)(fbytes / 8));
   if (t.ok) {
-    // stage the fields and clear the current tile
-    double* s_J = s_tile + NF * t.nodes;
+    R* s_tile = reinterpret_cast<R*>(s_dyn);
+    double* s_J = s_dyn + t.joff;
     for (int k = threadIdx.x; k < NF * t.nodes; k += blockDim.x) {
       const int f = k / t.nodes, nd = k - f * t.nodes;
-      s_tile[k] = gfield<D>(a, f)[tile_to_global<D>(M, t, nd)];
+      s_tile[k] = (R)gfield<D>(a, f)[tile_to_global<D>(M, t, nd)];
     }
     for (int k = threadIdx.x; k < 3 * t.nodes; k += blockDim.x) s_J[k] = 0.0;
   }
   __syncthreads();
 
+  // Gauss-Legendre nodes and weights on [0, 1]
+  constexpr int NQ = NGL > 0 ? NGL : kMaxGL;
+  R gx[NQ], gw[NQ];
+#pragma unroll
+  for (int k = 0; k < NQ; ++k) {
+    gx[k] = (R)a.glx[k];
+    gw[k] = (R)a.glw[k];
+  }
+
   double part[kOrbitParts];
 #pragma unroll
   for (int v = 0; v < kOrbitParts; ++v) part[v] = 0.0;
   if (i < a.np) {
-    const double q = a.q[i];
-    const double m = fabs(q);
-    double vin[3] = {a.v[i], a.v[ps + i], a.v[2 * ps + i]};
-    double Am[3] = {0.0, 0.0, 0.0};
-    if (valid) interp3<D>(a, t, D, xi0, Am);
+    PConst<R> pc;
+    pc.q = qp[i];
+    pc.m = fabs(pc.q);
+    pc.mk = pc.m * R(a.kappa);
+    pc.inv_mk = rcp_(pc.mk);
+    pc.tc = pc.q * R(a.dt) * rcp_(R(2) * pc.m);
+    pc.half_qdt = R(0.5) * pc.q * R(a.dt);
+    R vin[3] = {vp[i], vp[ps + i], vp[2 * ps + i]};
+    R Am[3] = {R(0), R(0), R(0)};
+    if (valid) interp3<D, R>(a, t, D, j0, f0, Am);
     int it = 0, segs = 0;
     bool conv = false;
     double kin = 0.0, work = 0.0, ra2 = 0.0;
     const int maxit = a.iterate ? a.max_inner : 1;
+    const R kap2 = R(a.kappa) * R(a.kappa);
     for (it = 1; it <= maxit; ++it) {
       // the orbit must stay finite and within the supported knot-crossing range
-      const double vnin = sqrt(vin[0] * vin[0] + vin[1] * vin[1] + vin[2] * vin[2]);
-      bool okv = valid && isfinite(vnin);
+      const R vn2 = vin[0] * vin[0] + vin[1] * vin[1] + vin[2] * vin[2];
+      bool okv = valid && isfinite(vn2);
 #pragma unroll
-      for (int l = 0; l < D; ++l) okv = okv && fabs(a.dt * vin[l] * M.inv_h[l]) < (double)(kMaxCross - 1);
+      for (int l = 0; l < D; ++l) okv = okv && fabs(R(a.dt) * vin[l] * R(M.inv_h[l])) < R(kMaxCross - 1);
       if (!okv) break;
-      const double P[3] = {a.P[i], a.P[ps + i], a.P[2 * ps + i]};
-      EvalOut o;
-      evaluate<D>(a, t, xi0, P, q, m, Am, vin, o);
+      const R P[3] = {Pp[i], Pp[ps + i], Pp[2 * ps + i]};
+      EvalOut<R> o;
+      evaluate<D, NGL, R>(a, t, gx, gw, j0, f0, P, pc, Am, vin, o);
       segs += o.nseg;
-      const double vn = sqrt(o.vout[0] * o.vout[0] + o.vout[1] * o.vout[1] + o.vout[2] * o.vout[2]);
-      if (!isfinite(vn) || !(vn < a.kappa)) break;  // finite and subluminal
-      double dmax = 0.0, vmax = 0.0;
+      const R vo2 = o.vout[0] * o.vout[0] + o.vout[1] * o.vout[1] + o.vout[2] * o.vout[2];
+      if (!isfinite(vo2) || !(vo2 < kap2)) break;  // finite and subluminal
+      R dmax = R(0), vmax = R(0);
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
         dmax = fmax(dmax, fabs(o.vout[c] - vin[c]));
         vmax = fmax(vmax, fabs(o.vout[c]));
       }
-      if (!a.iterate || dmax <= a.tol_abs + a.tol_rel * vmax) {
+      if (!a.iterate || dmax <= R(a.tol_abs) + R(a.tol_rel) * vmax) {
         // converged: deposit along the evaluated orbit, accept-pass diagnostics, store
         conv = true;
         double coef[3];
-        const double qv = q / M.dV;
+        const double qv = (double)pc.q / M.dV;
 #pragma unroll
-        for (int c = 0; c < 3; ++c) coef[c] = qv * o.vout[c];
-        double Ub[3];
-        deposit_orbit<D>(a, t, xi0, vin, coef, a.deposit != 0, Ub);
+        for (int c = 0; c < 3; ++c) coef[c] = qv * (double)o.vout[c];
+        R Ub[3];
+        deposit_orbit<D, NGL, R>(a, t, gx, gw, j0, f0, vin, coef, a.deposit != 0, Ub);
         double wk = 0.0;
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
           double Dv = 0.0;
 #pragma unroll
-          for (int j = 0; j < D; ++j) Dv += o.Dm[c][j] * vin[j];
-          const double r = o.Ap[c] - Am[c] - a.dt * (Ub[c] + Dv);
+          for (int j = 0; j < D; ++j) Dv += (double)o.Dm[c][j] * (double)vin[j];
+          const double r = ((double)o.Ap[c] - (double)Am[c]) - a.dt * ((double)Ub[c] + Dv);
           ra2 += r * r;
-          wk += o.vout[c] * (-o.gp[c] - Ub[c]);
+          wk += (double)o.vout[c] * (-(double)o.gp[c] - (double)Ub[c]);
         }
-        const double inv_mk = 1.0 / (m * a.kappa);
-        const double p2 = o.pn1[0] * o.pn1[0] + o.pn1[1] * o.pn1[1] + o.pn1[2] * o.pn1[2];
-        kin = p2 / (m * (gam(o.pn1, inv_mk) + 1.0));
-        work = q * wk;
+        const double m = (double)pc.m;
+        const double p2 = (double)o.pn1[0] * o.pn1[0] + (double)o.pn1[1] * o.pn1[1] + (double)o.pn1[2] * o.pn1[2];
+        const double gmm = sqrt(1.0 + p2 / (m * m * a.kappa * a.kappa));
+        kin = p2 / (m * (gmm + 1.0));
+        work = (double)pc.q * wk;
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
-          a.v[c * ps + i] = o.vout[c];
-          a.Pn[c * ps + i] = o.Pn1[c];
+          vp[c * ps + i] = o.vout[c];
+          Pnp[c * ps + i] = o.Pn1[c];
         }
 #pragma unroll
         for (int l = 0; l < D; ++l) {
-          double xv = x[l] + a.dt * vin[l];
+          double xv = x[l] + a.dt * (double)vin[l];
           const double top = M.lo[l] + M.len[l];
           if (xv >= top) xv -= M.len[l];
           if (xv < M.lo[l]) xv += M.len[l];
@@ -648,7 +771,7 @@ __global__ __launch_bounds__(kBlock) void k_orbit(OrbitArgs a) {
   __syncthreads();
   // flush the current tile: one atomic per nonzero tile node and component
   if (t.ok && a.deposit) {
-    const double* s_J = s_tile + NF * t.nodes;
+    const double* s_J = s_dyn + t.joff;
     for (int k = threadIdx.x; k < 3 * t.nodes; k += blockDim.x) {
       const double v = s_J[k];
       if (v == 0.0) continue;
@@ -678,19 +801,32 @@ __global__ __launch_bounds__(kBlock) void k_orbit(OrbitArgs a) {
   }
 }
 
+template <int D, class R>
+hipError_t launch_d(const OrbitArgs& a, unsigned blocks, hipStream_t s) {
+  // compile-time Gauss-Legendre orders: d+1 (exact for the per-segment polynomials)
+  // and 8 (the paper's); any other order runs the runtime loop
+  if (a.ngl == D + 1)
+    hipLaunchKernelGGL((k_orbit<D, D + 1, R>), dim3(blocks), dim3(kBlock), kTileBytes, s, a);
+  else if (a.ngl == 8)
+    hipLaunchKernelGGL((k_orbit<D, 8, R>), dim3(blocks), dim3(kBlock), kTileBytes, s, a);
+  else
+    hipLaunchKernelGGL((k_orbit<D, 0, R>), dim3(blocks), dim3(kBlock), kTileBytes, s, a);
+  return hipGetLastError();
+}
+
 }  // namespace
 
 hipError_t launch_orbit(const OrbitArgs& a, int ngl, hipStream_t s) {
   (void)ngl;
   if (a.np <= 0) return hipSuccess;
   const unsigned blocks = (unsigned)((a.np + kBlock - 1) / kBlock);
+  const bool f32 = a.precision == 1;
   switch (a.M.d) {
-    case 1: hipLaunchKernelGGL(k_orbit<1>, dim3(blocks), dim3(kBlock), kTileBytes, s, a); break;
-    case 2: hipLaunchKernelGGL(k_orbit<2>, dim3(blocks), dim3(kBlock), kTileBytes, s, a); break;
-    case 3: hipLaunchKernelGGL(k_orbit<3>, dim3(blocks), dim3(kBlock), kTileBytes, s, a); break;
+    case 1: return f32 ? launch_d<1, float>(a, blocks, s) : launch_d<1, double>(a, blocks, s);
+    case 2: return f32 ? launch_d<2, float>(a, blocks, s) : launch_d<2, double>(a, blocks, s);
+    case 3: return f32 ? launch_d<3, float>(a, blocks, s) : launch_d<3, double>(a, blocks, s);
     default: return hipErrorInvalidValue;
   }
-  return hipGetLastError();
 }
 
 }  // namespace gmhc

@@ -76,6 +76,9 @@ def load_library(path=LIB_PATH):
     if not os.path.exists(path):
         raise RuntimeError(f"libgmhc.so not found at {path}: build it with "
                            "`python -m paper_2609_36383_amd.build`")
+    # torch's HIP runtime must be the one the library binds to (one runtime per
+    # process: the workspace and stream come from torch)
+    import torch  # noqa: F401
     L = C.CDLL(path)
     vp, dp, i32, i64 = C.c_void_p, C.POINTER(C.c_double), C.c_int32, C.c_int64
     sig = {
