@@ -9,7 +9,7 @@
 #include <string>
 #include <vector>
 
-#include "../../include/gmhc.h"
+#include "gmhc.h"
 #include "gmhc_internal.h"
 
 using namespace gmhc;

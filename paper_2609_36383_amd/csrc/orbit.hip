@@ -288,77 +288,78 @@ __device__ __forceinline__ void interp3(const OrbitArgs& a, const Tile& t, int f
 
 // Quadrature of one knot segment for the gathers grad-phi-bar and D.
 //
-// The integrated weights of the stencil nodes are accumulated over the Gauss points
-// first (per z-plane in 3D),
-//   S_g = sum_q w_q S_g(s_q),  X0_g = sum_q w_q (1-s_q) dS_g/dxi,  X1_g = sum_q w_q s_q dS_g/dxi
-// (likewise Y0, Y1 and Z0, Z1), then contracted once with the node values:
-//   grad-phi-bar += S_g (grad phi)_g,  D_l. += X0_g A^n_{l,g} + X1_g A^{n+1}_{l,g}.
+// The stencil is visited one x-row at a time (3^(d-1) rows of three nodes).  For the
+// row, the integrated weights of its three nodes are accumulated over the Gauss
+// points first,
+//   S_c = sum_q w_q S_c(s_q),  X0_c = sum_q w_q (1-s_q) dS_c/dxi,  X1_c = sum_q w_q s_q dS_c/dxi
+// (likewise Y0, Y1 and Z0, Z1), then contracted once with the row's node values:
+//   grad-phi-bar += S_c (grad phi)_c,  D_l. += X0_c A^n_{l,c} + X1_c A^{n+1}_{l,c}.
 // This is the same quadrature summed in a different order; each field value is read
-// once per segment.  D is left in xi units and scaled by 1/h afterwards.
+// once per segment and only one row of weights is live at a time.  D is left in xi
+// units and scaled by 1/h afterwards.
 template <int D, int NGL, class R, bool LDS>
 __device__ __forceinline__ void eval_segment(const OrbitArgs& a, const Tile& t, const R* gx, const R* gw,
                                              const int jn[3], const R fs[3], const R* del, R sa, R sb,
                                              R gp[3], R Dm[3][3]) {
   const R len = sb - sa;
   Stencil<D, LDS> st(a.M, t, jn);
-  constexpr int NY = D > 1 ? 3 : 1;
-  constexpr int NP = D > 2 ? 3 : 1;
+  constexpr int NROW = D == 1 ? 1 : (D == 2 ? 3 : 9);
 #pragma unroll 1
-  for (int cz = 0; cz < NP; ++cz) {
-    R S[NY][3], X0[NY][3], X1[NY][3], Y0[NY][3], Y1[NY][3], Z0[NY][3], Z1[NY][3];
+  for (int row = 0; row < NROW; ++row) {
+    const int cy = D > 1 ? row % 3 : 0, cz = D > 2 ? row / 3 : 0;
+    // the row's field values first, so their latency overlaps the weight arithmetic
+    const int rowoff = st.row(cy, cz);
+    R F[3][D + 6];
 #pragma unroll
-    for (int b = 0; b < NY; ++b)
+    for (int c = 0; c < 3; ++c)
 #pragma unroll
-      for (int c = 0; c < 3; ++c) S[b][c] = X0[b][c] = X1[b][c] = Y0[b][c] = Y1[b][c] = Z0[b][c] = Z1[b][c] = R(0);
+      for (int f = 0; f < D + 6; ++f) F[c][f] = ld<D, R, LDS>(a, t, f, st.ix[c] + rowoff);
+    R S[3], X0[3], X1[3], Y0[3], Y1[3], Z0[3], Z1[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) S[c] = X0[c] = X1[c] = Y0[c] = Y1[c] = Z0[c] = Z1[c] = R(0);
+    // recompute the x weights per row rather than keep them live across rows
+    R sar = sa;
+    asm volatile("" : "+v"(sar));
     const int nq = GL<NGL>::n(a.ngl);
 #pragma unroll
     for (int q = 0; q < nq; ++q) {
-      const R s = sa + len * gx[q];
+      const R s = sar + len * gx[q];
       const R wq = len * gw[q];
       const R b1 = wq * s, a1 = wq - b1;  // w_q s and w_q (1 - s)
-      R wx[3], dwx[3], wy[3] = {R(1), R(0), R(0)}, dwy[3] = {R(0), R(0), R(0)};
+      R wx[3], dwx[3];
       bw(fs[0] + s * del[0], wx, dwx);
-      if (D > 1) bw(fs[1] + s * del[1], wy, dwy);
-      R wz = R(1), dwz = R(0);
+      R wy = R(1), dwy = R(0), wz = R(1), dwz = R(0);
+      if (D > 1) bw1(fs[1] + s * del[1], cy, wy, dwy);
       if (D > 2) bw1(fs[2] + s * del[2], cz, wz, dwz);
-      const R wqz = wq * wz, a1z = a1 * wz, b1z = b1 * wz;
-      const R a1d = a1 * dwz, b1d = b1 * dwz;
+      const R wyz = wy * wz;
+      const R sw = wq * wyz, xw0 = a1 * wyz, xw1 = b1 * wyz;
+      const R yz = dwy * wz, zy = wy * dwz;
+      const R yw0 = a1 * yz, yw1 = b1 * yz, zw0 = a1 * zy, zw1 = b1 * zy;
 #pragma unroll
-      for (int b = 0; b < NY; ++b) {
-        const R sw = wqz * wy[b], xw0 = a1z * wy[b], xw1 = b1z * wy[b];
-        const R yw0 = a1z * dwy[b], yw1 = b1z * dwy[b];
-        const R zw0 = a1d * wy[b], zw1 = b1d * wy[b];
-#pragma unroll
-        for (int c = 0; c < 3; ++c) {
-          S[b][c] += sw * wx[c];
-          X0[b][c] += xw0 * dwx[c];
-          X1[b][c] += xw1 * dwx[c];
-          if (D > 1) {
-            Y0[b][c] += yw0 * wx[c];
-            Y1[b][c] += yw1 * wx[c];
-          }
-          if (D > 2) {
-            Z0[b][c] += zw0 * wx[c];
-            Z1[b][c] += zw1 * wx[c];
-          }
+      for (int c = 0; c < 3; ++c) {
+        S[c] += sw * wx[c];
+        X0[c] += xw0 * dwx[c];
+        X1[c] += xw1 * dwx[c];
+        if (D > 1) {
+          Y0[c] += yw0 * wx[c];
+          Y1[c] += yw1 * wx[c];
+        }
+        if (D > 2) {
+          Z0[c] += zw0 * wx[c];
+          Z1[c] += zw1 * wx[c];
         }
       }
     }
 #pragma unroll
-    for (int b = 0; b < NY; ++b) {
-      const int rowoff = st.row(b, cz);
+    for (int c = 0; c < 3; ++c) {
 #pragma unroll
-      for (int c = 0; c < 3; ++c) {
-        const int g = st.ix[c] + rowoff;
+      for (int l = 0; l < D; ++l) gp[l] += S[c] * F[c][l];
 #pragma unroll
-        for (int l = 0; l < D; ++l) gp[l] += S[b][c] * ld<D, R, LDS>(a, t, l, g);
-#pragma unroll
-        for (int l = 0; l < 3; ++l) {
-          const R a0 = ld<D, R, LDS>(a, t, D + l, g), a1v = ld<D, R, LDS>(a, t, D + 3 + l, g);
-          Dm[l][0] += X0[b][c] * a0 + X1[b][c] * a1v;
-          if (D > 1) Dm[l][1] += Y0[b][c] * a0 + Y1[b][c] * a1v;
-          if (D > 2) Dm[l][2] += Z0[b][c] * a0 + Z1[b][c] * a1v;
-        }
+      for (int l = 0; l < 3; ++l) {
+        const R a0 = F[c][D + l], a1v = F[c][D + 3 + l];
+        Dm[l][0] += X0[c] * a0 + X1[c] * a1v;
+        if (D > 1) Dm[l][1] += Y0[c] * a0 + Y1[c] * a1v;
+        if (D > 2) Dm[l][2] += Z0[c] * a0 + Z1[c] * a1v;
       }
     }
   }
@@ -488,102 +489,302 @@ __device__ void evaluate(const OrbitArgs& a, const Tile& t, const R* gx, const R
   }
 }
 
-// Deposit sweep of one segment: S-bar of the stencil, U-bar gather, current deposit
-// (FP64 LDS tile or FP64 HBM atomics).
-template <int D, int NGL, class R, bool LDS>
-__device__ __forceinline__ void deposit_segment(const OrbitArgs& a, const Tile& t, const R* gx, const R* gw,
-                                                const int jn[3], const R fs[3], const R* del, R sa, R sb,
-                                                const double coef[3], bool do_dep, R Ub[3]) {
-  const R len = sb - sa;
-  Stencil<D, LDS> st(a.M, t, jn);
-  HIP_DYNAMIC_SHARED(double, s_dyn);
-  double* s_J = s_dyn + t.joff;
-  constexpr int NY = D > 1 ? 3 : 1;
-  constexpr int NP = D > 2 ? 3 : 1;
-#pragma unroll 1
-  for (int cz = 0; cz < NP; ++cz) {
-    R S[NY][3];
+// Per-lane iterator over the same knot-split segments as for_each_segment (same
+// arithmetic, so the deposit sees exactly the segments the gathers saw); lets a whole
+// wave step through its particles' segments in lockstep.
+template <int D, class R>
+struct SegIter {
+  R knot[3], next[3], stp[3], rd[3];
+  R sa;
+  int steps;
+  bool live;
+  __device__ __forceinline__ void init(const R* f0, const R* del, bool on) {
 #pragma unroll
-    for (int b = 0; b < NY; ++b)
-#pragma unroll
-      for (int c = 0; c < 3; ++c) S[b][c] = R(0);
-    const int nq = GL<NGL>::n(a.ngl);
-#pragma unroll
-    for (int q = 0; q < nq; ++q) {
-      const R s = sa + len * gx[q];
-      const R wq = len * gw[q];
-      R wx[3], dwx[3], wy[3] = {R(1), R(0), R(0)}, dwy[3];
-      bw(fs[0] + s * del[0], wx, dwx);
-      if (D > 1) bw(fs[1] + s * del[1], wy, dwy);
-      R wz = R(1), dwz;
-      if (D > 2) bw1(fs[2] + s * del[2], cz, wz, dwz);
-      const R wqz = wq * wz;
-#pragma unroll
-      for (int b = 0; b < NY; ++b) {
-        const R sw = wqz * wy[b];
-#pragma unroll
-        for (int c = 0; c < 3; ++c) S[b][c] += sw * wx[c];
+    for (int l = 0; l < D; ++l) {
+      rd[l] = del[l] != R(0) ? rcp_(del[l]) : R(0);
+      if (del[l] > R(0)) {
+        knot[l] = floor(f0[l] - R(0.5)) + R(1.5);
+        stp[l] = R(1);
+        next[l] = (knot[l] - f0[l]) * rd[l];
+      } else if (del[l] < R(0)) {
+        knot[l] = ceil(f0[l] - R(0.5)) - R(0.5);
+        stp[l] = R(-1);
+        next[l] = (knot[l] - f0[l]) * rd[l];
+      } else {
+        knot[l] = R(0);
+        stp[l] = R(0);
+        next[l] = R(2);
       }
     }
 #pragma unroll
-    for (int b = 0; b < NY; ++b) {
-      const int rowoff = st.row(b, cz);
+    for (int l = 0; l < 3; ++l) f0s[l] = l < D ? f0[l] : R(0);
+    sa = R(0);
+    steps = 0;
+    live = on;
+  }
+  // next segment [s0, s1] of nonzero length; false once the orbit is exhausted
+  __device__ __forceinline__ bool advance(R& s0, R& s1) {
+    while (live) {
+      R sb = R(1);
 #pragma unroll
-      for (int c = 0; c < 3; ++c) {
-        const int g = st.ix[c] + rowoff;
-        const R Sb = S[b][c];
+      for (int l = 0; l < D; ++l) sb = (next[l] < sb) ? next[l] : sb;
+      const R a0 = sa;
+      ++steps;
+      if (sb >= R(1) || steps > D * kMaxCross) {
+        live = false;
+      } else {
 #pragma unroll
-        for (int k = 0; k < 3; ++k) {
-          Ub[k] += Sb * ld<D, R, LDS>(a, t, D + 6 + k, g);
-          if (do_dep) {
-            const double v = coef[k] * (double)Sb;
-            if (LDS)
-              atomicAdd(s_J + k * t.nodes + g, v);
-            else
-              atomicAdd(a.J + (int64_t)k * a.M.Ng + g, v);
+        for (int l = 0; l < D; ++l)
+          if (next[l] == sb) {
+            knot[l] += stp[l];
+            next[l] = (knot[l] - f0s[l]) * rd[l];
+          }
+      }
+      sa = sb;
+      if (sb > a0) {
+        s0 = a0;
+        s1 = sb;
+        return true;
+      }
+    }
+    return false;
+  }
+  R f0s[3];
+};
+
+// ---- wave-wide reduce-scatter (all 64 lanes active)
+//
+// The deposit of a wave whose particles share a stencil is summed across the wave
+// before it reaches LDS: NP2 values per lane (NP2 = 16 or 32) are reduced so that
+// every lane ends with the wave total of one value.  Exchange partners per step:
+// lane ^ 32 and lane ^ 16 (gfx950 permlane swaps), lane ^ 8 (row rotation by 8),
+// lane ^ 7 (half-row mirror), lane ^ 2 and lane ^ 1 (quad permutations).  The six
+// masks span all 64 lanes, so each total covers the whole wave.
+__device__ __forceinline__ uint64_t as_u64(double x) { return (uint64_t)__double_as_longlong(x); }
+__device__ __forceinline__ double as_f64(uint32_t lo, uint32_t hi) {
+  return __longlong_as_double((long long)(((uint64_t)hi << 32) | (uint64_t)lo));
+}
+
+// (A, B) -> lower rows keep A and receive the partner's A; upper rows keep B and
+// receive the partner's B (partner lane ^ 32, or lane ^ 16 for ROW16).
+template <bool ROW16>
+__device__ __forceinline__ double swap_sum(double A, double B) {
+  const uint64_t a = as_u64(A), b = as_u64(B);
+  uint32_t alo, blo, ahi, bhi;
+  if (ROW16) {
+    const auto lo = __builtin_amdgcn_permlane16_swap((uint32_t)a, (uint32_t)b, false, false);
+    const auto hi = __builtin_amdgcn_permlane16_swap((uint32_t)(a >> 32), (uint32_t)(b >> 32), false, false);
+    alo = lo[0]; blo = lo[1]; ahi = hi[0]; bhi = hi[1];
+  } else {
+    const auto lo = __builtin_amdgcn_permlane32_swap((uint32_t)a, (uint32_t)b, false, false);
+    const auto hi = __builtin_amdgcn_permlane32_swap((uint32_t)(a >> 32), (uint32_t)(b >> 32), false, false);
+    alo = lo[0]; blo = lo[1]; ahi = hi[0]; bhi = hi[1];
+  }
+  return as_f64(alo, ahi) + as_f64(blo, bhi);
+}
+
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double x) {
+  const uint64_t u = as_u64(x);
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_mov_dpp((int)(uint32_t)u, CTRL, 0xF, 0xF, false);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_mov_dpp((int)(uint32_t)(u >> 32), CTRL, 0xF, 0xF, false);
+  return as_f64(lo, hi);
+}
+constexpr int kDppRor8 = 0x128;        // row_ror:8  -> lane ^ 8
+constexpr int kDppHalfMirror = 0x141;  // row_half_mirror -> lane ^ 7
+constexpr int kDppXor2 = 0x4E;         // quad_perm [2,3,0,1]
+constexpr int kDppXor1 = 0xB1;         // quad_perm [1,0,3,2]
+
+// one scatter step through a DPP exchange: the lane keeps the lower half of v if its
+// bit `kb` is clear, the upper half otherwise, and adds the partner's copy of it
+template <int H, int CTRL>
+__device__ __forceinline__ void dpp_step(double* v, bool up) {
+#pragma unroll
+  for (int j = 0; j < H; ++j) {
+    const double send = up ? v[j] : v[j + H];
+    const double keep = up ? v[j + H] : v[j];
+    v[j] = keep + dpp_f64<CTRL>(send);
+  }
+}
+
+// Reduce-scatter of v[NP2]; returns the wave total of value wave_slot<NP2>(lane).
+template <int NP2>
+__device__ __forceinline__ double wave_reduce_scatter(double* v, int lane) {
+  constexpr int H1 = NP2 / 2, H2 = NP2 / 4, H3 = NP2 / 8, H4 = NP2 / 16;
+#pragma unroll
+  for (int j = 0; j < H1; ++j) v[j] = swap_sum<false>(v[j], v[j + H1]);
+#pragma unroll
+  for (int j = 0; j < H2; ++j) v[j] = swap_sum<true>(v[j], v[j + H2]);
+  dpp_step<H3, kDppRor8>(v, (lane & 8) != 0);
+  dpp_step<H4, kDppHalfMirror>(v, (lane & 4) != 0);
+  if (NP2 == 32) {
+    dpp_step<1, kDppXor2>(v, (lane & 2) != 0);
+  } else {
+    v[0] += dpp_f64<kDppXor2>(v[0]);
+  }
+  v[0] += dpp_f64<kDppXor1>(v[0]);
+  return v[0];
+}
+// value index a lane holds after wave_reduce_scatter; owner() picks one copy of each
+template <int NP2>
+__device__ __forceinline__ int wave_slot(int lane) {
+  const int b5 = (lane >> 5) & 1, b4 = (lane >> 4) & 1, b3 = (lane >> 3) & 1, b2 = (lane >> 2) & 1;
+  return NP2 == 32 ? 16 * b5 + 8 * b4 + 4 * b3 + 2 * b2 + ((lane >> 1) & 1) : 8 * b5 + 4 * b4 + 2 * b3 + b2;
+}
+template <int NP2>
+__device__ __forceinline__ bool wave_owner(int lane) {
+  return NP2 == 32 ? (lane & 1) == 0 : (lane & 3) == 0;
+}
+
+constexpr int kMaxGroups = 4;  // stencil groups summed per wave and plane; the rest add per lane
+
+// Current deposit of one stencil row (three x-nodes) into the LDS tile.  Lanes whose
+// segment uses the same stencil are summed across the wave first (one group per
+// distinct stencil base, leader = lowest pending lane), so each tile node receives
+// one atomic per group instead of one per lane.  S holds the lane's integrated
+// weights of the row's nodes.
+template <int D, class R>
+__device__ __forceinline__ void deposit_row_tile(const Tile& t, const int jn[3], int cy, int cz, const R S[3],
+                                                 const double coef[3], bool in, int lane) {
+  HIP_DYNAMIC_SHARED(double, s_dyn);
+  double* s_J = s_dyn + t.joff;
+  constexpr int NV = 9, NP2 = 16;
+  uint64_t pend = __ballot(in);
+#pragma unroll 1
+  for (int r = 0; pend != 0; ++r) {
+    if (r == kMaxGroups) {
+      // many distinct stencils in this wave: the remaining lanes add one by one
+      if ((pend >> lane) & 1) {
+        const int g0 = (jn[0] - 1 - t.o[0]) + t.E[0] * ((D > 1 ? jn[1] + cy - 1 - t.o[1] : 0) +
+                                                        t.E[1] * (D > 2 ? jn[2] + cz - 1 - t.o[2] : 0));
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+#pragma unroll
+          for (int k = 0; k < 3; ++k) atomicAdd(s_J + k * t.nodes + g0 + c, coef[k] * (double)S[c]);
+      }
+      break;
+    }
+    const int leader = __builtin_ctzll(pend);
+    int kj[3] = {0, 0, 0};
+    bool mine = in;
+#pragma unroll
+    for (int l = 0; l < D; ++l) {
+      kj[l] = __builtin_amdgcn_readlane(jn[l], leader);
+      mine = mine && jn[l] == kj[l];
+    }
+    const uint64_t grp = __ballot(mine);
+    double v[NP2];
+#pragma unroll
+    for (int k = 0; k < 3; ++k)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) v[k * 3 + c] = mine ? coef[k] * (double)S[c] : 0.0;
+#pragma unroll
+    for (int j = NV; j < NP2; ++j) v[j] = 0.0;
+    const double tot = wave_reduce_scatter<NP2>(v, lane);
+    const int idx = wave_slot<NP2>(lane);
+    if (wave_owner<NP2>(lane) && idx < NV && tot != 0.0) {
+      const int k = idx / 3, c = idx - 3 * k;
+      const int g = (kj[0] + c - 1 - t.o[0]) + t.E[0] * ((D > 1 ? kj[1] + cy - 1 - t.o[1] : 0) +
+                                                         t.E[1] * (D > 2 ? kj[2] + cz - 1 - t.o[2] : 0));
+      atomicAdd(s_J + k * t.nodes + g, tot);
+    }
+    pend &= ~grp;
+  }
+}
+
+// Deposit phase of the pass, run by every lane of the workgroup: the lanes whose
+// particle converged walk the segments of their accepted orbit (v_in) in lockstep;
+// per segment and stencil row they gather U-bar and deposit J_g += q v_out S-bar_g / dV.
+// Stencils outside the tile read and add through global memory per lane.
+template <int D, int NGL, class R>
+__device__ void deposit_phase(const OrbitArgs& a, const Tile& t, const R* gx, const R* gw, const int j0[3],
+                              const R* f0, const R del[3], bool dep, const double coef[3], R Ub[3]) {
+  const int lane = threadIdx.x & 63;
+  const bool do_dep = a.deposit != 0;
+  SegIter<D, R> sit;
+  sit.init(f0, del, dep);
+  Ub[0] = Ub[1] = Ub[2] = R(0);
+#pragma unroll 1
+  for (int guard = 0; guard <= D * kMaxCross; ++guard) {
+    R sa = R(0), sb = R(0);
+    const bool has = sit.advance(sa, sb);
+    if (__ballot(has) == 0) break;
+    int jn[3] = {0, 0, 0};
+    R fs[3] = {R(0), R(0), R(0)};
+    if (has) seg_base<D, R>(j0, f0, del, R(0.5) * (sa + sb), jn, fs);
+    const bool in = has && inside<D>(t, jn);
+    const R len = sb - sa;  // zero for lanes without a segment: all weights vanish
+    constexpr int NROW = D == 1 ? 1 : (D == 2 ? 3 : 9);
+#pragma unroll 1
+    for (int row = 0; row < NROW; ++row) {
+      const int cy = D > 1 ? row % 3 : 0, cz = D > 2 ? row / 3 : 0;
+      R S[3] = {R(0), R(0), R(0)};
+      const int nq = GL<NGL>::n(a.ngl);
+#pragma unroll
+      for (int q = 0; q < nq; ++q) {
+        const R s = sa + len * gx[q];
+        const R wq = len * gw[q];
+        R wx[3], dwx[3];
+        bw(fs[0] + s * del[0], wx, dwx);
+        R wy = R(1), dwy, wz = R(1), dwz;
+        if (D > 1) bw1(fs[1] + s * del[1], cy, wy, dwy);
+        if (D > 2) bw1(fs[2] + s * del[2], cz, wz, dwz);
+        const R sw = wq * wy * wz;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) S[c] += sw * wx[c];
+      }
+      if (in) {
+        Stencil<D, true> st(a.M, t, jn);
+        const int rowoff = st.row(cy, cz);
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+#pragma unroll
+          for (int k = 0; k < 3; ++k) Ub[k] += S[c] * ld<D, R, true>(a, t, D + 6 + k, st.ix[c] + rowoff);
+      } else if (has) {
+        Stencil<D, false> st(a.M, t, jn);
+        const int rowoff = st.row(cy, cz);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          const int g = st.ix[c] + rowoff;
+#pragma unroll
+          for (int k = 0; k < 3; ++k) {
+            Ub[k] += S[c] * ld<D, R, false>(a, t, D + 6 + k, g);
+            if (do_dep) atomicAdd(a.J + (int64_t)k * a.M.Ng + g, coef[k] * (double)S[c]);
           }
         }
       }
+      if (do_dep && t.ok) deposit_row_tile<D, R>(t, jn, cy, cz, S, coef, in, lane);
     }
   }
 }
 
-template <int D, int NGL, class R>
-__device__ void deposit_orbit(const OrbitArgs& a, const Tile& t, const R* gx, const R* gw, const int j0[3],
-                              const R* f0, const R vin[3], const double coef[3], bool do_dep, R Ub[3]) {
-  R del[3] = {R(0), R(0), R(0)};
+// Block-wide min / max of D ints per thread (all threads participate).
+template <int D>
+__device__ __forceinline__ void block_minmax(int lo[3], int hi[3], int* sh) {
 #pragma unroll
-  for (int l = 0; l < D; ++l) del[l] = R(a.dt) * vin[l] * R(a.M.inv_h[l]);
-  Ub[0] = Ub[1] = Ub[2] = R(0);
-  for_each_segment<D, R>(f0, del, [&](R sa, R sb) {
-    int jn[3];
-    R fs[3];
-    seg_base<D, R>(j0, f0, del, R(0.5) * (sa + sb), jn, fs);
-    if (inside<D>(t, jn))
-      deposit_segment<D, NGL, R, true>(a, t, gx, gw, jn, fs, del, sa, sb, coef, do_dep, Ub);
-    else
-      deposit_segment<D, NGL, R, false>(a, t, gx, gw, jn, fs, del, sa, sb, coef, do_dep, Ub);
-  });
-}
-
-// Block-wide min / max of an int (all threads participate).
-__device__ __forceinline__ void block_minmax(int& lo, int& hi, int* sh) {
-  for (int off = 32; off > 0; off >>= 1) {
-    lo = min(lo, __shfl_xor(lo, off, 64));
-    hi = max(hi, __shfl_xor(hi, off, 64));
-  }
+  for (int l = 0; l < D; ++l)
+    for (int off = 32; off > 0; off >>= 1) {
+      lo[l] = min(lo[l], __shfl_xor(lo[l], off, 64));
+      hi[l] = max(hi[l], __shfl_xor(hi[l], off, 64));
+    }
   const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
+  const int nw = blockDim.x / 64;
   __syncthreads();
-  if (lane == 0) {
-    sh[2 * wave] = lo;
-    sh[2 * wave + 1] = hi;
-  }
+  if (lane == 0)
+#pragma unroll
+    for (int l = 0; l < D; ++l) {
+      sh[(2 * l) * nw + wave] = lo[l];
+      sh[(2 * l + 1) * nw + wave] = hi[l];
+    }
   __syncthreads();
-  lo = sh[0];
-  hi = sh[1];
-  for (int w = 1; w < (int)(blockDim.x / 64); ++w) {
-    lo = min(lo, sh[2 * w]);
-    hi = max(hi, sh[2 * w + 1]);
+#pragma unroll
+  for (int l = 0; l < D; ++l) {
+    lo[l] = sh[2 * l * nw];
+    hi[l] = sh[(2 * l + 1) * nw];
+    for (int w = 1; w < nw; ++w) {
+      lo[l] = min(lo[l], sh[2 * l * nw + w]);
+      hi[l] = max(hi[l], sh[(2 * l + 1) * nw + w]);
+    }
   }
 }
 
@@ -606,14 +807,14 @@ __attribute__((amdgpu_waves_per_eu(GMHC_ORBIT_WAVES_PER_EU))) void k_orbit(Orbit
   const Mesh& M = a.M;
   const int64_t ps = a.ps;
   HIP_DYNAMIC_SHARED(double, s_dyn);
-  __shared__ int s_mm[2 * (kBlock / 64)];
+  __shared__ int s_mm[2 * 3 * (kBlock / 64)];
   constexpr int NF = nfields<D>();
   const R* Pp = static_cast<const R*>(a.P);
   const R* qp = static_cast<const R*>(a.q);
   R* vp = static_cast<R*>(a.v);
   R* Pnp = static_cast<R*>(a.Pn);
 
-  // ---- particle position: nearest node j0 and offset f0 in [-1/2, 1/2)
+  // ---- particle position: nearest node j0 (wrapped into [0, n)) and offset f0
   double x[3] = {0.0, 0.0, 0.0};
   int j0[3] = {0, 0, 0};
   R f0[3] = {R(0), R(0), R(0)};
@@ -625,11 +826,13 @@ __attribute__((amdgpu_waves_per_eu(GMHC_ORBIT_WAVES_PER_EU))) void k_orbit(Orbit
       const double xi = (x[l] - M.lo[l]) * M.inv_h[l];
       valid = valid && isfinite(xi) && fabs(xi) < 1.0e8;
       const double jr = valid ? floor(xi + 0.5) : 0.0;
-      j0[l] = (int)jr;
+      j0[l] = valid ? wrapi((int)jr, M.n[l]) : 0;
       f0[l] = valid ? (R)(xi - jr) : R(0);
     }
   }
-  // ---- the workgroup's tile box
+  // ---- the workgroup's tile box, taken periodically: on an axis whose nodes spread
+  // over more than half the mesh, the low side moves up by one period, so particles
+  // on either side of the periodic seam become neighbours
   Tile t;
   int nodes = 1, ok = 1;
 #pragma unroll
@@ -637,18 +840,35 @@ __attribute__((amdgpu_waves_per_eu(GMHC_ORBIT_WAVES_PER_EU))) void k_orbit(Orbit
     t.o[l] = 0;
     t.E[l] = 1;
   }
+  int lo[3], hi[3];
 #pragma unroll
   for (int l = 0; l < D; ++l) {
-    int lo = valid ? j0[l] : INT_MAX;
-    int hi = valid ? j0[l] : INT_MIN;
-    block_minmax(lo, hi, s_mm);
-    if (lo > hi) {  // no valid particle in this workgroup
+    lo[l] = valid ? j0[l] : INT_MAX;
+    hi[l] = valid ? j0[l] : INT_MIN;
+  }
+  block_minmax<D>(lo, hi, s_mm);
+  int shift = 0;
+#pragma unroll
+  for (int l = 0; l < D; ++l)
+    if (lo[l] <= hi[l] && hi[l] - lo[l] > M.n[l] / 2) shift |= 1 << l;
+  if (uni(shift)) {
+#pragma unroll
+    for (int l = 0; l < D; ++l) {
+      if (((shift >> l) & 1) && valid && j0[l] < M.n[l] / 2) j0[l] += M.n[l];
+      lo[l] = valid ? j0[l] : INT_MAX;
+      hi[l] = valid ? j0[l] : INT_MIN;
+    }
+    block_minmax<D>(lo, hi, s_mm);
+  }
+#pragma unroll
+  for (int l = 0; l < D; ++l) {
+    if (lo[l] > hi[l]) {  // no valid particle in this workgroup
       ok = 0;
     } else {
-      t.o[l] = uni(lo - kHalo);
-      const int e = hi - lo + 1 + 2 * kHalo;
+      t.o[l] = uni(lo[l] - kHalo);
+      const int e = hi[l] - lo[l] + 1 + 2 * kHalo;
       t.E[l] = uni(e);
-      nodes = (e > 4096) ? (1 << 30) : nodes * e;
+      nodes = (e > 4096 || nodes > 4096) ? (1 << 30) : nodes * e;  // no overflow: 4096^2 < 2^30
     }
   }
   // field tile in R, then the FP64 current tile at an 8-byte boundary
@@ -680,6 +900,12 @@ __attribute__((amdgpu_waves_per_eu(GMHC_ORBIT_WAVES_PER_EU))) void k_orbit(Orbit
   double part[kOrbitParts];
 #pragma unroll
   for (int v = 0; v < kOrbitParts; ++v) part[v] = 0.0;
+  // state the deposit phase needs from the accepted evaluation
+  bool conv = false;
+  R vin[3] = {R(0), R(0), R(0)};
+  R q = R(0);
+  double vout[3] = {0.0, 0.0, 0.0}, Dv[3] = {0.0, 0.0, 0.0}, dA[3] = {0.0, 0.0, 0.0}, gpb[3] = {0.0, 0.0, 0.0};
+  double kin = 0.0;
   if (i < a.np) {
     PConst<R> pc;
     pc.q = qp[i];
@@ -688,14 +914,16 @@ __attribute__((amdgpu_waves_per_eu(GMHC_ORBIT_WAVES_PER_EU))) void k_orbit(Orbit
     pc.inv_mk = rcp_(pc.mk);
     pc.tc = pc.q * R(a.dt) * rcp_(R(2) * pc.m);
     pc.half_qdt = R(0.5) * pc.q * R(a.dt);
-    R vin[3] = {vp[i], vp[ps + i], vp[2 * ps + i]};
+    q = pc.q;
+    vin[0] = vp[i];
+    vin[1] = vp[ps + i];
+    vin[2] = vp[2 * ps + i];
     R Am[3] = {R(0), R(0), R(0)};
     if (valid) interp3<D, R>(a, t, D, j0, f0, Am);
     int it = 0, segs = 0;
-    bool conv = false;
-    double kin = 0.0, work = 0.0, ra2 = 0.0;
     const int maxit = a.iterate ? a.max_inner : 1;
     const R kap2 = R(a.kappa) * R(a.kappa);
+    const R P[3] = {Pp[i], Pp[ps + i], Pp[2 * ps + i]};
     for (it = 1; it <= maxit; ++it) {
       // the orbit must stay finite and within the supported knot-crossing range
       const R vn2 = vin[0] * vin[0] + vin[1] * vin[1] + vin[2] * vin[2];
@@ -703,7 +931,6 @@ __attribute__((amdgpu_waves_per_eu(GMHC_ORBIT_WAVES_PER_EU))) void k_orbit(Orbit
 #pragma unroll
       for (int l = 0; l < D; ++l) okv = okv && fabs(R(a.dt) * vin[l] * R(M.inv_h[l])) < R(kMaxCross - 1);
       if (!okv) break;
-      const R P[3] = {Pp[i], Pp[ps + i], Pp[2 * ps + i]};
       EvalOut<R> o;
       evaluate<D, NGL, R>(a, t, gx, gw, j0, f0, P, pc, Am, vin, o);
       segs += o.nseg;
@@ -716,29 +943,22 @@ __attribute__((amdgpu_waves_per_eu(GMHC_ORBIT_WAVES_PER_EU))) void k_orbit(Orbit
         vmax = fmax(vmax, fabs(o.vout[c]));
       }
       if (!a.iterate || dmax <= R(a.tol_abs) + R(a.tol_rel) * vmax) {
-        // converged: deposit along the evaluated orbit, accept-pass diagnostics, store
+        // converged: store the new state; the orbit of this v_in is deposited below
         conv = true;
-        double coef[3];
-        const double qv = (double)pc.q / M.dV;
-#pragma unroll
-        for (int c = 0; c < 3; ++c) coef[c] = qv * (double)o.vout[c];
-        R Ub[3];
-        deposit_orbit<D, NGL, R>(a, t, gx, gw, j0, f0, vin, coef, a.deposit != 0, Ub);
-        double wk = 0.0;
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
-          double Dv = 0.0;
+          double d = 0.0;
 #pragma unroll
-          for (int j = 0; j < D; ++j) Dv += (double)o.Dm[c][j] * (double)vin[j];
-          const double r = ((double)o.Ap[c] - (double)Am[c]) - a.dt * ((double)Ub[c] + Dv);
-          ra2 += r * r;
-          wk += (double)o.vout[c] * (-(double)o.gp[c] - (double)Ub[c]);
+          for (int j = 0; j < D; ++j) d += (double)o.Dm[c][j] * (double)vin[j];
+          Dv[c] = d;
+          dA[c] = (double)o.Ap[c] - (double)Am[c];
+          vout[c] = (double)o.vout[c];
+          gpb[c] = (double)o.gp[c];
         }
         const double m = (double)pc.m;
         const double p2 = (double)o.pn1[0] * o.pn1[0] + (double)o.pn1[1] * o.pn1[1] + (double)o.pn1[2] * o.pn1[2];
         const double gmm = sqrt(1.0 + p2 / (m * m * a.kappa * a.kappa));
         kin = p2 / (m * (gmm + 1.0));
-        work = (double)pc.q * wk;
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
           vp[c * ps + i] = o.vout[c];
@@ -763,10 +983,34 @@ __attribute__((amdgpu_waves_per_eu(GMHC_ORBIT_WAVES_PER_EU))) void k_orbit(Orbit
     part[OP_FAIL] = conv ? 0.0 : 1.0;
     part[OP_ITERS] = (double)it;
     part[OP_ITMAX] = (double)it;
-    part[OP_KIN] = kin;
-    part[OP_WORK] = work;
-    part[OP_RA2] = ra2;
     part[OP_SEGS] = (double)segs;
+  }
+
+  // ---- deposit phase (every lane of the workgroup, converged particles contribute)
+  {
+    R del[3] = {R(0), R(0), R(0)};
+    double coef[3] = {0.0, 0.0, 0.0};
+    if (conv) {
+#pragma unroll
+      for (int l = 0; l < D; ++l) del[l] = R(a.dt) * vin[l] * R(M.inv_h[l]);
+      const double qv = (double)q / M.dV;
+#pragma unroll
+      for (int c = 0; c < 3; ++c) coef[c] = qv * vout[c];
+    }
+    R Ub[3];
+    deposit_phase<D, NGL, R>(a, t, gx, gw, j0, f0, del, conv, coef, Ub);
+    if (conv) {
+      double wk = 0.0, ra2 = 0.0;
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        const double r = dA[c] - a.dt * ((double)Ub[c] + Dv[c]);
+        ra2 += r * r;
+        wk += vout[c] * (-gpb[c] - (double)Ub[c]);
+      }
+      part[OP_KIN] = kin;
+      part[OP_WORK] = (double)q * wk;
+      part[OP_RA2] = ra2;
+    }
   }
   __syncthreads();
   // flush the current tile: one atomic per nonzero tile node and component
