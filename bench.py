@@ -61,41 +61,65 @@ def bytes_per_node(d):
     return 8 * (d + 9) + 8 * 3 * 2
 
 
-def cpu_baseline(w, cfg_dict, ngl, target_s=12.0):
-    """The oracle's orbit pass (inner Picard loop, same GL order as the GPU) on a
-    bounded leading sample of the workload's particles at the first trial fields."""
-    import numpy as np
+def measured_traffic(workload, dtype):
+    """HBM bytes per orbit launch from the committed counter summary of this workload
+    (FETCH_SIZE and WRITE_SIZE scaled by a copy kernel), or None when there is none or
+    the kernel sources have changed since the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", f"k_orbit_{workload}_{dtype}_hbm_traffic.txt")
+    if not os.path.exists(path):
+        return None
+    meta = {}
+    for line in open(path):
+        if ":" in line:
+            k, v = line.split(":", 1)
+            meta[k.strip()] = v.strip()
+    if "kernel_sources" not in meta or "traffic_bytes_per_launch" not in meta:
+        return None
+    h = hashlib.sha256()
+    for f in meta["kernel_sources"].split():
+        h.update(open(os.path.join(ROOT, f), "rb").read())
+    if h.hexdigest() != meta.get("kernel_sources_sha256"):
+        return None
+    return float(meta["traffic_bytes_per_launch"])
 
+
+def cpu_baseline(w, cfg_dict, ngl, target_s=12.0):
+    """The CPU oracle's rate on the same workload: whole implicit steps (all outer
+    iterations, orbit passes and field solves) of the full particle set at the same
+    Gauss-Legendre order, as many as fit in about target_s seconds (at least one)."""
     import oracle as O
     from paper_2609_36383_amd import workloads as W
 
     x, u, q = W.particles(w)
-    cfg = O.config_from_dict(cfg_dict, gl_order=ngl)
-    full = O.OracleSim(cfg)
-    full.load_particles(x, u, q)
-    full.initialize()
-    fields = full.trial_fields(full.read_field("J"))
-    xf, Pf, vf = full.read_particles()
-    del full
-
-    def run(ns):
-        s = O.OracleSim(cfg)
-        s.load_particles(x[:, :ns], u[:, :ns], q[:ns])
-        s.set_particle_state(xf[:, :ns], Pf[:, :ns], vf[:, :ns])
+    sim = O.OracleSim(O.config_from_dict(cfg_dict, gl_order=ngl))
+    sim.load_particles(x, u, q)
+    sim.initialize()
+    evals, steps, el = 0, 0, 0.0
+    while steps == 0 or (el < target_s and steps < 50):
         t0 = time.perf_counter()
-        r = s.orbit_pass(*fields, vf[:, :ns], iterate=True)
-        dt = time.perf_counter() - t0
-        return int(r["iters"].sum()), dt
+        _, rep = sim.step()
+        el += time.perf_counter() - t0
+        evals += rep["evaluations"]
+        steps += 1
+    threads = int(O.lib().orc_max_threads())
+    return {"value": evals / el, "unit": "particle-iterations/s", "cores": threads, "kind": "oracle",
+            "particle_steps_per_s": q.size * steps / el,
+            "sample": f"{steps} whole implicit steps of the full {q.size}-particle workload (GL{ngl} per "
+                      f"knot segment, {evals} orbit evaluations) in {el:.1f} s on {threads} OpenMP threads"}
 
-    ns = 8192
-    ev, dt = run(ns)
-    ns = int(min(q.size, max(ns, ns * target_s / max(dt, 1e-3))))
-    ev, dt = run(ns)
-    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    return {"value": ev / dt, "unit": "particle-iterations/s", "cores": threads, "kind": "oracle",
-            "sample": f"oracle orbit pass with inner Picard loop, GL{ngl} per knot segment, on the first "
-                      f"{ns} of {q.size} particles of the workload at its first trial fields "
-                      f"({ev} evaluations in {dt:.2f} s)"}
+
+def copy_probe():
+    """One 256 MiB FP64 device copy: reads and writes 2^28 bytes each, the reference
+    against which the profiler's FETCH_SIZE / WRITE_SIZE counters are scaled."""
+    import torch
+    n = 1 << 25
+    a = torch.ones(n, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_read": n * 8, "copy_bytes_written": n * 8}), flush=True)
 
 
 def main():
@@ -107,7 +131,12 @@ def main():
     ap.add_argument("--sort-every", type=int, default=10)
     ap.add_argument("--gl-order", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="only run a 256 MiB device-to-device copy (calibrates HBM byte counters)")
     args = ap.parse_args()
+    if args.copy_probe:
+        copy_probe()
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build runs the orbit pass on a single MI355X "
               "(multi-GPU sharding is not implemented); use --gpus 1", file=sys.stderr)
@@ -186,7 +215,8 @@ def main():
             "peak": PEAK_FP64_VALU_TFLOPS,
             "unit": "TFLOP/s",
             "frac": achieved_tflops / PEAK_FP64_VALU_TFLOPS,
-            "traffic": None,
+            "traffic": measured_traffic(args.workload, "fp64"),
+            "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE x2.0 + WRITE_SIZE x1.0)",
             "kernel": f"k_orbit<{d}>",
             "launch_ms": launch_s * 1e3,
             "flops_per_launch": flops_launch,

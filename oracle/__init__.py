@@ -81,6 +81,8 @@ def lib():
         L.orc_interp.argtypes = [cfgp, dp, dp, dp]
         L.orc_orbit_eval.argtypes = [cfgp, dp, dp, dp, dp, dp, dp, C.c_double, C.c_double, dp,
                                      C.POINTER(EvalOut)]
+        L.orc_max_threads.argtypes = []
+        L.orc_max_threads.restype = C.c_int
         L.orc_create.argtypes = [cfgp, C.POINTER(C.c_int)]
         L.orc_create.restype = C.c_void_p
         L.orc_destroy.argtypes = [C.c_void_p]

@@ -1380,4 +1380,7 @@ int orc_trial_fields(void* h, const double* j, double* gphi, double* An, double*
 
 int64_t orc_num_particles(void* h) { return static_cast<Sim*>(h)->np; }
 
+// OpenMP threads a parallel region of the oracle runs with (for reporting timings).
+int orc_max_threads(void) { return omp_get_max_threads(); }
+
 }  // extern "C"
