@@ -49,10 +49,10 @@ def deposit_flops(d, seg_mean, ngl):
     return seg_mean * ngl * point + (3 ** d) * (3 * 2 + 3 * 2)
 
 
-def bytes_per_particle(d):
-    """Algorithmic HBM bytes per particle per orbit launch (FP64): read x, P, q, v_in;
-    write v_out, x^{n+1}, P^{n+1}."""
-    return 8 * d + 24 + 8 + 24 + 24 + 8 * d + 24
+def bytes_per_particle(d, bulk=8):
+    """Algorithmic HBM bytes per particle per orbit launch: read x (FP64), P, q, v_in;
+    write v_out, x^{n+1} (FP64), P^{n+1}.  bulk = bytes of the bulk type (8 FP64, 4 FP32)."""
+    return 8 * d + 3 * bulk + bulk + 3 * bulk + 3 * bulk + 8 * d + 3 * bulk
 
 
 def bytes_per_node(d):
@@ -122,6 +122,70 @@ def copy_probe():
     print(json.dumps({"copy_bytes_read": n * 8, "copy_bytes_written": n * 8}), flush=True)
 
 
+PEAK_FP32_VALU_TFLOPS = 157.3
+
+
+def run_case(args, w, fp32):
+    """Time args.steps whole implicit steps of workload w in one precision mode."""
+    import numpy as np
+    import torch
+
+    from paper_2609_36383_amd import gmhc as G
+    from paper_2609_36383_amd import workloads as W
+
+    base = W.config_dict(w, fp32_bulk=fp32)
+    ngl = args.gl_order if args.gl_order else w["dim"] + 1
+    cfg = G.config_from_dict(base, gl_order=ngl, sort_every=args.sort_every, timing=1,
+                             precision=G.FP32_BULK if fp32 else G.FP64)
+    x, u, q = W.particles(w)
+    npart = q.size
+    sim = G.Simulation(cfg, npart, device="cuda:0")
+    sim.load_particles(x, u, q)
+    sim.initialize()
+    drift = 0.0
+    for _ in range(args.warmup):
+        sim.step()
+    torch.cuda.synchronize()
+    evals = orbit_ms = 0.0
+    launches = outer = segs = 0
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        _, rep = sim.step()
+        evals += rep["evaluations"]
+        orbit_ms += rep["orbit_ms"]
+        launches += rep["orbit_launches"]
+        outer += rep["outer_iters"]
+        segs += rep["segments"]
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    drift = sim.diagnostics()["energy_rel"]
+    del sim
+    d = w["dim"]
+    ng = int(np.prod(w["n"]))
+    seg_mean = segs / max(evals, 1)  # measured knot-split segments per evaluation
+    flops_launch = (evals / max(launches, 1)) * flops_per_eval(d, seg_mean, ngl) + \
+        npart * deposit_flops(d, seg_mean, ngl)
+    bytes_launch = npart * bytes_per_particle(d, 4 if fp32 else 8) + ng * bytes_per_node(d)
+    launch_s = (orbit_ms / max(launches, 1)) * 1e-3
+    peak = PEAK_FP32_VALU_TFLOPS if fp32 else PEAK_FP64_VALU_TFLOPS
+    achieved = flops_launch / launch_s / 1e12
+    gbs = bytes_launch / launch_s / 1e9
+    return dict(
+        value=evals / elapsed, ms_per_step=elapsed * 1e3 / args.steps, ngl=ngl, npart=npart,
+        particle_steps_per_s=npart * args.steps / elapsed, outer_iters_mean=outer / args.steps,
+        evaluations_per_particle_step=evals / (npart * args.steps), energy_drift=drift,
+        segments_per_evaluation=seg_mean,
+        tolerances={k: base[k] for k in ("tol_outer_rel", "tol_outer_abs", "tol_inner_rel", "tol_inner_abs")},
+        roofline={
+            "bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
+            "traffic": measured_traffic(args.workload, "fp32" if fp32 else "fp64"),
+            "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE x2.0 + WRITE_SIZE x1.0)",
+            "kernel": f"k_orbit<{d},{ngl},{'float' if fp32 else 'double'}>", "launch_ms": launch_s * 1e3,
+            "flops_per_launch": flops_launch, "hbm_bytes_per_launch": bytes_launch,
+            "hbm_achieved_gbs": gbs, "hbm_frac": gbs / PEAK_HBM_GBS,
+        })
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -130,6 +194,8 @@ def main():
     ap.add_argument("--workload", default="weibel2d")
     ap.add_argument("--sort-every", type=int, default=10)
     ap.add_argument("--gl-order", type=int, default=0)
+    ap.add_argument("--precision", choices=("both", "fp64", "fp32"), default="both",
+                    help="FP64 (the headline value), FP32-bulk, or both (default)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a 256 MiB device-to-device copy (calibrates HBM byte counters)")
@@ -142,91 +208,43 @@ def main():
               "(multi-GPU sharding is not implemented); use --gpus 1", file=sys.stderr)
         sys.exit(2)
 
-    import numpy as np
-    import torch
-
-    from paper_2609_36383_amd import gmhc as G
     from paper_2609_36383_amd import workloads as W
 
     w = W.spec(args.workload)
-    base = W.config_dict(w)
-    ngl = args.gl_order if args.gl_order else w["dim"] + 1
-    cfg = G.config_from_dict(base, gl_order=ngl, sort_every=args.sort_every, timing=1)
-    x, u, q = W.particles(w)
-    npart = q.size
-    sim = G.Simulation(cfg, npart, device="cuda:0")
-    sim.load_particles(x, u, q)
-    sim.initialize()
-    for _ in range(args.warmup):
-        sim.step()
-    torch.cuda.synchronize()
-    evals = 0
-    orbit_ms = 0.0
-    launches = 0
-    outer = 0
-    segs = 0
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        st, rep = sim.step()
-        evals += rep["evaluations"]
-        orbit_ms += rep["orbit_ms"]
-        launches += rep["orbit_launches"]
-        outer += rep["outer_iters"]
-        segs += rep["segments"]
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    diag = sim.diagnostics()
-
-    d = w["dim"]
-    ng = int(np.prod(w["n"]))
-    seg_mean = segs / max(evals, 1)  # measured knot-split segments per evaluation
-    per_launch_evals = evals / max(launches, 1)
-    per_launch_conv = npart
-    flops_launch = per_launch_evals * flops_per_eval(d, seg_mean, ngl) + \
-        per_launch_conv * deposit_flops(d, seg_mean, ngl)
-    bytes_launch = npart * bytes_per_particle(d) + ng * bytes_per_node(d)
-    launch_s = (orbit_ms / max(launches, 1)) * 1e-3
-    achieved_tflops = flops_launch / launch_s / 1e12
-    achieved_gbs = bytes_launch / launch_s / 1e9
+    main_fp32 = args.precision == "fp32"
+    r = run_case(args, w, main_fp32)
+    other = run_case(args, w, True) if args.precision == "both" else None
     out = {
         "metric": METRIC,
-        "value": evals / elapsed,
+        "value": r["value"],
         "unit": "particle-iterations/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": elapsed * 1e3 / args.steps,
+        "ms_per_step": r["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f32-bulk" if main_fp32 else "f64",
         "data": "synthetic",
-        "config": {"workload": f"{args.workload}: {'x'.join(map(str, w['n']))} mesh, {npart} particles, "
-                               f"{w['ppc']} per cell, dt {w['dt']}, GL{ngl} per knot segment",
-                   "global_batch": npart, "seq_len": None, "parallelism": "single GPU"},
-        "particle_steps_per_s": npart * args.steps / elapsed,
-        "outer_iters_mean": outer / args.steps,
-        "evaluations_per_particle_step": evals / (npart * args.steps),
-        "energy_drift": diag["energy_rel"],
-        "segments_per_evaluation": seg_mean,
-        "roofline": {
-            "bound": "alu",
-            "achieved": achieved_tflops,
-            "peak": PEAK_FP64_VALU_TFLOPS,
-            "unit": "TFLOP/s",
-            "frac": achieved_tflops / PEAK_FP64_VALU_TFLOPS,
-            "traffic": measured_traffic(args.workload, "fp64"),
-            "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE x2.0 + WRITE_SIZE x1.0)",
-            "kernel": f"k_orbit<{d}>",
-            "launch_ms": launch_s * 1e3,
-            "flops_per_launch": flops_launch,
-            "hbm_bytes_per_launch": bytes_launch,
-            "hbm_achieved_gbs": achieved_gbs,
-            "hbm_frac": achieved_gbs / PEAK_HBM_GBS,
-        },
+        "config": {"workload": f"{args.workload}: {'x'.join(map(str, w['n']))} mesh, {r['npart']} particles, "
+                               f"{w['ppc']} per cell, dt {w['dt']}, GL{r['ngl']} per knot segment",
+                   "global_batch": r["npart"], "seq_len": None, "parallelism": "single GPU"},
     }
+    for k in ("particle_steps_per_s", "outer_iters_mean", "evaluations_per_particle_step", "energy_drift",
+              "segments_per_evaluation", "tolerances"):
+        out[k] = r[k]
+    out["roofline"] = r["roofline"]
+    if other is not None:
+        out["fp32_bulk"] = {k: other[k] for k in ("value", "ms_per_step", "particle_steps_per_s", "outer_iters_mean",
+                                                  "evaluations_per_particle_step", "energy_drift", "tolerances",
+                                                  "roofline")}
+        out["fp32_bulk"]["unit"] = "particle-iterations/s"
+        out["fp32_bulk"]["speedup_particle_steps_vs_fp64"] = other["particle_steps_per_s"] / r["particle_steps_per_s"]
+        out["fp32_bulk"]["speedup_per_iteration_vs_fp64"] = other["value"] / r["value"]
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(w, base, ngl)
+        base = W.config_dict(w, fp32_bulk=main_fp32)
+        out["cpu_baseline"] = cpu_baseline(w, base, r["ngl"])
     print(json.dumps(out), flush=True)
 
 

@@ -26,16 +26,19 @@ struct gmhc_ctx {
   size_t ws_bytes = 0;
   bool bound = false, loaded = false, initialized = false, have_pot = false, frozen = false,
        pass_done = false;
-  // particles (sorted order), SoA
+  // particles (sorted order), SoA.  Positions are FP64 in both modes; momenta, charges
+  // and orbit velocities are stored in the bulk type (double, or float in FP32-bulk).
+  int prec = GMHC_FP64;
+  size_t es = sizeof(double);  // bytes per bulk element
   double* x[3] = {};
   double* x2[3] = {};
-  double* P[3] = {};
-  double* P2[3] = {};
-  double* q = nullptr;
-  double* q2 = nullptr;
-  double* vb[3] = {};   // accepted orbit-velocity iterate (warm start)
-  double* vw[3] = {};   // working iterate of the current step / last frozen pass
-  double* pscr[3] = {}; // read-out scratch
+  void* P[3] = {};
+  void* P2[3] = {};
+  void* q = nullptr;
+  void* q2 = nullptr;
+  void* vb[3] = {};     // accepted orbit-velocity iterate (warm start)
+  void* vw[3] = {};     // working iterate of the current step / last frozen pass
+  double* pscr[3] = {}; // FP64 staging for loads and read-outs
   int32_t* id = nullptr;
   int32_t* id2 = nullptr;
   int32_t* iters = nullptr;
@@ -142,24 +145,25 @@ size_t carve(gmhc_ctx* c, char* base, int64_t np) {
   const int64_t Ng = c->M.Ng;
   const size_t N = (size_t)std::max<int64_t>(np, 1);
   // each SoA group is one contiguous block with component stride N
+  const size_t es = c->es;
   double* xb = cv.take<double>(d * N);
   double* x2b = cv.take<double>(d * N);
-  double* Pb = cv.take<double>(3 * N);
-  double* P2b = cv.take<double>(3 * N);
-  double* vbb = cv.take<double>(3 * N);
-  double* vwb = cv.take<double>(3 * N);
+  char* Pb = cv.take<char>(3 * N * es);
+  char* P2b = cv.take<char>(3 * N * es);
+  char* vbb = cv.take<char>(3 * N * es);
+  char* vwb = cv.take<char>(3 * N * es);
   double* psb = cv.take<double>(3 * N);
   for (int l = 0; l < 3; ++l) {
     c->x[l] = (l < d && xb) ? xb + l * N : nullptr;
     c->x2[l] = (l < d && x2b) ? x2b + l * N : nullptr;
-    c->P[l] = Pb ? Pb + l * N : nullptr;
-    c->P2[l] = P2b ? P2b + l * N : nullptr;
-    c->vb[l] = vbb ? vbb + l * N : nullptr;
-    c->vw[l] = vwb ? vwb + l * N : nullptr;
+    c->P[l] = Pb ? Pb + l * N * es : nullptr;
+    c->P2[l] = P2b ? P2b + l * N * es : nullptr;
+    c->vb[l] = vbb ? vbb + l * N * es : nullptr;
+    c->vw[l] = vwb ? vwb + l * N * es : nullptr;
     c->pscr[l] = psb ? psb + l * N : nullptr;
   }
-  c->q = cv.take<double>(N);
-  c->q2 = cv.take<double>(N);
+  c->q = cv.take<char>(N * es);
+  c->q2 = cv.take<char>(N * es);
   c->id = cv.take<int32_t>(N);
   c->id2 = cv.take<int32_t>(N);
   c->iters = cv.take<int32_t>(N);
@@ -275,17 +279,21 @@ int32_t sort_particles(gmhc_ctx* ctx) {
   int k = 0;
   const int d = ctx->M.d;
   for (int l = 0; l < d; ++l) {
+    a.esz[k] = sizeof(double);
     a.src[k] = ctx->x[l];
     a.dst[k++] = ctx->x2[l];
   }
   for (int l = 0; l < 3; ++l) {
+    a.esz[k] = (int32_t)ctx->es;
     a.src[k] = ctx->P[l];
     a.dst[k++] = ctx->P2[l];
   }
   for (int l = 0; l < 3; ++l) {
+    a.esz[k] = (int32_t)ctx->es;
     a.src[k] = ctx->vb[l];
     a.dst[k++] = ctx->vw[l];
   }
+  a.esz[k] = (int32_t)ctx->es;
   a.src[k] = ctx->q;
   a.dst[k++] = ctx->q2;
   a.ncomp = k;
@@ -376,12 +384,14 @@ int32_t gmhc_create(const gmhc_config* cfg, gmhc_ctx** out) {
   if (!(c.dt > 0.0) || !(c.kappa > 0.0) || !(c.sigma1 > 0.0) || !(c.sigma2 > 0.0)) return GMHC_EINVAL;
   if (fabs(c.sigma1 - c.kappa * c.kappa * c.sigma2) > 1e-14 * fabs(c.sigma1)) return GMHC_EINVAL;
   if (c.gl_order < 0 || c.gl_order > kMaxGL) return GMHC_EINVAL;
-  if (c.precision != GMHC_FP64) return GMHC_EINVAL;  // FP32-bulk selected elsewhere
+  if (c.precision != GMHC_FP64 && c.precision != GMHC_FP32_BULK) return GMHC_EINVAL;
   if (c.max_outer < 1 || c.max_inner < 1 || !(c.beta > 0.0 && c.beta <= 1.0)) return GMHC_EINVAL;
   if (c.tol_outer_abs < 0 || c.tol_outer_rel < 0 || c.tol_inner_abs < 0 || c.tol_inner_rel < 0)
     return GMHC_EINVAL;
   gmhc_ctx* ctx = new gmhc_ctx();
   ctx->cfg = c;
+  ctx->prec = c.precision;
+  ctx->es = c.precision == GMHC_FP32_BULK ? sizeof(float) : sizeof(double);
   Mesh& M = ctx->M;
   M.d = c.dim;
   M.Ng = 1;
@@ -420,6 +430,8 @@ int32_t gmhc_workspace_bytes(const gmhc_ctx* ctx, int64_t n_particles, size_t* b
   gmhc_ctx tmp;
   tmp.cfg = ctx->cfg;
   tmp.M = ctx->M;
+  tmp.prec = ctx->prec;
+  tmp.es = ctx->es;
   *bytes = carve(&tmp, nullptr, n_particles);
   return GMHC_OK;
 }
@@ -484,13 +496,15 @@ int32_t gmhc_load_particles(gmhc_ctx* ctx, const double* x, const double* u, con
   const size_t b = sizeof(double) * (size_t)np;
   for (int l = 0; l < ctx->M.d; ++l)
     if (np) HIPCK(hipMemcpyAsync(ctx->x[l], x + l * np, b, kind_of(ptr_kind, true), ctx->stream));
+  // u and q are staged in FP64 (pscr, and x2 which is free until the first sort),
+  // then stored in the bulk type with p = |q| kappa u
   for (int l = 0; l < 3; ++l)
-    if (np) HIPCK(hipMemcpyAsync(ctx->P[l], u + l * np, b, kind_of(ptr_kind, true), ctx->stream));
-  if (np) HIPCK(hipMemcpyAsync(ctx->q, q, b, kind_of(ptr_kind, true), ctx->stream));
-  HIPCK(launch_mech_from_u(ctx->P, ctx->q, ctx->cfg.kappa, np, ctx->stream));
+    if (np) HIPCK(hipMemcpyAsync(ctx->pscr[l], u + l * np, b, kind_of(ptr_kind, true), ctx->stream));
+  if (np) HIPCK(hipMemcpyAsync(ctx->x2[0], q, b, kind_of(ptr_kind, true), ctx->stream));
+  HIPCK(launch_load_state(ctx->pscr, ctx->x2[0], ctx->P, ctx->q, ctx->prec, ctx->cfg.kappa, np, ctx->stream));
   HIPCK(launch_iota(ctx->id, np, ctx->stream));
   for (int l = 0; l < 3; ++l)
-    if (np) HIPCK(hipMemsetAsync(ctx->vb[l], 0, b, ctx->stream));
+    if (np) HIPCK(hipMemsetAsync(ctx->vb[l], 0, ctx->es * (size_t)np, ctx->stream));
   HIPCK(hipStreamSynchronize(ctx->stream));
   ctx->loaded = true;
   ctx->initialized = false;
@@ -533,6 +547,7 @@ int32_t gmhc_initialize(gmhc_ctx* ctx) {
     ia.J[l] = ctx->Jdep + l * Ng;
   }
   ia.q = ctx->q;
+  ia.prec = ctx->prec;
   ia.rho = ctx->rscr;
   HIPCK(launch_init_deposit(ia, s));
   HIPCK(fft_nd(M, ctx->axes, 1, ctx->rscr, nullptr, ctx->S0 + 2 * Ng, nullptr, nullptr, false, false, s));
@@ -560,6 +575,7 @@ int32_t gmhc_initialize(gmhc_ctx* ctx) {
     ca.A[l] = ctx->An + l * Ng;
   }
   ca.q = ctx->q;
+  ca.prec = ctx->prec;
   ca.sign = 1.0;
   HIPCK(launch_canonical(ca, s));
   HIPCK(hipStreamSynchronize(s));
@@ -588,7 +604,7 @@ int32_t gmhc_step(gmhc_ctx* ctx, gmhc_step_report* rep) {
     if (st) return st;
   }
   for (int l = 0; l < 3; ++l)
-    if (np) HIPCK(hipMemcpyAsync(ctx->vw[l], ctx->vb[l], sizeof(double) * np, hipMemcpyDeviceToDevice, s));
+    if (np) HIPCK(hipMemcpyAsync(ctx->vw[l], ctx->vb[l], ctx->es * np, hipMemcpyDeviceToDevice, s));
   int cur = 0;
   for (int k = 1; k <= ctx->cfg.max_outer; ++k) {
     // field step for the trial current
@@ -705,6 +721,7 @@ int32_t gmhc_diagnostics(gmhc_ctx* ctx, gmhc_diag* out) {
     ka.A[l] = ctx->An + l * Ng;
   }
   ka.q = ctx->q;
+  ka.prec = ctx->prec;
   ka.partials = ctx->partials;
   const int kb = (int)std::min<int64_t>(std::max<int64_t>((ctx->np + kBlock - 1) / kBlock, 1), 1024);
   HIPCK(launch_kinetic(ka, kb, s));
@@ -754,17 +771,18 @@ int32_t gmhc_read_particles(gmhc_ctx* ctx, double* x, double* P, double* vbar, i
   if (!np) return GMHC_OK;
   hipStream_t s = ctx->stream;
   const size_t b = sizeof(double) * (size_t)np;
-  auto emit = [&](double* const* src, int nc, double* dst) -> int32_t {
-    HIPCK(launch_unpermute(src, ctx->pscr, nc, ctx->id, np, s));
+  auto emit = [&](void* const* src, int prec, int nc, double* dst) -> int32_t {
+    HIPCK(launch_unpermute(src, prec, ctx->pscr, nc, ctx->id, np, s));
     for (int c = 0; c < nc; ++c)
       HIPCK(hipMemcpyAsync(dst + c * np, ctx->pscr[c], b, kind_of(ptr_kind, false), s));
     HIPCK(hipStreamSynchronize(s));
     return GMHC_OK;
   };
   int32_t st = GMHC_OK;
-  if (x && (st = emit(ctx->x, ctx->M.d, x))) return st;
-  if (P && (st = emit(ctx->P, 3, P))) return st;
-  if (vbar && (st = emit(ctx->vb, 3, vbar))) return st;
+  void* const xs[3] = {ctx->x[0], ctx->x[1], ctx->x[2]};
+  if (x && (st = emit(xs, GMHC_FP64, ctx->M.d, x))) return st;
+  if (P && (st = emit(ctx->P, ctx->prec, 3, P))) return st;
+  if (vbar && (st = emit(ctx->vb, ctx->prec, 3, vbar))) return st;
   return GMHC_OK;
 }
 
@@ -777,17 +795,18 @@ int32_t gmhc_set_particle_state(gmhc_ctx* ctx, const double* x, const double* P,
   if (!np) return GMHC_OK;
   hipStream_t s = ctx->stream;
   const size_t b = sizeof(double) * (size_t)np;
-  auto take = [&](const double* src, int nc, double* const* dst) -> int32_t {
+  auto take = [&](const double* src, int nc, void* const* dst, int prec) -> int32_t {
     for (int c = 0; c < nc; ++c)
       HIPCK(hipMemcpyAsync(ctx->pscr[c], src + c * np, b, kind_of(ptr_kind, true), s));
-    HIPCK(launch_permute_in(ctx->pscr, dst, nc, ctx->id, np, s));
+    HIPCK(launch_permute_in(ctx->pscr, dst, prec, nc, ctx->id, np, s));
     HIPCK(hipStreamSynchronize(s));
     return GMHC_OK;
   };
   int32_t st = GMHC_OK;
-  if (x && (st = take(x, ctx->M.d, ctx->x))) return st;
-  if (P && (st = take(P, 3, ctx->P))) return st;
-  if (vbar && (st = take(vbar, 3, ctx->vb))) return st;
+  void* const xs[3] = {ctx->x[0], ctx->x[1], ctx->x[2]};
+  if (x && (st = take(x, ctx->M.d, xs, GMHC_FP64))) return st;
+  if (P && (st = take(P, 3, ctx->P, ctx->prec))) return st;
+  if (vbar && (st = take(vbar, 3, ctx->vb, ctx->prec))) return st;
   return GMHC_OK;
 }
 
@@ -887,7 +906,7 @@ int32_t gmhc_orbit_pass_frozen(gmhc_ctx* ctx, int32_t iterate, gmhc_pass_report*
   const int64_t np = ctx->np;
   hipStream_t s = ctx->stream;
   for (int l = 0; l < 3; ++l)
-    if (np) HIPCK(hipMemcpyAsync(ctx->vw[l], ctx->vb[l], sizeof(double) * np, hipMemcpyDeviceToDevice, s));
+    if (np) HIPCK(hipMemcpyAsync(ctx->vw[l], ctx->vb[l], ctx->es * np, hipMemcpyDeviceToDevice, s));
   int32_t st = run_orbit(ctx, iterate ? 1 : 0, nullptr);
   if (st) return st;
   double oms = 0.0;
@@ -915,12 +934,12 @@ int32_t gmhc_read_pass(gmhc_ctx* ctx, double* vout, double* Pnp1, double* J, int
   hipStream_t s = ctx->stream;
   const size_t b = sizeof(double) * (size_t)np;
   if (vout && np) {
-    HIPCK(launch_unpermute(ctx->vw, ctx->pscr, 3, ctx->id, np, s));
+    HIPCK(launch_unpermute(ctx->vw, ctx->prec, ctx->pscr, 3, ctx->id, np, s));
     for (int c = 0; c < 3; ++c) HIPCK(hipMemcpyAsync(vout + c * np, ctx->pscr[c], b, kind_of(ptr_kind, false), s));
     HIPCK(hipStreamSynchronize(s));
   }
   if (Pnp1 && np) {
-    HIPCK(launch_unpermute(ctx->P2, ctx->pscr, 3, ctx->id, np, s));
+    HIPCK(launch_unpermute(ctx->P2, ctx->prec, ctx->pscr, 3, ctx->id, np, s));
     for (int c = 0; c < 3; ++c) HIPCK(hipMemcpyAsync(Pnp1 + c * np, ctx->pscr[c], b, kind_of(ptr_kind, false), s));
     HIPCK(hipStreamSynchronize(s));
   }

@@ -26,6 +26,19 @@ enum OrbitPart {
   OP_PAD = 7
 };
 
+// Particle momenta, charges and orbit velocities are stored in the bulk type: FP64
+// (prec 0) or FP32 (prec 1, the FP32-bulk mode).  Off the orbit pass they are read and
+// written through these helpers and computed with in FP64.
+__device__ __forceinline__ double ld_bulk(const void* p, int64_t i, int prec) {
+  return prec ? (double)static_cast<const float*>(p)[i] : static_cast<const double*>(p)[i];
+}
+__device__ __forceinline__ void st_bulk(void* p, int64_t i, double v, int prec) {
+  if (prec)
+    static_cast<float*>(p)[i] = (float)v;
+  else
+    static_cast<double*>(p)[i] = v;
+}
+
 // Mesh geometry in the form the kernels use.
 struct Mesh {
   int d;
@@ -125,10 +138,11 @@ struct InitArgs {
   Mesh M;
   int64_t np;
   double kappa;
+  int prec;              // bulk type of P, q, v
   const double* x[3];
-  double* P[3];          // in: mechanical p; out: unchanged (canonical pass adds q A)
-  const double* q;
-  double* v[3];          // out: V(p)
+  void* P[3];            // in: mechanical p; out: unchanged (canonical pass adds q A)
+  const void* q;
+  void* v[3];            // out: V(p)
   double* rho;           // [Ng] accumulator
   double* J[3];          // accumulators
 };
@@ -145,9 +159,10 @@ hipError_t launch_init_spectral(const InitSpecArgs& a, hipStream_t s);
 struct CanonArgs {
   Mesh M;
   int64_t np;
+  int prec;              // bulk type of P, q
   const double* x[3];
-  double* P[3];
-  const double* q;
+  void* P[3];
+  const void* q;
   const double* A[3];    // real A^0
   double sign;           // +1: P = p + q A ; -1: p = P - q A
 };
@@ -157,9 +172,10 @@ struct KinArgs {
   Mesh M;
   int64_t np;
   double kappa;
+  int prec;              // bulk type of P, q
   const double* x[3];
-  const double* P[3];
-  const double* q;
+  const void* P[3];
+  const void* q;
   const double* A[3];
   double* partials;      // [blocks][kDiagParts]: K, sum|q|(vy^2+vz^2), sum|q|
 };
@@ -178,25 +194,30 @@ hipError_t launch_spec_diag(const SpecDiagArgs& a, int blocks, hipStream_t s);
 hipError_t launch_spec_field(const Mesh& M, int which_e, const double2* phi, const double2* A,
                              const double2* U, double2* out, hipStream_t s);
 
-// P[c][i] *= |q_i| kappa (mechanical momentum from u = p/(m kappa)).
-hipError_t launch_mech_from_u(double* const P[3], const double* q, double kappa, int64_t np, hipStream_t s);
+// Loaded particle state into the bulk type: q_i from qd, P[c][i] = |q_i| kappa u[c][i]
+// (mechanical momentum from u = p/(m kappa), with m = |q| as stored).
+hipError_t launch_load_state(double* const u[3], const double* qd, void* const P[3], void* q, int prec,
+                             double kappa, int64_t np, hipStream_t s);
 hipError_t launch_iota(int32_t* id, int64_t np, hipStream_t s);
 
 // ---- particle permutation -------------------------------------------------------
-// dst[c][id[i]] = src[c][i] for c < ncomp (un-permute to load order).
-hipError_t launch_unpermute(const double* const* src, double* const* dst, int ncomp,
+// dst[c][id[i]] = src[c][i] for c < ncomp (un-permute to load order); src in the
+// given type (prec 0 FP64, 1 FP32), dst FP64.
+hipError_t launch_unpermute(const void* const* src, int src_prec, double* const* dst, int ncomp,
                             const int32_t* id, int64_t np, hipStream_t s);
-// dst[c][i] = src[c][pos(i)] where pos is the inverse of id (gather to sorted order).
-hipError_t launch_permute_in(const double* const* src, double* const* dst, int ncomp,
+// dst[c][i] = src[c][id[i]]: gather load-order FP64 data into sorted order, stored in
+// the given type.
+hipError_t launch_permute_in(const double* const* src, void* const* dst, int dst_prec, int ncomp,
                              const int32_t* id, int64_t np, hipStream_t s);
 
 // Counting sort of particles by nearest-node cell.
 struct SortArgs {
   Mesh M;
   int64_t np;
-  int ncomp;              // number of double arrays to move
-  const double* src[12];
-  double* dst[12];
+  int ncomp;              // number of arrays to move
+  const void* src[12];
+  void* dst[12];
+  int32_t esz[12];        // element size of each array, 4 or 8 bytes
   const int32_t* id_src;
   int32_t* id_dst;
   const double* x[3];     // positions (also among src)

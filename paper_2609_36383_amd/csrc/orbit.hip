@@ -434,12 +434,13 @@ __device__ void evaluate(const OrbitArgs& a, const Tile& t, const R* gx, const R
   }
   // B_eff of the skew part K = D^T - D (D zero-padded to 3x3): (K23, -K13, K12)
   const R Beff[3] = {Dm[2][1] - Dm[1][2], -(Dm[2][0] - Dm[0][2]), Dm[1][0] - Dm[0][1]};
-  // normalized HC map
-  const R um[3] = {pm[0] * pc.inv_mk, pm[1] * pc.inv_mk, pm[2] * pc.inv_mk};
+  // normalized HC map.  The rotation is linear in u = p / (m kappa), so it is applied
+  // to p directly; u enters only through |u|^2 and u . tau in gamma_HC.  (Scaling p
+  // down and back up would bias every momentum by the same rounding in FP32.)
   const R tau[3] = {pc.tc * Beff[0], pc.tc * Beff[1], pc.tc * Beff[2]};
-  const R um2 = um[0] * um[0] + um[1] * um[1] + um[2] * um[2];
+  const R um2 = (pm[0] * pm[0] + pm[1] * pm[1] + pm[2] * pm[2]) * pc.inv_mk * pc.inv_mk;
   const R tau2 = tau[0] * tau[0] + tau[1] * tau[1] + tau[2] * tau[2];
-  const R ut = um[0] * tau[0] + um[1] * tau[1] + um[2] * tau[2];
+  const R ut = (pm[0] * tau[0] + pm[1] * tau[1] + pm[2] * tau[2]) * pc.inv_mk;
   const R sig = R(1) + um2 - tau2;
   const R X = tau2 + ut * ut;
   R tv[3];
@@ -457,11 +458,10 @@ __device__ void evaluate(const OrbitArgs& a, const Tile& t, const R* gx, const R
   const R t2 = tv[0] * tv[0] + tv[1] * tv[1] + tv[2] * tv[2];
   const R sf = R(2) * rcp_(R(1) + t2);
   const R sv[3] = {sf * tv[0], sf * tv[1], sf * tv[2]};
-  const R us[3] = {um[0] + (um[1] * tv[2] - um[2] * tv[1]), um[1] + (um[2] * tv[0] - um[0] * tv[2]),
-                   um[2] + (um[0] * tv[1] - um[1] * tv[0])};
-  const R up[3] = {um[0] + (us[1] * sv[2] - us[2] * sv[1]), um[1] + (us[2] * sv[0] - us[0] * sv[2]),
-                   um[2] + (us[0] * sv[1] - us[1] * sv[0])};
-  const R pp[3] = {pc.mk * up[0], pc.mk * up[1], pc.mk * up[2]};
+  const R ps[3] = {pm[0] + (pm[1] * tv[2] - pm[2] * tv[1]), pm[1] + (pm[2] * tv[0] - pm[0] * tv[2]),
+                   pm[2] + (pm[0] * tv[1] - pm[1] * tv[0])};
+  const R pp[3] = {pm[0] + (ps[1] * sv[2] - ps[2] * sv[1]), pm[1] + (ps[2] * sv[0] - ps[0] * sv[2]),
+                   pm[2] + (ps[0] * sv[1] - ps[1] * sv[0])};
   R pn[3], Pn1[3], pn1[3];
 #pragma unroll
   for (int c = 0; c < 3; ++c) {

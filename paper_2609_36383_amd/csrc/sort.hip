@@ -87,7 +87,12 @@ __global__ __launch_bounds__(kBlock) void k_scatter(SortArgs a) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= a.np) return;
   const int32_t pos = atomicAdd(a.cursor + a.key[i], 1);
-  for (int c = 0; c < a.ncomp; ++c) a.dst[c][pos] = a.src[c][i];
+  for (int c = 0; c < a.ncomp; ++c) {
+    if (a.esz[c] == 4)
+      static_cast<uint32_t*>(a.dst[c])[pos] = static_cast<const uint32_t*>(a.src[c])[i];
+    else
+      static_cast<uint64_t*>(a.dst[c])[pos] = static_cast<const uint64_t*>(a.src[c])[i];
+  }
   a.id_dst[pos] = a.id_src[i];
 }
 

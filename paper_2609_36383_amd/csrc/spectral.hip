@@ -298,14 +298,14 @@ __device__ __forceinline__ int point_stencil(const Mesh& M, const double* const*
 __global__ __launch_bounds__(kBlock) void k_init_deposit(InitArgs a) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= a.np) return;
-  const double q = a.q[i], m = fabs(q);
-  const double p[3] = {a.P[0][i], a.P[1][i], a.P[2][i]};
+  const double q = ld_bulk(a.q, i, a.prec), m = fabs(q);
+  const double p[3] = {ld_bulk(a.P[0], i, a.prec), ld_bulk(a.P[1], i, a.prec), ld_bulk(a.P[2], i, a.prec)};
   const double imk = 1.0 / (m * a.kappa);
   const double g = sqrt(1.0 + (p[0] * p[0] + p[1] * p[1] + p[2] * p[2]) * imk * imk);
   double v[3];
   for (int c = 0; c < 3; ++c) {
     v[c] = p[c] / (m * g);
-    a.v[c][i] = v[c];
+    st_bulk(a.v[c], i, v[c], a.prec);
   }
   int64_t nodes[27];
   double wts[27];
@@ -357,8 +357,8 @@ __global__ __launch_bounds__(kBlock) void k_canonical(CanonArgs a) {
   double Ah[3] = {0.0, 0.0, 0.0};
   for (int k = 0; k < cnt; ++k)
     for (int c = 0; c < 3; ++c) Ah[c] += wts[k] * a.A[c][nodes[k]];
-  const double q = a.q[i];
-  for (int c = 0; c < 3; ++c) a.P[c][i] += a.sign * q * Ah[c];
+  const double q = ld_bulk(a.q, i, a.prec);
+  for (int c = 0; c < 3; ++c) st_bulk(a.P[c], i, ld_bulk(a.P[c], i, a.prec) + a.sign * q * Ah[c], a.prec);
 }
 
 // Kinetic energy and transverse velocity moments of the accepted state.
@@ -373,9 +373,9 @@ __global__ __launch_bounds__(kBlock) void k_kinetic(KinArgs a) {
     double Ah[3] = {0.0, 0.0, 0.0};
     for (int k = 0; k < cnt; ++k)
       for (int c = 0; c < 3; ++c) Ah[c] += wts[k] * a.A[c][nodes[k]];
-    const double q = a.q[i], m = fabs(q);
+    const double q = ld_bulk(a.q, i, a.prec), m = fabs(q);
     double p[3];
-    for (int c = 0; c < 3; ++c) p[c] = a.P[c][i] - q * Ah[c];
+    for (int c = 0; c < 3; ++c) p[c] = ld_bulk(a.P[c], i, a.prec) - q * Ah[c];
     const double imk = 1.0 / (m * a.kappa);
     const double p2 = p[0] * p[0] + p[1] * p[1] + p[2] * p[2];
     const double g = sqrt(1.0 + p2 * imk * imk);
@@ -448,31 +448,35 @@ __global__ __launch_bounds__(kBlock) void k_spec_field(Mesh M, int which_e, cons
 }
 
 struct PermArgs {
-  const double* src[12];
-  double* dst[12];
+  const void* src[12];
+  void* dst[12];
 };
 
+// inverse = 0: scatter sorted data (type prec) back to load order (FP64);
+// inverse = 1: gather load-order data (FP64) into sorted order (type prec).
 __global__ __launch_bounds__(kBlock) void k_unpermute(PermArgs p, int ncomp, const int32_t* id,
-                                                      int64_t np, int inverse) {
+                                                      int64_t np, int inverse, int prec) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= np) return;
   const int64_t k = id[i];
   for (int c = 0; c < ncomp; ++c) {
     if (inverse)
-      p.dst[c][i] = p.src[c][k];  // gather load-order data into sorted order
+      st_bulk(p.dst[c], i, static_cast<const double*>(p.src[c])[k], prec);
     else
-      p.dst[c][k] = p.src[c][i];  // scatter sorted data back to load order
+      static_cast<double*>(p.dst[c])[k] = ld_bulk(p.src[c], i, prec);
   }
 }
 
-__global__ __launch_bounds__(kBlock) void k_mech_from_u(double* P0, double* P1, double* P2, const double* q,
-                                                        double kappa, int64_t np) {
+__global__ __launch_bounds__(kBlock) void k_load_state(const double* u0, const double* u1, const double* u2,
+                                                       const double* qd, void* P0, void* P1, void* P2, void* q,
+                                                       int prec, double kappa, int64_t np) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= np) return;
-  const double mk = fabs(q[i]) * kappa;
-  P0[i] *= mk;
-  P1[i] *= mk;
-  P2[i] *= mk;
+  st_bulk(q, i, qd[i], prec);
+  const double mk = fabs(ld_bulk(q, i, prec)) * kappa;  // m = |q| as stored
+  st_bulk(P0, i, mk * u0[i], prec);
+  st_bulk(P1, i, mk * u1[i], prec);
+  st_bulk(P2, i, mk * u2[i], prec);
 }
 
 __global__ __launch_bounds__(kBlock) void k_iota(int32_t* id, int64_t np) {
@@ -484,9 +488,11 @@ inline unsigned nblk(int64_t n) { return (unsigned)((n + kBlock - 1) / kBlock); 
 
 }  // namespace
 
-hipError_t launch_mech_from_u(double* const P[3], const double* q, double kappa, int64_t np, hipStream_t s) {
+hipError_t launch_load_state(double* const u[3], const double* qd, void* const P[3], void* q, int prec,
+                             double kappa, int64_t np, hipStream_t s) {
   if (np <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_mech_from_u, dim3(nblk(np)), dim3(kBlock), 0, s, P[0], P[1], P[2], q, kappa, np);
+  hipLaunchKernelGGL(k_load_state, dim3(nblk(np)), dim3(kBlock), 0, s, u[0], u[1], u[2], qd, P[0], P[1], P[2], q,
+                     prec, kappa, np);
   return hipGetLastError();
 }
 
@@ -593,27 +599,29 @@ hipError_t launch_spec_field(const Mesh& M, int which_e, const double2* phi, con
   return hipGetLastError();
 }
 
-hipError_t launch_unpermute(const double* const* src, double* const* dst, int ncomp,
+hipError_t launch_unpermute(const void* const* src, int src_prec, double* const* dst, int ncomp,
                             const int32_t* id, int64_t np, hipStream_t s) {
   if (np <= 0) return hipSuccess;
+  if (ncomp > 12) return hipErrorInvalidValue;
   PermArgs p;
-  for (int c = 0; c < ncomp && c < 12; ++c) {
+  for (int c = 0; c < ncomp; ++c) {
     p.src[c] = src[c];
     p.dst[c] = dst[c];
   }
-  hipLaunchKernelGGL(k_unpermute, dim3(nblk(np)), dim3(kBlock), 0, s, p, ncomp, id, np, 0);
+  hipLaunchKernelGGL(k_unpermute, dim3(nblk(np)), dim3(kBlock), 0, s, p, ncomp, id, np, 0, src_prec);
   return hipGetLastError();
 }
 
-hipError_t launch_permute_in(const double* const* src, double* const* dst, int ncomp,
+hipError_t launch_permute_in(const double* const* src, void* const* dst, int dst_prec, int ncomp,
                              const int32_t* id, int64_t np, hipStream_t s) {
   if (np <= 0) return hipSuccess;
+  if (ncomp > 12) return hipErrorInvalidValue;
   PermArgs p;
-  for (int c = 0; c < ncomp && c < 12; ++c) {
+  for (int c = 0; c < ncomp; ++c) {
     p.src[c] = src[c];
     p.dst[c] = dst[c];
   }
-  hipLaunchKernelGGL(k_unpermute, dim3(nblk(np)), dim3(kBlock), 0, s, p, ncomp, id, np, 1);
+  hipLaunchKernelGGL(k_unpermute, dim3(nblk(np)), dim3(kBlock), 0, s, p, ncomp, id, np, 1, dst_prec);
   return hipGetLastError();
 }
 

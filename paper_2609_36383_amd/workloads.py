@@ -34,8 +34,11 @@ COMMON = dict(kappa=1.0, sigma1=1.0, sigma2=1.0)
 
 
 def _tol(fp32_bulk=False):
+    # FP32-bulk: the inner test stops at 1e-6 relative, and the per-node outer residual
+    # then carries noise of about 5e-7 of the node current (measured), so the outer
+    # tests sit a factor 20 above that floor.
     if fp32_bulk:
-        return dict(tol_outer_abs=1e-10, tol_outer_rel=1e-7, tol_inner_abs=1e-10, tol_inner_rel=1e-6)
+        return dict(tol_outer_abs=1e-7, tol_outer_rel=1e-5, tol_inner_abs=1e-10, tol_inner_rel=1e-6)
     return dict(tol_outer_abs=1e-14, tol_outer_rel=1e-12, tol_inner_abs=1e-14, tol_inner_rel=1e-12)
 
 
