@@ -184,7 +184,7 @@ size_t carve(gmhc_ctx* c, char* base, int64_t np) {
   c->cursor = cv.take<int32_t>(Ng + 1);
   c->scan_tmp_bytes = sort_scan_tmp_bytes(Ng);
   c->scan_tmp = cv.take<char>(c->scan_tmp_bytes);
-  c->max_blocks = std::max<int64_t>((np + kBlock - 1) / kBlock, 1024);
+  c->max_blocks = std::max<int64_t>((np + kOrbitBlock - 1) / kOrbitBlock, 1024);
   c->partials = cv.take<double>((size_t)(c->max_blocks + 1024) * 8);
   c->dres = cv.take<double>(64);
   for (int l = 0; l < d; ++l) c->tw[l] = cv.take<double2>(std::max(c->M.n[l] / 2, 1));
@@ -246,7 +246,7 @@ int32_t run_orbit(gmhc_ctx* ctx, int iterate, double* ms) {
   if (ctx->cfg.timing) HIPCK(hipEventRecord(ctx->ev0, ctx->stream));
   HIPCK(launch_orbit(a, ctx->ngl, ctx->stream));
   if (ctx->cfg.timing) HIPCK(hipEventRecord(ctx->ev1, ctx->stream));
-  const int nb = (int)((ctx->np + kBlock - 1) / kBlock);
+  const int nb = (int)((ctx->np + kOrbitBlock - 1) / kOrbitBlock);
   if (nb > 0) {
     HIPCK(launch_reduce(ctx->partials, nb, kOrbitParts, kOrbitParts, 1u << OP_ITMAX, ctx->dres,
                         ctx->stream));

@@ -8,6 +8,7 @@
 namespace gmhc {
 
 constexpr int kBlock = 256;       // threads per workgroup (4 wave64)
+constexpr int kOrbitBlock = 64;   // threads per orbit-pass workgroup (one wave64)
 constexpr int kMaxGL = 8;         // Gauss-Legendre points per segment supported
 constexpr int kMaxCross = 8;      // knot crossings per axis per step supported
 constexpr int kOrbitParts = 8;    // per-block partial values written by the orbit pass

@@ -37,7 +37,11 @@ namespace gmhc {
 namespace {
 
 constexpr int kHalo = 2;               // tile halo in nodes
-constexpr int kTileBytes = 40 * 1024;  // LDS per workgroup for the field and current tiles
+// LDS per workgroup for the field and current tiles.  A one-wave workgroup of sorted
+// particles spans one or two cells; the budgets let eight workgroups share a CU's
+// 160 KB in every dimension (3D: a 6 x 5 x 5 box of 12 FP64 values per node).
+template <int D>
+constexpr int tile_bytes() { return D == 3 ? 18 * 1024 : 8 * 1024; }
 
 __device__ __forceinline__ int wrapi(int i, int n) {
   int r = i % n;
@@ -307,13 +311,17 @@ __device__ __forceinline__ void eval_segment(const OrbitArgs& a, const Tile& t, 
 #pragma unroll 1
   for (int row = 0; row < NROW; ++row) {
     const int cy = D > 1 ? row % 3 : 0, cz = D > 2 ? row / 3 : 0;
-    // the row's field values first, so their latency overlaps the weight arithmetic
     const int rowoff = st.row(cy, cz);
+    // FP32 has registers to spare: read the row's field values before the weight
+    // arithmetic so their latency overlaps it.  FP64 reads them node by node below.
+    constexpr bool kEarly = sizeof(R) == 4;
     R F[3][D + 6];
+    if (kEarly) {
 #pragma unroll
-    for (int c = 0; c < 3; ++c)
+      for (int c = 0; c < 3; ++c)
 #pragma unroll
-      for (int f = 0; f < D + 6; ++f) F[c][f] = ld<D, R, LDS>(a, t, f, st.ix[c] + rowoff);
+        for (int f = 0; f < D + 6; ++f) F[c][f] = ld<D, R, LDS>(a, t, f, st.ix[c] + rowoff);
+    }
     R S[3], X0[3], X1[3], Y0[3], Y1[3], Z0[3], Z1[3];
 #pragma unroll
     for (int c = 0; c < 3; ++c) S[c] = X0[c] = X1[c] = Y0[c] = Y1[c] = Z0[c] = Z1[c] = R(0);
@@ -352,6 +360,11 @@ __device__ __forceinline__ void eval_segment(const OrbitArgs& a, const Tile& t, 
     }
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
+      const int g = st.ix[c] + rowoff;
+      if (!kEarly) {
+#pragma unroll
+        for (int f = 0; f < D + 6; ++f) F[c][f] = ld<D, R, LDS>(a, t, f, g);
+      }
 #pragma unroll
       for (int l = 0; l < D; ++l) gp[l] += S[c] * F[c][l];
 #pragma unroll
@@ -801,13 +814,13 @@ __device__ __forceinline__ int tile_to_global(const Mesh& M, const Tile& t, int 
 #endif
 
 template <int D, int NGL, class R>
-__global__ __launch_bounds__(kBlock)
+__global__ __launch_bounds__(kOrbitBlock)
 __attribute__((amdgpu_waves_per_eu(GMHC_ORBIT_WAVES_PER_EU))) void k_orbit(OrbitArgs a) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const Mesh& M = a.M;
   const int64_t ps = a.ps;
   HIP_DYNAMIC_SHARED(double, s_dyn);
-  __shared__ int s_mm[2 * 3 * (kBlock / 64)];
+  __shared__ int s_mm[2 * 3 * (kOrbitBlock / 64)];
   constexpr int NF = nfields<D>();
   const R* Pp = static_cast<const R*>(a.P);
   const R* qp = static_cast<const R*>(a.q);
@@ -873,7 +886,7 @@ __attribute__((amdgpu_waves_per_eu(GMHC_ORBIT_WAVES_PER_EU))) void k_orbit(Orbit
   }
   // field tile in R, then the FP64 current tile at an 8-byte boundary
   const int64_t fbytes = ((int64_t)nodes * NF * (int64_t)sizeof(R) + 7) / 8 * 8;
-  if (ok && fbytes + (int64_t)nodes * 3 * 8 > kTileBytes) ok = 0;
+  if (ok && fbytes + (int64_t)nodes * 3 * 8 > tile_bytes<D>()) ok = 0;
   t.nodes = uni(nodes);
   t.ok = uni(ok);
   t.joff = uni((int)(fbytes / 8));
@@ -1031,7 +1044,7 @@ __attribute__((amdgpu_waves_per_eu(GMHC_ORBIT_WAVES_PER_EU))) void k_orbit(Orbit
       part[v] = (v == OP_ITMAX) ? fmax(part[v], o2) : part[v] + o2;
     }
   }
-  __shared__ double sh[kBlock / 64][kOrbitParts];
+  __shared__ double sh[kOrbitBlock / 64][kOrbitParts];
   const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
   if (lane == 0)
 #pragma unroll
@@ -1050,11 +1063,11 @@ hipError_t launch_d(const OrbitArgs& a, unsigned blocks, hipStream_t s) {
   // compile-time Gauss-Legendre orders: d+1 (exact for the per-segment polynomials)
   // and 8 (the paper's); any other order runs the runtime loop
   if (a.ngl == D + 1)
-    hipLaunchKernelGGL((k_orbit<D, D + 1, R>), dim3(blocks), dim3(kBlock), kTileBytes, s, a);
+    hipLaunchKernelGGL((k_orbit<D, D + 1, R>), dim3(blocks), dim3(kOrbitBlock), tile_bytes<D>(), s, a);
   else if (a.ngl == 8)
-    hipLaunchKernelGGL((k_orbit<D, 8, R>), dim3(blocks), dim3(kBlock), kTileBytes, s, a);
+    hipLaunchKernelGGL((k_orbit<D, 8, R>), dim3(blocks), dim3(kOrbitBlock), tile_bytes<D>(), s, a);
   else
-    hipLaunchKernelGGL((k_orbit<D, 0, R>), dim3(blocks), dim3(kBlock), kTileBytes, s, a);
+    hipLaunchKernelGGL((k_orbit<D, 0, R>), dim3(blocks), dim3(kOrbitBlock), tile_bytes<D>(), s, a);
   return hipGetLastError();
 }
 
@@ -1063,7 +1076,7 @@ hipError_t launch_d(const OrbitArgs& a, unsigned blocks, hipStream_t s) {
 hipError_t launch_orbit(const OrbitArgs& a, int ngl, hipStream_t s) {
   (void)ngl;
   if (a.np <= 0) return hipSuccess;
-  const unsigned blocks = (unsigned)((a.np + kBlock - 1) / kBlock);
+  const unsigned blocks = (unsigned)((a.np + kOrbitBlock - 1) / kOrbitBlock);
   const bool f32 = a.precision == 1;
   switch (a.M.d) {
     case 1: return f32 ? launch_d<1, float>(a, blocks, s) : launch_d<1, double>(a, blocks, s);
