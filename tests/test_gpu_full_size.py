@@ -1,0 +1,142 @@
+"""GPU parity at the full workload sizes, in the launch configuration the benchmark times.
+
+* Frozen-field single evaluation of every particle (load order is cell-sorted, so the
+  LDS tile path runs as in the benchmark): at 1M particles the oracle evaluates all of
+  them and v_out, P^{n+1} and J are compared element by element; at 67M particles the
+  oracle evaluates a seeded random sample of particles one by one and the current is
+  checked through the identity sum_g J_g dV = sum_i q_i v_out,i (the orbit-averaged
+  shape weights of each particle sum to one).
+* Whole implicit steps at full size: relative energy drift at most 10x the nonlinear
+  tolerance in FP64 (1e-6 in FP32-bulk), Gauss-law and Lorenz-gauge residuals at FP64
+  roundoff.
+"""
+import functools
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2609_36383_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def _gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2609_36383_amd import gmhc as G
+    return G
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _rel(a, b):
+    b = np.asarray(b)
+    return float(np.abs(np.asarray(a) - b).max() / max(np.abs(b).max(), 1e-300))
+
+
+@functools.lru_cache(maxsize=1)
+def _workload(name):
+    w = W.spec(name)
+    return w, W.particles(w)
+
+
+def _frozen_inputs(w, x, u, q, seed):
+    """Smooth random fields of the workload's mesh and a canonical state P = m kappa u,
+    v = u / gamma (kappa = 1)."""
+    d = w["dim"]
+    gphi, An, Anp1, _ = W.random_fields(d, w["n"], w["length"], seed=seed, amp=0.3)
+    Uh = (Anp1 - An) / w["dt"]
+    P = np.abs(q)[None, :] * u
+    v = u / np.sqrt(1.0 + (u * u).sum(axis=0))[None, :]
+    return gphi, An, Anp1, Uh, P, v
+
+
+@pytest.mark.parametrize("name", ["weibel2d", "tsi1d_big"])
+def test_full_size_frozen_evaluation_all_particles(name):
+    G = _gpu()
+    w, (x, u, q) = _workload(name)
+    gphi, An, Anp1, Uh, P, v = _frozen_inputs(w, x, u, q, seed=31)
+    kw = dict(dim=w["dim"], n=w["n"], lo=w["lo"], length=w["length"], dt=w["dt"])
+    sim = G.Simulation(G.make_config(**kw, gl_order=0), q.size)
+    sim.load_particles(x, u, q)
+    sim.set_particle_state(x, P, v)
+    sim.set_frozen_fields(gphi, An, Anp1, Uh)
+    rep = sim.orbit_pass_frozen(iterate=False)
+    vout, Pn1, J = sim.read_pass()
+    del sim
+    osim = O.OracleSim(O.make_config(**kw, gl_order=8))
+    osim.load_particles(x, u, q)
+    osim.set_particle_state(x, P, v)
+    ref = osim.orbit_pass(gphi, An, Anp1, Uh, v, iterate=False)
+    del osim
+    _say(f"{name} full frozen: {q.size} particles, v {_rel(vout, ref['vout']):.2e} "
+         f"P {_rel(Pn1, ref['Pnp1']):.2e} J {_rel(J, ref['J']):.2e}, {rep['segments']} segments")
+    assert rep["failed"] == 0
+    assert _rel(vout, ref["vout"]) < 1e-12
+    assert _rel(Pn1, ref["Pnp1"]) < 1e-12
+    assert _rel(J, ref["J"]) < 1e-12
+
+
+@pytest.mark.parametrize("name", ["mixed2d", "weibel3d"])
+def test_full_size_frozen_evaluation_sampled(name):
+    G = _gpu()
+    w, (x, u, q) = _workload(name)
+    gphi, An, Anp1, Uh, P, v = _frozen_inputs(w, x, u, q, seed=37)
+    kw = dict(dim=w["dim"], n=w["n"], lo=w["lo"], length=w["length"], dt=w["dt"])
+    sim = G.Simulation(G.make_config(**kw, gl_order=0), q.size)
+    sim.load_particles(x, u, q)
+    sim.set_particle_state(x, P, v)
+    sim.set_frozen_fields(gphi, An, Anp1, Uh)
+    rep = sim.orbit_pass_frozen(iterate=False)
+    vout, Pn1, J = sim.read_pass()
+    del sim
+    assert rep["failed"] == 0
+    # the oracle evaluates a seeded sample one by one
+    idx = np.sort(np.random.default_rng(41).choice(q.size, 16384, replace=False))
+    osim = O.OracleSim(O.make_config(**kw, gl_order=8))
+    osim.load_particles(x[:, idx], u[:, idx], q[idx])
+    osim.set_particle_state(x[:, idx], P[:, idx], v[:, idx])
+    ref = osim.orbit_pass(gphi, An, Anp1, Uh, v[:, idx], iterate=False)
+    del osim
+    dv, dP = _rel(vout[:, idx], ref["vout"]), _rel(Pn1[:, idx], ref["Pnp1"])
+    # total current identity over all particles
+    dV = float(np.prod([w["length"][i] / w["n"][i] for i in range(w["dim"])]))
+    lhs = J.sum(axis=1) * dV
+    rhs = (q[None, :] * vout).sum(axis=1)
+    scale = float((np.abs(q)[None, :] * np.abs(vout)).sum())
+    dj = float(np.abs(lhs - rhs).max() / scale)
+    _say(f"{name} full frozen (sample of 16384 of {q.size}): v {dv:.2e} P {dP:.2e}; current identity {dj:.2e}")
+    assert dv < 1e-12 and dP < 1e-12
+    assert dj < 1e-12
+
+
+@pytest.mark.parametrize("name,steps", [("weibel2d", 3), ("tsi1d_big", 3), ("mixed2d", 1), ("weibel3d", 1)])
+@pytest.mark.parametrize("fp32", [False, True], ids=["fp64", "fp32bulk"])
+def test_full_size_steps_energy_and_constraints(name, steps, fp32):
+    G = _gpu()
+    w, (x, u, q) = _workload(name)
+    cfg = G.config_from_dict(W.config_dict(w, fp32_bulk=fp32), gl_order=0, sort_every=10,
+                             precision=G.FP32_BULK if fp32 else G.FP64)
+    sim = G.Simulation(cfg, q.size)
+    sim.load_particles(x, u, q)
+    sim.initialize()
+    drift, gmax, lmax = 0.0, 0.0, 0.0
+    for _ in range(steps):
+        _, rep = sim.step()
+        d = sim.diagnostics()
+        drift = max(drift, d["energy_rel"])
+        gmax = max(gmax, d["gauss_rms"])
+        lmax = max(lmax, d["lorenz_rms"])
+    del sim
+    bound = 1e-6 if fp32 else 10 * W.config_dict(w)["tol_outer_rel"]
+    _say(f"{name} full {'fp32-bulk' if fp32 else 'fp64'}: {steps} steps, drift {drift:.2e} (bound {bound:.0e}), "
+         f"gauss {gmax:.2e}, lorenz {lmax:.2e}, outer {rep['outer_iters']}")
+    assert drift <= bound
+    assert gmax < 1e-10 and lmax < 1e-10
