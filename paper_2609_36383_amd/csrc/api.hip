@@ -236,6 +236,7 @@ OrbitArgs orbit_args(gmhc_ctx* c, int iterate) {
   a.q = c->q;
   a.iters = c->iters;
   a.partials = c->partials;
+  a.pstride = c->max_blocks;
   return a;
 }
 
@@ -248,7 +249,7 @@ int32_t run_orbit(gmhc_ctx* ctx, int iterate, double* ms) {
   if (ctx->cfg.timing) HIPCK(hipEventRecord(ctx->ev1, ctx->stream));
   const int nb = (int)((ctx->np + kOrbitBlock - 1) / kOrbitBlock);
   if (nb > 0) {
-    HIPCK(launch_reduce(ctx->partials, nb, kOrbitParts, kOrbitParts, 1u << OP_ITMAX, ctx->dres,
+    HIPCK(launch_reduce(ctx->partials, nb, 1, ctx->max_blocks, kOrbitParts, 1u << OP_ITMAX, ctx->dres,
                         ctx->stream));
   } else {
     HIPCK(hipMemsetAsync(ctx->dres, 0, sizeof(double) * kOrbitParts, ctx->stream));
@@ -647,7 +648,7 @@ int32_t gmhc_step(gmhc_ctx* ctx, gmhc_step_report* rep) {
     ra.partials = ctx->partials + (size_t)ctx->max_blocks * 8;  // disjoint from orbit partials
     const int rb = res_blocks(ctx);
     HIPCK(launch_residual(ra, rb, s));
-    HIPCK(launch_reduce(ra.partials, rb, kResParts, kResParts, 1u << 3, ctx->dres + kResOff, s));
+    HIPCK(launch_reduce(ra.partials, rb, kResParts, 1, kResParts, 1u << 3, ctx->dres + kResOff, s));
     double oms = 0.0;
     st = fetch_results(ctx, &oms);
     if (st) return st;
@@ -725,7 +726,7 @@ int32_t gmhc_diagnostics(gmhc_ctx* ctx, gmhc_diag* out) {
   ka.partials = ctx->partials;
   const int kb = (int)std::min<int64_t>(std::max<int64_t>((ctx->np + kBlock - 1) / kBlock, 1), 1024);
   HIPCK(launch_kinetic(ka, kb, s));
-  HIPCK(launch_reduce(ctx->partials, kb, kDiagParts, kDiagParts, 0u, ctx->dres, s));
+  HIPCK(launch_reduce(ctx->partials, kb, kDiagParts, 1, kDiagParts, 0u, ctx->dres, s));
   SpecDiagArgs sa{};
   sa.M = M;
   sa.kappa2 = ctx->cfg.kappa * ctx->cfg.kappa;
@@ -739,7 +740,7 @@ int32_t gmhc_diagnostics(gmhc_ctx* ctx, gmhc_diag* out) {
   sa.partials = ctx->partials + (size_t)ctx->max_blocks * 8;
   const int sb = res_blocks(ctx);
   HIPCK(launch_spec_diag(sa, sb, s));
-  HIPCK(launch_reduce(sa.partials, sb, kDiagParts, kDiagParts, 0u, ctx->dres + kResOff, s));
+  HIPCK(launch_reduce(sa.partials, sb, kDiagParts, 1, kDiagParts, 0u, ctx->dres + kResOff, s));
   HIPCK(hipMemcpyAsync(ctx->hres, ctx->dres, sizeof(double) * 32, hipMemcpyDeviceToHost, s));
   HIPCK(hipStreamSynchronize(s));
   const double* h = ctx->hres;

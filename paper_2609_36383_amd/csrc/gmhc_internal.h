@@ -78,7 +78,8 @@ struct OrbitArgs {
   const double* trial;   // [d+6]: grad_h phi^{n+1/2} (d), A^{n+1} (3), U^{n+1/2} (3)
   const double* An;      // [3] A^n
   double* J;             // [3] orbit current accumulator
-  double* partials;      // [gridDim.x][kOrbitParts]
+  double* partials;      // [kOrbitParts][pstride]: value v of block b at v * pstride + b
+  int64_t pstride;       // >= gridDim.x
 };
 
 hipError_t launch_orbit(const OrbitArgs& a, int ngl, hipStream_t s);
@@ -126,8 +127,9 @@ struct ResidualArgs {
 };
 hipError_t launch_residual(const ResidualArgs& a, int blocks, hipStream_t s);
 
-// out[v] = reduce over blocks of partials[b*stride + v]; ops bit v set = max, else sum.
-hipError_t launch_reduce(const double* partials, int nblocks, int stride, int nvals,
+// out[v] = reduce over blocks b of partials[b * bstride + v * vstride]; max_mask bit v
+// set = max, else sum.
+hipError_t launch_reduce(const double* partials, int nblocks, int64_t bstride, int64_t vstride, int nvals,
                          uint32_t max_mask, double* out, hipStream_t s);
 
 hipError_t launch_axpy2(double* y, const double* x, double2* yc, const double2* xc, double beta,

@@ -1054,7 +1054,7 @@ __attribute__((amdgpu_waves_per_eu(GMHC_ORBIT_WAVES_PER_EU))) void k_orbit(Orbit
     const int v = threadIdx.x;
     double acc = sh[0][v];
     for (int w = 1; w < (int)(blockDim.x / 64); ++w) acc = (v == OP_ITMAX) ? fmax(acc, sh[w][v]) : acc + sh[w][v];
-    a.partials[(int64_t)blockIdx.x * kOrbitParts + v] = acc;
+    a.partials[(int64_t)v * a.pstride + blockIdx.x] = acc;
   }
 }
 

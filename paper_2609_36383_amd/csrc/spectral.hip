@@ -217,8 +217,8 @@ __global__ __launch_bounds__(kBlock) void k_residual(ResidualArgs a) {
   block_store<kResParts>(part, 1u << 3, a.partials);
 }
 
-__global__ __launch_bounds__(kBlock) void k_reduce(const double* partials, int nblocks, int stride,
-                                                   int nvals, uint32_t max_mask, double* out) {
+__global__ __launch_bounds__(kBlock) void k_reduce(const double* partials, int nblocks, int64_t bstride,
+                                                   int64_t vstride, int nvals, uint32_t max_mask, double* out) {
   // One workgroup per value.  Thread t folds blocks t, t + 256, ... in order, then a
   // fixed pairwise tree combines the threads: the result depends only on nblocks.
   const int v = blockIdx.x;
@@ -226,7 +226,7 @@ __global__ __launch_bounds__(kBlock) void k_reduce(const double* partials, int n
   const bool mx = (max_mask >> v) & 1u;
   double acc = mx ? -INFINITY : 0.0;
   for (int b = threadIdx.x; b < nblocks; b += blockDim.x) {
-    const double x = partials[(int64_t)b * stride + v];
+    const double x = partials[(int64_t)b * bstride + (int64_t)v * vstride];
     acc = mx ? fmax(acc, x) : acc + x;
   }
   __shared__ double sh[kBlock];
@@ -552,9 +552,9 @@ hipError_t launch_residual(const ResidualArgs& a, int blocks, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_reduce(const double* partials, int nblocks, int stride, int nvals,
+hipError_t launch_reduce(const double* partials, int nblocks, int64_t bstride, int64_t vstride, int nvals,
                          uint32_t max_mask, double* out, hipStream_t s) {
-  hipLaunchKernelGGL(k_reduce, dim3((unsigned)nvals), dim3(kBlock), 0, s, partials, nblocks, stride, nvals,
+  hipLaunchKernelGGL(k_reduce, dim3((unsigned)nvals), dim3(kBlock), 0, s, partials, nblocks, bstride, vstride, nvals,
                      max_mask, out);
   return hipGetLastError();
 }
