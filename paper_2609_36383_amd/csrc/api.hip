@@ -65,6 +65,13 @@ struct gmhc_ctx {
   double2* tw[3] = {};
   FftPlanAxis axes[3];
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  // HIP graphs of the outer iteration, keyed by the buffers and slots they use
+  struct GraphEntry {
+    std::vector<uintptr_t> key;
+    hipGraphExec_t exec;
+  };
+  std::vector<GraphEntry> graphs;
+  bool graphs_off = false;  // capture failed once: run eagerly
   // bookkeeping
   double t = 0.0;
   int64_t step = 0;
@@ -240,10 +247,12 @@ OrbitArgs orbit_args(gmhc_ctx* c, int iterate) {
   return a;
 }
 
+int orbit_blocks(const gmhc_ctx* c) { return (int)((c->np + kOrbitBlock - 1) / kOrbitBlock); }
+
 // Orbit pass + first-level reduction to dres[0..7]; optional HIP-event timing.
 int32_t run_orbit(gmhc_ctx* ctx, int iterate, double* ms) {
   OrbitArgs a = orbit_args(ctx, iterate);
-  HIPCK(hipMemsetAsync(ctx->Jdep, 0, sizeof(double) * 3 * ctx->M.Ng, ctx->stream));
+  HIPCK(launch_zero(ctx->Jdep, 3 * ctx->M.Ng, ctx->stream));
   if (ctx->cfg.timing) HIPCK(hipEventRecord(ctx->ev0, ctx->stream));
   HIPCK(launch_orbit(a, ctx->ngl, ctx->stream));
   if (ctx->cfg.timing) HIPCK(hipEventRecord(ctx->ev1, ctx->stream));
@@ -262,8 +271,14 @@ int res_blocks(const gmhc_ctx* c) {
   return (int)std::min<int64_t>((c->M.Ng + kBlock - 1) / kBlock, 1024);
 }
 
+int32_t wait_results(gmhc_ctx* ctx, double* orbit_ms);
+
 int32_t fetch_results(gmhc_ctx* ctx, double* orbit_ms) {
   HIPCK(hipMemcpyAsync(ctx->hres, ctx->dres, sizeof(double) * 32, hipMemcpyDeviceToHost, ctx->stream));
+  return wait_results(ctx, orbit_ms);
+}
+
+int32_t wait_results(gmhc_ctx* ctx, double* orbit_ms) {
   HIPCK(hipStreamSynchronize(ctx->stream));
   if (ctx->cfg.timing && orbit_ms) {
     float f = 0.0f;
@@ -420,6 +435,7 @@ void gmhc_destroy(gmhc_ctx* ctx) {
     DevGuard g(ctx->device);
     (void)hipStreamSynchronize(ctx->stream);
     if (ctx->hres) (void)hipHostFree(ctx->hres);
+    for (auto& e : ctx->graphs) (void)hipGraphExecDestroy(e.exec);
     if (ctx->ev0) (void)hipEventDestroy(ctx->ev0);
     if (ctx->ev1) (void)hipEventDestroy(ctx->ev1);
   }
@@ -591,24 +607,21 @@ int32_t gmhc_initialize(gmhc_ctx* ctx) {
   return GMHC_OK;
 }
 
-int32_t gmhc_step(gmhc_ctx* ctx, gmhc_step_report* rep) {
-  if (!ctx) return GMHC_EINVAL;
-  if (!ctx->initialized) return fail(ctx, GMHC_ESTATE, "initialize before step");
-  DevGuard gd(ctx->device);
+// Parts of one outer iteration's device work (see enqueue_outer).
+enum OuterPart { OUTER_ALL = 0, OUTER_PRE = 1, OUTER_ORBIT = 2, OUTER_POST = 3 };
+
+// Device work of one outer iteration for the trial current in slot cur, with H(j)
+// written to slot hs: CN field step and trial fields (PRE), the orbit pass with its
+// inner Picard loop (ORBIT, bracketed by the timing events when timing is on), then
+// the pass reduction, projected orbit current, outer residual and the copy of the
+// results to pinned host memory (POST).  Enqueued without host synchronization, so
+// the parts can be captured as HIP graphs.
+int32_t enqueue_outer(gmhc_ctx* ctx, int cur, int hs, int part) {
   const Mesh& M = ctx->M;
-  const int64_t Ng = M.Ng, np = ctx->np;
+  const int64_t Ng = M.Ng;
   const int d = M.d;
   hipStream_t s = ctx->stream;
-  gmhc_step_report R{};
-  if (ctx->cfg.sort_every > 0 && ctx->step % ctx->cfg.sort_every == 0) {
-    int32_t st = sort_particles(ctx);
-    if (st) return st;
-  }
-  for (int l = 0; l < 3; ++l)
-    if (np) HIPCK(hipMemcpyAsync(ctx->vw[l], ctx->vb[l], ctx->es * np, hipMemcpyDeviceToDevice, s));
-  int cur = 0;
-  for (int k = 1; k <= ctx->cfg.max_outer; ++k) {
-    // field step for the trial current
+  if (part == OUTER_ALL || part == OUTER_PRE) {
     CNArgs ca{};
     ca.M = M;
     ca.dt = ctx->cfg.dt;
@@ -629,11 +642,18 @@ int32_t gmhc_step(gmhc_ctx* ctx, gmhc_step_report* rep) {
     ca.out = ctx->cout;
     HIPCK(launch_cn(ca, s));
     HIPCK(fft_nd(M, ctx->axes, d + 6, nullptr, ctx->cout, nullptr, ctx->trial, ctx->cout, true, false, s));
-    // orbit pass with the inner Picard loop
-    int32_t st = run_orbit(ctx, 1, nullptr);
-    if (st) return st;
+    HIPCK(launch_zero(ctx->Jdep, 3 * Ng, s));
+  }
+  if (part == OUTER_ALL || part == OUTER_ORBIT) {
+    const bool timed = ctx->cfg.timing && part == OUTER_ORBIT;
+    if (timed) HIPCK(hipEventRecord(ctx->ev0, s));
+    HIPCK(launch_orbit(orbit_args(ctx, 1), ctx->ngl, s));
+    if (timed) HIPCK(hipEventRecord(ctx->ev1, s));
+  }
+  if (part == OUTER_ALL || part == OUTER_POST) {
+    HIPCK(launch_reduce(ctx->partials, orbit_blocks(ctx), 1, ctx->max_blocks, kOrbitParts, 1u << OP_ITMAX,
+                        ctx->dres, s));
     // H(j) = P J_orb in spectral and real space
-    const int hs = (cur == 1) ? 2 : 1;
     HIPCK(fft_nd(M, ctx->axes, 3, ctx->Jdep, nullptr, ctx->jh[hs], nullptr, nullptr, false,
                  ctx->cfg.project_nyquist != 0, s));
     HIPCK(fft_nd(M, ctx->axes, 3, nullptr, ctx->jh[hs], nullptr, ctx->jr[hs], ctx->cscr, true, false, s));
@@ -649,8 +669,123 @@ int32_t gmhc_step(gmhc_ctx* ctx, gmhc_step_report* rep) {
     const int rb = res_blocks(ctx);
     HIPCK(launch_residual(ra, rb, s));
     HIPCK(launch_reduce(ra.partials, rb, kResParts, 1, kResParts, 1u << 3, ctx->dres + kResOff, s));
+    HIPCK(hipMemcpyAsync(ctx->hres, ctx->dres, sizeof(double) * 32, hipMemcpyDeviceToHost, s));
+  }
+  return GMHC_OK;
+}
+
+// The graph of enqueue_outer(cur, hs, part) for the current buffer layout: reused
+// while the buffers and slots it touches are the same (they alternate with commits and
+// sorts), captured on first use.  *ex = nullptr when capture is not possible; the
+// caller then runs the same work eagerly.
+int32_t outer_graph(gmhc_ctx* ctx, int cur, int hs, int part, hipGraphExec_t* ex) {
+  *ex = nullptr;
+  std::vector<uintptr_t> key = {(uintptr_t)cur, (uintptr_t)hs, (uintptr_t)part,
+                                (uintptr_t)ctx->S0, (uintptr_t)ctx->S1, (uintptr_t)ctx->q};
+  for (int l = 0; l < 3; ++l) {
+    key.push_back((uintptr_t)ctx->x[l]);
+    key.push_back((uintptr_t)ctx->x2[l]);
+    key.push_back((uintptr_t)ctx->P[l]);
+    key.push_back((uintptr_t)ctx->P2[l]);
+    key.push_back((uintptr_t)ctx->vw[l]);
+    key.push_back((uintptr_t)ctx->jr[l]);
+    key.push_back((uintptr_t)ctx->jh[l]);
+  }
+  for (auto& e : ctx->graphs)
+    if (e.key == key) {
+      *ex = e.exec;
+      return GMHC_OK;
+    }
+  hipStream_t s = ctx->stream;
+  if (hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+    (void)hipGetLastError();
+    ctx->graphs_off = true;
+    return GMHC_OK;
+  }
+  const int32_t st = enqueue_outer(ctx, cur, hs, part);
+  hipGraph_t g = nullptr;
+  const hipError_t ee = hipStreamEndCapture(s, &g);
+  hipGraphExec_t exec = nullptr;
+  const bool ok = st == GMHC_OK && ee == hipSuccess && g &&
+                  hipGraphInstantiate(&exec, g, nullptr, nullptr, 0) == hipSuccess;
+  if (g) (void)hipGraphDestroy(g);
+  if (!ok) {
+    (void)hipGetLastError();
+    ctx->err.clear();
+    ctx->graphs_off = true;
+    return GMHC_OK;
+  }
+  if (ctx->graphs.size() >= 24) {
+    (void)hipGraphExecDestroy(ctx->graphs.front().exec);
+    ctx->graphs.erase(ctx->graphs.begin());
+  }
+  ctx->graphs.push_back({key, exec});
+  *ex = exec;
+  return GMHC_OK;
+}
+
+// One outer iteration's device work: replayed graphs (with the orbit launch eager
+// between two graphs when its launches are timed), or eager launches.
+int32_t run_outer(gmhc_ctx* ctx, int cur, int hs, bool& use_graph, int32_t& replays) {
+  hipStream_t s = ctx->stream;
+  if (use_graph) {
+    const int parts[3] = {OUTER_PRE, OUTER_ORBIT, OUTER_POST};
+    const int np = ctx->cfg.timing ? 3 : 1;
+    hipGraphExec_t ex[3] = {nullptr, nullptr, nullptr};
+    bool ok = true;
+    for (int k = 0; k < np && ok; ++k) {
+      if (np == 3 && parts[k] == OUTER_ORBIT) continue;  // launched eagerly
+      int32_t st = outer_graph(ctx, cur, hs, np == 3 ? parts[k] : OUTER_ALL, &ex[k]);
+      if (st) return st;
+      ok = ex[k] != nullptr;
+    }
+    if (ok) {
+      for (int k = 0; k < np; ++k) {
+        if (np == 3 && parts[k] == OUTER_ORBIT) {
+          int32_t st = enqueue_outer(ctx, cur, hs, OUTER_ORBIT);
+          if (st) return st;
+        } else {
+          HIPCK(hipGraphLaunch(ex[k], s));
+        }
+      }
+      replays += 1;
+      return GMHC_OK;
+    }
+    use_graph = false;
+  }
+  if (ctx->cfg.timing) {
+    for (int part : {OUTER_PRE, OUTER_ORBIT, OUTER_POST}) {
+      int32_t st = enqueue_outer(ctx, cur, hs, part);
+      if (st) return st;
+    }
+    return GMHC_OK;
+  }
+  return enqueue_outer(ctx, cur, hs, OUTER_ALL);
+}
+
+int32_t gmhc_step(gmhc_ctx* ctx, gmhc_step_report* rep) {
+  if (!ctx) return GMHC_EINVAL;
+  if (!ctx->initialized) return fail(ctx, GMHC_ESTATE, "initialize before step");
+  DevGuard gd(ctx->device);
+  const Mesh& M = ctx->M;
+  const int64_t Ng = M.Ng, np = ctx->np;
+  const int d = M.d;
+  hipStream_t s = ctx->stream;
+  gmhc_step_report R{};
+  if (ctx->cfg.sort_every > 0 && ctx->step % ctx->cfg.sort_every == 0) {
+    int32_t st = sort_particles(ctx);
+    if (st) return st;
+  }
+  for (int l = 0; l < 3; ++l)
+    if (np) HIPCK(hipMemcpyAsync(ctx->vw[l], ctx->vb[l], ctx->es * np, hipMemcpyDeviceToDevice, s));
+  int cur = 0;
+  bool use_graph = ctx->cfg.graphs != 0 && ctx->stream != nullptr && !ctx->graphs_off;
+  for (int k = 1; k <= ctx->cfg.max_outer; ++k) {
+    const int hs = (cur == 1) ? 2 : 1;
+    int32_t st = run_outer(ctx, cur, hs, use_graph, R.graph_replays);
+    if (st) return st;
     double oms = 0.0;
-    st = fetch_results(ctx, &oms);
+    st = wait_results(ctx, &oms);
     if (st) return st;
     R.orbit_ms += oms;
     R.orbit_launches += 1;

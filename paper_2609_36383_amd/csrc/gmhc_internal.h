@@ -91,7 +91,8 @@ struct FftPlanAxis {
   int logN;
   int64_t stride;   // element stride of the axis
   int64_t nlines;   // Ng / N
-  int T;            // lines per workgroup
+  int T;            // lines per workgroup (a power of two)
+  int lds_tw;       // 1: twiddles staged in LDS after the lines, 0: read from tw
   const double2* tw;  // exp(-2 pi i m / N), m < N/2
 };
 
@@ -132,6 +133,8 @@ hipError_t launch_residual(const ResidualArgs& a, int blocks, hipStream_t s);
 hipError_t launch_reduce(const double* partials, int nblocks, int64_t bstride, int64_t vstride, int nvals,
                          uint32_t max_mask, double* out, hipStream_t s);
 
+// y[0..n) = 0 with a kernel (safe inside captured graphs, unlike a memset node).
+hipError_t launch_zero(double* y, int64_t n, hipStream_t s);
 hipError_t launch_axpy2(double* y, const double* x, double2* yc, const double2* xc, double beta,
                         int64_t nreal, int64_t ncplx, hipStream_t s);
 

@@ -52,19 +52,25 @@ __global__ __launch_bounds__(kBlock) void k_fft_axis(const double* src_r, const 
                                                      FftPlanAxis ax, int inverse, int project,
                                                      Mesh M) {
   extern __shared__ double2 lds[];
-  const int N = ax.N, T = ax.T;
+  const int N = ax.N, T = ax.T, logN = ax.logN;  // N and T are powers of two
+  const int logT = 31 - __clz(T);
   const int64_t comp = blockIdx.y;
   const int64_t line0 = (int64_t)blockIdx.x * T;
   const int64_t total = (int64_t)T * N;
-  const int shift = 32 - ax.logN;
+  const int shift = 32 - logN;
+  // twiddles exp(-2 pi i m / N), m < N/2, staged once after the T lines when they fit
+  double2* twl = lds + (int64_t)T * N;
+  if (ax.lds_tw)
+    for (int m = threadIdx.x; m < N / 2; m += blockDim.x) twl[m] = ax.tw[m];
+  const double2* tws = ax.lds_tw ? twl : ax.tw;
   for (int64_t e = threadIdx.x; e < total; e += blockDim.x) {
     int lt, k;
     if (ax.stride == 1) {
-      lt = (int)(e / N);
-      k = (int)(e % N);
+      lt = (int)(e >> logN);
+      k = (int)(e & (N - 1));
     } else {
-      lt = (int)(e % T);
-      k = (int)(e / T);
+      lt = (int)(e & (T - 1));
+      k = (int)(e >> logT);
     }
     const int64_t line = line0 + lt;
     double2 v = make_double2(0.0, 0.0);
@@ -80,14 +86,14 @@ __global__ __launch_bounds__(kBlock) void k_fft_axis(const double* src_r, const 
     lds[lt * N + rk] = v;
   }
   __syncthreads();
-  for (int st = 1; st <= ax.logN; ++st) {
+  for (int st = 1; st <= logN; ++st) {
     const int half = 1 << (st - 1);
     const int twstep = N >> st;
     for (int b = threadIdx.x; b < T * (N / 2); b += blockDim.x) {
-      const int lt = b / (N / 2), j = b % (N / 2);
+      const int lt = b >> (logN - 1), j = b & (N / 2 - 1);
       const int grp = j >> (st - 1), pos = j & (half - 1);
       const int i1 = lt * N + grp * (2 * half) + pos, i2 = i1 + half;
-      double2 w = ax.tw[pos * twstep];
+      double2 w = tws[pos * twstep];
       if (inverse) w.y = -w.y;
       const double2 u = lds[i1];
       const double2 t = cmul(lds[i2], w);
@@ -100,11 +106,11 @@ __global__ __launch_bounds__(kBlock) void k_fft_axis(const double* src_r, const 
   for (int64_t e = threadIdx.x; e < total; e += blockDim.x) {
     int lt, k;
     if (ax.stride == 1) {
-      lt = (int)(e / N);
-      k = (int)(e % N);
+      lt = (int)(e >> logN);
+      k = (int)(e & (N - 1));
     } else {
-      lt = (int)(e % T);
-      k = (int)(e / T);
+      lt = (int)(e & (T - 1));
+      k = (int)(e >> logT);
     }
     const int64_t line = line0 + lt;
     if (line >= ax.nlines) continue;
@@ -219,16 +225,38 @@ __global__ __launch_bounds__(kBlock) void k_residual(ResidualArgs a) {
 
 __global__ __launch_bounds__(kBlock) void k_reduce(const double* partials, int nblocks, int64_t bstride,
                                                    int64_t vstride, int nvals, uint32_t max_mask, double* out) {
-  // One workgroup per value.  Thread t folds blocks t, t + 256, ... in order, then a
-  // fixed pairwise tree combines the threads: the result depends only on nblocks.
+  // One workgroup per value.  Thread t folds blocks t, t + 256, ... into eight
+  // independent accumulators (so eight loads are in flight), combines them in a fixed
+  // order, then a fixed pairwise tree combines the threads: the result depends only
+  // on nblocks.
   const int v = blockIdx.x;
   if (v >= nvals) return;
   const bool mx = (max_mask >> v) & 1u;
-  double acc = mx ? -INFINITY : 0.0;
-  for (int b = threadIdx.x; b < nblocks; b += blockDim.x) {
-    const double x = partials[(int64_t)b * bstride + (int64_t)v * vstride];
-    acc = mx ? fmax(acc, x) : acc + x;
+  const double id = mx ? -INFINITY : 0.0;
+  const double* p = partials + (int64_t)v * vstride;
+  double a8[8];
+#pragma unroll
+  for (int k = 0; k < 8; ++k) a8[k] = id;
+  const int step = (int)blockDim.x;
+  int b = threadIdx.x;
+  for (; b + 7 * step < nblocks; b += 8 * step) {
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      const double x = p[(int64_t)(b + k * step) * bstride];
+      a8[k] = mx ? fmax(a8[k], x) : a8[k] + x;
+    }
   }
+#pragma unroll
+  for (int k = 0; k < 7; ++k) {
+    const int bb = b + k * step;
+    if (bb < nblocks) {
+      const double x = p[(int64_t)bb * bstride];
+      a8[k] = mx ? fmax(a8[k], x) : a8[k] + x;
+    }
+  }
+  double acc = a8[0];
+#pragma unroll
+  for (int k = 1; k < 8; ++k) acc = mx ? fmax(acc, a8[k]) : acc + a8[k];
   __shared__ double sh[kBlock];
   sh[threadIdx.x] = acc;
   __syncthreads();
@@ -240,6 +268,11 @@ __global__ __launch_bounds__(kBlock) void k_reduce(const double* partials, int n
     __syncthreads();
   }
   if (threadIdx.x == 0) out[v] = sh[0];
+}
+
+__global__ __launch_bounds__(kBlock) void k_zero(double* y, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) y[i] = 0.0;
 }
 
 __global__ void k_axpy2(double* y, const double* x, double2* yc, const double2* xc, double beta,
@@ -514,6 +547,10 @@ hipError_t fft_nd(const Mesh& M, const FftPlanAxis* axes, int ncomp, const doubl
     int64_t T = (ax.nlines * ncomp) / 512;
     T = std::max<int64_t>(1, std::min<int64_t>(T, std::max(1, 4096 / ax.N)));
     T = std::min<int64_t>(T, ax.nlines);
+    while (T & (T - 1)) T &= T - 1;  // a power of two (nlines is one)
+    // lines plus staged twiddles within 4096 complex values (64 KiB of LDS)
+    while (T > 1 && T * ax.N + ax.N / 2 > 4096) T >>= 1;
+    ax.lds_tw = (T * ax.N + ax.N / 2 <= 4096) ? 1 : 0;
     ax.T = (int)T;
     const int threads = (int)std::min<int64_t>(kBlock, std::max<int64_t>(64, (T * ax.N / 2 + 63) / 64 * 64));
     const bool first = (l == 0), last = (l == M.d - 1);
@@ -521,7 +558,7 @@ hipError_t fft_nd(const Mesh& M, const FftPlanAxis* axes, int ncomp, const doubl
     const bool out_real = last && dst_r != nullptr;
     const double2* in_c = first ? src_c : work;
     const unsigned gx = (unsigned)((ax.nlines + ax.T - 1) / ax.T);
-    const size_t lds = sizeof(double2) * (size_t)ax.T * ax.N;
+    const size_t lds = sizeof(double2) * ((size_t)ax.T * ax.N + (ax.lds_tw ? (size_t)std::max(ax.N / 2, 1) : 0));
     const int proj = (last && project && !inverse) ? 1 : 0;
     dim3 grid(gx, (unsigned)ncomp);
     if (in_real && out_real)
@@ -556,6 +593,12 @@ hipError_t launch_reduce(const double* partials, int nblocks, int64_t bstride, i
                          uint32_t max_mask, double* out, hipStream_t s) {
   hipLaunchKernelGGL(k_reduce, dim3((unsigned)nvals), dim3(kBlock), 0, s, partials, nblocks, bstride, vstride, nvals,
                      max_mask, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_zero(double* y, int64_t n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_zero, dim3(nblk(n)), dim3(kBlock), 0, s, y, n);
   return hipGetLastError();
 }
 

@@ -38,14 +38,14 @@ class Config(C.Structure):
         ("tol_outer_abs", C.c_double), ("tol_outer_rel", C.c_double),
         ("tol_inner_abs", C.c_double), ("tol_inner_rel", C.c_double),
         ("max_outer", C.c_int32), ("max_inner", C.c_int32), ("beta", C.c_double),
-        ("timing", C.c_int32), ("reserved", C.c_int32 * 7),
+        ("timing", C.c_int32), ("graphs", C.c_int32), ("reserved", C.c_int32 * 6),
     ]
 
 
 class StepReport(C.Structure):
     _fields_ = [("outer_iters", C.c_int32), ("inner_max", C.c_int32), ("inner_mean", C.c_double),
                 ("evaluations", C.c_int64), ("res_rms_ratio", C.c_double), ("res_max_ratio", C.c_double),
-                ("orbit_ms", C.c_double), ("orbit_launches", C.c_int32), ("pad", C.c_int32),
+                ("orbit_ms", C.c_double), ("orbit_launches", C.c_int32), ("graph_replays", C.c_int32),
                 ("segments", C.c_int64)]
 
 
@@ -120,7 +120,7 @@ class GmhcError(RuntimeError):
 def make_config(dim, n, lo, length, dt, kappa=1.0, sigma1=1.0, sigma2=1.0, gl_order=0,
                 project_nyquist=1, precision=FP64, sort_every=0, tol_outer_abs=1e-14,
                 tol_outer_rel=1e-12, tol_inner_abs=1e-14, tol_inner_rel=1e-12, max_outer=80,
-                max_inner=64, beta=1.0, timing=0):
+                max_inner=64, beta=1.0, timing=0, graphs=0):
     c = Config()
     c.dim = dim
     for i in range(3):
@@ -131,7 +131,7 @@ def make_config(dim, n, lo, length, dt, kappa=1.0, sigma1=1.0, sigma2=1.0, gl_or
     c.gl_order, c.project_nyquist, c.precision, c.sort_every = gl_order, project_nyquist, precision, sort_every
     c.tol_outer_abs, c.tol_outer_rel = tol_outer_abs, tol_outer_rel
     c.tol_inner_abs, c.tol_inner_rel = tol_inner_abs, tol_inner_rel
-    c.max_outer, c.max_inner, c.beta, c.timing = max_outer, max_inner, beta, timing
+    c.max_outer, c.max_inner, c.beta, c.timing, c.graphs = max_outer, max_inner, beta, timing, graphs
     return c
 
 
@@ -163,9 +163,12 @@ class Simulation:
         nbytes = C.c_size_t()
         self._chk(self.lib.gmhc_workspace_bytes(self.h, self.np, C.byref(nbytes)), "gmhc_workspace_bytes")
         self.device = torch.device(device)
-        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        # the library's own stream (default priority): a non-null stream, so that the
+        # outer iterations can be replayed as HIP graphs
+        self.stream = stream if stream is not None else torch.cuda.Stream(device=self.device)
         # 256-byte aligned device workspace owned by torch
         self.ws = torch.empty(nbytes.value + 256, dtype=torch.uint8, device=self.device)
+        self.stream.wait_stream(torch.cuda.current_stream(self.device))
         base = self.ws.data_ptr()
         self.ws_ptr = (base + 255) & ~255
         self.ws_bytes = nbytes.value
