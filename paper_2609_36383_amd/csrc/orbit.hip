@@ -890,14 +890,28 @@ __attribute__((amdgpu_waves_per_eu(GMHC_ORBIT_WAVES_PER_EU))) void k_orbit(Orbit
   t.nodes = uni(nodes);
   t.ok = uni(ok);
   t.joff = uni((int)(fbytes / 8));
+  // the particle's own inputs are read now, so their latency overlaps the staging
+  const bool live = i < a.np;
+  R qv = R(0), vin0[3] = {R(0), R(0), R(0)}, P0[3] = {R(0), R(0), R(0)};
+  if (live) {
+    qv = qp[i];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      vin0[c] = vp[c * ps + i];
+      P0[c] = Pp[c * ps + i];
+    }
+  }
   if (t.ok) {
+    // one tile node per lane at a time: its mesh index is computed once for all fields
     R* s_tile = reinterpret_cast<R*>(s_dyn);
     double* s_J = s_dyn + t.joff;
-    for (int k = threadIdx.x; k < NF * t.nodes; k += blockDim.x) {
-      const int f = k / t.nodes, nd = k - f * t.nodes;
-      s_tile[k] = (R)gfield<D>(a, f)[tile_to_global<D>(M, t, nd)];
+    for (int nd = threadIdx.x; nd < t.nodes; nd += blockDim.x) {
+      const int64_t g = tile_to_global<D>(M, t, nd);
+#pragma unroll
+      for (int f = 0; f < NF; ++f) s_tile[f * t.nodes + nd] = (R)gfield<D>(a, f)[g];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) s_J[c * t.nodes + nd] = 0.0;
     }
-    for (int k = threadIdx.x; k < 3 * t.nodes; k += blockDim.x) s_J[k] = 0.0;
   }
   __syncthreads();
 
@@ -919,24 +933,24 @@ __attribute__((amdgpu_waves_per_eu(GMHC_ORBIT_WAVES_PER_EU))) void k_orbit(Orbit
   R q = R(0);
   double vout[3] = {0.0, 0.0, 0.0}, Dv[3] = {0.0, 0.0, 0.0}, dA[3] = {0.0, 0.0, 0.0}, gpb[3] = {0.0, 0.0, 0.0};
   double kin = 0.0;
-  if (i < a.np) {
+  if (live) {
     PConst<R> pc;
-    pc.q = qp[i];
+    pc.q = qv;
     pc.m = fabs(pc.q);
     pc.mk = pc.m * R(a.kappa);
     pc.inv_mk = rcp_(pc.mk);
     pc.tc = pc.q * R(a.dt) * rcp_(R(2) * pc.m);
     pc.half_qdt = R(0.5) * pc.q * R(a.dt);
     q = pc.q;
-    vin[0] = vp[i];
-    vin[1] = vp[ps + i];
-    vin[2] = vp[2 * ps + i];
+    vin[0] = vin0[0];
+    vin[1] = vin0[1];
+    vin[2] = vin0[2];
     R Am[3] = {R(0), R(0), R(0)};
     if (valid) interp3<D, R>(a, t, D, j0, f0, Am);
     int it = 0, segs = 0;
     const int maxit = a.iterate ? a.max_inner : 1;
     const R kap2 = R(a.kappa) * R(a.kappa);
-    const R P[3] = {Pp[i], Pp[ps + i], Pp[2 * ps + i]};
+    const R P[3] = {P0[0], P0[1], P0[2]};
     for (it = 1; it <= maxit; ++it) {
       // the orbit must stay finite and within the supported knot-crossing range
       const R vn2 = vin[0] * vin[0] + vin[1] * vin[1] + vin[2] * vin[2];
@@ -1029,11 +1043,13 @@ __attribute__((amdgpu_waves_per_eu(GMHC_ORBIT_WAVES_PER_EU))) void k_orbit(Orbit
   // flush the current tile: one atomic per nonzero tile node and component
   if (t.ok && a.deposit) {
     const double* s_J = s_dyn + t.joff;
-    for (int k = threadIdx.x; k < 3 * t.nodes; k += blockDim.x) {
-      const double v = s_J[k];
-      if (v == 0.0) continue;
-      const int c = k / t.nodes, nd = k - c * t.nodes;
-      atomicAdd(a.J + (int64_t)c * M.Ng + tile_to_global<D>(M, t, nd), v);
+    for (int nd = threadIdx.x; nd < t.nodes; nd += blockDim.x) {
+      const double v[3] = {s_J[nd], s_J[t.nodes + nd], s_J[2 * t.nodes + nd]};
+      if (v[0] == 0.0 && v[1] == 0.0 && v[2] == 0.0) continue;
+      const int64_t g = tile_to_global<D>(M, t, nd);
+#pragma unroll
+      for (int c = 0; c < 3; ++c)
+        if (v[c] != 0.0) atomicAdd(a.J + (int64_t)c * M.Ng + g, v[c]);
     }
   }
   // block reduction in a fixed order: butterfly within each wave, then waves in order
