@@ -15,13 +15,13 @@
 // After the inner test passes, a second sweep over the same orbit deposits
 // J_g += q v_out S-bar_g / dV and gathers U-bar for the diagnostics.
 //
-// Memory layout on chip.  Particles arrive sorted by cell, so a workgroup's
-// particles sit in a small box of cells.  Each workgroup stages the mesh fields of
-// that box plus a halo of two nodes (stencil reach one node, orbit travel below one
-// cell) in LDS, and accumulates its current deposit in an FP64 LDS tile of the same
-// box, flushed to HBM with one atomic per tile node and component.  Orbits whose
-// stencil leaves the tile, and workgroups whose box does not fit, read and deposit
-// through global memory instead.
+// Memory layout on chip.  Particles arrive sorted by cell and a workgroup is one
+// wave, so its particles sit in a small box of cells.  Each workgroup stages in LDS the
+// mesh fields of the box spanned by its particles' nodes and their warm-start orbit
+// endpoints, plus the stencil reach of one node, and accumulates its current deposit
+// in an FP64 LDS tile of the same box, flushed to HBM with one atomic per tile node and
+// component.  Orbit segments whose stencil leaves the tile, and workgroups whose box
+// does not fit, read and deposit through global memory instead.
 //
 // Arithmetic.  The bulk type R (double, or float in the FP32-bulk mode) carries the
 // particle state, the staged fields, the quadrature and the push; positions stay
@@ -36,7 +36,7 @@
 namespace gmhc {
 namespace {
 
-constexpr int kHalo = 2;               // tile halo in nodes
+constexpr int kHalo = 1;               // tile halo in nodes (the stencil reach)
 // LDS per workgroup for the field and current tiles.  A one-wave workgroup of sorted
 // particles spans one or two cells; the budgets let eight workgroups share a CU's
 // 160 KB in every dimension (3D: a 6 x 5 x 5 box of 12 FP64 values per node).
@@ -843,6 +843,17 @@ __attribute__((amdgpu_waves_per_eu(GMHC_ORBIT_WAVES_PER_EU))) void k_orbit(Orbit
       f0[l] = valid ? (R)(xi - jr) : R(0);
     }
   }
+  // the particle's own inputs are read up front, so their latency overlaps the setup
+  const bool live = i < a.np;
+  R qv = R(0), vin0[3] = {R(0), R(0), R(0)}, P0[3] = {R(0), R(0), R(0)};
+  if (live) {
+    qv = qp[i];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      vin0[c] = vp[c * ps + i];
+      P0[c] = Pp[c * ps + i];
+    }
+  }
   // ---- the workgroup's tile box, taken periodically: on an axis whose nodes spread
   // over more than half the mesh, the low side moves up by one period, so particles
   // on either side of the periodic seam become neighbours
@@ -873,6 +884,21 @@ __attribute__((amdgpu_waves_per_eu(GMHC_ORBIT_WAVES_PER_EU))) void k_orbit(Orbit
     }
     block_minmax<D>(lo, hi, s_mm);
   }
+  // The box covers every particle's node and the node of its orbit endpoint under the
+  // warm-start velocity, plus the stencil reach.  Later inner iterates move the orbit
+  // little; a segment whose stencil still leaves the box takes the global path.
+  const bool any_valid = uni(lo[0] <= hi[0] ? 1 : 0) != 0;
+  if (any_valid) {
+#pragma unroll
+    for (int l = 0; l < D; ++l) {
+      int je = j0[l];
+      const double del = a.dt * (double)vin0[l] * M.inv_h[l];
+      if (valid && fabs(del) < (double)kMaxCross) je = j0[l] + (int)floor((double)f0[l] + del + 0.5);
+      lo[l] = valid ? min(j0[l], je) : INT_MAX;
+      hi[l] = valid ? max(j0[l], je) : INT_MIN;
+    }
+    block_minmax<D>(lo, hi, s_mm);
+  }
 #pragma unroll
   for (int l = 0; l < D; ++l) {
     if (lo[l] > hi[l]) {  // no valid particle in this workgroup
@@ -890,17 +916,6 @@ __attribute__((amdgpu_waves_per_eu(GMHC_ORBIT_WAVES_PER_EU))) void k_orbit(Orbit
   t.nodes = uni(nodes);
   t.ok = uni(ok);
   t.joff = uni((int)(fbytes / 8));
-  // the particle's own inputs are read now, so their latency overlaps the staging
-  const bool live = i < a.np;
-  R qv = R(0), vin0[3] = {R(0), R(0), R(0)}, P0[3] = {R(0), R(0), R(0)};
-  if (live) {
-    qv = qp[i];
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      vin0[c] = vp[c * ps + i];
-      P0[c] = Pp[c * ps + i];
-    }
-  }
   if (t.ok) {
     // one tile node per lane at a time: its mesh index is computed once for all fields
     R* s_tile = reinterpret_cast<R*>(s_dyn);
