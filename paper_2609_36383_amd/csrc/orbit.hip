@@ -809,13 +809,15 @@ __device__ __forceinline__ int tile_to_global(const Mesh& M, const Tile& t, int 
   return wrapi(ux, M.n[0]) + M.n[0] * ((D > 1 ? wrapi(uy, M.n[1]) : 0) + M.n[1] * (D > 2 ? wrapi(uz, M.n[2]) : 0));
 }
 
-#ifndef GMHC_ORBIT_WAVES_PER_EU
-#define GMHC_ORBIT_WAVES_PER_EU 2
-#endif
+// Occupancy target (waves per SIMD) the register allocator works to, chosen per
+// instantiation by measurement: the FP32 kernels of 1D and 2D fit three waves with
+// little spilling and gain from it; the others run best at two.
+template <int D, class R>
+constexpr int orbit_waves() { return (sizeof(R) == 4 && D <= 2) ? 3 : 2; }
 
 template <int D, int NGL, class R>
 __global__ __launch_bounds__(kOrbitBlock)
-__attribute__((amdgpu_waves_per_eu(GMHC_ORBIT_WAVES_PER_EU))) void k_orbit(OrbitArgs a) {
+__attribute__((amdgpu_waves_per_eu(orbit_waves<D, R>()))) void k_orbit(OrbitArgs a) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const Mesh& M = a.M;
   const int64_t ps = a.ps;
