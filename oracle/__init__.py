@@ -25,7 +25,9 @@ class Config(C.Structure):
         ("tol_outer_abs", C.c_double), ("tol_outer_rel", C.c_double),
         ("tol_inner_abs", C.c_double), ("tol_inner_rel", C.c_double),
         ("max_outer", C.c_int32), ("max_inner", C.c_int32), ("beta", C.c_double),
-        ("threads", C.c_int32),
+        ("threads", C.c_int32), ("outer_scheme", C.c_int32), ("anderson_m", C.c_int32),
+        ("anderson_start", C.c_int32), ("ls_halvings", C.c_int32), ("anderson_lambda", C.c_double),
+        ("ls_decrease", C.c_double), ("ls_growth", C.c_double),
     ]
 
 
@@ -122,7 +124,8 @@ def _f64(a):
 
 def make_config(dim, n, lo, length, dt, kappa=1.0, sigma1=1.0, sigma2=1.0, gl_order=8, project=1,
                 tol_outer_abs=1e-14, tol_outer_rel=1e-12, tol_inner_abs=1e-14, tol_inner_rel=1e-12,
-                max_outer=80, max_inner=64, beta=1.0, threads=0):
+                max_outer=80, max_inner=64, beta=1.0, threads=0, outer_scheme=0, anderson_m=4,
+                anderson_start=2, ls_halvings=6, anderson_lambda=1e-12, ls_decrease=1e-4, ls_growth=1.2):
     c = Config()
     c.dim = dim
     for i in range(3):
@@ -134,6 +137,8 @@ def make_config(dim, n, lo, length, dt, kappa=1.0, sigma1=1.0, sigma2=1.0, gl_or
     c.tol_outer_abs, c.tol_outer_rel = tol_outer_abs, tol_outer_rel
     c.tol_inner_abs, c.tol_inner_rel = tol_inner_abs, tol_inner_rel
     c.max_outer, c.max_inner, c.beta, c.threads = max_outer, max_inner, beta, threads
+    c.outer_scheme, c.anderson_m, c.anderson_start, c.ls_halvings = outer_scheme, anderson_m, anderson_start, ls_halvings
+    c.anderson_lambda, c.ls_decrease, c.ls_growth = anderson_lambda, ls_decrease, ls_growth
     return c
 
 

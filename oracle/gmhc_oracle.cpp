@@ -16,6 +16,7 @@
 //   mesh node g = i0 + n0*(i1 + n1*i2), node i at lo + i*h (periodic);
 //   real mesh arrays are [component][Ng]; particle arrays are [component][Np].
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <complex>
 #include <cstdint>
@@ -58,8 +59,15 @@ struct orc_config {
   double tol_outer_abs, tol_outer_rel;
   double tol_inner_abs, tol_inner_rel;
   int32_t max_outer, max_inner;
-  double beta;          // Picard damping of the outer current iteration
+  double beta;          // damping of the outer current iteration (Picard step beta r)
   int32_t threads;      // OpenMP threads (0: runtime default)
+  int32_t outer_scheme; // 0: damped Picard; 1: type-II Anderson (the paper's solver)
+  int32_t anderson_m;   // Anderson memory M (paper: 4)
+  int32_t anderson_start; // outer iteration from which Anderson is eligible (paper: 2)
+  int32_t ls_halvings;  // backtracking alpha = 1, 1/2, ..., 2^-ls_halvings (paper: 6)
+  double anderson_lambda; // regularization lambda (paper: 1e-12)
+  double ls_decrease;   // sufficient-decrease coefficient (paper: 1e-4)
+  double ls_growth;     // residual-growth limit (paper: 1.2)
 };
 
 // One orbit evaluation v_out = F(v_in) of one particle at frozen trial fields.
@@ -1118,142 +1126,310 @@ int orc_set_fields(void* h, const double* phi, const double* psi, const double* 
 
 // One implicit step (Algorithm 1 with a damped-Picard outer iteration on the mesh
 // current).  On failure the accepted state is left unchanged.
+// One evaluation of the outer map at the trial current j (Algorithm 1, one residual
+// evaluation): field step, inner Picard solve of every particle warm-started from vw,
+// orbit current deposit and projection H(j), and the mixed outer tests.  On return vw
+// holds each particle's last v_out.  Returns ORC_EINNER if any inner solve failed.
+struct OuterEval {
+  Trial T;
+  RVec H[3];
+  RVec vin_f[3], Pn1[3], Ra2, work;
+  double rr = 0.0, mr = 0.0;
+};
+
+int evaluate_outer(Sim& S, const RVec An[3], const RVec j[3], RVec vw[3], OuterEval& E, orc_report& R) {
+  const Mesh& M = S.M;
+  const int64_t np = S.np;
+  const int ngl = (int)S.glx.size();
+  field_solve(S, j, E.T);
+  FieldPtrs F = make_ptrs(S, E.T.gphi, An, E.T.Anp1, E.T.Uh);
+  for (int c = 0; c < 3; ++c) {
+    E.vin_f[c].assign(np, 0.0);
+    E.Pn1[c].assign(np, 0.0);
+  }
+  E.Ra2.assign(np, 0.0);
+  E.work.assign(np, 0.0);
+  std::vector<int32_t> iters(np), fail(np);
+#pragma omp parallel for schedule(dynamic, 256)
+  for (int64_t i = 0; i < np; ++i) {
+    double xi[3] = {S.x[0][i], S.x[1][i], S.x[2][i]};
+    double Pi[3] = {S.P[0][i], S.P[1][i], S.P[2][i]};
+    double vin[3] = {vw[0][i], vw[1][i], vw[2][i]};
+    orc_eval_out o{};
+    int it = 0;
+    bool ok = false;
+    for (it = 1; it <= S.cfg.max_inner; ++it) {
+      orbit_eval(M, S.ph, F, ngl, S.glx.data(), S.glw.data(), xi, Pi, S.q[i], S.m[i], vin, &o);
+      double vn = std::sqrt(o.vout[0] * o.vout[0] + o.vout[1] * o.vout[1] + o.vout[2] * o.vout[2]);
+      if (!std::isfinite(vn) || !(vn < S.cfg.kappa)) break;  // finite and subluminal
+      double dmax = 0.0, vmax = 0.0;
+      for (int c = 0; c < 3; ++c) {
+        dmax = std::max(dmax, std::fabs(o.vout[c] - vin[c]));
+        vmax = std::max(vmax, std::fabs(o.vout[c]));
+      }
+      if (dmax <= S.cfg.tol_inner_abs + S.cfg.tol_inner_rel * vmax) {
+        ok = true;
+        break;
+      }
+      for (int c = 0; c < 3; ++c) vin[c] = o.vout[c];
+    }
+    iters[i] = std::min(it, S.cfg.max_inner);
+    fail[i] = ok ? 0 : 1;
+    for (int c = 0; c < 3; ++c) {
+      E.vin_f[c][i] = vin[c];
+      vw[c][i] = o.vout[c];
+      E.Pn1[c][i] = o.Pnp1[c];
+    }
+    // accept-pass diagnostics of this evaluation
+    double Ra = 0.0, wk = 0.0;
+    for (int c = 0; c < 3; ++c) {
+      double Dv = 0.0;
+      for (int jj = 0; jj < M.d; ++jj) Dv += o.D[c * 3 + jj] * vin[jj];
+      double r = o.Aplus[c] - o.Aminus[c] - S.cfg.dt * (o.Ubar[c] + Dv);
+      Ra += r * r;
+      wk += S.q[i] * o.vout[c] * (-o.gradphibar[c] - o.Ubar[c]);
+    }
+    E.Ra2[i] = Ra;
+    E.work[i] = wk;
+  }
+  int64_t nfail = 0, evals = 0;
+  int imax = 0;
+  double isum = 0.0;
+  for (int64_t i = 0; i < np; ++i) {
+    nfail += fail[i];
+    evals += iters[i];
+    imax = std::max(imax, iters[i]);
+    isum += iters[i];
+  }
+  R.outer_iters += 1;
+  R.evaluations += evals;
+  R.inner_max = imax;
+  R.inner_mean = np ? isum / np : 0.0;
+  if (nfail) return ORC_EINNER;
+  RVec Jorb[3];
+  deposit(S, E.vin_f, vw, Jorb);
+  for (int c = 0; c < 3; ++c) {
+    CVec jh = to_spec(M, Jorb[c].data());
+    if (S.cfg.project) project(M, jh);
+    E.H[c] = to_real(M, jh);
+  }
+  outer_tests(S, E.H, j, E.rr, E.mr);
+  R.res_rms_ratio = E.rr;
+  R.res_max_ratio = E.mr;
+  return ORC_OK;
+}
+
+// Commit the state of the converged evaluation E at current j (Algorithm 1, commit).
+void commit_step(Sim& S, const RVec j[3], const RVec vw[3], const OuterEval& E) {
+  const Mesh& M = S.M;
+  const int64_t np = S.np;
+  const double dt = S.cfg.dt;
+  double sRa = 0.0, swk = 0.0;
+  for (int64_t i = 0; i < np; ++i) {
+    sRa += E.Ra2[i];
+    swk += E.work[i];
+  }
+  double mesh_work = 0.0;
+  for (int c = 0; c < 3; ++c)
+    for (int64_t g = 0; g < M.Ng; ++g) {
+      double gp = (c < M.d) ? E.T.gphi[c][g] : 0.0;
+      mesh_work += E.H[c][g] * (-gp - E.T.Uh[c][g]) * M.dV;
+    }
+  S.last_chain_rms = np ? std::sqrt(sRa / (3.0 * np)) : 0.0;
+  S.last_work = dt * (swk - mesh_work);
+  S.last_rms_ratio = E.rr;
+  S.last_max_ratio = E.mr;
+  S.phi = E.T.phi;
+  S.psi = E.T.psi;
+  S.rho = E.T.rho;
+  for (int c = 0; c < 3; ++c) {
+    S.A[c] = E.T.A[c];
+    S.U[c] = E.T.U[c];
+    S.Jacc[c] = j[c];
+    S.vbar[c] = vw[c];
+    S.P[c] = E.Pn1[c];
+  }
+  for (int l = 0; l < M.d; ++l)
+    for (int64_t i = 0; i < np; ++i) S.x[l][i] = wrap1(S.x[l][i] + dt * E.vin_f[l][i], M.lo[l], M.len[l]);
+  S.t += dt;
+  S.step += 1;
+}
+
+// Solve the small dense system A x = b (n <= 8) by Gaussian elimination with partial
+// pivoting; false if singular or not finite.
+bool small_solve(std::vector<double> A, std::vector<double> b, int n, std::vector<double>& x) {
+  for (int c = 0; c < n; ++c) {
+    int p = c;
+    for (int r = c + 1; r < n; ++r)
+      if (std::fabs(A[r * n + c]) > std::fabs(A[p * n + c])) p = r;
+    if (!(std::fabs(A[p * n + c]) > 0.0) || !std::isfinite(A[p * n + c])) return false;
+    if (p != c) {
+      for (int k = 0; k < n; ++k) std::swap(A[c * n + k], A[p * n + k]);
+      std::swap(b[c], b[p]);
+    }
+    for (int r = c + 1; r < n; ++r) {
+      const double f = A[r * n + c] / A[c * n + c];
+      for (int k = c; k < n; ++k) A[r * n + k] -= f * A[c * n + k];
+      b[r] -= f * b[c];
+    }
+  }
+  x.assign(n, 0.0);
+  for (int c = n - 1; c >= 0; --c) {
+    double v = b[c];
+    for (int k = c + 1; k < n; ++k) v -= A[c * n + k] * x[k];
+    x[c] = v / A[c * n + c];
+    if (!std::isfinite(x[c])) return false;
+  }
+  return true;
+}
+
+double dot3(const RVec a[3], const RVec b[3]) {
+  double s = 0.0;
+  for (int c = 0; c < 3; ++c)
+    for (size_t g = 0; g < a[c].size(); ++g) s += a[c][g] * b[c][g];
+  return s;
+}
+
+// Advance one implicit step (Algorithm 1).  The outer unknown is the mesh current j,
+// started from the accepted current.  Outer scheme 0: damped Picard j <- j + beta r.
+// Outer scheme 1 (the paper's solver, section on the implicit solver): limited-memory
+// type-II Anderson with regularization, history reset and backtracking, with a damped
+// Picard direction when the history is unusable or its direction is rejected.  Every
+// evaluation of the outer map counts against max_outer.
 int orc_step(void* h, orc_report* rep) {
   Sim& S = *static_cast<Sim*>(h);
   if (!S.initialized) return ORC_ESTATE;
   set_threads(S);
   const Mesh& M = S.M;
-  const int64_t np = S.np;
-  const double dt = S.cfg.dt;
-  const int ngl = (int)S.glx.size();
+  const int64_t Ng = M.Ng;
   RVec An[3];
   for (int c = 0; c < 3; ++c) An[c] = to_real(M, S.A[c]);
-  RVec j[3];
-  for (int c = 0; c < 3; ++c) j[c] = S.Jacc[c];
-  // per-particle work buffers (committed only on success)
-  RVec vw[3], vin_f[3], Pn1[3], Ra2(np), work(np);
+  RVec j[3], vw[3];
   for (int c = 0; c < 3; ++c) {
-    vw[c] = S.vbar[c];
-    vin_f[c].assign(np, 0.0);
-    Pn1[c].assign(np, 0.0);
+    j[c] = S.Jacc[c];
+    vw[c] = S.vbar[c];  // inner warm start, carried from evaluation to evaluation
   }
-  std::vector<int32_t> iters(np), fail(np);
   orc_report R{};
-  for (int k = 1; k <= S.cfg.max_outer; ++k) {
-    Trial T;
-    field_solve(S, j, T);
-    FieldPtrs F = make_ptrs(S, T.gphi, An, T.Anp1, T.Uh);
-#pragma omp parallel for schedule(dynamic, 256)
-    for (int64_t i = 0; i < np; ++i) {
-      double xi[3] = {S.x[0][i], S.x[1][i], S.x[2][i]};
-      double Pi[3] = {S.P[0][i], S.P[1][i], S.P[2][i]};
-      double vin[3] = {vw[0][i], vw[1][i], vw[2][i]};
-      orc_eval_out o{};
-      int it = 0;
-      bool ok = false;
-      for (it = 1; it <= S.cfg.max_inner; ++it) {
-        orbit_eval(M, S.ph, F, ngl, S.glx.data(), S.glw.data(), xi, Pi, S.q[i], S.m[i], vin, &o);
-        double vn = std::sqrt(o.vout[0] * o.vout[0] + o.vout[1] * o.vout[1] + o.vout[2] * o.vout[2]);
-        if (!std::isfinite(vn) || !(vn < S.cfg.kappa)) break;  // finite and subluminal
-        double dmax = 0.0, vmax = 0.0;
-        for (int c = 0; c < 3; ++c) {
-          dmax = std::max(dmax, std::fabs(o.vout[c] - vin[c]));
-          vmax = std::max(vmax, std::fabs(o.vout[c]));
+  auto finish = [&](int st) {
+    if (rep) *rep = R;
+    return st;
+  };
+  OuterEval E;
+  int st = evaluate_outer(S, An, j, vw, E, R);
+  if (st) return finish(st);
+  if (E.rr <= 1.0 && E.mr <= 1.0) {
+    commit_step(S, j, vw, E);
+    return finish(ORC_OK);
+  }
+  const bool anderson = S.cfg.outer_scheme == 1;
+  const int mem = std::max(1, std::min(S.cfg.anderson_m, 8));
+  std::vector<std::array<RVec, 3>> dJ, dR;  // history columns, oldest first
+  RVec r[3];
+  for (int c = 0; c < 3; ++c) {
+    r[c].resize(Ng);
+    for (int64_t g = 0; g < Ng; ++g) r[c][g] = E.H[c][g] - j[c][g];
+  }
+  while (R.outer_iters < S.cfg.max_outer) {
+    const int k = R.outer_iters;  // outer iterations done so far
+    bool accepted = false;
+    for (int pass = 0; pass < 2 && !accepted; ++pass) {
+      // pass 0: Anderson direction (when eligible and the history is usable); pass 1: damped Picard
+      const bool use_a = anderson && pass == 0 && k >= S.cfg.anderson_start && !dJ.empty();
+      if (pass == 0 && !use_a) continue;
+      RVec d[3];
+      for (int c = 0; c < 3; ++c) {
+        d[c].resize(Ng);
+        for (int64_t g = 0; g < Ng; ++g) d[c][g] = S.cfg.beta * r[c][g];
+      }
+      if (use_a) {
+        const int mh = (int)dR.size();
+        std::vector<double> G(mh * mh), b(mh), gam;
+        double tr = 0.0;
+        for (int a1 = 0; a1 < mh; ++a1) {
+          b[a1] = dot3(dR[a1].data(), r);
+          for (int a2 = 0; a2 < mh; ++a2) G[a1 * mh + a2] = dot3(dR[a1].data(), dR[a2].data());
+          tr += G[a1 * mh + a1];
         }
-        if (dmax <= S.cfg.tol_inner_abs + S.cfg.tol_inner_rel * vmax) {
-          ok = true;
+        for (int a1 = 0; a1 < mh; ++a1) G[a1 * mh + a1] += S.cfg.anderson_lambda * tr / mh;
+        if (!small_solve(G, b, mh, gam)) {
+          dJ.clear();
+          dR.clear();
+          continue;  // unusable history: damped Picard
+        }
+        for (int a1 = 0; a1 < mh; ++a1)
+          for (int c = 0; c < 3; ++c)
+            for (int64_t g = 0; g < Ng; ++g)
+              d[c][g] -= gam[a1] * (dJ[a1][c][g] + S.cfg.beta * dR[a1][c][g]);
+      }
+      // backtracking along d: alpha = 1, 1/2, ..., 2^-ls_halvings
+      double alpha = 1.0;
+      for (int hh = 0; hh <= S.cfg.ls_halvings && R.outer_iters < S.cfg.max_outer; ++hh, alpha *= 0.5) {
+        RVec jt[3], vt[3];
+        for (int c = 0; c < 3; ++c) {
+          jt[c].resize(Ng);
+          for (int64_t g = 0; g < Ng; ++g) jt[c][g] = j[c][g] + alpha * d[c][g];
+          vt[c] = vw[c];
+        }
+        OuterEval Et;
+        st = evaluate_outer(S, An, jt, vt, Et, R);
+        if (st) return finish(st);
+        for (int c = 0; c < 3; ++c) vw[c] = vt[c];
+        if (Et.rr <= 1.0 && Et.mr <= 1.0) {
+          commit_step(S, jt, vw, Et);
+          return finish(ORC_OK);
+        }
+        if (use_a && Et.rr > S.cfg.ls_growth * E.rr) {
+          dJ.clear();  // the residual grew too much along the Anderson direction
+          dR.clear();
+        }
+        if (Et.rr <= (1.0 - S.cfg.ls_decrease * alpha) * E.rr && Et.mr <= S.cfg.ls_growth * E.mr) {
+          // accept: record the differences, move to the trial
+          std::array<RVec, 3> cj, cr;
+          for (int c = 0; c < 3; ++c) {
+            cj[c].resize(Ng);
+            cr[c].resize(Ng);
+            for (int64_t g = 0; g < Ng; ++g) {
+              const double rt = Et.H[c][g] - jt[c][g];
+              cj[c][g] = jt[c][g] - j[c][g];
+              cr[c][g] = rt - r[c][g];
+              r[c][g] = rt;
+              j[c][g] = jt[c][g];
+            }
+          }
+          if (anderson) {
+            dJ.push_back(cj);
+            dR.push_back(cr);
+            if ((int)dJ.size() > mem) {
+              dJ.erase(dJ.begin());
+              dR.erase(dR.begin());
+            }
+          }
+          E = std::move(Et);
+          accepted = true;
           break;
         }
-        for (int c = 0; c < 3; ++c) vin[c] = o.vout[c];
-      }
-      iters[i] = std::min(it, S.cfg.max_inner);
-      fail[i] = ok ? 0 : 1;
-      for (int c = 0; c < 3; ++c) {
-        vin_f[c][i] = vin[c];
-        vw[c][i] = o.vout[c];
-        Pn1[c][i] = o.Pnp1[c];
-      }
-      // accept-pass diagnostics of this evaluation
-      double Ra = 0.0, wk = 0.0;
-      for (int c = 0; c < 3; ++c) {
-        double Dv = 0.0;
-        for (int jj = 0; jj < M.d; ++jj) Dv += o.D[c * 3 + jj] * vin[jj];
-        double r = o.Aplus[c] - o.Aminus[c] - dt * (o.Ubar[c] + Dv);
-        Ra += r * r;
-        wk += S.q[i] * o.vout[c] * (-o.gradphibar[c] - o.Ubar[c]);
-      }
-      Ra2[i] = Ra;
-      work[i] = wk;
-    }
-    int64_t nfail = 0, evals = 0;
-    int imax = 0;
-    double isum = 0.0;
-    for (int64_t i = 0; i < np; ++i) {
-      nfail += fail[i];
-      evals += iters[i];
-      imax = std::max(imax, iters[i]);
-      isum += iters[i];
-    }
-    R.outer_iters = k;
-    R.evaluations += evals;
-    R.inner_max = imax;
-    R.inner_mean = np ? isum / np : 0.0;
-    if (nfail) {
-      if (rep) *rep = R;
-      return ORC_EINNER;
-    }
-    RVec Jorb[3], H[3];
-    deposit(S, vin_f, vw, Jorb);
-    for (int c = 0; c < 3; ++c) {
-      CVec jh = to_spec(M, Jorb[c].data());
-      if (S.cfg.project) project(M, jh);
-      H[c] = to_real(M, jh);
-    }
-    double rr, mr;
-    outer_tests(S, H, j, rr, mr);
-    R.res_rms_ratio = rr;
-    R.res_max_ratio = mr;
-    if (rr <= 1.0 && mr <= 1.0) {
-      // diagnostics of the accepted evaluation
-      double sRa = 0.0, swk = 0.0;
-      for (int64_t i = 0; i < np; ++i) {
-        sRa += Ra2[i];
-        swk += work[i];
-      }
-      double mesh_work = 0.0;
-      for (int c = 0; c < 3; ++c)
-        for (int64_t g = 0; g < M.Ng; ++g) {
-          double gp = (c < M.d) ? T.gphi[c][g] : 0.0;
-          mesh_work += H[c][g] * (-gp - T.Uh[c][g]) * M.dV;
+        if (!anderson) {
+          // plain damped Picard takes every step (no line search)
+          std::array<RVec, 3> dummy;
+          (void)dummy;
+          for (int c = 0; c < 3; ++c)
+            for (int64_t g = 0; g < Ng; ++g) {
+              r[c][g] = Et.H[c][g] - jt[c][g];
+              j[c][g] = jt[c][g];
+            }
+          E = std::move(Et);
+          accepted = true;
+          break;
         }
-      S.last_chain_rms = np ? std::sqrt(sRa / (3.0 * np)) : 0.0;
-      S.last_work = dt * (swk - mesh_work);
-      S.last_rms_ratio = rr;
-      S.last_max_ratio = mr;
-      // commit
-      S.phi = T.phi;
-      S.psi = T.psi;
-      S.rho = T.rho;
-      for (int c = 0; c < 3; ++c) {
-        S.A[c] = T.A[c];
-        S.U[c] = T.U[c];
-        S.Jacc[c] = j[c];
-        S.vbar[c] = vw[c];
-        S.P[c] = Pn1[c];
       }
-      for (int l = 0; l < M.d; ++l)
-        for (int64_t i = 0; i < np; ++i)
-          S.x[l][i] = wrap1(S.x[l][i] + dt * vin_f[l][i], M.lo[l], M.len[l]);
-      S.t += dt;
-      S.step += 1;
-      if (rep) *rep = R;
-      return ORC_OK;
+      if (!accepted && use_a) {
+        dJ.clear();  // rejected Anderson direction: retry with damped Picard
+        dR.clear();
+      }
     }
-    for (int c = 0; c < 3; ++c)
-      for (int64_t g = 0; g < M.Ng; ++g) j[c][g] += S.cfg.beta * (H[c][g] - j[c][g]);
+    if (!accepted) return finish(ORC_ENOCONV);
   }
-  if (rep) *rep = R;
-  return ORC_ENOCONV;
+  return finish(ORC_ENOCONV);
 }
 
 int orc_diagnostics(void* h, orc_diag* d) {

@@ -60,6 +60,15 @@ struct gmhc_ctx {
   size_t scan_tmp_bytes = 0;
   double* partials = nullptr;
   int64_t max_blocks = 0;
+  // outer Anderson solver (outer_scheme 1): iterate, residual, direction [3 Ng] and
+  // the history columns (differences of iterates and of residuals)
+  double* jA = nullptr;
+  double* rA = nullptr;
+  double* dA = nullptr;
+  double* hJ[8] = {};
+  double* hR[8] = {};
+  double* ddot = nullptr;   // device dot products [kMaxDots]
+  double* hdot = nullptr;   // pinned host copy
   double* dres = nullptr;   // device results [32]
   double* hres = nullptr;   // pinned host results [32]
   double2* tw[3] = {};
@@ -194,6 +203,16 @@ size_t carve(gmhc_ctx* c, char* base, int64_t np) {
   c->max_blocks = std::max<int64_t>((np + kOrbitBlock - 1) / kOrbitBlock, 1024);
   c->partials = cv.take<double>((size_t)(c->max_blocks + 1024) * 8);
   c->dres = cv.take<double>(64);
+  c->ddot = cv.take<double>(kMaxDots);
+  if (c->cfg.outer_scheme == 1) {
+    c->jA = cv.take<double>(3 * Ng);
+    c->rA = cv.take<double>(3 * Ng);
+    c->dA = cv.take<double>(3 * Ng);
+    for (int m = 0; m < c->cfg.anderson_m; ++m) {
+      c->hJ[m] = cv.take<double>(3 * Ng);
+      c->hR[m] = cv.take<double>(3 * Ng);
+    }
+  }
   for (int l = 0; l < d; ++l) c->tw[l] = cv.take<double2>(std::max(c->M.n[l] / 2, 1));
   return (cv.off + 255) & ~(size_t)255;
 }
@@ -402,6 +421,11 @@ int32_t gmhc_create(const gmhc_config* cfg, gmhc_ctx** out) {
   if (c.gl_order < 0 || c.gl_order > kMaxGL) return GMHC_EINVAL;
   if (c.precision != GMHC_FP64 && c.precision != GMHC_FP32_BULK) return GMHC_EINVAL;
   if (c.max_outer < 1 || c.max_inner < 1 || !(c.beta > 0.0 && c.beta <= 1.0)) return GMHC_EINVAL;
+  if (c.outer_scheme != 0 && c.outer_scheme != 1) return GMHC_EINVAL;
+  if (c.outer_scheme == 1 &&
+      (c.anderson_m < 1 || c.anderson_m > 8 || c.anderson_start < 1 || c.ls_halvings < 0 || c.ls_halvings > 30 ||
+       !(c.anderson_lambda >= 0.0) || !(c.ls_decrease >= 0.0 && c.ls_decrease < 1.0) || !(c.ls_growth >= 1.0)))
+    return GMHC_EINVAL;
   if (c.tol_outer_abs < 0 || c.tol_outer_rel < 0 || c.tol_inner_abs < 0 || c.tol_inner_rel < 0)
     return GMHC_EINVAL;
   gmhc_ctx* ctx = new gmhc_ctx();
@@ -435,6 +459,7 @@ void gmhc_destroy(gmhc_ctx* ctx) {
     DevGuard g(ctx->device);
     (void)hipStreamSynchronize(ctx->stream);
     if (ctx->hres) (void)hipHostFree(ctx->hres);
+    if (ctx->hdot) (void)hipHostFree(ctx->hdot);
     for (auto& e : ctx->graphs) (void)hipGraphExecDestroy(e.exec);
     if (ctx->ev0) (void)hipEventDestroy(ctx->ev0);
     if (ctx->ev1) (void)hipEventDestroy(ctx->ev1);
@@ -470,6 +495,7 @@ int32_t gmhc_bind(gmhc_ctx* ctx, int64_t n_particles, void* dev_workspace, size_
   ctx->np = n_particles;
   carve(ctx, ctx->ws, n_particles);
   HIPCK(hipHostMalloc(reinterpret_cast<void**>(&ctx->hres), sizeof(double) * 64, hipHostMallocDefault));
+  HIPCK(hipHostMalloc(reinterpret_cast<void**>(&ctx->hdot), sizeof(double) * kMaxDots, hipHostMallocDefault));
   HIPCK(hipEventCreate(&ctx->ev0));
   HIPCK(hipEventCreate(&ctx->ev1));
   // FFT plans and twiddles exp(-2 pi i m / N)
@@ -763,81 +789,231 @@ int32_t run_outer(gmhc_ctx* ctx, int cur, int hs, bool& use_graph, int32_t& repl
   return enqueue_outer(ctx, cur, hs, OUTER_ALL);
 }
 
+// Evaluate the outer map at the trial current in slot cur (H(j) written to slot hs)
+// and read back the pass and residual results: rr and mr are the mixed RMS and
+// max-node test ratios.  GMHC_EINNER if an inner particle solve failed.
+int32_t eval_outer(gmhc_ctx* ctx, int cur, int hs, gmhc_step_report& R, bool& use_graph, double& rr, double& mr) {
+  const int64_t Ng = ctx->M.Ng, np = ctx->np;
+  int32_t st = run_outer(ctx, cur, hs, use_graph, R.graph_replays);
+  if (st) return st;
+  double oms = 0.0;
+  st = wait_results(ctx, &oms);
+  if (st) return st;
+  R.orbit_ms += oms;
+  R.orbit_launches += 1;
+  const double* h = ctx->hres;
+  R.outer_iters += 1;
+  R.evaluations += (int64_t)llround(h[OP_ITERS]);
+  R.segments += (int64_t)llround(h[OP_SEGS]);
+  R.inner_max = (int32_t)llround(h[OP_ITMAX]);
+  R.inner_mean = np ? h[OP_ITERS] / (double)np : 0.0;
+  if (h[OP_FAIL] > 0.0)
+    return fail(ctx, GMHC_EINNER,
+                "particle inner solve failed (" + std::to_string((long long)h[OP_FAIL]) + " particles)");
+  const double* r = ctx->hres + kResOff;
+  const double n3 = 3.0 * (double)Ng;
+  rr = sqrt(r[0] / n3) /
+       (ctx->cfg.tol_outer_abs + 0.5 * ctx->cfg.tol_outer_rel * (sqrt(r[1] / n3) + sqrt(r[2] / n3)));
+  mr = r[3];
+  R.res_rms_ratio = rr;
+  R.res_max_ratio = mr;
+  return GMHC_OK;
+}
+
+// Commit the state of the evaluation just made at the trial current in slot cur.
+int32_t commit_outer(gmhc_ctx* ctx, int cur, double rr, double mr) {
+  const Mesh& M = ctx->M;
+  const int64_t Ng = M.Ng, np = ctx->np;
+  const int d = M.d;
+  hipStream_t s = ctx->stream;
+  const double* h = ctx->hres;
+  const double* r = ctx->hres + kResOff;
+  std::swap(ctx->S0, ctx->S1);
+  HIPCK(hipMemcpyAsync(ctx->An, ctx->trial + (int64_t)d * Ng, sizeof(double) * 3 * Ng, hipMemcpyDeviceToDevice, s));
+  if (cur != 0) {
+    HIPCK(hipMemcpyAsync(ctx->jr[0], ctx->jr[cur], sizeof(double) * 3 * Ng, hipMemcpyDeviceToDevice, s));
+    HIPCK(hipMemcpyAsync(ctx->jh[0], ctx->jh[cur], sizeof(double2) * 3 * Ng, hipMemcpyDeviceToDevice, s));
+  }
+  for (int l = 0; l < d; ++l) std::swap(ctx->x[l], ctx->x2[l]);
+  for (int l = 0; l < 3; ++l) {
+    std::swap(ctx->P[l], ctx->P2[l]);
+    std::swap(ctx->vb[l], ctx->vw[l]);
+  }
+  HIPCK(hipStreamSynchronize(s));
+  ctx->last_chain = np ? sqrt(h[OP_RA2] / (3.0 * (double)np)) : 0.0;
+  ctx->last_work = ctx->cfg.dt * (h[OP_WORK] - r[4] * M.dV);
+  ctx->last_rr = rr;
+  ctx->last_mr = mr;
+  ctx->t += ctx->cfg.dt;
+  ctx->step += 1;
+  return GMHC_OK;
+}
+
+// Solve A x = b (n <= 8, row-major A) by Gaussian elimination with partial pivoting;
+// false when a pivot vanishes or the result is not finite.
+bool solve_small(double* A, double* b, int n, double* x) {
+  for (int c = 0; c < n; ++c) {
+    int p = c;
+    for (int r = c + 1; r < n; ++r)
+      if (fabs(A[r * n + c]) > fabs(A[p * n + c])) p = r;
+    const double piv = A[p * n + c];
+    if (!(fabs(piv) > 0.0) || !isfinite(piv)) return false;
+    if (p != c) {
+      for (int k = 0; k < n; ++k) std::swap(A[c * n + k], A[p * n + k]);
+      std::swap(b[c], b[p]);
+    }
+    for (int r = c + 1; r < n; ++r) {
+      const double f = A[r * n + c] / A[c * n + c];
+      for (int k = c; k < n; ++k) A[r * n + k] -= f * A[c * n + k];
+      b[r] -= f * b[c];
+    }
+  }
+  for (int c = n - 1; c >= 0; --c) {
+    double v = b[c];
+    for (int k = c + 1; k < n; ++k) v -= A[c * n + k] * x[k];
+    x[c] = v / A[c * n + c];
+    if (!isfinite(x[c])) return false;
+  }
+  return true;
+}
+
+// The paper's outer solver: limited-memory type-II Anderson acceleration of the current
+// iteration (section on the implicit solver).  With residual differences dR and
+// iterate differences dJ as history columns,
+//   [dR^T dR + lambda tr(dR^T dR)/m_h I] gamma = dR^T r,  j_A = j + beta r - (dJ + beta dR) gamma,
+// backtracking alpha = 1, 1/2, ... along the direction, accepting a trial whose scaled
+// RMS residual drops by at least a factor 1 - c alpha and whose scaled max-node
+// residual grows by at most the growth limit.  The history is cleared when unusable,
+// when a trial's RMS residual grows past the growth limit, or when the Anderson
+// direction is rejected, which is then retried as damped Picard (j + beta r).
+int32_t step_anderson(gmhc_ctx* ctx, gmhc_step_report& R, bool& use_graph) {
+  const Mesh& M = ctx->M;
+  const int64_t n = 3 * M.Ng;
+  hipStream_t s = ctx->stream;
+  const gmhc_config& c = ctx->cfg;
+  double rr = 0.0, mr = 0.0;
+  int32_t st = eval_outer(ctx, 0, 2, R, use_graph, rr, mr);
+  if (st) return st;
+  if (rr <= 1.0 && mr <= 1.0) return commit_outer(ctx, 0, rr, mr);
+  HIPCK(launch_axpbz(ctx->jA, 1.0, ctx->jr[0], 0.0, nullptr, n, s));
+  HIPCK(launch_axpbz(ctx->rA, 1.0, ctx->jr[2], -1.0, ctx->jr[0], n, s));
+  double err = rr, emr = mr;
+  const int mem = c.anderson_m;
+  int mh = 0, head = 0;  // history column k (oldest first) lives at index (head + k) % mem
+  while (R.outer_iters < c.max_outer) {
+    const int k = R.outer_iters;
+    bool accepted = false;
+    for (int pass = 0; pass < 2 && !accepted; ++pass) {
+      const bool use_a = pass == 0 && k >= c.anderson_start && mh > 0;
+      if (pass == 0 && !use_a) continue;
+      HIPCK(launch_axpbz(ctx->dA, c.beta, ctx->rA, 0.0, nullptr, n, s));
+      if (use_a) {
+        DotArgs da{};
+        da.K = mh + 1;
+        da.n = n;
+        for (int m = 0; m < mh; ++m) da.v[m] = ctx->hR[(head + m) % mem];
+        da.v[mh] = ctx->rA;
+        da.partials = ctx->partials;
+        const int nb = (int)std::min<int64_t>((n + kBlock - 1) / kBlock, 128);
+        HIPCK(launch_dots(da, nb, s));
+        HIPCK(launch_reduce(ctx->partials, nb, kMaxDots, 1, kMaxDots, 0u, ctx->ddot, s));
+        HIPCK(hipMemcpyAsync(ctx->hdot, ctx->ddot, sizeof(double) * kMaxDots, hipMemcpyDeviceToHost, s));
+        HIPCK(hipStreamSynchronize(s));
+        // unpack the upper triangle (k1 <= k2, row order over kMaxDotVecs vectors)
+        auto dot = [&](int k1, int k2) {
+          if (k1 > k2) std::swap(k1, k2);
+          return ctx->hdot[k1 * kMaxDotVecs - k1 * (k1 - 1) / 2 + (k2 - k1)];
+        };
+        double G[64], b[8], gam[8];
+        double tr = 0.0;
+        for (int a1 = 0; a1 < mh; ++a1) {
+          b[a1] = dot(a1, mh);
+          for (int a2 = 0; a2 < mh; ++a2) G[a1 * mh + a2] = dot(a1, a2);
+          tr += G[a1 * mh + a1];
+        }
+        for (int a1 = 0; a1 < mh; ++a1) G[a1 * mh + a1] += c.anderson_lambda * tr / mh;
+        if (!solve_small(G, b, mh, gam)) {
+          mh = 0;  // unusable history: damped Picard
+          continue;
+        }
+        for (int m = 0; m < mh; ++m) {
+          const int col = (head + m) % mem;
+          HIPCK(launch_axpbz(ctx->dA, 1.0, ctx->dA, -gam[m], ctx->hJ[col], n, s));
+          HIPCK(launch_axpbz(ctx->dA, 1.0, ctx->dA, -gam[m] * c.beta, ctx->hR[col], n, s));
+        }
+      }
+      double alpha = 1.0;
+      for (int hh = 0; hh <= c.ls_halvings && R.outer_iters < c.max_outer; ++hh, alpha *= 0.5) {
+        // trial j_t = j + alpha d in slot 1, with its projected spectrum for the field step
+        HIPCK(launch_axpbz(ctx->jr[1], 1.0, ctx->jA, alpha, ctx->dA, n, s));
+        HIPCK(fft_nd(M, ctx->axes, 3, ctx->jr[1], nullptr, ctx->jh[1], nullptr, nullptr, false,
+                     c.project_nyquist != 0, s));
+        st = eval_outer(ctx, 1, 2, R, use_graph, rr, mr);
+        if (st) return st;
+        if (rr <= 1.0 && mr <= 1.0) return commit_outer(ctx, 1, rr, mr);
+        if (use_a && rr > c.ls_growth * err) mh = 0;
+        if (rr <= (1.0 - c.ls_decrease * alpha) * err && mr <= c.ls_growth * emr) {
+          int col;
+          if (mh < mem) {
+            col = (head + mh) % mem;
+            ++mh;
+          } else {
+            col = head;
+            head = (head + 1) % mem;
+          }
+          // history column: dJ = j_t - j, dR = (H_t - j_t) - r; then j = j_t, r = H_t - j_t
+          HIPCK(launch_axpbz(ctx->hJ[col], 1.0, ctx->jr[1], -1.0, ctx->jA, n, s));
+          HIPCK(launch_axpbz(ctx->hR[col], 1.0, ctx->jr[2], -1.0, ctx->jr[1], n, s));
+          HIPCK(launch_axpbz(ctx->hR[col], 1.0, ctx->hR[col], -1.0, ctx->rA, n, s));
+          HIPCK(launch_axpbz(ctx->jA, 1.0, ctx->jr[1], 0.0, nullptr, n, s));
+          HIPCK(launch_axpbz(ctx->rA, 1.0, ctx->jr[2], -1.0, ctx->jr[1], n, s));
+          err = rr;
+          emr = mr;
+          accepted = true;
+          break;
+        }
+      }
+      if (!accepted && use_a) mh = 0;  // rejected Anderson direction: retry as damped Picard
+    }
+    if (!accepted) return fail(ctx, GMHC_ENOCONV, "no outer direction accepted by the backtracking safeguards");
+  }
+  return fail(ctx, GMHC_ENOCONV, "outer iteration limit reached");
+}
+
 int32_t gmhc_step(gmhc_ctx* ctx, gmhc_step_report* rep) {
   if (!ctx) return GMHC_EINVAL;
   if (!ctx->initialized) return fail(ctx, GMHC_ESTATE, "initialize before step");
   DevGuard gd(ctx->device);
   const Mesh& M = ctx->M;
   const int64_t Ng = M.Ng, np = ctx->np;
-  const int d = M.d;
   hipStream_t s = ctx->stream;
   gmhc_step_report R{};
+  auto done = [&](int32_t st) {
+    if (rep) *rep = R;
+    return st;
+  };
   if (ctx->cfg.sort_every > 0 && ctx->step % ctx->cfg.sort_every == 0) {
     int32_t st = sort_particles(ctx);
-    if (st) return st;
+    if (st) return done(st);
   }
   for (int l = 0; l < 3; ++l)
     if (np) HIPCK(hipMemcpyAsync(ctx->vw[l], ctx->vb[l], ctx->es * np, hipMemcpyDeviceToDevice, s));
-  int cur = 0;
   bool use_graph = ctx->cfg.graphs != 0 && ctx->stream != nullptr && !ctx->graphs_off;
-  for (int k = 1; k <= ctx->cfg.max_outer; ++k) {
+  if (ctx->cfg.outer_scheme == 1) return done(step_anderson(ctx, R, use_graph));
+  // damped Picard: j <- j + beta (H(j) - j)
+  int cur = 0;
+  while (R.outer_iters < ctx->cfg.max_outer) {
     const int hs = (cur == 1) ? 2 : 1;
-    int32_t st = run_outer(ctx, cur, hs, use_graph, R.graph_replays);
-    if (st) return st;
-    double oms = 0.0;
-    st = wait_results(ctx, &oms);
-    if (st) return st;
-    R.orbit_ms += oms;
-    R.orbit_launches += 1;
-    const double* h = ctx->hres;
-    R.outer_iters = k;
-    R.evaluations += (int64_t)llround(h[OP_ITERS]);
-    R.segments += (int64_t)llround(h[OP_SEGS]);
-    R.inner_max = (int32_t)llround(h[OP_ITMAX]);
-    R.inner_mean = np ? h[OP_ITERS] / (double)np : 0.0;
-    if (h[OP_FAIL] > 0.0) {
-      if (rep) *rep = R;
-      return fail(ctx, GMHC_EINNER, "particle inner solve failed (" + std::to_string((long long)h[OP_FAIL]) +
-                                        " particles)");
-    }
-    const double* r = ctx->hres + kResOff;
-    const double n3 = 3.0 * (double)Ng;
-    const double rr = sqrt(r[0] / n3) /
-                      (ctx->cfg.tol_outer_abs + 0.5 * ctx->cfg.tol_outer_rel * (sqrt(r[1] / n3) + sqrt(r[2] / n3)));
-    const double mr = r[3];
-    R.res_rms_ratio = rr;
-    R.res_max_ratio = mr;
-    if (rr <= 1.0 && mr <= 1.0) {
-      // commit the converged state
-      std::swap(ctx->S0, ctx->S1);
-      HIPCK(hipMemcpyAsync(ctx->An, ctx->trial + (int64_t)d * Ng, sizeof(double) * 3 * Ng,
-                           hipMemcpyDeviceToDevice, s));
-      if (cur != 0) {
-        HIPCK(hipMemcpyAsync(ctx->jr[0], ctx->jr[cur], sizeof(double) * 3 * Ng, hipMemcpyDeviceToDevice, s));
-        HIPCK(hipMemcpyAsync(ctx->jh[0], ctx->jh[cur], sizeof(double2) * 3 * Ng, hipMemcpyDeviceToDevice, s));
-      }
-      for (int l = 0; l < d; ++l) std::swap(ctx->x[l], ctx->x2[l]);
-      for (int l = 0; l < 3; ++l) {
-        std::swap(ctx->P[l], ctx->P2[l]);
-        std::swap(ctx->vb[l], ctx->vw[l]);
-      }
-      HIPCK(hipStreamSynchronize(s));
-      ctx->last_chain = np ? sqrt(h[OP_RA2] / (3.0 * (double)np)) : 0.0;
-      ctx->last_work = ctx->cfg.dt * (h[OP_WORK] - r[4] * M.dV);
-      ctx->last_rr = rr;
-      ctx->last_mr = mr;
-      ctx->t += ctx->cfg.dt;
-      ctx->step += 1;
-      if (rep) *rep = R;
-      return GMHC_OK;
-    }
+    double rr = 0.0, mr = 0.0;
+    int32_t st = eval_outer(ctx, cur, hs, R, use_graph, rr, mr);
+    if (st) return done(st);
+    if (rr <= 1.0 && mr <= 1.0) return done(commit_outer(ctx, cur, rr, mr));
     if (ctx->cfg.beta != 1.0)
       HIPCK(launch_axpy2(ctx->jr[hs], ctx->jr[cur], ctx->jh[hs], ctx->jh[cur], 1.0 - ctx->cfg.beta, 3 * Ng,
                          3 * Ng, s));
     cur = hs;
   }
-  if (rep) *rep = R;
-  return fail(ctx, GMHC_ENOCONV, "outer iteration limit reached");
+  return done(fail(ctx, GMHC_ENOCONV, "outer iteration limit reached"));
 }
 
 int32_t gmhc_diagnostics(gmhc_ctx* ctx, gmhc_diag* out) {

@@ -133,6 +133,22 @@ hipError_t launch_residual(const ResidualArgs& a, int blocks, hipStream_t s);
 hipError_t launch_reduce(const double* partials, int nblocks, int64_t bstride, int64_t vstride, int nvals,
                          uint32_t max_mask, double* out, hipStream_t s);
 
+// y = a x + b z over n values (z may be null).
+hipError_t launch_axpbz(double* y, double a, const double* x, double b, const double* z, int64_t n,
+                        hipStream_t s);
+
+// Pairwise dot products of up to kMaxDotVecs vectors: per-block partials of the upper
+// triangle (pairs (k1, k2), k1 <= k2, in row order), kMaxDots values per block.
+constexpr int kMaxDotVecs = 9;
+constexpr int kMaxDots = kMaxDotVecs * (kMaxDotVecs + 1) / 2;
+struct DotArgs {
+  int K;
+  int64_t n;
+  const double* v[kMaxDotVecs];
+  double* partials;  // [blocks][kMaxDots]
+};
+hipError_t launch_dots(const DotArgs& a, int blocks, hipStream_t s);
+
 // y[0..n) = 0 with a kernel (safe inside captured graphs, unlike a memset node).
 hipError_t launch_zero(double* y, int64_t n, hipStream_t s);
 hipError_t launch_axpy2(double* y, const double* x, double2* yc, const double2* xc, double beta,

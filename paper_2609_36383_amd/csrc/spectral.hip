@@ -275,6 +275,32 @@ __global__ __launch_bounds__(kBlock) void k_zero(double* y, int64_t n) {
   if (i < n) y[i] = 0.0;
 }
 
+// y = a x + b z over n values (outer-solver vector updates).
+__global__ __launch_bounds__(kBlock) void k_axpbz(double* y, double a, const double* x, double b, const double* z,
+                                                  int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) y[i] = a * x[i] + (z ? b * z[i] : 0.0);
+}
+
+// Pairwise dot products of K <= kMaxDotVecs vectors of length n: partial sums per block
+// of the upper triangle (a <= b) in row order, for the fixed-order reduction.
+__global__ __launch_bounds__(kBlock) void k_dots(DotArgs a) {
+  double part[kMaxDots];
+#pragma unroll
+  for (int v = 0; v < kMaxDots; ++v) part[v] = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < a.n; i += (int64_t)gridDim.x * blockDim.x) {
+    double x[kMaxDotVecs];
+#pragma unroll
+    for (int k = 0; k < kMaxDotVecs; ++k) x[k] = k < a.K ? a.v[k][i] : 0.0;
+    int p = 0;
+#pragma unroll
+    for (int k1 = 0; k1 < kMaxDotVecs; ++k1)
+#pragma unroll
+      for (int k2 = k1; k2 < kMaxDotVecs; ++k2) part[p++] += x[k1] * x[k2];
+  }
+  block_store<kMaxDots>(part, 0u, a.partials);
+}
+
 __global__ void k_axpy2(double* y, const double* x, double2* yc, const double2* xc, double beta,
                         int64_t nreal, int64_t ncplx) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -599,6 +625,18 @@ hipError_t launch_reduce(const double* partials, int nblocks, int64_t bstride, i
 hipError_t launch_zero(double* y, int64_t n, hipStream_t s) {
   if (n <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_zero, dim3(nblk(n)), dim3(kBlock), 0, s, y, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_axpbz(double* y, double a, const double* x, double b, const double* z, int64_t n,
+                        hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_axpbz, dim3(nblk(n)), dim3(kBlock), 0, s, y, a, x, b, z, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_dots(const DotArgs& a, int blocks, hipStream_t s) {
+  hipLaunchKernelGGL(k_dots, dim3(blocks), dim3(kBlock), 0, s, a);
   return hipGetLastError();
 }
 

@@ -15,7 +15,9 @@ LIB_PATH = os.path.join(HERE, "libgmhc.so")
 
 OK, EINVAL, ESTATE, ENOMEM, EDEVICE, EINNER, ENOCONV = 0, -1, -2, -3, -4, -5, -6
 HOST, DEVICE = 0, 1
+ABI_VERSION = 2  # layout of the structures below (include/gmhc.h, GMHC_ABI_VERSION)
 FP64, FP32_BULK = 0, 1
+PICARD, ANDERSON = 0, 1
 FIELD = {"phi": 0, "psi": 1, "A": 2, "U": 3, "rho": 4, "J": 5, "E": 6, "B": 7}
 FIELD_NCOMP = {"phi": 1, "psi": 1, "A": 3, "U": 3, "rho": 1, "J": 3, "E": 3, "B": 3}
 
@@ -38,7 +40,10 @@ class Config(C.Structure):
         ("tol_outer_abs", C.c_double), ("tol_outer_rel", C.c_double),
         ("tol_inner_abs", C.c_double), ("tol_inner_rel", C.c_double),
         ("max_outer", C.c_int32), ("max_inner", C.c_int32), ("beta", C.c_double),
-        ("timing", C.c_int32), ("graphs", C.c_int32), ("reserved", C.c_int32 * 6),
+        ("timing", C.c_int32), ("graphs", C.c_int32),
+        ("outer_scheme", C.c_int32), ("anderson_m", C.c_int32), ("anderson_start", C.c_int32),
+        ("ls_halvings", C.c_int32), ("reserved", C.c_int32 * 2),
+        ("anderson_lambda", C.c_double), ("ls_decrease", C.c_double), ("ls_growth", C.c_double),
     ]
 
 
@@ -106,6 +111,9 @@ def load_library(path=LIB_PATH):
         f = getattr(L, name)
         f.argtypes = args
         f.restype = res
+    if L.gmhc_abi_version() != ABI_VERSION:
+        raise RuntimeError(f"{path} has ABI version {L.gmhc_abi_version()}, this binding expects "
+                           f"{ABI_VERSION}: rebuild with `python -m paper_2609_36383_amd.build`")
     _lib = L
     return L
 
@@ -120,7 +128,8 @@ class GmhcError(RuntimeError):
 def make_config(dim, n, lo, length, dt, kappa=1.0, sigma1=1.0, sigma2=1.0, gl_order=0,
                 project_nyquist=1, precision=FP64, sort_every=0, tol_outer_abs=1e-14,
                 tol_outer_rel=1e-12, tol_inner_abs=1e-14, tol_inner_rel=1e-12, max_outer=80,
-                max_inner=64, beta=1.0, timing=0, graphs=0):
+                max_inner=64, beta=1.0, timing=0, graphs=0, outer_scheme=0, anderson_m=4,
+                anderson_start=2, ls_halvings=6, anderson_lambda=1e-12, ls_decrease=1e-4, ls_growth=1.2):
     c = Config()
     c.dim = dim
     for i in range(3):
@@ -132,6 +141,8 @@ def make_config(dim, n, lo, length, dt, kappa=1.0, sigma1=1.0, sigma2=1.0, gl_or
     c.tol_outer_abs, c.tol_outer_rel = tol_outer_abs, tol_outer_rel
     c.tol_inner_abs, c.tol_inner_rel = tol_inner_abs, tol_inner_rel
     c.max_outer, c.max_inner, c.beta, c.timing, c.graphs = max_outer, max_inner, beta, timing, graphs
+    c.outer_scheme, c.anderson_m, c.anderson_start, c.ls_halvings = outer_scheme, anderson_m, anderson_start, ls_halvings
+    c.anderson_lambda, c.ls_decrease, c.ls_growth = anderson_lambda, ls_decrease, ls_growth
     return c
 
 

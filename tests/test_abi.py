@@ -25,7 +25,7 @@ def test_library_exports_every_symbol():
     lib = G.load_library()
     for name in _declared():
         assert hasattr(lib, name), name
-    assert lib.gmhc_abi_version() == 1
+    assert lib.gmhc_abi_version() == G.ABI_VERSION
 
 
 def test_host_validation():
@@ -45,6 +45,11 @@ def test_host_validation():
         dict(gl_order=9),
         dict(beta=0.0),
         dict(max_outer=0),
+        dict(outer_scheme=2),
+        dict(outer_scheme=1, anderson_m=0),
+        dict(outer_scheme=1, anderson_m=9),
+        dict(outer_scheme=1, ls_growth=0.9),
+        dict(outer_scheme=1, ls_decrease=1.0),
     ]
     for over in bad:
         kw = dict(dim=2, n=(16, 16), lo=(0, 0), length=(3.2, 3.2), dt=0.05)
