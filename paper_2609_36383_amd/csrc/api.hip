@@ -67,6 +67,14 @@ struct gmhc_ctx {
   double* dA = nullptr;
   double* hJ[8] = {};
   double* hR[8] = {};
+  // device-side Picard control (see run_picard): stop flags, report accumulators,
+  // pinned host copies, per-iteration timing events, predicted iteration count
+  int32_t* dctl = nullptr;
+  double* dacc = nullptr;
+  int32_t* hctl = nullptr;
+  double* hacc = nullptr;
+  std::vector<hipEvent_t> evs;
+  int last_outer = 0;
   double* ddot = nullptr;   // device dot products [kMaxDots]
   double* hdot = nullptr;   // pinned host copy
   double* dres = nullptr;   // device results [32]
@@ -204,6 +212,8 @@ size_t carve(gmhc_ctx* c, char* base, int64_t np) {
   c->partials = cv.take<double>((size_t)(c->max_blocks + 1024) * 8);
   c->dres = cv.take<double>(64);
   c->ddot = cv.take<double>(kMaxDots);
+  c->dctl = cv.take<int32_t>(4);
+  c->dacc = cv.take<double>(16);
   if (c->cfg.outer_scheme == 1) {
     c->jA = cv.take<double>(3 * Ng);
     c->rA = cv.take<double>(3 * Ng);
@@ -460,6 +470,9 @@ void gmhc_destroy(gmhc_ctx* ctx) {
     (void)hipStreamSynchronize(ctx->stream);
     if (ctx->hres) (void)hipHostFree(ctx->hres);
     if (ctx->hdot) (void)hipHostFree(ctx->hdot);
+    if (ctx->hctl) (void)hipHostFree(ctx->hctl);
+    if (ctx->hacc) (void)hipHostFree(ctx->hacc);
+    for (hipEvent_t e : ctx->evs) (void)hipEventDestroy(e);
     for (auto& e : ctx->graphs) (void)hipGraphExecDestroy(e.exec);
     if (ctx->ev0) (void)hipEventDestroy(ctx->ev0);
     if (ctx->ev1) (void)hipEventDestroy(ctx->ev1);
@@ -496,6 +509,8 @@ int32_t gmhc_bind(gmhc_ctx* ctx, int64_t n_particles, void* dev_workspace, size_
   carve(ctx, ctx->ws, n_particles);
   HIPCK(hipHostMalloc(reinterpret_cast<void**>(&ctx->hres), sizeof(double) * 64, hipHostMallocDefault));
   HIPCK(hipHostMalloc(reinterpret_cast<void**>(&ctx->hdot), sizeof(double) * kMaxDots, hipHostMallocDefault));
+  HIPCK(hipHostMalloc(reinterpret_cast<void**>(&ctx->hctl), sizeof(int32_t) * 4, hipHostMallocDefault));
+  HIPCK(hipHostMalloc(reinterpret_cast<void**>(&ctx->hacc), sizeof(double) * 16, hipHostMallocDefault));
   HIPCK(hipEventCreate(&ctx->ev0));
   HIPCK(hipEventCreate(&ctx->ev1));
   // FFT plans and twiddles exp(-2 pi i m / N)
@@ -642,11 +657,21 @@ enum OuterPart { OUTER_ALL = 0, OUTER_PRE = 1, OUTER_ORBIT = 2, OUTER_POST = 3 }
 // the pass reduction, projected orbit current, outer residual and the copy of the
 // results to pinned host memory (POST).  Enqueued without host synchronization, so
 // the parts can be captured as HIP graphs.
-int32_t enqueue_outer(gmhc_ctx* ctx, int cur, int hs, int part) {
+//
+// With a device control block (stop != nullptr) every kernel first checks the stop flag
+// and returns when an earlier iteration already converged or failed; the iteration ends
+// with the device-side outer test of iteration k and, for beta < 1, the damped update of
+// the next trial current in slot hs, instead of copying the results to the host.
+int32_t enqueue_outer(gmhc_ctx* ctx, int cur, int hs, int part, const int32_t* stop = nullptr, int k = 0,
+                      hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr) {
   const Mesh& M = ctx->M;
   const int64_t Ng = M.Ng;
   const int d = M.d;
   hipStream_t s = ctx->stream;
+  if (!e0) {
+    e0 = ctx->ev0;
+    e1 = ctx->ev1;
+  }
   if (part == OUTER_ALL || part == OUTER_PRE) {
     CNArgs ca{};
     ca.M = M;
@@ -666,23 +691,26 @@ int32_t enqueue_outer(gmhc_ctx* ctx, int cur, int hs, int part) {
     ca.A1 = ctx->S1 + 3 * Ng;
     ca.U1 = ctx->S1 + 6 * Ng;
     ca.out = ctx->cout;
+    ca.stop = stop;
     HIPCK(launch_cn(ca, s));
-    HIPCK(fft_nd(M, ctx->axes, d + 6, nullptr, ctx->cout, nullptr, ctx->trial, ctx->cout, true, false, s));
-    HIPCK(launch_zero(ctx->Jdep, 3 * Ng, s));
+    HIPCK(fft_nd(M, ctx->axes, d + 6, nullptr, ctx->cout, nullptr, ctx->trial, ctx->cout, true, false, s, stop));
+    HIPCK(launch_zero(ctx->Jdep, 3 * Ng, s, stop));
   }
   if (part == OUTER_ALL || part == OUTER_ORBIT) {
     const bool timed = ctx->cfg.timing && part == OUTER_ORBIT;
-    if (timed) HIPCK(hipEventRecord(ctx->ev0, s));
-    HIPCK(launch_orbit(orbit_args(ctx, 1), ctx->ngl, s));
-    if (timed) HIPCK(hipEventRecord(ctx->ev1, s));
+    if (timed) HIPCK(hipEventRecord(e0, s));
+    OrbitArgs oa = orbit_args(ctx, 1);
+    oa.stop = stop;
+    HIPCK(launch_orbit(oa, ctx->ngl, s));
+    if (timed) HIPCK(hipEventRecord(e1, s));
   }
   if (part == OUTER_ALL || part == OUTER_POST) {
     HIPCK(launch_reduce(ctx->partials, orbit_blocks(ctx), 1, ctx->max_blocks, kOrbitParts, 1u << OP_ITMAX,
-                        ctx->dres, s));
+                        ctx->dres, s, stop));
     // H(j) = P J_orb in spectral and real space
     HIPCK(fft_nd(M, ctx->axes, 3, ctx->Jdep, nullptr, ctx->jh[hs], nullptr, nullptr, false,
-                 ctx->cfg.project_nyquist != 0, s));
-    HIPCK(fft_nd(M, ctx->axes, 3, nullptr, ctx->jh[hs], nullptr, ctx->jr[hs], ctx->cscr, true, false, s));
+                 ctx->cfg.project_nyquist != 0, s, stop));
+    HIPCK(fft_nd(M, ctx->axes, 3, nullptr, ctx->jh[hs], nullptr, ctx->jr[hs], ctx->cscr, true, false, s, stop));
     ResidualArgs ra{};
     ra.M = M;
     ra.tol_abs = ctx->cfg.tol_outer_abs;
@@ -692,10 +720,19 @@ int32_t enqueue_outer(gmhc_ctx* ctx, int cur, int hs, int part) {
     ra.gphi = ctx->trial;
     ra.Uh = ctx->trial + (int64_t)(d + 3) * Ng;
     ra.partials = ctx->partials + (size_t)ctx->max_blocks * 8;  // disjoint from orbit partials
+    ra.stop = stop;
     const int rb = res_blocks(ctx);
     HIPCK(launch_residual(ra, rb, s));
-    HIPCK(launch_reduce(ra.partials, rb, kResParts, 1, kResParts, 1u << 3, ctx->dres + kResOff, s));
-    HIPCK(hipMemcpyAsync(ctx->hres, ctx->dres, sizeof(double) * 32, hipMemcpyDeviceToHost, s));
+    HIPCK(launch_reduce(ra.partials, rb, kResParts, 1, kResParts, 1u << 3, ctx->dres + kResOff, s, stop));
+    if (stop) {
+      HIPCK(launch_outer_test(ctx->dres, kResOff, ctx->dctl, ctx->dacc, k, 3.0 * (double)Ng, ctx->cfg.tol_outer_abs,
+                              ctx->cfg.tol_outer_rel, s));
+      if (ctx->cfg.beta != 1.0)
+        HIPCK(launch_axpy2(ctx->jr[hs], ctx->jr[cur], ctx->jh[hs], ctx->jh[cur], 1.0 - ctx->cfg.beta, 3 * Ng,
+                           3 * Ng, s, stop));
+    } else {
+      HIPCK(hipMemcpyAsync(ctx->hres, ctx->dres, sizeof(double) * 32, hipMemcpyDeviceToHost, s));
+    }
   }
   return GMHC_OK;
 }
@@ -820,14 +857,13 @@ int32_t eval_outer(gmhc_ctx* ctx, int cur, int hs, gmhc_step_report& R, bool& us
   return GMHC_OK;
 }
 
-// Commit the state of the evaluation just made at the trial current in slot cur.
-int32_t commit_outer(gmhc_ctx* ctx, int cur, double rr, double mr) {
+// Commit the state of the converged evaluation at the trial current in slot cur; ra2,
+// pwork and mwork are its sum |R_A|^2, particle work and mesh work.
+int32_t commit_outer(gmhc_ctx* ctx, int cur, double rr, double mr, double ra2, double pwork, double mwork) {
   const Mesh& M = ctx->M;
   const int64_t Ng = M.Ng, np = ctx->np;
   const int d = M.d;
   hipStream_t s = ctx->stream;
-  const double* h = ctx->hres;
-  const double* r = ctx->hres + kResOff;
   std::swap(ctx->S0, ctx->S1);
   HIPCK(hipMemcpyAsync(ctx->An, ctx->trial + (int64_t)d * Ng, sizeof(double) * 3 * Ng, hipMemcpyDeviceToDevice, s));
   if (cur != 0) {
@@ -840,13 +876,89 @@ int32_t commit_outer(gmhc_ctx* ctx, int cur, double rr, double mr) {
     std::swap(ctx->vb[l], ctx->vw[l]);
   }
   HIPCK(hipStreamSynchronize(s));
-  ctx->last_chain = np ? sqrt(h[OP_RA2] / (3.0 * (double)np)) : 0.0;
-  ctx->last_work = ctx->cfg.dt * (h[OP_WORK] - r[4] * M.dV);
+  ctx->last_chain = np ? sqrt(ra2 / (3.0 * (double)np)) : 0.0;
+  ctx->last_work = ctx->cfg.dt * (pwork - mwork * M.dV);
   ctx->last_rr = rr;
   ctx->last_mr = mr;
   ctx->t += ctx->cfg.dt;
   ctx->step += 1;
   return GMHC_OK;
+}
+
+// Commit after a host-driven evaluation (its results are in hres).
+int32_t commit_host(gmhc_ctx* ctx, int cur, double rr, double mr) {
+  return commit_outer(ctx, cur, rr, mr, ctx->hres[OP_RA2], ctx->hres[OP_WORK], ctx->hres[kResOff + 4]);
+}
+
+// Damped Picard with the outer test on the device: iterations are enqueued in batches
+// (the size of the last step's count) without waiting; each ends with the device-side
+// test, and once it passes (or an inner solve fails) the kernels of the iterations
+// already queued return at once.  The host synchronizes once per batch, so the GPU does
+// not idle between outer iterations.
+int32_t run_picard(gmhc_ctx* ctx, gmhc_step_report& R) {
+  hipStream_t s = ctx->stream;
+  const int64_t np = ctx->np;
+  const int maxo = ctx->cfg.max_outer;
+  HIPCK(hipMemsetAsync(ctx->dctl, 0, sizeof(int32_t) * 4, s));
+  HIPCK(hipMemsetAsync(ctx->dacc, 0, sizeof(double) * 16, s));
+  const bool timed = ctx->cfg.timing != 0;
+  if (timed)
+    while ((int)ctx->evs.size() < 2 * maxo) {
+      hipEvent_t e;
+      HIPCK(hipEventCreate(&e));
+      ctx->evs.push_back(e);
+    }
+  std::vector<int> slot(maxo + 1, 0);
+  int k = 0, cur = 0;
+  int batch = std::max(1, std::min(ctx->last_outer, maxo));
+  while (true) {
+    const int k0 = k;
+    for (int b = 0; b < batch && k < maxo; ++b) {
+      ++k;
+      const int hs = (cur == 1) ? 2 : 1;
+      slot[k] = cur;
+      if (timed) {
+        hipEvent_t e0 = ctx->evs[2 * (k - 1)], e1 = ctx->evs[2 * (k - 1) + 1];
+        for (int part : {OUTER_PRE, OUTER_ORBIT, OUTER_POST}) {
+          int32_t st = enqueue_outer(ctx, cur, hs, part, ctx->dctl, k, e0, e1);
+          if (st) return st;
+        }
+      } else {
+        int32_t st = enqueue_outer(ctx, cur, hs, OUTER_ALL, ctx->dctl, k);
+        if (st) return st;
+      }
+      cur = hs;
+    }
+    HIPCK(hipMemcpyAsync(ctx->hctl, ctx->dctl, sizeof(int32_t) * 4, hipMemcpyDeviceToHost, s));
+    HIPCK(hipMemcpyAsync(ctx->hacc, ctx->dacc, sizeof(double) * 16, hipMemcpyDeviceToHost, s));
+    HIPCK(hipStreamSynchronize(s));
+    const int32_t* c = ctx->hctl;
+    const double* acc = ctx->hacc;
+    const int ran = (int)llround(acc[3]);  // iterations that ran (the rest returned at once)
+    if (timed)
+      for (int kk = k0 + 1; kk <= std::min(k, ran); ++kk) {
+        float f = 0.0f;
+        HIPCK(hipEventElapsedTime(&f, ctx->evs[2 * (kk - 1)], ctx->evs[2 * (kk - 1) + 1]));
+        R.orbit_ms += (double)f;
+      }
+    R.outer_iters = ran;
+    R.orbit_launches = ran;
+    R.evaluations = (int64_t)llround(acc[0]);
+    R.segments = (int64_t)llround(acc[1]);
+    R.inner_max = (int32_t)llround(acc[2]);
+    R.inner_mean = np ? acc[10] / (double)np : 0.0;
+    R.res_rms_ratio = acc[5];
+    R.res_max_ratio = acc[6];
+    if (c[0]) {
+      if (c[1])
+        return fail(ctx, GMHC_EINNER,
+                    "particle inner solve failed (" + std::to_string((long long)acc[4]) + " particles)");
+      ctx->last_outer = c[2];
+      return commit_outer(ctx, slot[c[2]], acc[5], acc[6], acc[7], acc[8], acc[9]);
+    }
+    if (k >= maxo) return fail(ctx, GMHC_ENOCONV, "outer iteration limit reached");
+    batch = 1;
+  }
 }
 
 // Solve A x = b (n <= 8, row-major A) by Gaussian elimination with partial pivoting;
@@ -894,7 +1006,7 @@ int32_t step_anderson(gmhc_ctx* ctx, gmhc_step_report& R, bool& use_graph) {
   double rr = 0.0, mr = 0.0;
   int32_t st = eval_outer(ctx, 0, 2, R, use_graph, rr, mr);
   if (st) return st;
-  if (rr <= 1.0 && mr <= 1.0) return commit_outer(ctx, 0, rr, mr);
+  if (rr <= 1.0 && mr <= 1.0) return commit_host(ctx, 0, rr, mr);
   HIPCK(launch_axpbz(ctx->jA, 1.0, ctx->jr[0], 0.0, nullptr, n, s));
   HIPCK(launch_axpbz(ctx->rA, 1.0, ctx->jr[2], -1.0, ctx->jr[0], n, s));
   double err = rr, emr = mr;
@@ -950,7 +1062,7 @@ int32_t step_anderson(gmhc_ctx* ctx, gmhc_step_report& R, bool& use_graph) {
                      c.project_nyquist != 0, s));
         st = eval_outer(ctx, 1, 2, R, use_graph, rr, mr);
         if (st) return st;
-        if (rr <= 1.0 && mr <= 1.0) return commit_outer(ctx, 1, rr, mr);
+        if (rr <= 1.0 && mr <= 1.0) return commit_host(ctx, 1, rr, mr);
         if (use_a && rr > c.ls_growth * err) mh = 0;
         if (rr <= (1.0 - c.ls_decrease * alpha) * err && mr <= c.ls_growth * emr) {
           int col;
@@ -1000,14 +1112,16 @@ int32_t gmhc_step(gmhc_ctx* ctx, gmhc_step_report* rep) {
     if (np) HIPCK(hipMemcpyAsync(ctx->vw[l], ctx->vb[l], ctx->es * np, hipMemcpyDeviceToDevice, s));
   bool use_graph = ctx->cfg.graphs != 0 && ctx->stream != nullptr && !ctx->graphs_off;
   if (ctx->cfg.outer_scheme == 1) return done(step_anderson(ctx, R, use_graph));
-  // damped Picard: j <- j + beta (H(j) - j)
+  // damped Picard: j <- j + beta (H(j) - j); the outer test runs on the device unless
+  // the outer iterations are replayed as graphs
+  if (!use_graph) return done(run_picard(ctx, R));
   int cur = 0;
   while (R.outer_iters < ctx->cfg.max_outer) {
     const int hs = (cur == 1) ? 2 : 1;
     double rr = 0.0, mr = 0.0;
     int32_t st = eval_outer(ctx, cur, hs, R, use_graph, rr, mr);
     if (st) return done(st);
-    if (rr <= 1.0 && mr <= 1.0) return done(commit_outer(ctx, cur, rr, mr));
+    if (rr <= 1.0 && mr <= 1.0) return done(commit_host(ctx, cur, rr, mr));
     if (ctx->cfg.beta != 1.0)
       HIPCK(launch_axpy2(ctx->jr[hs], ctx->jr[cur], ctx->jh[hs], ctx->jh[cur], 1.0 - ctx->cfg.beta, 3 * Ng,
                          3 * Ng, s));

@@ -80,6 +80,7 @@ struct OrbitArgs {
   double* J;             // [3] orbit current accumulator
   double* partials;      // [kOrbitParts][pstride]: value v of block b at v * pstride + b
   int64_t pstride;       // >= gridDim.x
+  const int32_t* stop;   // optional device flag: nonzero = skip the pass
 };
 
 hipError_t launch_orbit(const OrbitArgs& a, int ngl, hipStream_t s);
@@ -102,7 +103,7 @@ struct FftPlanAxis {
 // project = 1 zeroes the even-grid Nyquist planes of a forward result.
 hipError_t fft_nd(const Mesh& M, const FftPlanAxis* axes, int ncomp, const double* src_r,
                   const double2* src_c, double2* dst_c, double* dst_r, double2* scratch_c,
-                  bool inverse, bool project, hipStream_t s);
+                  bool inverse, bool project, hipStream_t s, const int32_t* stop = nullptr);
 
 struct CNArgs {
   Mesh M;
@@ -114,6 +115,7 @@ struct CNArgs {
   double2* phi1; double2* psi1; double2* rho1;
   double2* A1; double2* U1;
   double2* out;          // [d+6][Ng]: i k phi^{n+1/2} (d), A^{n+1} (3), U^{n+1/2} (3)
+  const int32_t* stop;   // optional device flag: nonzero = skip (outer iteration done)
 };
 hipError_t launch_cn(const CNArgs& a, hipStream_t s);
 
@@ -125,13 +127,24 @@ struct ResidualArgs {
   const double* gphi;    // [d][Ng]
   const double* Uh;      // [3][Ng]
   double* partials;      // [blocks][kResParts]
+  const int32_t* stop;   // optional device flag: nonzero = skip
 };
 hipError_t launch_residual(const ResidualArgs& a, int blocks, hipStream_t s);
 
 // out[v] = reduce over blocks b of partials[b * bstride + v * vstride]; max_mask bit v
 // set = max, else sum.
 hipError_t launch_reduce(const double* partials, int nblocks, int64_t bstride, int64_t vstride, int nvals,
-                         uint32_t max_mask, double* out, hipStream_t s);
+                         uint32_t max_mask, double* out, hipStream_t s, const int32_t* stop = nullptr);
+
+// Device-side outer test of a Picard iteration (one thread): reads the pass results
+// res[0..7] and residual sums res[kOff..], accumulates the step report in acc and, when
+// the mixed tests pass or an inner solve failed, sets ctl[0] (stop) and records the
+// iteration k.  ctl: [0] stop, [1] failed, [2] iteration that stopped.
+// acc: [0] evaluations, [1] segments, [2] inner max, [3] iterations, [4] failed count,
+// [5] rms ratio, [6] max ratio, [7] sum |R_A|^2, [8] particle work, [9] mesh work,
+// [10] evaluations of the last iteration.
+hipError_t launch_outer_test(const double* res, int koff, int32_t* ctl, double* acc, int k, double n3,
+                             double tol_abs, double tol_rel, hipStream_t s);
 
 // y = a x + b z over n values (z may be null).
 hipError_t launch_axpbz(double* y, double a, const double* x, double b, const double* z, int64_t n,
@@ -150,9 +163,9 @@ struct DotArgs {
 hipError_t launch_dots(const DotArgs& a, int blocks, hipStream_t s);
 
 // y[0..n) = 0 with a kernel (safe inside captured graphs, unlike a memset node).
-hipError_t launch_zero(double* y, int64_t n, hipStream_t s);
+hipError_t launch_zero(double* y, int64_t n, hipStream_t s, const int32_t* stop = nullptr);
 hipError_t launch_axpy2(double* y, const double* x, double2* yc, const double2* xc, double beta,
-                        int64_t nreal, int64_t ncplx, hipStream_t s);
+                        int64_t nreal, int64_t ncplx, hipStream_t s, const int32_t* stop = nullptr);
 
 // ---- initialization and diagnostics ----------------------------------------------
 

@@ -818,6 +818,7 @@ constexpr int orbit_waves() { return (sizeof(R) == 4 && D <= 2) ? 3 : 2; }
 template <int D, int NGL, class R>
 __global__ __launch_bounds__(kOrbitBlock)
 __attribute__((amdgpu_waves_per_eu(orbit_waves<D, R>()))) void k_orbit(OrbitArgs a) {
+  if (a.stop && *a.stop) return;  // the outer iteration this pass belongs to is done
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const Mesh& M = a.M;
   const int64_t ps = a.ps;

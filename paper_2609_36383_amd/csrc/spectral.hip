@@ -50,7 +50,8 @@ template <bool IN_REAL, bool OUT_REAL>
 __global__ __launch_bounds__(kBlock) void k_fft_axis(const double* src_r, const double2* src_c,
                                                      double2* dst_c, double* dst_r, int64_t Ng,
                                                      FftPlanAxis ax, int inverse, int project,
-                                                     Mesh M) {
+                                                     Mesh M, const int32_t* stop) {
+  if (stop && *stop) return;
   extern __shared__ double2 lds[];
   const int N = ax.N, T = ax.T, logN = ax.logN;  // N and T are powers of two
   const int logT = 31 - __clz(T);
@@ -130,6 +131,7 @@ __global__ __launch_bounds__(kBlock) void k_fft_axis(const double* src_r, const 
 }
 
 __global__ __launch_bounds__(kBlock) void k_cn(CNArgs a) {
+  if (a.stop && *a.stop) return;
   const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const Mesh& M = a.M;
   if (g >= M.Ng) return;
@@ -198,6 +200,7 @@ __device__ __forceinline__ void block_store(double (&part)[NV], uint32_t max_mas
 // Outer residual r = H(j) - j: sums of |r|^2, |H|^2, |j|^2, the max-node test ratio,
 // and the mesh work sum_g H . E^{n+1/2} (E^{n+1/2} = -grad phi^{n+1/2} - U^{n+1/2}).
 __global__ __launch_bounds__(kBlock) void k_residual(ResidualArgs a) {
+  if (a.stop && *a.stop) return;
   double part[kResParts];
 #pragma unroll
   for (int v = 0; v < kResParts; ++v) part[v] = 0.0;
@@ -224,7 +227,9 @@ __global__ __launch_bounds__(kBlock) void k_residual(ResidualArgs a) {
 }
 
 __global__ __launch_bounds__(kBlock) void k_reduce(const double* partials, int nblocks, int64_t bstride,
-                                                   int64_t vstride, int nvals, uint32_t max_mask, double* out) {
+                                                   int64_t vstride, int nvals, uint32_t max_mask, double* out,
+                                                   const int32_t* stop) {
+  if (stop && *stop) return;
   // One workgroup per value.  Thread t folds blocks t, t + 256, ... into eight
   // independent accumulators (so eight loads are in flight), combines them in a fixed
   // order, then a fixed pairwise tree combines the threads: the result depends only
@@ -270,9 +275,40 @@ __global__ __launch_bounds__(kBlock) void k_reduce(const double* partials, int n
   if (threadIdx.x == 0) out[v] = sh[0];
 }
 
-__global__ __launch_bounds__(kBlock) void k_zero(double* y, int64_t n) {
+__global__ __launch_bounds__(kBlock) void k_zero(double* y, int64_t n, const int32_t* stop) {
+  if (stop && *stop) return;
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) y[i] = 0.0;
+}
+
+__global__ void k_outer_test(const double* res, int koff, int32_t* ctl, double* acc, int k, double n3,
+                             double tol_abs, double tol_rel) {
+  if (threadIdx.x != 0 || ctl[0]) return;
+  const double* h = res;
+  const double* r = res + koff;
+  acc[0] += h[OP_ITERS];
+  acc[1] += h[OP_SEGS];
+  acc[2] = h[OP_ITMAX];
+  acc[3] += 1.0;
+  acc[10] = h[OP_ITERS];
+  if (h[OP_FAIL] > 0.0) {
+    acc[4] = h[OP_FAIL];
+    ctl[1] = 1;
+    ctl[2] = k;
+    ctl[0] = 1;
+    return;
+  }
+  const double rr = sqrt(r[0] / n3) / (tol_abs + 0.5 * tol_rel * (sqrt(r[1] / n3) + sqrt(r[2] / n3)));
+  const double mr = r[3];
+  acc[5] = rr;
+  acc[6] = mr;
+  if (rr <= 1.0 && mr <= 1.0) {
+    acc[7] = h[OP_RA2];
+    acc[8] = h[OP_WORK];
+    acc[9] = r[4];
+    ctl[2] = k;
+    ctl[0] = 1;
+  }
 }
 
 // y = a x + b z over n values (outer-solver vector updates).
@@ -302,7 +338,8 @@ __global__ __launch_bounds__(kBlock) void k_dots(DotArgs a) {
 }
 
 __global__ void k_axpy2(double* y, const double* x, double2* yc, const double2* xc, double beta,
-                        int64_t nreal, int64_t ncplx) {
+                        int64_t nreal, int64_t ncplx, const int32_t* stop) {
+  if (stop && *stop) return;
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < nreal) y[i] += beta * (x[i] - y[i]);
   if (i < ncplx) {
@@ -563,7 +600,7 @@ hipError_t launch_iota(int32_t* id, int64_t np, hipStream_t s) {
 
 hipError_t fft_nd(const Mesh& M, const FftPlanAxis* axes, int ncomp, const double* src_r,
                   const double2* src_c, double2* dst_c, double* dst_r, double2* scratch_c,
-                  bool inverse, bool project, hipStream_t s) {
+                  bool inverse, bool project, hipStream_t s, const int32_t* stop) {
   // passes: axis 0 .. d-1 (forward) or the same order (inverse; axes commute)
   double2* work = dst_c ? dst_c : scratch_c;
   for (int l = 0; l < M.d; ++l) {
@@ -589,16 +626,16 @@ hipError_t fft_nd(const Mesh& M, const FftPlanAxis* axes, int ncomp, const doubl
     dim3 grid(gx, (unsigned)ncomp);
     if (in_real && out_real)
       hipLaunchKernelGGL((k_fft_axis<true, true>), grid, dim3(threads), lds, s, src_r, nullptr, nullptr,
-                         dst_r, M.Ng, ax, inverse ? 1 : 0, proj, M);
+                         dst_r, M.Ng, ax, inverse ? 1 : 0, proj, M, stop);
     else if (in_real)
       hipLaunchKernelGGL((k_fft_axis<true, false>), grid, dim3(threads), lds, s, src_r, nullptr, work,
-                         nullptr, M.Ng, ax, inverse ? 1 : 0, proj, M);
+                         nullptr, M.Ng, ax, inverse ? 1 : 0, proj, M, stop);
     else if (out_real)
       hipLaunchKernelGGL((k_fft_axis<false, true>), grid, dim3(threads), lds, s, nullptr, in_c, nullptr,
-                         dst_r, M.Ng, ax, inverse ? 1 : 0, proj, M);
+                         dst_r, M.Ng, ax, inverse ? 1 : 0, proj, M, stop);
     else
       hipLaunchKernelGGL((k_fft_axis<false, false>), grid, dim3(threads), lds, s, nullptr, in_c, work,
-                         nullptr, M.Ng, ax, inverse ? 1 : 0, proj, M);
+                         nullptr, M.Ng, ax, inverse ? 1 : 0, proj, M, stop);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
@@ -616,15 +653,21 @@ hipError_t launch_residual(const ResidualArgs& a, int blocks, hipStream_t s) {
 }
 
 hipError_t launch_reduce(const double* partials, int nblocks, int64_t bstride, int64_t vstride, int nvals,
-                         uint32_t max_mask, double* out, hipStream_t s) {
+                         uint32_t max_mask, double* out, hipStream_t s, const int32_t* stop) {
   hipLaunchKernelGGL(k_reduce, dim3((unsigned)nvals), dim3(kBlock), 0, s, partials, nblocks, bstride, vstride, nvals,
-                     max_mask, out);
+                     max_mask, out, stop);
   return hipGetLastError();
 }
 
-hipError_t launch_zero(double* y, int64_t n, hipStream_t s) {
+hipError_t launch_zero(double* y, int64_t n, hipStream_t s, const int32_t* stop) {
   if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_zero, dim3(nblk(n)), dim3(kBlock), 0, s, y, n);
+  hipLaunchKernelGGL(k_zero, dim3(nblk(n)), dim3(kBlock), 0, s, y, n, stop);
+  return hipGetLastError();
+}
+
+hipError_t launch_outer_test(const double* res, int koff, int32_t* ctl, double* acc, int k, double n3,
+                             double tol_abs, double tol_rel, hipStream_t s) {
+  hipLaunchKernelGGL(k_outer_test, dim3(1), dim3(64), 0, s, res, koff, ctl, acc, k, n3, tol_abs, tol_rel);
   return hipGetLastError();
 }
 
@@ -641,9 +684,9 @@ hipError_t launch_dots(const DotArgs& a, int blocks, hipStream_t s) {
 }
 
 hipError_t launch_axpy2(double* y, const double* x, double2* yc, const double2* xc, double beta,
-                        int64_t nreal, int64_t ncplx, hipStream_t s) {
+                        int64_t nreal, int64_t ncplx, hipStream_t s, const int32_t* stop) {
   const int64_t n = nreal > ncplx ? nreal : ncplx;
-  hipLaunchKernelGGL(k_axpy2, dim3(nblk(n)), dim3(kBlock), 0, s, y, x, yc, xc, beta, nreal, ncplx);
+  hipLaunchKernelGGL(k_axpy2, dim3(nblk(n)), dim3(kBlock), 0, s, y, x, yc, xc, beta, nreal, ncplx, stop);
   return hipGetLastError();
 }
 
