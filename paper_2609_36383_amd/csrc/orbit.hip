@@ -567,12 +567,13 @@ struct SegIter {
 
 // ---- wave-wide reduce-scatter (all 64 lanes active)
 //
-// The deposit of a wave whose particles share a stencil is summed across the wave
-// before it reaches LDS: NP2 values per lane (NP2 = 16 or 32) are reduced so that
-// every lane ends with the wave total of one value.  Exchange partners per step:
-// lane ^ 32 and lane ^ 16 (gfx950 permlane swaps), lane ^ 8 (row rotation by 8),
-// lane ^ 7 (half-row mirror), lane ^ 2 and lane ^ 1 (quad permutations).  The six
-// masks span all 64 lanes, so each total covers the whole wave.
+// The deposit of a wave is summed across the wave before it reaches LDS: NP2 values
+// per lane (NP2 = 16, 32 or 64) are reduced so that every lane ends with the wave total
+// of one value.  Exchange partners per step: lane ^ 32 and lane ^ 16 (gfx950 permlane
+// swaps), lane ^ 8 (row rotation by 8), lane ^ 7 (half-row mirror), lane ^ 2 and
+// lane ^ 1 (quad permutations).  The six masks span all 64 lanes, so each total covers
+// the whole wave.  Each step halves the values a lane holds; once a lane holds one
+// value, the remaining steps add the partner's copy instead.
 __device__ __forceinline__ uint64_t as_u64(double x) { return (uint64_t)__double_as_longlong(x); }
 __device__ __forceinline__ double as_f64(uint32_t lo, uint32_t hi) {
   return __longlong_as_double((long long)(((uint64_t)hi << 32) | (uint64_t)lo));
@@ -623,91 +624,150 @@ __device__ __forceinline__ void dpp_step(double* v, bool up) {
 // Reduce-scatter of v[NP2]; returns the wave total of value wave_slot<NP2>(lane).
 template <int NP2>
 __device__ __forceinline__ double wave_reduce_scatter(double* v, int lane) {
-  constexpr int H1 = NP2 / 2, H2 = NP2 / 4, H3 = NP2 / 8, H4 = NP2 / 16;
+  static_assert(NP2 == 16 || NP2 == 32 || NP2 == 64, "NP2");
+  constexpr int H1 = NP2 / 2, H2 = NP2 / 4, H3 = NP2 / 8, H4 = NP2 / 16, H5 = NP2 / 32, H6 = NP2 / 64;
 #pragma unroll
   for (int j = 0; j < H1; ++j) v[j] = swap_sum<false>(v[j], v[j + H1]);
 #pragma unroll
   for (int j = 0; j < H2; ++j) v[j] = swap_sum<true>(v[j], v[j + H2]);
   dpp_step<H3, kDppRor8>(v, (lane & 8) != 0);
   dpp_step<H4, kDppHalfMirror>(v, (lane & 4) != 0);
-  if (NP2 == 32) {
-    dpp_step<1, kDppXor2>(v, (lane & 2) != 0);
+  if constexpr (H5 > 0) {
+    dpp_step<H5, kDppXor2>(v, (lane & 2) != 0);
   } else {
     v[0] += dpp_f64<kDppXor2>(v[0]);
   }
-  v[0] += dpp_f64<kDppXor1>(v[0]);
+  if constexpr (H6 > 0) {
+    dpp_step<H6, kDppXor1>(v, (lane & 1) != 0);
+  } else {
+    v[0] += dpp_f64<kDppXor1>(v[0]);
+  }
   return v[0];
 }
-// value index a lane holds after wave_reduce_scatter; owner() picks one copy of each
+// value index a lane holds after wave_reduce_scatter (lane bit b stands for the half
+// NP2 / 2^(6-b) kept at its step); owner() picks one copy of each
 template <int NP2>
 __device__ __forceinline__ int wave_slot(int lane) {
   const int b5 = (lane >> 5) & 1, b4 = (lane >> 4) & 1, b3 = (lane >> 3) & 1, b2 = (lane >> 2) & 1;
+  if (NP2 == 64) return lane;
   return NP2 == 32 ? 16 * b5 + 8 * b4 + 4 * b3 + 2 * b2 + ((lane >> 1) & 1) : 8 * b5 + 4 * b4 + 2 * b3 + b2;
 }
 template <int NP2>
 __device__ __forceinline__ bool wave_owner(int lane) {
-  return NP2 == 32 ? (lane & 1) == 0 : (lane & 3) == 0;
+  return NP2 == 64 ? true : (NP2 == 32 ? (lane & 1) == 0 : (lane & 3) == 0);
 }
 
-constexpr int kMaxGroups = 4;  // stencil groups summed per wave and plane; the rest add per lane
-
-// Current deposit of one stencil row (three x-nodes) into the LDS tile.  Lanes whose
-// segment uses the same stencil are summed across the wave first (one group per
-// distinct stencil base, leader = lowest pending lane), so each tile node receives
-// one atomic per group instead of one per lane.  S holds the lane's integrated
-// weights of the row's nodes.
-template <int D, class R>
-__device__ __forceinline__ void deposit_row_tile(const Tile& t, const int jn[3], int cy, int cz, const R S[3],
-                                                 const double coef[3], bool in, int lane) {
+// Current deposit of one segment into the LDS tile.  S[row][c] holds the lane's
+// integrated weights of its stencil (row = cy + 3 cz, node c along x).
+//
+// The lanes whose stencil lies in the tile share a window of four nodes per axis
+// anchored one node below the wave's lowest stencil base b, so a lane whose base is b
+// or b + 1 on every axis covers its whole stencil with it.  Those lanes place
+// q v_out S / dV into the window (shifted by their offset from b); a reduce-scatter
+// over the wave then leaves each window value on one lane, which adds it to the tile.
+// In 2D and 3D the window is 4 x 4 nodes in x and y, taken one z-plane at a time and
+// reduced two y-rows (24 values) at a time.  Lanes whose base lies further out add
+// their values one by one.
+template <int D, class R, int NR>
+__device__ __forceinline__ void deposit_window(const Tile& t, const int jn[3], const R (&S)[NR][3],
+                                               const double coef[3], bool in, int lane) {
   HIP_DYNAMIC_SHARED(double, s_dyn);
   double* s_J = s_dyn + t.joff;
-  constexpr int NV = 9, NP2 = 16;
-  uint64_t pend = __ballot(in);
-#pragma unroll 1
-  for (int r = 0; pend != 0; ++r) {
-    if (r == kMaxGroups) {
-      // many distinct stencils in this wave: the remaining lanes add one by one
-      if ((pend >> lane) & 1) {
-        const int g0 = (jn[0] - 1 - t.o[0]) + t.E[0] * ((D > 1 ? jn[1] + cy - 1 - t.o[1] : 0) +
-                                                        t.E[1] * (D > 2 ? jn[2] + cz - 1 - t.o[2] : 0));
+  if (__ballot(in) == 0) return;
+  int b[3] = {0, 0, 0}, o[3] = {0, 0, 0};
+  bool win = in;
 #pragma unroll
-        for (int c = 0; c < 3; ++c)
+  for (int l = 0; l < D; ++l) {
+    int m = in ? jn[l] : INT_MAX;
 #pragma unroll
-          for (int k = 0; k < 3; ++k) atomicAdd(s_J + k * t.nodes + g0 + c, coef[k] * (double)S[c]);
+    for (int off = 32; off > 0; off >>= 1) m = min(m, __shfl_xor(m, off, 64));
+    b[l] = uni(m);
+    o[l] = jn[l] - b[l];
+    win = win && o[l] <= 1;
+  }
+  if (in && !win) {
+#pragma unroll
+    for (int row = 0; row < NR; ++row) {
+      const int cy = D > 1 ? row % 3 : 0, cz = D > 2 ? row / 3 : 0;
+      const int g0 = (jn[0] - 1 - t.o[0]) + t.E[0] * ((D > 1 ? jn[1] + cy - 1 - t.o[1] : 0) +
+                                                      t.E[1] * (D > 2 ? jn[2] + cz - 1 - t.o[2] : 0));
+#pragma unroll
+      for (int c = 0; c < 3; ++c)
+#pragma unroll
+        for (int k = 0; k < 3; ++k) atomicAdd(s_J + k * t.nodes + g0 + c, coef[k] * (double)S[row][c]);
+    }
+  }
+  // window rows per reduction: two in 2D and 3D (24 values), the single row in 1D
+  constexpr int NY = D > 1 ? 4 : 1, HR = D > 1 ? 2 : 1, NN = 4 * HR, NV = 3 * NN, NP2 = D == 1 ? 16 : 32;
+  constexpr int NZ = D > 2 ? 4 : 1;
+  const double cf[3] = {win ? coef[0] : 0.0, win ? coef[1] : 0.0, win ? coef[2] : 0.0};
+  const bool sx = o[0] != 0, sy = o[1] != 0;
+#pragma unroll
+  for (int zp = 0; zp < NZ; ++zp) {
+    // the lane's stencil plane for window plane zp (zero when it has none there)
+    R P[3][3];
+#pragma unroll
+    for (int cy = 0; cy < 3; ++cy)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        if (D == 3) {
+          const int cz = zp - o[2];
+          P[cy][c] = cz == 0 ? S[cy % NR][c] : (cz == 1 ? S[(3 + cy) % NR][c] : (cz == 2 ? S[(6 + cy) % NR][c] : R(0)));
+        } else if (D == 2) {
+          P[cy][c] = S[cy % NR][c];
+        } else {
+          P[cy][c] = cy == 0 ? S[0][c] : R(0);
+        }
       }
-      break;
+    // shift along x, then along y, into the window
+    R Wx[3][4];
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+      Wx[r][0] = sx ? R(0) : P[r][0];
+      Wx[r][1] = sx ? P[r][0] : P[r][1];
+      Wx[r][2] = sx ? P[r][1] : P[r][2];
+      Wx[r][3] = sx ? P[r][2] : R(0);
     }
-    const int leader = __builtin_ctzll(pend);
-    int kj[3] = {0, 0, 0};
-    bool mine = in;
+    R W[NY][4];
 #pragma unroll
-    for (int l = 0; l < D; ++l) {
-      kj[l] = __builtin_amdgcn_readlane(jn[l], leader);
-      mine = mine && jn[l] == kj[l];
+    for (int x = 0; x < 4; ++x) {
+      if (D > 1) {
+        W[0][x] = sy ? R(0) : Wx[0][x];
+        W[1 % NY][x] = sy ? Wx[0][x] : Wx[1][x];
+        W[2 % NY][x] = sy ? Wx[1][x] : Wx[2][x];
+        W[3 % NY][x] = sy ? Wx[2][x] : R(0);
+      } else {
+        W[0][x] = Wx[0][x];
+      }
     }
-    const uint64_t grp = __ballot(mine);
-    double v[NP2];
 #pragma unroll
-    for (int k = 0; k < 3; ++k)
+    for (int hy = 0; hy < NY / HR; ++hy) {
+      double v[NP2];
 #pragma unroll
-      for (int c = 0; c < 3; ++c) v[k * 3 + c] = mine ? coef[k] * (double)S[c] : 0.0;
+      for (int k = 0; k < 3; ++k)
 #pragma unroll
-    for (int j = NV; j < NP2; ++j) v[j] = 0.0;
-    const double tot = wave_reduce_scatter<NP2>(v, lane);
-    const int idx = wave_slot<NP2>(lane);
-    if (wave_owner<NP2>(lane) && idx < NV && tot != 0.0) {
-      const int k = idx / 3, c = idx - 3 * k;
-      const int g = (kj[0] + c - 1 - t.o[0]) + t.E[0] * ((D > 1 ? kj[1] + cy - 1 - t.o[1] : 0) +
-                                                         t.E[1] * (D > 2 ? kj[2] + cz - 1 - t.o[2] : 0));
-      atomicAdd(s_J + k * t.nodes + g, tot);
+        for (int nd = 0; nd < NN; ++nd) v[k * NN + nd] = cf[k] * (double)W[hy * HR + nd / 4][nd % 4];
+#pragma unroll
+      for (int j = NV; j < NP2; ++j) v[j] = 0.0;
+      const double tot = wave_reduce_scatter<NP2>(v, lane);
+      const int idx = wave_slot<NP2>(lane);
+      if (wave_owner<NP2>(lane) && idx < NV && tot != 0.0) {
+        const int k = idx / NN, nd = idx - k * NN;
+        const int gx = b[0] - 1 + (nd % 4) - t.o[0];
+        const int gy = D > 1 ? b[1] - 1 + hy * HR + nd / 4 - t.o[1] : 0;
+        const int gz = D > 2 ? b[2] - 1 + zp - t.o[2] : 0;
+        // a nonzero total comes from stencils inside the tile; the test is a guard
+        if (gx >= 0 && gx < t.E[0] && gy >= 0 && gy < t.E[1] && gz >= 0 && gz < t.E[2])
+          atomicAdd(s_J + k * t.nodes + gx + t.E[0] * (gy + t.E[1] * gz), tot);
+      }
     }
-    pend &= ~grp;
   }
 }
 
 // Deposit phase of the pass, run by every lane of the workgroup: the lanes whose
 // particle converged walk the segments of their accepted orbit (v_in) in lockstep;
-// per segment and stencil row they gather U-bar and deposit J_g += q v_out S-bar_g / dV.
+// per segment they take the integrated weights of every stencil row, gather U-bar and
+// deposit J_g += q v_out S-bar_g / dV into the tile through the window deposit.
 // Stencils outside the tile read and add through global memory per lane.
 template <int D, int NGL, class R>
 __device__ void deposit_phase(const OrbitArgs& a, const Tile& t, const R* gx, const R* gw, const int j0[3],
@@ -728,10 +788,12 @@ __device__ void deposit_phase(const OrbitArgs& a, const Tile& t, const R* gx, co
     const bool in = has && inside<D>(t, jn);
     const R len = sb - sa;  // zero for lanes without a segment: all weights vanish
     constexpr int NROW = D == 1 ? 1 : (D == 2 ? 3 : 9);
-#pragma unroll 1
+    R Sr[NROW][3];
+#pragma unroll
     for (int row = 0; row < NROW; ++row) {
       const int cy = D > 1 ? row % 3 : 0, cz = D > 2 ? row / 3 : 0;
-      R S[3] = {R(0), R(0), R(0)};
+      R* S = Sr[row];
+      S[0] = S[1] = S[2] = R(0);
       const int nq = GL<NGL>::n(a.ngl);
 #pragma unroll
       for (int q = 0; q < nq; ++q) {
@@ -766,8 +828,8 @@ __device__ void deposit_phase(const OrbitArgs& a, const Tile& t, const R* gx, co
           }
         }
       }
-      if (do_dep && t.ok) deposit_row_tile<D, R>(t, jn, cy, cz, S, coef, in, lane);
     }
+    if (do_dep && t.ok) deposit_window<D, R, NROW>(t, jn, Sr, coef, in, lane);
   }
 }
 
