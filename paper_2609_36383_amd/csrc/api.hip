@@ -209,7 +209,10 @@ size_t carve(gmhc_ctx* c, char* base, int64_t np) {
   c->scan_tmp_bytes = sort_scan_tmp_bytes(Ng);
   c->scan_tmp = cv.take<char>(c->scan_tmp_bytes);
   c->max_blocks = std::max<int64_t>((np + kOrbitBlock - 1) / kOrbitBlock, 1024);
-  c->partials = cv.take<double>((size_t)(c->max_blocks + 1024) * 8);
+  // orbit partials, then residual / diagnostic partials: at most one block per axis-0
+  // line (the residual folded into the last FFT pass) or 1024
+  const int64_t res_cap = std::max<int64_t>(1024, c->M.Ng / c->M.n[0]);
+  c->partials = cv.take<double>((size_t)(c->max_blocks + res_cap) * 8);
   c->dres = cv.take<double>(64);
   c->ddot = cv.take<double>(kMaxDots);
   c->dctl = cv.take<int32_t>(4);
@@ -451,8 +454,10 @@ int32_t gmhc_create(const gmhc_config* cfg, gmhc_ctx** out) {
     M.n[l] = r ? c.n[l] : 1;
     M.lo[l] = r ? c.lo[l] : 0.0;
     M.len[l] = r ? c.len[l] : 1.0;
+    M.ln[l] = ilog2(M.n[l]);
     M.h[l] = M.len[l] / M.n[l];
     M.inv_h[l] = 1.0 / M.h[l];
+    M.kf[l] = r ? 2.0 * M_PI / M.len[l] : 0.0;
     M.Ng *= M.n[l];
     if (r) M.dV *= M.h[l];
   }
@@ -528,6 +533,7 @@ int32_t gmhc_bind(gmhc_ctx* ctx, int64_t n_particles, void* dev_workspace, size_
     ax.N = N;
     ax.logN = ilog2(N);
     ax.stride = stride;
+    ax.lstride = ilog2((int)stride);
     ax.nlines = ctx->M.Ng / N;
     ax.T = std::max(1, 4096 / N);
     if (ax.T > ax.nlines) ax.T = (int)ax.nlines;
@@ -690,11 +696,9 @@ int32_t enqueue_outer(gmhc_ctx* ctx, int cur, int hs, int part, const int32_t* s
     ca.rho1 = ctx->S1 + 2 * Ng;
     ca.A1 = ctx->S1 + 3 * Ng;
     ca.U1 = ctx->S1 + 6 * Ng;
-    ca.out = ctx->cout;
     ca.stop = stop;
-    HIPCK(launch_cn(ca, s));
-    HIPCK(fft_nd(M, ctx->axes, d + 6, nullptr, ctx->cout, nullptr, ctx->trial, ctx->cout, true, false, s, stop));
-    HIPCK(launch_zero(ctx->Jdep, 3 * Ng, s, stop));
+    // CN solve, trial fields in real space, deposit buffer cleared
+    HIPCK(field_trial(M, ctx->axes, ca, ctx->trial, ctx->cout, ctx->Jdep, s));
   }
   if (part == OUTER_ALL || part == OUTER_ORBIT) {
     const bool timed = ctx->cfg.timing && part == OUTER_ORBIT;
@@ -705,28 +709,28 @@ int32_t enqueue_outer(gmhc_ctx* ctx, int cur, int hs, int part, const int32_t* s
     if (timed) HIPCK(hipEventRecord(e1, s));
   }
   if (part == OUTER_ALL || part == OUTER_POST) {
-    HIPCK(launch_reduce(ctx->partials, orbit_blocks(ctx), 1, ctx->max_blocks, kOrbitParts, 1u << OP_ITMAX,
-                        ctx->dres, s, stop));
-    // H(j) = P J_orb in spectral and real space
-    HIPCK(fft_nd(M, ctx->axes, 3, ctx->Jdep, nullptr, ctx->jh[hs], nullptr, nullptr, false,
-                 ctx->cfg.project_nyquist != 0, s, stop));
-    HIPCK(fft_nd(M, ctx->axes, 3, nullptr, ctx->jh[hs], nullptr, ctx->jr[hs], ctx->cscr, true, false, s, stop));
+    // H(j) = P J_orb in spectral and real space, with the residual partials
     ResidualArgs ra{};
     ra.M = M;
     ra.tol_abs = ctx->cfg.tol_outer_abs;
     ra.tol_rel = ctx->cfg.tol_outer_rel;
-    ra.H = ctx->jr[hs];
     ra.j = ctx->jr[cur];
     ra.gphi = ctx->trial;
     ra.Uh = ctx->trial + (int64_t)(d + 3) * Ng;
     ra.partials = ctx->partials + (size_t)ctx->max_blocks * 8;  // disjoint from orbit partials
     ra.stop = stop;
-    const int rb = res_blocks(ctx);
-    HIPCK(launch_residual(ra, rb, s));
-    HIPCK(launch_reduce(ra.partials, rb, kResParts, 1, kResParts, 1u << 3, ctx->dres + kResOff, s, stop));
+    int rb = 0;
+    HIPCK(field_h(M, ctx->axes, ctx->Jdep, ctx->jh[hs], ctx->cscr, ctx->jr[hs], ctx->cfg.project_nyquist != 0, ra,
+                  &rb, s));
+    // pass and residual sums, then (device control) the outer test
+    const ReduceSet ro{ctx->partials, orbit_blocks(ctx), 1, ctx->max_blocks, kOrbitParts, 1u << OP_ITMAX, ctx->dres};
+    const ReduceSet rr{ra.partials, rb, kResParts, 1, kResParts, 1u << 3, ctx->dres + kResOff};
+    OuterTest ot{};
+    if (stop)
+      ot = OuterTest{ctx->dres, kResOff, ctx->dctl, ctx->dacc, k, 3.0 * (double)Ng, ctx->cfg.tol_outer_abs,
+                     ctx->cfg.tol_outer_rel};
+    HIPCK(launch_reduce_outer(ro, rr, ot, s, stop));
     if (stop) {
-      HIPCK(launch_outer_test(ctx->dres, kResOff, ctx->dctl, ctx->dacc, k, 3.0 * (double)Ng, ctx->cfg.tol_outer_abs,
-                              ctx->cfg.tol_outer_rel, s));
       if (ctx->cfg.beta != 1.0)
         HIPCK(launch_axpy2(ctx->jr[hs], ctx->jr[cur], ctx->jh[hs], ctx->jh[cur], 1.0 - ctx->cfg.beta, 3 * Ng,
                            3 * Ng, s, stop));

@@ -43,12 +43,14 @@ __device__ __forceinline__ void st_bulk(void* p, int64_t i, double v, int prec) 
 // Mesh geometry in the form the kernels use.
 struct Mesh {
   int d;
-  int n[3];
+  int n[3];          // powers of two (1 on unused axes)
+  int ln[3];         // log2 n
   int64_t Ng;
   double lo[3];
   double len[3];
   double h[3];
   double inv_h[3];
+  double kf[3];      // 2 pi / len (wavenumber of mode 1; 0 on unused axes)
   double dV;
 };
 
@@ -90,7 +92,8 @@ hipError_t launch_orbit(const OrbitArgs& a, int ngl, hipStream_t s);
 struct FftPlanAxis {
   int N;
   int logN;
-  int64_t stride;   // element stride of the axis
+  int64_t stride;   // element stride of the axis (a power of two)
+  int lstride;      // log2 stride
   int64_t nlines;   // Ng / N
   int T;            // lines per workgroup (a power of two)
   int lds_tw;       // 1: twiddles staged in LDS after the lines, 0: read from tw
@@ -114,10 +117,8 @@ struct CNArgs {
   const double2* U;      // [3][Ng]
   double2* phi1; double2* psi1; double2* rho1;
   double2* A1; double2* U1;
-  double2* out;          // [d+6][Ng]: i k phi^{n+1/2} (d), A^{n+1} (3), U^{n+1/2} (3)
   const int32_t* stop;   // optional device flag: nonzero = skip (outer iteration done)
 };
-hipError_t launch_cn(const CNArgs& a, hipStream_t s);
 
 struct ResidualArgs {
   Mesh M;
@@ -129,22 +130,59 @@ struct ResidualArgs {
   double* partials;      // [blocks][kResParts]
   const int32_t* stop;   // optional device flag: nonzero = skip
 };
-hipError_t launch_residual(const ResidualArgs& a, int blocks, hipStream_t s);
 
 // out[v] = reduce over blocks b of partials[b * bstride + v * vstride]; max_mask bit v
 // set = max, else sum.
 hipError_t launch_reduce(const double* partials, int nblocks, int64_t bstride, int64_t vstride, int nvals,
                          uint32_t max_mask, double* out, hipStream_t s, const int32_t* stop = nullptr);
 
-// Device-side outer test of a Picard iteration (one thread): reads the pass results
-// res[0..7] and residual sums res[kOff..], accumulates the step report in acc and, when
-// the mixed tests pass or an inner solve failed, sets ctl[0] (stop) and records the
-// iteration k.  ctl: [0] stop, [1] failed, [2] iteration that stopped.
-// acc: [0] evaluations, [1] segments, [2] inner max, [3] iterations, [4] failed count,
-// [5] rms ratio, [6] max ratio, [7] sum |R_A|^2, [8] particle work, [9] mesh work,
-// [10] evaluations of the last iteration.
-hipError_t launch_outer_test(const double* res, int koff, int32_t* ctl, double* acc, int k, double n3,
-                             double tol_abs, double tol_rel, hipStream_t s);
+// Trial fields of the outer iteration: the Crank-Nicolson solve at the trial current
+// (cn.jh; cn.out is unused) computed while loading the first inverse-FFT pass, the new
+// state stored to cn.rho1 .. cn.U1, and the real trial fields [d+6][Ng] written to trial
+// (i k phi^{n+1/2} (d), A^{n+1} (3), U^{n+1/2} (3)) through the complex scratch work;
+// zero[3 Ng] is cleared on the way (may be null).  Skipped when *cn.stop is set.
+hipError_t field_trial(const Mesh& M, const FftPlanAxis* axes, const CNArgs& cn, double* trial, double2* work,
+                       double* zero, hipStream_t s);
+
+// H = P J of the deposited current J [3][Ng]: the (Nyquist-projected when project)
+// spectrum to spec [3][Ng] and the real field to H [3][Ng] through the complex scratch
+// work, with the residual partials of ra (ra.H is H) written to ra.partials; their
+// block count goes to *res_blocks.  The residual is folded into the last FFT pass when
+// three components of an axis-0 line fit a workgroup.  Skipped when *ra.stop is set.
+hipError_t field_h(const Mesh& M, const FftPlanAxis* axes, const double* J, double2* spec, double2* work, double* H,
+                   bool project, const ResidualArgs& ra, int* res_blocks, hipStream_t s);
+
+// Partials of one reduction: out[v] = reduce over blocks b of p[b * bstride + v * vstride]
+// for v < nvals; max_mask bit v set = max, else sum.
+struct ReduceSet {
+  const double* p;
+  int nblocks;
+  int64_t bstride, vstride;
+  int nvals;
+  uint32_t max_mask;
+  double* out;
+};
+
+// Device-side outer test of Picard iteration k (ctl == nullptr: none): reads the pass
+// results res[0..7] and residual sums res[koff..], accumulates the step report in acc and,
+// when the mixed tests pass or an inner solve failed, sets ctl[0] (stop) and records the
+// iteration k.  ctl: [0] stop, [1] failed, [2] iteration that stopped, [3] ticket
+// counter (zero between launches).  acc: [0] evaluations, [1] segments, [2] inner max,
+// [3] iterations, [4] failed count, [5] rms ratio, [6] max ratio, [7] sum |R_A|^2,
+// [8] particle work, [9] mesh work, [10] evaluations of the last iteration.
+struct OuterTest {
+  const double* res;
+  int koff;
+  int32_t* ctl;
+  double* acc;
+  int k;
+  double n3, tol_abs, tol_rel;
+};
+
+// Reductions a and b in one launch; with t.ctl, the last workgroup then runs the outer
+// test on their results.  Skipped when *stop is set.
+hipError_t launch_reduce_outer(const ReduceSet& a, const ReduceSet& b, const OuterTest& t, hipStream_t s,
+                               const int32_t* stop);
 
 // y = a x + b z over n values (z may be null).
 hipError_t launch_axpbz(double* y, double a, const double* x, double b, const double* z, int64_t n,

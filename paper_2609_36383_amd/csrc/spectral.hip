@@ -28,13 +28,14 @@ __device__ __forceinline__ double ksym(const Mesh& M, int l, int64_t m) {
   if (l >= M.d) return 0.0;
   if ((n & 1) == 0 && m == n / 2) return 0.0;
   const int64_t ms = (m <= n / 2) ? m : m - n;
-  return 2.0 * M_PI * (double)ms / M.len[l];
+  return M.kf[l] * (double)ms;
 }
 
+// per-axis mode index of node g (mesh sizes are powers of two)
 __device__ __forceinline__ void mode_index(const Mesh& M, int64_t g, int64_t idx[3]) {
-  idx[0] = g % M.n[0];
-  idx[1] = (g / M.n[0]) % M.n[1];
-  idx[2] = g / ((int64_t)M.n[0] * M.n[1]);
+  idx[0] = g & (M.n[0] - 1);
+  idx[1] = (g >> M.ln[0]) & (M.n[1] - 1);
+  idx[2] = g >> (M.ln[0] + M.ln[1]);
 }
 
 __device__ __forceinline__ bool on_nyquist(const Mesh& M, const int64_t idx[3]) {
@@ -43,135 +44,53 @@ __device__ __forceinline__ bool on_nyquist(const Mesh& M, const int64_t idx[3]) 
   return r;
 }
 
-// One axis pass of a batched complex FFT.  A workgroup loads T lines of length N
-// into LDS in bit-reversed order, runs log2 N radix-2 butterfly stages and writes
-// the lines back.  blockIdx.y selects the component.
-template <bool IN_REAL, bool OUT_REAL>
-__global__ __launch_bounds__(kBlock) void k_fft_axis(const double* src_r, const double2* src_c,
-                                                     double2* dst_c, double* dst_r, int64_t Ng,
-                                                     FftPlanAxis ax, int inverse, int project,
-                                                     Mesh M, const int32_t* stop) {
-  if (stop && *stop) return;
-  extern __shared__ double2 lds[];
-  const int N = ax.N, T = ax.T, logN = ax.logN;  // N and T are powers of two
-  const int logT = 31 - __clz(T);
-  const int64_t comp = blockIdx.y;
-  const int64_t line0 = (int64_t)blockIdx.x * T;
-  const int64_t total = (int64_t)T * N;
-  const int shift = 32 - logN;
-  // twiddles exp(-2 pi i m / N), m < N/2, staged once after the T lines when they fit
-  double2* twl = lds + (int64_t)T * N;
-  if (ax.lds_tw)
-    for (int m = threadIdx.x; m < N / 2; m += blockDim.x) twl[m] = ax.tw[m];
-  const double2* tws = ax.lds_tw ? twl : ax.tw;
-  for (int64_t e = threadIdx.x; e < total; e += blockDim.x) {
-    int lt, k;
-    if (ax.stride == 1) {
-      lt = (int)(e >> logN);
-      k = (int)(e & (N - 1));
-    } else {
-      lt = (int)(e & (T - 1));
-      k = (int)(e >> logT);
-    }
-    const int64_t line = line0 + lt;
-    double2 v = make_double2(0.0, 0.0);
-    if (line < ax.nlines) {
-      const int64_t iin = line % ax.stride, iout = line / ax.stride;
-      const int64_t addr = comp * Ng + iin + ax.stride * ((int64_t)k + (int64_t)N * iout);
-      if (IN_REAL)
-        v = make_double2(src_r[addr], 0.0);
-      else
-        v = src_c[addr];
-    }
-    const int rk = (N > 1) ? (int)(__brev((unsigned)k) >> shift) : 0;
-    lds[lt * N + rk] = v;
-  }
-  __syncthreads();
-  for (int st = 1; st <= logN; ++st) {
-    const int half = 1 << (st - 1);
-    const int twstep = N >> st;
-    for (int b = threadIdx.x; b < T * (N / 2); b += blockDim.x) {
-      const int lt = b >> (logN - 1), j = b & (N / 2 - 1);
-      const int grp = j >> (st - 1), pos = j & (half - 1);
-      const int i1 = lt * N + grp * (2 * half) + pos, i2 = i1 + half;
-      double2 w = tws[pos * twstep];
-      if (inverse) w.y = -w.y;
-      const double2 u = lds[i1];
-      const double2 t = cmul(lds[i2], w);
-      lds[i1] = cadd(u, t);
-      lds[i2] = csub(u, t);
-    }
-    __syncthreads();
-  }
-  const double sc = inverse ? 1.0 / (double)N : 1.0;
-  for (int64_t e = threadIdx.x; e < total; e += blockDim.x) {
-    int lt, k;
-    if (ax.stride == 1) {
-      lt = (int)(e >> logN);
-      k = (int)(e & (N - 1));
-    } else {
-      lt = (int)(e & (T - 1));
-      k = (int)(e >> logT);
-    }
-    const int64_t line = line0 + lt;
-    if (line >= ax.nlines) continue;
-    const int64_t iin = line % ax.stride, iout = line / ax.stride;
-    const int64_t g = iin + ax.stride * ((int64_t)k + (int64_t)N * iout);
-    double2 v = cscale(lds[lt * N + k], sc);
-    if (project) {
-      int64_t idx[3];
-      mode_index(M, g, idx);
-      if (on_nyquist(M, idx)) v = make_double2(0.0, 0.0);
-    }
-    if (OUT_REAL)
-      dst_r[comp * Ng + g] = v.x;
-    else
-      dst_c[comp * Ng + g] = v;
-  }
-}
-
-__global__ __launch_bounds__(kBlock) void k_cn(CNArgs a) {
-  if (a.stop && *a.stop) return;
-  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+// Crank-Nicolson solve of mode g at the trial current: returns component `comp` of the
+// trial-field spectrum [d+6]: i k phi^{n+1/2} (d), A^{n+1} (3), U^{n+1/2} (3).  With
+// `side`, the new state the component belongs to is stored as well (rho, phi, psi with
+// component 0; A and U of axis c with component d + c).
+__device__ __forceinline__ double2 cn_point(const CNArgs& a, int64_t g, int comp, bool side) {
   const Mesh& M = a.M;
-  if (g >= M.Ng) return;
+  const int64_t Ng = M.Ng;
+  const int d = M.d;
   int64_t idx[3];
   mode_index(M, g, idx);
   const double k[3] = {ksym(M, 0, idx[0]), ksym(M, 1, idx[1]), ksym(M, 2, idx[2])};
-  const int64_t Ng = M.Ng;
-  const double2 j0 = a.jh[g], j1 = a.jh[Ng + g], j2 = a.jh[2 * Ng + g];
-  // continuity: rho^{n+1} = rho^n - dt div_h J^{n+1/2}
-  double2 divj = cadd(cadd(cik(k[0], j0), cik(k[1], j1)), cik(k[2], j2));
   const double h = a.dt;
-  const double2 rho0 = a.rho[g];
-  const double2 rho1 = csub(rho0, cscale(divj, h));
-  const double2 rhoh = cscale(cadd(rho0, rho1), 0.5);
   const double av = a.kappa2 * (k[0] * k[0] + k[1] * k[1] + k[2] * k[2]);
   const double q4 = 0.25 * h * h * av;
   const double inv_den = 1.0 / (1.0 + q4);
   const double c1 = 1.0 - q4;
-  const double src1 = 0.5 * h * h * a.kappa2 * a.sigma1;
-  const double src2 = 0.5 * h * h * a.kappa2 * a.sigma2;
-  // (phi, psi): phi^{n+1} from the CN pair with psi eliminated
-  const double2 ph0 = a.phi[g], ps0 = a.psi[g];
-  const double2 ph1 = cscale(cadd(cadd(cscale(ph0, c1), cscale(ps0, h)), cscale(rhoh, src1)), inv_den);
-  const double2 ps1 = csub(cscale(csub(ph1, ph0), 2.0 / h), ps0);
-  a.rho1[g] = rho1;
-  a.phi1[g] = ph1;
-  a.psi1[g] = ps1;
-  const double2 phh = cscale(cadd(ph0, ph1), 0.5);
-  int o = 0;
-  for (int l = 0; l < M.d; ++l) a.out[(int64_t)(o++) * Ng + g] = cik(k[l], phh);
-  const double2 jj[3] = {j0, j1, j2};
-  for (int c = 0; c < 3; ++c) {
-    const double2 A0 = a.A[c * Ng + g], U0 = a.U[c * Ng + g];
-    const double2 A1 = cscale(cadd(cadd(cscale(A0, c1), cscale(U0, h)), cscale(jj[c], src2)), inv_den);
-    const double2 U1 = csub(cscale(csub(A1, A0), 2.0 / h), U0);
-    a.A1[c * Ng + g] = A1;
-    a.U1[c * Ng + g] = U1;
-    a.out[(int64_t)(M.d + c) * Ng + g] = A1;
-    a.out[(int64_t)(M.d + 3 + c) * Ng + g] = cscale(cadd(U0, U1), 0.5);
+  if (comp < d) {
+    const double2 j0 = a.jh[g], j1 = a.jh[Ng + g], j2 = a.jh[2 * Ng + g];
+    // continuity: rho^{n+1} = rho^n - dt div_h J^{n+1/2}
+    const double2 divj = cadd(cadd(cik(k[0], j0), cik(k[1], j1)), cik(k[2], j2));
+    const double2 rho0 = a.rho[g];
+    const double2 rho1 = csub(rho0, cscale(divj, h));
+    const double2 rhoh = cscale(cadd(rho0, rho1), 0.5);
+    const double src1 = 0.5 * h * h * a.kappa2 * a.sigma1;
+    // (phi, psi): phi^{n+1} from the CN pair with psi eliminated
+    const double2 ph0 = a.phi[g], ps0 = a.psi[g];
+    const double2 ph1 = cscale(cadd(cadd(cscale(ph0, c1), cscale(ps0, h)), cscale(rhoh, src1)), inv_den);
+    if (side && comp == 0) {
+      a.rho1[g] = rho1;
+      a.phi1[g] = ph1;
+      a.psi1[g] = csub(cscale(csub(ph1, ph0), 2.0 / h), ps0);
+    }
+    return cik(k[comp], cscale(cadd(ph0, ph1), 0.5));
   }
+  const int c = (comp - d) % 3;
+  const double src2 = 0.5 * h * h * a.kappa2 * a.sigma2;
+  const double2 A0 = a.A[c * Ng + g], U0 = a.U[c * Ng + g], jc = a.jh[c * Ng + g];
+  const double2 A1 = cscale(cadd(cadd(cscale(A0, c1), cscale(U0, h)), cscale(jc, src2)), inv_den);
+  if (comp < d + 3) {
+    if (side) {
+      a.A1[c * Ng + g] = A1;
+      a.U1[c * Ng + g] = csub(cscale(csub(A1, A0), 2.0 / h), U0);
+    }
+    return A1;
+  }
+  const double2 U1 = csub(cscale(csub(A1, A0), 2.0 / h), U0);
+  return cscale(cadd(U0, U1), 0.5);
 }
 
 template <int NV>
@@ -197,8 +116,30 @@ __device__ __forceinline__ void block_store(double (&part)[NV], uint32_t max_mas
   }
 }
 
-// Outer residual r = H(j) - j: sums of |r|^2, |H|^2, |j|^2, the max-node test ratio,
-// and the mesh work sum_g H . E^{n+1/2} (E^{n+1/2} = -grad phi^{n+1/2} - U^{n+1/2}).
+// Outer residual r = H(j) - j at node g, folded into part: sums of |r|^2, |H|^2, |j|^2,
+// the max-node test ratio, and the mesh work sum_g H . E^{n+1/2}
+// (E^{n+1/2} = -grad phi^{n+1/2} - U^{n+1/2}).
+__device__ __forceinline__ void residual_node(const ResidualArgs& a, int64_t g, const double H[3],
+                                              double (&part)[kResParts]) {
+  const int64_t Ng = a.M.Ng;
+  double r2 = 0.0, h2 = 0.0, j2 = 0.0, w = 0.0;
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    const double j = a.j[c * Ng + g];
+    const double r = H[c] - j;
+    r2 += r * r;
+    h2 += H[c] * H[c];
+    j2 += j * j;
+    const double gp = (c < a.M.d) ? a.gphi[c * Ng + g] : 0.0;
+    w += H[c] * (-gp - a.Uh[c * Ng + g]);
+  }
+  part[0] += r2;
+  part[1] += h2;
+  part[2] += j2;
+  part[3] = fmax(part[3], sqrt(r2) / (a.tol_abs + 0.5 * a.tol_rel * (sqrt(h2) + sqrt(j2))));
+  part[4] += w;
+}
+
 __global__ __launch_bounds__(kBlock) void k_residual(ResidualArgs a) {
   if (a.stop && *a.stop) return;
   double part[kResParts];
@@ -207,72 +148,263 @@ __global__ __launch_bounds__(kBlock) void k_residual(ResidualArgs a) {
   const int64_t Ng = a.M.Ng;
   for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < Ng;
        g += (int64_t)gridDim.x * blockDim.x) {
-    double r2 = 0.0, h2 = 0.0, j2 = 0.0, w = 0.0;
-    for (int c = 0; c < 3; ++c) {
-      const double H = a.H[c * Ng + g], j = a.j[c * Ng + g];
-      const double r = H - j;
-      r2 += r * r;
-      h2 += H * H;
-      j2 += j * j;
-      const double gp = (c < a.M.d) ? a.gphi[c * Ng + g] : 0.0;
-      w += H * (-gp - a.Uh[c * Ng + g]);
-    }
-    part[0] += r2;
-    part[1] += h2;
-    part[2] += j2;
-    part[3] = fmax(part[3], sqrt(r2) / (a.tol_abs + 0.5 * a.tol_rel * (sqrt(h2) + sqrt(j2))));
-    part[4] += w;
+    const double H[3] = {a.H[g], a.H[Ng + g], a.H[2 * Ng + g]};
+    residual_node(a, g, H, part);
   }
   block_store<kResParts>(part, 1u << 3, a.partials);
 }
 
-__global__ __launch_bounds__(kBlock) void k_reduce(const double* partials, int nblocks, int64_t bstride,
-                                                   int64_t vstride, int nvals, uint32_t max_mask, double* out,
-                                                   const int32_t* stop) {
+// ---- batched line FFTs along one axis
+//
+// A workgroup loads T lines of length N of cpb components into LDS and runs radix-2
+// butterfly stages on them (all lines at once, one barrier per stage).  The first
+// transform is decimation in time (bit-reversed load, natural-order result).  A pass
+// with both transforms (the last forward axis of H = P J) then zeroes the even-grid
+// Nyquist modes, stores the projected spectrum and runs the inverse by decimation in
+// frequency (natural order in, bit-reversed out), so the spectrum is never reordered.
+// The load can compute the Crank-Nicolson solve of the trial current instead of reading
+// (the first inverse pass of the trial fields); the store can zero a deposit buffer and,
+// with the three current components in one workgroup, fold the outer residual.
+struct FftTask {
+  FftPlanAxis ax;
+  int cpb;              // components per workgroup
+  int fwd, inv;         // transforms of the pass (forward first when both)
+  int project;          // zero the even-grid Nyquist modes after the forward transform
+  const double* src_r;  // real input, or
+  const double2* src_c; // complex input (unless the load computes the CN solve)
+  double2* dst_c;       // complex output, or
+  double* dst_r;        // real part of the output
+  double2* spec;        // fwd && inv: the projected spectrum is stored here
+  double* zero;         // zero[c Ng + g] = 0 at the output positions of components c < 3
+  int res;              // fold the outer residual of H = output (cpb == 3)
+  ResidualArgs ra;
+};
+
+__device__ __forceinline__ int brev_n(int k, int logN) {
+  return logN > 0 ? (int)(__brev((unsigned)k) >> (32 - logN)) : 0;
+}
+
+// IN: 0 complex input, 1 real input, 2 CN solve at load
+constexpr int kFftThreads = 1024;  // threads per FFT workgroup at most
+
+template <int IN, bool OUT_REAL>
+__global__ __launch_bounds__(kFftThreads) void k_fft_pass(FftTask t, CNArgs cn, Mesh M, const int32_t* stop) {
   if (stop && *stop) return;
-  // One workgroup per value.  Thread t folds blocks t, t + 256, ... into eight
-  // independent accumulators (so eight loads are in flight), combines them in a fixed
-  // order, then a fixed pairwise tree combines the threads: the result depends only
-  // on nblocks.
-  const int v = blockIdx.x;
-  if (v >= nvals) return;
-  const bool mx = (max_mask >> v) & 1u;
-  const double id = mx ? -INFINITY : 0.0;
-  const double* p = partials + (int64_t)v * vstride;
-  double a8[8];
-#pragma unroll
-  for (int k = 0; k < 8; ++k) a8[k] = id;
-  const int step = (int)blockDim.x;
-  int b = threadIdx.x;
-  for (; b + 7 * step < nblocks; b += 8 * step) {
-#pragma unroll
-    for (int k = 0; k < 8; ++k) {
-      const double x = p[(int64_t)(b + k * step) * bstride];
-      a8[k] = mx ? fmax(a8[k], x) : a8[k] + x;
+  extern __shared__ double2 lds[];
+  const FftPlanAxis& ax = t.ax;
+  const int N = ax.N, T = ax.T, logN = ax.logN;  // N and T are powers of two
+  const int logT = 31 - __clz(T);
+  const int64_t Ng = M.Ng;
+  const int64_t comp0 = (int64_t)blockIdx.y * t.cpb;
+  const int64_t line0 = (int64_t)blockIdx.x * T;
+  const int per = T * N, total = per * t.cpb;
+  // twiddles exp(-2 pi i m / N), m < N/2, staged once after the lines when they fit
+  double2* twl = lds + total;
+  if (ax.lds_tw)
+    for (int m = threadIdx.x; m < N / 2; m += blockDim.x) twl[m] = ax.tw[m];
+  const double2* tws = ax.lds_tw ? twl : ax.tw;
+  // element e -> (component c, line lt, index k), coalesced in the axis' memory order
+  const int logPer = logT + logN;
+  auto split = [&](int e, int& c, int& lt, int& k) {
+    c = e >> logPer;
+    const int r = e & (per - 1);
+    if (ax.stride == 1) {
+      lt = r >> logN;
+      k = r & (N - 1);
+    } else {
+      lt = r & (T - 1);
+      k = r >> logT;
+    }
+  };
+  auto node = [&](int64_t line, int k) {
+    const int64_t iin = line & (ax.stride - 1), iout = line >> ax.lstride;
+    return iin + (((int64_t)k + (iout << logN)) << ax.lstride);
+  };
+  for (int e = threadIdx.x; e < total; e += blockDim.x) {
+    int c, lt, k;
+    split(e, c, lt, k);
+    const int64_t line = line0 + lt;
+    double2 v = make_double2(0.0, 0.0);
+    if (line < ax.nlines) {
+      const int64_t g = node(line, k);
+      const int64_t comp = comp0 + c;
+      if (IN == 2)
+        v = cn_point(cn, g, (int)comp, true);
+      else if (IN == 1)
+        v = make_double2(t.src_r[comp * Ng + g], 0.0);
+      else
+        v = t.src_c[comp * Ng + g];
+    }
+    lds[(c * T + lt) * N + brev_n(k, logN)] = v;
+  }
+  __syncthreads();
+  const int nbf = t.cpb * T * (N / 2);  // butterflies per stage
+  // decimation in time: forward, or the inverse when the pass has no forward transform
+  const bool conj1 = !t.fwd;
+  for (int st = 1; st <= logN; ++st) {
+    const int half = 1 << (st - 1);
+    const int twstep = N >> st;
+    for (int b = threadIdx.x; b < nbf; b += blockDim.x) {
+      const int lt = b >> (logN - 1), j = b & (N / 2 - 1);
+      const int grp = j >> (st - 1), pos = j & (half - 1);
+      const int i1 = lt * N + grp * (2 * half) + pos, i2 = i1 + half;
+      double2 w = tws[pos * twstep];
+      if (conj1) w.y = -w.y;
+      const double2 u = lds[i1];
+      const double2 tt = cmul(lds[i2], w);
+      lds[i1] = cadd(u, tt);
+      lds[i2] = csub(u, tt);
+    }
+    __syncthreads();
+  }
+  const bool both = t.fwd && t.inv;
+  if (both) {
+    for (int e = threadIdx.x; e < total; e += blockDim.x) {
+      int c, lt, k;
+      split(e, c, lt, k);
+      const int64_t line = line0 + lt;
+      if (line >= ax.nlines) continue;
+      const int64_t g = node(line, k);
+      const int li = (c * T + lt) * N + k;
+      double2 v = lds[li];
+      if (t.project) {
+        int64_t idx[3];
+        mode_index(M, g, idx);
+        if (on_nyquist(M, idx)) {
+          v = make_double2(0.0, 0.0);
+          lds[li] = v;
+        }
+      }
+      t.spec[(comp0 + c) * Ng + g] = v;
+    }
+    __syncthreads();
+    // inverse by decimation in frequency
+    for (int st = logN; st >= 1; --st) {
+      const int half = 1 << (st - 1);
+      const int twstep = N >> st;
+      for (int b = threadIdx.x; b < nbf; b += blockDim.x) {
+        const int lt = b >> (logN - 1), j = b & (N / 2 - 1);
+        const int grp = j >> (st - 1), pos = j & (half - 1);
+        const int i1 = lt * N + grp * (2 * half) + pos, i2 = i1 + half;
+        double2 w = tws[pos * twstep];
+        w.y = -w.y;
+        const double2 u = lds[i1], v = lds[i2];
+        lds[i1] = cadd(u, v);
+        lds[i2] = cmul(csub(u, v), w);
+      }
+      __syncthreads();
     }
   }
+  const double sc = t.inv ? 1.0 / (double)N : 1.0;
+  for (int e = threadIdx.x; e < total; e += blockDim.x) {
+    int c, lt, k;
+    split(e, c, lt, k);
+    const int64_t line = line0 + lt;
+    if (line >= ax.nlines) continue;
+    const int64_t g = node(line, k);
+    const int64_t comp = comp0 + c;
+    double2 v = cscale(lds[(c * T + lt) * N + (both ? brev_n(k, logN) : k)], sc);
+    if (t.project && !both) {
+      int64_t idx[3];
+      mode_index(M, g, idx);
+      if (on_nyquist(M, idx)) v = make_double2(0.0, 0.0);
+    }
+    if (OUT_REAL)
+      t.dst_r[comp * Ng + g] = v.x;
+    else
+      t.dst_c[comp * Ng + g] = v;
+    if (t.zero && comp < 3) t.zero[comp * Ng + g] = 0.0;
+  }
+  if (t.res) {
+    // the three components of H at each node of the workgroup's lines
+    double part[kResParts];
 #pragma unroll
-  for (int k = 0; k < 7; ++k) {
-    const int bb = b + k * step;
+    for (int v = 0; v < kResParts; ++v) part[v] = 0.0;
+    for (int e = threadIdx.x; e < per; e += blockDim.x) {
+      int c, lt, k;
+      split(e, c, lt, k);
+      const int64_t line = line0 + lt;
+      if (line >= ax.nlines) continue;
+      const int kk = both ? brev_n(k, logN) : k;
+      const double H[3] = {lds[lt * N + kk].x * sc, lds[(T + lt) * N + kk].x * sc, lds[(2 * T + lt) * N + kk].x * sc};
+      residual_node(t.ra, node(line, k), H, part);
+    }
+    // wave butterflies, then the waves in order; the lines' LDS holds the wave sums
+#pragma unroll
+    for (int v = 0; v < kResParts; ++v)
+      for (int off = 32; off > 0; off >>= 1) {
+        const double o2 = __shfl_xor(part[v], off, 64);
+        part[v] = (v == 3) ? fmax(part[v], o2) : part[v] + o2;
+      }
+    __syncthreads();
+    double* shd = reinterpret_cast<double*>(lds);
+    const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
+    if (lane == 0)
+#pragma unroll
+      for (int v = 0; v < kResParts; ++v) shd[wave * kResParts + v] = part[v];
+    __syncthreads();
+    if ((int)threadIdx.x < kResParts) {
+      const int v = threadIdx.x;
+      double acc = shd[v];
+      for (int w = 1; w < (int)(blockDim.x / 64); ++w)
+        acc = (v == 3) ? fmax(acc, shd[w * kResParts + v]) : acc + shd[w * kResParts + v];
+      t.ra.partials[(int64_t)blockIdx.x * kResParts + v] = acc;
+    }
+  }
+}
+
+// Reduction of one value over nblocks partials p[b * bstride] (max or sum) by a
+// workgroup of NT threads; the result is valid in thread 0.  Thread t folds blocks t,
+// t + NT, ... into sixteen independent accumulators (so sixteen loads are in flight),
+// combines them in a fixed order, then a fixed pairwise tree combines the threads: the
+// result depends only on nblocks and NT.
+template <int NT>
+__device__ double reduce_value(const double* p, int nblocks, int64_t bstride, bool mx) {
+  constexpr int NA = 16;
+  const double id = mx ? -INFINITY : 0.0;
+  double acc16[NA];
+#pragma unroll
+  for (int k = 0; k < NA; ++k) acc16[k] = id;
+  int b = threadIdx.x;
+  for (; b + (NA - 1) * NT < nblocks; b += NA * NT) {
+    double x[NA];
+#pragma unroll
+    for (int k = 0; k < NA; ++k) x[k] = p[(int64_t)(b + k * NT) * bstride];
+#pragma unroll
+    for (int k = 0; k < NA; ++k) acc16[k] = mx ? fmax(acc16[k], x[k]) : acc16[k] + x[k];
+  }
+#pragma unroll
+  for (int k = 0; k < NA - 1; ++k) {
+    const int bb = b + k * NT;
     if (bb < nblocks) {
       const double x = p[(int64_t)bb * bstride];
-      a8[k] = mx ? fmax(a8[k], x) : a8[k] + x;
+      acc16[k] = mx ? fmax(acc16[k], x) : acc16[k] + x;
     }
   }
-  double acc = a8[0];
+  double acc = acc16[0];
 #pragma unroll
-  for (int k = 1; k < 8; ++k) acc = mx ? fmax(acc, a8[k]) : acc + a8[k];
-  __shared__ double sh[kBlock];
+  for (int k = 1; k < NA; ++k) acc = mx ? fmax(acc, acc16[k]) : acc + acc16[k];
+  __shared__ double sh[NT];
   sh[threadIdx.x] = acc;
   __syncthreads();
-  for (int h = kBlock / 2; h > 0; h >>= 1) {
+  for (int h = NT / 2; h > 0; h >>= 1) {
     if ((int)threadIdx.x < h) {
       const double o = sh[threadIdx.x + h];
       sh[threadIdx.x] = mx ? fmax(sh[threadIdx.x], o) : sh[threadIdx.x] + o;
     }
     __syncthreads();
   }
-  if (threadIdx.x == 0) out[v] = sh[0];
+  return sh[0];
+}
+
+__global__ __launch_bounds__(kBlock) void k_reduce(const double* partials, int nblocks, int64_t bstride,
+                                                   int64_t vstride, int nvals, uint32_t max_mask, double* out,
+                                                   const int32_t* stop) {
+  if (stop && *stop) return;
+  const int v = blockIdx.x;  // one workgroup per value
+  if (v >= nvals) return;
+  const double x = reduce_value<kBlock>(partials + (int64_t)v * vstride, nblocks, bstride, (max_mask >> v) & 1u);
+  if (threadIdx.x == 0) out[v] = x;
 }
 
 __global__ __launch_bounds__(kBlock) void k_zero(double* y, int64_t n, const int32_t* stop) {
@@ -281,11 +413,12 @@ __global__ __launch_bounds__(kBlock) void k_zero(double* y, int64_t n, const int
   if (i < n) y[i] = 0.0;
 }
 
-__global__ void k_outer_test(const double* res, int koff, int32_t* ctl, double* acc, int k, double n3,
-                             double tol_abs, double tol_rel) {
-  if (threadIdx.x != 0 || ctl[0]) return;
-  const double* h = res;
-  const double* r = res + koff;
+// Outer test of Picard iteration t.k (one thread; see launch_reduce_outer).
+__device__ void outer_test(const OuterTest& t) {
+  if (t.ctl[0]) return;
+  const double* h = t.res;
+  const double* r = t.res + t.koff;
+  double* acc = t.acc;
   acc[0] += h[OP_ITERS];
   acc[1] += h[OP_SEGS];
   acc[2] = h[OP_ITMAX];
@@ -293,12 +426,12 @@ __global__ void k_outer_test(const double* res, int koff, int32_t* ctl, double* 
   acc[10] = h[OP_ITERS];
   if (h[OP_FAIL] > 0.0) {
     acc[4] = h[OP_FAIL];
-    ctl[1] = 1;
-    ctl[2] = k;
-    ctl[0] = 1;
+    t.ctl[1] = 1;
+    t.ctl[2] = t.k;
+    t.ctl[0] = 1;
     return;
   }
-  const double rr = sqrt(r[0] / n3) / (tol_abs + 0.5 * tol_rel * (sqrt(r[1] / n3) + sqrt(r[2] / n3)));
+  const double rr = sqrt(r[0] / t.n3) / (t.tol_abs + 0.5 * t.tol_rel * (sqrt(r[1] / t.n3) + sqrt(r[2] / t.n3)));
   const double mr = r[3];
   acc[5] = rr;
   acc[6] = mr;
@@ -306,8 +439,36 @@ __global__ void k_outer_test(const double* res, int koff, int32_t* ctl, double* 
     acc[7] = h[OP_RA2];
     acc[8] = h[OP_WORK];
     acc[9] = r[4];
-    ctl[2] = k;
-    ctl[0] = 1;
+    t.ctl[2] = t.k;
+    t.ctl[0] = 1;
+  }
+}
+
+// Both partial sets in one launch, one workgroup per value; the last workgroup to finish
+// (ticket ctl[3], left at zero) runs the outer test.
+constexpr int kRedThreads = 1024;  // threads per workgroup of the merged reduction
+
+__global__ __launch_bounds__(kRedThreads) void k_reduce_outer(ReduceSet a, ReduceSet b, OuterTest t,
+                                                              const int32_t* stop) {
+  if (stop && *stop) return;
+  const bool inb = (int)blockIdx.x >= a.nvals;
+  const ReduceSet& r = inb ? b : a;
+  const int v = inb ? (int)blockIdx.x - a.nvals : (int)blockIdx.x;
+  const double x = reduce_value<kRedThreads>(r.p + (int64_t)v * r.vstride, r.nblocks, r.bstride, (r.max_mask >> v) & 1u);
+  __shared__ int s_last;
+  if (threadIdx.x == 0) {
+    r.out[v] = x;
+    s_last = 0;
+    if (t.ctl) {
+      __threadfence();  // the value is visible before the ticket counts it
+      s_last = atomicAdd(&t.ctl[3], 1) == (int)gridDim.x - 1;
+    }
+  }
+  __syncthreads();
+  if (s_last && threadIdx.x == 0) {
+    __threadfence();  // every other workgroup's value is visible
+    t.ctl[3] = 0;
+    outer_test(t);
   }
 }
 
@@ -598,58 +759,153 @@ hipError_t launch_iota(int32_t* id, int64_t np, hipStream_t s) {
   return hipGetLastError();
 }
 
+namespace {
+
+constexpr int kFftLds = 4096;  // complex values of LDS per FFT workgroup (64 KiB)
+
+// Whether cpb components of one line of this axis fit a workgroup's LDS.
+bool fits(const FftPlanAxis& ax, int cpb) { return (int64_t)cpb * ax.N <= kFftLds; }
+
+// Launch one pass over ncomp components (ncomp a multiple of t.cpb); in: 0 complex,
+// 1 real, 2 CN solve.  The number of workgroups along x goes to *nblk when asked.
+hipError_t fft_pass(const Mesh& M, FftTask t, int ncomp, int in, bool out_real, const CNArgs* cn, hipStream_t s,
+                    const int32_t* stop, int* nblk = nullptr) {
+  FftPlanAxis& ax = t.ax;
+  const int cpb = t.cpb;
+  // lines per workgroup: enough workgroups to cover the chip (>= 512 when the mesh
+  // allows), the lines and the staged twiddles within kFftLds complex values
+  int64_t T = (ax.nlines * (ncomp / cpb)) / 512;
+  T = std::max<int64_t>(1, std::min<int64_t>(T, std::max<int64_t>(1, kFftLds / ((int64_t)ax.N * cpb))));
+  T = std::min<int64_t>(T, ax.nlines);
+  while (T & (T - 1)) T &= T - 1;  // a power of two (nlines is one)
+  while (T > 1 && T * ax.N * cpb + ax.N / 2 > kFftLds) T >>= 1;
+  if (T * ax.N * cpb > kFftLds) return hipErrorInvalidValue;
+  ax.lds_tw = (T * ax.N * cpb + ax.N / 2 <= kFftLds) ? 1 : 0;
+  ax.T = (int)T;
+  // one butterfly per thread and stage, up to kFftThreads
+  const int threads = (int)std::min<int64_t>(kFftThreads, std::max<int64_t>(64, (cpb * T * ax.N / 2 + 63) / 64 * 64));
+  const unsigned gx = (unsigned)((ax.nlines + ax.T - 1) / ax.T);
+  // (at least the residual's wave sums: kFftThreads / 64 waves x kResParts doubles)
+  const size_t lds = std::max<size_t>(sizeof(double) * (kFftThreads / 64) * kResParts,
+                                      sizeof(double2) * ((size_t)cpb * ax.T * ax.N +
+                                                         (ax.lds_tw ? (size_t)std::max(ax.N / 2, 1) : 0)));
+  const dim3 grid(gx, (unsigned)(ncomp / cpb));
+  const CNArgs c0 = cn ? *cn : CNArgs{};
+  if (nblk) *nblk = (int)gx;
+  if (in == 2) {
+    if (out_real)
+      hipLaunchKernelGGL((k_fft_pass<2, true>), grid, dim3(threads), lds, s, t, c0, M, stop);
+    else
+      hipLaunchKernelGGL((k_fft_pass<2, false>), grid, dim3(threads), lds, s, t, c0, M, stop);
+  } else if (in == 1) {
+    if (out_real)
+      hipLaunchKernelGGL((k_fft_pass<1, true>), grid, dim3(threads), lds, s, t, c0, M, stop);
+    else
+      hipLaunchKernelGGL((k_fft_pass<1, false>), grid, dim3(threads), lds, s, t, c0, M, stop);
+  } else {
+    if (out_real)
+      hipLaunchKernelGGL((k_fft_pass<0, true>), grid, dim3(threads), lds, s, t, c0, M, stop);
+    else
+      hipLaunchKernelGGL((k_fft_pass<0, false>), grid, dim3(threads), lds, s, t, c0, M, stop);
+  }
+  return hipGetLastError();
+}
+
+}  // namespace
+
 hipError_t fft_nd(const Mesh& M, const FftPlanAxis* axes, int ncomp, const double* src_r,
                   const double2* src_c, double2* dst_c, double* dst_r, double2* scratch_c,
                   bool inverse, bool project, hipStream_t s, const int32_t* stop) {
   // passes: axis 0 .. d-1 (forward) or the same order (inverse; axes commute)
   double2* work = dst_c ? dst_c : scratch_c;
   for (int l = 0; l < M.d; ++l) {
-    // lines per workgroup: enough workgroups to cover the chip (>= 512 when the mesh
-    // allows), at most 4096 elements (64 KiB of LDS) per workgroup
-    FftPlanAxis ax = axes[l];
-    int64_t T = (ax.nlines * ncomp) / 512;
-    T = std::max<int64_t>(1, std::min<int64_t>(T, std::max(1, 4096 / ax.N)));
-    T = std::min<int64_t>(T, ax.nlines);
-    while (T & (T - 1)) T &= T - 1;  // a power of two (nlines is one)
-    // lines plus staged twiddles within 4096 complex values (64 KiB of LDS)
-    while (T > 1 && T * ax.N + ax.N / 2 > 4096) T >>= 1;
-    ax.lds_tw = (T * ax.N + ax.N / 2 <= 4096) ? 1 : 0;
-    ax.T = (int)T;
-    const int threads = (int)std::min<int64_t>(kBlock, std::max<int64_t>(64, (T * ax.N / 2 + 63) / 64 * 64));
     const bool first = (l == 0), last = (l == M.d - 1);
+    FftTask t{};
+    t.ax = axes[l];
+    t.cpb = 1;
+    t.fwd = inverse ? 0 : 1;
+    t.inv = inverse ? 1 : 0;
+    t.project = (last && project && !inverse) ? 1 : 0;
+    t.src_r = src_r;
+    t.src_c = first ? src_c : work;
+    t.dst_c = work;
+    t.dst_r = dst_r;
     const bool in_real = first && src_r != nullptr;
     const bool out_real = last && dst_r != nullptr;
-    const double2* in_c = first ? src_c : work;
-    const unsigned gx = (unsigned)((ax.nlines + ax.T - 1) / ax.T);
-    const size_t lds = sizeof(double2) * ((size_t)ax.T * ax.N + (ax.lds_tw ? (size_t)std::max(ax.N / 2, 1) : 0));
-    const int proj = (last && project && !inverse) ? 1 : 0;
-    dim3 grid(gx, (unsigned)ncomp);
-    if (in_real && out_real)
-      hipLaunchKernelGGL((k_fft_axis<true, true>), grid, dim3(threads), lds, s, src_r, nullptr, nullptr,
-                         dst_r, M.Ng, ax, inverse ? 1 : 0, proj, M, stop);
-    else if (in_real)
-      hipLaunchKernelGGL((k_fft_axis<true, false>), grid, dim3(threads), lds, s, src_r, nullptr, work,
-                         nullptr, M.Ng, ax, inverse ? 1 : 0, proj, M, stop);
-    else if (out_real)
-      hipLaunchKernelGGL((k_fft_axis<false, true>), grid, dim3(threads), lds, s, nullptr, in_c, nullptr,
-                         dst_r, M.Ng, ax, inverse ? 1 : 0, proj, M, stop);
-    else
-      hipLaunchKernelGGL((k_fft_axis<false, false>), grid, dim3(threads), lds, s, nullptr, in_c, work,
-                         nullptr, M.Ng, ax, inverse ? 1 : 0, proj, M, stop);
-    hipError_t e = hipGetLastError();
+    hipError_t e = fft_pass(M, t, ncomp, in_real ? 1 : 0, out_real, nullptr, s, stop);
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
 }
 
-hipError_t launch_cn(const CNArgs& a, hipStream_t s) {
-  hipLaunchKernelGGL(k_cn, dim3(nblk(a.M.Ng)), dim3(kBlock), 0, s, a);
-  return hipGetLastError();
+hipError_t field_trial(const Mesh& M, const FftPlanAxis* axes, const CNArgs& cn, double* trial, double2* work,
+                       double* zero, hipStream_t s) {
+  const int d = M.d;
+  for (int l = 0; l < d; ++l) {
+    const bool last = (l == d - 1);
+    FftTask t{};
+    t.ax = axes[l];
+    t.cpb = 1;
+    t.inv = 1;
+    t.src_c = work;
+    t.dst_c = work;
+    t.dst_r = trial;
+    t.zero = last ? zero : nullptr;
+    hipError_t e = fft_pass(M, t, d + 6, l == 0 ? 2 : 0, last, &cn, s, cn.stop);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
-hipError_t launch_residual(const ResidualArgs& a, int blocks, hipStream_t s) {
-  hipLaunchKernelGGL(k_residual, dim3(blocks), dim3(kBlock), 0, s, a);
-  return hipGetLastError();
+hipError_t field_h(const Mesh& M, const FftPlanAxis* axes, const double* J, double2* spec, double2* work, double* H,
+                   bool project, const ResidualArgs& ra, int* res_blocks, hipStream_t s) {
+  const int d = M.d;
+  const int32_t* stop = ra.stop;
+  const bool fuse_res = fits(axes[0], 3);
+  // forward passes of axes 0 .. d-2
+  for (int l = 0; l < d - 1; ++l) {
+    FftTask t{};
+    t.ax = axes[l];
+    t.cpb = 1;
+    t.fwd = 1;
+    t.src_r = J;
+    t.src_c = work;
+    t.dst_c = work;
+    hipError_t e = fft_pass(M, t, 3, l == 0 ? 1 : 0, false, nullptr, s, stop);
+    if (e != hipSuccess) return e;
+  }
+  // axis d-1: forward, projected spectrum out, then its inverse; then the inverse passes
+  // of axes d-2 .. 0.  The last pass (axis 0) writes H and folds the residual.
+  for (int l = d - 1; l >= 0; --l) {
+    const bool top = (l == d - 1), last = (l == 0);
+    FftTask t{};
+    t.ax = axes[l];
+    t.fwd = top ? 1 : 0;
+    t.inv = 1;
+    t.project = (top && project) ? 1 : 0;
+    t.cpb = (last && fuse_res) ? 3 : 1;
+    t.res = (last && fuse_res) ? 1 : 0;
+    t.src_r = J;
+    t.src_c = work;
+    t.dst_c = work;
+    t.dst_r = H;
+    t.spec = spec;
+    t.ra = ra;
+    t.ra.H = H;
+    int nb = 0;
+    hipError_t e = fft_pass(M, t, 3, (top && d == 1) ? 1 : 0, last, nullptr, s, stop, &nb);
+    if (e != hipSuccess) return e;
+    if (t.res) *res_blocks = nb;
+  }
+  if (!fuse_res) {
+    ResidualArgs r = ra;
+    r.H = H;
+    const int rb = (int)std::min<int64_t>((M.Ng + kBlock - 1) / kBlock, 1024);
+    hipLaunchKernelGGL(k_residual, dim3(rb), dim3(kBlock), 0, s, r);
+    *res_blocks = rb;
+    return hipGetLastError();
+  }
+  return hipSuccess;
 }
 
 hipError_t launch_reduce(const double* partials, int nblocks, int64_t bstride, int64_t vstride, int nvals,
@@ -665,9 +921,9 @@ hipError_t launch_zero(double* y, int64_t n, hipStream_t s, const int32_t* stop)
   return hipGetLastError();
 }
 
-hipError_t launch_outer_test(const double* res, int koff, int32_t* ctl, double* acc, int k, double n3,
-                             double tol_abs, double tol_rel, hipStream_t s) {
-  hipLaunchKernelGGL(k_outer_test, dim3(1), dim3(64), 0, s, res, koff, ctl, acc, k, n3, tol_abs, tol_rel);
+hipError_t launch_reduce_outer(const ReduceSet& a, const ReduceSet& b, const OuterTest& t, hipStream_t s,
+                               const int32_t* stop) {
+  hipLaunchKernelGGL(k_reduce_outer, dim3((unsigned)(a.nvals + b.nvals)), dim3(kRedThreads), 0, s, a, b, t, stop);
   return hipGetLastError();
 }
 
