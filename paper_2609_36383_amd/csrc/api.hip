@@ -38,6 +38,7 @@ struct gmhc_ctx {
   void* q2 = nullptr;
   void* vb[3] = {};     // accepted orbit-velocity iterate (warm start)
   void* vw[3] = {};     // working iterate of the current step / last frozen pass
+  bool vin_first = false;  // the next orbit pass starts from vb (first pass of a step)
   double* pscr[3] = {}; // FP64 staging for loads and read-outs
   int32_t* id = nullptr;
   int32_t* id2 = nullptr;
@@ -268,6 +269,7 @@ OrbitArgs orbit_args(gmhc_ctx* c, int iterate) {
   a.xn = c->x2[0];
   a.P = c->P[0];
   a.Pn = c->P2[0];
+  a.vin = c->vin_first ? c->vb[0] : c->vw[0];
   a.v = c->vw[0];
   a.trial = c->trial;
   a.An = c->An;
@@ -706,6 +708,7 @@ int32_t enqueue_outer(gmhc_ctx* ctx, int cur, int hs, int part, const int32_t* s
     OrbitArgs oa = orbit_args(ctx, 1);
     oa.stop = stop;
     HIPCK(launch_orbit(oa, ctx->ngl, s));
+    ctx->vin_first = false;  // later passes of the step start from their predecessor's v_out
     if (timed) HIPCK(hipEventRecord(e1, s));
   }
   if (part == OUTER_ALL || part == OUTER_POST) {
@@ -748,7 +751,8 @@ int32_t enqueue_outer(gmhc_ctx* ctx, int cur, int hs, int part, const int32_t* s
 int32_t outer_graph(gmhc_ctx* ctx, int cur, int hs, int part, hipGraphExec_t* ex) {
   *ex = nullptr;
   std::vector<uintptr_t> key = {(uintptr_t)cur, (uintptr_t)hs, (uintptr_t)part,
-                                (uintptr_t)ctx->S0, (uintptr_t)ctx->S1, (uintptr_t)ctx->q};
+                                (uintptr_t)ctx->S0, (uintptr_t)ctx->S1, (uintptr_t)ctx->q,
+                                (uintptr_t)(ctx->vin_first ? ctx->vb[0] : ctx->vw[0])};
   for (int l = 0; l < 3; ++l) {
     key.push_back((uintptr_t)ctx->x[l]);
     key.push_back((uintptr_t)ctx->x2[l]);
@@ -815,6 +819,7 @@ int32_t run_outer(gmhc_ctx* ctx, int cur, int hs, bool& use_graph, int32_t& repl
           HIPCK(hipGraphLaunch(ex[k], s));
         }
       }
+      ctx->vin_first = false;  // the iteration's orbit pass has run
       replays += 1;
       return GMHC_OK;
     }
@@ -870,9 +875,9 @@ int32_t commit_outer(gmhc_ctx* ctx, int cur, double rr, double mr, double ra2, d
   hipStream_t s = ctx->stream;
   std::swap(ctx->S0, ctx->S1);
   HIPCK(hipMemcpyAsync(ctx->An, ctx->trial + (int64_t)d * Ng, sizeof(double) * 3 * Ng, hipMemcpyDeviceToDevice, s));
-  if (cur != 0) {
-    HIPCK(hipMemcpyAsync(ctx->jr[0], ctx->jr[cur], sizeof(double) * 3 * Ng, hipMemcpyDeviceToDevice, s));
-    HIPCK(hipMemcpyAsync(ctx->jh[0], ctx->jh[cur], sizeof(double2) * 3 * Ng, hipMemcpyDeviceToDevice, s));
+  if (cur != 0) {  // the accepted current becomes slot 0
+    std::swap(ctx->jr[0], ctx->jr[cur]);
+    std::swap(ctx->jh[0], ctx->jh[cur]);
   }
   for (int l = 0; l < d; ++l) std::swap(ctx->x[l], ctx->x2[l]);
   for (int l = 0; l < 3; ++l) {
@@ -1112,8 +1117,7 @@ int32_t gmhc_step(gmhc_ctx* ctx, gmhc_step_report* rep) {
     int32_t st = sort_particles(ctx);
     if (st) return done(st);
   }
-  for (int l = 0; l < 3; ++l)
-    if (np) HIPCK(hipMemcpyAsync(ctx->vw[l], ctx->vb[l], ctx->es * np, hipMemcpyDeviceToDevice, s));
+  ctx->vin_first = true;  // the first orbit pass reads the accepted v from vb
   bool use_graph = ctx->cfg.graphs != 0 && ctx->stream != nullptr && !ctx->graphs_off;
   if (ctx->cfg.outer_scheme == 1) return done(step_anderson(ctx, R, use_graph));
   // damped Picard: j <- j + beta (H(j) - j); the outer test runs on the device unless
@@ -1337,6 +1341,7 @@ int32_t gmhc_orbit_pass_frozen(gmhc_ctx* ctx, int32_t iterate, gmhc_pass_report*
   hipStream_t s = ctx->stream;
   for (int l = 0; l < 3; ++l)
     if (np) HIPCK(hipMemcpyAsync(ctx->vw[l], ctx->vb[l], ctx->es * np, hipMemcpyDeviceToDevice, s));
+  ctx->vin_first = false;
   int32_t st = run_orbit(ctx, iterate ? 1 : 0, nullptr);
   if (st) return st;
   double oms = 0.0;

@@ -72,7 +72,8 @@ struct OrbitArgs {
   const double* x;       // [d]
   const void* P;         // [3]
   const void* q;         // [1]
-  void* v;               // [3] in: v_in warm start; out: v_out of the final evaluation
+  const void* vin;       // [3] v_in warm start (may be v itself)
+  void* v;               // [3] out: v_out of the final evaluation
   double* xn;            // [d] out: wrapped x^n + dt v_in
   void* Pn;              // [3] out: P^{n+1}
   int32_t* iters;        // out: inner evaluations

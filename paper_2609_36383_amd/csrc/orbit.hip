@@ -889,6 +889,7 @@ __attribute__((amdgpu_waves_per_eu(orbit_waves<D, R>()))) void k_orbit(OrbitArgs
   constexpr int NF = nfields<D>();
   const R* Pp = static_cast<const R*>(a.P);
   const R* qp = static_cast<const R*>(a.q);
+  const R* vinp = static_cast<const R*>(a.vin);
   R* vp = static_cast<R*>(a.v);
   R* Pnp = static_cast<R*>(a.Pn);
 
@@ -915,7 +916,7 @@ __attribute__((amdgpu_waves_per_eu(orbit_waves<D, R>()))) void k_orbit(OrbitArgs
     qv = qp[i];
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-      vin0[c] = vp[c * ps + i];
+      vin0[c] = vinp[c * ps + i];
       P0[c] = Pp[c * ps + i];
     }
   }
