@@ -604,6 +604,57 @@ __device__ __forceinline__ double dpp_f64(double x) {
   const uint32_t hi = (uint32_t)__builtin_amdgcn_mov_dpp((int)(uint32_t)(u >> 32), CTRL, 0xF, 0xF, false);
   return as_f64(lo, hi);
 }
+// ---- wave-wide reductions through DPP row shifts (no LDS): an inclusive scan within each
+// row of 16 lanes (shifts by 1, 2, 4 and 8; lanes without a source take the identity),
+// then the four row results are read from lanes 15, 31, 47 and 63 and combined in order.
+// All 64 lanes must be active; the result is wave-uniform.
+constexpr int kDppShr1 = 0x111, kDppShr2 = 0x112, kDppShr4 = 0x114, kDppShr8 = 0x118;
+
+template <int CTRL>
+__device__ __forceinline__ int dpp_i32(int id, int v) {
+  return __builtin_amdgcn_update_dpp(id, v, CTRL, 0xF, 0xF, false);
+}
+__device__ __forceinline__ int wave_min_i32(int v) {
+  v = min(v, dpp_i32<kDppShr1>(INT_MAX, v));
+  v = min(v, dpp_i32<kDppShr2>(INT_MAX, v));
+  v = min(v, dpp_i32<kDppShr4>(INT_MAX, v));
+  v = min(v, dpp_i32<kDppShr8>(INT_MAX, v));
+  return min(min(__builtin_amdgcn_readlane(v, 15), __builtin_amdgcn_readlane(v, 31)),
+             min(__builtin_amdgcn_readlane(v, 47), __builtin_amdgcn_readlane(v, 63)));
+}
+__device__ __forceinline__ int wave_max_i32(int v) {
+  v = max(v, dpp_i32<kDppShr1>(INT_MIN, v));
+  v = max(v, dpp_i32<kDppShr2>(INT_MIN, v));
+  v = max(v, dpp_i32<kDppShr4>(INT_MIN, v));
+  v = max(v, dpp_i32<kDppShr8>(INT_MIN, v));
+  return max(max(__builtin_amdgcn_readlane(v, 15), __builtin_amdgcn_readlane(v, 31)),
+             max(__builtin_amdgcn_readlane(v, 47), __builtin_amdgcn_readlane(v, 63)));
+}
+// the source lane's x, or id where there is none
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64_id(double id, double x) {
+  const uint64_t u = as_u64(x), e = as_u64(id);
+  const uint32_t lo = (uint32_t)dpp_i32<CTRL>((int)(uint32_t)e, (int)(uint32_t)u);
+  const uint32_t hi = (uint32_t)dpp_i32<CTRL>((int)(uint32_t)(e >> 32), (int)(uint32_t)(u >> 32));
+  return as_f64(lo, hi);
+}
+__device__ __forceinline__ double readlane_f64(double x, int l) {
+  const uint64_t u = as_u64(x);
+  return as_f64((uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)u, l),
+                (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(u >> 32), l));
+}
+// wave sum (MAX = false) or maximum (MAX = true) of x
+template <bool MAX>
+__device__ __forceinline__ double wave_reduce_f64(double x) {
+  const double id = MAX ? -INFINITY : 0.0;
+  auto op = [](double a, double b) { return MAX ? fmax(a, b) : a + b; };
+  x = op(x, dpp_f64_id<kDppShr1>(id, x));
+  x = op(x, dpp_f64_id<kDppShr2>(id, x));
+  x = op(x, dpp_f64_id<kDppShr4>(id, x));
+  x = op(x, dpp_f64_id<kDppShr8>(id, x));
+  return op(op(readlane_f64(x, 15), readlane_f64(x, 31)), op(readlane_f64(x, 47), readlane_f64(x, 63)));
+}
+
 constexpr int kDppRor8 = 0x128;        // row_ror:8  -> lane ^ 8
 constexpr int kDppHalfMirror = 0x141;  // row_half_mirror -> lane ^ 7
 constexpr int kDppXor2 = 0x4E;         // quad_perm [2,3,0,1]
@@ -657,53 +708,41 @@ __device__ __forceinline__ bool wave_owner(int lane) {
   return NP2 == 64 ? true : (NP2 == 32 ? (lane & 1) == 0 : (lane & 3) == 0);
 }
 
-// Current deposit of one segment into the LDS tile.  S[row][c] holds the lane's
-// integrated weights of its stencil (row = cy + 3 cz, node c along x).
-//
-// The lanes whose stencil lies in the tile share a window of four nodes per axis
-// anchored one node below the wave's lowest stencil base b, so a lane whose base is b
-// or b + 1 on every axis covers its whole stencil with it.  Those lanes place
-// q v_out S / dV into the window (shifted by their offset from b); a reduce-scatter
-// over the wave then leaves each window value on one lane, which adds it to the tile.
-// In 2D and 3D the window is 4 x 4 nodes in x and y, taken one z-plane at a time and
-// reduced two y-rows (24 values) at a time.  Lanes whose base lies further out add
-// their values one by one.
-template <int D, class R, int NR>
-__device__ __forceinline__ void deposit_window(const Tile& t, const int jn[3], const R (&S)[NR][3],
-                                               const double coef[3], bool in, int lane) {
-  HIP_DYNAMIC_SHARED(double, s_dyn);
-  double* s_J = s_dyn + t.joff;
-  if (__ballot(in) == 0) return;
-  int b[3] = {0, 0, 0}, o[3] = {0, 0, 0};
-  bool win = in;
+// Rows Y0 .. Y0+NR-1 of a window WX nodes wide: the lanes' values cf[k] W[y][x] are summed
+// over the wave by one reduce-scatter, and each total is added to its tile node by the lane
+// holding it (window node (x, y) is tile node b - 1 + (x, y, zp)).
+template <int D, int WX, int Y0, int NR, class R>
+__device__ __forceinline__ void window_rows(const Tile& t, const R (&W)[4][4], const double cf[3], const int b[3],
+                                            int zp, int lane, double* s_J) {
+  constexpr int NN = WX * NR, NV = 3 * NN, NP2 = NV <= 16 ? 16 : 32;
+  double v[NP2];
 #pragma unroll
-  for (int l = 0; l < D; ++l) {
-    int m = in ? jn[l] : INT_MAX;
+  for (int k = 0; k < 3; ++k)
 #pragma unroll
-    for (int off = 32; off > 0; off >>= 1) m = min(m, __shfl_xor(m, off, 64));
-    b[l] = uni(m);
-    o[l] = jn[l] - b[l];
-    win = win && o[l] <= 1;
+    for (int nd = 0; nd < NN; ++nd) v[k * NN + nd] = cf[k] * (double)W[Y0 + nd / WX][nd % WX];
+#pragma unroll
+  for (int j = NV; j < NP2; ++j) v[j] = 0.0;
+  const double tot = wave_reduce_scatter<NP2>(v, lane);
+  const int idx = wave_slot<NP2>(lane);
+  if (wave_owner<NP2>(lane) && idx < NV && tot != 0.0) {
+    const int k = idx / NN, nd = idx - k * NN;
+    const int gx = b[0] - 1 + (nd % WX) - t.o[0];
+    const int gy = D > 1 ? b[1] - 1 + Y0 + nd / WX - t.o[1] : 0;
+    const int gz = D > 2 ? b[2] - 1 + zp - t.o[2] : 0;
+    // a nonzero total comes from stencils inside the tile; the test is a guard
+    if (gx >= 0 && gx < t.E[0] && gy >= 0 && gy < t.E[1] && gz >= 0 && gz < t.E[2])
+      atomicAdd(s_J + k * t.nodes + gx + t.E[0] * (gy + t.E[1] * gz), tot);
   }
-  if (in && !win) {
-#pragma unroll
-    for (int row = 0; row < NR; ++row) {
-      const int cy = D > 1 ? row % 3 : 0, cz = D > 2 ? row / 3 : 0;
-      const int g0 = (jn[0] - 1 - t.o[0]) + t.E[0] * ((D > 1 ? jn[1] + cy - 1 - t.o[1] : 0) +
-                                                      t.E[1] * (D > 2 ? jn[2] + cz - 1 - t.o[2] : 0));
-#pragma unroll
-      for (int c = 0; c < 3; ++c)
-#pragma unroll
-        for (int k = 0; k < 3; ++k) atomicAdd(s_J + k * t.nodes + g0 + c, coef[k] * (double)S[row][c]);
-    }
-  }
-  // window rows per reduction: two in 2D and 3D (24 values), the single row in 1D
-  constexpr int NY = D > 1 ? 4 : 1, HR = D > 1 ? 2 : 1, NN = 4 * HR, NV = 3 * NN, NP2 = D == 1 ? 16 : 32;
-  constexpr int NZ = D > 2 ? 4 : 1;
-  const double cf[3] = {win ? coef[0] : 0.0, win ? coef[1] : 0.0, win ? coef[2] : 0.0};
-  const bool sx = o[0] != 0, sy = o[1] != 0;
-#pragma unroll
-  for (int zp = 0; zp < NZ; ++zp) {
+}
+
+// Window deposit with a window of WX x WY nodes per z-plane (WX, WY = 3 when no lane's
+// base sits one node above b on that axis, else 4) and nz z-planes.
+template <int D, class R, int NR, int WX, int WY>
+__device__ void window_deposit(const Tile& t, const R (&S)[NR][3], const int o[3], const int b[3], const double cf[3],
+                               int nz, int lane, double* s_J) {
+  const bool sx = WX == 4 && o[0] != 0, sy = WY == 4 && o[1] != 0;
+#pragma unroll 1
+  for (int zp = 0; zp < nz; ++zp) {
     // the lane's stencil plane for window plane zp (zero when it has none there)
     R P[3][3];
 #pragma unroll
@@ -723,44 +762,100 @@ __device__ __forceinline__ void deposit_window(const Tile& t, const int jn[3], c
     R Wx[3][4];
 #pragma unroll
     for (int r = 0; r < 3; ++r) {
-      Wx[r][0] = sx ? R(0) : P[r][0];
-      Wx[r][1] = sx ? P[r][0] : P[r][1];
-      Wx[r][2] = sx ? P[r][1] : P[r][2];
-      Wx[r][3] = sx ? P[r][2] : R(0);
+      if (WX == 4) {
+        Wx[r][0] = sx ? R(0) : P[r][0];
+        Wx[r][1] = sx ? P[r][0] : P[r][1];
+        Wx[r][2] = sx ? P[r][1] : P[r][2];
+        Wx[r][3] = sx ? P[r][2] : R(0);
+      } else {
+        Wx[r][0] = P[r][0];
+        Wx[r][1] = P[r][1];
+        Wx[r][2] = P[r][2];
+        Wx[r][3] = R(0);
+      }
     }
-    R W[NY][4];
+    R W[4][4];
 #pragma unroll
     for (int x = 0; x < 4; ++x) {
-      if (D > 1) {
+      if (WY == 4) {
         W[0][x] = sy ? R(0) : Wx[0][x];
-        W[1 % NY][x] = sy ? Wx[0][x] : Wx[1][x];
-        W[2 % NY][x] = sy ? Wx[1][x] : Wx[2][x];
-        W[3 % NY][x] = sy ? Wx[2][x] : R(0);
+        W[1][x] = sy ? Wx[0][x] : Wx[1][x];
+        W[2][x] = sy ? Wx[1][x] : Wx[2][x];
+        W[3][x] = sy ? Wx[2][x] : R(0);
       } else {
         W[0][x] = Wx[0][x];
+        W[1][x] = Wx[1][x];
+        W[2][x] = Wx[2][x];
+        W[3][x] = R(0);
       }
     }
-#pragma unroll
-    for (int hy = 0; hy < NY / HR; ++hy) {
-      double v[NP2];
-#pragma unroll
-      for (int k = 0; k < 3; ++k)
-#pragma unroll
-        for (int nd = 0; nd < NN; ++nd) v[k * NN + nd] = cf[k] * (double)W[hy * HR + nd / 4][nd % 4];
-#pragma unroll
-      for (int j = NV; j < NP2; ++j) v[j] = 0.0;
-      const double tot = wave_reduce_scatter<NP2>(v, lane);
-      const int idx = wave_slot<NP2>(lane);
-      if (wave_owner<NP2>(lane) && idx < NV && tot != 0.0) {
-        const int k = idx / NN, nd = idx - k * NN;
-        const int gx = b[0] - 1 + (nd % 4) - t.o[0];
-        const int gy = D > 1 ? b[1] - 1 + hy * HR + nd / 4 - t.o[1] : 0;
-        const int gz = D > 2 ? b[2] - 1 + zp - t.o[2] : 0;
-        // a nonzero total comes from stencils inside the tile; the test is a guard
-        if (gx >= 0 && gx < t.E[0] && gy >= 0 && gy < t.E[1] && gz >= 0 && gz < t.E[2])
-          atomicAdd(s_J + k * t.nodes + gx + t.E[0] * (gy + t.E[1] * gz), tot);
-      }
+    // reduce-scatters of at most 32 values: two or three rows at a time
+    if (D == 1) {
+      window_rows<D, WX, 0, 1>(t, W, cf, b, zp, lane, s_J);
+    } else if (WX == 4) {
+      window_rows<D, 4, 0, 2>(t, W, cf, b, zp, lane, s_J);
+      if (WY == 4)
+        window_rows<D, 4, 2, 2>(t, W, cf, b, zp, lane, s_J);
+      else
+        window_rows<D, 4, 2, 1>(t, W, cf, b, zp, lane, s_J);
+    } else {
+      window_rows<D, 3, 0, 3>(t, W, cf, b, zp, lane, s_J);
+      if (WY == 4) window_rows<D, 3, 3, 1>(t, W, cf, b, zp, lane, s_J);
     }
+  }
+}
+
+// Current deposit of one segment into the LDS tile.  S[row][c] holds the lane's
+// integrated weights of its stencil (row = cy + 3 cz, node c along x).
+//
+// The lanes whose stencil lies in the tile share a window anchored one node below the
+// wave's lowest stencil base b: three nodes per axis when every such lane has its base at
+// b, four when some have it at b + 1; a lane whose base lies further out on some axis
+// adds its values one by one.  The window lanes place q v_out S / dV into the window
+// (shifted by their offset from b); reduce-scatters over the wave then leave each window
+// value on one lane, which adds it to the tile.  In 2D and 3D the window is taken one
+// z-plane at a time, two or three y-rows (at most 32 values) per reduction.
+template <int D, class R, int NR>
+__device__ __forceinline__ void deposit_window(const Tile& t, const int jn[3], const R (&S)[NR][3],
+                                               const double coef[3], bool in, int lane) {
+  HIP_DYNAMIC_SHARED(double, s_dyn);
+  double* s_J = s_dyn + t.joff;
+  if (__ballot(in) == 0) return;
+  int b[3] = {0, 0, 0}, o[3] = {0, 0, 0};
+  bool win = in;
+#pragma unroll
+  for (int l = 0; l < D; ++l) {
+    b[l] = wave_min_i32(in ? jn[l] : INT_MAX);
+    o[l] = jn[l] - b[l];
+    win = win && o[l] <= 1;
+  }
+  if (in && !win) {
+#pragma unroll
+    for (int row = 0; row < NR; ++row) {
+      const int cy = D > 1 ? row % 3 : 0, cz = D > 2 ? row / 3 : 0;
+      const int g0 = (jn[0] - 1 - t.o[0]) + t.E[0] * ((D > 1 ? jn[1] + cy - 1 - t.o[1] : 0) +
+                                                      t.E[1] * (D > 2 ? jn[2] + cz - 1 - t.o[2] : 0));
+#pragma unroll
+      for (int c = 0; c < 3; ++c)
+#pragma unroll
+        for (int k = 0; k < 3; ++k) atomicAdd(s_J + k * t.nodes + g0 + c, coef[k] * (double)S[row][c]);
+    }
+  }
+  const double cf[3] = {win ? coef[0] : 0.0, win ? coef[1] : 0.0, win ? coef[2] : 0.0};
+  // window extent: wave-uniform choices
+  const bool wx4 = uni(__ballot(win && o[0] != 0) != 0 ? 1 : 0) != 0;
+  const bool wy4 = D > 1 && uni(__ballot(win && o[1] != 0) != 0 ? 1 : 0) != 0;
+  const int nz = D > 2 ? (uni(__ballot(win && o[2] != 0) != 0 ? 1 : 0) ? 4 : 3) : 1;
+  if (wx4) {
+    if (wy4)
+      window_deposit<D, R, NR, 4, 4>(t, S, o, b, cf, nz, lane, s_J);
+    else
+      window_deposit<D, R, NR, 4, 3>(t, S, o, b, cf, nz, lane, s_J);
+  } else {
+    if (wy4)
+      window_deposit<D, R, NR, 3, 4>(t, S, o, b, cf, nz, lane, s_J);
+    else
+      window_deposit<D, R, NR, 3, 3>(t, S, o, b, cf, nz, lane, s_J);
   }
 }
 
@@ -833,33 +928,14 @@ __device__ void deposit_phase(const OrbitArgs& a, const Tile& t, const R* gx, co
   }
 }
 
-// Block-wide min / max of D ints per thread (all threads participate).
+// Workgroup-wide (one wave) min / max of D ints per thread (all threads participate).
 template <int D>
-__device__ __forceinline__ void block_minmax(int lo[3], int hi[3], int* sh) {
-#pragma unroll
-  for (int l = 0; l < D; ++l)
-    for (int off = 32; off > 0; off >>= 1) {
-      lo[l] = min(lo[l], __shfl_xor(lo[l], off, 64));
-      hi[l] = max(hi[l], __shfl_xor(hi[l], off, 64));
-    }
-  const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
-  const int nw = blockDim.x / 64;
-  __syncthreads();
-  if (lane == 0)
-#pragma unroll
-    for (int l = 0; l < D; ++l) {
-      sh[(2 * l) * nw + wave] = lo[l];
-      sh[(2 * l + 1) * nw + wave] = hi[l];
-    }
-  __syncthreads();
+__device__ __forceinline__ void block_minmax(int lo[3], int hi[3]) {
+  static_assert(kOrbitBlock == 64, "the orbit workgroup is one wave");
 #pragma unroll
   for (int l = 0; l < D; ++l) {
-    lo[l] = sh[2 * l * nw];
-    hi[l] = sh[(2 * l + 1) * nw];
-    for (int w = 1; w < nw; ++w) {
-      lo[l] = min(lo[l], sh[2 * l * nw + w]);
-      hi[l] = max(hi[l], sh[(2 * l + 1) * nw + w]);
-    }
+    lo[l] = wave_min_i32(lo[l]);
+    hi[l] = wave_max_i32(hi[l]);
   }
 }
 
@@ -885,7 +961,6 @@ __attribute__((amdgpu_waves_per_eu(orbit_waves<D, R>()))) void k_orbit(OrbitArgs
   const Mesh& M = a.M;
   const int64_t ps = a.ps;
   HIP_DYNAMIC_SHARED(double, s_dyn);
-  __shared__ int s_mm[2 * 3 * (kOrbitBlock / 64)];
   constexpr int NF = nfields<D>();
   const R* Pp = static_cast<const R*>(a.P);
   const R* qp = static_cast<const R*>(a.q);
@@ -936,7 +1011,7 @@ __attribute__((amdgpu_waves_per_eu(orbit_waves<D, R>()))) void k_orbit(OrbitArgs
     lo[l] = valid ? j0[l] : INT_MAX;
     hi[l] = valid ? j0[l] : INT_MIN;
   }
-  block_minmax<D>(lo, hi, s_mm);
+  block_minmax<D>(lo, hi);
   int shift = 0;
 #pragma unroll
   for (int l = 0; l < D; ++l)
@@ -948,7 +1023,7 @@ __attribute__((amdgpu_waves_per_eu(orbit_waves<D, R>()))) void k_orbit(OrbitArgs
       lo[l] = valid ? j0[l] : INT_MAX;
       hi[l] = valid ? j0[l] : INT_MIN;
     }
-    block_minmax<D>(lo, hi, s_mm);
+    block_minmax<D>(lo, hi);
   }
   // The box covers every particle's node and the node of its orbit endpoint under the
   // warm-start velocity, plus the stencil reach.  Later inner iterates move the orbit
@@ -963,7 +1038,7 @@ __attribute__((amdgpu_waves_per_eu(orbit_waves<D, R>()))) void k_orbit(OrbitArgs
       lo[l] = valid ? min(j0[l], je) : INT_MAX;
       hi[l] = valid ? max(j0[l], je) : INT_MIN;
     }
-    block_minmax<D>(lo, hi, s_mm);
+    block_minmax<D>(lo, hi);
   }
 #pragma unroll
   for (int l = 0; l < D; ++l) {
@@ -1133,26 +1208,14 @@ __attribute__((amdgpu_waves_per_eu(orbit_waves<D, R>()))) void k_orbit(OrbitArgs
         if (v[c] != 0.0) atomicAdd(a.J + (int64_t)c * M.Ng + g, v[c]);
     }
   }
-  // block reduction in a fixed order: butterfly within each wave, then waves in order
+  // workgroup (one wave) reduction in a fixed order
+  double tot[kOrbitParts];
 #pragma unroll
-  for (int v = 0; v < kOrbitParts; ++v) {
-    for (int off = 32; off > 0; off >>= 1) {
-      const double o2 = __shfl_xor(part[v], off, 64);
-      part[v] = (v == OP_ITMAX) ? fmax(part[v], o2) : part[v] + o2;
-    }
-  }
-  __shared__ double sh[kOrbitBlock / 64][kOrbitParts];
-  const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
-  if (lane == 0)
+  for (int v = 0; v < kOrbitParts; ++v)
+    tot[v] = (v == OP_ITMAX) ? wave_reduce_f64<true>(part[v]) : wave_reduce_f64<false>(part[v]);
+  if (threadIdx.x == 0)
 #pragma unroll
-    for (int v = 0; v < kOrbitParts; ++v) sh[wave][v] = part[v];
-  __syncthreads();
-  if (threadIdx.x < kOrbitParts) {
-    const int v = threadIdx.x;
-    double acc = sh[0][v];
-    for (int w = 1; w < (int)(blockDim.x / 64); ++w) acc = (v == OP_ITMAX) ? fmax(acc, sh[w][v]) : acc + sh[w][v];
-    a.partials[(int64_t)v * a.pstride + blockIdx.x] = acc;
-  }
+    for (int v = 0; v < kOrbitParts; ++v) a.partials[(int64_t)v * a.pstride + blockIdx.x] = tot[v];
 }
 
 template <int D, class R>
