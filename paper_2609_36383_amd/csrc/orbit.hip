@@ -43,10 +43,9 @@ constexpr int kHalo = 1;               // tile halo in nodes (the stencil reach)
 template <int D>
 constexpr int tile_bytes() { return D == 3 ? 18 * 1024 : 8 * 1024; }
 
-__device__ __forceinline__ int wrapi(int i, int n) {
-  int r = i % n;
-  return r < 0 ? r + n : r;
-}
+// i mod n for a mesh size n (a power of two; two's complement makes this the
+// non-negative residue for negative i too)
+__device__ __forceinline__ int wrapi(int i, int n) { return i & (n - 1); }
 
 __device__ __forceinline__ int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
@@ -308,7 +307,10 @@ __device__ __forceinline__ void eval_segment(const OrbitArgs& a, const Tile& t, 
   const R len = sb - sa;
   Stencil<D, LDS> st(a.M, t, jn);
   constexpr int NROW = D == 1 ? 1 : (D == 2 ? 3 : 9);
-#pragma unroll 1
+  // 1D and 2D rows at a compile-time GL order are unrolled (the y weights specialise
+  // per row); 3D and the runtime order keep a loop
+  constexpr int kRowUnroll = (D < 3 && NGL > 0) ? NROW : 1;
+#pragma unroll kRowUnroll
   for (int row = 0; row < NROW; ++row) {
     const int cy = D > 1 ? row % 3 : 0, cz = D > 2 ? row / 3 : 0;
     const int rowoff = st.row(cy, cz);
