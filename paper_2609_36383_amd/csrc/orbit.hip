@@ -395,6 +395,7 @@ struct EvalOut {
 template <class R>
 struct PConst {
   R q, m, inv_mk, mk, tc, half_qdt;
+  R gpn;  // gamma of p^n = P^n - q A^- (fixed over the inner iterations)
 };
 
 // One orbit evaluation of one particle.
@@ -489,7 +490,7 @@ __device__ void evaluate(const OrbitArgs& a, const Tile& t, const R* gx, const R
     const R ux = p[0] * pc.inv_mk, uy = p[1] * pc.inv_mk, uz = p[2] * pc.inv_mk;
     return sqrt_(R(1) + ux * ux + uy * uy + uz * uz);
   };
-  const R d1 = rcp_(pc.m * (gam(pm) + gam(pn)));
+  const R d1 = rcp_(pc.m * (gam(pm) + pc.gpn));
   const R d2 = rcp_(pc.m * (gam(pn1) + gam(pp)));
   o.nseg = nseg;
 #pragma unroll
@@ -1105,6 +1106,15 @@ __attribute__((amdgpu_waves_per_eu(orbit_waves<D, R>()))) void k_orbit(OrbitArgs
     vin[2] = vin0[2];
     R Am[3] = {R(0), R(0), R(0)};
     if (valid) interp3<D, R>(a, t, D, j0, f0, Am);
+    {
+      R u2 = R(0);
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        const R u = (P0[c] - pc.q * Am[c]) * pc.inv_mk;
+        u2 += u * u;
+      }
+      pc.gpn = sqrt_(R(1) + u2);
+    }
     int it = 0, segs = 0;
     const int maxit = a.iterate ? a.max_inner : 1;
     const R kap2 = R(a.kappa) * R(a.kappa);
