@@ -354,14 +354,16 @@ __global__ __launch_bounds__(kFftThreads) void k_fft_pass(FftTask t, CNArgs cn, 
 }
 
 // Reduction of one value over nblocks partials p[b * bstride] (max or sum) by a
-// workgroup of NT threads; the result is valid in thread 0.  Thread t folds blocks t,
+// workgroup of NT threads; the result is valid in thread 0.  Every maximum reduced here
+// is of nonnegative values (iteration counts, residual ratios), so 0 is its identity and
+// an empty set (no particles) reduces to 0.  Thread t folds blocks t,
 // t + NT, ... into sixteen independent accumulators (so sixteen loads are in flight),
 // combines them in a fixed order, then a fixed pairwise tree combines the threads: the
 // result depends only on nblocks and NT.
 template <int NT>
 __device__ double reduce_value(const double* p, int nblocks, int64_t bstride, bool mx) {
   constexpr int NA = 16;
-  const double id = mx ? -INFINITY : 0.0;
+  const double id = 0.0;
   double acc16[NA];
 #pragma unroll
   for (int k = 0; k < NA; ++k) acc16[k] = id;

@@ -1,0 +1,108 @@
+"""GPU edge cases against the CPU oracle.
+
+* No particles: the step is the field solve alone (a seeded vacuum potential evolves by
+  the Crank-Nicolson update), and the report must stay well defined.
+* One particle: a workgroup with a single live lane.
+* 65 particles: one full wave and a one-lane tail.
+Whole steps compare fields and particle state to 1e-9 relative (as the step parity
+tests); a frozen evaluation of one particle compares to 1e-12.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2609_36383_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def _gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2609_36383_amd import gmhc as G
+    return G
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _rel(a, b):
+    b = np.asarray(b)
+    return float(np.abs(np.asarray(a) - b).max() / max(np.abs(b).max(), 1e-300))
+
+
+def _vacuum_potential(n, length):
+    """A^z of one standing mode along x (no charge, so it stays divergence-free)."""
+    nx, ny = n
+    ix = np.arange(nx * ny) % nx
+    A0 = np.zeros((3, nx * ny))
+    A0[2] = 0.01 * np.sin(2.0 * math.pi * ix / nx)
+    return A0, np.zeros((3, nx * ny))
+
+
+@pytest.mark.parametrize("num", [0, 1, 65])
+def test_tiny_particle_counts_steps(num):
+    G = _gpu()
+    dim, n, length, dt = 2, (8, 8), (1.6, 1.6), 0.05
+    x, u, q = W.random_particles(dim, n, length, num, 17, umax=0.5)
+    A0, U0 = _vacuum_potential(n, length)
+    kw = dict(dim=dim, n=n, lo=(0.0, 0.0), length=length, dt=dt)
+    osim = O.OracleSim(O.make_config(**kw, gl_order=8))
+    osim.load_particles(x, u, q)
+    osim.load_potentials(A0, U0)
+    osim.initialize()
+    sim = G.Simulation(G.make_config(**kw, gl_order=0, sort_every=2), num)
+    sim.load_particles(x, u, q)
+    sim.load_potentials(A0, U0)
+    sim.initialize()
+    for s in range(6):
+        osim.step()
+        st, rep = sim.step()
+        assert rep["inner_max"] >= 0 and rep["outer_iters"] >= 1
+        if num == 0:
+            assert rep["evaluations"] == 0 and rep["inner_max"] == 0
+    for f in ("A", "E", "phi", "J"):
+        ref = osim.read_field(f)
+        scale = max(np.abs(ref).max(), 1e-300)
+        d = float(np.abs(sim.read_field(f) - ref).max() / scale) if np.abs(ref).max() > 0 else \
+            float(np.abs(sim.read_field(f)).max())
+        _say(f"{num} particles, field {f}: {d:.2e}")
+        assert d < 1e-9, f
+    if num:
+        xo, Po, vo = osim.read_particles()
+        xg, Pg, vg = sim.read_particles()
+        assert _rel(Pg, Po) < 1e-9 and _rel(vg, vo) < 1e-9
+        assert float(np.abs(xg - xo).max()) < 1e-9 * max(length)
+    d = sim.diagnostics()
+    assert d["energy_rel"] < 1e-11
+
+
+def test_single_particle_frozen_evaluation():
+    G = _gpu()
+    dim, n, length, dt = 3, (8, 8, 4), (1.6, 1.6, 0.8), 0.05
+    gphi, An, Anp1, _ = W.random_fields(dim, n, length, seed=23, amp=0.3)
+    Uh = (Anp1 - An) / dt
+    x, u, q = W.random_particles(dim, n, length, 1, 29, umax=0.8)
+    P = np.abs(q)[None, :] * u
+    vbar = np.array([[0.3], [-0.2], [0.1]])
+    kw = dict(dim=dim, n=n, lo=(0.0,) * dim, length=length, dt=dt)
+    osim = O.OracleSim(O.make_config(**kw, gl_order=8))
+    osim.load_particles(x, u, q)
+    osim.set_particle_state(x, P, vbar)
+    ref = osim.orbit_pass(gphi, An, Anp1, Uh, vbar, iterate=True)
+    sim = G.Simulation(G.make_config(**kw, gl_order=0), 1)
+    sim.load_particles(x, u, q)
+    sim.set_particle_state(x, P, vbar)
+    sim.set_frozen_fields(gphi, An, Anp1, Uh)
+    rep = sim.orbit_pass_frozen(iterate=True)
+    vout, Pn1, J = sim.read_pass()
+    _say(f"one particle: iterations {rep['inner_max']} (oracle {int(ref['iters'][0])}), "
+         f"v {_rel(vout, ref['vout']):.2e} J {_rel(J, ref['J']):.2e}")
+    assert rep["failed"] == 0 and rep["inner_max"] == int(ref["iters"][0])
+    assert _rel(vout, ref["vout"]) < 1e-12 and _rel(Pn1, ref["Pnp1"]) < 1e-12 and _rel(J, ref["J"]) < 1e-12
