@@ -39,6 +39,7 @@ struct gmhc_ctx {
   void* vb[3] = {};     // accepted orbit-velocity iterate (warm start)
   void* vw[3] = {};     // working iterate of the current step / last frozen pass
   bool vin_first = false;  // the next orbit pass starts from vb (first pass of a step)
+  bool timed_now = false;  // orbit launches of the current call are timed
   double* pscr[3] = {}; // FP64 staging for loads and read-outs
   int32_t* id = nullptr;
   int32_t* id2 = nullptr;
@@ -102,6 +103,7 @@ struct gmhc_ctx {
 namespace {
 
 const int kResOff = 16;  // offset of residual results in dres
+const size_t kCtlBytes = sizeof(int32_t) * 4 + sizeof(double) * 16;  // control block + accumulators
 
 int32_t fail(gmhc_ctx* c, int32_t st, const std::string& msg) {
   if (c) c->err = msg;
@@ -216,8 +218,9 @@ size_t carve(gmhc_ctx* c, char* base, int64_t np) {
   c->partials = cv.take<double>((size_t)(c->max_blocks + res_cap) * 8);
   c->dres = cv.take<double>(64);
   c->ddot = cv.take<double>(kMaxDots);
-  c->dctl = cv.take<int32_t>(4);
-  c->dacc = cv.take<double>(16);
+  // control block [4] int32 then the report accumulators [16] double, contiguous
+  c->dctl = cv.take<int32_t>(kCtlBytes / sizeof(int32_t));
+  c->dacc = c->dctl ? reinterpret_cast<double*>(c->dctl + 4) : nullptr;
   if (c->cfg.outer_scheme == 1) {
     c->jA = cv.take<double>(3 * Ng);
     c->rA = cv.take<double>(3 * Ng);
@@ -287,9 +290,8 @@ int orbit_blocks(const gmhc_ctx* c) { return (int)((c->np + kOrbitBlock - 1) / k
 int32_t run_orbit(gmhc_ctx* ctx, int iterate, double* ms) {
   OrbitArgs a = orbit_args(ctx, iterate);
   HIPCK(launch_zero(ctx->Jdep, 3 * ctx->M.Ng, ctx->stream));
-  if (ctx->cfg.timing) HIPCK(hipEventRecord(ctx->ev0, ctx->stream));
-  HIPCK(launch_orbit(a, ctx->ngl, ctx->stream));
-  if (ctx->cfg.timing) HIPCK(hipEventRecord(ctx->ev1, ctx->stream));
+  const bool timed = ctx->timed_now;
+  HIPCK(launch_orbit(a, ctx->ngl, ctx->stream, timed ? ctx->ev0 : nullptr, timed ? ctx->ev1 : nullptr));
   const int nb = (int)((ctx->np + kOrbitBlock - 1) / kOrbitBlock);
   if (nb > 0) {
     HIPCK(launch_reduce(ctx->partials, nb, 1, ctx->max_blocks, kOrbitParts, 1u << OP_ITMAX, ctx->dres,
@@ -314,7 +316,7 @@ int32_t fetch_results(gmhc_ctx* ctx, double* orbit_ms) {
 
 int32_t wait_results(gmhc_ctx* ctx, double* orbit_ms) {
   HIPCK(hipStreamSynchronize(ctx->stream));
-  if (ctx->cfg.timing && orbit_ms) {
+  if (ctx->timed_now && orbit_ms) {
     float f = 0.0f;
     HIPCK(hipEventElapsedTime(&f, ctx->ev0, ctx->ev1));
     *orbit_ms += (double)f;
@@ -436,6 +438,7 @@ int32_t gmhc_create(const gmhc_config* cfg, gmhc_ctx** out) {
   if (c.gl_order < 0 || c.gl_order > kMaxGL) return GMHC_EINVAL;
   if (c.precision != GMHC_FP64 && c.precision != GMHC_FP32_BULK) return GMHC_EINVAL;
   if (c.max_outer < 1 || c.max_inner < 1 || !(c.beta > 0.0 && c.beta <= 1.0)) return GMHC_EINVAL;
+  if (c.timing < 0) return GMHC_EINVAL;
   if (c.outer_scheme != 0 && c.outer_scheme != 1) return GMHC_EINVAL;
   if (c.outer_scheme == 1 &&
       (c.anderson_m < 1 || c.anderson_m > 8 || c.anderson_start < 1 || c.ls_halvings < 0 || c.ls_halvings > 30 ||
@@ -478,7 +481,6 @@ void gmhc_destroy(gmhc_ctx* ctx) {
     if (ctx->hres) (void)hipHostFree(ctx->hres);
     if (ctx->hdot) (void)hipHostFree(ctx->hdot);
     if (ctx->hctl) (void)hipHostFree(ctx->hctl);
-    if (ctx->hacc) (void)hipHostFree(ctx->hacc);
     for (hipEvent_t e : ctx->evs) (void)hipEventDestroy(e);
     for (auto& e : ctx->graphs) (void)hipGraphExecDestroy(e.exec);
     if (ctx->ev0) (void)hipEventDestroy(ctx->ev0);
@@ -516,8 +518,8 @@ int32_t gmhc_bind(gmhc_ctx* ctx, int64_t n_particles, void* dev_workspace, size_
   carve(ctx, ctx->ws, n_particles);
   HIPCK(hipHostMalloc(reinterpret_cast<void**>(&ctx->hres), sizeof(double) * 64, hipHostMallocDefault));
   HIPCK(hipHostMalloc(reinterpret_cast<void**>(&ctx->hdot), sizeof(double) * kMaxDots, hipHostMallocDefault));
-  HIPCK(hipHostMalloc(reinterpret_cast<void**>(&ctx->hctl), sizeof(int32_t) * 4, hipHostMallocDefault));
-  HIPCK(hipHostMalloc(reinterpret_cast<void**>(&ctx->hacc), sizeof(double) * 16, hipHostMallocDefault));
+  HIPCK(hipHostMalloc(reinterpret_cast<void**>(&ctx->hctl), kCtlBytes, hipHostMallocDefault));
+  ctx->hacc = reinterpret_cast<double*>(ctx->hctl + 4);
   HIPCK(hipEventCreate(&ctx->ev0));
   HIPCK(hipEventCreate(&ctx->ev1));
   // FFT plans and twiddles exp(-2 pi i m / N)
@@ -703,13 +705,13 @@ int32_t enqueue_outer(gmhc_ctx* ctx, int cur, int hs, int part, const int32_t* s
     HIPCK(field_trial(M, ctx->axes, ca, ctx->trial, ctx->cout, ctx->Jdep, s));
   }
   if (part == OUTER_ALL || part == OUTER_ORBIT) {
-    const bool timed = ctx->cfg.timing && part == OUTER_ORBIT;
-    if (timed) HIPCK(hipEventRecord(e0, s));
+    // timed launches record their own start and stop (never inside a captured graph:
+    // timed graph runs launch the orbit pass eagerly)
+    const bool timed = ctx->timed_now && (part == OUTER_ORBIT || stop != nullptr);
     OrbitArgs oa = orbit_args(ctx, 1);
     oa.stop = stop;
-    HIPCK(launch_orbit(oa, ctx->ngl, s));
+    HIPCK(launch_orbit(oa, ctx->ngl, s, timed ? e0 : nullptr, timed ? e1 : nullptr));
     ctx->vin_first = false;  // later passes of the step start from their predecessor's v_out
-    if (timed) HIPCK(hipEventRecord(e1, s));
   }
   if (part == OUTER_ALL || part == OUTER_POST) {
     // H(j) = P J_orb in spectral and real space, with the residual partials
@@ -801,7 +803,7 @@ int32_t run_outer(gmhc_ctx* ctx, int cur, int hs, bool& use_graph, int32_t& repl
   hipStream_t s = ctx->stream;
   if (use_graph) {
     const int parts[3] = {OUTER_PRE, OUTER_ORBIT, OUTER_POST};
-    const int np = ctx->cfg.timing ? 3 : 1;
+    const int np = ctx->timed_now ? 3 : 1;
     hipGraphExec_t ex[3] = {nullptr, nullptr, nullptr};
     bool ok = true;
     for (int k = 0; k < np && ok; ++k) {
@@ -825,7 +827,7 @@ int32_t run_outer(gmhc_ctx* ctx, int cur, int hs, bool& use_graph, int32_t& repl
     }
     use_graph = false;
   }
-  if (ctx->cfg.timing) {
+  if (ctx->timed_now) {
     for (int part : {OUTER_PRE, OUTER_ORBIT, OUTER_POST}) {
       int32_t st = enqueue_outer(ctx, cur, hs, part);
       if (st) return st;
@@ -884,7 +886,8 @@ int32_t commit_outer(gmhc_ctx* ctx, int cur, double rr, double mr, double ra2, d
     std::swap(ctx->P[l], ctx->P2[l]);
     std::swap(ctx->vb[l], ctx->vw[l]);
   }
-  HIPCK(hipStreamSynchronize(s));
+  // no wait: the next step's work is ordered behind the copy on the same stream, and
+  // every read-out synchronizes the stream itself
   ctx->last_chain = np ? sqrt(ra2 / (3.0 * (double)np)) : 0.0;
   ctx->last_work = ctx->cfg.dt * (pwork - mwork * M.dV);
   ctx->last_rr = rr;
@@ -908,9 +911,8 @@ int32_t run_picard(gmhc_ctx* ctx, gmhc_step_report& R) {
   hipStream_t s = ctx->stream;
   const int64_t np = ctx->np;
   const int maxo = ctx->cfg.max_outer;
-  HIPCK(hipMemsetAsync(ctx->dctl, 0, sizeof(int32_t) * 4, s));
-  HIPCK(hipMemsetAsync(ctx->dacc, 0, sizeof(double) * 16, s));
-  const bool timed = ctx->cfg.timing != 0;
+  HIPCK(hipMemsetAsync(ctx->dctl, 0, kCtlBytes, s));
+  const bool timed = ctx->timed_now;
   if (timed)
     while ((int)ctx->evs.size() < 2 * maxo) {
       hipEvent_t e;
@@ -926,20 +928,12 @@ int32_t run_picard(gmhc_ctx* ctx, gmhc_step_report& R) {
       ++k;
       const int hs = (cur == 1) ? 2 : 1;
       slot[k] = cur;
-      if (timed) {
-        hipEvent_t e0 = ctx->evs[2 * (k - 1)], e1 = ctx->evs[2 * (k - 1) + 1];
-        for (int part : {OUTER_PRE, OUTER_ORBIT, OUTER_POST}) {
-          int32_t st = enqueue_outer(ctx, cur, hs, part, ctx->dctl, k, e0, e1);
-          if (st) return st;
-        }
-      } else {
-        int32_t st = enqueue_outer(ctx, cur, hs, OUTER_ALL, ctx->dctl, k);
-        if (st) return st;
-      }
+      hipEvent_t e0 = timed ? ctx->evs[2 * (k - 1)] : nullptr, e1 = timed ? ctx->evs[2 * (k - 1) + 1] : nullptr;
+      int32_t st = enqueue_outer(ctx, cur, hs, OUTER_ALL, ctx->dctl, k, e0, e1);
+      if (st) return st;
       cur = hs;
     }
-    HIPCK(hipMemcpyAsync(ctx->hctl, ctx->dctl, sizeof(int32_t) * 4, hipMemcpyDeviceToHost, s));
-    HIPCK(hipMemcpyAsync(ctx->hacc, ctx->dacc, sizeof(double) * 16, hipMemcpyDeviceToHost, s));
+    HIPCK(hipMemcpyAsync(ctx->hctl, ctx->dctl, kCtlBytes, hipMemcpyDeviceToHost, s));
     HIPCK(hipStreamSynchronize(s));
     const int32_t* c = ctx->hctl;
     const double* acc = ctx->hacc;
@@ -1106,7 +1100,7 @@ int32_t gmhc_step(gmhc_ctx* ctx, gmhc_step_report* rep) {
   if (!ctx->initialized) return fail(ctx, GMHC_ESTATE, "initialize before step");
   DevGuard gd(ctx->device);
   const Mesh& M = ctx->M;
-  const int64_t Ng = M.Ng, np = ctx->np;
+  const int64_t Ng = M.Ng;
   hipStream_t s = ctx->stream;
   gmhc_step_report R{};
   auto done = [&](int32_t st) {
@@ -1118,6 +1112,8 @@ int32_t gmhc_step(gmhc_ctx* ctx, gmhc_step_report* rep) {
     if (st) return done(st);
   }
   ctx->vin_first = true;  // the first orbit pass reads the accepted v from vb
+  const int tk = ctx->cfg.timing;
+  ctx->timed_now = tk == 1 || (tk > 1 && ctx->step % tk == 0);
   bool use_graph = ctx->cfg.graphs != 0 && ctx->stream != nullptr && !ctx->graphs_off;
   if (ctx->cfg.outer_scheme == 1) return done(step_anderson(ctx, R, use_graph));
   // damped Picard: j <- j + beta (H(j) - j); the outer test runs on the device unless
@@ -1342,6 +1338,7 @@ int32_t gmhc_orbit_pass_frozen(gmhc_ctx* ctx, int32_t iterate, gmhc_pass_report*
   for (int l = 0; l < 3; ++l)
     if (np) HIPCK(hipMemcpyAsync(ctx->vw[l], ctx->vb[l], ctx->es * np, hipMemcpyDeviceToDevice, s));
   ctx->vin_first = false;
+  ctx->timed_now = ctx->cfg.timing != 0;
   int32_t st = run_orbit(ctx, iterate ? 1 : 0, nullptr);
   if (st) return st;
   double oms = 0.0;

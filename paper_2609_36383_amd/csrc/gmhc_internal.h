@@ -86,7 +86,10 @@ struct OrbitArgs {
   const int32_t* stop;   // optional device flag: nonzero = skip the pass
 };
 
-hipError_t launch_orbit(const OrbitArgs& a, int ngl, hipStream_t s);
+// With events e0 and e1, the launch itself records its start and stop in them (no
+// separate marker packets on the stream); with no particles both are recorded at once.
+hipError_t launch_orbit(const OrbitArgs& a, int ngl, hipStream_t s, hipEvent_t e0 = nullptr,
+                        hipEvent_t e1 = nullptr);
 
 // ---- spectral field step ---------------------------------------------------------
 

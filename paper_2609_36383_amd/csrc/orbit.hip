@@ -28,6 +28,7 @@
 // FP64 and the orbit geometry is taken relative to the particle's nearest node, so
 // FP32 keeps sub-cell resolution.  The deposit tile, the current and every
 // reduction (kinetic energy, work, chain-rule residual) are FP64.
+#include <hip/hip_ext.h>
 #include <limits.h>
 #include <math.h>
 
@@ -1230,30 +1231,40 @@ __attribute__((amdgpu_waves_per_eu(orbit_waves<D, R>()))) void k_orbit(OrbitArgs
     for (int v = 0; v < kOrbitParts; ++v) a.partials[(int64_t)v * a.pstride + blockIdx.x] = tot[v];
 }
 
+template <int D, int NGL, class R>
+hipError_t launch_k(const OrbitArgs& a, unsigned blocks, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
+  if (e0 || e1)
+    hipExtLaunchKernelGGL((k_orbit<D, NGL, R>), dim3(blocks), dim3(kOrbitBlock), tile_bytes<D>(), s, e0, e1, 0u, a);
+  else
+    hipLaunchKernelGGL((k_orbit<D, NGL, R>), dim3(blocks), dim3(kOrbitBlock), tile_bytes<D>(), s, a);
+  return hipGetLastError();
+}
+
 template <int D, class R>
-hipError_t launch_d(const OrbitArgs& a, unsigned blocks, hipStream_t s) {
+hipError_t launch_d(const OrbitArgs& a, unsigned blocks, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
   // compile-time Gauss-Legendre orders: d+1 (exact for the per-segment polynomials)
   // and 8 (the paper's); any other order runs the runtime loop
-  if (a.ngl == D + 1)
-    hipLaunchKernelGGL((k_orbit<D, D + 1, R>), dim3(blocks), dim3(kOrbitBlock), tile_bytes<D>(), s, a);
-  else if (a.ngl == 8)
-    hipLaunchKernelGGL((k_orbit<D, 8, R>), dim3(blocks), dim3(kOrbitBlock), tile_bytes<D>(), s, a);
-  else
-    hipLaunchKernelGGL((k_orbit<D, 0, R>), dim3(blocks), dim3(kOrbitBlock), tile_bytes<D>(), s, a);
-  return hipGetLastError();
+  if (a.ngl == D + 1) return launch_k<D, D + 1, R>(a, blocks, s, e0, e1);
+  if (a.ngl == 8) return launch_k<D, 8, R>(a, blocks, s, e0, e1);
+  return launch_k<D, 0, R>(a, blocks, s, e0, e1);
 }
 
 }  // namespace
 
-hipError_t launch_orbit(const OrbitArgs& a, int ngl, hipStream_t s) {
+hipError_t launch_orbit(const OrbitArgs& a, int ngl, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
   (void)ngl;
-  if (a.np <= 0) return hipSuccess;
+  if (a.np <= 0) {
+    hipError_t e = hipSuccess;
+    if (e0) e = hipEventRecord(e0, s);
+    if (e1 && e == hipSuccess) e = hipEventRecord(e1, s);
+    return e;
+  }
   const unsigned blocks = (unsigned)((a.np + kOrbitBlock - 1) / kOrbitBlock);
   const bool f32 = a.precision == 1;
   switch (a.M.d) {
-    case 1: return f32 ? launch_d<1, float>(a, blocks, s) : launch_d<1, double>(a, blocks, s);
-    case 2: return f32 ? launch_d<2, float>(a, blocks, s) : launch_d<2, double>(a, blocks, s);
-    case 3: return f32 ? launch_d<3, float>(a, blocks, s) : launch_d<3, double>(a, blocks, s);
+    case 1: return f32 ? launch_d<1, float>(a, blocks, s, e0, e1) : launch_d<1, double>(a, blocks, s, e0, e1);
+    case 2: return f32 ? launch_d<2, float>(a, blocks, s, e0, e1) : launch_d<2, double>(a, blocks, s, e0, e1);
+    case 3: return f32 ? launch_d<3, float>(a, blocks, s, e0, e1) : launch_d<3, double>(a, blocks, s, e0, e1);
     default: return hipErrorInvalidValue;
   }
 }

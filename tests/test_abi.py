@@ -50,6 +50,7 @@ def test_host_validation():
         dict(outer_scheme=1, anderson_m=9),
         dict(outer_scheme=1, ls_growth=0.9),
         dict(outer_scheme=1, ls_decrease=1.0),
+        dict(timing=-1),
     ]
     for over in bad:
         kw = dict(dim=2, n=(16, 16), lo=(0, 0), length=(3.2, 3.2), dt=0.05)

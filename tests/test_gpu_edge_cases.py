@@ -106,3 +106,17 @@ def test_single_particle_frozen_evaluation():
          f"v {_rel(vout, ref['vout']):.2e} J {_rel(J, ref['J']):.2e}")
     assert rep["failed"] == 0 and rep["inner_max"] == int(ref["iters"][0])
     assert _rel(vout, ref["vout"]) < 1e-12 and _rel(Pn1, ref["Pnp1"]) < 1e-12 and _rel(J, ref["J"]) < 1e-12
+
+
+def test_sampled_orbit_timing():
+    """timing = k times the orbit launches of every k-th step only (step index 0, k, ...)."""
+    G = _gpu()
+    w = W.spec("weibel2d", n=(16, 16), ppc=8)
+    x, u, q = W.particles(w)
+    sim = G.Simulation(G.config_from_dict(W.config_dict(w), gl_order=0, timing=3), q.size)
+    sim.load_particles(x, u, q)
+    sim.initialize()
+    for k in range(7):
+        _, rep = sim.step()
+        assert (rep["orbit_ms"] > 0.0) == (k % 3 == 0), (k, rep["orbit_ms"])
+        assert rep["orbit_launches"] == rep["outer_iters"]
