@@ -40,6 +40,8 @@ struct gmhc_ctx {
   void* vw[3] = {};     // working iterate of the current step / last frozen pass
   bool vin_first = false;  // the next orbit pass starts from vb (first pass of a step)
   bool timed_now = false;  // orbit launches of the current call are timed
+  bool ctl_clean = false;  // the device control block and accumulators are zero
+  hipEvent_t evsync = nullptr;  // end of a batch's control-block copy (polled)
   double* pscr[3] = {}; // FP64 staging for loads and read-outs
   int32_t* id = nullptr;
   int32_t* id2 = nullptr;
@@ -482,6 +484,7 @@ void gmhc_destroy(gmhc_ctx* ctx) {
     if (ctx->hdot) (void)hipHostFree(ctx->hdot);
     if (ctx->hctl) (void)hipHostFree(ctx->hctl);
     for (hipEvent_t e : ctx->evs) (void)hipEventDestroy(e);
+    if (ctx->evsync) (void)hipEventDestroy(ctx->evsync);
     for (auto& e : ctx->graphs) (void)hipGraphExecDestroy(e.exec);
     if (ctx->ev0) (void)hipEventDestroy(ctx->ev0);
     if (ctx->ev1) (void)hipEventDestroy(ctx->ev1);
@@ -522,6 +525,7 @@ int32_t gmhc_bind(gmhc_ctx* ctx, int64_t n_particles, void* dev_workspace, size_
   ctx->hacc = reinterpret_cast<double*>(ctx->hctl + 4);
   HIPCK(hipEventCreate(&ctx->ev0));
   HIPCK(hipEventCreate(&ctx->ev1));
+  HIPCK(hipEventCreateWithFlags(&ctx->evsync, hipEventDisableTiming));
   // FFT plans and twiddles exp(-2 pi i m / N)
   const long double pi = 3.141592653589793238462643383279502884L;
   int64_t stride = 1;
@@ -870,13 +874,16 @@ int32_t eval_outer(gmhc_ctx* ctx, int cur, int hs, gmhc_step_report& R, bool& us
 
 // Commit the state of the converged evaluation at the trial current in slot cur; ra2,
 // pwork and mwork are its sum |R_A|^2, particle work and mesh work.
-int32_t commit_outer(gmhc_ctx* ctx, int cur, double rr, double mr, double ra2, double pwork, double mwork) {
+// With an_done, A^n was already copied on the device (launch_commit_tail).
+int32_t commit_outer(gmhc_ctx* ctx, int cur, double rr, double mr, double ra2, double pwork, double mwork,
+                     bool an_done = false) {
   const Mesh& M = ctx->M;
   const int64_t Ng = M.Ng, np = ctx->np;
   const int d = M.d;
   hipStream_t s = ctx->stream;
   std::swap(ctx->S0, ctx->S1);
-  HIPCK(hipMemcpyAsync(ctx->An, ctx->trial + (int64_t)d * Ng, sizeof(double) * 3 * Ng, hipMemcpyDeviceToDevice, s));
+  if (!an_done)
+    HIPCK(hipMemcpyAsync(ctx->An, ctx->trial + (int64_t)d * Ng, sizeof(double) * 3 * Ng, hipMemcpyDeviceToDevice, s));
   if (cur != 0) {  // the accepted current becomes slot 0
     std::swap(ctx->jr[0], ctx->jr[cur]);
     std::swap(ctx->jh[0], ctx->jh[cur]);
@@ -911,7 +918,9 @@ int32_t run_picard(gmhc_ctx* ctx, gmhc_step_report& R) {
   hipStream_t s = ctx->stream;
   const int64_t np = ctx->np;
   const int maxo = ctx->cfg.max_outer;
-  HIPCK(hipMemsetAsync(ctx->dctl, 0, kCtlBytes, s));
+  if (!ctx->ctl_clean) HIPCK(hipMemsetAsync(ctx->dctl, 0, kCtlBytes, s));
+  ctx->ctl_clean = false;
+  const Mesh& M = ctx->M;
   const bool timed = ctx->timed_now;
   if (timed)
     while ((int)ctx->evs.size() < 2 * maxo) {
@@ -934,7 +943,15 @@ int32_t run_picard(gmhc_ctx* ctx, gmhc_step_report& R) {
       cur = hs;
     }
     HIPCK(hipMemcpyAsync(ctx->hctl, ctx->dctl, kCtlBytes, hipMemcpyDeviceToHost, s));
-    HIPCK(hipStreamSynchronize(s));
+    HIPCK(hipEventRecord(ctx->evsync, s));
+    // the converged step's A^n copy and the control reset run on the device behind the
+    // copy, so nothing waits for the host between steps
+    HIPCK(launch_commit_tail(ctx->dctl, ctx->dacc, 16, ctx->trial + (int64_t)M.d * M.Ng, ctx->An, 3 * M.Ng, s));
+    // poll the copy's completion (a blocking wait adds tens of microseconds of wake-up)
+    hipError_t q;
+    while ((q = hipEventQuery(ctx->evsync)) == hipErrorNotReady) {
+    }
+    if (q != hipSuccess) HIPCK(q);
     const int32_t* c = ctx->hctl;
     const double* acc = ctx->hacc;
     const int ran = (int)llround(acc[3]);  // iterations that ran (the rest returned at once)
@@ -953,11 +970,12 @@ int32_t run_picard(gmhc_ctx* ctx, gmhc_step_report& R) {
     R.res_rms_ratio = acc[5];
     R.res_max_ratio = acc[6];
     if (c[0]) {
+      ctx->ctl_clean = true;  // cleared by launch_commit_tail
       if (c[1])
         return fail(ctx, GMHC_EINNER,
                     "particle inner solve failed (" + std::to_string((long long)acc[4]) + " particles)");
       ctx->last_outer = c[2];
-      return commit_outer(ctx, slot[c[2]], acc[5], acc[6], acc[7], acc[8], acc[9]);
+      return commit_outer(ctx, slot[c[2]], acc[5], acc[6], acc[7], acc[8], acc[9], true);
     }
     if (k >= maxo) return fail(ctx, GMHC_ENOCONV, "outer iteration limit reached");
     batch = 1;

@@ -474,6 +474,25 @@ __global__ __launch_bounds__(kRedThreads) void k_reduce_outer(ReduceSet a, Reduc
   }
 }
 
+// End of a Picard batch on the device, after the control block was read back: when the
+// outer test stopped the step with success (ctl[0] set, ctl[1] clear), A^{n+1} of the
+// trial fields becomes A^n (k_commit_copy); once the step stopped either way, the
+// control block and the report accumulators are cleared for the next step (k_ctl_reset,
+// a separate launch so every copying workgroup has read ctl first).
+__global__ __launch_bounds__(kBlock) void k_commit_copy(const int32_t* ctl, const double* src, double* dst,
+                                                        int64_t n) {
+  if (!ctl[0] || ctl[1]) return;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    dst[i] = src[i];
+}
+
+__global__ void k_ctl_reset(int32_t* ctl, double* acc, int nacc) {
+  if (threadIdx.x != 0 || !ctl[0]) return;
+  for (int i = 0; i < nacc; ++i) acc[i] = 0.0;
+  ctl[1] = ctl[2] = ctl[3] = 0;
+  ctl[0] = 0;
+}
+
 // y = a x + b z over n values (outer-solver vector updates).
 __global__ __launch_bounds__(kBlock) void k_axpbz(double* y, double a, const double* x, double b, const double* z,
                                                   int64_t n) {
@@ -926,6 +945,16 @@ hipError_t launch_zero(double* y, int64_t n, hipStream_t s, const int32_t* stop)
 hipError_t launch_reduce_outer(const ReduceSet& a, const ReduceSet& b, const OuterTest& t, hipStream_t s,
                                const int32_t* stop) {
   hipLaunchKernelGGL(k_reduce_outer, dim3((unsigned)(a.nvals + b.nvals)), dim3(kRedThreads), 0, s, a, b, t, stop);
+  return hipGetLastError();
+}
+
+hipError_t launch_commit_tail(int32_t* ctl, double* acc, int nacc, const double* src, double* dst, int64_t n,
+                              hipStream_t s) {
+  if (n > 0) {
+    const unsigned blocks = (unsigned)std::min<int64_t>((n + kBlock - 1) / kBlock, 1024);
+    hipLaunchKernelGGL(k_commit_copy, dim3(blocks), dim3(kBlock), 0, s, ctl, src, dst, n);
+  }
+  hipLaunchKernelGGL(k_ctl_reset, dim3(1), dim3(64), 0, s, ctl, acc, nacc);
   return hipGetLastError();
 }
 
