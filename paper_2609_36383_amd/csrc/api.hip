@@ -430,9 +430,12 @@ int32_t gmhc_create(const gmhc_config* cfg, gmhc_ctx** out) {
   *out = nullptr;
   const gmhc_config& c = *cfg;
   if (c.dim < 1 || c.dim > 3) return GMHC_EINVAL;
+  int64_t ng = 1;
   for (int l = 0; l < c.dim; ++l) {
     const int n = c.n[l];
     if (n < 4 || n > 4096 || (n & (n - 1)) != 0) return GMHC_EINVAL;
+    ng *= n;
+    if (ng > (int64_t)1 << 30) return GMHC_EINVAL;  // node indices stay within int32
     if (!(c.len[l] > 0.0) || !isfinite(c.lo[l])) return GMHC_EINVAL;
   }
   if (!(c.dt > 0.0) || !(c.kappa > 0.0) || !(c.sigma1 > 0.0) || !(c.sigma2 > 0.0)) return GMHC_EINVAL;

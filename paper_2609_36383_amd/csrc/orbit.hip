@@ -93,6 +93,7 @@ struct Tile {
   int nodes;
   int ok;     // 1: fields staged in LDS
   int joff;   // double offset of the current tile in the dynamic LDS block
+  int goff;   // int offset of the tile nodes' mesh indices in the dynamic LDS block
 };
 
 // Fields of the staged tile: 0..D-1 grad phi, D..D+2 A^n, D+3..D+5 A^{n+1},
@@ -1055,18 +1056,23 @@ __attribute__((amdgpu_waves_per_eu(orbit_waves<D, R>()))) void k_orbit(OrbitArgs
       nodes = (e > 4096 || nodes > 4096) ? (1 << 30) : nodes * e;  // no overflow: 4096^2 < 2^30
     }
   }
-  // field tile in R, then the FP64 current tile at an 8-byte boundary
+  // field tile in R, then the FP64 current tile at an 8-byte boundary, then the tile
+  // nodes' mesh indices (int32; the mesh has at most 2^30 nodes)
   const int64_t fbytes = ((int64_t)nodes * NF * (int64_t)sizeof(R) + 7) / 8 * 8;
-  if (ok && fbytes + (int64_t)nodes * 3 * 8 > tile_bytes<D>()) ok = 0;
+  if (ok && fbytes + (int64_t)nodes * (3 * 8 + 4) > tile_bytes<D>()) ok = 0;
   t.nodes = uni(nodes);
   t.ok = uni(ok);
   t.joff = uni((int)(fbytes / 8));
+  t.goff = uni((int)(fbytes / 4) + 6 * nodes);
   if (t.ok) {
     // one tile node per lane at a time: its mesh index is computed once for all fields
+    // and kept for the flush
     R* s_tile = reinterpret_cast<R*>(s_dyn);
     double* s_J = s_dyn + t.joff;
+    int* s_g = reinterpret_cast<int*>(s_dyn) + t.goff;
     for (int nd = threadIdx.x; nd < t.nodes; nd += blockDim.x) {
-      const int64_t g = tile_to_global<D>(M, t, nd);
+      const int g = tile_to_global<D>(M, t, nd);
+      s_g[nd] = g;
 #pragma unroll
       for (int f = 0; f < NF; ++f) s_tile[f * t.nodes + nd] = (R)gfield<D>(a, f)[g];
 #pragma unroll
@@ -1212,10 +1218,11 @@ __attribute__((amdgpu_waves_per_eu(orbit_waves<D, R>()))) void k_orbit(OrbitArgs
   // flush the current tile: one atomic per nonzero tile node and component
   if (t.ok && a.deposit) {
     const double* s_J = s_dyn + t.joff;
+    const int* s_g = reinterpret_cast<const int*>(s_dyn) + t.goff;
     for (int nd = threadIdx.x; nd < t.nodes; nd += blockDim.x) {
       const double v[3] = {s_J[nd], s_J[t.nodes + nd], s_J[2 * t.nodes + nd]};
       if (v[0] == 0.0 && v[1] == 0.0 && v[2] == 0.0) continue;
-      const int64_t g = tile_to_global<D>(M, t, nd);
+      const int64_t g = s_g[nd];
 #pragma unroll
       for (int c = 0; c < 3; ++c)
         if (v[c] != 0.0) atomicAdd(a.J + (int64_t)c * M.Ng + g, v[c]);

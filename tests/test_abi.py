@@ -58,6 +58,10 @@ def test_host_validation():
         c = G.make_config(**kw)
         hh = C.c_void_p()
         assert lib.gmhc_create(C.byref(c), C.byref(hh)) == G.EINVAL, over
+    # more than 2^30 mesh nodes (node indices are int32 in the kernels)
+    c = G.make_config(3, (4096, 4096, 128), (0, 0, 0), (1, 1, 1), 0.1)
+    hh = C.c_void_p()
+    assert lib.gmhc_create(C.byref(c), C.byref(hh)) == G.EINVAL
     c = G.make_config(4, (16, 16, 16), (0, 0, 0), (1, 1, 1), 0.1)
     c.dim = 4
     assert lib.gmhc_create(C.byref(c), C.byref(C.c_void_p())) == G.EINVAL
