@@ -8,6 +8,7 @@
 #include <algorithm>
 
 #include "gmhc_internal.h"
+#include "wave.h"
 
 namespace gmhc {
 namespace {
@@ -329,13 +330,10 @@ __global__ __launch_bounds__(kFftThreads) void k_fft_pass(FftTask t, CNArgs cn, 
       const double H[3] = {lds[lt * N + kk].x * sc, lds[(T + lt) * N + kk].x * sc, lds[(2 * T + lt) * N + kk].x * sc};
       residual_node(t.ra, node(line, k), H, part);
     }
-    // wave butterflies, then the waves in order; the lines' LDS holds the wave sums
+    // each wave through DPP, then the waves in order; the lines' LDS holds the wave sums
 #pragma unroll
     for (int v = 0; v < kResParts; ++v)
-      for (int off = 32; off > 0; off >>= 1) {
-        const double o2 = __shfl_xor(part[v], off, 64);
-        part[v] = (v == 3) ? fmax(part[v], o2) : part[v] + o2;
-      }
+      part[v] = (v == 3) ? wave_reduce_f64<true>(part[v]) : wave_reduce_f64<false>(part[v]);
     __syncthreads();
     double* shd = reinterpret_cast<double*>(lds);
     const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
@@ -386,17 +384,14 @@ __device__ double reduce_value(const double* p, int nblocks, int64_t bstride, bo
   double acc = acc16[0];
 #pragma unroll
   for (int k = 1; k < NA; ++k) acc = mx ? fmax(acc, acc16[k]) : acc + acc16[k];
-  __shared__ double sh[NT];
-  sh[threadIdx.x] = acc;
+  // each wave through DPP, then the wave sums in order
+  acc = mx ? wave_reduce_f64<true>(acc) : wave_reduce_f64<false>(acc);
+  __shared__ double sh[NT / 64];
+  if (threadIdx.x % 64 == 0) sh[threadIdx.x / 64] = acc;
   __syncthreads();
-  for (int h = NT / 2; h > 0; h >>= 1) {
-    if ((int)threadIdx.x < h) {
-      const double o = sh[threadIdx.x + h];
-      sh[threadIdx.x] = mx ? fmax(sh[threadIdx.x], o) : sh[threadIdx.x] + o;
-    }
-    __syncthreads();
-  }
-  return sh[0];
+  double r = sh[0];
+  for (int w = 1; w < NT / 64; ++w) r = mx ? fmax(r, sh[w]) : r + sh[w];
+  return r;
 }
 
 __global__ __launch_bounds__(kBlock) void k_reduce(const double* partials, int nblocks, int64_t bstride,
