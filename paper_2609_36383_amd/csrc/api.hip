@@ -41,7 +41,7 @@ struct gmhc_ctx {
   bool vin_first = false;  // the next orbit pass starts from vb (first pass of a step)
   bool timed_now = false;  // orbit launches of the current call are timed
   bool ctl_clean = false;  // the device control block and accumulators are zero
-  hipEvent_t evsync = nullptr;  // end of a batch's control-block copy (polled)
+  bool ahead = false;      // the next step's first outer iteration is already enqueued
   double* pscr[3] = {}; // FP64 staging for loads and read-outs
   int32_t* id = nullptr;
   int32_t* id2 = nullptr;
@@ -75,8 +75,11 @@ struct gmhc_ctx {
   // pinned host copies, per-iteration timing events, predicted iteration count
   int32_t* dctl = nullptr;
   double* dacc = nullptr;
-  int32_t* hctl = nullptr;
+  int32_t* hctl = nullptr;       // coherent pinned block: control, accumulators, sequence
   double* hacc = nullptr;
+  uint32_t* hseq = nullptr;
+  CtlPublish dpub{};              // the same block as the device addresses it
+  uint32_t pub_seq = 0;           // sequence number of the last batch published
   std::vector<hipEvent_t> evs;
   int last_outer = 0;
   double* ddot = nullptr;   // device dot products [kMaxDots]
@@ -110,6 +113,14 @@ const size_t kCtlBytes = sizeof(int32_t) * 4 + sizeof(double) * 16;  // control 
 int32_t fail(gmhc_ctx* c, int32_t st, const std::string& msg) {
   if (c) c->err = msg;
   return st;
+}
+
+// Discard an enqueued first outer iteration: the next step starts afresh, with the
+// control block cleared again.
+void drop_ahead(gmhc_ctx* ctx) {
+  if (!ctx->ahead) return;
+  ctx->ahead = false;
+  ctx->ctl_clean = false;
 }
 
 #define HIPCK(expr)                                                                  \
@@ -487,7 +498,6 @@ void gmhc_destroy(gmhc_ctx* ctx) {
     if (ctx->hdot) (void)hipHostFree(ctx->hdot);
     if (ctx->hctl) (void)hipHostFree(ctx->hctl);
     for (hipEvent_t e : ctx->evs) (void)hipEventDestroy(e);
-    if (ctx->evsync) (void)hipEventDestroy(ctx->evsync);
     for (auto& e : ctx->graphs) (void)hipGraphExecDestroy(e.exec);
     if (ctx->ev0) (void)hipEventDestroy(ctx->ev0);
     if (ctx->ev1) (void)hipEventDestroy(ctx->ev1);
@@ -524,11 +534,20 @@ int32_t gmhc_bind(gmhc_ctx* ctx, int64_t n_particles, void* dev_workspace, size_
   carve(ctx, ctx->ws, n_particles);
   HIPCK(hipHostMalloc(reinterpret_cast<void**>(&ctx->hres), sizeof(double) * 64, hipHostMallocDefault));
   HIPCK(hipHostMalloc(reinterpret_cast<void**>(&ctx->hdot), sizeof(double) * kMaxDots, hipHostMallocDefault));
-  HIPCK(hipHostMalloc(reinterpret_cast<void**>(&ctx->hctl), kCtlBytes, hipHostMallocDefault));
+  // the control block is published by a kernel straight into coherent host memory
+  HIPCK(hipHostMalloc(reinterpret_cast<void**>(&ctx->hctl), kCtlBytes + 64, hipHostMallocMapped | hipHostMallocCoherent));
   ctx->hacc = reinterpret_cast<double*>(ctx->hctl + 4);
+  ctx->hseq = reinterpret_cast<uint32_t*>(reinterpret_cast<char*>(ctx->hctl) + kCtlBytes);
+  *ctx->hseq = 0;
+  {
+    void* dp = nullptr;
+    HIPCK(hipHostGetDevicePointer(&dp, ctx->hctl, 0));
+    char* db = static_cast<char*>(dp);
+    ctx->dpub = CtlPublish{reinterpret_cast<int32_t*>(db), reinterpret_cast<double*>(db + 4 * sizeof(int32_t)),
+                           reinterpret_cast<uint32_t*>(db + kCtlBytes)};
+  }
   HIPCK(hipEventCreate(&ctx->ev0));
   HIPCK(hipEventCreate(&ctx->ev1));
-  HIPCK(hipEventCreateWithFlags(&ctx->evsync, hipEventDisableTiming));
   // FFT plans and twiddles exp(-2 pi i m / N)
   const long double pi = 3.141592653589793238462643383279502884L;
   int64_t stride = 1;
@@ -564,6 +583,7 @@ int32_t gmhc_bind(gmhc_ctx* ctx, int64_t n_particles, void* dev_workspace, size_
 int32_t gmhc_load_particles(gmhc_ctx* ctx, const double* x, const double* u, const double* q,
                             int32_t ptr_kind) {
   if (!ctx) return GMHC_EINVAL;
+  drop_ahead(ctx);
   if (!ctx->bound) return fail(ctx, GMHC_ESTATE, "bind before loading particles");
   const int64_t np = ctx->np;
   if (np > 0 && (!x || !u || !q)) return fail(ctx, GMHC_EINVAL, "null particle array");
@@ -588,6 +608,7 @@ int32_t gmhc_load_particles(gmhc_ctx* ctx, const double* x, const double* u, con
 
 int32_t gmhc_load_potentials(gmhc_ctx* ctx, const double* A0, const double* U0, int32_t ptr_kind) {
   if (!ctx || !A0 || !U0) return GMHC_EINVAL;
+  drop_ahead(ctx);
   if (!ctx->bound) return fail(ctx, GMHC_ESTATE, "bind before loading potentials");
   DevGuard g(ctx->device);
   const int64_t Ng = ctx->M.Ng;
@@ -602,6 +623,7 @@ int32_t gmhc_load_potentials(gmhc_ctx* ctx, const double* A0, const double* U0, 
 
 int32_t gmhc_initialize(gmhc_ctx* ctx) {
   if (!ctx) return GMHC_EINVAL;
+  drop_ahead(ctx);
   if (!ctx->loaded) return fail(ctx, GMHC_ESTATE, "load particles before initialize");
   DevGuard g(ctx->device);
   const Mesh& M = ctx->M;
@@ -917,47 +939,105 @@ int32_t commit_host(gmhc_ctx* ctx, int cur, double rr, double mr) {
 // test, and once it passes (or an inner solve fails) the kernels of the iterations
 // already queued return at once.  The host synchronizes once per batch, so the GPU does
 // not idle between outer iterations.
-int32_t run_picard(gmhc_ctx* ctx, gmhc_step_report& R) {
-  hipStream_t s = ctx->stream;
-  const int64_t np = ctx->np;
-  const int maxo = ctx->cfg.max_outer;
-  if (!ctx->ctl_clean) HIPCK(hipMemsetAsync(ctx->dctl, 0, kCtlBytes, s));
-  ctx->ctl_clean = false;
-  const Mesh& M = ctx->M;
-  const bool timed = ctx->timed_now;
-  if (timed)
-    while ((int)ctx->evs.size() < 2 * maxo) {
+// Per-step flags: the first orbit pass reads the accepted v from vb, and the orbit
+// launches of every timing-th step are timed.
+void begin_step(gmhc_ctx* ctx) {
+  ctx->vin_first = true;
+  const int tk = ctx->cfg.timing;
+  ctx->timed_now = tk == 1 || (tk > 1 && ctx->step % tk == 0);
+}
+
+// Enqueue outer iteration k (1-based) of a device-controlled Picard step from current
+// slot cur into slot 1 or 2 (whichever cur is not); timed steps record events 2(k-1)
+// and 2(k-1)+1 around the orbit launch.
+int32_t enqueue_picard_iter(gmhc_ctx* ctx, int k, int cur) {
+  const int hs = (cur == 1) ? 2 : 1;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (ctx->timed_now) {
+    while ((int)ctx->evs.size() < 2 * k) {
       hipEvent_t e;
       HIPCK(hipEventCreate(&e));
       ctx->evs.push_back(e);
     }
+    e0 = ctx->evs[2 * (k - 1)];
+    e1 = ctx->evs[2 * (k - 1) + 1];
+  }
+  return enqueue_outer(ctx, cur, hs, OUTER_ALL, ctx->dctl, k, e0, e1);
+}
+
+// Steps that can start before the caller asks for them: device-controlled Picard
+// without graphs, and no particle sort due at the step's start.
+bool can_run_ahead(const gmhc_ctx* ctx) {
+  const gmhc_config& c = ctx->cfg;
+  const bool graph = c.graphs != 0 && ctx->stream != nullptr && !ctx->graphs_off;
+  const bool sort = c.sort_every > 0 && ctx->step % c.sort_every == 0;
+  return c.outer_scheme != 1 && !graph && !sort && c.max_outer >= 1;
+}
+
+// After a commit, enqueue the next step's first outer iteration at once: it reads only
+// the accepted state and writes only scratch (trial fields, the new-time spectra, the
+// deposit, the slot 1 current, the new particle slots and the control block), so the
+// GPU need not wait for the caller's next gmhc_step.  Any other call discards it
+// (drop_ahead); the work already queued is then simply redone.
+int32_t run_ahead(gmhc_ctx* ctx) {
+  if (!can_run_ahead(ctx)) return GMHC_OK;
+  begin_step(ctx);
+  ctx->ctl_clean = false;
+  int32_t st = enqueue_picard_iter(ctx, 1, 0);
+  if (st) return st;
+  ctx->ahead = true;
+  return GMHC_OK;
+}
+
+int32_t run_picard(gmhc_ctx* ctx, gmhc_step_report& R) {
+  hipStream_t s = ctx->stream;
+  const int64_t np = ctx->np;
+  const int maxo = ctx->cfg.max_outer;
   std::vector<int> slot(maxo + 1, 0);
   int k = 0, cur = 0;
+  if (ctx->ahead) {  // iteration 1 was enqueued when the previous step committed
+    ctx->ahead = false;
+    k = 1;
+    cur = 1;
+  } else {
+    if (!ctx->ctl_clean) HIPCK(hipMemsetAsync(ctx->dctl, 0, kCtlBytes, s));
+    ctx->ctl_clean = false;
+  }
+  const Mesh& M = ctx->M;
+  const bool timed = ctx->timed_now;
   int batch = std::max(1, std::min(ctx->last_outer, maxo));
+  int k0 = 0;
   while (true) {
-    const int k0 = k;
-    for (int b = 0; b < batch && k < maxo; ++b) {
+    while (k < k0 + batch && k < maxo) {
       ++k;
-      const int hs = (cur == 1) ? 2 : 1;
       slot[k] = cur;
-      hipEvent_t e0 = timed ? ctx->evs[2 * (k - 1)] : nullptr, e1 = timed ? ctx->evs[2 * (k - 1) + 1] : nullptr;
-      int32_t st = enqueue_outer(ctx, cur, hs, OUTER_ALL, ctx->dctl, k, e0, e1);
+      int32_t st = enqueue_picard_iter(ctx, k, cur);
       if (st) return st;
-      cur = hs;
+      cur = (cur == 1) ? 2 : 1;
     }
-    HIPCK(hipMemcpyAsync(ctx->hctl, ctx->dctl, kCtlBytes, hipMemcpyDeviceToHost, s));
-    HIPCK(hipEventRecord(ctx->evsync, s));
-    // the converged step's A^n copy and the control reset run on the device behind the
-    // copy, so nothing waits for the host between steps
-    HIPCK(launch_commit_tail(ctx->dctl, ctx->dacc, 16, ctx->trial + (int64_t)M.d * M.Ng, ctx->An, 3 * M.Ng, s));
-    // poll the copy's completion (a blocking wait adds tens of microseconds of wake-up)
-    hipError_t q;
-    while ((q = hipEventQuery(ctx->evsync)) == hipErrorNotReady) {
+    // the batch-end kernel publishes the control block to host memory; the converged
+    // step's A^n copy and the control reset run on the device behind it, so nothing
+    // waits for the host between steps
+    if (++ctx->pub_seq == 0) ++ctx->pub_seq;
+    const uint32_t want = ctx->pub_seq;
+    HIPCK(launch_commit_tail(ctx->dctl, ctx->dacc, 16, ctx->dpub, want, ctx->trial + (int64_t)M.d * M.Ng, ctx->An,
+                             3 * M.Ng, s));
+    // spin on the sequence number (a blocking wait or an event query adds tens of
+    // microseconds of wake-up); the stream is queried now and then so that the wait
+    // ends even if the word never arrives
+    for (uint32_t spin = 1; __atomic_load_n(ctx->hseq, __ATOMIC_ACQUIRE) != want; ++spin) {
+      if (spin % 4096 != 0) continue;
+      const hipError_t q = hipStreamQuery(s);
+      if (q == hipErrorNotReady) continue;
+      if (q != hipSuccess) HIPCK(q);
+      if (__atomic_load_n(ctx->hseq, __ATOMIC_ACQUIRE) != want)
+        return fail(ctx, GMHC_EDEVICE, "the batch control block was not published");
     }
-    if (q != hipSuccess) HIPCK(q);
     const int32_t* c = ctx->hctl;
     const double* acc = ctx->hacc;
     const int ran = (int)llround(acc[3]);  // iterations that ran (the rest returned at once)
+    if (timed && std::min(k, ran) > k0)
+      HIPCK(hipEventSynchronize(ctx->evs[2 * (std::min(k, ran) - 1) + 1]));
     if (timed)
       for (int kk = k0 + 1; kk <= std::min(k, ran); ++kk) {
         float f = 0.0f;
@@ -978,9 +1058,12 @@ int32_t run_picard(gmhc_ctx* ctx, gmhc_step_report& R) {
         return fail(ctx, GMHC_EINNER,
                     "particle inner solve failed (" + std::to_string((long long)acc[4]) + " particles)");
       ctx->last_outer = c[2];
-      return commit_outer(ctx, slot[c[2]], acc[5], acc[6], acc[7], acc[8], acc[9], true);
+      int32_t st = commit_outer(ctx, slot[c[2]], acc[5], acc[6], acc[7], acc[8], acc[9], true);
+      if (st) return st;
+      return run_ahead(ctx);
     }
     if (k >= maxo) return fail(ctx, GMHC_ENOCONV, "outer iteration limit reached");
+    k0 = k;
     batch = 1;
   }
 }
@@ -1128,13 +1211,14 @@ int32_t gmhc_step(gmhc_ctx* ctx, gmhc_step_report* rep) {
     if (rep) *rep = R;
     return st;
   };
-  if (ctx->cfg.sort_every > 0 && ctx->step % ctx->cfg.sort_every == 0) {
-    int32_t st = sort_particles(ctx);
-    if (st) return done(st);
+  ctx->pass_done = false;  // the step reuses the frozen pass's buffers
+  if (!ctx->ahead) {  // else the previous step began this one (no sort was due)
+    if (ctx->cfg.sort_every > 0 && ctx->step % ctx->cfg.sort_every == 0) {
+      int32_t st = sort_particles(ctx);
+      if (st) return done(st);
+    }
+    begin_step(ctx);
   }
-  ctx->vin_first = true;  // the first orbit pass reads the accepted v from vb
-  const int tk = ctx->cfg.timing;
-  ctx->timed_now = tk == 1 || (tk > 1 && ctx->step % tk == 0);
   bool use_graph = ctx->cfg.graphs != 0 && ctx->stream != nullptr && !ctx->graphs_off;
   if (ctx->cfg.outer_scheme == 1) return done(step_anderson(ctx, R, use_graph));
   // damped Picard: j <- j + beta (H(j) - j); the outer test runs on the device unless
@@ -1157,6 +1241,7 @@ int32_t gmhc_step(gmhc_ctx* ctx, gmhc_step_report* rep) {
 
 int32_t gmhc_diagnostics(gmhc_ctx* ctx, gmhc_diag* out) {
   if (!ctx || !out) return GMHC_EINVAL;
+  drop_ahead(ctx);
   if (!ctx->initialized) return fail(ctx, GMHC_ESTATE, "initialize before diagnostics");
   DevGuard gd(ctx->device);
   const Mesh& M = ctx->M;
@@ -1216,6 +1301,7 @@ int32_t gmhc_diagnostics(gmhc_ctx* ctx, gmhc_diag* out) {
 
 int32_t gmhc_read_particles(gmhc_ctx* ctx, double* x, double* P, double* vbar, int32_t ptr_kind) {
   if (!ctx) return GMHC_EINVAL;
+  drop_ahead(ctx);
   if (!ctx->loaded) return fail(ctx, GMHC_ESTATE, "no particles loaded");
   DevGuard gd(ctx->device);
   const int64_t np = ctx->np;
@@ -1240,6 +1326,7 @@ int32_t gmhc_read_particles(gmhc_ctx* ctx, double* x, double* P, double* vbar, i
 int32_t gmhc_set_particle_state(gmhc_ctx* ctx, const double* x, const double* P, const double* vbar,
                                 int32_t ptr_kind) {
   if (!ctx) return GMHC_EINVAL;
+  drop_ahead(ctx);
   if (!ctx->loaded) return fail(ctx, GMHC_ESTATE, "no particles loaded");
   DevGuard gd(ctx->device);
   const int64_t np = ctx->np;
@@ -1263,6 +1350,7 @@ int32_t gmhc_set_particle_state(gmhc_ctx* ctx, const double* x, const double* P,
 
 int32_t gmhc_read_field(gmhc_ctx* ctx, int32_t which, double* dst, int32_t ptr_kind) {
   if (!ctx || !dst) return GMHC_EINVAL;
+  drop_ahead(ctx);
   if (!ctx->bound) return fail(ctx, GMHC_ESTATE, "bind before reading fields");
   DevGuard gd(ctx->device);
   int nc = 0;
@@ -1275,6 +1363,7 @@ int32_t gmhc_read_field(gmhc_ctx* ctx, int32_t which, double* dst, int32_t ptr_k
 
 int32_t gmhc_mode_amplitude(gmhc_ctx* ctx, int32_t which, int32_t comp, const int32_t mode[3], double* amp) {
   if (!ctx || !mode || !amp) return GMHC_EINVAL;
+  drop_ahead(ctx);
   if (!ctx->bound) return fail(ctx, GMHC_ESTATE, "bind before reading modes");
   if (comp < 0 || comp >= ncomp_of(which)) return fail(ctx, GMHC_EINVAL, "bad component");
   DevGuard gd(ctx->device);
@@ -1336,6 +1425,7 @@ int32_t gmhc_mode_amplitude(gmhc_ctx* ctx, int32_t which, int32_t comp, const in
 int32_t gmhc_set_frozen_fields(gmhc_ctx* ctx, const double* gradphi, const double* An, const double* Anp1,
                                const double* Uh, int32_t ptr_kind) {
   if (!ctx || !gradphi || !An || !Anp1 || !Uh) return GMHC_EINVAL;
+  drop_ahead(ctx);
   if (!ctx->bound) return fail(ctx, GMHC_ESTATE, "bind before setting fields");
   DevGuard gd(ctx->device);
   const int64_t Ng = ctx->M.Ng;
@@ -1347,11 +1437,13 @@ int32_t gmhc_set_frozen_fields(gmhc_ctx* ctx, const double* gradphi, const doubl
   HIPCK(hipMemcpyAsync(ctx->trial + (d + 3) * Ng, Uh, sizeof(double) * 3 * Ng, kind_of(ptr_kind, true), s));
   HIPCK(hipStreamSynchronize(s));
   ctx->frozen = true;
+  ctx->initialized = false;  // A^n of the stepping state was replaced
   return GMHC_OK;
 }
 
 int32_t gmhc_orbit_pass_frozen(gmhc_ctx* ctx, int32_t iterate, gmhc_pass_report* rep) {
   if (!ctx) return GMHC_EINVAL;
+  drop_ahead(ctx);
   if (!ctx->loaded || !ctx->frozen) return fail(ctx, GMHC_ESTATE, "load particles and set frozen fields first");
   DevGuard gd(ctx->device);
   const int64_t np = ctx->np;
@@ -1381,6 +1473,7 @@ int32_t gmhc_orbit_pass_frozen(gmhc_ctx* ctx, int32_t iterate, gmhc_pass_report*
 
 int32_t gmhc_read_pass(gmhc_ctx* ctx, double* vout, double* Pnp1, double* J, int32_t ptr_kind) {
   if (!ctx) return GMHC_EINVAL;
+  drop_ahead(ctx);
   if (!ctx->pass_done) return fail(ctx, GMHC_ESTATE, "no frozen pass has run");
   DevGuard gd(ctx->device);
   const int64_t np = ctx->np, Ng = ctx->M.Ng;

@@ -188,11 +188,20 @@ struct OuterTest {
 hipError_t launch_reduce_outer(const ReduceSet& a, const ReduceSet& b, const OuterTest& t, hipStream_t s,
                                const int32_t* stop);
 
-// Device-side end of a Picard batch (enqueued after the control block was copied out):
-// dst[0..n) = src[0..n) when ctl[0] is set and ctl[1] clear (the step converged); then,
-// when ctl[0] is set, ctl[0..3] and acc[0..nacc) are cleared for the next step.
-hipError_t launch_commit_tail(int32_t* ctl, double* acc, int nacc, const double* src, double* dst, int64_t n,
-                              hipStream_t s);
+// Host-visible (coherent pinned) copy of the Picard control block: ctl[0..3] and
+// acc[0..nacc), then seq, written last with a system-scope release.
+struct CtlPublish {
+  int32_t* ctl;
+  double* acc;
+  uint32_t* seq;
+};
+
+// Device-side end of a Picard batch: the control block and accumulators are published
+// to pub with sequence number seq; dst[0..n) = src[0..n) when ctl[0] is set and ctl[1]
+// clear (the step converged); then, when ctl[0] is set, ctl[0..3] and acc[0..nacc) are
+// cleared for the next step.
+hipError_t launch_commit_tail(int32_t* ctl, double* acc, int nacc, const CtlPublish& pub, uint32_t seq,
+                              const double* src, double* dst, int64_t n, hipStream_t s);
 
 // y = a x + b z over n values (z may be null).
 hipError_t launch_axpbz(double* y, double a, const double* x, double b, const double* z, int64_t n,

@@ -469,13 +469,25 @@ __global__ __launch_bounds__(kRedThreads) void k_reduce_outer(ReduceSet a, Reduc
   }
 }
 
-// End of a Picard batch on the device, after the control block was read back: when the
-// outer test stopped the step with success (ctl[0] set, ctl[1] clear), A^{n+1} of the
-// trial fields becomes A^n (k_commit_copy); once the step stopped either way, the
-// control block and the report accumulators are cleared for the next step (k_ctl_reset,
-// a separate launch so every copying workgroup has read ctl first).
-__global__ __launch_bounds__(kBlock) void k_commit_copy(const int32_t* ctl, const double* src, double* dst,
-                                                        int64_t n) {
+// End of a Picard batch on the device: the first thread publishes the control block and
+// the report accumulators to host memory, the sequence number last (the host spins on
+// it); when the outer test stopped the step with success (ctl[0] set, ctl[1] clear),
+// A^{n+1} of the trial fields becomes A^n (k_commit_copy); once the step stopped either
+// way, the control block and the report accumulators are cleared for the next step
+// (k_ctl_reset, a separate launch so every copying workgroup has read ctl first).
+__global__ __launch_bounds__(kBlock) void k_commit_copy(const int32_t* ctl, const double* acc, int nacc,
+                                                        CtlPublish pub, uint32_t seq, const double* src,
+                                                        double* dst, int64_t n) {
+  static_assert(kBlock >= 4 + 16, "one value per thread");
+  if (blockIdx.x == 0) {  // one value per thread, then the sequence number
+    const int l = threadIdx.x;
+    if (l < 4)
+      pub.ctl[l] = ctl[l];
+    else if (l < 4 + nacc)
+      pub.acc[l - 4] = acc[l - 4];
+    __syncthreads();
+    if (l == 0) __hip_atomic_store(pub.seq, seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+  }
   if (!ctl[0] || ctl[1]) return;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
     dst[i] = src[i];
@@ -943,12 +955,11 @@ hipError_t launch_reduce_outer(const ReduceSet& a, const ReduceSet& b, const Out
   return hipGetLastError();
 }
 
-hipError_t launch_commit_tail(int32_t* ctl, double* acc, int nacc, const double* src, double* dst, int64_t n,
-                              hipStream_t s) {
-  if (n > 0) {
-    const unsigned blocks = (unsigned)std::min<int64_t>((n + kBlock - 1) / kBlock, 1024);
-    hipLaunchKernelGGL(k_commit_copy, dim3(blocks), dim3(kBlock), 0, s, ctl, src, dst, n);
-  }
+hipError_t launch_commit_tail(int32_t* ctl, double* acc, int nacc, const CtlPublish& pub, uint32_t seq,
+                              const double* src, double* dst, int64_t n, hipStream_t s) {
+  const unsigned blocks = (unsigned)std::max<int64_t>(1, std::min<int64_t>((n + kBlock - 1) / kBlock, 1024));
+  hipLaunchKernelGGL(k_commit_copy, dim3(blocks), dim3(kBlock), 0, s, (const int32_t*)ctl, (const double*)acc,
+                     nacc, pub, seq, src, dst, n);
   hipLaunchKernelGGL(k_ctl_reset, dim3(1), dim3(64), 0, s, ctl, acc, nacc);
   return hipGetLastError();
 }

@@ -168,6 +168,59 @@ def test_step_parity_with_sorting():
     assert worst["x"] < 1e-9 and worst["P"] < 1e-9 and worst["v"] < 1e-9
 
 
+def test_back_to_back_steps_match_oracle():
+    """Steps called with nothing in between: each continues from the first outer
+    iteration that the previous step enqueued after its commit.  With sort_every=4 a
+    sort is due every fourth step, which starts afresh; a read in the middle discards
+    the enqueued iteration."""
+    G = _gpu()
+    w = W.spec("weibel2d", n=(16, 16), ppc=8)
+    base = W.config_dict(w)
+    x, u, q = W.particles(w)
+    osim = O.OracleSim(O.config_from_dict(base, gl_order=8))
+    osim.load_particles(x, u, q)
+    osim.initialize()
+    for _ in range(12):
+        osim.step()
+    xo, Po, vo = osim.read_particles()
+    for over in ({}, dict(sort_every=4)):
+        sim = G.Simulation(G.config_from_dict(base, gl_order=0, **over), q.size)
+        sim.load_particles(x, u, q)
+        sim.initialize()
+        for s in range(1, 13):
+            st, rep = sim.step()
+            assert rep["outer_iters"] >= 1
+            if s == 6:
+                sim.read_field("A")
+        xg, Pg, vg = sim.read_particles()
+        _say(f"back-to-back {over}: rel x {_periodic_rel(xg, xo, w['length']):.2e} P {_rel(Pg, Po):.2e}")
+        assert _periodic_rel(xg, xo, w["length"]) < 1e-9
+        assert _rel(Pg, Po) < 1e-9 and _rel(vg, vo) < 1e-9
+        for k in ("A", "rho", "J"):
+            assert _rel(sim.read_field(k), osim.read_field(k)) < 1e-9, k
+        assert sim.diagnostics()["energy_rel"] < 1e-11
+        sim.close()
+
+
+def test_frozen_fields_require_initialize_before_step():
+    G = _gpu()
+    w = W.spec("weibel2d", n=(8, 8), ppc=4)
+    base = W.config_dict(w)
+    x, u, q = W.particles(w)
+    sim = G.Simulation(G.config_from_dict(base), q.size)
+    sim.load_particles(x, u, q)
+    sim.initialize()
+    sim.step()
+    Ng = 64
+    z2, z3 = np.zeros((2, Ng)), np.zeros((3, Ng))
+    sim.set_frozen_fields(z2, z3, z3, z3)
+    st, _ = sim.step(raise_on_error=False)
+    assert st == G.ESTATE
+    sim.initialize()
+    st, _ = sim.step(raise_on_error=False)
+    assert st == G.OK
+
+
 def test_mode_amplitude_and_fields_match():
     G = _gpu()
     sim, osim, gd, od, worst = _run_pair("tsi1d", {}, 5, 5)
