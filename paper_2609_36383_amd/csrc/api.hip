@@ -977,8 +977,11 @@ bool can_run_ahead(const gmhc_ctx* ctx) {
 // After a commit, enqueue the next step's first outer iteration at once: it reads only
 // the accepted state and writes only scratch (trial fields, the new-time spectra, the
 // deposit, the slot 1 current, the new particle slots and the control block), so the
-// GPU need not wait for the caller's next gmhc_step.  Any other call discards it
-// (drop_ahead); the work already queued is then simply redone.
+// GPU need not wait for the caller's next gmhc_step.  The read-outs of the accepted
+// state (diagnostics, particles, fields, mode amplitudes) leave it in place: they use
+// only reduction and transform scratch that the iteration has consumed by the time they
+// run and that the next iteration rewrites before reading.  Every other call discards
+// it (drop_ahead), and the next step then starts afresh.
 int32_t run_ahead(gmhc_ctx* ctx) {
   if (!can_run_ahead(ctx)) return GMHC_OK;
   begin_step(ctx);
@@ -1241,7 +1244,6 @@ int32_t gmhc_step(gmhc_ctx* ctx, gmhc_step_report* rep) {
 
 int32_t gmhc_diagnostics(gmhc_ctx* ctx, gmhc_diag* out) {
   if (!ctx || !out) return GMHC_EINVAL;
-  drop_ahead(ctx);
   if (!ctx->initialized) return fail(ctx, GMHC_ESTATE, "initialize before diagnostics");
   DevGuard gd(ctx->device);
   const Mesh& M = ctx->M;
@@ -1301,7 +1303,6 @@ int32_t gmhc_diagnostics(gmhc_ctx* ctx, gmhc_diag* out) {
 
 int32_t gmhc_read_particles(gmhc_ctx* ctx, double* x, double* P, double* vbar, int32_t ptr_kind) {
   if (!ctx) return GMHC_EINVAL;
-  drop_ahead(ctx);
   if (!ctx->loaded) return fail(ctx, GMHC_ESTATE, "no particles loaded");
   DevGuard gd(ctx->device);
   const int64_t np = ctx->np;
@@ -1350,7 +1351,6 @@ int32_t gmhc_set_particle_state(gmhc_ctx* ctx, const double* x, const double* P,
 
 int32_t gmhc_read_field(gmhc_ctx* ctx, int32_t which, double* dst, int32_t ptr_kind) {
   if (!ctx || !dst) return GMHC_EINVAL;
-  drop_ahead(ctx);
   if (!ctx->bound) return fail(ctx, GMHC_ESTATE, "bind before reading fields");
   DevGuard gd(ctx->device);
   int nc = 0;
@@ -1363,7 +1363,6 @@ int32_t gmhc_read_field(gmhc_ctx* ctx, int32_t which, double* dst, int32_t ptr_k
 
 int32_t gmhc_mode_amplitude(gmhc_ctx* ctx, int32_t which, int32_t comp, const int32_t mode[3], double* amp) {
   if (!ctx || !mode || !amp) return GMHC_EINVAL;
-  drop_ahead(ctx);
   if (!ctx->bound) return fail(ctx, GMHC_ESTATE, "bind before reading modes");
   if (comp < 0 || comp >= ncomp_of(which)) return fail(ctx, GMHC_EINVAL, "bad component");
   DevGuard gd(ctx->device);

@@ -169,10 +169,10 @@ def test_step_parity_with_sorting():
 
 
 def test_back_to_back_steps_match_oracle():
-    """Steps called with nothing in between: each continues from the first outer
-    iteration that the previous step enqueued after its commit.  With sort_every=4 a
-    sort is due every fourth step, which starts afresh; a read in the middle discards
-    the enqueued iteration."""
+    """Steps called back to back continue from the first outer iteration that the
+    previous step enqueued after its commit; read-outs between steps keep it, a state
+    change discards it (here re-setting the same particle state after step 6), and with
+    sort_every=4 every fourth step sorts and starts afresh."""
     G = _gpu()
     w = W.spec("weibel2d", n=(16, 16), ppc=8)
     base = W.config_dict(w)
@@ -190,8 +190,12 @@ def test_back_to_back_steps_match_oracle():
         for s in range(1, 13):
             st, rep = sim.step()
             assert rep["outer_iters"] >= 1
-            if s == 6:
+            if s in (3, 9):
                 sim.read_field("A")
+                sim.diagnostics()
+                sim.mode_amplitude("E", 0, (1, 0, 0))
+            if s == 6:
+                sim.set_particle_state(*sim.read_particles())
         xg, Pg, vg = sim.read_particles()
         _say(f"back-to-back {over}: rel x {_periodic_rel(xg, xo, w['length']):.2e} P {_rel(Pg, Po):.2e}")
         assert _periodic_rel(xg, xo, w["length"]) < 1e-9
