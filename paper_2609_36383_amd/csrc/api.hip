@@ -49,12 +49,12 @@ struct gmhc_ctx {
   int32_t* key = nullptr;
   // mesh
   double* An = nullptr;     // [3][Ng] real A^n
-  double* trial = nullptr;  // [d+6][Ng] real: grad phi^{n+1/2}, A^{n+1}, U^{n+1/2}
+  double* trial[2] = {};    // [d+6][Ng] real: grad phi^{n+1/2}, A^{n+1}, U^{n+1/2}, by parity
   double* Jdep = nullptr;   // [3][Ng]
   double* jr[3] = {};       // real current slots [3][Ng]; slot 0 = accepted J^{n-1/2}
   double2* jh[3] = {};      // spectral current slots
   double2* S0 = nullptr;    // accepted spectral state [9][Ng]: phi psi rho A(3) U(3)
-  double2* S1 = nullptr;    // trial spectral state
+  double2* S1[2] = {};      // trial spectral state, by outer-iteration parity
   double2* cout = nullptr;  // [9][Ng] complex scratch (CN outputs, FFT work)
   double2* cscr = nullptr;  // [9][Ng] complex scratch
   double* rscr = nullptr;   // [9][Ng] real scratch
@@ -209,14 +209,14 @@ size_t carve(gmhc_ctx* c, char* base, int64_t np) {
   c->iters = cv.take<int32_t>(N);
   c->key = cv.take<int32_t>(N);
   c->An = cv.take<double>(3 * Ng);
-  c->trial = cv.take<double>((size_t)(d + 6) * Ng);
+  for (int p = 0; p < 2; ++p) c->trial[p] = cv.take<double>((size_t)(d + 6) * Ng);
   c->Jdep = cv.take<double>(3 * Ng);
   for (int s = 0; s < 3; ++s) {
     c->jr[s] = cv.take<double>(3 * Ng);
     c->jh[s] = cv.take<double2>(3 * Ng);
   }
   c->S0 = cv.take<double2>(9 * Ng);
-  c->S1 = cv.take<double2>(9 * Ng);
+  for (int p = 0; p < 2; ++p) c->S1[p] = cv.take<double2>(9 * Ng);
   c->cout = cv.take<double2>(9 * Ng);
   c->cscr = cv.take<double2>(9 * Ng);
   c->rscr = cv.take<double>(9 * Ng);
@@ -263,7 +263,7 @@ hipMemcpyKind kind_of(int32_t ptr_kind, bool to_device) {
   return to_device ? hipMemcpyHostToDevice : hipMemcpyDeviceToHost;
 }
 
-OrbitArgs orbit_args(gmhc_ctx* c, int iterate) {
+OrbitArgs orbit_args(gmhc_ctx* c, int iterate, int par = 0) {
   OrbitArgs a{};
   a.M = c->M;
   a.np = c->np;
@@ -287,7 +287,7 @@ OrbitArgs orbit_args(gmhc_ctx* c, int iterate) {
   a.Pn = c->P2[0];
   a.vin = c->vin_first ? c->vb[0] : c->vw[0];
   a.v = c->vw[0];
-  a.trial = c->trial;
+  a.trial = c->trial[par];
   a.An = c->An;
   a.J = c->Jdep;
   a.q = c->q;
@@ -574,7 +574,8 @@ int32_t gmhc_bind(gmhc_ctx* ctx, int64_t n_particles, void* dev_workspace, size_
   HIPCK(hipMemsetAsync(ctx->jr[0], 0, sizeof(double) * 3 * ctx->M.Ng, ctx->stream));
   HIPCK(hipMemsetAsync(ctx->jh[0], 0, sizeof(double2) * 3 * ctx->M.Ng, ctx->stream));
   HIPCK(hipMemsetAsync(ctx->An, 0, sizeof(double) * 3 * ctx->M.Ng, ctx->stream));
-  HIPCK(hipMemsetAsync(ctx->trial, 0, sizeof(double) * (ctx->M.d + 6) * ctx->M.Ng, ctx->stream));
+  for (int p = 0; p < 2; ++p)
+    HIPCK(hipMemsetAsync(ctx->trial[p], 0, sizeof(double) * (ctx->M.d + 6) * ctx->M.Ng, ctx->stream));
   HIPCK(hipStreamSynchronize(ctx->stream));
   ctx->bound = true;
   return GMHC_OK;
@@ -688,7 +689,9 @@ int32_t gmhc_initialize(gmhc_ctx* ctx) {
 }
 
 // Parts of one outer iteration's device work (see enqueue_outer).
-enum OuterPart { OUTER_ALL = 0, OUTER_PRE = 1, OUTER_ORBIT = 2, OUTER_POST = 3 };
+// Parts of an outer iteration: all, the field solve before the orbit pass, the orbit
+// pass, the field step after it, and the last two together.
+enum OuterPart { OUTER_ALL = 0, OUTER_PRE = 1, OUTER_ORBIT = 2, OUTER_POST = 3, OUTER_TAIL = 4 };
 
 // Device work of one outer iteration for the trial current in slot cur, with H(j)
 // written to slot hs: CN field step and trial fields (PRE), the orbit pass with its
@@ -701,68 +704,89 @@ enum OuterPart { OUTER_ALL = 0, OUTER_PRE = 1, OUTER_ORBIT = 2, OUTER_POST = 3 }
 // and returns when an earlier iteration already converged or failed; the iteration ends
 // with the device-side outer test of iteration k and, for beta < 1, the damped update of
 // the next trial current in slot hs, instead of copying the results to the host.
+//
+// The trial fields and new-time spectra of iteration k live in the buffers of parity
+// k & 1 (host-controlled iterations pass k = 0).  With next (undamped Picard under device
+// control) POST also solves and transforms those of iteration k + 1 into the other
+// parity, from the projected spectrum of H, which is that iteration's current; it then
+// runs as OUTER_TAIL, without PRE.  The iteration that converges keeps its own buffers.
+CNArgs cn_args(const gmhc_ctx* ctx, const double2* jh, double2* S1, const int32_t* stop) {
+  const int64_t Ng = ctx->M.Ng;
+  CNArgs ca{};
+  ca.M = ctx->M;
+  ca.dt = ctx->cfg.dt;
+  ca.kappa2 = ctx->cfg.kappa * ctx->cfg.kappa;
+  ca.sigma1 = ctx->cfg.sigma1;
+  ca.sigma2 = ctx->cfg.sigma2;
+  ca.jh = jh;
+  ca.phi = ctx->S0;
+  ca.psi = ctx->S0 + Ng;
+  ca.rho = ctx->S0 + 2 * Ng;
+  ca.A = ctx->S0 + 3 * Ng;
+  ca.U = ctx->S0 + 6 * Ng;
+  ca.phi1 = S1;
+  ca.psi1 = S1 + Ng;
+  ca.rho1 = S1 + 2 * Ng;
+  ca.A1 = S1 + 3 * Ng;
+  ca.U1 = S1 + 6 * Ng;
+  ca.stop = stop;
+  return ca;
+}
+
 int32_t enqueue_outer(gmhc_ctx* ctx, int cur, int hs, int part, const int32_t* stop = nullptr, int k = 0,
-                      hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr) {
+                      hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr, bool next = false) {
   const Mesh& M = ctx->M;
   const int64_t Ng = M.Ng;
   const int d = M.d;
+  const int par = k & 1;
   hipStream_t s = ctx->stream;
   if (!e0) {
     e0 = ctx->ev0;
     e1 = ctx->ev1;
   }
   if (part == OUTER_ALL || part == OUTER_PRE) {
-    CNArgs ca{};
-    ca.M = M;
-    ca.dt = ctx->cfg.dt;
-    ca.kappa2 = ctx->cfg.kappa * ctx->cfg.kappa;
-    ca.sigma1 = ctx->cfg.sigma1;
-    ca.sigma2 = ctx->cfg.sigma2;
-    ca.jh = ctx->jh[cur];
-    ca.phi = ctx->S0;
-    ca.psi = ctx->S0 + Ng;
-    ca.rho = ctx->S0 + 2 * Ng;
-    ca.A = ctx->S0 + 3 * Ng;
-    ca.U = ctx->S0 + 6 * Ng;
-    ca.phi1 = ctx->S1;
-    ca.psi1 = ctx->S1 + Ng;
-    ca.rho1 = ctx->S1 + 2 * Ng;
-    ca.A1 = ctx->S1 + 3 * Ng;
-    ca.U1 = ctx->S1 + 6 * Ng;
-    ca.stop = stop;
     // CN solve, trial fields in real space, deposit buffer cleared
-    HIPCK(field_trial(M, ctx->axes, ca, ctx->trial, ctx->cout, ctx->Jdep, s));
+    HIPCK(field_trial(M, ctx->axes, cn_args(ctx, ctx->jh[cur], ctx->S1[par], stop), ctx->trial[par], ctx->cout,
+                      ctx->Jdep, s));
   }
-  if (part == OUTER_ALL || part == OUTER_ORBIT) {
+  if (part == OUTER_ALL || part == OUTER_ORBIT || part == OUTER_TAIL) {
     // timed launches record their own start and stop (never inside a captured graph:
     // timed graph runs launch the orbit pass eagerly)
     const bool timed = ctx->timed_now && (part == OUTER_ORBIT || stop != nullptr);
-    OrbitArgs oa = orbit_args(ctx, 1);
+    OrbitArgs oa = orbit_args(ctx, 1, par);
     oa.stop = stop;
     HIPCK(launch_orbit(oa, ctx->ngl, s, timed ? e0 : nullptr, timed ? e1 : nullptr));
     ctx->vin_first = false;  // later passes of the step start from their predecessor's v_out
   }
-  if (part == OUTER_ALL || part == OUTER_POST) {
+  if (part == OUTER_ALL || part == OUTER_POST || part == OUTER_TAIL) {
     // H(j) = P J_orb in spectral and real space, with the residual partials
     ResidualArgs ra{};
     ra.M = M;
     ra.tol_abs = ctx->cfg.tol_outer_abs;
     ra.tol_rel = ctx->cfg.tol_outer_rel;
     ra.j = ctx->jr[cur];
-    ra.gphi = ctx->trial;
-    ra.Uh = ctx->trial + (int64_t)(d + 3) * Ng;
+    ra.gphi = ctx->trial[par];
+    ra.Uh = ctx->trial[par] + (int64_t)(d + 3) * Ng;
     ra.partials = ctx->partials + (size_t)ctx->max_blocks * 8;  // disjoint from orbit partials
     ra.stop = stop;
-    int rb = 0;
-    HIPCK(field_h(M, ctx->axes, ctx->Jdep, ctx->jh[hs], ctx->cscr, ctx->jr[hs], ctx->cfg.project_nyquist != 0, ra,
-                  &rb, s));
+    const bool proj = ctx->cfg.project_nyquist != 0;
     // pass and residual sums, then (device control) the outer test
     const ReduceSet ro{ctx->partials, orbit_blocks(ctx), 1, ctx->max_blocks, kOrbitParts, 1u << OP_ITMAX, ctx->dres};
-    const ReduceSet rr{ra.partials, rb, kResParts, 1, kResParts, 1u << 3, ctx->dres + kResOff};
+    ReduceSet rr{ra.partials, 0, kResParts, 1, kResParts, 1u << 3, ctx->dres + kResOff};
     OuterTest ot{};
     if (stop)
       ot = OuterTest{ctx->dres, kResOff, ctx->dctl, ctx->dacc, k, 3.0 * (double)Ng, ctx->cfg.tol_outer_abs,
                      ctx->cfg.tol_outer_rel};
+    if (next) {
+      // the next iteration's trial fields are solved and transformed beside these passes
+      const int np1 = par ^ 1;
+      HIPCK(field_h_next(M, ctx->axes, ctx->Jdep, ctx->jh[hs], ctx->cscr, ctx->jr[hs], proj, ra, ro, rr, ot,
+                         cn_args(ctx, ctx->jh[hs], ctx->S1[np1], stop), ctx->trial[np1], ctx->cout, ctx->Jdep, s));
+      return GMHC_OK;
+    }
+    int rb = 0;
+    HIPCK(field_h(M, ctx->axes, ctx->Jdep, ctx->jh[hs], ctx->cscr, ctx->jr[hs], proj, ra, &rb, s));
+    rr.nblocks = rb;
     HIPCK(launch_reduce_outer(ro, rr, ot, s, stop));
     if (stop) {
       if (ctx->cfg.beta != 1.0)
@@ -782,7 +806,7 @@ int32_t enqueue_outer(gmhc_ctx* ctx, int cur, int hs, int part, const int32_t* s
 int32_t outer_graph(gmhc_ctx* ctx, int cur, int hs, int part, hipGraphExec_t* ex) {
   *ex = nullptr;
   std::vector<uintptr_t> key = {(uintptr_t)cur, (uintptr_t)hs, (uintptr_t)part,
-                                (uintptr_t)ctx->S0, (uintptr_t)ctx->S1, (uintptr_t)ctx->q,
+                                (uintptr_t)ctx->S0, (uintptr_t)ctx->S1[0], (uintptr_t)ctx->q,
                                 (uintptr_t)(ctx->vin_first ? ctx->vb[0] : ctx->vw[0])};
   for (int l = 0; l < 3; ++l) {
     key.push_back((uintptr_t)ctx->x[l]);
@@ -901,14 +925,15 @@ int32_t eval_outer(gmhc_ctx* ctx, int cur, int hs, gmhc_step_report& R, bool& us
 // pwork and mwork are its sum |R_A|^2, particle work and mesh work.
 // With an_done, A^n was already copied on the device (launch_commit_tail).
 int32_t commit_outer(gmhc_ctx* ctx, int cur, double rr, double mr, double ra2, double pwork, double mwork,
-                     bool an_done = false) {
+                     bool an_done = false, int par = 0) {
   const Mesh& M = ctx->M;
   const int64_t Ng = M.Ng, np = ctx->np;
   const int d = M.d;
   hipStream_t s = ctx->stream;
-  std::swap(ctx->S0, ctx->S1);
+  std::swap(ctx->S0, ctx->S1[par]);
   if (!an_done)
-    HIPCK(hipMemcpyAsync(ctx->An, ctx->trial + (int64_t)d * Ng, sizeof(double) * 3 * Ng, hipMemcpyDeviceToDevice, s));
+    HIPCK(hipMemcpyAsync(ctx->An, ctx->trial[par] + (int64_t)d * Ng, sizeof(double) * 3 * Ng,
+                         hipMemcpyDeviceToDevice, s));
   if (cur != 0) {  // the accepted current becomes slot 0
     std::swap(ctx->jr[0], ctx->jr[cur]);
     std::swap(ctx->jh[0], ctx->jh[cur]);
@@ -952,6 +977,8 @@ void begin_step(gmhc_ctx* ctx) {
 // and 2(k-1)+1 around the orbit launch.
 int32_t enqueue_picard_iter(gmhc_ctx* ctx, int k, int cur) {
   const int hs = (cur == 1) ? 2 : 1;
+  // undamped: each iteration also prepares the next one's trial fields
+  const bool next = ctx->cfg.beta == 1.0 && field_h_next_fits(ctx->M, ctx->axes);
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (ctx->timed_now) {
     while ((int)ctx->evs.size() < 2 * k) {
@@ -962,7 +989,7 @@ int32_t enqueue_picard_iter(gmhc_ctx* ctx, int k, int cur) {
     e0 = ctx->evs[2 * (k - 1)];
     e1 = ctx->evs[2 * (k - 1) + 1];
   }
-  return enqueue_outer(ctx, cur, hs, OUTER_ALL, ctx->dctl, k, e0, e1);
+  return enqueue_outer(ctx, cur, hs, (next && k > 1) ? OUTER_TAIL : OUTER_ALL, ctx->dctl, k, e0, e1, next);
 }
 
 // Steps that can start before the caller asks for them: device-controlled Picard
@@ -1023,8 +1050,8 @@ int32_t run_picard(gmhc_ctx* ctx, gmhc_step_report& R) {
     // waits for the host between steps
     if (++ctx->pub_seq == 0) ++ctx->pub_seq;
     const uint32_t want = ctx->pub_seq;
-    HIPCK(launch_commit_tail(ctx->dctl, ctx->dacc, 16, ctx->dpub, want, ctx->trial + (int64_t)M.d * M.Ng, ctx->An,
-                             3 * M.Ng, s));
+    HIPCK(launch_commit_tail(ctx->dctl, ctx->dacc, 16, ctx->dpub, want, ctx->trial[0] + (int64_t)M.d * M.Ng,
+                             ctx->trial[1] + (int64_t)M.d * M.Ng, ctx->An, 3 * M.Ng, s));
     // spin on the sequence number (a blocking wait or an event query adds tens of
     // microseconds of wake-up); the stream is queried now and then so that the wait
     // ends even if the word never arrives
@@ -1061,7 +1088,7 @@ int32_t run_picard(gmhc_ctx* ctx, gmhc_step_report& R) {
         return fail(ctx, GMHC_EINNER,
                     "particle inner solve failed (" + std::to_string((long long)acc[4]) + " particles)");
       ctx->last_outer = c[2];
-      int32_t st = commit_outer(ctx, slot[c[2]], acc[5], acc[6], acc[7], acc[8], acc[9], true);
+      int32_t st = commit_outer(ctx, slot[c[2]], acc[5], acc[6], acc[7], acc[8], acc[9], true, c[2] & 1);
       if (st) return st;
       return run_ahead(ctx);
     }
@@ -1430,10 +1457,10 @@ int32_t gmhc_set_frozen_fields(gmhc_ctx* ctx, const double* gradphi, const doubl
   const int64_t Ng = ctx->M.Ng;
   const int d = ctx->M.d;
   hipStream_t s = ctx->stream;
-  HIPCK(hipMemcpyAsync(ctx->trial, gradphi, sizeof(double) * d * Ng, kind_of(ptr_kind, true), s));
+  HIPCK(hipMemcpyAsync(ctx->trial[0], gradphi, sizeof(double) * d * Ng, kind_of(ptr_kind, true), s));
   HIPCK(hipMemcpyAsync(ctx->An, An, sizeof(double) * 3 * Ng, kind_of(ptr_kind, true), s));
-  HIPCK(hipMemcpyAsync(ctx->trial + d * Ng, Anp1, sizeof(double) * 3 * Ng, kind_of(ptr_kind, true), s));
-  HIPCK(hipMemcpyAsync(ctx->trial + (d + 3) * Ng, Uh, sizeof(double) * 3 * Ng, kind_of(ptr_kind, true), s));
+  HIPCK(hipMemcpyAsync(ctx->trial[0] + d * Ng, Anp1, sizeof(double) * 3 * Ng, kind_of(ptr_kind, true), s));
+  HIPCK(hipMemcpyAsync(ctx->trial[0] + (d + 3) * Ng, Uh, sizeof(double) * 3 * Ng, kind_of(ptr_kind, true), s));
   HIPCK(hipStreamSynchronize(s));
   ctx->frozen = true;
   ctx->initialized = false;  // A^n of the stepping state was replaced

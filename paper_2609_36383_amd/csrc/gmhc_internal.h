@@ -141,7 +141,7 @@ hipError_t launch_reduce(const double* partials, int nblocks, int64_t bstride, i
                          uint32_t max_mask, double* out, hipStream_t s, const int32_t* stop = nullptr);
 
 // Trial fields of the outer iteration: the Crank-Nicolson solve at the trial current
-// (cn.jh; cn.out is unused) computed while loading the first inverse-FFT pass, the new
+// (cn.jh) computed while loading the first inverse-FFT pass, the new
 // state stored to cn.rho1 .. cn.U1, and the real trial fields [d+6][Ng] written to trial
 // (i k phi^{n+1/2} (d), A^{n+1} (3), U^{n+1/2} (3)) through the complex scratch work;
 // zero[3 Ng] is cleared on the way (may be null).  Skipped when *cn.stop is set.
@@ -188,6 +188,18 @@ struct OuterTest {
 hipError_t launch_reduce_outer(const ReduceSet& a, const ReduceSet& b, const OuterTest& t, hipStream_t s,
                                const int32_t* stop);
 
+// field_h, launch_reduce_outer (with rr.nblocks set to the residual's block count) and
+// field_trial of the next iteration in fewer launches, for a next current equal to H
+// (undamped Picard): the next trial fields are solved from the projected spectrum of H
+// and transformed beside H's last pass and beside the reduction, into trial and the new
+// state of cn, through the complex scratch twork (not work).  cn.jh must be spec.
+// Requires field_h_next_fits (the residual folded into the last pass).
+bool field_h_next_fits(const Mesh& M, const FftPlanAxis* axes);
+hipError_t field_h_next(const Mesh& M, const FftPlanAxis* axes, const double* J, double2* spec, double2* work,
+                        double* H, bool project, const ResidualArgs& ra, const ReduceSet& ro, const ReduceSet& rr,
+                        const OuterTest& ot, const CNArgs& cn, double* trial, double2* twork, double* zero,
+                        hipStream_t s);
+
 // Host-visible (coherent pinned) copy of the Picard control block: ctl[0..3] and
 // acc[0..nacc), then seq, written last with a system-scope release.
 struct CtlPublish {
@@ -197,11 +209,12 @@ struct CtlPublish {
 };
 
 // Device-side end of a Picard batch: the control block and accumulators are published
-// to pub with sequence number seq; dst[0..n) = src[0..n) when ctl[0] is set and ctl[1]
-// clear (the step converged); then, when ctl[0] is set, ctl[0..3] and acc[0..nacc) are
+// to pub with sequence number seq; dst[0..n) = src[ctl[2] & 1][0..n) when ctl[0] is set
+// and ctl[1] clear (the step converged at iteration ctl[2], whose trial fields sit in
+// the buffer of its parity); then, when ctl[0] is set, ctl[0..3] and acc[0..nacc) are
 // cleared for the next step.
 hipError_t launch_commit_tail(int32_t* ctl, double* acc, int nacc, const CtlPublish& pub, uint32_t seq,
-                              const double* src, double* dst, int64_t n, hipStream_t s);
+                              const double* src0, const double* src1, double* dst, int64_t n, hipStream_t s);
 
 // y = a x + b z over n values (z may be null).
 hipError_t launch_axpbz(double* y, double a, const double* x, double b, const double* z, int64_t n,

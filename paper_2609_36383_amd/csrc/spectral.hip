@@ -188,16 +188,17 @@ __device__ __forceinline__ int brev_n(int k, int logN) {
 // IN: 0 complex input, 1 real input, 2 CN solve at load
 constexpr int kFftThreads = 1024;  // threads per FFT workgroup at most
 
+// One pass as workgroup (bx, by) of its grid: lines bx T .. bx T + T - 1, components
+// by cpb .. by cpb + cpb - 1.
 template <int IN, bool OUT_REAL>
-__global__ __launch_bounds__(kFftThreads) void k_fft_pass(FftTask t, CNArgs cn, Mesh M, const int32_t* stop) {
-  if (stop && *stop) return;
-  extern __shared__ double2 lds[];
+__device__ __forceinline__ void fft_body(const FftTask& t, const CNArgs& cn, const Mesh& M, int bx, int by,
+                                         double2* lds) {
   const FftPlanAxis& ax = t.ax;
   const int N = ax.N, T = ax.T, logN = ax.logN;  // N and T are powers of two
   const int logT = 31 - __clz(T);
   const int64_t Ng = M.Ng;
-  const int64_t comp0 = (int64_t)blockIdx.y * t.cpb;
-  const int64_t line0 = (int64_t)blockIdx.x * T;
+  const int64_t comp0 = (int64_t)by * t.cpb;
+  const int64_t line0 = (int64_t)bx * T;
   const int per = T * N, total = per * t.cpb;
   // twiddles exp(-2 pi i m / N), m < N/2, staged once after the lines when they fit
   double2* twl = lds + total;
@@ -346,9 +347,30 @@ __global__ __launch_bounds__(kFftThreads) void k_fft_pass(FftTask t, CNArgs cn, 
       double acc = shd[v];
       for (int w = 1; w < (int)(blockDim.x / 64); ++w)
         acc = (v == 3) ? fmax(acc, shd[w * kResParts + v]) : acc + shd[w * kResParts + v];
-      t.ra.partials[(int64_t)blockIdx.x * kResParts + v] = acc;
+      t.ra.partials[(int64_t)bx * kResParts + v] = acc;
     }
   }
+}
+
+template <int IN, bool OUT_REAL>
+__global__ __launch_bounds__(kFftThreads) void k_fft_pass(FftTask t, CNArgs cn, Mesh M, const int32_t* stop) {
+  if (stop && *stop) return;
+  extern __shared__ double2 lds[];
+  fft_body<IN, OUT_REAL>(t, cn, M, blockIdx.x, blockIdx.y, lds);
+}
+
+// Two independent passes in one launch: workgroup b < n1 is workgroup (b mod gx1,
+// b div gx1) of pass 1, workgroup n1 + b' is (b' mod gx2, b' div gx2) of pass 2.
+template <int IN1, bool OUT1, int IN2, bool OUT2>
+__global__ __launch_bounds__(kFftThreads) void k_fft_pass2(FftTask t1, int gx1, int n1, FftTask t2, int gx2,
+                                                           CNArgs cn, Mesh M, const int32_t* stop) {
+  if (stop && *stop) return;
+  extern __shared__ double2 lds[];
+  const int b = blockIdx.x;
+  if (b < n1)
+    fft_body<IN1, OUT1>(t1, cn, M, b % gx1, b / gx1, lds);
+  else
+    fft_body<IN2, OUT2>(t2, cn, M, (b - n1) % gx2, (b - n1) / gx2, lds);
 }
 
 // Reduction of one value over nblocks partials p[b * bstride] (max or sum) by a
@@ -445,12 +467,12 @@ __device__ void outer_test(const OuterTest& t) {
 // (ticket ctl[3], left at zero) runs the outer test.
 constexpr int kRedThreads = 1024;  // threads per workgroup of the merged reduction
 
-__global__ __launch_bounds__(kRedThreads) void k_reduce_outer(ReduceSet a, ReduceSet b, OuterTest t,
-                                                              const int32_t* stop) {
-  if (stop && *stop) return;
-  const bool inb = (int)blockIdx.x >= a.nvals;
+// Workgroup bx of the nred = a.nvals + b.nvals reduction workgroups (kRedThreads each).
+__device__ __forceinline__ void reduce_outer_body(const ReduceSet& a, const ReduceSet& b, const OuterTest& t,
+                                                  int bx, int nred) {
+  const bool inb = bx >= a.nvals;
   const ReduceSet& r = inb ? b : a;
-  const int v = inb ? (int)blockIdx.x - a.nvals : (int)blockIdx.x;
+  const int v = inb ? bx - a.nvals : bx;
   const double x = reduce_value<kRedThreads>(r.p + (int64_t)v * r.vstride, r.nblocks, r.bstride, (r.max_mask >> v) & 1u);
   __shared__ int s_last;
   if (threadIdx.x == 0) {
@@ -458,7 +480,7 @@ __global__ __launch_bounds__(kRedThreads) void k_reduce_outer(ReduceSet a, Reduc
     s_last = 0;
     if (t.ctl) {
       __threadfence();  // the value is visible before the ticket counts it
-      s_last = atomicAdd(&t.ctl[3], 1) == (int)gridDim.x - 1;
+      s_last = atomicAdd(&t.ctl[3], 1) == nred - 1;
     }
   }
   __syncthreads();
@@ -469,15 +491,39 @@ __global__ __launch_bounds__(kRedThreads) void k_reduce_outer(ReduceSet a, Reduc
   }
 }
 
+__global__ __launch_bounds__(kRedThreads) void k_reduce_outer(ReduceSet a, ReduceSet b, OuterTest t,
+                                                              const int32_t* stop) {
+  if (stop && *stop) return;
+  reduce_outer_body(a, b, t, blockIdx.x, gridDim.x);
+}
+
+// The reduction with its outer test and an independent FFT pass in one launch: the first
+// a.nvals + b.nvals workgroups reduce, workgroup nred + e is workgroup (e mod gx,
+// e div gx) of the pass.
+template <int IN, bool OUT_REAL>
+__global__ __launch_bounds__(kRedThreads) void k_reduce_fft(ReduceSet a, ReduceSet b, OuterTest t, FftTask te,
+                                                            int gx, CNArgs cn, Mesh M, const int32_t* stop) {
+  if (stop && *stop) return;
+  const int nred = a.nvals + b.nvals;
+  if ((int)blockIdx.x < nred) {
+    reduce_outer_body(a, b, t, blockIdx.x, nred);
+    return;
+  }
+  extern __shared__ double2 lds[];
+  const int e = (int)blockIdx.x - nred;
+  fft_body<IN, OUT_REAL>(te, cn, M, e % gx, e / gx, lds);
+}
+
 // End of a Picard batch on the device: the first thread publishes the control block and
 // the report accumulators to host memory, the sequence number last (the host spins on
 // it); when the outer test stopped the step with success (ctl[0] set, ctl[1] clear),
-// A^{n+1} of the trial fields becomes A^n (k_commit_copy); once the step stopped either
+// A^{n+1} of the converged iteration's trial fields (the buffer of its parity) becomes
+// A^n (k_commit_copy); once the step stopped either
 // way, the control block and the report accumulators are cleared for the next step
 // (k_ctl_reset, a separate launch so every copying workgroup has read ctl first).
 __global__ __launch_bounds__(kBlock) void k_commit_copy(const int32_t* ctl, const double* acc, int nacc,
-                                                        CtlPublish pub, uint32_t seq, const double* src,
-                                                        double* dst, int64_t n) {
+                                                        CtlPublish pub, uint32_t seq, const double* src0,
+                                                        const double* src1, double* dst, int64_t n) {
   static_assert(kBlock >= 4 + 16, "one value per thread");
   if (blockIdx.x == 0) {  // one value per thread, then the sequence number
     const int l = threadIdx.x;
@@ -489,6 +535,7 @@ __global__ __launch_bounds__(kBlock) void k_commit_copy(const int32_t* ctl, cons
     if (l == 0) __hip_atomic_store(pub.seq, seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
   }
   if (!ctl[0] || ctl[1]) return;
+  const double* src = (ctl[2] & 1) ? src1 : src0;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
     dst[i] = src[i];
 }
@@ -796,13 +843,24 @@ bool fits(const FftPlanAxis& ax, int cpb) { return (int64_t)cpb * ax.N <= kFftLd
 
 // Launch one pass over ncomp components (ncomp a multiple of t.cpb); in: 0 complex,
 // 1 real, 2 CN solve.  The number of workgroups along x goes to *nblk when asked.
-hipError_t fft_pass(const Mesh& M, FftTask t, int ncomp, int in, bool out_real, const CNArgs* cn, hipStream_t s,
-                    const int32_t* stop, int* nblk = nullptr) {
+// Launch shape of one pass over ncomp components.
+struct PassShape {
+  FftTask t;      // with the lines per workgroup and the twiddle staging filled in
+  unsigned gx;    // workgroups along the lines
+  unsigned ny;    // workgroups along the components
+  int threads;
+  size_t lds;     // dynamic LDS bytes
+};
+
+// With want_threads, the lines per workgroup are instead as many as give that many
+// butterflies per stage (for a launch whose workgroup size is fixed by another part).
+hipError_t shape_pass(FftTask t, int ncomp, PassShape& p, int want_threads = 0) {
   FftPlanAxis& ax = t.ax;
   const int cpb = t.cpb;
   // lines per workgroup: enough workgroups to cover the chip (>= 512 when the mesh
   // allows), the lines and the staged twiddles within kFftLds complex values
-  int64_t T = (ax.nlines * (ncomp / cpb)) / 512;
+  int64_t T = want_threads > 0 ? (2 * (int64_t)want_threads) / ((int64_t)cpb * ax.N)
+                               : (ax.nlines * (ncomp / cpb)) / 512;
   T = std::max<int64_t>(1, std::min<int64_t>(T, std::max<int64_t>(1, kFftLds / ((int64_t)ax.N * cpb))));
   T = std::min<int64_t>(T, ax.nlines);
   while (T & (T - 1)) T &= T - 1;  // a power of two (nlines is one)
@@ -817,9 +875,21 @@ hipError_t fft_pass(const Mesh& M, FftTask t, int ncomp, int in, bool out_real, 
   const size_t lds = std::max<size_t>(sizeof(double) * (kFftThreads / 64) * kResParts,
                                       sizeof(double2) * ((size_t)cpb * ax.T * ax.N +
                                                          (ax.lds_tw ? (size_t)std::max(ax.N / 2, 1) : 0)));
-  const dim3 grid(gx, (unsigned)(ncomp / cpb));
+  p = PassShape{t, gx, (unsigned)(ncomp / cpb), threads, lds};
+  return hipSuccess;
+}
+
+hipError_t fft_pass(const Mesh& M, FftTask task, int ncomp, int in, bool out_real, const CNArgs* cn, hipStream_t s,
+                    const int32_t* stop, int* nblk = nullptr) {
+  PassShape p;
+  hipError_t err = shape_pass(task, ncomp, p);
+  if (err != hipSuccess) return err;
+  const FftTask& t = p.t;
+  const dim3 grid(p.gx, p.ny);
+  const int threads = p.threads;
+  const size_t lds = p.lds;
   const CNArgs c0 = cn ? *cn : CNArgs{};
-  if (nblk) *nblk = (int)gx;
+  if (nblk) *nblk = (int)p.gx;
   if (in == 2) {
     if (out_real)
       hipLaunchKernelGGL((k_fft_pass<2, true>), grid, dim3(threads), lds, s, t, c0, M, stop);
@@ -866,20 +936,65 @@ hipError_t fft_nd(const Mesh& M, const FftPlanAxis* axes, int ncomp, const doubl
   return hipSuccess;
 }
 
+namespace {
+
+// field_trial's pass over axis l: the CN solve at load (l = 0), the inverse along l, and on
+// the last axis the real trial fields with `zero` cleared.
+FftTask trial_task(const Mesh& M, const FftPlanAxis* axes, int l, double* trial, double2* work, double* zero) {
+  FftTask t{};
+  t.ax = axes[l];
+  t.cpb = 1;
+  t.inv = 1;
+  t.src_c = work;
+  t.dst_c = work;
+  t.dst_r = trial;
+  t.zero = (l == M.d - 1) ? zero : nullptr;
+  return t;
+}
+
+// field_h's forward pass over axis l < d - 1 (real J in on axis 0).
+FftTask h_forward_task(const FftPlanAxis* axes, int l, const double* J, double2* work) {
+  FftTask t{};
+  t.ax = axes[l];
+  t.cpb = 1;
+  t.fwd = 1;
+  t.src_r = J;
+  t.src_c = work;
+  t.dst_c = work;
+  return t;
+}
+
+// field_h's pass over axis l of its inverse sweep: on axis d - 1 the forward transform
+// first, the projected spectrum out, then the inverse; on axis 0 H out and, with
+// fuse_res, the residual folded.
+FftTask h_inverse_task(const Mesh& M, const FftPlanAxis* axes, int l, const double* J, double2* spec,
+                       double2* work, double* H, bool project, bool fuse_res, const ResidualArgs& ra) {
+  const bool top = (l == M.d - 1), last = (l == 0);
+  FftTask t{};
+  t.ax = axes[l];
+  t.fwd = top ? 1 : 0;
+  t.inv = 1;
+  t.project = (top && project) ? 1 : 0;
+  t.cpb = (last && fuse_res) ? 3 : 1;
+  t.res = (last && fuse_res) ? 1 : 0;
+  t.src_r = J;
+  t.src_c = work;
+  t.dst_c = work;
+  t.dst_r = H;
+  t.spec = spec;
+  t.ra = ra;
+  t.ra.H = H;
+  return t;
+}
+
+}  // namespace
+
 hipError_t field_trial(const Mesh& M, const FftPlanAxis* axes, const CNArgs& cn, double* trial, double2* work,
                        double* zero, hipStream_t s) {
   const int d = M.d;
   for (int l = 0; l < d; ++l) {
-    const bool last = (l == d - 1);
-    FftTask t{};
-    t.ax = axes[l];
-    t.cpb = 1;
-    t.inv = 1;
-    t.src_c = work;
-    t.dst_c = work;
-    t.dst_r = trial;
-    t.zero = last ? zero : nullptr;
-    hipError_t e = fft_pass(M, t, d + 6, l == 0 ? 2 : 0, last, &cn, s, cn.stop);
+    hipError_t e = fft_pass(M, trial_task(M, axes, l, trial, work, zero), d + 6, l == 0 ? 2 : 0, l == d - 1, &cn, s,
+                            cn.stop);
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
@@ -892,36 +1007,15 @@ hipError_t field_h(const Mesh& M, const FftPlanAxis* axes, const double* J, doub
   const bool fuse_res = fits(axes[0], 3);
   // forward passes of axes 0 .. d-2
   for (int l = 0; l < d - 1; ++l) {
-    FftTask t{};
-    t.ax = axes[l];
-    t.cpb = 1;
-    t.fwd = 1;
-    t.src_r = J;
-    t.src_c = work;
-    t.dst_c = work;
-    hipError_t e = fft_pass(M, t, 3, l == 0 ? 1 : 0, false, nullptr, s, stop);
+    hipError_t e = fft_pass(M, h_forward_task(axes, l, J, work), 3, l == 0 ? 1 : 0, false, nullptr, s, stop);
     if (e != hipSuccess) return e;
   }
   // axis d-1: forward, projected spectrum out, then its inverse; then the inverse passes
   // of axes d-2 .. 0.  The last pass (axis 0) writes H and folds the residual.
   for (int l = d - 1; l >= 0; --l) {
-    const bool top = (l == d - 1), last = (l == 0);
-    FftTask t{};
-    t.ax = axes[l];
-    t.fwd = top ? 1 : 0;
-    t.inv = 1;
-    t.project = (top && project) ? 1 : 0;
-    t.cpb = (last && fuse_res) ? 3 : 1;
-    t.res = (last && fuse_res) ? 1 : 0;
-    t.src_r = J;
-    t.src_c = work;
-    t.dst_c = work;
-    t.dst_r = H;
-    t.spec = spec;
-    t.ra = ra;
-    t.ra.H = H;
+    const FftTask t = h_inverse_task(M, axes, l, J, spec, work, H, project, fuse_res, ra);
     int nb = 0;
-    hipError_t e = fft_pass(M, t, 3, (top && d == 1) ? 1 : 0, last, nullptr, s, stop, &nb);
+    hipError_t e = fft_pass(M, t, 3, (l == d - 1 && d == 1) ? 1 : 0, l == 0, nullptr, s, stop, &nb);
     if (e != hipSuccess) return e;
     if (t.res) *res_blocks = nb;
   }
@@ -932,6 +1026,75 @@ hipError_t field_h(const Mesh& M, const FftPlanAxis* axes, const double* J, doub
     hipLaunchKernelGGL(k_residual, dim3(rb), dim3(kBlock), 0, s, r);
     *res_blocks = rb;
     return hipGetLastError();
+  }
+  return hipSuccess;
+}
+
+bool field_h_next_fits(const Mesh& M, const FftPlanAxis* axes) { return fits(axes[0], 3); }
+
+hipError_t field_h_next(const Mesh& M, const FftPlanAxis* axes, const double* J, double2* spec, double2* work,
+                        double* H, bool project, const ResidualArgs& ra, const ReduceSet& ro, const ReduceSet& rr,
+                        const OuterTest& ot, const CNArgs& cn, double* trial, double2* twork, double* zero,
+                        hipStream_t s) {
+  const int d = M.d;
+  const int32_t* stop = ra.stop;
+  if (!fits(axes[0], 3)) return hipErrorInvalidValue;
+  // the passes of field_h down to axis 1, unchanged
+  for (int l = 0; l < d - 1; ++l) {
+    hipError_t e = fft_pass(M, h_forward_task(axes, l, J, work), 3, l == 0 ? 1 : 0, false, nullptr, s, stop);
+    if (e != hipSuccess) return e;
+  }
+  for (int l = d - 1; l >= 1; --l) {
+    hipError_t e = fft_pass(M, h_inverse_task(M, axes, l, J, spec, work, H, project, true, ra), 3, 0, false,
+                            nullptr, s, stop);
+    if (e != hipSuccess) return e;
+  }
+  const FftTask th = h_inverse_task(M, axes, 0, J, spec, work, H, project, true, ra);
+  const FftTask tc = trial_task(M, axes, 0, trial, twork, zero);
+  PassShape ph, pc;
+  hipError_t e = shape_pass(th, 3, ph);
+  if (e == hipSuccess) e = shape_pass(tc, d + 6, pc);
+  // sharing one launch (d > 1), the narrower pass takes more lines per workgroup
+  if (e == hipSuccess && d > 1 && ph.threads != pc.threads)
+    e = ph.threads < pc.threads ? shape_pass(th, 3, ph, pc.threads) : shape_pass(tc, d + 6, pc, ph.threads);
+  if (e != hipSuccess) return e;
+  ReduceSet rrh = rr;
+  rrh.nblocks = (int)ph.gx;  // residual partials: one set per workgroup of the H pass
+  const int nred = ro.nvals + rrh.nvals;
+  if (d == 1) {
+    // the H pass stores the spectrum that the CN solve reads: it runs first, then the
+    // reduction beside the CN pass (which is also the trial fields' last)
+    hipLaunchKernelGGL((k_fft_pass<1, true>), dim3(ph.gx, ph.ny), dim3(ph.threads), ph.lds, s, ph.t, CNArgs{}, M,
+                       stop);
+    PassShape pd;
+    e = shape_pass(trial_task(M, axes, 0, trial, twork, zero), d + 6, pd, kRedThreads);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((k_reduce_fft<2, true>), dim3((unsigned)nred + pd.gx * pd.ny), dim3(kRedThreads), pd.lds, s,
+                       ro, rrh, ot, pd.t, (int)pd.gx, cn, M, stop);
+    return hipGetLastError();
+  }
+  // axis 0: H with the residual fold beside the CN solve and axis-0 inverse of the next
+  // trial fields (the spectrum it reads was stored by the axis d-1 pass)
+  const unsigned n1 = ph.gx * ph.ny, n2 = pc.gx * pc.ny;
+  hipLaunchKernelGGL((k_fft_pass2<0, true, 2, false>), dim3(n1 + n2), dim3(std::max(ph.threads, pc.threads)),
+                     std::max(ph.lds, pc.lds), s, ph.t, (int)ph.gx, (int)n1, pc.t, (int)pc.gx, cn, M, stop);
+  // the reduction and outer test beside the trial fields' axis-1 inverse
+  PassShape pe;
+  e = shape_pass(trial_task(M, axes, 1, trial, twork, zero), d + 6, pe, kRedThreads);
+  if (e != hipSuccess) return e;
+  const dim3 ge((unsigned)nred + pe.gx * pe.ny);
+  if (d == 2)
+    hipLaunchKernelGGL((k_reduce_fft<0, true>), ge, dim3(kRedThreads), pe.lds, s, ro, rrh, ot, pe.t, (int)pe.gx, cn,
+                       M, stop);
+  else
+    hipLaunchKernelGGL((k_reduce_fft<0, false>), ge, dim3(kRedThreads), pe.lds, s, ro, rrh, ot, pe.t, (int)pe.gx,
+                       cn, M, stop);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  // the trial fields' remaining axes
+  for (int l = 2; l < d; ++l) {
+    e = fft_pass(M, trial_task(M, axes, l, trial, twork, zero), d + 6, 0, l == d - 1, &cn, s, stop);
+    if (e != hipSuccess) return e;
   }
   return hipSuccess;
 }
@@ -956,10 +1119,10 @@ hipError_t launch_reduce_outer(const ReduceSet& a, const ReduceSet& b, const Out
 }
 
 hipError_t launch_commit_tail(int32_t* ctl, double* acc, int nacc, const CtlPublish& pub, uint32_t seq,
-                              const double* src, double* dst, int64_t n, hipStream_t s) {
+                              const double* src0, const double* src1, double* dst, int64_t n, hipStream_t s) {
   const unsigned blocks = (unsigned)std::max<int64_t>(1, std::min<int64_t>((n + kBlock - 1) / kBlock, 1024));
   hipLaunchKernelGGL(k_commit_copy, dim3(blocks), dim3(kBlock), 0, s, (const int32_t*)ctl, (const double*)acc,
-                     nacc, pub, seq, src, dst, n);
+                     nacc, pub, seq, src0, src1, dst, n);
   hipLaunchKernelGGL(k_ctl_reset, dim3(1), dim3(64), 0, s, ctl, acc, nacc);
   return hipGetLastError();
 }

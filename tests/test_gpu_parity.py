@@ -225,6 +225,15 @@ def test_frozen_fields_require_initialize_before_step():
     assert st == G.OK
 
 
+def test_damped_picard_parity():
+    """Damped Picard (beta < 1) under the device outer test, which keeps the separate
+    field passes and the damped update, against the oracle's damped Picard."""
+    sim, osim, gd, od, worst = _run_pair("weibel2d", dict(n=(16, 16), ppc=8), 10, 5,
+                                         gpu_over=dict(beta=0.7), orc_over=dict(beta=0.7))
+    assert worst["x"] < 1e-9 and worst["P"] < 1e-9 and worst["v"] < 1e-9
+    assert max(d["energy_rel"] for d in gd) < 1e-11
+
+
 def test_mode_amplitude_and_fields_match():
     G = _gpu()
     sim, osim, gd, od, worst = _run_pair("tsi1d", {}, 5, 5)
