@@ -1174,14 +1174,18 @@ __attribute__((amdgpu_waves_per_eu(orbit_waves<D, R>()))) void k_orbit(OrbitArgs
         if (v[c] != 0.0) atomicAdd(a.J + (int64_t)c * M.Ng + g, v[c]);
     }
   }
-  // workgroup (one wave) reduction in a fixed order
-  double tot[kOrbitParts];
+  // workgroup (one wave) reduction in a fixed order: the sums by one reduce-scatter (the
+  // lane that ends up holding a total stores it), the maximum by a DPP maximum
+  static_assert(kOrbitParts <= 16 && kOrbitBlock == 64, "one reduce-scatter of 16 over one wave");
+  double v[16];
 #pragma unroll
-  for (int v = 0; v < kOrbitParts; ++v)
-    tot[v] = (v == OP_ITMAX) ? wave_reduce_f64<true>(part[v]) : wave_reduce_f64<false>(part[v]);
-  if (threadIdx.x == 0)
-#pragma unroll
-    for (int v = 0; v < kOrbitParts; ++v) a.partials[(int64_t)v * a.pstride + blockIdx.x] = tot[v];
+  for (int k = 0; k < 16; ++k) v[k] = (k < kOrbitParts && k != OP_ITMAX) ? part[k] : 0.0;
+  const int lane = threadIdx.x;
+  const double tot = wave_reduce_scatter<16>(v, lane);
+  const double itmax = wave_reduce_f64<true>(part[OP_ITMAX]);
+  const int idx = wave_slot<16>(lane);
+  if (wave_owner<16>(lane) && idx < kOrbitParts)
+    a.partials[(int64_t)idx * a.pstride + blockIdx.x] = idx == OP_ITMAX ? itmax : tot;
 }
 
 template <int D, int NGL, class R>
