@@ -61,9 +61,13 @@ def gamma_weibel(k, v0, dx, kappa=1.0, sigma1=1.0, rho0=1.0, r=2):
 
 
 def fit_growth(t, amp, t0, t1):
-    """Least-squares slope of log(amp) against t over [t0, t1]."""
+    """Least-squares slope of log(amp) against t over the closed window [t0, t1] (the
+    results section fits over closed time windows).  Sample times within 1e-9 of the
+    window edges count as inside, so a time accumulated step by step that rounds just
+    past t1 keeps its sample."""
     t = np.asarray(t)
     amp = np.asarray(amp)
-    sel = (t >= t0) & (t <= t1)
+    eps = 1e-9 * max(1.0, abs(t1))
+    sel = (t >= t0 - eps) & (t <= t1 + eps)
     slope, _ = np.polyfit(t[sel], np.log(amp[sel]), 1)
     return float(slope)

@@ -19,12 +19,20 @@ m = |q|, uniform immobile neutralizing background):
             phases, dt = 0.1, 50 steps.
   weibel3d  3D Weibel, 128^3, dx = 0.2, beams u_z = +-0.8 with spread 0.01,
             32 particles/cell (67,108,864), dt = 0.05, 50 steps.
+  wbi       the paper's cold relativistic Weibel/filamentation run: [-pi, pi]^3 on 32^3
+            (dy = pi/16), 25 pairs/cell (1,638,400), beams v = +-0.9 x, the growing
+            eigenmode of k_y = 1 with B0 = 1e-4 in the fields and the particles, dt = 0.04
+            (WBI-0.04; dt = 0.2 is WBI-0.2), 2500 steps, the paper's tolerances.  The
+            caller supplies the growth rate eig_gamma; potentials(w) gives A0, U0.
 
-Beam loading: 1D workloads use a quiet start (both beams share the positions
+Beam loading: 1D workloads and wbi use a quiet start (both beams share the positions
 x_j = lo + (j + 1/2) L / N_beam, weights carry the density perturbation).  2D and 3D
 workloads place ppc/2 symmetry-related pairs per cell at uniform random positions;
 the two members of a pair share the position and have opposite momenta
 +-(u_d e + du), du ~ N(0, sigma^2 I), so the initial current and net momentum vanish.
+wbi places the pairs of every cell at the cell's y centre, on the same a x b lattice in
+(x, z) (a b = pairs per cell, as square as it divides), so the node density is uniform and
+every cell samples the y-dependent eigenmode at the same height as one pair per cell.
 """
 import math
 
@@ -53,6 +61,9 @@ WORKLOADS = {
                       steps=50, ppc=1024, u_drift=1.0, eps=1e-3, modes=tuple(range(1, 9)), seed=4),
     "weibel3d": dict(kind="pairs", dim=3, n=(128, 128, 128), dx=0.2, dt=0.05, steps=50, ppc=32,
                      drift_axis=2, u_drift=0.8, u_spread=0.01, seed=5),
+    "wbi": dict(kind="wbi", dim=3, n=(32, 32, 32), dx=None, lo=(-math.pi,) * 3, length=(2.0 * math.pi,) * 3,
+                dt=0.04, steps=2500, ppc=50, v0=0.9, B0=1e-4, ky_mode=1, eig_gamma=None,
+                tol=dict(tol_outer_abs=1e-13, tol_outer_rel=1e-11, tol_inner_abs=1e-14, tol_inner_rel=1e-12)),
 }
 
 
@@ -64,7 +75,7 @@ def spec(name, **over):
     d = w["dim"]
     if w["kind"] == "pairs":
         w["length"] = tuple(w["n"][i] * w["dx"] for i in range(d))
-    w["lo"] = (0.0,) * d
+    w["lo"] = tuple(w["lo"]) if "lo" in w else (0.0,) * d
     w["n"] = tuple(int(v) for v in w["n"])
     ncell = int(np.prod(w["n"]))
     w["num_particles"] = ncell * int(w["ppc"])
@@ -75,7 +86,7 @@ def config_dict(w, fp32_bulk=False):
     """Mesh, physics and solver settings of a workload as plain keyword values."""
     d = dict(dim=w["dim"], n=tuple(w["n"]), lo=tuple(w["lo"]), length=tuple(w["length"]), dt=w["dt"])
     d.update(COMMON)
-    d.update(_tol(fp32_bulk))
+    d.update(w["tol"] if "tol" in w and not fp32_bulk else _tol(fp32_bulk))
     d.update(max_outer=80, max_inner=64, beta=1.0)
     return d
 
@@ -84,7 +95,66 @@ def particles(w):
     """Initial arrays (x [d][N], u = p/(m kappa) [3][N], q [N]) of a workload."""
     if w["kind"] == "quiet1d":
         return _quiet1d(w)
+    if w["kind"] == "wbi":
+        return _wbi(w)
     return _pairs(w)
+
+
+def potentials(w):
+    """Initial potentials (A0, U0) [3][Ng] of a workload, or None when they start at zero."""
+    if w["kind"] != "wbi":
+        return None
+    n = w["n"]
+    ky = 2.0 * math.pi * w["ky_mode"] / w["length"][1]
+    y = w["lo"][1] + np.arange(n[1]) * (w["length"][1] / n[1])
+    # node g = i0 + n0 (i1 + n1 i2): the y index is (g // n0) % n1
+    ng = int(np.prod(n))
+    yg = y[(np.arange(ng) // n[0]) % n[1]]
+    A0 = np.zeros((3, ng))
+    U0 = np.zeros((3, ng))
+    A0[0] = w["B0"] / ky * np.cos(ky * yg)
+    U0[0] = w["eig_gamma"] * A0[0]
+    return A0, U0
+
+
+def _wbi(w):
+    """The paper's Weibel eigenmode loading: for stream s = +-1 at height y,
+      v_x = s v0 + chi B0 cos(k y) / (k g0^3),  v_y = s chi v0 B0 sin(k y) / (g0 Gamma),
+      weight 1 - s chi v0 k B0 cos(k y) / (g0 Gamma^2),
+    with chi = sinc(k dy / 2)^3 and Gamma = eig_gamma (from the caller)."""
+    if not w.get("eig_gamma"):
+        raise ValueError("wbi needs eig_gamma (the Weibel growth rate)")
+    n, L, lo = w["n"], w["length"], w["lo"]
+    dx = [L[i] / n[i] for i in range(3)]
+    npair = w["ppc"] // 2
+    a = max(f for f in range(1, int(math.isqrt(npair)) + 1) if npair % f == 0)
+    b = npair // a
+    ncell = int(np.prod(n))
+    cells = np.repeat(np.arange(ncell, dtype=np.int64), npair)
+    sub = np.tile(np.arange(npair, dtype=np.int64), ncell)
+    ci = (cells % n[0], (cells // n[0]) % n[1], cells // (n[0] * n[1]))
+    frac = ((sub % a + 0.5) / a, np.full(sub.size, 0.5), (sub // a + 0.5) / b)
+    pos = [lo[i] + (ci[i] + frac[i]) * dx[i] for i in range(3)]
+    v0, B0, G = w["v0"], w["B0"], w["eig_gamma"]
+    g0 = 1.0 / math.sqrt(1.0 - v0 * v0)
+    k = 2.0 * math.pi * w["ky_mode"] / L[1]
+    z = 0.5 * k * dx[1]
+    chi = (math.sin(z) / z) ** 3
+    cy, sy = np.cos(k * pos[1]), np.sin(k * pos[1])
+    xs = np.empty((3, 2 * cells.size))
+    u = np.zeros((3, 2 * cells.size))
+    q = np.empty(2 * cells.size)
+    qc = float(np.prod(dx)) / w["ppc"]
+    for s, sl in ((1.0, slice(0, None, 2)), (-1.0, slice(1, None, 2))):
+        for i in range(3):
+            xs[i, sl] = pos[i]
+        vx = s * v0 + chi * B0 * cy / (k * g0 ** 3)
+        vy = s * chi * v0 * B0 * sy / (g0 * G)
+        gam = 1.0 / np.sqrt(1.0 - vx * vx - vy * vy)
+        u[0, sl] = gam * vx
+        u[1, sl] = gam * vy
+        q[sl] = -qc * (1.0 - s * chi * v0 * k * B0 * cy / (g0 * G * G))
+    return xs, u, q
 
 
 def _quiet1d(w):
