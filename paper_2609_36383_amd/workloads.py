@@ -19,20 +19,26 @@ m = |q|, uniform immobile neutralizing background):
             phases, dt = 0.1, 50 steps.
   weibel3d  3D Weibel, 128^3, dx = 0.2, beams u_z = +-0.8 with spread 0.01,
             32 particles/cell (67,108,864), dt = 0.05, 50 steps.
+  tsi       the paper's cold relativistic two-stream run: [-4 pi, 4 pi]^3 on 32^3
+            (dx = pi/4), 10 pairs/cell (655,360), beams v = +-0.9 x, the growing
+            eigenmode of k_x = 1/4 with grid charge density 5e-3 cos(k x') (E_x =
+            0.02 sin(k x'), x' = x - lo), dt = 0.1 (TSI-0.1; dt = 0.3 is TSI-0.3), 600
+            steps, the paper's tolerances.  The caller supplies eig_gamma.
   wbi       the paper's cold relativistic Weibel/filamentation run: [-pi, pi]^3 on 32^3
             (dy = pi/16), 25 pairs/cell (1,638,400), beams v = +-0.9 x, the growing
             eigenmode of k_y = 1 with B0 = 1e-4 in the fields and the particles, dt = 0.04
             (WBI-0.04; dt = 0.2 is WBI-0.2), 2500 steps, the paper's tolerances.  The
             caller supplies the growth rate eig_gamma; potentials(w) gives A0, U0.
 
-Beam loading: 1D workloads and wbi use a quiet start (both beams share the positions
+Beam loading: 1D workloads, tsi and wbi use a quiet start (both beams share the positions
 x_j = lo + (j + 1/2) L / N_beam, weights carry the density perturbation).  2D and 3D
 workloads place ppc/2 symmetry-related pairs per cell at uniform random positions;
 the two members of a pair share the position and have opposite momenta
 +-(u_d e + du), du ~ N(0, sigma^2 I), so the initial current and net momentum vanish.
-wbi places the pairs of every cell at the cell's y centre, on the same a x b lattice in
-(x, z) (a b = pairs per cell, as square as it divides), so the node density is uniform and
-every cell samples the y-dependent eigenmode at the same height as one pair per cell.
+tsi and wbi place the pairs of every cell evenly along x, x = lo + (i + (j + 1/2) / npair) dx,
+at the cell centre in y and z; the two members of a pair share the position.  This loading
+reproduces the growth rates the paper prints for both runs.  Eigenmode perturbations are
+applied to the velocities (u = gamma(v) v afterwards) and to the weights.
 """
 import math
 
@@ -61,6 +67,10 @@ WORKLOADS = {
                       steps=50, ppc=1024, u_drift=1.0, eps=1e-3, modes=tuple(range(1, 9)), seed=4),
     "weibel3d": dict(kind="pairs", dim=3, n=(128, 128, 128), dx=0.2, dt=0.05, steps=50, ppc=32,
                      drift_axis=2, u_drift=0.8, u_spread=0.01, seed=5),
+    "tsi": dict(kind="tsi", dim=3, n=(32, 32, 32), dx=None, lo=(-4.0 * math.pi,) * 3,
+                length=(8.0 * math.pi,) * 3, dt=0.1, steps=600, ppc=20, v0=0.9, alpha=5e-3, kx_mode=1,
+                eig_gamma=None,
+                tol=dict(tol_outer_abs=1e-13, tol_outer_rel=1e-11, tol_inner_abs=1e-13, tol_inner_rel=1e-11)),
     "wbi": dict(kind="wbi", dim=3, n=(32, 32, 32), dx=None, lo=(-math.pi,) * 3, length=(2.0 * math.pi,) * 3,
                 dt=0.04, steps=2500, ppc=50, v0=0.9, B0=1e-4, ky_mode=1, eig_gamma=None,
                 tol=dict(tol_outer_abs=1e-13, tol_outer_rel=1e-11, tol_inner_abs=1e-14, tol_inner_rel=1e-12)),
@@ -97,6 +107,8 @@ def particles(w):
         return _quiet1d(w)
     if w["kind"] == "wbi":
         return _wbi(w)
+    if w["kind"] == "tsi":
+        return _tsi(w)
     return _pairs(w)
 
 
@@ -117,6 +129,59 @@ def potentials(w):
     return A0, U0
 
 
+def _pairs_along_x(w):
+    """Pair positions [d][ncell npair]: npair per cell evenly along x, cell centre in y, z."""
+    n, L, lo = w["n"], w["length"], w["lo"]
+    d = len(n)
+    npair = w["ppc"] // 2
+    ncell = int(np.prod(n))
+    cells = np.repeat(np.arange(ncell, dtype=np.int64), npair)
+    sub = np.tile(np.arange(npair, dtype=np.int64), ncell)
+    pos = []
+    rem = cells
+    for i in range(d):
+        ci = rem % n[i]
+        rem = rem // n[i]
+        frac = (sub + 0.5) / npair if i == 0 else np.full(sub.size, 0.5)
+        pos.append(lo[i] + (ci + frac) * (L[i] / n[i]))
+    return pos
+
+
+def _tsi(w):
+    """The paper's two-stream eigenmode loading.  For the gathered field chi E (E = E0
+    sin(k x'), E0 = sigma1 alpha rho0 / k, chi = sinc(k dx / 2)^3) and stream s = +-1 with
+    w_s = i Gamma - k s v0, the linear cold-fluid response is dv_s = i (q/m) chi E_c /
+    (g0^3 w_s) (E_c = -i E0 the complex amplitude) and dn_s = k dv_s / w_s: velocity s v0 +
+    Re(dv_s e^{i k x'}) along x and relative weight 1 + Re(dn_s e^{i k x'})."""
+    if not w.get("eig_gamma"):
+        raise ValueError("tsi needs eig_gamma (the two-stream growth rate)")
+    n, L, lo = w["n"], w["length"], w["lo"]
+    d = len(n)
+    pos = _pairs_along_x(w)
+    v0, G = w["v0"], w["eig_gamma"]
+    g0 = 1.0 / math.sqrt(1.0 - v0 * v0)
+    k = 2.0 * math.pi * w["kx_mode"] / L[0]
+    dx = L[0] / n[0]
+    z = 0.5 * k * dx
+    chi = (math.sin(z) / z) ** 3
+    Ec = -1j * w["alpha"] / k  # sigma1 = rho0 = 1
+    ph = np.exp(1j * k * (pos[0] - lo[0]))
+    m = pos[0].size
+    xs = np.empty((d, 2 * m))
+    u = np.zeros((3, 2 * m))
+    q = np.empty(2 * m)
+    qc = float(np.prod([L[i] / n[i] for i in range(d)])) / w["ppc"]
+    for s, sl in ((1.0, slice(0, None, 2)), (-1.0, slice(1, None, 2))):
+        for i in range(d):
+            xs[i, sl] = pos[i]
+        ws = 1j * G - k * s * v0
+        dv = 1j * (-1.0) * chi * Ec / (g0 ** 3 * ws)
+        vx = s * v0 + np.real(dv * ph)
+        u[0, sl] = vx / np.sqrt(1.0 - vx * vx)
+        q[sl] = -qc * (1.0 + np.real(k * dv / ws * ph))
+    return xs, u, q
+
+
 def _wbi(w):
     """The paper's Weibel eigenmode loading: for stream s = +-1 at height y,
       v_x = s v0 + chi B0 cos(k y) / (k g0^3),  v_y = s chi v0 B0 sin(k y) / (g0 Gamma),
@@ -126,24 +191,16 @@ def _wbi(w):
         raise ValueError("wbi needs eig_gamma (the Weibel growth rate)")
     n, L, lo = w["n"], w["length"], w["lo"]
     dx = [L[i] / n[i] for i in range(3)]
-    npair = w["ppc"] // 2
-    a = max(f for f in range(1, int(math.isqrt(npair)) + 1) if npair % f == 0)
-    b = npair // a
-    ncell = int(np.prod(n))
-    cells = np.repeat(np.arange(ncell, dtype=np.int64), npair)
-    sub = np.tile(np.arange(npair, dtype=np.int64), ncell)
-    ci = (cells % n[0], (cells // n[0]) % n[1], cells // (n[0] * n[1]))
-    frac = ((sub % a + 0.5) / a, np.full(sub.size, 0.5), (sub // a + 0.5) / b)
-    pos = [lo[i] + (ci[i] + frac[i]) * dx[i] for i in range(3)]
+    pos = _pairs_along_x(w)
     v0, B0, G = w["v0"], w["B0"], w["eig_gamma"]
     g0 = 1.0 / math.sqrt(1.0 - v0 * v0)
     k = 2.0 * math.pi * w["ky_mode"] / L[1]
     z = 0.5 * k * dx[1]
     chi = (math.sin(z) / z) ** 3
     cy, sy = np.cos(k * pos[1]), np.sin(k * pos[1])
-    xs = np.empty((3, 2 * cells.size))
-    u = np.zeros((3, 2 * cells.size))
-    q = np.empty(2 * cells.size)
+    xs = np.empty((3, 2 * pos[0].size))
+    u = np.zeros((3, 2 * pos[0].size))
+    q = np.empty(2 * pos[0].size)
     qc = float(np.prod(dx)) / w["ppc"]
     for s, sl in ((1.0, slice(0, None, 2)), (-1.0, slice(1, None, 2))):
         for i in range(3):
@@ -183,10 +240,11 @@ def _eigen1d(w, xj, u):
 
     The caller supplies the growth rate ``eig_gamma`` and the field amplitude ``eig_E``
     (E_x = eig_E sin(k x) after the field solve).  For beam s with drift s v0 and
-    w' = i Gamma - k s v0, linear cold-fluid theory gives the momentum perturbation
-    du = i (q/m) chi E / w' (chi = sinc(k dx / 2)^3 is the gathered-field factor) and
-    the relative density (weight) perturbation k (du / g0^3) / w'.  Modifies ``u`` in
-    place and returns the charges.
+    w' = i Gamma - k s v0, linear cold-fluid theory gives the velocity perturbation
+    dv = i (q/m) chi E / (g0^3 w') (chi = sinc(k dx / 2)^3 is the gathered-field factor)
+    and the relative density (weight) perturbation k dv / w'.  The perturbation is
+    applied to the velocity (u = gamma(v) v), as for the tsi workload.  Modifies ``u``
+    in place and returns the charges.
     """
     L = w["length"][0]
     nb = xj.size
@@ -202,10 +260,10 @@ def _eigen1d(w, xj, u):
     w0 = 0.5 * (L / nb)
     for s, sl in ((1.0, slice(0, nb)), (-1.0, slice(nb, 2 * nb))):
         wp = 1j * w["eig_gamma"] - k * s * v0
-        du = 1j * (-1.0) * chi * E1 / wp
-        dw = k * (du / g0 ** 3) / wp
-        u[0, sl] = s * u0 + np.real(du * phase)
-        q[sl] = -w0 * (1.0 + np.real(dw * phase))
+        dv = 1j * (-1.0) * chi * E1 / (g0 ** 3 * wp)
+        vx = s * v0 + np.real(dv * phase)
+        u[0, sl] = vx / np.sqrt(1.0 - vx * vx)
+        q[sl] = -w0 * (1.0 + np.real(k * dv / wp * phase))
     return q
 
 
