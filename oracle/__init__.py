@@ -46,7 +46,8 @@ class EvalOut(C.Structure):
 
 class Report(C.Structure):
     _fields_ = [("outer_iters", C.c_int32), ("inner_max", C.c_int32), ("inner_mean", C.c_double),
-                ("evaluations", C.c_int64), ("res_rms_ratio", C.c_double), ("res_max_ratio", C.c_double)]
+                ("evaluations", C.c_int64), ("res_rms_ratio", C.c_double), ("res_max_ratio", C.c_double),
+                ("outer_updates", C.c_int32), ("pad", C.c_int32)]
 
 
 class Diag(C.Structure):

@@ -95,6 +95,8 @@ struct orc_report {
   int64_t evaluations;      // orbit evaluations over all outer iterations
   double res_rms_ratio;     // RMS test ratio at exit (<=1 passes)
   double res_max_ratio;     // max-node test ratio at exit
+  int32_t outer_updates;    // accepted outer updates (the algorithm's outer iterations are this + 1)
+  int32_t pad;
 };
 
 struct orc_diag {
@@ -1406,6 +1408,7 @@ int orc_step(void* h, orc_report* rep) {
           }
           E = std::move(Et);
           accepted = true;
+          ++R.outer_updates;
           break;
         }
         if (!anderson) {
@@ -1419,6 +1422,7 @@ int orc_step(void* h, orc_report* rep) {
             }
           E = std::move(Et);
           accepted = true;
+          ++R.outer_updates;
           break;
         }
       }

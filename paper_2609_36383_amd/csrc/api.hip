@@ -1075,6 +1075,7 @@ int32_t run_picard(gmhc_ctx* ctx, gmhc_step_report& R) {
         R.orbit_ms += (double)f;
       }
     R.outer_iters = ran;
+    R.outer_updates = ran - 1;  // every evaluation after the first follows one Picard update
     R.orbit_launches = ran;
     R.evaluations = (int64_t)llround(acc[0]);
     R.segments = (int64_t)llround(acc[1]);
@@ -1219,6 +1220,7 @@ int32_t step_anderson(gmhc_ctx* ctx, gmhc_step_report& R, bool& use_graph) {
           err = rr;
           emr = mr;
           accepted = true;
+          ++R.outer_updates;
           break;
         }
       }
@@ -1264,6 +1266,7 @@ int32_t gmhc_step(gmhc_ctx* ctx, gmhc_step_report* rep) {
     if (ctx->cfg.beta != 1.0)
       HIPCK(launch_axpy2(ctx->jr[hs], ctx->jr[cur], ctx->jh[hs], ctx->jh[cur], 1.0 - ctx->cfg.beta, 3 * Ng,
                          3 * Ng, s));
+    ++R.outer_updates;
     cur = hs;
   }
   return done(fail(ctx, GMHC_ENOCONV, "outer iteration limit reached"));

@@ -15,7 +15,7 @@ LIB_PATH = os.path.join(HERE, "libgmhc.so")
 
 OK, EINVAL, ESTATE, ENOMEM, EDEVICE, EINNER, ENOCONV = 0, -1, -2, -3, -4, -5, -6
 HOST, DEVICE = 0, 1
-ABI_VERSION = 2  # layout of the structures below (include/gmhc.h, GMHC_ABI_VERSION)
+ABI_VERSION = 3  # layout of the structures below (include/gmhc.h, GMHC_ABI_VERSION)
 FP64, FP32_BULK = 0, 1
 PICARD, ANDERSON = 0, 1
 FIELD = {"phi": 0, "psi": 1, "A": 2, "U": 3, "rho": 4, "J": 5, "E": 6, "B": 7}
@@ -51,7 +51,7 @@ class StepReport(C.Structure):
     _fields_ = [("outer_iters", C.c_int32), ("inner_max", C.c_int32), ("inner_mean", C.c_double),
                 ("evaluations", C.c_int64), ("res_rms_ratio", C.c_double), ("res_max_ratio", C.c_double),
                 ("orbit_ms", C.c_double), ("orbit_launches", C.c_int32), ("graph_replays", C.c_int32),
-                ("segments", C.c_int64)]
+                ("segments", C.c_int64), ("outer_updates", C.c_int32), ("reserved", C.c_int32)]
 
 
 class Diag(C.Structure):

@@ -43,3 +43,24 @@ def test_tsi_fitted_growth_rate_equals_printed(run):
     assert abs(fit - g["fitted_rate"]) <= 5e-9, fit
     assert abs(abs(fit / GTS - 1) - g["fitted_rate_rel_err"]) < 0.01e-3
     assert drift < 1e-12
+
+
+def test_tsi_0p3_anderson_outer_counts_match_printed():
+    """TSI-0.3 through T = 60 with the paper's Anderson settings: the outer iterations as
+    the paper's algorithm counts them (accepted updates plus one) average within 5% of
+    the printed mean, and their maximum equals the printed one."""
+    g = GOLD["TSI-0.3"]
+    w = W.spec("tsi", dim=1, n=(32,), lo=(-4.0 * math.pi,), length=(8.0 * math.pi,), dt=g["dt"], eig_gamma=GTS)
+    x, u, q = W.particles(w)
+    sim = O.OracleSim(O.config_from_dict(W.config_dict(w), gl_order=8, outer_scheme=1, beta=0.5))
+    sim.load_particles(x, u, q)
+    sim.initialize()
+    counts = []
+    for _ in range(int(round(g["end_time"] / g["dt"]))):
+        _, rep = sim.step()
+        counts.append(rep["outer_updates"] + 1)
+    mean = sum(counts) / len(counts)
+    assert abs(mean / g["outer_mean"] - 1) < 0.05, mean
+    assert max(counts) == g["outer_max"]
+    # the amplitude at T = 60 (nonlinear trapping) equals the printed one
+    assert abs(sim.mode_amplitude("E", 0, (1, 0, 0)) - g["amp_T60"]) <= 5e-8
