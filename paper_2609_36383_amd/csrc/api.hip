@@ -693,23 +693,8 @@ int32_t gmhc_initialize(gmhc_ctx* ctx) {
 // pass, the field step after it, and the last two together.
 enum OuterPart { OUTER_ALL = 0, OUTER_PRE = 1, OUTER_ORBIT = 2, OUTER_POST = 3, OUTER_TAIL = 4 };
 
-// Device work of one outer iteration for the trial current in slot cur, with H(j)
-// written to slot hs: CN field step and trial fields (PRE), the orbit pass with its
-// inner Picard loop (ORBIT, bracketed by the timing events when timing is on), then
-// the pass reduction, projected orbit current, outer residual and the copy of the
-// results to pinned host memory (POST).  Enqueued without host synchronization, so
-// the parts can be captured as HIP graphs.
-//
-// With a device control block (stop != nullptr) every kernel first checks the stop flag
-// and returns when an earlier iteration already converged or failed; the iteration ends
-// with the device-side outer test of iteration k and, for beta < 1, the damped update of
-// the next trial current in slot hs, instead of copying the results to the host.
-//
-// The trial fields and new-time spectra of iteration k live in the buffers of parity
-// k & 1 (host-controlled iterations pass k = 0).  With next (undamped Picard under device
-// control) POST also solves and transforms those of iteration k + 1 into the other
-// parity, from the projected spectrum of H, which is that iteration's current; it then
-// runs as OUTER_TAIL, without PRE.  The iteration that converges keeps its own buffers.
+// CN solve arguments: the trial current spectrum jh against the accepted state S0, new
+// state into S1.
 CNArgs cn_args(const gmhc_ctx* ctx, const double2* jh, double2* S1, const int32_t* stop) {
   const int64_t Ng = ctx->M.Ng;
   CNArgs ca{};
@@ -733,6 +718,24 @@ CNArgs cn_args(const gmhc_ctx* ctx, const double2* jh, double2* S1, const int32_
   return ca;
 }
 
+// Device work of one outer iteration for the trial current in slot cur, with H(j)
+// written to slot hs: CN field step and trial fields (PRE), the orbit pass with its
+// inner Picard loop (ORBIT, bracketed by the timing events when timing is on), then
+// the pass reduction, projected orbit current, outer residual and the copy of the
+// results to pinned host memory (POST).  Enqueued without host synchronization, so
+// the parts can be captured as HIP graphs.
+//
+// With a device control block (stop != nullptr) every kernel first checks the stop flag
+// and returns when an earlier iteration already converged or failed; the iteration ends
+// with the device-side outer test of iteration k and, for beta < 1, the damped update of
+// the next trial current in slot hs, instead of copying the results to the host.
+//
+// The trial fields and new-time spectra of iteration k live in the buffers of parity
+// k & 1 (host-controlled iterations pass k = 0).  With next (undamped Picard under device
+// control) POST also solves and transforms those of iteration k + 1 into the other
+// parity, from the projected spectrum of H, which is that iteration's current; the next
+// iteration then runs as OUTER_TAIL, without PRE.  The iteration that converges keeps its
+// own buffers.
 int32_t enqueue_outer(gmhc_ctx* ctx, int cur, int hs, int part, const int32_t* stop = nullptr, int k = 0,
                       hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr, bool next = false) {
   const Mesh& M = ctx->M;
