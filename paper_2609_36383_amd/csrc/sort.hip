@@ -1,8 +1,11 @@
 // sort.hip -- counting sort of the particle SoA by nearest-node cell, so that the
 // particles a workgroup processes are spatially close (mesh reads and deposits then
 // hit the same cache lines).  Histogram with integer atomics, two-level exclusive scan,
-// scatter through per-cell cursors.  The order inside one cell is not specified; a
-// particle-id array travels with the data so results can be returned in load order.
+// scatter through per-cell cursors.  Both atomic passes aggregate over the wave: the
+// lanes that share a cell take one atomic for the group, and each lane its rank in lane
+// order, so particles of one wave keep their order within a cell; the order of different
+// waves within a cell is not specified.  A particle-id array travels with the data so
+// results can be returned in load order.
 #include <math.h>
 
 #include "gmhc_internal.h"
@@ -17,20 +20,45 @@ __device__ __forceinline__ int wrapi(int i, int n) {
   return r < 0 ? r + n : r;
 }
 
-__global__ __launch_bounds__(kBlock) void k_cell_key(SortArgs a) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= a.np) return;
-  int64_t g = 0, mul = 1;
-  for (int l = 0; l < a.M.d; ++l) {
-    const double xi = (a.x[l][i] - a.M.lo[l]) * a.M.inv_h[l];
-    // positions are finite and inside the box; clamp anything else into range
-    double r = floor(xi + 0.5);
-    if (!(r > -1.0e9 && r < 1.0e9)) r = 0.0;
-    g += (int64_t)wrapi((int)r, a.M.n[l]) * mul;
-    mul *= a.M.n[l];
+// ctr[key] += (number of active lanes of the wave with this key), one atomic per
+// distinct key; returns the value before the group's addition plus the lane's rank
+// among the group's lanes in lane order.  Called by every lane of the wave.
+__device__ __forceinline__ int32_t wave_group_add(int32_t* ctr, int32_t key, bool active) {
+  const int lane = (int)(threadIdx.x & 63);
+  uint64_t todo = __ballot(active);
+  int32_t mine = 0;
+  while (todo) {
+    const int leader = __ffsll((long long)todo) - 1;
+    const int32_t k = __builtin_amdgcn_readlane(key, leader);
+    const uint64_t grp = __ballot(key == k) & todo;
+    int32_t base = 0;
+    if (lane == leader) base = atomicAdd(ctr + k, __popcll(grp));
+    base = __builtin_amdgcn_readlane(base, leader);
+    if ((grp >> lane) & 1ull) mine = base + __popcll(grp & ((1ull << lane) - 1ull));
+    todo &= ~grp;
   }
-  a.key[i] = (int32_t)g;
-  atomicAdd(a.count + g, 1);
+  return mine;
+}
+
+__global__ __launch_bounds__(kBlock) void k_cell_key(SortArgs a) {
+  static_assert(kBlock % 64 == 0, "whole waves");
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const bool valid = i < a.np;
+  int32_t g = 0;
+  if (valid) {
+    int64_t mul = 1, gg = 0;
+    for (int l = 0; l < a.M.d; ++l) {
+      const double xi = (a.x[l][i] - a.M.lo[l]) * a.M.inv_h[l];
+      // positions are finite and inside the box; clamp anything else into range
+      double r = floor(xi + 0.5);
+      if (!(r > -1.0e9 && r < 1.0e9)) r = 0.0;
+      gg += (int64_t)wrapi((int)r, a.M.n[l]) * mul;
+      mul *= a.M.n[l];
+    }
+    g = (int32_t)gg;
+    a.key[i] = g;
+  }
+  (void)wave_group_add(a.count, g, valid);
 }
 
 // exclusive scan of count[0..n) in place; block sums to bsum
@@ -85,8 +113,10 @@ __global__ __launch_bounds__(kScanBlock) void k_scan_add(int32_t* data, int64_t 
 
 __global__ __launch_bounds__(kBlock) void k_scatter(SortArgs a) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= a.np) return;
-  const int32_t pos = atomicAdd(a.cursor + a.key[i], 1);
+  const bool valid = i < a.np;
+  const int32_t key = valid ? a.key[i] : 0;
+  const int32_t pos = wave_group_add(a.cursor, key, valid);
+  if (!valid) return;
   for (int c = 0; c < a.ncomp; ++c) {
     if (a.esz[c] == 4)
       static_cast<uint32_t*>(a.dst[c])[pos] = static_cast<const uint32_t*>(a.src[c])[i];
