@@ -48,7 +48,9 @@ struct gmhc_ctx {
   int32_t* iters = nullptr;
   int32_t* key = nullptr;
   // mesh
-  double* An = nullptr;     // [3][Ng] real A^n
+  double* tacc = nullptr;   // [d+6][Ng] block in the trial layout whose A part is A^n; at
+                            // commit it trades places with the converged trial block
+  double* An = nullptr;     // [3][Ng] real A^n (= tacc + d Ng)
   double* trial[2] = {};    // [d+6][Ng] real: grad phi^{n+1/2}, A^{n+1}, U^{n+1/2}, by parity
   double* Jdep = nullptr;   // [3][Ng]
   double* jr[3] = {};       // real current slots [3][Ng]; slot 0 = accepted J^{n-1/2}
@@ -208,7 +210,8 @@ size_t carve(gmhc_ctx* c, char* base, int64_t np) {
   c->id2 = cv.take<int32_t>(N);
   c->iters = cv.take<int32_t>(N);
   c->key = cv.take<int32_t>(N);
-  c->An = cv.take<double>(3 * Ng);
+  c->tacc = cv.take<double>((size_t)(d + 6) * Ng);
+  c->An = c->tacc + (size_t)d * Ng;
   for (int p = 0; p < 2; ++p) c->trial[p] = cv.take<double>((size_t)(d + 6) * Ng);
   c->Jdep = cv.take<double>(3 * Ng);
   for (int s = 0; s < 3; ++s) {
@@ -924,19 +927,20 @@ int32_t eval_outer(gmhc_ctx* ctx, int cur, int hs, gmhc_step_report& R, bool& us
   return GMHC_OK;
 }
 
-// Commit the state of the converged evaluation at the trial current in slot cur; ra2,
-// pwork and mwork are its sum |R_A|^2, particle work and mesh work.
-// With an_done, A^n was already copied on the device (launch_commit_tail).
+// Commit the state of the converged evaluation at the trial current in slot cur, whose
+// trial fields and new-time spectra sit in the buffers of parity par; ra2, pwork and
+// mwork are its sum |R_A|^2, particle work and mesh work.
 int32_t commit_outer(gmhc_ctx* ctx, int cur, double rr, double mr, double ra2, double pwork, double mwork,
-                     bool an_done = false, int par = 0) {
+                     int par = 0) {
   const Mesh& M = ctx->M;
   const int64_t Ng = M.Ng, np = ctx->np;
   const int d = M.d;
-  hipStream_t s = ctx->stream;
   std::swap(ctx->S0, ctx->S1[par]);
-  if (!an_done)
-    HIPCK(hipMemcpyAsync(ctx->An, ctx->trial[par] + (int64_t)d * Ng, sizeof(double) * 3 * Ng,
-                         hipMemcpyDeviceToDevice, s));
+  // A^{n+1} of the converged trial fields becomes A^n: their block takes the place of
+  // the accepted one, whose storage the next trial fields of this parity reuse (the
+  // device work of the step has finished or is ordered before any later use)
+  std::swap(ctx->tacc, ctx->trial[par]);
+  ctx->An = ctx->tacc + (int64_t)d * Ng;
   if (cur != 0) {  // the accepted current becomes slot 0
     std::swap(ctx->jr[0], ctx->jr[cur]);
     std::swap(ctx->jh[0], ctx->jh[cur]);
@@ -1036,7 +1040,6 @@ int32_t run_picard(gmhc_ctx* ctx, gmhc_step_report& R) {
     if (!ctx->ctl_clean) HIPCK(hipMemsetAsync(ctx->dctl, 0, kCtlBytes, s));
     ctx->ctl_clean = false;
   }
-  const Mesh& M = ctx->M;
   const bool timed = ctx->timed_now;
   int batch = std::max(1, std::min(ctx->last_outer, maxo));
   int k0 = 0;
@@ -1048,13 +1051,12 @@ int32_t run_picard(gmhc_ctx* ctx, gmhc_step_report& R) {
       if (st) return st;
       cur = (cur == 1) ? 2 : 1;
     }
-    // the batch-end kernel publishes the control block to host memory; the converged
-    // step's A^n copy and the control reset run on the device behind it, so nothing
-    // waits for the host between steps
+    // the batch-end kernel publishes the control block to host memory and, once the step
+    // stopped, clears it for the next step on the device, so nothing waits for the host
+    // between steps
     if (++ctx->pub_seq == 0) ++ctx->pub_seq;
     const uint32_t want = ctx->pub_seq;
-    HIPCK(launch_commit_tail(ctx->dctl, ctx->dacc, 16, ctx->dpub, want, ctx->trial[0] + (int64_t)M.d * M.Ng,
-                             ctx->trial[1] + (int64_t)M.d * M.Ng, ctx->An, 3 * M.Ng, s));
+    HIPCK(launch_ctl_publish(ctx->dctl, ctx->dacc, 16, ctx->dpub, want, s));
     // spin on the sequence number (a blocking wait or an event query adds tens of
     // microseconds of wake-up); the stream is queried now and then so that the wait
     // ends even if the word never arrives
@@ -1087,12 +1089,12 @@ int32_t run_picard(gmhc_ctx* ctx, gmhc_step_report& R) {
     R.res_rms_ratio = acc[5];
     R.res_max_ratio = acc[6];
     if (c[0]) {
-      ctx->ctl_clean = true;  // cleared by launch_commit_tail
+      ctx->ctl_clean = true;  // cleared by launch_ctl_publish
       if (c[1])
         return fail(ctx, GMHC_EINNER,
                     "particle inner solve failed (" + std::to_string((long long)acc[4]) + " particles)");
       ctx->last_outer = c[2];
-      int32_t st = commit_outer(ctx, slot[c[2]], acc[5], acc[6], acc[7], acc[8], acc[9], true, c[2] & 1);
+      int32_t st = commit_outer(ctx, slot[c[2]], acc[5], acc[6], acc[7], acc[8], acc[9], c[2] & 1);
       if (st) return st;
       return run_ahead(ctx);
     }

@@ -208,13 +208,11 @@ struct CtlPublish {
   uint32_t* seq;
 };
 
-// Device-side end of a Picard batch: the control block and accumulators are published
-// to pub with sequence number seq; dst[0..n) = src[ctl[2] & 1][0..n) when ctl[0] is set
-// and ctl[1] clear (the step converged at iteration ctl[2], whose trial fields sit in
-// the buffer of its parity); then, when ctl[0] is set, ctl[0..3] and acc[0..nacc) are
-// cleared for the next step.
-hipError_t launch_commit_tail(int32_t* ctl, double* acc, int nacc, const CtlPublish& pub, uint32_t seq,
-                              const double* src0, const double* src1, double* dst, int64_t n, hipStream_t s);
+// Device-side end of a Picard batch (one workgroup, nacc <= 16): ctl[0..3] and
+// acc[0..nacc) are published to pub, then, when ctl[0] is set (the step stopped),
+// cleared for the next step; the sequence number seq is stored last.
+hipError_t launch_ctl_publish(int32_t* ctl, double* acc, int nacc, const CtlPublish& pub, uint32_t seq,
+                              hipStream_t s);
 
 // y = a x + b z over n values (z may be null).
 hipError_t launch_axpbz(double* y, double a, const double* x, double b, const double* z, int64_t n,

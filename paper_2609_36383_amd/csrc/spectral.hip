@@ -514,37 +514,30 @@ __global__ __launch_bounds__(kRedThreads) void k_reduce_fft(ReduceSet a, ReduceS
   fft_body<IN, OUT_REAL>(te, cn, M, e % gx, e / gx, lds);
 }
 
-// End of a Picard batch on the device: the first thread publishes the control block and
-// the report accumulators to host memory, the sequence number last (the host spins on
-// it); when the outer test stopped the step with success (ctl[0] set, ctl[1] clear),
-// A^{n+1} of the converged iteration's trial fields (the buffer of its parity) becomes
-// A^n (k_commit_copy); once the step stopped either
-// way, the control block and the report accumulators are cleared for the next step
-// (k_ctl_reset, a separate launch so every copying workgroup has read ctl first).
-__global__ __launch_bounds__(kBlock) void k_commit_copy(const int32_t* ctl, const double* acc, int nacc,
-                                                        CtlPublish pub, uint32_t seq, const double* src0,
-                                                        const double* src1, double* dst, int64_t n) {
-  static_assert(kBlock >= 4 + 16, "one value per thread");
-  if (blockIdx.x == 0) {  // one value per thread, then the sequence number
-    const int l = threadIdx.x;
-    if (l < 4)
-      pub.ctl[l] = ctl[l];
-    else if (l < 4 + nacc)
-      pub.acc[l - 4] = acc[l - 4];
-    __syncthreads();
-    if (l == 0) __hip_atomic_store(pub.seq, seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+// End of a Picard batch on the device (one workgroup): every value of the control block
+// and the report accumulators is read, published to host memory and, once the outer
+// test stopped the step (ctl[0] set, success or failure), cleared for the next step;
+// the sequence number is stored last (the host spins on it).
+__global__ __launch_bounds__(64) void k_ctl_publish(int32_t* ctl, double* acc, int nacc, CtlPublish pub,
+                                                    uint32_t seq) {
+  const int l = threadIdx.x;
+  const bool stop = ctl[0] != 0;
+  int32_t cv = 0;
+  double av = 0.0;
+  if (l < 4)
+    cv = ctl[l];
+  else if (l < 4 + nacc)
+    av = acc[l - 4];
+  __syncthreads();  // every value read before any is cleared
+  if (l < 4) {
+    pub.ctl[l] = cv;
+    if (stop) ctl[l] = 0;
+  } else if (l < 4 + nacc) {
+    pub.acc[l - 4] = av;
+    if (stop) acc[l - 4] = 0.0;
   }
-  if (!ctl[0] || ctl[1]) return;
-  const double* src = (ctl[2] & 1) ? src1 : src0;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
-    dst[i] = src[i];
-}
-
-__global__ void k_ctl_reset(int32_t* ctl, double* acc, int nacc) {
-  if (threadIdx.x != 0 || !ctl[0]) return;
-  for (int i = 0; i < nacc; ++i) acc[i] = 0.0;
-  ctl[1] = ctl[2] = ctl[3] = 0;
-  ctl[0] = 0;
+  __syncthreads();
+  if (l == 0) __hip_atomic_store(pub.seq, seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
 }
 
 // y = a x + b z over n values (outer-solver vector updates).
@@ -1118,12 +1111,10 @@ hipError_t launch_reduce_outer(const ReduceSet& a, const ReduceSet& b, const Out
   return hipGetLastError();
 }
 
-hipError_t launch_commit_tail(int32_t* ctl, double* acc, int nacc, const CtlPublish& pub, uint32_t seq,
-                              const double* src0, const double* src1, double* dst, int64_t n, hipStream_t s) {
-  const unsigned blocks = (unsigned)std::max<int64_t>(1, std::min<int64_t>((n + kBlock - 1) / kBlock, 1024));
-  hipLaunchKernelGGL(k_commit_copy, dim3(blocks), dim3(kBlock), 0, s, (const int32_t*)ctl, (const double*)acc,
-                     nacc, pub, seq, src0, src1, dst, n);
-  hipLaunchKernelGGL(k_ctl_reset, dim3(1), dim3(64), 0, s, ctl, acc, nacc);
+hipError_t launch_ctl_publish(int32_t* ctl, double* acc, int nacc, const CtlPublish& pub, uint32_t seq,
+                              hipStream_t s) {
+  if (nacc < 0 || nacc > 16) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_ctl_publish, dim3(1), dim3(64), 0, s, ctl, acc, nacc, pub, seq);
   return hipGetLastError();
 }
 
