@@ -96,6 +96,9 @@ def cpu_baseline(w, cfg_dict, ngl, target_s=12.0):
     x, u, q = W.particles(w)
     sim = O.OracleSim(O.config_from_dict(cfg_dict, gl_order=ngl))
     sim.load_particles(x, u, q)
+    pot = W.potentials(w)
+    if pot is not None:
+        sim.load_potentials(*pot)
     sim.initialize()
     evals, steps, el = 0, 0, 0.0
     while steps == 0 or (el < target_s and steps < 50):
@@ -146,6 +149,9 @@ def run_case(args, w, fp32):
     npart = q.size
     sim = G.Simulation(cfg, npart, device="cuda:0")
     sim.load_particles(x, u, q)
+    pot = W.potentials(w)
+    if pot is not None:
+        sim.load_potentials(*pot)
     sim.initialize()
     # relative energy drift, max over the sampled states: every warmup step and the
     # state after the timed steps (diagnostics stay outside the timed region)

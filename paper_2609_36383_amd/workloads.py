@@ -23,12 +23,12 @@ m = |q|, uniform immobile neutralizing background):
             (dx = pi/4), 10 pairs/cell (655,360), beams v = +-0.9 x, the growing
             eigenmode of k_x = 1/4 with grid charge density 5e-3 cos(k x') (E_x =
             0.02 sin(k x'), x' = x - lo), dt = 0.1 (TSI-0.1; dt = 0.3 is TSI-0.3), 600
-            steps, the paper's tolerances.  The caller supplies eig_gamma.
+            steps, the paper's tolerances.  eig_gamma defaults to the printed growth rate.
   wbi       the paper's cold relativistic Weibel/filamentation run: [-pi, pi]^3 on 32^3
             (dy = pi/16), 25 pairs/cell (1,638,400), beams v = +-0.9 x, the growing
             eigenmode of k_y = 1 with B0 = 1e-4 in the fields and the particles, dt = 0.04
-            (WBI-0.04; dt = 0.2 is WBI-0.2), 2500 steps, the paper's tolerances.  The
-            caller supplies the growth rate eig_gamma; potentials(w) gives A0, U0.
+            (WBI-0.04; dt = 0.2 is WBI-0.2), 2500 steps, the paper's tolerances.
+            eig_gamma defaults to the printed growth rate; potentials(w) gives A0, U0.
 
 Beam loading: 1D workloads, tsi and wbi use a quiet start (both beams share the positions
 x_j = lo + (j + 1/2) L / N_beam, weights carry the density perturbation).  2D and 3D
@@ -69,10 +69,11 @@ WORKLOADS = {
                      drift_axis=2, u_drift=0.8, u_spread=0.01, seed=5),
     "tsi": dict(kind="tsi", dim=3, n=(32, 32, 32), dx=None, lo=(-4.0 * math.pi,) * 3,
                 length=(8.0 * math.pi,) * 3, dt=0.1, steps=600, ppc=20, v0=0.9, alpha=5e-3, kx_mode=1,
-                eig_gamma=None,
+                eig_gamma=9.109138040e-2,  # Gamma_TS as the two-stream subsection prints it
                 tol=dict(tol_outer_abs=1e-13, tol_outer_rel=1e-11, tol_inner_abs=1e-13, tol_inner_rel=1e-11)),
     "wbi": dict(kind="wbi", dim=3, n=(32, 32, 32), dx=None, lo=(-math.pi,) * 3, length=(2.0 * math.pi,) * 3,
-                dt=0.04, steps=2500, ppc=50, v0=0.9, B0=1e-4, ky_mode=1, eig_gamma=None,
+                dt=0.04, steps=2500, ppc=50, v0=0.9, B0=1e-4, ky_mode=1,
+                eig_gamma=5.103647904e-1,  # Gamma_W as the Weibel subsection prints it
                 tol=dict(tol_outer_abs=1e-13, tol_outer_rel=1e-11, tol_inner_abs=1e-14, tol_inner_rel=1e-12)),
 }
 
