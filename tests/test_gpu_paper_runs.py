@@ -238,3 +238,43 @@ def test_tsi_nyquist_ablation():
     ref = GOLD_TSI["ablation"]["vperp_rms_unprojected_T60"]
     assert ref / 3 < vp[-1] < 3 * ref
     assert vp[99] < 1e-12  # it starts from roundoff
+
+
+def test_wbi_0p04_through_end_time_on_the_device_controlled_path():
+    """WBI-0.04 through T = 100 (2500 steps) on the default path: undamped Picard under the
+    device outer test, each step enqueued ahead by the previous one, the next iteration's
+    trial fields prepared inside the field step.  The structural residual maxima stay within
+    ten times those the paper prints for this run.  The printed energy maximum comes from
+    an Anderson-accelerated run (Weibel subsection of the numerical results).  Undamped
+    Picard accepts each step with its residual just under the outer tolerance, and once the
+    instability turns nonlinear the energy change grows by about 1e-15 per step; the oracle
+    shows the same on a reduced mesh (3.8e-13 by T = 20 under Picard, 5.9e-14 under
+    Anderson).  The energy bound is therefore ten outer relative tolerances: the
+    total-energy theorem of the energy-balance section holds at the converged fixed point,
+    and the outer test is what stands between the accepted iterate and that point."""
+    G = _gpu()
+    g = GOLD["WBI-0.04"]
+    steps = int(round(g["end_time"] / g["dt"]))
+    w = W.spec("wbi", dt=g["dt"], eig_gamma=GW)
+    sim = G.Simulation(G.config_from_dict(W.config_dict(w), gl_order=0, sort_every=10), w["num_particles"])
+    _load(sim, w)
+    keys = ("energy_rel", "gauss_rms", "lorenz_rms", "chain_rms", "work_residual")
+    worst = dict.fromkeys(keys, 0.0)
+    t0 = time.perf_counter()
+    for s in range(steps):
+        sim.step()
+        d = sim.diagnostics()
+        for k in keys:
+            worst[k] = max(worst[k], abs(d[k]))
+        if (s + 1) % 500 == 0:
+            _say(f"WBI-0.04 step {s + 1}: t {d['t']:.2f} energy {worst['energy_rel']:.2e} "
+                 f"gauss {worst['gauss_rms']:.2e} ({time.perf_counter() - t0:.1f} s)")
+    sim.close()
+    printed = dict(energy_rel=g["max_energy_rel"], gauss_rms=g["max_gauss_rms"], lorenz_rms=g["max_lorenz_rms"],
+                   chain_rms=g["max_chain_rms"], work_residual=g["max_work_residual"])
+    for k in keys:
+        _say(f"WBI-0.04 max {k}: {worst[k]:.3e} (printed {printed[k]:.3e})")
+    assert abs(d["t"] - g["end_time"]) < 1e-9
+    assert worst["energy_rel"] <= 10.0 * W.config_dict(w)["tol_outer_rel"]
+    for k in keys[1:]:
+        assert worst[k] <= 10.0 * printed[k], k
