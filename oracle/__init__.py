@@ -27,7 +27,7 @@ class Config(C.Structure):
         ("max_outer", C.c_int32), ("max_inner", C.c_int32), ("beta", C.c_double),
         ("threads", C.c_int32), ("outer_scheme", C.c_int32), ("anderson_m", C.c_int32),
         ("anderson_start", C.c_int32), ("ls_halvings", C.c_int32), ("anderson_lambda", C.c_double),
-        ("ls_decrease", C.c_double), ("ls_growth", C.c_double),
+        ("ls_decrease", C.c_double), ("ls_growth", C.c_double), ("shape_order", C.c_int32),
     ]
 
 
@@ -74,6 +74,8 @@ def lib():
         L.orc_gl_rule.argtypes = [C.c_int, dp, dp]
         L.orc_shape.argtypes = [C.c_double, dp, dp]
         L.orc_shape.restype = None
+        L.orc_shape_r.argtypes = [C.c_int, C.c_double, dp, dp]
+        L.orc_shape_r.restype = None
         L.orc_hc_map.argtypes = [dp, dp, dp]
         L.orc_hc_map.restype = C.c_double
         L.orc_vdg.argtypes = [dp, dp, C.c_double, C.c_double, dp]
@@ -126,7 +128,8 @@ def _f64(a):
 def make_config(dim, n, lo, length, dt, kappa=1.0, sigma1=1.0, sigma2=1.0, gl_order=8, project=1,
                 tol_outer_abs=1e-14, tol_outer_rel=1e-12, tol_inner_abs=1e-14, tol_inner_rel=1e-12,
                 max_outer=80, max_inner=64, beta=1.0, threads=0, outer_scheme=0, anderson_m=4,
-                anderson_start=2, ls_halvings=6, anderson_lambda=1e-12, ls_decrease=1e-4, ls_growth=1.2):
+                anderson_start=2, ls_halvings=6, anderson_lambda=1e-12, ls_decrease=1e-4, ls_growth=1.2,
+                shape_order=2):
     c = Config()
     c.dim = dim
     for i in range(3):
@@ -140,6 +143,7 @@ def make_config(dim, n, lo, length, dt, kappa=1.0, sigma1=1.0, sigma2=1.0, gl_or
     c.max_outer, c.max_inner, c.beta, c.threads = max_outer, max_inner, beta, threads
     c.outer_scheme, c.anderson_m, c.anderson_start, c.ls_halvings = outer_scheme, anderson_m, anderson_start, ls_halvings
     c.anderson_lambda, c.ls_decrease, c.ls_growth = anderson_lambda, ls_decrease, ls_growth
+    c.shape_order = shape_order
     return c
 
 
@@ -165,10 +169,12 @@ def gl_rule(n):
     return x, w
 
 
-def shape(xi):
+def shape(xi, r=2):
+    """Centered B-spline S_r(xi) of degree r (2: the paper's quadratic; 1: linear) and
+    its derivative."""
     S = C.c_double()
     dS = C.c_double()
-    lib().orc_shape(float(xi), C.byref(S), C.byref(dS))
+    lib().orc_shape_r(int(r), float(xi), C.byref(S), C.byref(dS))
     return S.value, dS.value
 
 

@@ -68,6 +68,8 @@ struct orc_config {
   double anderson_lambda; // regularization lambda (paper: 1e-12)
   double ls_decrease;   // sufficient-decrease coefficient (paper: 1e-4)
   double ls_growth;     // residual-growth limit (paper: 1.2)
+  int32_t shape_order;  // B-spline degree r of the particle shape: 2 (the paper's; 0 selects
+                        // it) or 1, the linear shape of the spline-degree comparison
 };
 
 // One orbit evaluation v_out = F(v_in) of one particle at frozen trial fields.
@@ -180,10 +182,22 @@ double dS2(double xi) {
   return -sg * (t1 - 3.0 * t2);
 }
 
+// Centered linear B-spline S_1(xi) = (1-|xi|)_+, the degree the solver section raises
+// to two (and the r = 1 case of the spline-degree comparison in the results section),
+// and its derivative (one-sided value -sign(xi) inside the support, zero at the knots
+// xi = 0 and |xi| = 1, where quadrature never evaluates it).
+double S1(double xi) { return std::max(1.0 - std::fabs(xi), 0.0); }
+double dS1(double xi) {
+  double a = std::fabs(xi);
+  if (a >= 1.0 || xi == 0.0) return 0.0;
+  return xi > 0.0 ? -1.0 : 1.0;
+}
+
 // ---------------------------------------------------------------------------
 // Mesh geometry.
 struct Mesh {
   int d;
+  int r;  // B-spline degree of the particle shape (1 or 2)
   int n[3];
   double lo[3], len[3], h[3];
   int64_t Ng;
@@ -195,7 +209,7 @@ struct Mesh {
 };
 
 // Shape weights of all candidate nodes around one point.  For each resolved axis,
-// five candidates floor(xi)-2 .. floor(xi)+2 are evaluated with the plain S2
+// five candidates floor(xi)-2 .. floor(xi)+2 are evaluated with the plain S_r
 // definition (nodes outside the support simply get zero).
 struct PointWeights {
   int64_t base[3];
@@ -213,8 +227,8 @@ void point_weights(const Mesh& M, const double x[3], PointWeights& pw) {
       pw.cnt[l] = 5;
       for (int c = 0; c < 5; ++c) {
         double r = xi - (double)(b + c);
-        pw.S[l][c] = S2(r);
-        pw.dS[l][c] = dS2(r) / M.h[l];
+        pw.S[l][c] = M.r == 1 ? S1(r) : S2(r);
+        pw.dS[l][c] = (M.r == 1 ? dS1(r) : dS2(r)) / M.h[l];
       }
     } else {
       pw.base[l] = 0;
@@ -242,7 +256,7 @@ void interp3(const Mesh& M, const double* const F[3], const double x[3], double 
 // ---------------------------------------------------------------------------
 // Knot split of the straight unwrapped orbit x(s) = x + s dx, s in [0,1]
 // (orbit-averaged maps section; knot-split Gaussian quadrature).  Knots of S2
-// centred at nodes lo + g h lie at lo + (j+1/2) h.  Reading: a crossing counts
+// centred at nodes lo + g h lie at lo + (j+1/2) h; those of S1 at the nodes lo + j h.  Reading: a crossing counts
 // only if 0 < s < 1 strictly; zero-length segments are dropped.
 void knot_split(const Mesh& M, const double x[3], const double dx[3], std::vector<double>& s) {
   s.clear();
@@ -254,7 +268,7 @@ void knot_split(const Mesh& M, const double x[3], const double dx[3], std::vecto
     double dxi = dx[l] / M.h[l];
     double a = std::min(xi0, xi0 + dxi), b = std::max(xi0, xi0 + dxi);
     for (int64_t j = (int64_t)std::floor(a) - 1; j <= (int64_t)std::ceil(b) + 1; ++j) {
-      double sk = ((double)j + 0.5 - xi0) / dxi;
+      double sk = ((double)j + (M.r == 1 ? 0.0 : 0.5) - xi0) / dxi;
       if (sk > 0.0 && sk < 1.0) s.push_back(sk);
     }
   }
@@ -547,6 +561,8 @@ struct Sim {
 int setup_mesh(const orc_config* c, Mesh& M, bool need_pow2 = false) {
   if (c->dim < 1 || c->dim > 3) return ORC_EINVAL;
   M.d = c->dim;
+  M.r = c->shape_order == 0 ? 2 : c->shape_order;
+  if (M.r != 1 && M.r != 2) return ORC_EINVAL;
   M.Ng = 1;
   M.dV = 1.0;
   for (int l = 0; l < 3; ++l) {
@@ -799,6 +815,11 @@ int orc_gl_rule(int n, double* x, double* w) {
 void orc_shape(double xi, double* S, double* dS) {
   *S = S2(xi);
   *dS = dS2(xi);
+}
+
+void orc_shape_r(int r, double xi, double* S, double* dS) {
+  *S = r == 1 ? S1(xi) : S2(xi);
+  *dS = r == 1 ? dS1(xi) : dS2(xi);
 }
 
 double orc_hc_map(const double* um, const double* tau, double* up) { return hc_map_u(um, tau, up); }
