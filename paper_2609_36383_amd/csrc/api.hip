@@ -455,6 +455,7 @@ int32_t gmhc_create(const gmhc_config* cfg, gmhc_ctx** out) {
   if (!(c.dt > 0.0) || !(c.kappa > 0.0) || !(c.sigma1 > 0.0) || !(c.sigma2 > 0.0)) return GMHC_EINVAL;
   if (fabs(c.sigma1 - c.kappa * c.kappa * c.sigma2) > 1e-14 * fabs(c.sigma1)) return GMHC_EINVAL;
   if (c.gl_order < 0 || c.gl_order > kMaxGL) return GMHC_EINVAL;
+  if (c.shape_order < 0 || c.shape_order > 2) return GMHC_EINVAL;
   if (c.precision != GMHC_FP64 && c.precision != GMHC_FP32_BULK) return GMHC_EINVAL;
   if (c.max_outer < 1 || c.max_inner < 1 || !(c.beta > 0.0 && c.beta <= 1.0)) return GMHC_EINVAL;
   if (c.timing < 0) return GMHC_EINVAL;
@@ -471,6 +472,7 @@ int32_t gmhc_create(const gmhc_config* cfg, gmhc_ctx** out) {
   ctx->es = c.precision == GMHC_FP32_BULK ? sizeof(float) : sizeof(double);
   Mesh& M = ctx->M;
   M.d = c.dim;
+  M.shape = c.shape_order == 1 ? 1 : 2;
   M.Ng = 1;
   M.dV = 1.0;
   for (int l = 0; l < 3; ++l) {
@@ -485,7 +487,7 @@ int32_t gmhc_create(const gmhc_config* cfg, gmhc_ctx** out) {
     M.Ng *= M.n[l];
     if (r) M.dV *= M.h[l];
   }
-  ctx->ngl = c.gl_order ? c.gl_order : c.dim + 1;
+  ctx->ngl = c.gl_order ? c.gl_order : (M.shape == 1 ? (c.dim + 2) / 2 : c.dim + 1);
   for (int k = 0; k < kMaxGL; ++k) ctx->glx[k] = ctx->glw[k] = 0.0;
   gl01(ctx->ngl, ctx->glx, ctx->glw);
   *out = ctx;

@@ -52,6 +52,7 @@ struct Mesh {
   double inv_h[3];
   double kf[3];      // 2 pi / len (wavenumber of mode 1; 0 on unused axes)
   double dV;
+  int shape;         // B-spline degree of the particle shape (1 or 2)
 };
 
 // Arguments of the orbit pass (one thread per particle).

@@ -5,7 +5,8 @@
 // "Orbit-averaged discrete chain rule", "No-explicit-A_t GM-HC step",
 // "Mechanical split and magnetic zero work"):
 //   1. straight unwrapped orbit x(s) = x^n + s dt v_in, split at the knots of the
-//      quadratic B-spline (half-integer node offsets), Gauss-Legendre on each piece;
+//      B-spline shape (quadratic: half-integer node offsets; linear: the nodes),
+//      Gauss-Legendre on each piece;
 //   2. orbit gathers: grad phi-bar = int sum_g (grad_h phi^{n+1/2})_g S_g ds and the
 //      orbit discrete gradient D_lj = int sum_g ((1-s) A^n + s A^{n+1})_{l,g} d_j S_g ds;
 //   3. endpoint interpolants A^- = A_h^n(x^n), A^+ = A_h^{n+1}(x^n + dt v_in);
@@ -151,44 +152,68 @@ __device__ __forceinline__ bool inside(const Tile& t, const int jn[3]) {
   return r;
 }
 
-// Quadratic B-spline weights of nodes j-1, j, j+1 at local offset f in [-1/2, 1/2] and
-// their derivatives with respect to xi (times h they are d/dx).
-template <class R>
+// B-spline weights of nodes j-1, j, j+1 at local offset f from node j, and their
+// derivatives with respect to xi (times h they are d/dx).  SH = 2: the quadratic S_2,
+// f in [-1/2, 1/2].  SH = 1: the linear S_1 = (1-|xi|)_+ (the degree the paper raises
+// to two); f in [-1, 1] keeps one sign over a knot segment, whose ends are nodes, so the
+// one-sided derivatives are those of the segment.
+template <int SH, class R>
 __device__ __forceinline__ void bw(R f, R w[3], R dw[3]) {
-  const R a = R(0.5) - f, b = R(0.5) + f;
-  w[0] = R(0.5) * a * a;
-  w[1] = R(0.75) - f * f;
-  w[2] = R(0.5) * b * b;
-  dw[0] = -a;
-  dw[1] = R(-2.0) * f;
-  dw[2] = b;
+  if constexpr (SH == 1) {
+    const bool neg = f < R(0);
+    w[0] = neg ? -f : R(0);
+    w[1] = R(1) - fabs(f);
+    w[2] = neg ? R(0) : f;
+    dw[0] = neg ? R(-1) : R(0);
+    dw[1] = neg ? R(1) : R(-1);
+    dw[2] = neg ? R(0) : R(1);
+  } else {
+    const R a = R(0.5) - f, b = R(0.5) + f;
+    w[0] = R(0.5) * a * a;
+    w[1] = R(0.75) - f * f;
+    w[2] = R(0.5) * b * b;
+    dw[0] = -a;
+    dw[1] = R(-2.0) * f;
+    dw[2] = b;
+  }
 }
 // weight and derivative of the single stencil node c (0, 1, 2)
-template <class R>
+template <int SH, class R>
 __device__ __forceinline__ void bw1(R f, int c, R& w, R& dw) {
   const R t = f - R(c - 1);  // offset from node j + c - 1
   const R at = fabs(t);
-  const R o = R(1.5) - at;
-  const R sg = t > R(0) ? R(1) : R(-1);
-  w = c == 1 ? R(0.75) - t * t : R(0.5) * o * o;
-  dw = c == 1 ? R(-2.0) * t : -sg * o;
+  if constexpr (SH == 1) {
+    const R o = R(1) - at;
+    w = o > R(0) ? o : R(0);
+    dw = o > R(0) ? (t > R(0) ? R(-1) : R(1)) : R(0);
+  } else {
+    const R o = R(1.5) - at;
+    const R sg = t > R(0) ? R(1) : R(-1);
+    w = c == 1 ? R(0.75) - t * t : R(0.5) * o * o;
+    dw = c == 1 ? R(-2.0) * t : -sg * o;
+  }
 }
+
+// Knot offset from the nodes of the B-spline of degree SH: half-integer for S_2, the
+// nodes themselves for S_1.
+template <int SH, class R>
+__device__ __forceinline__ constexpr R knot_off() { return SH == 1 ? R(0) : R(0.5); }
 
 // Orbit geometry relative to the particle's node j0: xi(s) = j0 + f0 + s del.
 // Visits the knot-split segments [sa, sb] of s in [0, 1]; each axis' crossings of the
 // half-integer knots are monotone in s and are merged on the fly.
-template <int D, class R, class F>
+template <int D, int SH, class R, class F>
 __device__ __forceinline__ void for_each_segment(const R* f0, const R* del, F&& f) {
   R knot[3], next[3], stp[3], rd[3];
 #pragma unroll
   for (int l = 0; l < D; ++l) {
     rd[l] = del[l] != R(0) ? rcp_(del[l]) : R(0);
     if (del[l] > R(0)) {
-      knot[l] = floor(f0[l] - R(0.5)) + R(1.5);
+      knot[l] = floor(f0[l] - knot_off<SH, R>()) + R(1) + knot_off<SH, R>();
       stp[l] = R(1);
       next[l] = (knot[l] - f0[l]) * rd[l];
     } else if (del[l] < R(0)) {
-      knot[l] = ceil(f0[l] - R(0.5)) - R(0.5);
+      knot[l] = ceil(f0[l] - knot_off<SH, R>()) - R(1) + knot_off<SH, R>();
       stp[l] = R(-1);
       next[l] = (knot[l] - f0[l]) * rd[l];
     } else {
@@ -239,14 +264,14 @@ struct GL {
 };
 
 // Point interpolant sum_g F_g S_g at node jn with local offsets f (field base fb).
-template <int D, class R, bool LDS>
+template <int D, int SH, class R, bool LDS>
 __device__ __forceinline__ void interp3_at(const OrbitArgs& a, const Tile& t, int fb, const int jn[3],
                                            const R f[3], R out[3]) {
   R w[3][3], dw[3][3];
 #pragma unroll
   for (int l = 0; l < 3; ++l) {
     if (l < D) {
-      bw(f[l], w[l], dw[l]);
+      bw<SH>(f[l], w[l], dw[l]);
     } else {
       w[l][0] = R(1);
     }
@@ -270,7 +295,7 @@ __device__ __forceinline__ void interp3_at(const OrbitArgs& a, const Tile& t, in
     }
 }
 
-template <int D, class R>
+template <int D, int SH, class R>
 __device__ __forceinline__ void interp3(const OrbitArgs& a, const Tile& t, int fb, const int j0[3], const R* fr,
                                         R out[3]) {
   int jn[3];
@@ -287,9 +312,9 @@ __device__ __forceinline__ void interp3(const OrbitArgs& a, const Tile& t, int f
     }
   }
   if (inside<D>(t, jn))
-    interp3_at<D, R, true>(a, t, fb, jn, f, out);
+    interp3_at<D, SH, R, true>(a, t, fb, jn, f, out);
   else
-    interp3_at<D, R, false>(a, t, fb, jn, f, out);
+    interp3_at<D, SH, R, false>(a, t, fb, jn, f, out);
 }
 
 // Quadrature of one knot segment for the gathers grad-phi-bar and D.
@@ -303,7 +328,7 @@ __device__ __forceinline__ void interp3(const OrbitArgs& a, const Tile& t, int f
 // This is the same quadrature summed in a different order; each field value is read
 // once per segment and only one row of weights is live at a time.  D is left in xi
 // units and scaled by 1/h afterwards.
-template <int D, int NGL, class R, bool LDS>
+template <int D, int SH, int NGL, class R, bool LDS>
 __device__ __forceinline__ void eval_segment(const OrbitArgs& a, const Tile& t, const R* gx, const R* gw,
                                              const int jn[3], const R fs[3], const R* del, R sa, R sb,
                                              R gp[3], R Dm[3][3]) {
@@ -340,10 +365,10 @@ __device__ __forceinline__ void eval_segment(const OrbitArgs& a, const Tile& t, 
       const R wq = len * gw[q];
       const R b1 = wq * s, a1 = wq - b1;  // w_q s and w_q (1 - s)
       R wx[3], dwx[3];
-      bw(fs[0] + s * del[0], wx, dwx);
+      bw<SH>(fs[0] + s * del[0], wx, dwx);
       R wy = R(1), dwy = R(0), wz = R(1), dwz = R(0);
-      if (D > 1) bw1(fs[1] + s * del[1], cy, wy, dwy);
-      if (D > 2) bw1(fs[2] + s * del[2], cz, wz, dwz);
+      if (D > 1) bw1<SH>(fs[1] + s * del[1], cy, wy, dwy);
+      if (D > 2) bw1<SH>(fs[2] + s * del[2], cz, wz, dwz);
       const R wyz = wy * wz;
       const R sw = wq * wyz, xw0 = a1 * wyz, xw1 = b1 * wyz;
       const R yz = dwy * wz, zy = wy * dwz;
@@ -402,7 +427,7 @@ struct PConst {
 };
 
 // One orbit evaluation of one particle.
-template <int D, int NGL, class R>
+template <int D, int SH, int NGL, class R>
 __device__ void evaluate(const OrbitArgs& a, const Tile& t, const R* gx, const R* gw, const int j0[3], const R* f0,
                          const R P[3], const PConst<R>& pc, const R Am[3], const R vin[3], EvalOut<R>& o) {
   const Mesh& M = a.M;
@@ -416,15 +441,15 @@ __device__ void evaluate(const OrbitArgs& a, const Tile& t, const R* gx, const R
 #pragma unroll
     for (int j = 0; j < 3; ++j) Dm[l][j] = R(0);
   int nseg = 0;
-  for_each_segment<D, R>(f0, del, [&](R sa, R sb) {
+  for_each_segment<D, SH, R>(f0, del, [&](R sa, R sb) {
     ++nseg;
     int jn[3];
     R fs[3];
     seg_base<D, R>(j0, f0, del, R(0.5) * (sa + sb), jn, fs);
     if (inside<D>(t, jn))
-      eval_segment<D, NGL, R, true>(a, t, gx, gw, jn, fs, del, sa, sb, gp, Dm);
+      eval_segment<D, SH, NGL, R, true>(a, t, gx, gw, jn, fs, del, sa, sb, gp, Dm);
     else
-      eval_segment<D, NGL, R, false>(a, t, gx, gw, jn, fs, del, sa, sb, gp, Dm);
+      eval_segment<D, SH, NGL, R, false>(a, t, gx, gw, jn, fs, del, sa, sb, gp, Dm);
   });
 #pragma unroll
   for (int j = 0; j < D; ++j) {
@@ -438,7 +463,7 @@ __device__ void evaluate(const OrbitArgs& a, const Tile& t, const R* gx, const R
 #pragma unroll
   for (int l = 0; l < D; ++l) fe[l] = f0[l] + del[l];
   R Ap[3];
-  interp3<D, R>(a, t, D + 3, j0, fe, Ap);
+  interp3<D, SH, R>(a, t, D + 3, j0, fe, Ap);
 
   const R q = pc.q;
   R Aep[3], kick[3], pm[3];
@@ -511,7 +536,7 @@ __device__ void evaluate(const OrbitArgs& a, const Tile& t, const R* gx, const R
 // Per-lane iterator over the same knot-split segments as for_each_segment (same
 // arithmetic, so the deposit sees exactly the segments the gathers saw); lets a whole
 // wave step through its particles' segments in lockstep.
-template <int D, class R>
+template <int D, int SH, class R>
 struct SegIter {
   R knot[3], next[3], stp[3], rd[3];
   R sa;
@@ -522,11 +547,11 @@ struct SegIter {
     for (int l = 0; l < D; ++l) {
       rd[l] = del[l] != R(0) ? rcp_(del[l]) : R(0);
       if (del[l] > R(0)) {
-        knot[l] = floor(f0[l] - R(0.5)) + R(1.5);
+        knot[l] = floor(f0[l] - knot_off<SH, R>()) + R(1) + knot_off<SH, R>();
         stp[l] = R(1);
         next[l] = (knot[l] - f0[l]) * rd[l];
       } else if (del[l] < R(0)) {
-        knot[l] = ceil(f0[l] - R(0.5)) - R(0.5);
+        knot[l] = ceil(f0[l] - knot_off<SH, R>()) - R(1) + knot_off<SH, R>();
         stp[l] = R(-1);
         next[l] = (knot[l] - f0[l]) * rd[l];
       } else {
@@ -815,12 +840,12 @@ __device__ __forceinline__ void deposit_window(const Tile& t, const int jn[3], c
 // per segment they take the integrated weights of every stencil row, gather U-bar and
 // deposit J_g += q v_out S-bar_g / dV into the tile through the window deposit.
 // Stencils outside the tile read and add through global memory per lane.
-template <int D, int NGL, class R>
+template <int D, int SH, int NGL, class R>
 __device__ void deposit_phase(const OrbitArgs& a, const Tile& t, const R* gx, const R* gw, const int j0[3],
                               const R* f0, const R del[3], bool dep, const double coef[3], R Ub[3]) {
   const int lane = threadIdx.x & 63;
   const bool do_dep = a.deposit != 0;
-  SegIter<D, R> sit;
+  SegIter<D, SH, R> sit;
   sit.init(f0, del, dep);
   Ub[0] = Ub[1] = Ub[2] = R(0);
 #pragma unroll 1
@@ -846,10 +871,10 @@ __device__ void deposit_phase(const OrbitArgs& a, const Tile& t, const R* gx, co
         const R s = sa + len * gx[q];
         const R wq = len * gw[q];
         R wx[3], dwx[3];
-        bw(fs[0] + s * del[0], wx, dwx);
+        bw<SH>(fs[0] + s * del[0], wx, dwx);
         R wy = R(1), dwy, wz = R(1), dwz;
-        if (D > 1) bw1(fs[1] + s * del[1], cy, wy, dwy);
-        if (D > 2) bw1(fs[2] + s * del[2], cz, wz, dwz);
+        if (D > 1) bw1<SH>(fs[1] + s * del[1], cy, wy, dwy);
+        if (D > 2) bw1<SH>(fs[2] + s * del[2], cz, wz, dwz);
         const R sw = wq * wy * wz;
 #pragma unroll
         for (int c = 0; c < 3; ++c) S[c] += sw * wx[c];
@@ -904,7 +929,7 @@ __device__ __forceinline__ int tile_to_global(const Mesh& M, const Tile& t, int 
 template <int D, class R>
 constexpr int orbit_waves() { return (sizeof(R) == 4 && D <= 2) ? 3 : 2; }
 
-template <int D, int NGL, class R>
+template <int D, int SH, int NGL, class R>
 __global__ __launch_bounds__(kOrbitBlock)
 __attribute__((amdgpu_waves_per_eu(orbit_waves<D, R>()))) void k_orbit(OrbitArgs a) {
   if (a.stop && *a.stop) return;  // the outer iteration this pass belongs to is done
@@ -1058,7 +1083,7 @@ __attribute__((amdgpu_waves_per_eu(orbit_waves<D, R>()))) void k_orbit(OrbitArgs
     vin[1] = vin0[1];
     vin[2] = vin0[2];
     R Am[3] = {R(0), R(0), R(0)};
-    if (valid) interp3<D, R>(a, t, D, j0, f0, Am);
+    if (valid) interp3<D, SH, R>(a, t, D, j0, f0, Am);
     {
       R u2 = R(0);
 #pragma unroll
@@ -1080,7 +1105,7 @@ __attribute__((amdgpu_waves_per_eu(orbit_waves<D, R>()))) void k_orbit(OrbitArgs
       for (int l = 0; l < D; ++l) okv = okv && fabs(R(a.dt) * vin[l] * R(M.inv_h[l])) < R(kMaxCross - 1);
       if (!okv) break;
       EvalOut<R> o;
-      evaluate<D, NGL, R>(a, t, gx, gw, j0, f0, P, pc, Am, vin, o);
+      evaluate<D, SH, NGL, R>(a, t, gx, gw, j0, f0, P, pc, Am, vin, o);
       segs += o.nseg;
       const R vo2 = o.vout[0] * o.vout[0] + o.vout[1] * o.vout[1] + o.vout[2] * o.vout[2];
       if (!isfinite(vo2) || !(vo2 < kap2)) break;  // finite and subluminal
@@ -1146,7 +1171,7 @@ __attribute__((amdgpu_waves_per_eu(orbit_waves<D, R>()))) void k_orbit(OrbitArgs
       for (int c = 0; c < 3; ++c) coef[c] = qv * vout[c];
     }
     R Ub[3];
-    deposit_phase<D, NGL, R>(a, t, gx, gw, j0, f0, del, conv, coef, Ub);
+    deposit_phase<D, SH, NGL, R>(a, t, gx, gw, j0, f0, del, conv, coef, Ub);
     if (conv) {
       double wk = 0.0, ra2 = 0.0;
 #pragma unroll
@@ -1188,22 +1213,28 @@ __attribute__((amdgpu_waves_per_eu(orbit_waves<D, R>()))) void k_orbit(OrbitArgs
     a.partials[(int64_t)idx * a.pstride + blockIdx.x] = idx == OP_ITMAX ? itmax : tot;
 }
 
-template <int D, int NGL, class R>
+template <int D, int SH, int NGL, class R>
 hipError_t launch_k(const OrbitArgs& a, unsigned blocks, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
   if (e0 || e1)
-    hipExtLaunchKernelGGL((k_orbit<D, NGL, R>), dim3(blocks), dim3(kOrbitBlock), tile_bytes<D>(), s, e0, e1, 0u, a);
+    hipExtLaunchKernelGGL((k_orbit<D, SH, NGL, R>), dim3(blocks), dim3(kOrbitBlock), tile_bytes<D>(), s, e0, e1, 0u,
+                          a);
   else
-    hipLaunchKernelGGL((k_orbit<D, NGL, R>), dim3(blocks), dim3(kOrbitBlock), tile_bytes<D>(), s, a);
+    hipLaunchKernelGGL((k_orbit<D, SH, NGL, R>), dim3(blocks), dim3(kOrbitBlock), tile_bytes<D>(), s, a);
   return hipGetLastError();
 }
 
 template <int D, class R>
 hipError_t launch_d(const OrbitArgs& a, unsigned blocks, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
-  // compile-time Gauss-Legendre orders: d+1 (exact for the per-segment polynomials)
-  // and 8 (the paper's); any other order runs the runtime loop
-  if (a.ngl == D + 1) return launch_k<D, D + 1, R>(a, blocks, s, e0, e1);
-  if (a.ngl == 8) return launch_k<D, 8, R>(a, blocks, s, e0, e1);
-  return launch_k<D, 0, R>(a, blocks, s, e0, e1);
+  // compile-time Gauss-Legendre orders: the least exact for the per-segment polynomials
+  // (d+1 for S_2, ceil((d+1)/2) for S_1) and, for S_2, the paper's 8; any other order
+  // runs the runtime loop
+  if (a.M.shape == 1) {
+    if (a.ngl == (D + 2) / 2) return launch_k<D, 1, (D + 2) / 2, R>(a, blocks, s, e0, e1);
+    return launch_k<D, 1, 0, R>(a, blocks, s, e0, e1);
+  }
+  if (a.ngl == D + 1) return launch_k<D, 2, D + 1, R>(a, blocks, s, e0, e1);
+  if (a.ngl == 8) return launch_k<D, 2, 8, R>(a, blocks, s, e0, e1);
+  return launch_k<D, 2, 0, R>(a, blocks, s, e0, e1);
 }
 
 }  // namespace

@@ -584,14 +584,22 @@ __device__ __forceinline__ int wrapi(int i, int n) {
   return r < 0 ? r + n : r;
 }
 
-__device__ __forceinline__ void pw(double xi, int n, int gi[3], double w[3]) {
+// Point weights of nodes j-1, j, j+1 (j the nearest node) under the quadratic S_2 or,
+// for shape 1, the linear S_1.
+__device__ __forceinline__ void pw(double xi, int n, int shape, int gi[3], double w[3]) {
   if (!(xi > -1.0e9 && xi < 1.0e9)) xi = 0.0;  // non-finite positions map to a valid node
   const int j = (int)floor(xi + 0.5);
   const double f = xi - (double)j;
-  const double a = 0.5 - f, b = 0.5 + f;
-  w[0] = 0.5 * a * a;
-  w[1] = 0.75 - f * f;
-  w[2] = 0.5 * b * b;
+  if (shape == 1) {
+    w[0] = f < 0.0 ? -f : 0.0;
+    w[1] = 1.0 - fabs(f);
+    w[2] = f > 0.0 ? f : 0.0;
+  } else {
+    const double a = 0.5 - f, b = 0.5 + f;
+    w[0] = 0.5 * a * a;
+    w[1] = 0.75 - f * f;
+    w[2] = 0.5 * b * b;
+  }
   for (int c = 0; c < 3; ++c) gi[c] = wrapi(j + c - 1, n);
 }
 
@@ -602,7 +610,7 @@ __device__ __forceinline__ int point_stencil(const Mesh& M, const double* const*
   double w[3][3];
   for (int l = 0; l < 3; ++l) {
     if (l < M.d) {
-      pw((x[l][i] - M.lo[l]) * M.inv_h[l], M.n[l], gi[l], w[l]);
+      pw((x[l][i] - M.lo[l]) * M.inv_h[l], M.n[l], M.shape, gi[l], w[l]);
     } else {
       gi[l][0] = 0;
       w[l][0] = 1.0;

@@ -42,7 +42,8 @@ class Config(C.Structure):
         ("max_outer", C.c_int32), ("max_inner", C.c_int32), ("beta", C.c_double),
         ("timing", C.c_int32), ("graphs", C.c_int32),
         ("outer_scheme", C.c_int32), ("anderson_m", C.c_int32), ("anderson_start", C.c_int32),
-        ("ls_halvings", C.c_int32), ("reserved", C.c_int32 * 2),
+        ("ls_halvings", C.c_int32), ("shape_order", C.c_int32),
+        ("reserved", C.c_int32),
         ("anderson_lambda", C.c_double), ("ls_decrease", C.c_double), ("ls_growth", C.c_double),
     ]
 
@@ -129,7 +130,8 @@ def make_config(dim, n, lo, length, dt, kappa=1.0, sigma1=1.0, sigma2=1.0, gl_or
                 project_nyquist=1, precision=FP64, sort_every=0, tol_outer_abs=1e-14,
                 tol_outer_rel=1e-12, tol_inner_abs=1e-14, tol_inner_rel=1e-12, max_outer=80,
                 max_inner=64, beta=1.0, timing=0, graphs=0, outer_scheme=0, anderson_m=4,
-                anderson_start=2, ls_halvings=6, anderson_lambda=1e-12, ls_decrease=1e-4, ls_growth=1.2):
+                anderson_start=2, ls_halvings=6, anderson_lambda=1e-12, ls_decrease=1e-4, ls_growth=1.2,
+                shape_order=2):
     c = Config()
     c.dim = dim
     for i in range(3):
@@ -143,6 +145,7 @@ def make_config(dim, n, lo, length, dt, kappa=1.0, sigma1=1.0, sigma2=1.0, gl_or
     c.max_outer, c.max_inner, c.beta, c.timing, c.graphs = max_outer, max_inner, beta, timing, graphs
     c.outer_scheme, c.anderson_m, c.anderson_start, c.ls_halvings = outer_scheme, anderson_m, anderson_start, ls_halvings
     c.anderson_lambda, c.ls_decrease, c.ls_growth = anderson_lambda, ls_decrease, ls_growth
+    c.shape_order = shape_order
     return c
 
 

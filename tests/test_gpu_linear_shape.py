@@ -1,0 +1,135 @@
+"""GPU parity of the linear particle shape (r = 1: S_1 = (1-|xi|)_+, knots at the nodes)
+against the CPU oracle, through the C ABI.  Same bars as the quadratic shape: one
+frozen evaluation to 1e-12 of the array scale (the GPU's least exact Gauss-Legendre
+order, ceil((d+1)/2), against the oracle's GL8), whole steps to 1e-9 in particle state
+with drift at most ten times the nonlinear tolerance; FP32-bulk to FP32 rounding."""
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2609_36383_amd import workloads as W
+from test_gpu_parity import _gpu, _periodic_rel, _rel, _say
+
+pytestmark = pytest.mark.gpu
+
+
+def _frozen(dim, n, length, num, seed, dt, iterate, gl=0, precision=None):
+    G = _gpu()
+    gphi, An, Anp1, _ = W.random_fields(dim, n, length, seed=seed, amp=0.3)
+    Uh = (Anp1 - An) / dt
+    x, u, q = W.random_particles(dim, n, length, num, seed + 1, umax=0.8)
+    rng = np.random.default_rng(seed + 2)
+    P = rng.normal(size=(3, num)) * 0.01 * np.abs(q)[None, :]
+    vbar = rng.uniform(-0.5, 0.5, (3, num))
+    kw = dict(dim=dim, n=n, lo=(0.0,) * dim, length=length, dt=dt, shape_order=1)
+    osim = O.OracleSim(O.make_config(**kw, gl_order=8))
+    osim.load_particles(x, u, q)
+    osim.set_particle_state(x, P, vbar)
+    ref = osim.orbit_pass(gphi, An, Anp1, Uh, vbar, iterate=iterate)
+    extra = {} if precision is None else dict(precision=precision)
+    sim = G.Simulation(G.make_config(**kw, gl_order=gl, **extra), num)
+    sim.load_particles(x, u, q)
+    sim.set_particle_state(x, P, vbar)
+    sim.set_frozen_fields(gphi, An, Anp1, Uh)
+    rep = sim.orbit_pass_frozen(iterate=iterate)
+    vout, Pn1, J = sim.read_pass()
+    sim.close()
+    ref["segments"] = sum(len(O.knot_split(O.make_config(**kw), x[:, i], dt * vbar[:dim, i])) - 1
+                          for i in range(num)) if not iterate else None
+    return ref, rep, vout, Pn1, J
+
+
+CASES = [
+    (1, (64,), (12.5,), 1000),
+    (2, (16, 8), (3.2, 1.6), 1777),
+    (3, (8, 8, 4), (1.6, 1.6, 0.8), 1301),
+]
+
+
+@pytest.mark.parametrize("dim,n,length,num", CASES)
+def test_linear_frozen_single_evaluation(dim, n, length, num):
+    _say(f"linear shape: frozen single evaluation dim={dim} n={n} np={num}")
+    ref, rep, vout, Pn1, J = _frozen(dim, n, length, num, seed=40 + dim, dt=0.3, iterate=False)
+    assert rep["failed"] == 0
+    assert _rel(vout, ref["vout"]) < 1e-12
+    assert _rel(Pn1, ref["Pnp1"]) < 1e-12
+    assert _rel(J, ref["J"]) < 1e-12
+    assert rep["segments"] == ref["segments"]  # the same knot split at the nodes
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_linear_frozen_runtime_gl_order(dim):
+    """GL8 through the runtime-order kernel agrees with the exact low order."""
+    _, n, length, num = CASES[dim - 1]
+    _say(f"linear shape: frozen evaluation, runtime GL8, dim={dim}")
+    ref, rep, vout, Pn1, J = _frozen(dim, n, length, num, seed=50 + dim, dt=0.3, iterate=False, gl=8)
+    assert _rel(vout, ref["vout"]) < 1e-12 and _rel(Pn1, ref["Pnp1"]) < 1e-12 and _rel(J, ref["J"]) < 1e-12
+
+
+@pytest.mark.parametrize("dim", [1, 2, 3])
+def test_linear_frozen_inner_loop(dim):
+    n = {1: (32,), 2: (16, 16), 3: (8, 8, 8)}[dim]
+    length = tuple(0.2 * v for v in n)
+    _say(f"linear shape: frozen inner loop dim={dim}")
+    ref, rep, vout, Pn1, J = _frozen(dim, n, length, 2500, seed=60 + dim, dt=0.05, iterate=True)
+    assert rep["failed"] == 0 and ref["nfail"] == 0
+    assert _rel(vout, ref["vout"]) < 1e-11
+    assert _rel(Pn1, ref["Pnp1"]) < 1e-11
+    assert _rel(J, ref["J"]) < 1e-11
+    assert abs(rep["inner_mean"] - ref["iters"].mean()) < 0.05
+
+
+def test_linear_frozen_fp32_bulk():
+    G = _gpu()
+    dim, n, length, num = CASES[1]
+    _say("linear shape: frozen single evaluation, FP32-bulk")
+    ref, rep, vout, Pn1, J = _frozen(dim, n, length, num, seed=70, dt=0.3, iterate=False,
+                                     precision=G.FP32_BULK)
+    assert _rel(vout, ref["vout"]) < 2e-5 and _rel(Pn1, ref["Pnp1"]) < 2e-5 and _rel(J, ref["J"]) < 2e-5
+
+
+@pytest.mark.parametrize("name,over,steps", [
+    ("tsi1d", dict(), 50),
+    ("weibel2d", dict(n=(16, 16), ppc=8), 30),
+    ("weibel3d", dict(n=(8, 8, 8), ppc=4), 8),
+])
+def test_linear_step_parity(name, over, steps):
+    G = _gpu()
+    w = W.spec(name, **over)
+    base = W.config_dict(w)
+    osim = O.OracleSim(O.config_from_dict(base, gl_order=8, shape_order=1))
+    sim = G.Simulation(G.config_from_dict(base, gl_order=0, shape_order=1, sort_every=5), w["num_particles"])
+    x, u, q = W.particles(w)
+    for s in (osim, sim):
+        s.load_particles(x, u, q)
+        s.initialize()
+    worst = dict(x=0.0, P=0.0, v=0.0)
+    gd = [sim.diagnostics()]
+    for s in range(1, steps + 1):
+        osim.step()
+        sim.step()
+        gd.append(sim.diagnostics())
+        if s % 10 == 0 or s == steps:
+            xo, Po, vo = osim.read_particles()
+            xg, Pg, vg = sim.read_particles()
+            worst["x"] = max(worst["x"], _periodic_rel(xg, xo, w["length"]))
+            worst["P"] = max(worst["P"], _rel(Pg, Po))
+            worst["v"] = max(worst["v"], _rel(vg, vo))
+            _say(f"linear shape {name} step {s}: rel x {worst['x']:.2e} P {worst['P']:.2e} "
+                 f"v {worst['v']:.2e} drift {gd[-1]['energy_rel']:.2e}")
+    for k in ("E", "A", "rho"):
+        assert _rel(sim.read_field(k), osim.read_field(k)) < 1e-9, k
+    sim.close()
+    assert worst["x"] < 1e-9 and worst["P"] < 1e-9 and worst["v"] < 1e-9
+    assert max(d["energy_rel"] for d in gd) < 1e-11
+    assert max(d["gauss_rms"] for d in gd) < 1e-11
+    assert max(d["lorenz_rms"] for d in gd) < 1e-11
+    assert max(d["chain_rms"] for d in gd) < 1e-15
+    assert max(abs(d["work_residual"]) for d in gd) < 1e-13
+
+
+def test_shape_order_out_of_range_rejected():
+    G = _gpu()
+    w = W.spec("tsi1d")
+    with pytest.raises(G.GmhcError):
+        G.Simulation(G.config_from_dict(W.config_dict(w), shape_order=3), w["num_particles"])
