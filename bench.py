@@ -30,25 +30,34 @@ PEAK_FP64_VALU_TFLOPS = 78.6
 TIMING_EVERY = 4
 
 
-def flops_per_eval(d, seg_mean, ngl):
+def _support(shape):
+    """Nodes per axis in the support of the shape at a point, and flops per axis of its
+    1D weights and derivatives: 3 and 10 for the quadratic S_2, 2 and 3 for the linear
+    S_1 (whose derivatives are constants on a knot segment)."""
+    return (3, 10) if shape == 2 else (2, 3)
+
+
+def flops_per_eval(d, seg_mean, ngl, shape=2):
     """Algorithmic flops of one orbit evaluation (FMA = 2).
 
-    Per Gauss-Legendre point: 1D weights and derivatives (10 per axis), the time blend
-    (3), and per stencil node (3^d): tensor weights d-1 + d(d-1), grad-phi gather 2d,
-    D gather 3(3 + 2d), quadrature weight 1.  Per evaluation add the endpoint
-    interpolant A^+ (3^d (d - 1 + 6) + 6d) and the push, HC rotation, secant velocity
-    and inner test (250).
+    Per Gauss-Legendre point: 1D weights and derivatives (10 per axis for S_2), the
+    time blend (3), and per support node (3^d for S_2, 2^d for S_1): tensor weights
+    d-1 + d(d-1), grad-phi gather 2d, D gather 3(3 + 2d), quadrature weight 1.  Per
+    evaluation add the endpoint interpolant A^+ (support (d - 1 + 6) + 6d) and the push,
+    HC rotation, secant velocity and inner test (250).
     """
+    k, wf = _support(shape)
     node = (d - 1) + d * (d - 1) + 2 * d + 3 * (3 + 2 * d) + 1
-    point = 10 * d + 3 + (3 ** d) * node
-    endpoint = (3 ** d) * (d - 1 + 6) + 6 * d
+    point = wf * d + 3 + (k ** d) * node
+    endpoint = (k ** d) * (d - 1 + 6) + 6 * d
     return seg_mean * ngl * point + endpoint + 250
 
 
-def deposit_flops(d, seg_mean, ngl):
+def deposit_flops(d, seg_mean, ngl, shape=2):
     """Flops of the deposit sweep (once per converged particle per launch)."""
-    point = 10 * d + (3 ** d) * d
-    return seg_mean * ngl * point + (3 ** d) * (3 * 2 + 3 * 2)
+    k, wf = _support(shape)
+    point = wf * d + (k ** d) * d
+    return seg_mean * ngl * point + (k ** d) * (3 * 2 + 3 * 2)
 
 
 def bytes_per_particle(d, bulk=8):
@@ -63,12 +72,13 @@ def bytes_per_node(d):
     return 8 * (d + 9) + 8 * 3 * 2
 
 
-def measured_traffic(workload, dtype):
+def measured_traffic(workload, dtype, shape=2):
     """HBM bytes per orbit launch from the committed counter summary of this workload
     (FETCH_SIZE and WRITE_SIZE scaled by a copy kernel), or None when there is none or
     the kernel sources have changed since the counters were taken."""
     import hashlib
-    path = os.path.join(ROOT, "profiles", f"k_orbit_{workload}_{dtype}_hbm_traffic.txt")
+    tag = "" if shape == 2 else "_linear"
+    path = os.path.join(ROOT, "profiles", f"k_orbit_{workload}{tag}_{dtype}_hbm_traffic.txt")
     if not os.path.exists(path):
         return None
     meta = {}
@@ -86,7 +96,7 @@ def measured_traffic(workload, dtype):
     return float(meta["traffic_bytes_per_launch"])
 
 
-def cpu_baseline(w, cfg_dict, ngl, target_s=12.0):
+def cpu_baseline(w, cfg_dict, ngl, target_s=12.0, shape=2):
     """The CPU oracle's rate on the same workload: whole implicit steps (all outer
     iterations, orbit passes and field solves) of the full particle set at the same
     Gauss-Legendre order, as many as fit in about target_s seconds (at least one)."""
@@ -94,7 +104,7 @@ def cpu_baseline(w, cfg_dict, ngl, target_s=12.0):
     from paper_2609_36383_amd import workloads as W
 
     x, u, q = W.particles(w)
-    sim = O.OracleSim(O.config_from_dict(cfg_dict, gl_order=ngl))
+    sim = O.OracleSim(O.config_from_dict(cfg_dict, gl_order=ngl, shape_order=shape))
     sim.load_particles(x, u, q)
     pot = W.potentials(w)
     if pot is not None:
@@ -139,12 +149,13 @@ def run_case(args, w, fp32):
     from paper_2609_36383_amd import workloads as W
 
     base = W.config_dict(w, fp32_bulk=fp32)
-    ngl = args.gl_order if args.gl_order else w["dim"] + 1
+    sh = args.shape
+    ngl = args.gl_order if args.gl_order else (w["dim"] + 1 if sh == 2 else (w["dim"] + 2) // 2)
     # the orbit launches of every TIMING_EVERY-th step record HIP events (the events
     # leave small gaps on the stream, so they stay off the other steps)
     cfg = G.config_from_dict(base, gl_order=ngl, sort_every=args.sort_every,
                              timing=TIMING_EVERY if args.steps >= TIMING_EVERY else 1,
-                             precision=G.FP32_BULK if fp32 else G.FP64)
+                             precision=G.FP32_BULK if fp32 else G.FP64, shape_order=sh)
     x, u, q = W.particles(w)
     npart = q.size
     sim = G.Simulation(cfg, npart, device="cuda:0")
@@ -181,8 +192,8 @@ def run_case(args, w, fp32):
     ng = int(np.prod(w["n"]))
     seg_mean = segs / max(evals, 1)  # measured knot-split segments per evaluation
     # flops of the timed launches (evaluations per launch of the timed steps)
-    flops_launch = (timed_evals / max(timed_launches, 1)) * flops_per_eval(d, seg_mean, ngl) + \
-        npart * deposit_flops(d, seg_mean, ngl)
+    flops_launch = (timed_evals / max(timed_launches, 1)) * flops_per_eval(d, seg_mean, ngl, sh) + \
+        npart * deposit_flops(d, seg_mean, ngl, sh)
     bytes_launch = npart * bytes_per_particle(d, 4 if fp32 else 8) + ng * bytes_per_node(d)
     launch_s = (orbit_ms / max(timed_launches, 1)) * 1e-3
     peak = PEAK_FP32_VALU_TFLOPS if fp32 else PEAK_FP64_VALU_TFLOPS
@@ -196,9 +207,9 @@ def run_case(args, w, fp32):
         tolerances={k: base[k] for k in ("tol_outer_rel", "tol_outer_abs", "tol_inner_rel", "tol_inner_abs")},
         roofline={
             "bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
-            "traffic": measured_traffic(args.workload, "fp32" if fp32 else "fp64"),
+            "traffic": measured_traffic(args.workload, "fp32" if fp32 else "fp64", sh),
             "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE x2.0 + WRITE_SIZE x1.0)",
-            "kernel": f"k_orbit<{d},{ngl},{'float' if fp32 else 'double'}>", "launch_ms": launch_s * 1e3,
+            "kernel": f"k_orbit<{d},{sh},{ngl},{'float' if fp32 else 'double'}>", "launch_ms": launch_s * 1e3,
             "flops_per_launch": flops_launch, "hbm_bytes_per_launch": bytes_launch,
             "hbm_achieved_gbs": gbs, "hbm_frac": gbs / PEAK_HBM_GBS,
         })
@@ -212,6 +223,8 @@ def main():
     ap.add_argument("--workload", default="weibel2d")
     ap.add_argument("--sort-every", type=int, default=10)
     ap.add_argument("--gl-order", type=int, default=0)
+    ap.add_argument("--shape", type=int, choices=(1, 2), default=2,
+                    help="particle-shape B-spline degree: 2 quadratic (the paper's), 1 linear")
     ap.add_argument("--precision", choices=("both", "fp64", "fp32"), default="both",
                     help="FP64 (the headline value), FP32-bulk, or both (default)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -246,7 +259,8 @@ def main():
         "dtype": "f32-bulk" if main_fp32 else "f64",
         "data": "synthetic",
         "config": {"workload": f"{args.workload}: {'x'.join(map(str, w['n']))} mesh, {r['npart']} particles, "
-                               f"{w['ppc']} per cell, dt {w['dt']}, GL{r['ngl']} per knot segment",
+                               f"{w['ppc']} per cell, dt {w['dt']}, GL{r['ngl']} per knot segment"
+                               + ("" if args.shape == 2 else ", linear B-spline shape"),
                    "global_batch": r["npart"], "seq_len": None, "parallelism": "single GPU"},
     }
     for k in ("particle_steps_per_s", "outer_iters_mean", "evaluations_per_particle_step", "energy_drift",
@@ -262,7 +276,7 @@ def main():
         out["fp32_bulk"]["speedup_per_iteration_vs_fp64"] = other["value"] / r["value"]
     if not args.no_cpu_baseline:
         base = W.config_dict(w, fp32_bulk=main_fp32)
-        out["cpu_baseline"] = cpu_baseline(w, base, r["ngl"])
+        out["cpu_baseline"] = cpu_baseline(w, base, r["ngl"], shape=args.shape)
     print(json.dumps(out), flush=True)
 
 
