@@ -154,19 +154,19 @@ __device__ __forceinline__ bool inside(const Tile& t, const int jn[3]) {
 
 // B-spline weights of nodes j-1, j, j+1 at local offset f from node j, and their
 // derivatives with respect to xi (times h they are d/dx).  SH = 2: the quadratic S_2,
-// f in [-1/2, 1/2].  SH = 1: the linear S_1 = (1-|xi|)_+ (the degree the paper raises
-// to two); f in [-1, 1] keeps one sign over a knot segment, whose ends are nodes, so the
-// one-sided derivatives are those of the segment.
+// j the nearest node, f in [-1/2, 1/2].  SH = 1: the linear S_1 = (1-|xi|)_+ (the
+// degree the paper raises to two), j = floor(xi), f in [0, 1]: only nodes j and j+1
+// (stencil columns 1 and 2) carry weight, and the derivatives are those of the knot
+// segment [j, j+1] the point lies in.
 template <int SH, class R>
 __device__ __forceinline__ void bw(R f, R w[3], R dw[3]) {
   if constexpr (SH == 1) {
-    const bool neg = f < R(0);
-    w[0] = neg ? -f : R(0);
-    w[1] = R(1) - fabs(f);
-    w[2] = neg ? R(0) : f;
-    dw[0] = neg ? R(-1) : R(0);
-    dw[1] = neg ? R(1) : R(-1);
-    dw[2] = neg ? R(0) : R(1);
+    w[0] = R(0);
+    w[1] = R(1) - f;
+    w[2] = f;
+    dw[0] = R(0);
+    dw[1] = R(-1);
+    dw[2] = R(1);
   } else {
     const R a = R(0.5) - f, b = R(0.5) + f;
     w[0] = R(0.5) * a * a;
@@ -180,19 +180,26 @@ __device__ __forceinline__ void bw(R f, R w[3], R dw[3]) {
 // weight and derivative of the single stencil node c (0, 1, 2)
 template <int SH, class R>
 __device__ __forceinline__ void bw1(R f, int c, R& w, R& dw) {
-  const R t = f - R(c - 1);  // offset from node j + c - 1
-  const R at = fabs(t);
   if constexpr (SH == 1) {
-    const R o = R(1) - at;
-    w = o > R(0) ? o : R(0);
-    dw = o > R(0) ? (t > R(0) ? R(-1) : R(1)) : R(0);
+    w = c == 0 ? R(0) : (c == 1 ? R(1) - f : f);
+    dw = c == 0 ? R(0) : (c == 1 ? R(-1) : R(1));
   } else {
+    const R t = f - R(c - 1);  // offset from node j + c - 1
+    const R at = fabs(t);
     const R o = R(1.5) - at;
     const R sg = t > R(0) ? R(1) : R(-1);
     w = c == 1 ? R(0.75) - t * t : R(0.5) * o * o;
     dw = c == 1 ? R(-2.0) * t : -sg * o;
   }
 }
+
+// Stencil rows and columns that carry weight: all three per axis for S_2, the upper two
+// (nodes j and j+1) for S_1.  Rows of the 3^(d-1) row layout are visited as
+// cy = RB + row % RW, cz = RB + row / RW.
+template <int SH>
+constexpr int kC0 = SH == 1 ? 1 : 0;
+template <int D, int SH>
+constexpr int kRows = D == 1 ? 1 : (SH == 1 ? (D == 2 ? 2 : 4) : (D == 2 ? 3 : 9));
 
 // Knot offset from the nodes of the B-spline of degree SH: half-integer for S_2, the
 // nodes themselves for S_1.
@@ -240,14 +247,15 @@ __device__ __forceinline__ void for_each_segment(const R* f0, const R* del, F&& 
   }
 }
 
-// Nearest node of the segment point s: relative offsets k and local offset at s = 0.
-template <int D, class R>
+// Base node of the segment point s (nearest node for S_2, the node below for S_1):
+// relative offsets k and local offset at s = 0.
+template <int D, int SH, class R>
 __device__ __forceinline__ void seg_base(const int j0[3], const R* f0, const R* del, R sm, int jn[3], R fs[3]) {
 #pragma unroll
   for (int l = 0; l < 3; ++l) {
     if (l < D) {
       const R xm = f0[l] + sm * del[l];
-      const int k = (int)floor(xm + R(0.5));
+      const int k = SH == 1 ? (int)floor(xm) : (int)floor(xm + R(0.5));
       jn[l] = j0[l] + k;
       fs[l] = f0[l] - R(k);
     } else {
@@ -279,14 +287,15 @@ __device__ __forceinline__ void interp3_at(const OrbitArgs& a, const Tile& t, in
   Stencil<D, LDS> st(a.M, t, jn);
   out[0] = out[1] = out[2] = R(0);
   constexpr int NY = D > 1 ? 3 : 1, NZ = D > 2 ? 3 : 1;
+  constexpr int Y0 = D > 1 ? kC0<SH> : 0, Z0 = D > 2 ? kC0<SH> : 0;
 #pragma unroll
-  for (int cz = 0; cz < NZ; ++cz)
+  for (int cz = Z0; cz < NZ; ++cz)
 #pragma unroll
-    for (int cy = 0; cy < NY; ++cy) {
+    for (int cy = Y0; cy < NY; ++cy) {
       const R wyz = w[1][cy] * w[2][cz];
       const int rowoff = st.row(cy, cz);
 #pragma unroll
-      for (int cx = 0; cx < 3; ++cx) {
+      for (int cx = kC0<SH>; cx < 3; ++cx) {
         const R S = w[0][cx] * wyz;
         const int g = st.ix[cx] + rowoff;
 #pragma unroll
@@ -303,7 +312,7 @@ __device__ __forceinline__ void interp3(const OrbitArgs& a, const Tile& t, int f
 #pragma unroll
   for (int l = 0; l < 3; ++l) {
     if (l < D) {
-      const int k = (int)floor(fr[l] + R(0.5));
+      const int k = SH == 1 ? (int)floor(fr[l]) : (int)floor(fr[l] + R(0.5));
       jn[l] = j0[l] + k;
       f[l] = fr[l] - R(k);
     } else {
@@ -334,13 +343,14 @@ __device__ __forceinline__ void eval_segment(const OrbitArgs& a, const Tile& t, 
                                              R gp[3], R Dm[3][3]) {
   const R len = sb - sa;
   Stencil<D, LDS> st(a.M, t, jn);
-  constexpr int NROW = D == 1 ? 1 : (D == 2 ? 3 : 9);
+  constexpr int NROW = kRows<D, SH>;
+  constexpr int RW = SH == 1 ? 2 : 3, RB = kC0<SH>;
   // 1D and 2D rows at a compile-time GL order are unrolled (the y weights specialise
   // per row); 3D and the runtime order keep a loop
   constexpr int kRowUnroll = (D < 3 && NGL > 0) ? NROW : 1;
 #pragma unroll kRowUnroll
   for (int row = 0; row < NROW; ++row) {
-    const int cy = D > 1 ? row % 3 : 0, cz = D > 2 ? row / 3 : 0;
+    const int cy = D > 1 ? RB + row % RW : 0, cz = D > 2 ? RB + row / RW : 0;
     const int rowoff = st.row(cy, cz);
     // FP32 has registers to spare: read the row's field values before the weight
     // arithmetic so their latency overlaps it.  FP64 reads them node by node below.
@@ -348,7 +358,7 @@ __device__ __forceinline__ void eval_segment(const OrbitArgs& a, const Tile& t, 
     R F[3][D + 6];
     if (kEarly) {
 #pragma unroll
-      for (int c = 0; c < 3; ++c)
+      for (int c = kC0<SH>; c < 3; ++c)
 #pragma unroll
         for (int f = 0; f < D + 6; ++f) F[c][f] = ld<D, R, LDS>(a, t, f, st.ix[c] + rowoff);
     }
@@ -374,7 +384,7 @@ __device__ __forceinline__ void eval_segment(const OrbitArgs& a, const Tile& t, 
       const R yz = dwy * wz, zy = wy * dwz;
       const R yw0 = a1 * yz, yw1 = b1 * yz, zw0 = a1 * zy, zw1 = b1 * zy;
 #pragma unroll
-      for (int c = 0; c < 3; ++c) {
+      for (int c = kC0<SH>; c < 3; ++c) {
         S[c] += sw * wx[c];
         X0[c] += xw0 * dwx[c];
         X1[c] += xw1 * dwx[c];
@@ -389,7 +399,7 @@ __device__ __forceinline__ void eval_segment(const OrbitArgs& a, const Tile& t, 
       }
     }
 #pragma unroll
-    for (int c = 0; c < 3; ++c) {
+    for (int c = kC0<SH>; c < 3; ++c) {
       const int g = st.ix[c] + rowoff;
       if (!kEarly) {
 #pragma unroll
@@ -445,7 +455,7 @@ __device__ void evaluate(const OrbitArgs& a, const Tile& t, const R* gx, const R
     ++nseg;
     int jn[3];
     R fs[3];
-    seg_base<D, R>(j0, f0, del, R(0.5) * (sa + sb), jn, fs);
+    seg_base<D, SH, R>(j0, f0, del, R(0.5) * (sa + sb), jn, fs);
     if (inside<D>(t, jn))
       eval_segment<D, SH, NGL, R, true>(a, t, gx, gw, jn, fs, del, sa, sb, gp, Dm);
     else
@@ -855,7 +865,7 @@ __device__ void deposit_phase(const OrbitArgs& a, const Tile& t, const R* gx, co
     if (__ballot(has) == 0) break;
     int jn[3] = {0, 0, 0};
     R fs[3] = {R(0), R(0), R(0)};
-    if (has) seg_base<D, R>(j0, f0, del, R(0.5) * (sa + sb), jn, fs);
+    if (has) seg_base<D, SH, R>(j0, f0, del, R(0.5) * (sa + sb), jn, fs);
     const bool in = has && inside<D>(t, jn);
     const R len = sb - sa;  // zero for lanes without a segment: all weights vanish
     constexpr int NROW = D == 1 ? 1 : (D == 2 ? 3 : 9);
@@ -865,6 +875,7 @@ __device__ void deposit_phase(const OrbitArgs& a, const Tile& t, const R* gx, co
       const int cy = D > 1 ? row % 3 : 0, cz = D > 2 ? row / 3 : 0;
       R* S = Sr[row];
       S[0] = S[1] = S[2] = R(0);
+      if (SH == 1 && ((D > 1 && cy == 0) || (D > 2 && cz == 0))) continue;  // S_1: no weight here
       const int nq = GL<NGL>::n(a.ngl);
 #pragma unroll
       for (int q = 0; q < nq; ++q) {
@@ -877,20 +888,20 @@ __device__ void deposit_phase(const OrbitArgs& a, const Tile& t, const R* gx, co
         if (D > 2) bw1<SH>(fs[2] + s * del[2], cz, wz, dwz);
         const R sw = wq * wy * wz;
 #pragma unroll
-        for (int c = 0; c < 3; ++c) S[c] += sw * wx[c];
+        for (int c = kC0<SH>; c < 3; ++c) S[c] += sw * wx[c];
       }
       if (in) {
         Stencil<D, true> st(a.M, t, jn);
         const int rowoff = st.row(cy, cz);
 #pragma unroll
-        for (int c = 0; c < 3; ++c)
+        for (int c = kC0<SH>; c < 3; ++c)
 #pragma unroll
           for (int k = 0; k < 3; ++k) Ub[k] += S[c] * ld<D, R, true>(a, t, D + 6 + k, st.ix[c] + rowoff);
       } else if (has) {
         Stencil<D, false> st(a.M, t, jn);
         const int rowoff = st.row(cy, cz);
 #pragma unroll
-        for (int c = 0; c < 3; ++c) {
+        for (int c = kC0<SH>; c < 3; ++c) {
           const int g = st.ix[c] + rowoff;
 #pragma unroll
           for (int k = 0; k < 3; ++k) {
@@ -1021,8 +1032,10 @@ __attribute__((amdgpu_waves_per_eu(orbit_waves<D, R>()))) void k_orbit(OrbitArgs
     if (lo[l] > hi[l]) {  // no valid particle in this workgroup
       ok = 0;
     } else {
-      t.o[l] = uni(lo[l] - kHalo);
-      const int e = hi[l] - lo[l] + 1 + 2 * kHalo;
+      // S_1 bases its stencil on the node below the point, which can lie one node
+      // under the nearest: the box reaches one node further down
+      t.o[l] = uni(lo[l] - kHalo - (SH == 1 ? 1 : 0));
+      const int e = hi[l] - lo[l] + 1 + 2 * kHalo + (SH == 1 ? 1 : 0);
       t.E[l] = uni(e);
       nodes = (e > 4096 || nodes > 4096) ? (1 << 30) : nodes * e;  // no overflow: 4096^2 < 2^30
     }
