@@ -38,6 +38,14 @@ def test_host_validation():
     n2 = C.c_size_t()
     assert lib.gmhc_workspace_bytes(h, 100000, C.byref(n2)) == G.OK and n2.value > n.value
     lib.gmhc_destroy(h)
+    for sh in (0, 1, 2):  # 0 selects the quadratic shape
+        c = G.make_config(2, (16, 16), (0, 0), (3.2, 3.2), 0.05, shape_order=sh)
+        hh = C.c_void_p()
+        assert lib.gmhc_create(C.byref(c), C.byref(hh)) == G.OK, sh
+        lib.gmhc_destroy(hh)
+    # shape_order took the place of one reserved int: the struct layout is unchanged
+    assert G.Config.shape_order.offset == G.Config.ls_halvings.offset + 4
+    assert G.Config.anderson_lambda.offset == G.Config.reserved.offset + 4
     bad = [
         dict(sigma1=2.0),                 # sigma1 != kappa^2 sigma2
         dict(dt=0.0),
@@ -51,6 +59,8 @@ def test_host_validation():
         dict(outer_scheme=1, ls_growth=0.9),
         dict(outer_scheme=1, ls_decrease=1.0),
         dict(timing=-1),
+        dict(shape_order=3),
+        dict(shape_order=-1),
     ]
     for over in bad:
         kw = dict(dim=2, n=(16, 16), lo=(0, 0), length=(3.2, 3.2), dt=0.05)

@@ -30,8 +30,9 @@ def _rel(a, b):
     return float(np.abs(np.asarray(a) - b).max() / max(np.abs(b).max(), 1e-300))
 
 
-@pytest.mark.parametrize("fp32,timing", [(False, 0), (False, 1), (True, 1)], ids=["fp64", "fp64-timed", "fp32-timed"])
-def test_graph_replays_match_eager(fp32, timing):
+@pytest.mark.parametrize("fp32,timing,shape", [(False, 0, 2), (False, 1, 2), (True, 1, 2), (False, 0, 1)],
+                         ids=["fp64", "fp64-timed", "fp32-timed", "fp64-linear"])
+def test_graph_replays_match_eager(fp32, timing, shape):
     G = _gpu()
     w = W.spec("weibel2d", n=(16, 16), ppc=16)
     x, u, q = W.particles(w)
@@ -39,7 +40,8 @@ def test_graph_replays_match_eager(fp32, timing):
     prec = G.FP32_BULK if fp32 else G.FP64
     sims = []
     for graphs in (1, 0):
-        s = G.Simulation(G.config_from_dict(base, sort_every=4, timing=timing, graphs=graphs, precision=prec), q.size)
+        s = G.Simulation(G.config_from_dict(base, sort_every=4, timing=timing, graphs=graphs, precision=prec,
+                                            shape_order=shape), q.size)
         s.load_particles(x, u, q)
         s.initialize()
         sims.append(s)
