@@ -235,7 +235,7 @@ def main():
         copy_probe()
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU only: this build runs the orbit pass on a single MI355X "
+        print("bench.py measures one GPU only: the library runs the orbit pass on a single MI355X "
               "(multi-GPU sharding is not implemented); use --gpus 1", file=sys.stderr)
         sys.exit(2)
 
