@@ -296,19 +296,20 @@ def test_tsi1d_eigenmode_growth_on_gpu():
     assert abs(CF.fit_growth(ts, amps, 0.0, 2.0) / Gm - 1) < 5e-3
 
 
-@pytest.mark.parametrize("name,over,steps,beta", [
-    ("tsi1d", {}, 50, 0.5),
-    ("tsi1d", {}, 20, 1.0),
-    ("weibel2d", dict(n=(16, 16), ppc=16), 20, 0.5),
+@pytest.mark.parametrize("name,over,steps,beta,shape", [
+    ("tsi1d", {}, 50, 0.5, 2),
+    ("tsi1d", {}, 20, 1.0, 2),
+    ("weibel2d", dict(n=(16, 16), ppc=16), 20, 0.5, 2),
+    ("weibel2d", dict(n=(16, 16), ppc=16), 20, 0.5, 1),  # the linear particle shape
 ])
-def test_anderson_outer_solver_parity(name, over, steps, beta):
+def test_anderson_outer_solver_parity(name, over, steps, beta, shape):
     # the paper's Anderson outer solver on both sides: same particle state to 1e-9 and
     # the same number of outer-map evaluations per step, except that a step whose test
     # ratio lands on 1 within rounding may stop one evaluation apart (at most twice)
     G = _gpu()
     w = W.spec(name, **over)
     base = W.config_dict(w)
-    kw = dict(outer_scheme=1, beta=beta)
+    kw = dict(outer_scheme=1, beta=beta, shape_order=shape)
     x, u, q = W.particles(w)
     osim = O.OracleSim(O.config_from_dict(base, gl_order=8, **kw))
     osim.load_particles(x, u, q)
@@ -327,7 +328,7 @@ def test_anderson_outer_solver_parity(name, over, steps, beta):
     assert apart <= 2
     xo, Po, vo = osim.read_particles()
     xg, Pg, vg = sim.read_particles()
-    _say(f"anderson {name} beta {beta}: {steps} steps, rel x {_periodic_rel(xg, xo, L):.2e} "
+    _say(f"anderson {name} beta {beta} shape {shape}: {steps} steps, rel x {_periodic_rel(xg, xo, L):.2e} "
          f"P {_rel(Pg, Po):.2e} v {_rel(vg, vo):.2e}, outer {rg['outer_iters']}, drift {drift:.2e}")
     assert _periodic_rel(xg, xo, L) < 1e-9 and _rel(Pg, Po) < 1e-9 and _rel(vg, vo) < 1e-9
     assert drift < 1e-11
