@@ -14,6 +14,8 @@
 
 using namespace gmhc;
 
+static_assert(GMHC_MAX_ORBIT_CELLS == kMaxCross - 1, "the orbit pass supports |dt v / h| < kMaxCross - 1");
+
 struct gmhc_ctx {
   gmhc_config cfg;
   Mesh M;
@@ -47,12 +49,17 @@ struct gmhc_ctx {
   int32_t* id2 = nullptr;
   int32_t* iters = nullptr;
   int32_t* key = nullptr;
+  int32_t* key2 = nullptr;  // radix sort buffers
+  int32_t* ridx = nullptr;
+  int32_t* ridx2 = nullptr;
+  int32_t* rcount = nullptr;
   // mesh
   double* tacc = nullptr;   // [d+6][Ng] block in the trial layout whose A part is A^n; at
                             // commit it trades places with the converged trial block
   double* An = nullptr;     // [3][Ng] real A^n (= tacc + d Ng)
   double* trial[2] = {};    // [d+6][Ng] real: grad phi^{n+1/2}, A^{n+1}, U^{n+1/2}, by parity
-  double* Jdep = nullptr;   // [3][Ng]
+  unsigned long long* Jdep = nullptr;  // [3][Ng] deposited current, fixed-point pairs (fixsum.h)
+  double* pot0 = nullptr;   // [6][Ng] loaded initial potentials A0, U0 (real space)
   double* jr[3] = {};       // real current slots [3][Ng]; slot 0 = accepted J^{n-1/2}
   double2* jh[3] = {};      // spectral current slots
   double2* S0 = nullptr;    // accepted spectral state [9][Ng]: phi psi rho A(3) U(3)
@@ -210,10 +217,15 @@ size_t carve(gmhc_ctx* c, char* base, int64_t np) {
   c->id2 = cv.take<int32_t>(N);
   c->iters = cv.take<int32_t>(N);
   c->key = cv.take<int32_t>(N);
+  c->key2 = cv.take<int32_t>(N);
+  c->ridx = cv.take<int32_t>(N);
+  c->ridx2 = cv.take<int32_t>(N);
+  c->rcount = cv.take<int32_t>((size_t)radix_count_ints(np));
   c->tacc = cv.take<double>((size_t)(d + 6) * Ng);
   c->An = c->tacc + (size_t)d * Ng;
   for (int p = 0; p < 2; ++p) c->trial[p] = cv.take<double>((size_t)(d + 6) * Ng);
-  c->Jdep = cv.take<double>(3 * Ng);
+  c->Jdep = cv.take<unsigned long long>(6 * Ng);
+  c->pot0 = cv.take<double>(6 * Ng);
   for (int s = 0; s < 3; ++s) {
     c->jr[s] = cv.take<double>(3 * Ng);
     c->jh[s] = cv.take<double2>(3 * Ng);
@@ -305,7 +317,7 @@ int orbit_blocks(const gmhc_ctx* c) { return (int)((c->np + kOrbitBlock - 1) / k
 // Orbit pass + first-level reduction to dres[0..7]; optional HIP-event timing.
 int32_t run_orbit(gmhc_ctx* ctx, int iterate, double* ms) {
   OrbitArgs a = orbit_args(ctx, iterate);
-  HIPCK(launch_zero(ctx->Jdep, 3 * ctx->M.Ng, ctx->stream));
+  HIPCK(launch_zero(reinterpret_cast<double*>(ctx->Jdep), 6 * ctx->M.Ng, ctx->stream));
   const bool timed = ctx->timed_now;
   HIPCK(launch_orbit(a, ctx->ngl, ctx->stream, timed ? ctx->ev0 : nullptr, timed ? ctx->ev1 : nullptr));
   const int nb = (int)((ctx->np + kOrbitBlock - 1) / kOrbitBlock);
@@ -371,6 +383,11 @@ int32_t sort_particles(gmhc_ctx* ctx) {
   a.key = ctx->key;
   a.count = ctx->count;
   a.cursor = ctx->cursor;
+  a.stable = ctx->cfg.deterministic != 0;
+  a.key2 = ctx->key2;
+  a.idx = ctx->ridx;
+  a.idx2 = ctx->ridx2;
+  a.rcount = ctx->rcount;
   HIPCK(sort_by_cell(a, ctx->scan_tmp, ctx->scan_tmp_bytes, ctx->stream));
   for (int l = 0; l < d; ++l) std::swap(ctx->x[l], ctx->x2[l]);
   for (int l = 0; l < 3; ++l) {
@@ -412,6 +429,77 @@ int32_t field_to_rscr(gmhc_ctx* ctx, int32_t which, int* ncomp) {
   HIPCK(fft_nd(ctx->M, ctx->axes, nc, nullptr, src, nullptr, ctx->rscr, ctx->cout, true, false, ctx->stream));
   *ncomp = nc;
   return GMHC_OK;
+}
+
+// Fixed-point scale of the deposited charge and current (fixsum.h): every sum of
+// contributions to one node is bounded by max(kappa, 1) sum_i |q_i| / dV (|v| < kappa,
+// and the shape weights of a particle sum to one).  Synchronizes the stream.
+int32_t set_fix_scale(gmhc_ctx* ctx) {
+  double qsum = 0.0;
+  if (ctx->np > 0) {
+    const int kb = (int)std::min<int64_t>((ctx->np + kBlock - 1) / kBlock, 1024);
+    HIPCK(launch_abs_charge(ctx->q, ctx->prec, ctx->np, ctx->partials, kb, ctx->stream));
+    HIPCK(launch_reduce(ctx->partials, kb, kDiagParts, 1, 1, 0u, ctx->dres, ctx->stream));
+    HIPCK(hipMemcpyAsync(ctx->hres, ctx->dres, sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+  }
+  HIPCK(hipStreamSynchronize(ctx->stream));
+  if (ctx->np > 0) qsum = ctx->hres[0];
+  if (!isfinite(qsum)) return fail(ctx, GMHC_EINVAL, "non-finite particle charges");
+  ctx->M.fx = fix_scale(std::max(ctx->cfg.kappa, 1.0) * qsum / ctx->M.dV);
+  return GMHC_OK;
+}
+
+// Text of an inner-solve failure: failed particles, and those whose orbit reached the
+// supported knot-crossing range.
+std::string inner_fail_msg(double failed, double xlim) {
+  std::string m = "particle inner solve failed (" + std::to_string((long long)failed) + " particles)";
+  if (xlim > 0.0)
+    m += "; " + std::to_string((long long)xlim) + " of them with an orbit of " +
+         std::to_string(GMHC_MAX_ORBIT_CELLS) +
+         " or more cells on some axis (|dt v / h| >= GMHC_MAX_ORBIT_CELLS, the supported knot-crossing range)";
+  return m;
+}
+
+// Image of the accepted state (gmhc_save / gmhc_load): this header, then the sections
+// listed by state_sections, each at an 8-byte boundary.
+struct StateHeader {
+  char magic[8];
+  int32_t abi, dim, n[3], precision, shape, have_pot, last_outer, pad;
+  int64_t np, ng, step, bytes;
+  double t, E0, last_chain, last_work, last_rr, last_mr;
+  double fx[3];
+};
+constexpr char kStateMagic[8] = {'G', 'M', 'H', 'C', 'S', 'T', 'A', 'T'};
+
+struct StateSection {
+  void* dev;
+  size_t bytes;
+};
+
+// Device buffers of the accepted state, in image order: particles in the internal
+// (sorted) order with their load-order ids, positions, canonical momenta, accepted orbit
+// velocities, charges; the spectral state, real A^n, the accepted current (real and
+// spectral) and the loaded initial potentials.
+std::vector<StateSection> state_sections(gmhc_ctx* c) {
+  const size_t np = (size_t)c->np, Ng = (size_t)c->M.Ng, es = c->es;
+  std::vector<StateSection> v;
+  for (int l = 0; l < c->M.d; ++l) v.push_back({c->x[l], sizeof(double) * np});
+  for (int l = 0; l < 3; ++l) v.push_back({c->P[l], es * np});
+  for (int l = 0; l < 3; ++l) v.push_back({c->vb[l], es * np});
+  v.push_back({c->q, es * np});
+  v.push_back({c->id, sizeof(int32_t) * np});
+  v.push_back({c->S0, sizeof(double2) * 9 * Ng});
+  v.push_back({c->An, sizeof(double) * 3 * Ng});
+  v.push_back({c->jr[0], sizeof(double) * 3 * Ng});
+  v.push_back({c->jh[0], sizeof(double2) * 3 * Ng});
+  v.push_back({c->pot0, sizeof(double) * 6 * Ng});
+  return v;
+}
+
+size_t state_bytes(gmhc_ctx* c) {
+  size_t off = (sizeof(StateHeader) + 7) & ~(size_t)7;
+  for (const auto& sc : state_sections(c)) off += (sc.bytes + 7) & ~(size_t)7;
+  return off;
 }
 
 int ncomp_of(int32_t which) {
@@ -459,6 +547,7 @@ int32_t gmhc_create(const gmhc_config* cfg, gmhc_ctx** out) {
   if (c.precision != GMHC_FP64 && c.precision != GMHC_FP32_BULK) return GMHC_EINVAL;
   if (c.max_outer < 1 || c.max_inner < 1 || !(c.beta > 0.0 && c.beta <= 1.0)) return GMHC_EINVAL;
   if (c.timing < 0) return GMHC_EINVAL;
+  if (c.deterministic != 0 && c.deterministic != 1) return GMHC_EINVAL;
   if (c.outer_scheme != 0 && c.outer_scheme != 1) return GMHC_EINVAL;
   if (c.outer_scheme == 1 &&
       (c.anderson_m < 1 || c.anderson_m > 8 || c.anderson_start < 1 || c.ls_halvings < 0 || c.ls_halvings > 30 ||
@@ -606,7 +695,8 @@ int32_t gmhc_load_particles(gmhc_ctx* ctx, const double* x, const double* u, con
   HIPCK(launch_iota(ctx->id, np, ctx->stream));
   for (int l = 0; l < 3; ++l)
     if (np) HIPCK(hipMemsetAsync(ctx->vb[l], 0, ctx->es * (size_t)np, ctx->stream));
-  HIPCK(hipStreamSynchronize(ctx->stream));
+  int32_t st = set_fix_scale(ctx);
+  if (st) return st;
   ctx->loaded = true;
   ctx->initialized = false;
   return GMHC_OK;
@@ -618,12 +708,12 @@ int32_t gmhc_load_potentials(gmhc_ctx* ctx, const double* A0, const double* U0, 
   if (!ctx->bound) return fail(ctx, GMHC_ESTATE, "bind before loading potentials");
   DevGuard g(ctx->device);
   const int64_t Ng = ctx->M.Ng;
-  HIPCK(hipMemcpyAsync(ctx->rscr, A0, sizeof(double) * 3 * Ng, kind_of(ptr_kind, true), ctx->stream));
-  HIPCK(hipMemcpyAsync(ctx->rscr + 3 * Ng, U0, sizeof(double) * 3 * Ng, kind_of(ptr_kind, true), ctx->stream));
-  HIPCK(fft_nd(ctx->M, ctx->axes, 6, ctx->rscr, nullptr, ctx->S0 + 3 * Ng, nullptr, nullptr, false, false,
-               ctx->stream));
+  // kept in real space: every later gmhc_initialize starts from them
+  HIPCK(hipMemcpyAsync(ctx->pot0, A0, sizeof(double) * 3 * Ng, kind_of(ptr_kind, true), ctx->stream));
+  HIPCK(hipMemcpyAsync(ctx->pot0 + 3 * Ng, U0, sizeof(double) * 3 * Ng, kind_of(ptr_kind, true), ctx->stream));
   HIPCK(hipStreamSynchronize(ctx->stream));
   ctx->have_pot = true;
+  ctx->initialized = false;
   return GMHC_OK;
 }
 
@@ -635,10 +725,15 @@ int32_t gmhc_initialize(gmhc_ctx* ctx) {
   const Mesh& M = ctx->M;
   const int64_t Ng = M.Ng;
   hipStream_t s = ctx->stream;
-  if (!ctx->have_pot) HIPCK(hipMemsetAsync(ctx->S0 + 3 * Ng, 0, sizeof(double2) * 6 * Ng, s));
-  // point-shape deposit of rho (into rscr[0]) and J (into Jdep); v = V(p)
-  HIPCK(hipMemsetAsync(ctx->rscr, 0, sizeof(double) * Ng, s));
-  HIPCK(hipMemsetAsync(ctx->Jdep, 0, sizeof(double) * 3 * Ng, s));
+  if (ctx->have_pot)
+    HIPCK(fft_nd(M, ctx->axes, 6, ctx->pot0, nullptr, ctx->S0 + 3 * Ng, nullptr, nullptr, false, false, s));
+  else
+    HIPCK(hipMemsetAsync(ctx->S0 + 3 * Ng, 0, sizeof(double2) * 6 * Ng, s));
+  // point-shape deposit of rho and J as fixed-point sums (rho in cscr, J in Jdep), then
+  // to FP64 in rscr (rho) and rscr + Ng (J); v = V(p)
+  unsigned long long* rho_fx = reinterpret_cast<unsigned long long*>(ctx->cscr);
+  HIPCK(hipMemsetAsync(rho_fx, 0, sizeof(unsigned long long) * 2 * Ng, s));
+  HIPCK(hipMemsetAsync(ctx->Jdep, 0, sizeof(unsigned long long) * 6 * Ng, s));
   InitArgs ia{};
   ia.M = M;
   ia.np = ctx->np;
@@ -647,14 +742,16 @@ int32_t gmhc_initialize(gmhc_ctx* ctx) {
     ia.x[l] = ctx->x[l];
     ia.P[l] = ctx->P[l];
     ia.v[l] = ctx->vb[l];
-    ia.J[l] = ctx->Jdep + l * Ng;
   }
+  ia.J = ctx->Jdep;
   ia.q = ctx->q;
   ia.prec = ctx->prec;
-  ia.rho = ctx->rscr;
+  ia.rho = rho_fx;
   HIPCK(launch_init_deposit(ia, s));
+  HIPCK(launch_fix_to_double(rho_fx, ctx->rscr, Ng, M.fx, s));
+  HIPCK(launch_fix_to_double(ctx->Jdep, ctx->rscr + Ng, 3 * Ng, M.fx, s));
   HIPCK(fft_nd(M, ctx->axes, 1, ctx->rscr, nullptr, ctx->S0 + 2 * Ng, nullptr, nullptr, false, false, s));
-  HIPCK(fft_nd(M, ctx->axes, 3, ctx->Jdep, nullptr, ctx->jh[0], nullptr, nullptr, false, false, s));
+  HIPCK(fft_nd(M, ctx->axes, 3, ctx->rscr + Ng, nullptr, ctx->jh[0], nullptr, nullptr, false, false, s));
   InitSpecArgs sa{};
   sa.M = M;
   sa.kappa2 = ctx->cfg.kappa * ctx->cfg.kappa;
@@ -916,9 +1013,7 @@ int32_t eval_outer(gmhc_ctx* ctx, int cur, int hs, gmhc_step_report& R, bool& us
   R.segments += (int64_t)llround(h[OP_SEGS]);
   R.inner_max = (int32_t)llround(h[OP_ITMAX]);
   R.inner_mean = np ? h[OP_ITERS] / (double)np : 0.0;
-  if (h[OP_FAIL] > 0.0)
-    return fail(ctx, GMHC_EINNER,
-                "particle inner solve failed (" + std::to_string((long long)h[OP_FAIL]) + " particles)");
+  if (h[OP_FAIL] > 0.0) return fail(ctx, GMHC_EINNER, inner_fail_msg(h[OP_FAIL], h[OP_XLIM]));
   const double* r = ctx->hres + kResOff;
   const double n3 = 3.0 * (double)Ng;
   rr = sqrt(r[0] / n3) /
@@ -1092,9 +1187,7 @@ int32_t run_picard(gmhc_ctx* ctx, gmhc_step_report& R) {
     R.res_max_ratio = acc[6];
     if (c[0]) {
       ctx->ctl_clean = true;  // cleared by launch_ctl_publish
-      if (c[1])
-        return fail(ctx, GMHC_EINNER,
-                    "particle inner solve failed (" + std::to_string((long long)acc[4]) + " particles)");
+      if (c[1]) return fail(ctx, GMHC_EINNER, inner_fail_msg(acc[4], acc[11]));
       ctx->last_outer = c[2];
       int32_t st = commit_outer(ctx, slot[c[2]], acc[5], acc[6], acc[7], acc[8], acc[9], c[2] & 1);
       if (st) return st;
@@ -1496,6 +1589,7 @@ int32_t gmhc_orbit_pass_frozen(gmhc_ctx* ctx, int32_t iterate, gmhc_pass_report*
   gmhc_pass_report R{};
   const double* h = ctx->hres;
   R.failed = (int64_t)llround(h[OP_FAIL]);
+  R.over_limit = (int32_t)llround(h[OP_XLIM]);
   R.inner_max = (int32_t)llround(h[OP_ITMAX]);
   R.evaluations = (int64_t)llround(h[OP_ITERS]);
   R.segments = (int64_t)llround(h[OP_SEGS]);
@@ -1525,8 +1619,101 @@ int32_t gmhc_read_pass(gmhc_ctx* ctx, double* vout, double* Pnp1, double* J, int
     for (int c = 0; c < 3; ++c) HIPCK(hipMemcpyAsync(Pnp1 + c * np, ctx->pscr[c], b, kind_of(ptr_kind, false), s));
     HIPCK(hipStreamSynchronize(s));
   }
-  if (J) HIPCK(hipMemcpyAsync(J, ctx->Jdep, sizeof(double) * 3 * Ng, kind_of(ptr_kind, false), s));
+  if (J) {
+    HIPCK(launch_fix_to_double(ctx->Jdep, ctx->rscr, 3 * Ng, ctx->M.fx, s));
+    HIPCK(hipMemcpyAsync(J, ctx->rscr, sizeof(double) * 3 * Ng, kind_of(ptr_kind, false), s));
+  }
   HIPCK(hipStreamSynchronize(s));
+  return GMHC_OK;
+}
+
+int32_t gmhc_state_bytes(const gmhc_ctx* cctx, size_t* bytes) {
+  gmhc_ctx* ctx = const_cast<gmhc_ctx*>(cctx);
+  if (!ctx || !bytes) return GMHC_EINVAL;
+  if (!ctx->bound) return fail(ctx, GMHC_ESTATE, "bind before asking for the state size");
+  *bytes = state_bytes(ctx);
+  return GMHC_OK;
+}
+
+int32_t gmhc_save(gmhc_ctx* ctx, void* dst, size_t bytes, int32_t ptr_kind) {
+  if (!ctx || !dst) return GMHC_EINVAL;
+  if (!ctx->initialized) return fail(ctx, GMHC_ESTATE, "initialize (or load a state) before saving");
+  if (bytes < state_bytes(ctx)) return fail(ctx, GMHC_EINVAL, "destination smaller than gmhc_state_bytes");
+  DevGuard gd(ctx->device);
+  hipStream_t s = ctx->stream;
+  StateHeader h{};
+  memcpy(h.magic, kStateMagic, sizeof(h.magic));
+  h.abi = GMHC_ABI_VERSION;
+  h.dim = ctx->M.d;
+  for (int l = 0; l < 3; ++l) h.n[l] = ctx->M.n[l];
+  h.precision = ctx->prec;
+  h.shape = ctx->M.shape;
+  h.have_pot = ctx->have_pot ? 1 : 0;
+  h.last_outer = ctx->last_outer;
+  h.np = ctx->np;
+  h.ng = ctx->M.Ng;
+  h.step = ctx->step;
+  h.bytes = (int64_t)state_bytes(ctx);
+  h.t = ctx->t;
+  h.E0 = ctx->E0;
+  h.last_chain = ctx->last_chain;
+  h.last_work = ctx->last_work;
+  h.last_rr = ctx->last_rr;
+  h.last_mr = ctx->last_mr;
+  h.fx[0] = ctx->M.fx.up;
+  h.fx[1] = ctx->M.fx.hi;
+  h.fx[2] = ctx->M.fx.lo;
+  char* out = static_cast<char*>(dst);
+  const hipMemcpyKind to = kind_of(ptr_kind, false);
+  HIPCK(hipMemcpyAsync(out, &h, sizeof(h), ptr_kind == GMHC_DEVICE ? hipMemcpyHostToDevice : hipMemcpyHostToHost, s));
+  size_t off = (sizeof(StateHeader) + 7) & ~(size_t)7;
+  for (const auto& sc : state_sections(ctx)) {
+    if (sc.bytes) HIPCK(hipMemcpyAsync(out + off, sc.dev, sc.bytes, to, s));
+    off += (sc.bytes + 7) & ~(size_t)7;
+  }
+  HIPCK(hipStreamSynchronize(s));  // also keeps h alive until its copy is done
+  return GMHC_OK;
+}
+
+int32_t gmhc_load(gmhc_ctx* ctx, const void* src, size_t bytes, int32_t ptr_kind) {
+  if (!ctx || !src) return GMHC_EINVAL;
+  drop_ahead(ctx);
+  if (!ctx->bound) return fail(ctx, GMHC_ESTATE, "bind before loading a state");
+  DevGuard gd(ctx->device);
+  hipStream_t s = ctx->stream;
+  const char* in = static_cast<const char*>(src);
+  StateHeader h{};
+  if (bytes < sizeof(h)) return fail(ctx, GMHC_EINVAL, "state image too small");
+  HIPCK(hipMemcpy(&h, in, sizeof(h), ptr_kind == GMHC_DEVICE ? hipMemcpyDeviceToHost : hipMemcpyHostToHost));
+  bool same = memcmp(h.magic, kStateMagic, sizeof(h.magic)) == 0 && h.abi == GMHC_ABI_VERSION &&
+              h.dim == ctx->M.d && h.precision == ctx->prec && h.shape == ctx->M.shape && h.np == ctx->np &&
+              h.ng == ctx->M.Ng && h.bytes == (int64_t)state_bytes(ctx) && bytes >= (size_t)h.bytes;
+  for (int l = 0; l < 3; ++l) same = same && h.n[l] == ctx->M.n[l];
+  if (!same)
+    return fail(ctx, GMHC_EINVAL,
+                "state image does not match this context (mesh, particle count, precision, shape or ABI)");
+  const hipMemcpyKind from = kind_of(ptr_kind, true);
+  size_t off = (sizeof(StateHeader) + 7) & ~(size_t)7;
+  for (const auto& sc : state_sections(ctx)) {
+    if (sc.bytes) HIPCK(hipMemcpyAsync(sc.dev, in + off, sc.bytes, from, s));
+    off += (sc.bytes + 7) & ~(size_t)7;
+  }
+  HIPCK(hipStreamSynchronize(s));
+  ctx->M.fx = FixScale{h.fx[0], h.fx[1], h.fx[2]};
+  ctx->have_pot = h.have_pot != 0;
+  ctx->last_outer = h.last_outer;
+  ctx->t = h.t;
+  ctx->step = h.step;
+  ctx->E0 = h.E0;
+  ctx->last_chain = h.last_chain;
+  ctx->last_work = h.last_work;
+  ctx->last_rr = h.last_rr;
+  ctx->last_mr = h.last_mr;
+  ctx->loaded = true;
+  ctx->initialized = true;
+  ctx->frozen = false;
+  ctx->pass_done = false;
+  ctx->ctl_clean = false;
   return GMHC_OK;
 }
 

@@ -5,6 +5,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "fixsum.h"
+
 namespace gmhc {
 
 constexpr int kBlock = 256;       // threads per workgroup (4 wave64)
@@ -24,7 +26,7 @@ enum OrbitPart {
   OP_WORK = 4,    // sum q v_out . E-bar
   OP_RA2 = 5,     // sum |R_A|^2
   OP_SEGS = 6,    // knot-split segments over all evaluations (sum)
-  OP_PAD = 7
+  OP_XLIM = 7     // failed solves whose orbit reached the knot-crossing limit (sum)
 };
 
 // Particle momenta, charges and orbit velocities are stored in the bulk type: FP64
@@ -53,6 +55,7 @@ struct Mesh {
   double kf[3];      // 2 pi / len (wavenumber of mode 1; 0 on unused axes)
   double dV;
   int shape;         // B-spline degree of the particle shape (1 or 2)
+  FixScale fx;       // fixed-point scale of the deposited current and charge (fixsum.h)
 };
 
 // Arguments of the orbit pass (one thread per particle).
@@ -81,7 +84,7 @@ struct OrbitArgs {
   // mesh arrays, component stride Ng
   const double* trial;   // [d+6]: grad_h phi^{n+1/2} (d), A^{n+1} (3), U^{n+1/2} (3)
   const double* An;      // [3] A^n
-  double* J;             // [3] orbit current accumulator
+  unsigned long long* J;  // [3] orbit current accumulator, one fixed-point pair per value
   double* partials;      // [kOrbitParts][pstride]: value v of block b at v * pstride + b
   int64_t pstride;       // >= gridDim.x
   const int32_t* stop;   // optional device flag: nonzero = skip the pass
@@ -145,17 +148,17 @@ hipError_t launch_reduce(const double* partials, int nblocks, int64_t bstride, i
 // (cn.jh) computed while loading the first inverse-FFT pass, the new
 // state stored to cn.rho1 .. cn.U1, and the real trial fields [d+6][Ng] written to trial
 // (i k phi^{n+1/2} (d), A^{n+1} (3), U^{n+1/2} (3)) through the complex scratch work;
-// zero[3 Ng] is cleared on the way (may be null).  Skipped when *cn.stop is set.
+// the fixed-point accumulator zero (3 Ng pairs) is cleared on the way (may be null).  Skipped when *cn.stop is set.
 hipError_t field_trial(const Mesh& M, const FftPlanAxis* axes, const CNArgs& cn, double* trial, double2* work,
-                       double* zero, hipStream_t s);
+                       unsigned long long* zero, hipStream_t s);
 
-// H = P J of the deposited current J [3][Ng]: the (Nyquist-projected when project)
+// H = P J of the deposited current J (3 Ng fixed-point pairs, fixsum.h): the (Nyquist-projected when project)
 // spectrum to spec [3][Ng] and the real field to H [3][Ng] through the complex scratch
 // work, with the residual partials of ra (ra.H is H) written to ra.partials; their
 // block count goes to *res_blocks.  The residual is folded into the last FFT pass when
 // three components of an axis-0 line fit a workgroup.  Skipped when *ra.stop is set.
-hipError_t field_h(const Mesh& M, const FftPlanAxis* axes, const double* J, double2* spec, double2* work, double* H,
-                   bool project, const ResidualArgs& ra, int* res_blocks, hipStream_t s);
+hipError_t field_h(const Mesh& M, const FftPlanAxis* axes, const unsigned long long* J, double2* spec,
+                   double2* work, double* H, bool project, const ResidualArgs& ra, int* res_blocks, hipStream_t s);
 
 // Partials of one reduction: out[v] = reduce over blocks b of p[b * bstride + v * vstride]
 // for v < nvals; max_mask bit v set = max, else sum.
@@ -196,10 +199,10 @@ hipError_t launch_reduce_outer(const ReduceSet& a, const ReduceSet& b, const Out
 // state of cn, through the complex scratch twork (not work).  cn.jh must be spec.
 // Requires field_h_next_fits (the residual folded into the last pass).
 bool field_h_next_fits(const Mesh& M, const FftPlanAxis* axes);
-hipError_t field_h_next(const Mesh& M, const FftPlanAxis* axes, const double* J, double2* spec, double2* work,
-                        double* H, bool project, const ResidualArgs& ra, const ReduceSet& ro, const ReduceSet& rr,
-                        const OuterTest& ot, const CNArgs& cn, double* trial, double2* twork, double* zero,
-                        hipStream_t s);
+hipError_t field_h_next(const Mesh& M, const FftPlanAxis* axes, const unsigned long long* J, double2* spec,
+                        double2* work, double* H, bool project, const ResidualArgs& ra, const ReduceSet& ro,
+                        const ReduceSet& rr, const OuterTest& ot, const CNArgs& cn, double* trial, double2* twork,
+                        unsigned long long* zero, hipStream_t s);
 
 // Host-visible (coherent pinned) copy of the Picard control block: ctl[0..3] and
 // acc[0..nacc), then seq, written last with a system-scope release.
@@ -247,10 +250,18 @@ struct InitArgs {
   void* P[3];            // in: mechanical p; out: unchanged (canonical pass adds q A)
   const void* q;
   void* v[3];            // out: V(p)
-  double* rho;           // [Ng] accumulator
-  double* J[3];          // accumulators
+  unsigned long long* rho;  // [Ng] fixed-point accumulator pairs
+  unsigned long long* J;    // [3][Ng] fixed-point accumulator pairs
 };
 hipError_t launch_init_deposit(const InitArgs& a, hipStream_t s);
+
+// out[i] = the FP64 value of fixed-point pair i of acc, i < n.
+hipError_t launch_fix_to_double(const unsigned long long* acc, double* out, int64_t n, const FixScale& fx,
+                                hipStream_t s);
+
+// Per-block sums of |q_i| (bulk type prec) into partials[b * kDiagParts] (the other
+// values of the block are zero), for the fixed-point scale.
+hipError_t launch_abs_charge(const void* q, int prec, int64_t np, double* partials, int blocks, hipStream_t s);
 
 struct InitSpecArgs {
   Mesh M;
@@ -314,7 +325,8 @@ hipError_t launch_unpermute(const void* const* src, int src_prec, double* const*
 hipError_t launch_permute_in(const double* const* src, void* const* dst, int dst_prec, int ncomp,
                              const int32_t* id, int64_t np, hipStream_t s);
 
-// Counting sort of particles by nearest-node cell.
+// Sort of particles by nearest-node cell: the stable radix sort (stable = 1) or the
+// counting sort with atomic cursors (stable = 0); see sort.hip.
 struct SortArgs {
   Mesh M;
   int64_t np;
@@ -326,10 +338,16 @@ struct SortArgs {
   int32_t* id_dst;
   const double* x[3];     // positions (also among src)
   int32_t* key;           // [np]
-  int32_t* count;         // [Ng + 1]
-  int32_t* cursor;        // [Ng]
+  int32_t* count;         // [Ng + 1] (counting sort)
+  int32_t* cursor;        // [Ng] (counting sort)
+  int stable;             // 1: the stable radix sort
+  int32_t* key2;          // [np] (radix sort: keys and indices ping-pong)
+  int32_t* idx;           // [np]
+  int32_t* idx2;          // [np]
+  int32_t* rcount;        // [radix_count_ints(np)] digit counts and scan block sums
 };
 hipError_t sort_by_cell(const SortArgs& a, void* scan_tmp, size_t scan_tmp_bytes, hipStream_t s);
 size_t sort_scan_tmp_bytes(int64_t Ng);
+int64_t radix_count_ints(int64_t np);
 
 }  // namespace gmhc

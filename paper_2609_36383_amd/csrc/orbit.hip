@@ -20,9 +20,11 @@
 // wave, so its particles sit in a small box of cells.  Each workgroup stages in LDS the
 // mesh fields of the box spanned by its particles' nodes and their warm-start orbit
 // endpoints, plus the stencil reach of one node, and accumulates its current deposit
-// in an FP64 LDS tile of the same box, flushed to HBM with one atomic per tile node and
-// component.  Orbit segments whose stencil leaves the tile, and workgroups whose box
-// does not fit, read and deposit through global memory instead.
+// in an FP64 LDS tile of the same box, summed in a fixed order within the wave.  The
+// tile is flushed to HBM as fixed-point integers (fixsum.h), one pair of integer atomics
+// per tile node and component, so the current is the same whatever the order in which
+// workgroups finish.  Orbit segments whose stencil leaves the tile, and workgroups whose
+// box does not fit, read and deposit (fixed-point) through global memory instead.
 //
 // Arithmetic.  The bulk type R (double, or float in the FP32-bulk mode) carries the
 // particle state, the staged fields, the quadrature and the push; positions stay
@@ -815,7 +817,10 @@ __device__ __forceinline__ void deposit_window(const Tile& t, const int jn[3], c
     o[l] = jn[l] - b[l];
     win = win && o[l] <= 1;
   }
-  if (in && !win) {
+  // lanes outside the window add their stencils one lane at a time, in lane order, so
+  // that every tile value is summed in the same order on every run
+  for (uint64_t far = __ballot(in && !win); far != 0; far &= far - 1) {
+    if (lane != __ffsll((long long)far) - 1) continue;
 #pragma unroll
     for (int row = 0; row < NR; ++row) {
       const int cy = D > 1 ? row % 3 : 0, cz = D > 2 ? row / 3 : 0;
@@ -824,7 +829,7 @@ __device__ __forceinline__ void deposit_window(const Tile& t, const int jn[3], c
 #pragma unroll
       for (int c = 0; c < 3; ++c)
 #pragma unroll
-        for (int k = 0; k < 3; ++k) atomicAdd(s_J + k * t.nodes + g0 + c, coef[k] * (double)S[row][c]);
+        for (int k = 0; k < 3; ++k) s_J[k * t.nodes + g0 + c] += coef[k] * (double)S[row][c];
     }
   }
   const double cf[3] = {win ? coef[0] : 0.0, win ? coef[1] : 0.0, win ? coef[2] : 0.0};
@@ -906,7 +911,7 @@ __device__ void deposit_phase(const OrbitArgs& a, const Tile& t, const R* gx, co
 #pragma unroll
           for (int k = 0; k < 3; ++k) {
             Ub[k] += S[c] * ld<D, R, false>(a, t, D + 6 + k, g);
-            if (do_dep) atomicAdd(a.J + (int64_t)k * a.M.Ng + g, coef[k] * (double)S[c]);
+            if (do_dep) fix_add(a.J, (int64_t)k * a.M.Ng + g, coef[k] * (double)S[c], a.M.fx.up);
           }
         }
       }
@@ -1107,6 +1112,7 @@ __attribute__((amdgpu_waves_per_eu(orbit_waves<D, R>()))) void k_orbit(OrbitArgs
       pc.gpn = sqrt_(R(1) + u2);
     }
     int it = 0, segs = 0;
+    bool xlim = false;  // the orbit reached the supported knot-crossing range
     const int maxit = a.iterate ? a.max_inner : 1;
     const R kap2 = R(a.kappa) * R(a.kappa);
     const R P[3] = {P0[0], P0[1], P0[2]};
@@ -1114,9 +1120,11 @@ __attribute__((amdgpu_waves_per_eu(orbit_waves<D, R>()))) void k_orbit(OrbitArgs
       // the orbit must stay finite and within the supported knot-crossing range
       const R vn2 = vin[0] * vin[0] + vin[1] * vin[1] + vin[2] * vin[2];
       bool okv = valid && isfinite(vn2);
+      bool inr = true;
 #pragma unroll
-      for (int l = 0; l < D; ++l) okv = okv && fabs(R(a.dt) * vin[l] * R(M.inv_h[l])) < R(kMaxCross - 1);
-      if (!okv) break;
+      for (int l = 0; l < D; ++l) inr = inr && fabs(R(a.dt) * vin[l] * R(M.inv_h[l])) < R(kMaxCross - 1);
+      xlim = okv && !inr;
+      if (!okv || !inr) break;
       EvalOut<R> o;
       evaluate<D, SH, NGL, R>(a, t, gx, gw, j0, f0, P, pc, Am, vin, o);
       segs += o.nseg;
@@ -1170,6 +1178,7 @@ __attribute__((amdgpu_waves_per_eu(orbit_waves<D, R>()))) void k_orbit(OrbitArgs
     part[OP_ITERS] = (double)it;
     part[OP_ITMAX] = (double)it;
     part[OP_SEGS] = (double)segs;
+    part[OP_XLIM] = (!conv && xlim) ? 1.0 : 0.0;
   }
 
   // ---- deposit phase (every lane of the workgroup, converged particles contribute)
@@ -1199,7 +1208,8 @@ __attribute__((amdgpu_waves_per_eu(orbit_waves<D, R>()))) void k_orbit(OrbitArgs
     }
   }
   __syncthreads();
-  // flush the current tile: one atomic per nonzero tile node and component
+  // flush the current tile: one fixed-point addition (two integer atomics) per nonzero
+  // tile node and component, so the sum over workgroups does not depend on their order
   if (t.ok && a.deposit) {
     const double* s_J = s_dyn + t.joff;
     const int* s_g = reinterpret_cast<const int*>(s_dyn) + t.goff;
@@ -1209,7 +1219,7 @@ __attribute__((amdgpu_waves_per_eu(orbit_waves<D, R>()))) void k_orbit(OrbitArgs
       const int64_t g = s_g[nd];
 #pragma unroll
       for (int c = 0; c < 3; ++c)
-        if (v[c] != 0.0) atomicAdd(a.J + (int64_t)c * M.Ng + g, v[c]);
+        if (v[c] != 0.0) fix_add(a.J, (int64_t)c * M.Ng + g, v[c], M.fx.up);
     }
   }
   // workgroup (one wave) reduction in a fixed order: the sums by one reduce-scatter (the

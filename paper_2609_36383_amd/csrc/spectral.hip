@@ -172,11 +172,13 @@ struct FftTask {
   int fwd, inv;         // transforms of the pass (forward first when both)
   int project;          // zero the even-grid Nyquist modes after the forward transform
   const double* src_r;  // real input, or
+  const unsigned long long* src_fx;  // real input as fixed-point pairs (fixsum.h), or
   const double2* src_c; // complex input (unless the load computes the CN solve)
   double2* dst_c;       // complex output, or
   double* dst_r;        // real part of the output
   double2* spec;        // fwd && inv: the projected spectrum is stored here
-  double* zero;         // zero[c Ng + g] = 0 at the output positions of components c < 3
+  unsigned long long* zero;  // fixed-point pair c Ng + g cleared at the output positions
+                             // of components c < 3
   int res;              // fold the outer residual of H = output (cpb == 3)
   ResidualArgs ra;
 };
@@ -233,7 +235,8 @@ __device__ __forceinline__ void fft_body(const FftTask& t, const CNArgs& cn, con
       if (IN == 2)
         v = cn_point(cn, g, (int)comp, true);
       else if (IN == 1)
-        v = make_double2(t.src_r[comp * Ng + g], 0.0);
+        v = make_double2(t.src_fx ? fix_value(t.src_fx, comp * Ng + g, M.fx.hi, M.fx.lo) : t.src_r[comp * Ng + g],
+                         0.0);
       else
         v = t.src_c[comp * Ng + g];
     }
@@ -315,7 +318,10 @@ __device__ __forceinline__ void fft_body(const FftTask& t, const CNArgs& cn, con
       t.dst_r[comp * Ng + g] = v.x;
     else
       t.dst_c[comp * Ng + g] = v;
-    if (t.zero && comp < 3) t.zero[comp * Ng + g] = 0.0;
+    if (t.zero && comp < 3) {
+      t.zero[2 * (comp * Ng + g)] = 0ull;
+      t.zero[2 * (comp * Ng + g) + 1] = 0ull;
+    }
   }
   if (t.res) {
     // the three components of H at each node of the workgroup's lines
@@ -445,6 +451,7 @@ __device__ void outer_test(const OuterTest& t) {
   acc[10] = h[OP_ITERS];
   if (h[OP_FAIL] > 0.0) {
     acc[4] = h[OP_FAIL];
+    acc[11] = h[OP_XLIM];
     t.ctl[1] = 1;
     t.ctl[2] = t.k;
     t.ctl[0] = 1;
@@ -644,10 +651,27 @@ __global__ __launch_bounds__(kBlock) void k_init_deposit(InitArgs a) {
   double wts[27];
   const int cnt = point_stencil(a.M, a.x, i, nodes, wts);
   const double qd = q / a.M.dV;
+  const int64_t Ng = a.M.Ng;
   for (int k = 0; k < cnt; ++k) {
-    atomicAdd(a.rho + nodes[k], qd * wts[k]);
-    for (int c = 0; c < 3; ++c) atomicAdd(a.J[c] + nodes[k], qd * v[c] * wts[k]);
+    fix_add(a.rho, nodes[k], qd * wts[k], a.M.fx.up);
+    for (int c = 0; c < 3; ++c) fix_add(a.J, c * Ng + nodes[k], qd * v[c] * wts[k], a.M.fx.up);
   }
+}
+
+__global__ __launch_bounds__(kBlock) void k_fix_to_double(const unsigned long long* acc, double* out, int64_t n,
+                                                          FixScale fx) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = fix_value(acc, i, fx.hi, fx.lo);
+}
+
+// Sum of |q| (bound of the charge and current sums per node): one value per block in
+// the first slot of its kDiagParts partials.
+__global__ __launch_bounds__(kBlock) void k_abs_charge(const void* q, int prec, int64_t np, double* partials) {
+  double part[kDiagParts];
+  for (int v = 0; v < kDiagParts; ++v) part[v] = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < np; i += (int64_t)gridDim.x * blockDim.x)
+    part[0] += fabs(ld_bulk(q, i, prec));
+  block_store<kDiagParts>(part, 0u, partials);
 }
 
 // Spectral initialization: neutralizing background (k = 0 charge removed), Nyquist
@@ -941,7 +965,8 @@ namespace {
 
 // field_trial's pass over axis l: the CN solve at load (l = 0), the inverse along l, and on
 // the last axis the real trial fields with `zero` cleared.
-FftTask trial_task(const Mesh& M, const FftPlanAxis* axes, int l, double* trial, double2* work, double* zero) {
+FftTask trial_task(const Mesh& M, const FftPlanAxis* axes, int l, double* trial, double2* work,
+                   unsigned long long* zero) {
   FftTask t{};
   t.ax = axes[l];
   t.cpb = 1;
@@ -954,12 +979,12 @@ FftTask trial_task(const Mesh& M, const FftPlanAxis* axes, int l, double* trial,
 }
 
 // field_h's forward pass over axis l < d - 1 (real J in on axis 0).
-FftTask h_forward_task(const FftPlanAxis* axes, int l, const double* J, double2* work) {
+FftTask h_forward_task(const FftPlanAxis* axes, int l, const unsigned long long* J, double2* work) {
   FftTask t{};
   t.ax = axes[l];
   t.cpb = 1;
   t.fwd = 1;
-  t.src_r = J;
+  t.src_fx = J;
   t.src_c = work;
   t.dst_c = work;
   return t;
@@ -968,7 +993,7 @@ FftTask h_forward_task(const FftPlanAxis* axes, int l, const double* J, double2*
 // field_h's pass over axis l of its inverse sweep: on axis d - 1 the forward transform
 // first, the projected spectrum out, then the inverse; on axis 0 H out and, with
 // fuse_res, the residual folded.
-FftTask h_inverse_task(const Mesh& M, const FftPlanAxis* axes, int l, const double* J, double2* spec,
+FftTask h_inverse_task(const Mesh& M, const FftPlanAxis* axes, int l, const unsigned long long* J, double2* spec,
                        double2* work, double* H, bool project, bool fuse_res, const ResidualArgs& ra) {
   const bool top = (l == M.d - 1), last = (l == 0);
   FftTask t{};
@@ -978,7 +1003,7 @@ FftTask h_inverse_task(const Mesh& M, const FftPlanAxis* axes, int l, const doub
   t.project = (top && project) ? 1 : 0;
   t.cpb = (last && fuse_res) ? 3 : 1;
   t.res = (last && fuse_res) ? 1 : 0;
-  t.src_r = J;
+  t.src_fx = J;
   t.src_c = work;
   t.dst_c = work;
   t.dst_r = H;
@@ -991,7 +1016,7 @@ FftTask h_inverse_task(const Mesh& M, const FftPlanAxis* axes, int l, const doub
 }  // namespace
 
 hipError_t field_trial(const Mesh& M, const FftPlanAxis* axes, const CNArgs& cn, double* trial, double2* work,
-                       double* zero, hipStream_t s) {
+                       unsigned long long* zero, hipStream_t s) {
   const int d = M.d;
   for (int l = 0; l < d; ++l) {
     hipError_t e = fft_pass(M, trial_task(M, axes, l, trial, work, zero), d + 6, l == 0 ? 2 : 0, l == d - 1, &cn, s,
@@ -1001,8 +1026,8 @@ hipError_t field_trial(const Mesh& M, const FftPlanAxis* axes, const CNArgs& cn,
   return hipSuccess;
 }
 
-hipError_t field_h(const Mesh& M, const FftPlanAxis* axes, const double* J, double2* spec, double2* work, double* H,
-                   bool project, const ResidualArgs& ra, int* res_blocks, hipStream_t s) {
+hipError_t field_h(const Mesh& M, const FftPlanAxis* axes, const unsigned long long* J, double2* spec,
+                   double2* work, double* H, bool project, const ResidualArgs& ra, int* res_blocks, hipStream_t s) {
   const int d = M.d;
   const int32_t* stop = ra.stop;
   const bool fuse_res = fits(axes[0], 3);
@@ -1033,10 +1058,10 @@ hipError_t field_h(const Mesh& M, const FftPlanAxis* axes, const double* J, doub
 
 bool field_h_next_fits(const Mesh& M, const FftPlanAxis* axes) { return fits(axes[0], 3); }
 
-hipError_t field_h_next(const Mesh& M, const FftPlanAxis* axes, const double* J, double2* spec, double2* work,
-                        double* H, bool project, const ResidualArgs& ra, const ReduceSet& ro, const ReduceSet& rr,
-                        const OuterTest& ot, const CNArgs& cn, double* trial, double2* twork, double* zero,
-                        hipStream_t s) {
+hipError_t field_h_next(const Mesh& M, const FftPlanAxis* axes, const unsigned long long* J, double2* spec,
+                        double2* work, double* H, bool project, const ResidualArgs& ra, const ReduceSet& ro,
+                        const ReduceSet& rr, const OuterTest& ot, const CNArgs& cn, double* trial, double2* twork,
+                        unsigned long long* zero, hipStream_t s) {
   const int d = M.d;
   const int32_t* stop = ra.stop;
   if (!fits(axes[0], 3)) return hipErrorInvalidValue;
@@ -1148,6 +1173,18 @@ hipError_t launch_axpy2(double* y, const double* x, double2* yc, const double2* 
 hipError_t launch_init_deposit(const InitArgs& a, hipStream_t s) {
   if (a.np <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_init_deposit, dim3(nblk(a.np)), dim3(kBlock), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_fix_to_double(const unsigned long long* acc, double* out, int64_t n, const FixScale& fx,
+                                hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fix_to_double, dim3(nblk(n)), dim3(kBlock), 0, s, acc, out, n, fx);
+  return hipGetLastError();
+}
+
+hipError_t launch_abs_charge(const void* q, int prec, int64_t np, double* partials, int blocks, hipStream_t s) {
+  hipLaunchKernelGGL(k_abs_charge, dim3((unsigned)blocks), dim3(kBlock), 0, s, q, prec, np, partials);
   return hipGetLastError();
 }
 

@@ -15,7 +15,7 @@ LIB_PATH = os.path.join(HERE, "libgmhc.so")
 
 OK, EINVAL, ESTATE, ENOMEM, EDEVICE, EINNER, ENOCONV = 0, -1, -2, -3, -4, -5, -6
 HOST, DEVICE = 0, 1
-ABI_VERSION = 3  # layout of the structures below (include/gmhc.h, GMHC_ABI_VERSION)
+ABI_VERSION = 4  # layout of the structures below (include/gmhc.h, GMHC_ABI_VERSION)
 FP64, FP32_BULK = 0, 1
 PICARD, ANDERSON = 0, 1
 FIELD = {"phi": 0, "psi": 1, "A": 2, "U": 3, "rho": 4, "J": 5, "E": 6, "B": 7}
@@ -27,7 +27,7 @@ SYMBOLS = (
     "gmhc_workspace_bytes", "gmhc_bind", "gmhc_load_particles", "gmhc_load_potentials",
     "gmhc_initialize", "gmhc_step", "gmhc_diagnostics", "gmhc_read_particles",
     "gmhc_set_particle_state", "gmhc_read_field", "gmhc_mode_amplitude", "gmhc_set_frozen_fields",
-    "gmhc_orbit_pass_frozen", "gmhc_read_pass",
+    "gmhc_orbit_pass_frozen", "gmhc_read_pass", "gmhc_state_bytes", "gmhc_save", "gmhc_load",
 )
 
 
@@ -43,7 +43,7 @@ class Config(C.Structure):
         ("timing", C.c_int32), ("graphs", C.c_int32),
         ("outer_scheme", C.c_int32), ("anderson_m", C.c_int32), ("anderson_start", C.c_int32),
         ("ls_halvings", C.c_int32), ("shape_order", C.c_int32),
-        ("reserved", C.c_int32),
+        ("deterministic", C.c_int32),
         ("anderson_lambda", C.c_double), ("ls_decrease", C.c_double), ("ls_growth", C.c_double),
     ]
 
@@ -62,7 +62,7 @@ class Diag(C.Structure):
 
 
 class PassReport(C.Structure):
-    _fields_ = [("failed", C.c_int64), ("inner_max", C.c_int32), ("pad", C.c_int32),
+    _fields_ = [("failed", C.c_int64), ("inner_max", C.c_int32), ("over_limit", C.c_int32),
                 ("inner_mean", C.c_double), ("evaluations", C.c_int64), ("orbit_ms", C.c_double),
                 ("segments", C.c_int64)]
 
@@ -107,6 +107,9 @@ def load_library(path=LIB_PATH):
         "gmhc_set_frozen_fields": ([vp, vp, vp, vp, vp, i32], i32),
         "gmhc_orbit_pass_frozen": ([vp, i32, C.POINTER(PassReport)], i32),
         "gmhc_read_pass": ([vp, vp, vp, vp, i32], i32),
+        "gmhc_state_bytes": ([vp, C.POINTER(C.c_size_t)], i32),
+        "gmhc_save": ([vp, vp, C.c_size_t, i32], i32),
+        "gmhc_load": ([vp, vp, C.c_size_t, i32], i32),
     }
     for name, (args, res) in sig.items():
         f = getattr(L, name)
@@ -131,7 +134,7 @@ def make_config(dim, n, lo, length, dt, kappa=1.0, sigma1=1.0, sigma2=1.0, gl_or
                 tol_outer_rel=1e-12, tol_inner_abs=1e-14, tol_inner_rel=1e-12, max_outer=80,
                 max_inner=64, beta=1.0, timing=0, graphs=0, outer_scheme=0, anderson_m=4,
                 anderson_start=2, ls_halvings=6, anderson_lambda=1e-12, ls_decrease=1e-4, ls_growth=1.2,
-                shape_order=2):
+                shape_order=2, deterministic=1):
     c = Config()
     c.dim = dim
     for i in range(3):
@@ -146,6 +149,7 @@ def make_config(dim, n, lo, length, dt, kappa=1.0, sigma1=1.0, sigma2=1.0, gl_or
     c.outer_scheme, c.anderson_m, c.anderson_start, c.ls_halvings = outer_scheme, anderson_m, anderson_start, ls_halvings
     c.anderson_lambda, c.ls_decrease, c.ls_growth = anderson_lambda, ls_decrease, ls_growth
     c.shape_order = shape_order
+    c.deterministic = deterministic
     return c
 
 
@@ -276,6 +280,36 @@ class Simulation:
         r = PassReport()
         self._chk(self.lib.gmhc_orbit_pass_frozen(self.h, int(iterate), C.byref(r)), "gmhc_orbit_pass_frozen")
         return _todict(r)
+
+    # -- checkpoint / restore of the accepted state ---------------------------------
+    def state_bytes(self):
+        n = C.c_size_t()
+        self._chk(self.lib.gmhc_state_bytes(self.h, C.byref(n)), "gmhc_state_bytes")
+        return n.value
+
+    def save(self, out=None):
+        """The accepted state as an image: into a new host uint8 array, or into `out`
+        (a numpy uint8 array, or a torch uint8 tensor on this device)."""
+        n = self.state_bytes()
+        if out is None:
+            out = np.zeros(n, dtype=np.uint8)
+        if isinstance(out, np.ndarray):
+            assert out.dtype == np.uint8 and out.size >= n and out.flags.c_contiguous
+            self._chk(self.lib.gmhc_save(self.h, out.ctypes.data_as(C.c_void_p), out.size, HOST), "gmhc_save")
+        else:
+            assert out.dtype == self.torch.uint8 and out.numel() >= n and out.is_contiguous()
+            self.stream.wait_stream(self.torch.cuda.current_stream(self.device))
+            self._chk(self.lib.gmhc_save(self.h, C.c_void_p(out.data_ptr()), out.numel(), DEVICE), "gmhc_save")
+        return out
+
+    def load(self, image):
+        """Restore an image written by save() (numpy or device tensor)."""
+        if isinstance(image, np.ndarray):
+            image = np.ascontiguousarray(image, dtype=np.uint8)
+            self._chk(self.lib.gmhc_load(self.h, image.ctypes.data_as(C.c_void_p), image.size, HOST), "gmhc_load")
+        else:
+            self.stream.wait_stream(self.torch.cuda.current_stream(self.device))
+            self._chk(self.lib.gmhc_load(self.h, C.c_void_p(image.data_ptr()), image.numel(), DEVICE), "gmhc_load")
 
     def read_pass(self):
         vout = np.zeros((3, self.np))

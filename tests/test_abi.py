@@ -43,9 +43,15 @@ def test_host_validation():
         hh = C.c_void_p()
         assert lib.gmhc_create(C.byref(c), C.byref(hh)) == G.OK, sh
         lib.gmhc_destroy(hh)
-    # shape_order took the place of one reserved int: the struct layout is unchanged
+    # shape_order and deterministic took the places of two reserved ints: the struct
+    # layout is unchanged
     assert G.Config.shape_order.offset == G.Config.ls_halvings.offset + 4
-    assert G.Config.anderson_lambda.offset == G.Config.reserved.offset + 4
+    assert G.Config.anderson_lambda.offset == G.Config.deterministic.offset + 4
+    for det in (0, 1):
+        c = G.make_config(2, (16, 16), (0, 0), (3.2, 3.2), 0.05, deterministic=det)
+        hh = C.c_void_p()
+        assert lib.gmhc_create(C.byref(c), C.byref(hh)) == G.OK, det
+        lib.gmhc_destroy(hh)
     bad = [
         dict(sigma1=2.0),                 # sigma1 != kappa^2 sigma2
         dict(dt=0.0),
@@ -61,6 +67,7 @@ def test_host_validation():
         dict(timing=-1),
         dict(shape_order=3),
         dict(shape_order=-1),
+        dict(deterministic=2),
     ]
     for over in bad:
         kw = dict(dim=2, n=(16, 16), lo=(0, 0), length=(3.2, 3.2), dt=0.05)
@@ -84,5 +91,10 @@ def test_calls_out_of_order_are_rejected():
     assert lib.gmhc_create(C.byref(c), C.byref(h)) == G.OK
     assert lib.gmhc_initialize(h) == G.ESTATE
     assert lib.gmhc_step(h, None) == G.ESTATE
+    n = C.c_size_t()
+    assert lib.gmhc_state_bytes(h, C.byref(n)) == G.ESTATE  # not bound
+    buf = (C.c_uint8 * 64)()
+    assert lib.gmhc_save(h, buf, 64, G.HOST) == G.ESTATE
+    assert lib.gmhc_load(h, buf, 64, G.HOST) == G.ESTATE
     assert b"initialize" in lib.gmhc_last_error(h) or lib.gmhc_last_error(h)
     lib.gmhc_destroy(h)
