@@ -797,56 +797,53 @@ __device__ void window_deposit(const Tile& t, const R (&S)[NR][3], const int o[3
 // integrated weights of its stencil (row = cy + 3 cz, node c along x).
 //
 // The lanes whose stencil lies in the tile share a window anchored one node below the
-// wave's lowest stencil base b: three nodes per axis when every such lane has its base at
-// b, four when some have it at b + 1; a lane whose base lies further out on some axis
-// adds its values one by one.  The window lanes place q v_out S / dV into the window
-// (shifted by their offset from b); reduce-scatters over the wave then leave each window
-// value on one lane, which adds it to the tile.  In 2D and 3D the window is taken one
+// lowest stencil base b of their cluster: three nodes per axis when every lane of the
+// cluster has its base at b, four when some have it at b + 1.  The window lanes place
+// q v_out S / dV into the window (shifted by their offset from b); reduce-scatters over
+// the wave then leave each window value on one lane, which adds it to the tile.  In 2D and 3D the window is taken one
 // z-plane at a time, two or three y-rows (at most 32 values) per reduction.
 template <int D, class R, int NR>
 __device__ __forceinline__ void deposit_window(const Tile& t, const int jn[3], const R (&S)[NR][3],
                                                const double coef[3], bool in, int lane) {
   HIP_DYNAMIC_SHARED(double, s_dyn);
   double* s_J = s_dyn + t.joff;
-  if (__ballot(in) == 0) return;
-  int b[3] = {0, 0, 0}, o[3] = {0, 0, 0};
-  bool win = in;
+  // The lanes are taken in clusters.  Each pass takes the lanes whose base lies within one
+  // node, on every axis, of the lowest remaining lane's base, and deposits them through
+  // one window anchored at their lowest base (a fixed-order wave reduction, so every tile
+  // value is summed in the same order on every run).  A sorted wave needs one pass; a wave
+  // whose particles have drifted apart (counter-streaming beams) needs one per cluster.
+  bool todo = in;
+#pragma unroll 1
+  for (uint64_t m = __ballot(todo); m != 0; m = __ballot(todo)) {
+    const int lead = __ffsll((long long)m) - 1;  // wave-uniform
+    bool near = todo;
 #pragma unroll
-  for (int l = 0; l < D; ++l) {
-    b[l] = wave_min_i32(in ? jn[l] : INT_MAX);
-    o[l] = jn[l] - b[l];
-    win = win && o[l] <= 1;
-  }
-  // lanes outside the window add their stencils one lane at a time, in lane order, so
-  // that every tile value is summed in the same order on every run
-  for (uint64_t far = __ballot(in && !win); far != 0; far &= far - 1) {
-    if (lane != __ffsll((long long)far) - 1) continue;
+    for (int l = 0; l < D; ++l) near = near && abs(jn[l] - __builtin_amdgcn_readlane(jn[l], lead)) <= 1;
+    int b[3] = {0, 0, 0}, o[3] = {0, 0, 0};
+    bool win = near;
 #pragma unroll
-    for (int row = 0; row < NR; ++row) {
-      const int cy = D > 1 ? row % 3 : 0, cz = D > 2 ? row / 3 : 0;
-      const int g0 = (jn[0] - 1 - t.o[0]) + t.E[0] * ((D > 1 ? jn[1] + cy - 1 - t.o[1] : 0) +
-                                                      t.E[1] * (D > 2 ? jn[2] + cz - 1 - t.o[2] : 0));
-#pragma unroll
-      for (int c = 0; c < 3; ++c)
-#pragma unroll
-        for (int k = 0; k < 3; ++k) s_J[k * t.nodes + g0 + c] += coef[k] * (double)S[row][c];
+    for (int l = 0; l < D; ++l) {
+      b[l] = wave_min_i32(near ? jn[l] : INT_MAX);
+      o[l] = jn[l] - b[l];
+      win = win && o[l] <= 1;
     }
-  }
-  const double cf[3] = {win ? coef[0] : 0.0, win ? coef[1] : 0.0, win ? coef[2] : 0.0};
-  // window extent: wave-uniform choices
-  const bool wx4 = uni(__ballot(win && o[0] != 0) != 0 ? 1 : 0) != 0;
-  const bool wy4 = D > 1 && uni(__ballot(win && o[1] != 0) != 0 ? 1 : 0) != 0;
-  const int nz = D > 2 ? (uni(__ballot(win && o[2] != 0) != 0 ? 1 : 0) ? 4 : 3) : 1;
-  if (wx4) {
-    if (wy4)
-      window_deposit<D, R, NR, 4, 4>(t, S, o, b, cf, nz, lane, s_J);
-    else
-      window_deposit<D, R, NR, 4, 3>(t, S, o, b, cf, nz, lane, s_J);
-  } else {
-    if (wy4)
-      window_deposit<D, R, NR, 3, 4>(t, S, o, b, cf, nz, lane, s_J);
-    else
-      window_deposit<D, R, NR, 3, 3>(t, S, o, b, cf, nz, lane, s_J);
+    const double cf[3] = {win ? coef[0] : 0.0, win ? coef[1] : 0.0, win ? coef[2] : 0.0};
+    // window extent: wave-uniform choices
+    const bool wx4 = uni(__ballot(win && o[0] != 0) != 0 ? 1 : 0) != 0;
+    const bool wy4 = D > 1 && uni(__ballot(win && o[1] != 0) != 0 ? 1 : 0) != 0;
+    const int nz = D > 2 ? (uni(__ballot(win && o[2] != 0) != 0 ? 1 : 0) ? 4 : 3) : 1;
+    if (wx4) {
+      if (wy4)
+        window_deposit<D, R, NR, 4, 4>(t, S, o, b, cf, nz, lane, s_J);
+      else
+        window_deposit<D, R, NR, 4, 3>(t, S, o, b, cf, nz, lane, s_J);
+    } else {
+      if (wy4)
+        window_deposit<D, R, NR, 3, 4>(t, S, o, b, cf, nz, lane, s_J);
+      else
+        window_deposit<D, R, NR, 3, 3>(t, S, o, b, cf, nz, lane, s_J);
+    }
+    todo = todo && !win;
   }
 }
 

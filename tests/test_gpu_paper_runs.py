@@ -20,11 +20,11 @@ Two-stream (TSI):
 * TSI-0.3 through T = 60 with the paper's Anderson settings: the energy change within ten
   times the printed maximum, the mode amplitude at T = 60 within 5% of the printed one
   (the paper's two time steps differ there by 1.4%), and the transverse RMS velocity far
-  below the O(0.1) the paper reports without the Nyquist projection.  The atomic deposit
-  sums each node in its own order, so node values that should be equal along y and z
-  differ in their last bit; the cold beams are filamentation-unstable across (growth
-  about 0.3 at k = 1/4), which lifts that seed from about 1e-15 to about 1e-7 by T = 60,
-  where the paper prints 4.6e-12.
+  below the O(0.1) the paper reports without the Nyquist projection.  The cell-centre
+  positions carry a row-to-row rounding asymmetry of about 1e-15 in grid units, and the
+  cold beams are filamentation-unstable across (growth about 0.3 at k = 1/4), which lifts
+  that seed to about 1e-7 by T = 60, where the paper prints 4.6e-12.  The GPU adds no
+  asymmetry of its own: on the reduction its transverse velocity follows the oracle's.
 * The projection ablation: TSI-0.1 without Nyquist projection through T = 60 grows
   transverse motion from roundoff to the saturated level the paper prints (0.37).
 """
@@ -165,6 +165,31 @@ def test_tsi_reduced_parity_with_oracle():
     xo, Po, vo = osim.read_particles()
     _say(f"tsi reduced: rel x {_rel(xg, xo):.2e} P {_rel(Pg, Po):.2e} v {_rel(vg, vo):.2e}")
     assert _rel(xg, xo) < 1e-9 and _rel(Pg, Po) < 1e-9 and _rel(vg, vo) < 1e-9
+
+
+def test_tsi_transverse_velocity_parity_on_reduction():
+    """Transverse motion in TSI grows from the loading: the cell-centre positions in y and z
+    are doubles whose offsets from their nearest nodes differ from row to row by up to
+    about 4e-15 (rounding of lo + (i + 1/2) h), and the beams are filamentation-unstable
+    across.  The GPU sums the deposit across workgroups exactly, and in a fixed order
+    within one, so it must add no asymmetry of its own: on the 32 x 4 x 4 reduction its
+    transverse RMS velocity follows the oracle's step by step."""
+    G = _gpu()
+    w = W.spec("tsi", n=(32, 4, 4), dt=0.3, eig_gamma=GTS)
+    base = W.config_dict(w)
+    osim = O.OracleSim(O.config_from_dict(base, gl_order=8))
+    sim = G.Simulation(G.config_from_dict(base, gl_order=0, deterministic=1), w["num_particles"])
+    _load(osim, w)
+    _load(sim, w)
+    worst = 0.0
+    for s in range(30):
+        osim.step()
+        sim.step()
+        a, b = sim.diagnostics()["vperp_rms"], osim.diagnostics()["vperp_rms"]
+        if s % 10 == 9:
+            _say(f"tsi reduction t = {0.3 * (s + 1):.1f}: v_perp,rms GPU {a:.4e} oracle {b:.4e}")
+        worst = max(worst, abs(a - b) / max(b, 1e-300))
+    assert worst < 1e-3, worst
 
 
 def _full_tsi(G, run, steps, **over):
