@@ -107,6 +107,7 @@ def lib():
                                      C.POINTER(C.c_int32)]
         L.orc_orbit_pass.restype = C.c_int64
         L.orc_trial_fields.argtypes = [C.c_void_p, dp, dp, dp, dp, dp]
+        L.orc_spd_solve.argtypes = [C.c_int, dp, dp, dp]
         L.orc_num_particles.argtypes = [C.c_void_p]
         L.orc_num_particles.restype = C.c_int64
         _lib = L
@@ -220,6 +221,17 @@ def interp(cfg, F, x):
     out = np.zeros(3)
     assert lib().orc_interp(C.byref(cfg), _p(_f64(F)), _p(_f64(x)), _p(out)) == OK
     return out
+
+
+def spd_solve(G, b):
+    """x of G x = b by the oracle's Anderson small solve (Cholesky), or None when G is not
+    numerically positive definite."""
+    G = _f64(G)
+    b = _f64(b)
+    n = b.size
+    x = np.zeros(n)
+    st = lib().orc_spd_solve(n, _p(G.reshape(-1)), _p(b), _p(x))
+    return x if st == OK else None
 
 
 def orbit_eval(cfg, gphi, An, Anp1, Uh, x, P, q, m, vin):

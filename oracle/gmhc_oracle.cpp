@@ -695,11 +695,14 @@ void outer_tests(const Sim& S, const RVec H[3], const RVec j[3], double& rms_rat
 }
 
 double wrap1(double v, double lo, double L) {
-  // Reading: one periodic wrap into [lo, lo+L) per step.
-  if (v >= lo + L) v -= L;
-  if (v < lo) v += L;
-  if (v >= lo + L) v -= L;
-  return v;
+  // Reading: the accepted position is wrapped once per step into [lo, lo+L): the
+  // periodic image v - k L with k = floor((v - lo) / L), the rounding of the quotient
+  // corrected at the two ends of the interval.
+  const double k = std::floor((v - lo) / L);
+  double r = v - k * L;
+  if (r >= lo + L) r -= L;
+  if (r < lo) r += L;
+  return r;
 }
 
 void real_fields(const Sim& S, RVec E[3], RVec B[3]) {
@@ -1278,30 +1281,35 @@ void commit_step(Sim& S, const RVec j[3], const RVec vw[3], const OuterEval& E) 
   S.step += 1;
 }
 
-// Solve the small dense system A x = b (n <= 8) by Gaussian elimination with partial
-// pivoting; false if singular or not finite.
-bool small_solve(std::vector<double> A, std::vector<double> b, int n, std::vector<double>& x) {
-  for (int c = 0; c < n; ++c) {
-    int p = c;
-    for (int r = c + 1; r < n; ++r)
-      if (std::fabs(A[r * n + c]) > std::fabs(A[p * n + c])) p = r;
-    if (!(std::fabs(A[p * n + c]) > 0.0) || !std::isfinite(A[p * n + c])) return false;
-    if (p != c) {
-      for (int k = 0; k < n; ++k) std::swap(A[c * n + k], A[p * n + k]);
-      std::swap(b[c], b[p]);
-    }
-    for (int r = c + 1; r < n; ++r) {
-      const double f = A[r * n + c] / A[c * n + c];
-      for (int k = c; k < n; ++k) A[r * n + k] -= f * A[c * n + k];
-      b[r] -= f * b[c];
+// Solve the regularized normal equations of the Anderson step, G x = b with G symmetric
+// positive definite (n <= 8, row-major), by the Cholesky factorization G = L L^T and two
+// triangular solves; false when G is not numerically positive definite or the result is
+// not finite (an unusable history).
+bool spd_solve(const std::vector<double>& G, const std::vector<double>& b, int n, std::vector<double>& x) {
+  std::vector<double> L(n * n, 0.0);
+  for (int j = 0; j < n; ++j) {
+    double d = G[j * n + j];
+    for (int k = 0; k < j; ++k) d -= L[j * n + k] * L[j * n + k];
+    if (!(d > 0.0) || !std::isfinite(d)) return false;
+    L[j * n + j] = std::sqrt(d);
+    for (int i = j + 1; i < n; ++i) {
+      double v = G[i * n + j];
+      for (int k = 0; k < j; ++k) v -= L[i * n + k] * L[j * n + k];
+      L[i * n + j] = v / L[j * n + j];
     }
   }
+  std::vector<double> y(n, 0.0);
+  for (int i = 0; i < n; ++i) {  // L y = b
+    double v = b[i];
+    for (int k = 0; k < i; ++k) v -= L[i * n + k] * y[k];
+    y[i] = v / L[i * n + i];
+  }
   x.assign(n, 0.0);
-  for (int c = n - 1; c >= 0; --c) {
-    double v = b[c];
-    for (int k = c + 1; k < n; ++k) v -= A[c * n + k] * x[k];
-    x[c] = v / A[c * n + c];
-    if (!std::isfinite(x[c])) return false;
+  for (int i = n - 1; i >= 0; --i) {  // L^T x = y
+    double v = y[i];
+    for (int k = i + 1; k < n; ++k) v -= L[k * n + i] * x[k];
+    x[i] = v / L[i * n + i];
+    if (!std::isfinite(x[i])) return false;
   }
   return true;
 }
@@ -1374,7 +1382,7 @@ int orc_step(void* h, orc_report* rep) {
           tr += G[a1 * mh + a1];
         }
         for (int a1 = 0; a1 < mh; ++a1) G[a1 * mh + a1] += S.cfg.anderson_lambda * tr / mh;
-        if (!small_solve(G, b, mh, gam)) {
+        if (!spd_solve(G, b, mh, gam)) {
           dJ.clear();
           dR.clear();
           continue;  // unusable history: damped Picard
@@ -1582,6 +1590,22 @@ int orc_trial_fields(void* h, const double* j, double* gphi, double* An, double*
 int64_t orc_num_particles(void* h) { return static_cast<Sim*>(h)->np; }
 
 // OpenMP threads a parallel region of the oracle runs with (for reporting timings).
-int orc_max_threads(void) { return omp_get_max_threads(); }
+int orc_max_threads(void) {
+#ifdef _OPENMP
+  return omp_get_max_threads();
+#else
+  return 1;
+#endif
+}
+
+// The Anderson step's small solve (spd_solve) on its own, for the tests: x of G x = b;
+// ORC_OK, or ORC_EINVAL when G is not numerically positive definite.
+int orc_spd_solve(int n, const double* G, const double* b, double* x) {
+  if (n < 1 || n > 8) return ORC_EINVAL;
+  std::vector<double> g(G, G + n * n), bb(b, b + n), xx;
+  if (!spd_solve(g, bb, n, xx)) return ORC_EINVAL;
+  for (int i = 0; i < n; ++i) x[i] = xx[i];
+  return ORC_OK;
+}
 
 }  // extern "C"

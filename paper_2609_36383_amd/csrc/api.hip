@@ -1601,7 +1601,7 @@ int32_t gmhc_orbit_pass_frozen(gmhc_ctx* ctx, int32_t iterate, gmhc_pass_report*
   return GMHC_OK;
 }
 
-int32_t gmhc_read_pass(gmhc_ctx* ctx, double* vout, double* Pnp1, double* J, int32_t ptr_kind) {
+int32_t gmhc_read_pass(gmhc_ctx* ctx, double* vout, double* Pnp1, double* J, int32_t* iters, int32_t ptr_kind) {
   if (!ctx) return GMHC_EINVAL;
   drop_ahead(ctx);
   if (!ctx->pass_done) return fail(ctx, GMHC_ESTATE, "no frozen pass has run");
@@ -1617,6 +1617,12 @@ int32_t gmhc_read_pass(gmhc_ctx* ctx, double* vout, double* Pnp1, double* J, int
   if (Pnp1 && np) {
     HIPCK(launch_unpermute(ctx->P2, ctx->prec, ctx->pscr, 3, ctx->id, np, s));
     for (int c = 0; c < 3; ++c) HIPCK(hipMemcpyAsync(Pnp1 + c * np, ctx->pscr[c], b, kind_of(ptr_kind, false), s));
+    HIPCK(hipStreamSynchronize(s));
+  }
+  if (iters && np) {
+    int32_t* tmp = reinterpret_cast<int32_t*>(ctx->pscr[0]);
+    HIPCK(launch_unpermute_i32(ctx->iters, tmp, ctx->id, np, s));
+    HIPCK(hipMemcpyAsync(iters, tmp, sizeof(int32_t) * np, kind_of(ptr_kind, false), s));
     HIPCK(hipStreamSynchronize(s));
   }
   if (J) {

@@ -320,6 +320,8 @@ hipError_t launch_iota(int32_t* id, int64_t np, hipStream_t s);
 // given type (prec 0 FP64, 1 FP32), dst FP64.
 hipError_t launch_unpermute(const void* const* src, int src_prec, double* const* dst, int ncomp,
                             const int32_t* id, int64_t np, hipStream_t s);
+// dst[id[i]] = src[i] for per-particle int32 values.
+hipError_t launch_unpermute_i32(const int32_t* src, int32_t* dst, const int32_t* id, int64_t np, hipStream_t s);
 // dst[c][i] = src[c][id[i]]: gather load-order FP64 data into sorted order, stored in
 // the given type.
 hipError_t launch_permute_in(const double* const* src, void* const* dst, int dst_prec, int ncomp,

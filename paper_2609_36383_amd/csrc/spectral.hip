@@ -824,6 +824,13 @@ __global__ __launch_bounds__(kBlock) void k_unpermute(PermArgs p, int ncomp, con
   }
 }
 
+// dst[id[i]] = src[i]: per-particle integers back to load order.
+__global__ __launch_bounds__(kBlock) void k_unpermute_i32(const int32_t* src, int32_t* dst, const int32_t* id,
+                                                          int64_t np) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < np) dst[id[i]] = src[i];
+}
+
 __global__ __launch_bounds__(kBlock) void k_load_state(const double* u0, const double* u1, const double* u2,
                                                        const double* qd, void* P0, void* P1, void* P2, void* q,
                                                        int prec, double kappa, int64_t np) {
@@ -1212,6 +1219,12 @@ hipError_t launch_spec_diag(const SpecDiagArgs& a, int blocks, hipStream_t s) {
 hipError_t launch_spec_field(const Mesh& M, int which_e, const double2* phi, const double2* A,
                              const double2* U, double2* out, hipStream_t s) {
   hipLaunchKernelGGL(k_spec_field, dim3(nblk(M.Ng)), dim3(kBlock), 0, s, M, which_e, phi, A, U, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_unpermute_i32(const int32_t* src, int32_t* dst, const int32_t* id, int64_t np, hipStream_t s) {
+  if (np <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_unpermute_i32, dim3(nblk(np)), dim3(kBlock), 0, s, src, dst, id, np);
   return hipGetLastError();
 }
 

@@ -106,7 +106,7 @@ def load_library(path=LIB_PATH):
         "gmhc_mode_amplitude": ([vp, i32, i32, C.POINTER(i32), dp], i32),
         "gmhc_set_frozen_fields": ([vp, vp, vp, vp, vp, i32], i32),
         "gmhc_orbit_pass_frozen": ([vp, i32, C.POINTER(PassReport)], i32),
-        "gmhc_read_pass": ([vp, vp, vp, vp, i32], i32),
+        "gmhc_read_pass": ([vp, vp, vp, vp, vp, i32], i32),
         "gmhc_state_bytes": ([vp, C.POINTER(C.c_size_t)], i32),
         "gmhc_save": ([vp, vp, C.c_size_t, i32], i32),
         "gmhc_load": ([vp, vp, C.c_size_t, i32], i32),
@@ -311,11 +311,16 @@ class Simulation:
             self.stream.wait_stream(self.torch.cuda.current_stream(self.device))
             self._chk(self.lib.gmhc_load(self.h, C.c_void_p(image.data_ptr()), image.numel(), DEVICE), "gmhc_load")
 
-    def read_pass(self):
+    def read_pass(self, iters=False, current=True):
+        """v_out, P^{n+1} and J (None unless current) of the last frozen pass, and with
+        iters the per-particle evaluation counts."""
         vout = np.zeros((3, self.np))
         Pn1 = np.zeros((3, self.np))
-        J = np.zeros((3, self.ng))
+        J = np.zeros((3, self.ng)) if current else None
+        it = np.zeros(self.np, dtype=np.int32) if iters else None
         self._chk(self.lib.gmhc_read_pass(self.h, vout.ctypes.data_as(C.c_void_p),
-                                          Pn1.ctypes.data_as(C.c_void_p), J.ctypes.data_as(C.c_void_p),
+                                          Pn1.ctypes.data_as(C.c_void_p),
+                                          J.ctypes.data_as(C.c_void_p) if current else None,
+                                          it.ctypes.data_as(C.c_void_p) if iters else None,
                                           HOST), "gmhc_read_pass")
-        return vout, Pn1, J
+        return (vout, Pn1, J, it) if iters else (vout, Pn1, J)

@@ -4,9 +4,12 @@ current deposit, energy, work and residual sums and the field solve in FP64.
 Checked against the FP64 CPU oracle:
   * one frozen-field orbit evaluation agrees to FP32 rounding (relative 2e-5 of the
     array scale; FP32 epsilon is 6e-8 and the gathers sum up to 27 terms);
-  * whole steps keep the relative energy drift at most 1e-6 and the Gauss-law and
-    Lorenz-gauge residuals at FP64 roundoff (the field solve is FP64);
-  * the two-stream eigenmode grows at the closed-form rate to the same 0.5% as FP64.
+  * whole steps (2D, mixed 2D and 3D reductions) against the FP64 oracle run side by side:
+    relative energy drift at most 1e-6, Gauss-law and Lorenz-gauge residuals at FP64
+    roundoff (the field solve is FP64), momenta, current and field energy within FP32-level
+    error of the oracle;
+  * the two-stream eigenmode's fitted growth rate against the FP64 oracle's fit of the same
+    run, and against the closed form to the same 0.5% as FP64.
 """
 import math
 import sys
@@ -75,16 +78,22 @@ def test_fp32_frozen_single_evaluation(dim, n, length, num):
 @pytest.mark.parametrize("name,over,steps", [
     ("weibel2d", dict(n=(16, 16), ppc=16), 30),
     ("weibel3d", dict(n=(8, 8, 8), ppc=8), 10),
+    ("mixed2d", dict(n=(32, 32), ppc=16), 20),
 ])
-def test_fp32_bulk_steps_energy_and_constraints(name, over, steps):
+def test_fp32_bulk_steps_against_fp64_oracle(name, over, steps):
+    """FP32-bulk whole steps against the FP64 oracle on the same inputs: the relative energy
+    drift of the FP32 run at most 1e-6, Gauss and Lorenz residuals at FP64 roundoff, and
+    the particle momenta, field energy and current within FP32-level error of the FP64
+    oracle (the FP32 inner test stops at 1e-6 relative, so differences of order 1e-5 of
+    the array scale accumulate over the run)."""
     G = _gpu()
     w = W.spec(name, **over)
     x, u, q = W.particles(w)
     sim = G.Simulation(G.config_from_dict(W.config_dict(w, fp32_bulk=True), gl_order=0,
-                                          precision=G.FP32_BULK), q.size)
+                                          precision=G.FP32_BULK, sort_every=5), q.size)
     sim.load_particles(x, u, q)
     sim.initialize()
-    ref = G.Simulation(G.config_from_dict(W.config_dict(w), gl_order=0), q.size)
+    ref = O.OracleSim(O.config_from_dict(W.config_dict(w), gl_order=8))
     ref.load_particles(x, u, q)
     ref.initialize()
     drift = 0.0
@@ -97,13 +106,18 @@ def test_fp32_bulk_steps_energy_and_constraints(name, over, steps):
     xg, Pg, _ = sim.read_particles()
     xr, Pr, _ = ref.read_particles()
     dP = _rel(Pg, Pr)
-    _say(f"fp32 {name}: {steps} steps, drift {drift:.2e}, outer {rep['outer_iters']}, "
-         f"P vs FP64 {dP:.2e}")
+    dJ = _rel(sim.read_field("J"), ref.read_field("J"))
+    dg, do = sim.diagnostics(), ref.diagnostics()
+    dW = abs(dg["field"] - do["field"]) / do["field"]
+    _say(f"fp32 {name} {over}: {steps} steps, energy drift {drift:.2e} (FP64 oracle {do['energy_rel']:.2e}), "
+         f"P vs FP64 oracle {dP:.2e}, J {dJ:.2e}, field energy {dW:.2e}, outer {rep['outer_iters']}")
     assert drift <= 1e-6
-    assert dP < 1e-3
+    assert dP < 1e-4 and dJ < 1e-3 and dW < 1e-3
 
 
 def test_fp32_bulk_eigenmode_growth_rate():
+    """The two-stream eigenmode in FP32-bulk: fitted growth rate against the FP64 oracle's
+    fit of the same run (and against the closed form), and the energy drift."""
     from oracle import closed_forms as CF
     G = _gpu()
     L, n = 4 * math.pi, 64
@@ -113,15 +127,25 @@ def test_fp32_bulk_eigenmode_growth_rate():
     sim = G.Simulation(G.config_from_dict(W.config_dict(w, fp32_bulk=True), precision=G.FP32_BULK), q.size)
     sim.load_particles(x, u, q)
     sim.initialize()
-    ts, amps = [0.0], [sim.mode_amplitude("E", 0, (1, 0, 0))]
+    ref = O.OracleSim(O.config_from_dict(W.config_dict(w), gl_order=8))
+    ref.load_particles(x, u, q)
+    ref.initialize()
+    ts, amps, oamps = [0.0], [sim.mode_amplitude("E", 0, (1, 0, 0))], [ref.mode_amplitude("E", 0, (1, 0, 0))]
     drift = 0.0
     for _ in range(20):
         sim.step()
+        ref.step()
         d = sim.diagnostics()
         drift = max(drift, d["energy_rel"])
         ts.append(d["t"])
         amps.append(sim.mode_amplitude("E", 0, (1, 0, 0)))
-    err = CF.fit_growth(ts, amps, 0.0, 2.0) / Gm - 1
-    _say(f"fp32 tsi1d eigenmode: growth-rate error {err:.2e}, drift {drift:.2e}")
-    assert abs(err) < 5e-3
+        oamps.append(ref.mode_amplitude("E", 0, (1, 0, 0)))
+    fit, ofit = CF.fit_growth(ts, amps, 0.0, 2.0), CF.fit_growth(ts, oamps, 0.0, 2.0)
+    err_oracle, err_closed = fit / ofit - 1, fit / Gm - 1
+    _say(f"fp32 tsi1d eigenmode: growth rate {fit:.8f}, FP64 oracle {ofit:.8f} (error {err_oracle:.2e}), "
+         f"closed form {Gm:.8f} (error {err_closed:.2e}), energy drift {drift:.2e}")
+    # the FP32-bulk outer test accepts a current within 1e-5 relative of the fixed point,
+    # so the mode amplitudes, and a rate fitted over two time units, may differ by that
+    assert abs(err_oracle) < 10 * W.config_dict(w, fp32_bulk=True)["tol_outer_rel"]
+    assert abs(err_closed) < 5e-3
     assert drift <= 1e-6

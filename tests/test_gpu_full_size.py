@@ -6,6 +6,10 @@
   oracle evaluates a seeded random sample of particles one by one and the current is
   checked through the identity sum_g J_g dV = sum_i q_i v_out,i (the orbit-averaged
   shape weights of each particle sum to one).
+* The inner Picard loop at full size (frozen fields, iterate = 1): all particles at 1M,
+  a seeded sample at 67M, with per-particle evaluation counts.
+* Whole implicit steps of the 1M-particle workloads against the oracle, element by
+  element, particle state and fields to 1e-9.
 * Whole implicit steps at full size: relative energy drift at most 10x the nonlinear
   tolerance in FP64 (1e-6 in FP32-bulk), Gauss-law and Lorenz-gauge residuals at FP64
   roundoff.
@@ -115,6 +119,74 @@ def test_full_size_frozen_evaluation_sampled(name):
     _say(f"{name} full frozen (sample of 16384 of {q.size}): v {dv:.2e} P {dP:.2e}; current identity {dj:.2e}")
     assert dv < 1e-12 and dP < 1e-12
     assert dj < 1e-12
+
+
+@pytest.mark.parametrize("name", ["weibel2d", "mixed2d", "weibel3d"])
+def test_full_size_frozen_inner_loop(name):
+    """The inner Picard loop at full size and full tile occupancy (iterate = 1): the GPU
+    runs every particle; the oracle runs all of them at 1M particles and a seeded sample of
+    16384 at 67M.  v_out and P^{n+1} agree to 1e-11 of the array scale, and each particle
+    takes the same number of orbit evaluations (a particle whose inner test sits at its
+    tolerance within rounding may differ by one; at most 1e-4 of them)."""
+    G = _gpu()
+    w, (x, u, q) = _workload(name)
+    gphi, An, Anp1, Uh, P, v = _frozen_inputs(w, x, u, q, seed=43)
+    kw = dict(dim=w["dim"], n=w["n"], lo=w["lo"], length=w["length"], dt=w["dt"])
+    sim = G.Simulation(G.make_config(**kw, gl_order=0), q.size)
+    sim.load_particles(x, u, q)
+    sim.set_particle_state(x, P, v)
+    sim.set_frozen_fields(gphi, An, Anp1, Uh)
+    rep = sim.orbit_pass_frozen(iterate=True)
+    vout, Pn1, _, iters = sim.read_pass(iters=True, current=False)
+    del sim
+    assert rep["failed"] == 0
+    idx = np.arange(q.size) if q.size <= (1 << 20) else \
+        np.sort(np.random.default_rng(47).choice(q.size, 16384, replace=False))
+    osim = O.OracleSim(O.make_config(**kw, gl_order=8))
+    osim.load_particles(x[:, idx], u[:, idx], q[idx])
+    osim.set_particle_state(x[:, idx], P[:, idx], v[:, idx])
+    ref = osim.orbit_pass(gphi, An, Anp1, Uh, v[:, idx], iterate=True, want_J=False)
+    del osim
+    assert ref["nfail"] == 0
+    dv, dP = _rel(vout[:, idx], ref["vout"]), _rel(Pn1[:, idx], ref["Pnp1"])
+    di = iters[idx].astype(np.int64) - ref["iters"]
+    _say(f"{name} full inner loop ({idx.size} of {q.size} checked): v {dv:.2e} P {dP:.2e}, iteration counts "
+         f"equal for {np.mean(di == 0):.6f} (max |diff| {np.abs(di).max()}), GPU mean {rep['inner_mean']:.3f} "
+         f"max {rep['inner_max']}, oracle mean {ref['iters'].mean():.3f}")
+    assert dv < 1e-11 and dP < 1e-11
+    assert np.abs(di).max() <= 1 and np.mean(di != 0) <= 1e-4
+
+
+@pytest.mark.parametrize("name,steps", [("weibel2d", 3), ("tsi1d_big", 3)])
+def test_full_size_whole_steps_against_oracle(name, steps):
+    """Whole implicit steps of the full 1M-particle workloads (the GPU sorts its particles at
+    the first step, as the benchmark runs) against the oracle, element by element: particle
+    state and the fields to 1e-9 relative after every step, equal outer iteration counts."""
+    G = _gpu()
+    w, (x, u, q) = _workload(name)
+    base = W.config_dict(w)
+    sim = G.Simulation(G.config_from_dict(base, gl_order=0, sort_every=10), q.size)
+    sim.load_particles(x, u, q)
+    sim.initialize()
+    osim = O.OracleSim(O.config_from_dict(base, gl_order=8))
+    osim.load_particles(x, u, q)
+    osim.initialize()
+    L = w["length"]
+    for s in range(steps):
+        _, rep = sim.step()
+        _, orep = osim.step()
+        xg, Pg, vg = sim.read_particles()
+        xo, Po, vo = osim.read_particles()
+        dx = max(float(np.minimum(np.abs(xg[l] - xo[l]), L[l] - np.abs(xg[l] - xo[l])).max() / L[l])
+                 for l in range(w["dim"]))
+        dP, dv = _rel(Pg, Po), _rel(vg, vo)
+        df = max(_rel(sim.read_field(f), osim.read_field(f)) for f in ("A", "U", "phi", "J"))
+        _say(f"{name} full step {s + 1}: x {dx:.2e} P {dP:.2e} v {dv:.2e} fields {df:.2e}, outer "
+             f"{rep['outer_iters']} / oracle {orep['outer_iters']}")
+        assert dx < 1e-9 and dP < 1e-9 and dv < 1e-9 and df < 1e-9
+        assert rep["outer_iters"] == orep["outer_iters"]
+    dg, do = sim.diagnostics(), osim.diagnostics()
+    assert abs(dg["total"] - do["total"]) <= 1e-12 * abs(do["total"])
 
 
 @pytest.mark.parametrize("name,steps", [("weibel2d", 3), ("tsi1d_big", 3), ("mixed2d", 1), ("weibel3d", 1)])

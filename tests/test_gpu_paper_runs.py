@@ -168,12 +168,14 @@ def test_tsi_reduced_parity_with_oracle():
 
 
 def test_tsi_transverse_velocity_parity_on_reduction():
-    """Transverse motion in TSI grows from the loading: the cell-centre positions in y and z
-    are doubles whose offsets from their nearest nodes differ from row to row by up to
-    about 4e-15 (rounding of lo + (i + 1/2) h), and the beams are filamentation-unstable
-    across.  The GPU sums the deposit across workgroups exactly, and in a fixed order
-    within one, so it must add no asymmetry of its own: on the 32 x 4 x 4 reduction its
-    transverse RMS velocity follows the oracle's step by step."""
+    """Transverse motion in TSI grows from the loading: at full size the cell-centre
+    positions in y and z are doubles whose offsets from their nearest nodes differ from row
+    to row by up to about 4e-15 (rounding of lo + (i + 1/2) h), and the beams are
+    filamentation-unstable across.  The GPU sums the deposit across workgroups exactly, and
+    in a fixed order within one, so it must add no asymmetry of its own: on the 32 x 4 x 4
+    reduction, whose four rows sit at nearly the same offsets, both the GPU and the oracle
+    keep the transverse RMS velocity at roundoff (below 1e-17, against 1e-7 at full size by
+    T = 60) through t = 9, within a factor of ten of each other."""
     G = _gpu()
     w = W.spec("tsi", n=(32, 4, 4), dt=0.3, eig_gamma=GTS)
     base = W.config_dict(w)
@@ -181,15 +183,14 @@ def test_tsi_transverse_velocity_parity_on_reduction():
     sim = G.Simulation(G.config_from_dict(base, gl_order=0, deterministic=1), w["num_particles"])
     _load(osim, w)
     _load(sim, w)
-    worst = 0.0
     for s in range(30):
         osim.step()
         sim.step()
         a, b = sim.diagnostics()["vperp_rms"], osim.diagnostics()["vperp_rms"]
         if s % 10 == 9:
             _say(f"tsi reduction t = {0.3 * (s + 1):.1f}: v_perp,rms GPU {a:.4e} oracle {b:.4e}")
-        worst = max(worst, abs(a - b) / max(b, 1e-300))
-    assert worst < 1e-3, worst
+        assert a < 1e-17 and b < 1e-17, (s, a, b)
+        assert a <= 10.0 * max(b, 1e-21) and b <= 10.0 * max(a, 1e-21), (s, a, b)
 
 
 def _full_tsi(G, run, steps, **over):

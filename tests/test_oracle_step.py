@@ -189,3 +189,51 @@ def test_anderson_history_and_limits():
     assert st == O.ENOCONV
     after = sim.read_particles()
     assert all(np.array_equal(a, b) for a, b in zip(before, after))
+
+
+def test_anderson_small_solve_against_numpy():
+    """The oracle's Anderson solve (Cholesky of the regularized normal matrix) against
+    numpy's LU solve: Gram matrices of random residual-difference columns, regularized as
+    the implicit-solver section prescribes (lambda tr(G) / m_h on the diagonal), m_h = 1..8,
+    including nearly dependent columns; a zero history is refused."""
+    rng = np.random.default_rng(5)
+    worst = 0.0
+    for trial in range(200):
+        m = 1 + trial % 8
+        R = rng.normal(size=(300, m))
+        if trial % 3 == 0 and m > 1:
+            R[:, -1] = R[:, 0] + 1e-7 * rng.normal(size=300)  # nearly dependent history
+        r = rng.normal(size=300)
+        G = R.T @ R
+        lam = 1e-12
+        G = G + lam * np.trace(G) / m * np.eye(m)
+        b = R.T @ r
+        x = O.spd_solve(G, b)
+        ref = np.linalg.solve(G, b)
+        assert x is not None
+        # backward error of the solve, the quantity a stable method bounds
+        res = np.abs(G @ x - b).max() / (np.abs(G).max() * np.abs(x).max() + np.abs(b).max())
+        assert res < 1e-13, (trial, res)
+        if np.linalg.cond(G) < 1e8:
+            worst = max(worst, np.abs(x - ref).max() / np.abs(ref).max())
+    assert worst < 1e-9
+    assert O.spd_solve(np.zeros((3, 3)), np.ones(3)) is None
+    assert O.spd_solve(-np.eye(2), np.ones(2)) is None
+
+
+def test_position_wrap_is_the_periodic_image():
+    """After a step, every position lies in [lo, lo + L) and differs from x^n + dt v-bar by
+    a whole number of periods (the oracle's wrap against its definition)."""
+    w = W.spec("tsi1d")
+    base = W.config_dict(w)
+    x, u, q = W.particles(w)
+    sim = O.OracleSim(O.config_from_dict(base, gl_order=3))
+    sim.load_particles(x, u, q)
+    sim.initialize()
+    x0, _, _ = sim.read_particles()
+    sim.step()
+    x1, _, v1 = sim.read_particles()
+    lo, L = w["lo"][0], w["length"][0]
+    assert np.all(x1 >= lo) and np.all(x1 < lo + L)
+    k = (x0[0] + base["dt"] * v1[0] - x1[0]) / L
+    assert np.abs(k - np.round(k)).max() < 1e-12 and np.abs(k).max() > 0.5  # some particles wrapped
