@@ -1,9 +1,10 @@
 """Benchmark of the GM-HC-CN implicit step on one MI355X.
 
-Workload (default): 2D Weibel/filamentation, 128 x 128 periodic mesh, dx = 0.2,
-64 particles per cell (1,048,576 electrons), beams u_z = +-0.5 with spread 0.01,
-dt = 0.05, quadratic shapes, FP64, nonlinear tolerances 1e-12 (relative) / 1e-14
-(absolute).  Inputs are seeded synthetic arrays, resident in HBM before timing.
+Workload (default): 2D mixed two-stream/filamentation, 512 x 512 periodic mesh,
+dx = 0.2, 256 particles per cell (67,108,864 electrons), beams u_x = +-1.0 with spread
+0.02, dt = 0.05, quadratic shapes, FP64, nonlinear tolerances 1e-12 (relative) / 1e-14
+(absolute), beside the FP32-bulk mode.  Inputs are seeded synthetic arrays, resident in
+HBM before timing.
 
 One timed step is one full implicit Crank-Nicolson step (all outer iterations, each
 with the field solve, the orbit pass with its inner Picard loop and the deposit).
@@ -11,13 +12,18 @@ with the field solve, the orbit pass with its inner Picard loop and the deposit)
 iteration of the orbit pass) per second of wall time over the timed steps.
 
 The JSON line also carries the roofline of the dominant kernel (the orbit pass) from
-its HIP-event timed launches, and the CPU oracle's rate on a bounded sample.
+its HIP-event timed launches, the FP32-bulk mode (at its own tolerances, and FP64 at
+those same tolerances, so the gain from precision and the gain from the looser tests
+are stated apart), an on-device copy bandwidth, and the CPU oracle's rate on a bounded
+sample.
 """
 import argparse
 import json
 import os
 import sys
 import time
+
+import numpy as np
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
@@ -96,32 +102,78 @@ def measured_traffic(workload, dtype, shape=2):
     return float(meta["traffic_bytes_per_launch"])
 
 
-def cpu_baseline(w, cfg_dict, ngl, target_s=12.0, shape=2):
-    """The CPU oracle's rate on the same workload: whole implicit steps (all outer
-    iterations, orbit passes and field solves) of the full particle set at the same
-    Gauss-Legendre order, as many as fit in about target_s seconds (at least one)."""
+def _cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(w, cfg_dict, ngl, parts, shape=2, sample=65536, block=1 << 24):
+    """The CPU oracle's rate on the same workload: one orbit evaluation (a particle through
+    one Picard iteration of the orbit pass, with its deposit) of each particle of the first
+    `block` particles in load order (whole rows of cells), at frozen smooth fields of the
+    workload's mesh, at the GPU's Gauss-Legendre order on all host threads; beside it a
+    seeded sample of `sample` particles on one thread at the same order and at the paper's
+    GL8."""
     import oracle as O
     from paper_2609_36383_amd import workloads as W
 
-    x, u, q = W.particles(w)
-    sim = O.OracleSim(O.config_from_dict(cfg_dict, gl_order=ngl, shape_order=shape))
-    sim.load_particles(x, u, q)
-    pot = W.potentials(w)
-    if pot is not None:
-        sim.load_potentials(*pot)
-    sim.initialize()
-    evals, steps, el = 0, 0, 0.0
-    while steps == 0 or (el < target_s and steps < 50):
+    x, u, q = parts
+    d = w["dim"]
+    gphi, An, Anp1, _ = W.random_fields(d, w["n"], w["length"], seed=31, amp=0.3)
+    Uh = (Anp1 - An) / w["dt"]
+    P = np.abs(q)[None, :] * u
+    v = u / np.sqrt(1.0 + (u * u).sum(axis=0))[None, :]
+
+    def rate(idx, order, threads):
+        sim = O.OracleSim(O.config_from_dict(cfg_dict, gl_order=order, shape_order=shape, threads=threads))
+        xs, us, qs = (x, u, q) if idx is None else (x[:, idx], u[:, idx], q[idx])
+        Ps, vs = (P, v) if idx is None else (P[:, idx], v[:, idx])
+        sim.load_particles(xs, us, qs)
+        sim.set_particle_state(xs, Ps, vs)
         t0 = time.perf_counter()
-        _, rep = sim.step()
-        el += time.perf_counter() - t0
-        evals += rep["evaluations"]
-        steps += 1
+        sim.orbit_pass(gphi, An, Anp1, Uh, vs, iterate=False)
+        el = time.perf_counter() - t0
+        return qs.size / el, el
+
     threads = int(O.lib().orc_max_threads())
-    return {"value": evals / el, "unit": "particle-iterations/s", "cores": threads, "kind": "oracle",
-            "particle_steps_per_s": q.size * steps / el,
-            "sample": f"{steps} whole implicit steps of the full {q.size}-particle workload (GL{ngl} per "
-                      f"knot segment, {evals} orbit evaluations) in {el:.1f} s on {threads} OpenMP threads"}
+    nb = min(block, q.size)
+    full, el = rate(None if nb == q.size else np.arange(nb), ngl, 0)
+    idx = np.sort(np.random.default_rng(53).choice(q.size, min(sample, q.size), replace=False))
+    one, el1 = rate(idx, ngl, 1)
+    one8, el8 = rate(idx, 8, 1)
+    return {"value": full, "unit": "particle-iterations/s", "cores": threads, "kind": "oracle",
+            "single_thread": one, f"single_thread_gl8": one8,
+            "host": f"{_cpu_model()}, nproc {os.cpu_count()}",
+            "sample": f"one frozen-field orbit evaluation with deposit of {nb} of the {q.size} particles (the first "
+                      f"in load order, GL{ngl} per knot segment, the GPU's order) in {el:.1f} s on {threads} OpenMP "
+                      f"threads; a seeded sample of "
+                      f"{idx.size} particles on 1 thread: {one:.4g}/s at GL{ngl} ({el1:.1f} s), {one8:.4g}/s at "
+                      f"GL8 ({el8:.1f} s)"}
+
+
+def copy_bandwidth():
+    """Device-to-device copy bandwidth on this GPU (read + write bytes per second of a
+    2 GiB FP64 copy, best of five), the practical ceiling beside the 8 TB/s datasheet."""
+    import torch
+    n = 1 << 28
+    a = torch.ones(n, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    best = 0.0
+    for _ in range(6):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        b.copy_(a)
+        e1.record()
+        e1.synchronize()
+        best = max(best, 2.0 * n * 8 / (e0.elapsed_time(e1) * 1e-3) / 1e9)
+    del a, b
+    torch.cuda.empty_cache()
+    return best
 
 
 def copy_probe():
@@ -140,15 +192,15 @@ def copy_probe():
 PEAK_FP32_VALU_TFLOPS = 157.3
 
 
-def run_case(args, w, fp32):
-    """Time args.steps whole implicit steps of workload w in one precision mode."""
-    import numpy as np
+def run_case(args, w, fp32, parts, tol_of_fp32=None):
+    """Time args.steps whole implicit steps of workload w in one precision mode (with
+    tol_of_fp32, at the tolerances of that mode instead of its own)."""
     import torch
 
     from paper_2609_36383_amd import gmhc as G
     from paper_2609_36383_amd import workloads as W
 
-    base = W.config_dict(w, fp32_bulk=fp32)
+    base = W.config_dict(w, fp32_bulk=fp32 if tol_of_fp32 is None else tol_of_fp32)
     sh = args.shape
     ngl = args.gl_order if args.gl_order else (w["dim"] + 1 if sh == 2 else (w["dim"] + 2) // 2)
     # the orbit launches of every TIMING_EVERY-th step record HIP events (the events
@@ -156,7 +208,7 @@ def run_case(args, w, fp32):
     cfg = G.config_from_dict(base, gl_order=ngl, sort_every=args.sort_every,
                              timing=TIMING_EVERY if args.steps >= TIMING_EVERY else 1,
                              precision=G.FP32_BULK if fp32 else G.FP64, shape_order=sh)
-    x, u, q = W.particles(w)
+    x, u, q = parts
     npart = q.size
     sim = G.Simulation(cfg, npart, device="cuda:0")
     sim.load_particles(x, u, q)
@@ -201,6 +253,7 @@ def run_case(args, w, fp32):
     gbs = bytes_launch / launch_s / 1e9
     return dict(
         value=evals / elapsed, ms_per_step=elapsed * 1e3 / args.steps, ngl=ngl, npart=npart,
+        ns_per_evaluation=launch_s * 1e9 / max(timed_evals / max(timed_launches, 1), 1),
         particle_steps_per_s=npart * args.steps / elapsed, outer_iters_mean=outer / args.steps,
         evaluations_per_particle_step=evals / (npart * args.steps), energy_drift=drift,
         segments_per_evaluation=seg_mean,
@@ -220,7 +273,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="weibel2d")
+    ap.add_argument("--workload", default="mixed2d")
     ap.add_argument("--sort-every", type=int, default=10)
     ap.add_argument("--gl-order", type=int, default=0)
     ap.add_argument("--shape", type=int, choices=(1, 2), default=2,
@@ -242,9 +295,12 @@ def main():
     from paper_2609_36383_amd import workloads as W
 
     w = W.spec(args.workload)
+    parts = W.particles(w)
     main_fp32 = args.precision == "fp32"
-    r = run_case(args, w, main_fp32)
-    other = run_case(args, w, True) if args.precision == "both" else None
+    r = run_case(args, w, main_fp32, parts)
+    other = run_case(args, w, True, parts) if args.precision == "both" else None
+    matched = run_case(args, w, False, parts, tol_of_fp32=True) if args.precision == "both" else None
+    copy_gbs = copy_bandwidth()
     out = {
         "metric": METRIC,
         "value": r["value"],
@@ -266,17 +322,26 @@ def main():
     for k in ("particle_steps_per_s", "outer_iters_mean", "evaluations_per_particle_step", "energy_drift",
               "segments_per_evaluation", "tolerances"):
         out[k] = r[k]
+    out["ns_per_evaluation"] = r["ns_per_evaluation"]
     out["roofline"] = r["roofline"]
+    out["roofline"]["hbm_copy_gbs"] = copy_gbs
+    out["roofline"]["hbm_frac_of_copy"] = r["roofline"]["hbm_achieved_gbs"] / copy_gbs
     if other is not None:
-        out["fp32_bulk"] = {k: other[k] for k in ("value", "ms_per_step", "particle_steps_per_s", "outer_iters_mean",
-                                                  "evaluations_per_particle_step", "energy_drift", "tolerances",
-                                                  "roofline")}
-        out["fp32_bulk"]["unit"] = "particle-iterations/s"
-        out["fp32_bulk"]["speedup_particle_steps_vs_fp64"] = other["particle_steps_per_s"] / r["particle_steps_per_s"]
-        out["fp32_bulk"]["speedup_per_iteration_vs_fp64"] = other["value"] / r["value"]
+        keys = ("value", "ms_per_step", "particle_steps_per_s", "outer_iters_mean", "evaluations_per_particle_step",
+                "energy_drift", "ns_per_evaluation", "tolerances", "roofline")
+        f = out["fp32_bulk"] = {k: other[k] for k in keys}
+        f["unit"] = "particle-iterations/s"
+        # the gain of FP32-bulk, split: the same tolerances in both precisions (the gain
+        # from precision alone), per orbit evaluation in the kernel, and with each mode's
+        # own tolerances (which adds the gain of fewer outer and inner iterations)
+        f["fp64_at_fp32_tolerances"] = {k: matched[k] for k in keys if k != "roofline"}
+        f["speedup_per_evaluation_vs_fp64"] = r["ns_per_evaluation"] / other["ns_per_evaluation"]
+        f["speedup_particle_steps_same_tolerances"] = other["particle_steps_per_s"] / matched["particle_steps_per_s"]
+        f["speedup_particle_steps_own_tolerances"] = other["particle_steps_per_s"] / r["particle_steps_per_s"]
+        f["speedup_per_iteration_vs_fp64"] = other["value"] / r["value"]
     if not args.no_cpu_baseline:
         base = W.config_dict(w, fp32_bulk=main_fp32)
-        out["cpu_baseline"] = cpu_baseline(w, base, r["ngl"], shape=args.shape)
+        out["cpu_baseline"] = cpu_baseline(w, base, r["ngl"], parts, shape=args.shape)
     print(json.dumps(out), flush=True)
 
 

@@ -72,6 +72,7 @@ struct gmhc_ctx {
   void* scan_tmp = nullptr;
   size_t scan_tmp_bytes = 0;
   double* partials = nullptr;
+  double* pchunk = nullptr;  // first-level sums of long reductions [kOrbitParts][kReduceChunks]
   int64_t max_blocks = 0;
   // outer Anderson solver (outer_scheme 1): iterate, residual, direction [3 Ng] and
   // the history columns (differences of iterates and of residuals)
@@ -244,6 +245,7 @@ size_t carve(gmhc_ctx* c, char* base, int64_t np) {
   // line (the residual folded into the last FFT pass) or 1024
   const int64_t res_cap = std::max<int64_t>(1024, c->M.Ng / c->M.n[0]);
   c->partials = cv.take<double>((size_t)(c->max_blocks + res_cap) * 8);
+  c->pchunk = cv.take<double>((size_t)kOrbitParts * kReduceChunks);
   c->dres = cv.take<double>(64);
   c->ddot = cv.take<double>(kMaxDots);
   // control block [4] int32 then the report accumulators [16] double, contiguous
@@ -322,8 +324,10 @@ int32_t run_orbit(gmhc_ctx* ctx, int iterate, double* ms) {
   HIPCK(launch_orbit(a, ctx->ngl, ctx->stream, timed ? ctx->ev0 : nullptr, timed ? ctx->ev1 : nullptr));
   const int nb = (int)((ctx->np + kOrbitBlock - 1) / kOrbitBlock);
   if (nb > 0) {
-    HIPCK(launch_reduce(ctx->partials, nb, 1, ctx->max_blocks, kOrbitParts, 1u << OP_ITMAX, ctx->dres,
-                        ctx->stream));
+    const ReduceSet r = reduce_chunks(
+        ReduceSet{ctx->partials, nb, 1, ctx->max_blocks, kOrbitParts, 1u << OP_ITMAX, ctx->dres}, ctx->pchunk,
+        ctx->stream);
+    HIPCK(launch_reduce(r.p, r.nblocks, r.bstride, r.vstride, r.nvals, r.max_mask, r.out, ctx->stream));
   } else {
     HIPCK(hipMemsetAsync(ctx->dres, 0, sizeof(double) * kOrbitParts, ctx->stream));
   }
@@ -876,7 +880,9 @@ int32_t enqueue_outer(gmhc_ctx* ctx, int cur, int hs, int part, const int32_t* s
     ra.stop = stop;
     const bool proj = ctx->cfg.project_nyquist != 0;
     // pass and residual sums, then (device control) the outer test
-    const ReduceSet ro{ctx->partials, orbit_blocks(ctx), 1, ctx->max_blocks, kOrbitParts, 1u << OP_ITMAX, ctx->dres};
+    const ReduceSet ro = reduce_chunks(
+        ReduceSet{ctx->partials, orbit_blocks(ctx), 1, ctx->max_blocks, kOrbitParts, 1u << OP_ITMAX, ctx->dres},
+        ctx->pchunk, s, stop);
     ReduceSet rr{ra.partials, 0, kResParts, 1, kResParts, 1u << 3, ctx->dres + kResOff};
     OuterTest ot{};
     if (stop)

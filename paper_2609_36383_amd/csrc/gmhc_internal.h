@@ -171,6 +171,14 @@ struct ReduceSet {
   double* out;
 };
 
+// Long reductions (more than kReduceChunkMin blocks of unit stride, such as the orbit
+// pass's per-workgroup partials at 67M particles) first reduce up to kReduceChunks
+// chunks of consecutive blocks in a fixed order into scratch [nvals][kReduceChunks];
+// returns the set that reads those.  Shorter sets are returned unchanged.
+constexpr int kReduceChunkMin = 16384;
+constexpr int kReduceChunks = 1024;
+ReduceSet reduce_chunks(const ReduceSet& r, double* scratch, hipStream_t s, const int32_t* stop = nullptr);
+
 // Device-side outer test of Picard iteration k (ctl == nullptr: none): reads the pass
 // results res[0..7] and residual sums res[koff..], accumulates the step report in acc and,
 // when the mixed tests pass or an inner solve failed, sets ctl[0] (stop) and records the

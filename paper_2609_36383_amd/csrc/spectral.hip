@@ -432,6 +432,20 @@ __global__ __launch_bounds__(kBlock) void k_reduce(const double* partials, int n
   if (threadIdx.x == 0) out[v] = x;
 }
 
+// First level of a long reduction: workgroup (c, v) reduces blocks [c chunk, c chunk +
+// chunk) of value v in a fixed order into out[v nchunks + c], so the second level reads
+// nchunks values per value instead of nblocks.
+__global__ __launch_bounds__(kBlock) void k_reduce_chunks(const double* p, int nblocks, int64_t vstride,
+                                                          uint32_t max_mask, int chunk, double* out,
+                                                          const int32_t* stop) {
+  if (stop && *stop) return;
+  const int c = blockIdx.x, v = blockIdx.y;
+  const int b0 = c * chunk;
+  const int nb = min(chunk, nblocks - b0);
+  const double x = reduce_value<kBlock>(p + (int64_t)v * vstride + b0, nb, 1, (max_mask >> v) & 1u);
+  if (threadIdx.x == 0) out[(int64_t)v * gridDim.x + c] = x;
+}
+
 __global__ __launch_bounds__(kBlock) void k_zero(double* y, int64_t n, const int32_t* stop) {
   if (stop && *stop) return;
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -1137,6 +1151,20 @@ hipError_t launch_reduce(const double* partials, int nblocks, int64_t bstride, i
   hipLaunchKernelGGL(k_reduce, dim3((unsigned)nvals), dim3(kBlock), 0, s, partials, nblocks, bstride, vstride, nvals,
                      max_mask, out, stop);
   return hipGetLastError();
+}
+
+ReduceSet reduce_chunks(const ReduceSet& r, double* scratch, hipStream_t s, const int32_t* stop) {
+  if (r.nblocks <= kReduceChunkMin || r.bstride != 1) return r;
+  const int chunk = (r.nblocks + kReduceChunks - 1) / kReduceChunks;
+  const int nch = (r.nblocks + chunk - 1) / chunk;
+  hipLaunchKernelGGL(k_reduce_chunks, dim3((unsigned)nch, (unsigned)r.nvals), dim3(kBlock), 0, s, r.p, r.nblocks,
+                     r.vstride, r.max_mask, chunk, scratch, stop);
+  ReduceSet o = r;
+  o.p = scratch;
+  o.nblocks = nch;
+  o.bstride = 1;
+  o.vstride = nch;
+  return o;
 }
 
 hipError_t launch_zero(double* y, int64_t n, hipStream_t s, const int32_t* stop) {
