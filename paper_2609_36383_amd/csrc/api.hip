@@ -304,7 +304,9 @@ OrbitArgs orbit_args(gmhc_ctx* c, int iterate, int par = 0) {
   a.Pn = c->P2[0];
   a.vin = c->vin_first ? c->vb[0] : c->vw[0];
   a.v = c->vw[0];
-  a.trial = c->trial[par];
+  a.gphi = c->trial[par];
+  a.Anp1 = c->trial[par] + (int64_t)c->M.d * c->M.Ng;
+  a.Uh = c->trial[par] + (int64_t)(c->M.d + 3) * c->M.Ng;
   a.An = c->An;
   a.J = c->Jdep;
   a.q = c->q;
@@ -512,6 +514,62 @@ int ncomp_of(int32_t which) {
 
 }  // namespace
 
+namespace gmhc {
+
+// Host-side validation of a configuration (the rules gmhc_create documents).
+bool config_ok(const gmhc_config& c) {
+  if (c.dim < 1 || c.dim > 3) return false;
+  int64_t ng = 1;
+  for (int l = 0; l < c.dim; ++l) {
+    const int n = c.n[l];
+    if (n < 4 || n > 4096 || (n & (n - 1)) != 0) return false;
+    ng *= n;
+    if (ng > (int64_t)1 << 30) return false;  // node indices stay within int32
+    if (!(c.len[l] > 0.0) || !isfinite(c.lo[l])) return false;
+  }
+  if (!(c.dt > 0.0) || !(c.kappa > 0.0) || !(c.sigma1 > 0.0) || !(c.sigma2 > 0.0)) return false;
+  if (fabs(c.sigma1 - c.kappa * c.kappa * c.sigma2) > 1e-14 * fabs(c.sigma1)) return false;
+  if (c.gl_order < 0 || c.gl_order > kMaxGL) return false;
+  if (c.shape_order < 0 || c.shape_order > 2) return false;
+  if (c.precision != GMHC_FP64 && c.precision != GMHC_FP32_BULK) return false;
+  if (c.max_outer < 1 || c.max_inner < 1 || !(c.beta > 0.0 && c.beta <= 1.0)) return false;
+  if (c.timing < 0) return false;
+  if (c.deterministic != 0 && c.deterministic != 1) return false;
+  if (c.outer_scheme != 0 && c.outer_scheme != 1) return false;
+  if (c.outer_scheme == 1 &&
+      (c.anderson_m < 1 || c.anderson_m > 8 || c.anderson_start < 1 || c.ls_halvings < 0 || c.ls_halvings > 30 ||
+       !(c.anderson_lambda >= 0.0) || !(c.ls_decrease >= 0.0 && c.ls_decrease < 1.0) || !(c.ls_growth >= 1.0)))
+    return false;
+  if (c.tol_outer_abs < 0 || c.tol_outer_rel < 0 || c.tol_inner_abs < 0 || c.tol_inner_rel < 0) return false;
+  return true;
+}
+
+// Mesh geometry and the Gauss-Legendre rule of a valid configuration.
+void set_geometry(const gmhc_config& c, Mesh& M, int& ngl, double* glx, double* glw) {
+  M = Mesh{};
+  M.d = c.dim;
+  M.shape = c.shape_order == 1 ? 1 : 2;
+  M.Ng = 1;
+  M.dV = 1.0;
+  for (int l = 0; l < 3; ++l) {
+    const bool r = l < c.dim;
+    M.n[l] = r ? c.n[l] : 1;
+    M.lo[l] = r ? c.lo[l] : 0.0;
+    M.len[l] = r ? c.len[l] : 1.0;
+    M.ln[l] = ilog2(M.n[l]);
+    M.h[l] = M.len[l] / M.n[l];
+    M.inv_h[l] = 1.0 / M.h[l];
+    M.kf[l] = r ? 2.0 * M_PI / M.len[l] : 0.0;
+    M.Ng *= M.n[l];
+    if (r) M.dV *= M.h[l];
+  }
+  ngl = c.gl_order ? c.gl_order : (M.shape == 1 ? (c.dim + 2) / 2 : c.dim + 1);
+  for (int k = 0; k < kMaxGL; ++k) glx[k] = glw[k] = 0.0;
+  gl01(ngl, glx, glw);
+}
+
+}  // namespace gmhc
+
 extern "C" {
 
 int32_t gmhc_abi_version(void) { return GMHC_ABI_VERSION; }
@@ -534,55 +592,12 @@ const char* gmhc_last_error(const gmhc_ctx* ctx) { return ctx ? ctx->err.c_str()
 int32_t gmhc_create(const gmhc_config* cfg, gmhc_ctx** out) {
   if (!cfg || !out) return GMHC_EINVAL;
   *out = nullptr;
-  const gmhc_config& c = *cfg;
-  if (c.dim < 1 || c.dim > 3) return GMHC_EINVAL;
-  int64_t ng = 1;
-  for (int l = 0; l < c.dim; ++l) {
-    const int n = c.n[l];
-    if (n < 4 || n > 4096 || (n & (n - 1)) != 0) return GMHC_EINVAL;
-    ng *= n;
-    if (ng > (int64_t)1 << 30) return GMHC_EINVAL;  // node indices stay within int32
-    if (!(c.len[l] > 0.0) || !isfinite(c.lo[l])) return GMHC_EINVAL;
-  }
-  if (!(c.dt > 0.0) || !(c.kappa > 0.0) || !(c.sigma1 > 0.0) || !(c.sigma2 > 0.0)) return GMHC_EINVAL;
-  if (fabs(c.sigma1 - c.kappa * c.kappa * c.sigma2) > 1e-14 * fabs(c.sigma1)) return GMHC_EINVAL;
-  if (c.gl_order < 0 || c.gl_order > kMaxGL) return GMHC_EINVAL;
-  if (c.shape_order < 0 || c.shape_order > 2) return GMHC_EINVAL;
-  if (c.precision != GMHC_FP64 && c.precision != GMHC_FP32_BULK) return GMHC_EINVAL;
-  if (c.max_outer < 1 || c.max_inner < 1 || !(c.beta > 0.0 && c.beta <= 1.0)) return GMHC_EINVAL;
-  if (c.timing < 0) return GMHC_EINVAL;
-  if (c.deterministic != 0 && c.deterministic != 1) return GMHC_EINVAL;
-  if (c.outer_scheme != 0 && c.outer_scheme != 1) return GMHC_EINVAL;
-  if (c.outer_scheme == 1 &&
-      (c.anderson_m < 1 || c.anderson_m > 8 || c.anderson_start < 1 || c.ls_halvings < 0 || c.ls_halvings > 30 ||
-       !(c.anderson_lambda >= 0.0) || !(c.ls_decrease >= 0.0 && c.ls_decrease < 1.0) || !(c.ls_growth >= 1.0)))
-    return GMHC_EINVAL;
-  if (c.tol_outer_abs < 0 || c.tol_outer_rel < 0 || c.tol_inner_abs < 0 || c.tol_inner_rel < 0)
-    return GMHC_EINVAL;
+  if (!config_ok(*cfg)) return GMHC_EINVAL;
   gmhc_ctx* ctx = new gmhc_ctx();
-  ctx->cfg = c;
-  ctx->prec = c.precision;
-  ctx->es = c.precision == GMHC_FP32_BULK ? sizeof(float) : sizeof(double);
-  Mesh& M = ctx->M;
-  M.d = c.dim;
-  M.shape = c.shape_order == 1 ? 1 : 2;
-  M.Ng = 1;
-  M.dV = 1.0;
-  for (int l = 0; l < 3; ++l) {
-    const bool r = l < c.dim;
-    M.n[l] = r ? c.n[l] : 1;
-    M.lo[l] = r ? c.lo[l] : 0.0;
-    M.len[l] = r ? c.len[l] : 1.0;
-    M.ln[l] = ilog2(M.n[l]);
-    M.h[l] = M.len[l] / M.n[l];
-    M.inv_h[l] = 1.0 / M.h[l];
-    M.kf[l] = r ? 2.0 * M_PI / M.len[l] : 0.0;
-    M.Ng *= M.n[l];
-    if (r) M.dV *= M.h[l];
-  }
-  ctx->ngl = c.gl_order ? c.gl_order : (M.shape == 1 ? (c.dim + 2) / 2 : c.dim + 1);
-  for (int k = 0; k < kMaxGL; ++k) ctx->glx[k] = ctx->glw[k] = 0.0;
-  gl01(ctx->ngl, ctx->glx, ctx->glw);
+  ctx->cfg = *cfg;
+  ctx->prec = cfg->precision;
+  ctx->es = cfg->precision == GMHC_FP32_BULK ? sizeof(float) : sizeof(double);
+  set_geometry(*cfg, ctx->M, ctx->ngl, ctx->glx, ctx->glw);
   *out = ctx;
   return GMHC_OK;
 }

@@ -80,10 +80,12 @@ struct OrbitArgs {
   void* v;               // [3] out: v_out of the final evaluation
   double* xn;            // [d] out: wrapped x^n + dt v_in
   void* Pn;              // [3] out: P^{n+1}
-  int32_t* iters;        // out: inner evaluations
+  int32_t* iters;        // out: inner evaluations (may be null)
   // mesh arrays, component stride Ng
-  const double* trial;   // [d+6]: grad_h phi^{n+1/2} (d), A^{n+1} (3), U^{n+1/2} (3)
+  const double* gphi;    // [d] grad_h phi^{n+1/2}
   const double* An;      // [3] A^n
+  const double* Anp1;    // [3] A^{n+1}
+  const double* Uh;      // [3] U^{n+1/2}
   unsigned long long* J;  // [3] orbit current accumulator, one fixed-point pair per value
   double* partials;      // [kOrbitParts][pstride]: value v of block b at v * pstride + b
   int64_t pstride;       // >= gridDim.x
@@ -334,6 +336,17 @@ hipError_t launch_unpermute_i32(const int32_t* src, int32_t* dst, const int32_t*
 // the given type.
 hipError_t launch_permute_in(const double* const* src, void* const* dst, int dst_prec, int ncomp,
                              const int32_t* id, int64_t np, hipStream_t s);
+
+// ---- host-side configuration helpers (api.hip) ---------------------------------
+
+}  // namespace gmhc
+struct gmhc_config;
+namespace gmhc {
+// The validation rules gmhc_create documents.
+bool config_ok(const gmhc_config& c);
+// Mesh geometry and the Gauss-Legendre rule (nodes and weights on [0, 1], kMaxGL slots)
+// of a valid configuration.
+void set_geometry(const gmhc_config& c, Mesh& M, int& ngl, double* glx, double* glw);
 
 // Sort of particles by nearest-node cell: the stable radix sort (stable = 1) or the
 // counting sort with atomic cursors (stable = 0); see sort.hip.

@@ -108,9 +108,10 @@ __device__ __forceinline__ constexpr int nfields() { return D + 9; }
 template <int D>
 __device__ __forceinline__ const double* gfield(const OrbitArgs& a, int f) {
   const int64_t Ng = a.M.Ng;
-  if (f < D) return a.trial + (int64_t)f * Ng;
+  if (f < D) return a.gphi + (int64_t)f * Ng;
   if (f < D + 3) return a.An + (int64_t)(f - D) * Ng;
-  return a.trial + (int64_t)(f - 3) * Ng;
+  if (f < D + 6) return a.Anp1 + (int64_t)(f - D - 3) * Ng;
+  return a.Uh + (int64_t)(f - D - 6) * Ng;
 }
 
 template <int D, class R, bool LDS>
@@ -1170,7 +1171,7 @@ __attribute__((amdgpu_waves_per_eu(orbit_waves<D, R>()))) void k_orbit(OrbitArgs
       for (int c = 0; c < 3; ++c) vin[c] = o.vout[c];
     }
     if (it > maxit) it = maxit;
-    a.iters[i] = it;
+    if (a.iters) a.iters[i] = it;
     part[OP_FAIL] = conv ? 0.0 : 1.0;
     part[OP_ITERS] = (double)it;
     part[OP_ITMAX] = (double)it;
