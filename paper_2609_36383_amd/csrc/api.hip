@@ -587,7 +587,7 @@ const char* gmhc_status_str(int32_t s) {
   }
 }
 
-const char* gmhc_last_error(const gmhc_ctx* ctx) { return ctx ? ctx->err.c_str() : ""; }
+const char* gmhc_last_error(const gmhc_ctx* ctx) { return ctx ? ctx->err.c_str() : static_last_error(); }
 
 int32_t gmhc_create(const gmhc_config* cfg, gmhc_ctx** out) {
   if (!cfg || !out) return GMHC_EINVAL;

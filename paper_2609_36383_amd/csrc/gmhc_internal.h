@@ -347,6 +347,8 @@ bool config_ok(const gmhc_config& c);
 // Mesh geometry and the Gauss-Legendre rule (nodes and weights on [0, 1], kMaxGL slots)
 // of a valid configuration.
 void set_geometry(const gmhc_config& c, Mesh& M, int& ngl, double* glx, double* glw);
+// The calling thread's last gmhc_orbit_pass_static error (static_pass.hip).
+const char* static_last_error();
 
 // Sort of particles by nearest-node cell: the stable radix sort (stable = 1) or the
 // counting sort with atomic cursors (stable = 0); see sort.hip.

@@ -28,7 +28,10 @@ SYMBOLS = (
     "gmhc_initialize", "gmhc_step", "gmhc_diagnostics", "gmhc_read_particles",
     "gmhc_set_particle_state", "gmhc_read_field", "gmhc_mode_amplitude", "gmhc_set_frozen_fields",
     "gmhc_orbit_pass_frozen", "gmhc_read_pass", "gmhc_state_bytes", "gmhc_save", "gmhc_load",
+    "gmhc_orbit_pass_static",
 )
+STATIC_MAX_PARTICLES = 1 << 22  # GMHC_STATIC_MAX_PARTICLES
+STATIC_MAX_NODES = 1 << 18      # GMHC_STATIC_MAX_NODES
 
 
 class Config(C.Structure):
@@ -110,6 +113,8 @@ def load_library(path=LIB_PATH):
         "gmhc_state_bytes": ([vp, C.POINTER(C.c_size_t)], i32),
         "gmhc_save": ([vp, vp, C.c_size_t, i32], i32),
         "gmhc_load": ([vp, vp, C.c_size_t, i32], i32),
+        "gmhc_orbit_pass_static": ([C.POINTER(Config), i64] + [vp] * 8 + [i32] + [vp] * 5 +
+                                   [C.POINTER(PassReport)], i32),
     }
     for name, (args, res) in sig.items():
         f = getattr(L, name)
@@ -324,3 +329,21 @@ class Simulation:
                                           it.ctypes.data_as(C.c_void_p) if iters else None,
                                           HOST), "gmhc_read_pass")
         return (vout, Pn1, J, it) if iters else (vout, Pn1, J)
+
+
+def orbit_pass_static(cfg, x, P, q, vin, gradphi, An, Anp1, Uh, vout, Pnp1, xnp1, J, iterate=False,
+                      stream=None, report=True):
+    """gmhc_orbit_pass_static on torch device tensors (FP64, contiguous; shapes as the
+    header states).  Allocates nothing on the device; returns the pass report (a dict)
+    or None."""
+    lib = load_library()
+    n = int(q.numel())
+    ptr = [C.c_void_p(t.data_ptr()) for t in (x, P, q, vin, gradphi, An, Anp1, Uh)]
+    out = [C.c_void_p(t.data_ptr()) for t in (vout, Pnp1, xnp1, J)]
+    r = PassReport()
+    st = lib.gmhc_orbit_pass_static(C.byref(cfg), n, *ptr, int(iterate), *out,
+                                    C.c_void_p(stream.cuda_stream) if stream is not None else None,
+                                    C.byref(r) if report else None)
+    if st != OK:
+        raise GmhcError(st, "gmhc_orbit_pass_static", lib.gmhc_last_error(None).decode())
+    return _todict(r) if report else None
