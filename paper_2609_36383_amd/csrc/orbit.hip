@@ -432,11 +432,13 @@ struct EvalOut {
   int nseg;
 };
 
-// Constants of one particle.
+// Constants of one particle: its charge (m = |q|) and the gamma of p^n = P^n - q A^-
+// (fixed over the inner iterations).  The other per-particle factors are recomputed from q
+// after the segment quadrature, where fewer registers are live.
 template <class R>
 struct PConst {
-  R q, m, inv_mk, mk, tc, half_qdt;
-  R gpn;  // gamma of p^n = P^n - q A^- (fixed over the inner iterations)
+  R q;
+  R gpn;
 };
 
 // One orbit evaluation of one particle.
@@ -479,6 +481,10 @@ __device__ void evaluate(const OrbitArgs& a, const Tile& t, const R* gx, const R
   interp3<D, SH, R>(a, t, D + 3, j0, fe, Ap);
 
   const R q = pc.q;
+  const R m = fabs(q);
+  const R inv_mk = rcp_(m * R(a.kappa));
+  const R tc = q * R(a.dt) * rcp_(R(2) * m);
+  const R half_qdt = R(0.5) * q * R(a.dt);
   R Aep[3], kick[3], pm[3];
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
@@ -486,7 +492,7 @@ __device__ void evaluate(const OrbitArgs& a, const Tile& t, const R* gx, const R
     R Dv = R(0);
 #pragma unroll
     for (int j = 0; j < D; ++j) Dv += Dm[c][j] * vin[j];
-    kick[c] = pc.half_qdt * (Dv - gp[c]);
+    kick[c] = half_qdt * (Dv - gp[c]);
     pm[c] = P[c] - q * Aep[c] + kick[c];
   }
   // B_eff of the skew part K = D^T - D (D zero-padded to 3x3): (K23, -K13, K12)
@@ -494,10 +500,10 @@ __device__ void evaluate(const OrbitArgs& a, const Tile& t, const R* gx, const R
   // normalized HC map.  The rotation is linear in u = p / (m kappa), so it is applied
   // to p directly; u enters only through |u|^2 and u . tau in gamma_HC.  (Scaling p
   // down and back up would bias every momentum by the same rounding in FP32.)
-  const R tau[3] = {pc.tc * Beff[0], pc.tc * Beff[1], pc.tc * Beff[2]};
-  const R um2 = (pm[0] * pm[0] + pm[1] * pm[1] + pm[2] * pm[2]) * pc.inv_mk * pc.inv_mk;
+  const R tau[3] = {tc * Beff[0], tc * Beff[1], tc * Beff[2]};
+  const R um2 = (pm[0] * pm[0] + pm[1] * pm[1] + pm[2] * pm[2]) * inv_mk * inv_mk;
   const R tau2 = tau[0] * tau[0] + tau[1] * tau[1] + tau[2] * tau[2];
-  const R ut = (pm[0] * tau[0] + pm[1] * tau[1] + pm[2] * tau[2]) * pc.inv_mk;
+  const R ut = (pm[0] * tau[0] + pm[1] * tau[1] + pm[2] * tau[2]) * inv_mk;
   const R sig = R(1) + um2 - tau2;
   const R X = tau2 + ut * ut;
   R tv[3];
@@ -528,11 +534,11 @@ __device__ void evaluate(const OrbitArgs& a, const Tile& t, const R* gx, const R
   }
   // secant velocities V^dg and the orbit velocity
   auto gam = [&](const R p[3]) {
-    const R ux = p[0] * pc.inv_mk, uy = p[1] * pc.inv_mk, uz = p[2] * pc.inv_mk;
+    const R ux = p[0] * inv_mk, uy = p[1] * inv_mk, uz = p[2] * inv_mk;
     return sqrt_(R(1) + ux * ux + uy * uy + uz * uz);
   };
-  const R d1 = rcp_(pc.m * (gam(pm) + pc.gpn));
-  const R d2 = rcp_(pc.m * (gam(pn1) + gam(pp)));
+  const R d1 = rcp_(m * (gam(pm) + pc.gpn));
+  const R d2 = rcp_(m * (gam(pn1) + gam(pp)));
   o.nseg = nseg;
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
@@ -1084,16 +1090,14 @@ __attribute__((amdgpu_waves_per_eu(orbit_waves<D, R>()))) void k_orbit(OrbitArgs
   bool conv = false;
   R vin[3] = {R(0), R(0), R(0)};
   R q = R(0);
-  double vout[3] = {0.0, 0.0, 0.0}, Dv[3] = {0.0, 0.0, 0.0}, dA[3] = {0.0, 0.0, 0.0}, gpb[3] = {0.0, 0.0, 0.0};
-  double kin = 0.0;
+  // of the accepted evaluation: v_out, the chain-rule part w = (A^+ - A^-) - dt D v_in
+  // (the residual R_A once dt U-bar is subtracted), the work part -v_out . grad-phi-bar and
+  // the kinetic energy of p^{n+1}
+  double vout[3] = {0.0, 0.0, 0.0}, wra[3] = {0.0, 0.0, 0.0};
+  double wgp = 0.0, kin = 0.0;
   if (live) {
     PConst<R> pc;
     pc.q = qv;
-    pc.m = fabs(pc.q);
-    pc.mk = pc.m * R(a.kappa);
-    pc.inv_mk = rcp_(pc.mk);
-    pc.tc = pc.q * R(a.dt) * rcp_(R(2) * pc.m);
-    pc.half_qdt = R(0.5) * pc.q * R(a.dt);
     q = pc.q;
     vin[0] = vin0[0];
     vin[1] = vin0[1];
@@ -1104,7 +1108,7 @@ __attribute__((amdgpu_waves_per_eu(orbit_waves<D, R>()))) void k_orbit(OrbitArgs
       R u2 = R(0);
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
-        const R u = (P0[c] - pc.q * Am[c]) * pc.inv_mk;
+        const R u = (P0[c] - pc.q * Am[c]) * rcp_(fabs(pc.q) * R(a.kappa));
         u2 += u * u;
       }
       pc.gpn = sqrt_(R(1) + u2);
@@ -1142,12 +1146,11 @@ __attribute__((amdgpu_waves_per_eu(orbit_waves<D, R>()))) void k_orbit(OrbitArgs
           double d = 0.0;
 #pragma unroll
           for (int j = 0; j < D; ++j) d += (double)o.Dm[c][j] * (double)vin[j];
-          Dv[c] = d;
-          dA[c] = (double)o.Ap[c] - (double)Am[c];
+          wra[c] = ((double)o.Ap[c] - (double)Am[c]) - a.dt * d;
           vout[c] = (double)o.vout[c];
-          gpb[c] = (double)o.gp[c];
+          wgp -= vout[c] * (double)o.gp[c];
         }
-        const double m = (double)pc.m;
+        const double m = fabs((double)pc.q);
         const double p2 = (double)o.pn1[0] * o.pn1[0] + (double)o.pn1[1] * o.pn1[1] + (double)o.pn1[2] * o.pn1[2];
         const double gmm = sqrt(1.0 + p2 / (m * m * a.kappa * a.kappa));
         kin = p2 / (m * (gmm + 1.0));
@@ -1158,7 +1161,7 @@ __attribute__((amdgpu_waves_per_eu(orbit_waves<D, R>()))) void k_orbit(OrbitArgs
         }
 #pragma unroll
         for (int l = 0; l < D; ++l) {
-          double xv = x[l] + a.dt * (double)vin[l];
+          double xv = a.x[l * ps + i] + a.dt * (double)vin[l];
           const double top = M.lo[l] + M.len[l];
           if (xv >= top) xv -= M.len[l];
           if (xv < M.lo[l]) xv += M.len[l];
@@ -1196,10 +1199,11 @@ __attribute__((amdgpu_waves_per_eu(orbit_waves<D, R>()))) void k_orbit(OrbitArgs
       double wk = 0.0, ra2 = 0.0;
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
-        const double r = dA[c] - a.dt * ((double)Ub[c] + Dv[c]);
+        const double r = wra[c] - a.dt * (double)Ub[c];
         ra2 += r * r;
-        wk += vout[c] * (-gpb[c] - (double)Ub[c]);
+        wk -= vout[c] * (double)Ub[c];
       }
+      wk += wgp;
       part[OP_KIN] = kin;
       part[OP_WORK] = (double)q * wk;
       part[OP_RA2] = ra2;
