@@ -28,6 +28,7 @@ class Config(C.Structure):
         ("threads", C.c_int32), ("outer_scheme", C.c_int32), ("anderson_m", C.c_int32),
         ("anderson_start", C.c_int32), ("ls_halvings", C.c_int32), ("anderson_lambda", C.c_double),
         ("ls_decrease", C.c_double), ("ls_growth", C.c_double), ("shape_order", C.c_int32),
+        ("refine_levels", C.c_int32),
     ]
 
 
@@ -47,7 +48,7 @@ class EvalOut(C.Structure):
 class Report(C.Structure):
     _fields_ = [("outer_iters", C.c_int32), ("inner_max", C.c_int32), ("inner_mean", C.c_double),
                 ("evaluations", C.c_int64), ("res_rms_ratio", C.c_double), ("res_max_ratio", C.c_double),
-                ("outer_updates", C.c_int32), ("pad", C.c_int32)]
+                ("outer_updates", C.c_int32), ("refined", C.c_int32)]
 
 
 class Diag(C.Structure):
@@ -103,8 +104,8 @@ def lib():
         L.orc_step.argtypes = [C.c_void_p, C.POINTER(Report)]
         L.orc_diagnostics.argtypes = [C.c_void_p, C.POINTER(Diag)]
         L.orc_mode_amplitude.argtypes = [C.c_void_p, C.c_int, C.c_int, C.POINTER(C.c_int32), dp]
-        L.orc_orbit_pass.argtypes = [C.c_void_p, dp, dp, dp, dp, dp, C.c_int, dp, dp, dp,
-                                     C.POINTER(C.c_int32)]
+        ip = C.POINTER(C.c_int32)
+        L.orc_orbit_pass.argtypes = [C.c_void_p, dp, dp, dp, dp, dp, C.c_int, dp, dp, dp, ip, ip, ip, dp, dp]
         L.orc_orbit_pass.restype = C.c_int64
         L.orc_trial_fields.argtypes = [C.c_void_p, dp, dp, dp, dp, dp]
         L.orc_spd_solve.argtypes = [C.c_int, dp, dp, dp]
@@ -130,7 +131,7 @@ def make_config(dim, n, lo, length, dt, kappa=1.0, sigma1=1.0, sigma2=1.0, gl_or
                 tol_outer_abs=1e-14, tol_outer_rel=1e-12, tol_inner_abs=1e-14, tol_inner_rel=1e-12,
                 max_outer=80, max_inner=64, beta=1.0, threads=0, outer_scheme=0, anderson_m=4,
                 anderson_start=2, ls_halvings=6, anderson_lambda=1e-12, ls_decrease=1e-4, ls_growth=1.2,
-                shape_order=2):
+                shape_order=2, refine_levels=0):
     c = Config()
     c.dim = dim
     for i in range(3):
@@ -145,6 +146,7 @@ def make_config(dim, n, lo, length, dt, kappa=1.0, sigma1=1.0, sigma2=1.0, gl_or
     c.outer_scheme, c.anderson_m, c.anderson_start, c.ls_halvings = outer_scheme, anderson_m, anderson_start, ls_halvings
     c.anderson_lambda, c.ls_decrease, c.ls_growth = anderson_lambda, ls_decrease, ls_growth
     c.shape_order = shape_order
+    c.refine_levels = refine_levels
     return c
 
 
@@ -338,14 +340,28 @@ class OracleSim:
                                          _p(Anp1), _p(Uh)), "trial_fields")
         return gphi, An, Anp1, Uh
 
-    def orbit_pass(self, gphi, An, Anp1, Uh, vin, iterate=False, want_J=True):
+    def orbit_pass(self, gphi, An, Anp1, Uh, vin, iterate=False, want_J=True, level_in=None):
+        """One frozen-field pass; level_in (iterate only) sets the refinement level each
+        particle starts at.  Returns v_out, P^{n+1}, J, per-particle evaluations and levels,
+        the converged v_in and the unwrapped end positions."""
+        ip = C.POINTER(C.c_int32)
         vout = np.zeros((3, self.np))
         Pn1 = np.zeros((3, self.np))
         J = np.zeros((3, self.ng)) if want_J else None
         iters = np.zeros(self.np, dtype=np.int32)
+        level = np.zeros(self.np, dtype=np.int32)
+        vinc = np.zeros((3, self.np))
+        xend = np.zeros((self.d, self.np))
+        lin = None
+        if level_in is not None:
+            lin = np.ascontiguousarray(np.broadcast_to(np.asarray(level_in, dtype=np.int32), (self.np,)))
         nfail = lib().orc_orbit_pass(self.h, _p(_f64(gphi).reshape(self.d, -1)),
                                      _p(_f64(An).reshape(3, -1)), _p(_f64(Anp1).reshape(3, -1)),
                                      _p(_f64(Uh).reshape(3, -1)), _p(_f64(vin).reshape(3, -1)),
-                                     int(iterate), _p(vout), _p(Pn1), _p(J),
-                                     iters.ctypes.data_as(C.POINTER(C.c_int32)))
-        return {"vout": vout, "Pnp1": Pn1, "J": J, "iters": iters, "nfail": int(nfail)}
+                                     int(iterate), _p(vout), _p(Pn1), _p(J), iters.ctypes.data_as(ip),
+                                     None if lin is None else lin.ctypes.data_as(ip), level.ctypes.data_as(ip),
+                                     _p(vinc), _p(xend))
+        if nfail < 0:
+            raise OracleError(EINVAL, "orbit_pass: level_in outside 0..refine_levels")
+        return {"vout": vout, "Pnp1": Pn1, "J": J, "iters": iters, "nfail": int(nfail), "level": level,
+                "vin": vinc, "xend": xend}

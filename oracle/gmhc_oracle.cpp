@@ -70,6 +70,9 @@ struct orc_config {
   double ls_growth;     // residual-growth limit (paper: 1.2)
   int32_t shape_order;  // B-spline degree r of the particle shape: 2 (the paper's; 0 selects
                         // it) or 1, the linear shape of the spline-degree comparison
+  int32_t refine_levels;  // convergence-triggered particle refinement: a particle whose
+                          // solve fails is retried with 2, 4, ... 2^refine_levels equal
+                          // particle sub-steps (0: off; at most kMaxRefine)
 };
 
 // One orbit evaluation v_out = F(v_in) of one particle at frozen trial fields.
@@ -98,7 +101,7 @@ struct orc_report {
   double res_rms_ratio;     // RMS test ratio at exit (<=1 passes)
   double res_max_ratio;     // max-node test ratio at exit
   int32_t outer_updates;    // accepted outer updates (the algorithm's outer iterations are this + 1)
-  int32_t pad;
+  int32_t refined;          // particles solved with sub-steps, final map evaluation
 };
 
 struct orc_diag {
@@ -556,6 +559,8 @@ struct Sim {
   // frozen fields for single-pass tests
   RVec fz_gphi[3], fz_An[3], fz_Anp1[3], fz_Uh[3];
   bool have_frozen = false;
+  // refinement level of each particle within the current step (0: the full step)
+  std::vector<int32_t> level;
 };
 
 int setup_mesh(const orc_config* c, Mesh& M, bool need_pow2 = false) {
@@ -593,19 +598,204 @@ FieldPtrs make_ptrs(const Sim& S, const RVec gphi[3], const RVec An[3], const RV
   return F;
 }
 
+// ---- Convergence-triggered particle refinement (spline-degree comparison of the
+// results section): a particle whose inner solve over the full step fails is solved
+// again with K = 2, 4, ..., 2^refine_levels equal particle sub-steps of dt/K while the
+// field step stays fixed.  The paper says only that; the rest is this reading:
+//  * sub-step k covers the fraction [k/K, (k+1)/K] of the step, with the step's fields
+//    restricted to it: grad phi^{n+1/2} and U^{n+1/2} as they are, and as vector
+//    potentials at its ends A(k/K) and A((k+1)/K) of the interpolant
+//    A(s) = (1-s) A^n + s A^{n+1} that the orbit discrete gradient already uses.  The
+//    sub-step is the full-step particle map with these fields and dt/K, started from the
+//    position and canonical momentum the previous sub-step ended with; the endpoint
+//    potential of one sub-step is then the starting one of the next.
+//  * each sub-step runs the same inner Picard loop (tests and limit), warm-started from
+//    the particle's warm start (k = 0) or the previous sub-step's v_out.
+//  * the orbit current is the time average of the sub-step orbit currents,
+//    J += (1/K) sum_k q v_out,k Sbar_k / dV.  With this weight the particle work of the
+//    sub-steps, sum_k (dt/K) q v_out,k . (-grad-phi-bar_k - U-bar_k), equals the mesh work
+//    of the deposit term by term (the particle-grid work identity of the energy proof),
+//    so a refined step conserves energy like an unrefined one.
+//  * within a step a particle's level only rises (every step starts at the full step),
+//    so once the levels have settled the outer map is one fixed function of the trial
+//    current.
+//  * the accepted orbit velocity of a refined particle (its warm start for the next
+//    evaluation) is the mean of its sub-step v_out; its position is the end of its last
+//    sub-step.
+const int kMaxRefine = 3;
+
+struct SubStep {
+  double x[3];     // start of the sub-step orbit (unwrapped)
+  double vin[3];   // converged v_in: the orbit x + s (dt/K) v_in, s in [0, 1]
+  double vout[3];  // its v_out
+};
+
+// One particle's solve over the field step.
+struct ParticleSolve {
+  bool ok = false;
+  int evals = 0;              // orbit evaluations, failed attempts included
+  int level = 0;              // level of the last attempt (K = 2^level sub-steps)
+  std::vector<SubStep> sub;   // sub-steps of a refined solve (empty at level 0)
+  double vin[3] = {0, 0, 0};  // level 0: converged v_in; refined: mean over sub-steps
+  double vout[3] = {0, 0, 0}; // level 0: its v_out; refined: mean over sub-steps
+  double Pn1[3] = {0, 0, 0};  // canonical momentum at the end of the step
+  double xend[3] = {0, 0, 0}; // end position (unwrapped)
+  double Ra2 = 0.0;           // sum over sub-steps of |R_A|^2
+  double work = 0.0;          // particle work / dt: sum_k (1/K) q v_out,k . (-gphibar_k - Ubar_k)
+};
+
+// Inner Picard loop of one particle over one (sub-)step of length ph.dt at fields F,
+// from the warm start v (Algorithm 1, inner solve): true when the mixed test passes with
+// finite, subluminal iterates.  v ends as the v_in of the last evaluation o.  With
+// iterate false, one evaluation of v and success.
+bool inner_solve(const Sim& S, const Phys& ph, const FieldPtrs& F, const double x[3], const double P[3],
+                 int64_t i, bool iterate, double v[3], orc_eval_out& o, int& evals) {
+  const int ngl = (int)S.glx.size();
+  const int maxit = iterate ? S.cfg.max_inner : 1;
+  for (int it = 1; it <= maxit; ++it) {
+    orbit_eval(S.M, ph, F, ngl, S.glx.data(), S.glw.data(), x, P, S.q[i], S.m[i], v, &o);
+    ++evals;
+    if (!iterate) return true;
+    double vn = std::sqrt(o.vout[0] * o.vout[0] + o.vout[1] * o.vout[1] + o.vout[2] * o.vout[2]);
+    if (!std::isfinite(vn) || !(vn < S.cfg.kappa)) return false;  // finite and subluminal
+    double dmax = 0.0, vmax = 0.0;
+    for (int c = 0; c < 3; ++c) {
+      dmax = std::max(dmax, std::fabs(o.vout[c] - v[c]));
+      vmax = std::max(vmax, std::fabs(o.vout[c]));
+    }
+    if (dmax <= S.cfg.tol_inner_abs + S.cfg.tol_inner_rel * vmax) return true;
+    for (int c = 0; c < 3; ++c) v[c] = o.vout[c];
+  }
+  return false;
+}
+
+// Solve particle i over the step whose vector potential at the fractions j / kmax of the
+// step is Ab[j] (j = 0..kmax, kmax = 2^refine_levels; Ab[0] = A^n, Ab[kmax] = A^{n+1}),
+// with grad phi and U from F0, from the warm start vw, starting at level level0 and
+// rising on failure up to refine_levels (iterate only).
+void solve_particle(const Sim& S, const std::vector<std::array<const double*, 3>>& Ab, const FieldPtrs& F0,
+                    int64_t i, const double vw[3], int level0, bool iterate, ParticleSolve& ps) {
+  const Mesh& M = S.M;
+  const int kmax = (int)Ab.size() - 1;
+  const int top = iterate ? S.cfg.refine_levels : 0;
+  for (int L = level0; L <= std::max(level0, top); ++L) {
+    const int K = 1 << L;
+    const double dtk = S.cfg.dt / K;
+    const Phys ph{S.cfg.kappa, dtk};
+    double x[3] = {S.x[0][i], S.x[1][i], S.x[2][i]};
+    double P[3] = {S.P[0][i], S.P[1][i], S.P[2][i]};
+    double warm[3] = {vw[0], vw[1], vw[2]};
+    double vsum[3] = {0, 0, 0}, isum[3] = {0, 0, 0};
+    ps.level = L;
+    ps.sub.clear();
+    ps.Ra2 = 0.0;
+    ps.work = 0.0;
+    bool ok = true;
+    for (int k = 0; k < K && ok; ++k) {
+      FieldPtrs F = F0;
+      for (int c = 0; c < 3; ++c) {
+        F.An[c] = Ab[k * (kmax / K)][c];
+        F.Anp1[c] = Ab[(k + 1) * (kmax / K)][c];
+      }
+      double v[3] = {warm[0], warm[1], warm[2]};
+      orc_eval_out o{};
+      ok = inner_solve(S, ph, F, x, P, i, iterate, v, o, ps.evals);
+      // the evaluation's chain-rule residual and work (accept-pass diagnostics)
+      double Ra = 0.0, wk = 0.0;
+      for (int c = 0; c < 3; ++c) {
+        double Dv = 0.0;
+        for (int j = 0; j < M.d; ++j) Dv += o.D[c * 3 + j] * v[j];
+        double r = o.Aplus[c] - o.Aminus[c] - dtk * (o.Ubar[c] + Dv);
+        Ra += r * r;
+        wk += S.q[i] * o.vout[c] * (-o.gradphibar[c] - o.Ubar[c]);
+      }
+      ps.Ra2 += Ra;
+      ps.work += wk / K;
+      SubStep st;
+      for (int c = 0; c < 3; ++c) {
+        st.x[c] = x[c];
+        st.vin[c] = v[c];
+        st.vout[c] = o.vout[c];
+        vsum[c] += o.vout[c];
+        isum[c] += v[c];
+        P[c] = o.Pnp1[c];
+        warm[c] = o.vout[c];
+      }
+      if (K > 1) ps.sub.push_back(st);
+      for (int l = 0; l < M.d; ++l) x[l] = x[l] + dtk * v[l];
+      if (K == 1)
+        for (int c = 0; c < 3; ++c) {
+          ps.vin[c] = v[c];
+          ps.vout[c] = o.vout[c];
+        }
+    }
+    if (K > 1)
+      for (int c = 0; c < 3; ++c) {
+        ps.vin[c] = isum[c] / K;
+        ps.vout[c] = vsum[c] / K;
+      }
+    for (int c = 0; c < 3; ++c) {
+      ps.Pn1[c] = P[c];
+      ps.xend[c] = x[c];
+    }
+    ps.ok = ok;
+    if (ok) return;
+  }
+}
+
+// A^n, A^{n+1} and, with refinement, the interpolant A(j / kmax) = (1 - s) A^n + s A^{n+1}
+// at the interior fractions s = j / kmax: store holds the interior arrays, Ab points at
+// all kmax + 1.
+void step_potentials(const Sim& S, const double* const An[3], const double* const Anp1[3],
+                     std::vector<std::array<RVec, 3>>& store, std::vector<std::array<const double*, 3>>& Ab) {
+  const int kmax = 1 << S.cfg.refine_levels;
+  const int64_t Ng = S.M.Ng;
+  store.assign(kmax > 1 ? kmax - 1 : 0, std::array<RVec, 3>{});
+  Ab.assign(kmax + 1, std::array<const double*, 3>{});
+  for (int c = 0; c < 3; ++c) {
+    Ab[0][c] = An[c];
+    Ab[kmax][c] = Anp1[c];
+  }
+  for (int j = 1; j < kmax; ++j) {
+    const double s = (double)j / kmax;
+    for (int c = 0; c < 3; ++c) {
+      RVec& a = store[j - 1][c];
+      a.resize(Ng);
+      for (int64_t g = 0; g < Ng; ++g) a[g] = (1.0 - s) * An[c][g] + s * Anp1[c][g];
+      Ab[j][c] = a.data();
+    }
+  }
+}
+
 // Orbit current deposit J_g = (1/dV) sum_i q_i vout_i Sbar_ig with Sbar from the
 // orbit of v_in (reading: the evaluated orbit), summed over particles in index
-// order so the result does not depend on the thread count.
-void deposit(const Sim& S, const RVec vin[3], const RVec vout[3], RVec J[3]) {
+// order so the result does not depend on the thread count.  A refined particle (sub
+// non-empty) deposits the mean of its sub-step orbit currents.
+void deposit(const Sim& S, const RVec vin[3], const RVec vout[3], RVec J[3],
+             const std::vector<std::vector<SubStep>>* sub = nullptr) {
   const Mesh& M = S.M;
+  const int ngl = (int)S.glx.size();
   for (int c = 0; c < 3; ++c) J[c].assign(M.Ng, 0.0);
   std::vector<std::pair<int64_t, double>> sb;
   for (int64_t i = 0; i < S.np; ++i) {
+    if (sub && !(*sub)[i].empty()) {
+      const std::vector<SubStep>& ss = (*sub)[i];
+      const int K = (int)ss.size();
+      for (const SubStep& st : ss) {
+        double dx[3] = {0.0, 0.0, 0.0};
+        for (int l = 0; l < M.d; ++l) dx[l] = (S.ph.dt / K) * st.vin[l];
+        sb.clear();
+        orbit_quadrature(M, nullptr, ngl, S.glx.data(), S.glw.data(), st.x, dx, nullptr, &sb);
+        for (auto& e : sb)
+          for (int c = 0; c < 3; ++c) J[c][e.first] += S.q[i] * st.vout[c] / K * e.second / M.dV;
+      }
+      continue;
+    }
     double xi[3] = {S.x[0][i], S.x[1][i], S.x[2][i]};
     double dx[3] = {0.0, 0.0, 0.0};
     for (int l = 0; l < M.d; ++l) dx[l] = S.ph.dt * vin[l][i];
     sb.clear();
-    orbit_quadrature(M, nullptr, (int)S.glx.size(), S.glx.data(), S.glw.data(), xi, dx, nullptr, &sb);
+    orbit_quadrature(M, nullptr, ngl, S.glx.data(), S.glw.data(), xi, dx, nullptr, &sb);
     for (auto& e : sb)
       for (int c = 0; c < 3; ++c) J[c][e.first] += S.q[i] * vout[c][i] * e.second / M.dV;
   }
@@ -934,6 +1124,7 @@ void* orc_create(const orc_config* cfg, int* status) {
                  1e-14 * std::fabs(cfg->sigma1))
     st = ORC_EINVAL;
   if (!st && (cfg->max_outer < 1 || cfg->max_inner < 1)) st = ORC_EINVAL;
+  if (!st && (cfg->refine_levels < 0 || cfg->refine_levels > kMaxRefine)) st = ORC_EINVAL;
   if (status) *status = st;
   if (st) return nullptr;
   Sim* S = new Sim();
@@ -1150,90 +1341,73 @@ int orc_set_fields(void* h, const double* phi, const double* psi, const double* 
   return ORC_OK;
 }
 
-// One implicit step (Algorithm 1 with a damped-Picard outer iteration on the mesh
-// current).  On failure the accepted state is left unchanged.
 // One evaluation of the outer map at the trial current j (Algorithm 1, one residual
-// evaluation): field step, inner Picard solve of every particle warm-started from vw,
-// orbit current deposit and projection H(j), and the mixed outer tests.  On return vw
-// holds each particle's last v_out.  Returns ORC_EINNER if any inner solve failed.
+// evaluation): field step, inner Picard solve of every particle warm-started from vw
+// (with refinement of the particles whose full-step solve fails, when enabled), orbit
+// current deposit and projection H(j), and the mixed outer tests.  On return vw holds
+// each particle's last v_out (the sub-step mean for a refined one).  Returns ORC_EINNER
+// if any particle solve failed.
 struct OuterEval {
   Trial T;
   RVec H[3];
-  RVec vin_f[3], Pn1[3], Ra2, work;
+  RVec vin_f[3], Pn1[3], xend[3], Ra2, work;
+  std::vector<std::vector<SubStep>> sub;  // sub-steps of refined particles (else empty)
   double rr = 0.0, mr = 0.0;
 };
 
 int evaluate_outer(Sim& S, const RVec An[3], const RVec j[3], RVec vw[3], OuterEval& E, orc_report& R) {
   const Mesh& M = S.M;
   const int64_t np = S.np;
-  const int ngl = (int)S.glx.size();
   field_solve(S, j, E.T);
   FieldPtrs F = make_ptrs(S, E.T.gphi, An, E.T.Anp1, E.T.Uh);
+  std::vector<std::array<RVec, 3>> Astore;
+  std::vector<std::array<const double*, 3>> Ab;
+  step_potentials(S, F.An, F.Anp1, Astore, Ab);
   for (int c = 0; c < 3; ++c) {
     E.vin_f[c].assign(np, 0.0);
     E.Pn1[c].assign(np, 0.0);
+    E.xend[c].assign(np, 0.0);
   }
   E.Ra2.assign(np, 0.0);
   E.work.assign(np, 0.0);
+  E.sub.assign(np, std::vector<SubStep>());
   std::vector<int32_t> iters(np), fail(np);
 #pragma omp parallel for schedule(dynamic, 256)
   for (int64_t i = 0; i < np; ++i) {
-    double xi[3] = {S.x[0][i], S.x[1][i], S.x[2][i]};
-    double Pi[3] = {S.P[0][i], S.P[1][i], S.P[2][i]};
-    double vin[3] = {vw[0][i], vw[1][i], vw[2][i]};
-    orc_eval_out o{};
-    int it = 0;
-    bool ok = false;
-    for (it = 1; it <= S.cfg.max_inner; ++it) {
-      orbit_eval(M, S.ph, F, ngl, S.glx.data(), S.glw.data(), xi, Pi, S.q[i], S.m[i], vin, &o);
-      double vn = std::sqrt(o.vout[0] * o.vout[0] + o.vout[1] * o.vout[1] + o.vout[2] * o.vout[2]);
-      if (!std::isfinite(vn) || !(vn < S.cfg.kappa)) break;  // finite and subluminal
-      double dmax = 0.0, vmax = 0.0;
-      for (int c = 0; c < 3; ++c) {
-        dmax = std::max(dmax, std::fabs(o.vout[c] - vin[c]));
-        vmax = std::max(vmax, std::fabs(o.vout[c]));
-      }
-      if (dmax <= S.cfg.tol_inner_abs + S.cfg.tol_inner_rel * vmax) {
-        ok = true;
-        break;
-      }
-      for (int c = 0; c < 3; ++c) vin[c] = o.vout[c];
-    }
-    iters[i] = std::min(it, S.cfg.max_inner);
-    fail[i] = ok ? 0 : 1;
+    double v0[3] = {vw[0][i], vw[1][i], vw[2][i]};
+    ParticleSolve ps;
+    solve_particle(S, Ab, F, i, v0, S.level[i], true, ps);
+    iters[i] = ps.evals;
+    fail[i] = ps.ok ? 0 : 1;
+    if (ps.ok) S.level[i] = ps.level;
     for (int c = 0; c < 3; ++c) {
-      E.vin_f[c][i] = vin[c];
-      vw[c][i] = o.vout[c];
-      E.Pn1[c][i] = o.Pnp1[c];
+      E.vin_f[c][i] = ps.vin[c];
+      vw[c][i] = ps.vout[c];
+      E.Pn1[c][i] = ps.Pn1[c];
+      E.xend[c][i] = ps.xend[c];
     }
-    // accept-pass diagnostics of this evaluation
-    double Ra = 0.0, wk = 0.0;
-    for (int c = 0; c < 3; ++c) {
-      double Dv = 0.0;
-      for (int jj = 0; jj < M.d; ++jj) Dv += o.D[c * 3 + jj] * vin[jj];
-      double r = o.Aplus[c] - o.Aminus[c] - S.cfg.dt * (o.Ubar[c] + Dv);
-      Ra += r * r;
-      wk += S.q[i] * o.vout[c] * (-o.gradphibar[c] - o.Ubar[c]);
-    }
-    E.Ra2[i] = Ra;
-    E.work[i] = wk;
+    E.Ra2[i] = ps.Ra2;
+    E.work[i] = ps.work;
+    E.sub[i] = std::move(ps.sub);
   }
   int64_t nfail = 0, evals = 0;
-  int imax = 0;
+  int imax = 0, refined = 0;
   double isum = 0.0;
   for (int64_t i = 0; i < np; ++i) {
     nfail += fail[i];
     evals += iters[i];
     imax = std::max(imax, iters[i]);
     isum += iters[i];
+    refined += E.sub[i].empty() ? 0 : 1;
   }
   R.outer_iters += 1;
   R.evaluations += evals;
   R.inner_max = imax;
   R.inner_mean = np ? isum / np : 0.0;
+  R.refined = refined;
   if (nfail) return ORC_EINNER;
   RVec Jorb[3];
-  deposit(S, E.vin_f, vw, Jorb);
+  deposit(S, E.vin_f, vw, Jorb, &E.sub);
   for (int c = 0; c < 3; ++c) {
     CVec jh = to_spec(M, Jorb[c].data());
     if (S.cfg.project) project(M, jh);
@@ -1276,7 +1450,7 @@ void commit_step(Sim& S, const RVec j[3], const RVec vw[3], const OuterEval& E) 
     S.P[c] = E.Pn1[c];
   }
   for (int l = 0; l < M.d; ++l)
-    for (int64_t i = 0; i < np; ++i) S.x[l][i] = wrap1(S.x[l][i] + dt * E.vin_f[l][i], M.lo[l], M.len[l]);
+    for (int64_t i = 0; i < np; ++i) S.x[l][i] = wrap1(E.xend[l][i], M.lo[l], M.len[l]);
   S.t += dt;
   S.step += 1;
 }
@@ -1340,6 +1514,7 @@ int orc_step(void* h, orc_report* rep) {
     j[c] = S.Jacc[c];
     vw[c] = S.vbar[c];  // inner warm start, carried from evaluation to evaluation
   }
+  S.level.assign(S.np, 0);  // every step starts with full-step particle solves
   orc_report R{};
   auto finish = [&](int st) {
     if (rep) *rep = R;
@@ -1502,12 +1677,17 @@ int orc_mode_amplitude(void* h, int which, int comp, const int32_t* mode, double
 
 // One frozen-field orbit pass over all loaded particles with the fields given
 // explicitly: a single evaluation v_out = F(v_in) per particle (iterate = 0), or the
-// inner Picard loop to the inner tolerance (iterate = 1, v_in warm start).  Writes
-// v_out [3][n], P^{n+1} [3][n] and the unprojected orbit current J [3][Ng].
-// Returns the number of particles whose inner solve failed (iterate = 1).
+// inner Picard loop to the inner tolerance (iterate = 1, v_in warm start) with
+// refinement of failed particles when refine_levels > 0.  Writes v_out [3][n], P^{n+1}
+// [3][n], the unprojected orbit current J [3][Ng], orbit evaluations per particle, the
+// level each particle was solved at, its converged v_in [3][n] and its end position
+// xend [d][n] (unwrapped); any output may be null.  level_in (may be null: all 0) sets the
+// level each particle starts at (iterate = 1; at most refine_levels).  Returns the number
+// of particles whose solve failed (iterate = 1), or -1 for an invalid level_in.
 int64_t orc_orbit_pass(void* h, const double* gphi, const double* An, const double* Anp1,
                        const double* Uh, const double* vin, int iterate, double* vout, double* Pn1,
-                       double* J, int32_t* iters) {
+                       double* J, int32_t* iters, const int32_t* level_in, int32_t* level_out,
+                       double* vin_out, double* xend) {
   Sim& S = *static_cast<Sim*>(h);
   set_threads(S);
   const Mesh& M = S.M;
@@ -1519,50 +1699,41 @@ int64_t orc_orbit_pass(void* h, const double* gphi, const double* An, const doub
     F.Anp1[l] = Anp1 + l * M.Ng;
     F.Uh[l] = Uh + l * M.Ng;
   }
-  const int ngl = (int)S.glx.size();
+  if (level_in)
+    for (int64_t i = 0; i < np; ++i)
+      if (level_in[i] < 0 || level_in[i] > (iterate ? S.cfg.refine_levels : 0)) return -1;
+  std::vector<std::array<RVec, 3>> Astore;
+  std::vector<std::array<const double*, 3>> Ab;
+  step_potentials(S, F.An, F.Anp1, Astore, Ab);
   RVec vi[3], vo[3];
   for (int c = 0; c < 3; ++c) {
-    vi[c].assign(vin + c * np, vin + (c + 1) * np);
+    vi[c].assign(np, 0.0);
     vo[c].assign(np, 0.0);
   }
+  std::vector<std::vector<SubStep>> sub(np);
   int64_t nfail = 0;
 #pragma omp parallel for schedule(dynamic, 256) reduction(+ : nfail)
   for (int64_t i = 0; i < np; ++i) {
-    double xi[3] = {S.x[0][i], S.x[1][i], S.x[2][i]};
-    double Pi[3] = {S.P[0][i], S.P[1][i], S.P[2][i]};
-    double v[3] = {vi[0][i], vi[1][i], vi[2][i]};
-    orc_eval_out o{};
-    int maxit = iterate ? S.cfg.max_inner : 1;
-    bool ok = !iterate;
-    int it;
-    for (it = 1; it <= maxit; ++it) {
-      orbit_eval(M, S.ph, F, ngl, S.glx.data(), S.glw.data(), xi, Pi, S.q[i], S.m[i], v, &o);
-      if (!iterate) break;
-      double vn = std::sqrt(o.vout[0] * o.vout[0] + o.vout[1] * o.vout[1] + o.vout[2] * o.vout[2]);
-      if (!std::isfinite(vn) || !(vn < S.cfg.kappa)) break;
-      double dmax = 0.0, vmax = 0.0;
-      for (int c = 0; c < 3; ++c) {
-        dmax = std::max(dmax, std::fabs(o.vout[c] - v[c]));
-        vmax = std::max(vmax, std::fabs(o.vout[c]));
-      }
-      if (dmax <= S.cfg.tol_inner_abs + S.cfg.tol_inner_rel * vmax) {
-        ok = true;
-        break;
-      }
-      for (int c = 0; c < 3; ++c) v[c] = o.vout[c];
-    }
-    if (iters) iters[i] = std::min(it, maxit);
-    if (!ok) nfail += 1;
+    double v0[3] = {vin[i], vin[np + i], vin[2 * np + i]};
+    ParticleSolve ps;
+    solve_particle(S, Ab, F, i, v0, level_in ? level_in[i] : 0, iterate != 0, ps);
+    if (iters) iters[i] = ps.evals;
+    if (level_out) level_out[i] = ps.level;
+    if (!ps.ok) nfail += 1;
     for (int c = 0; c < 3; ++c) {
-      vi[c][i] = v[c];
-      vo[c][i] = o.vout[c];
-      if (vout) vout[c * np + i] = o.vout[c];
-      if (Pn1) Pn1[c * np + i] = o.Pnp1[c];
+      vi[c][i] = ps.vin[c];
+      vo[c][i] = ps.vout[c];
+      if (vout) vout[c * np + i] = ps.vout[c];
+      if (Pn1) Pn1[c * np + i] = ps.Pn1[c];
+      if (vin_out) vin_out[c * np + i] = ps.vin[c];
     }
+    if (xend)
+      for (int l = 0; l < M.d; ++l) xend[l * np + i] = ps.xend[l];
+    sub[i] = std::move(ps.sub);
   }
   if (J) {
     RVec Jr[3];
-    deposit(S, vi, vo, Jr);
+    deposit(S, vi, vo, Jr, &sub);
     for (int c = 0; c < 3; ++c) std::memcpy(J + c * M.Ng, Jr[c].data(), sizeof(double) * M.Ng);
   }
   return nfail;
