@@ -342,8 +342,9 @@ class OracleSim:
 
     def orbit_pass(self, gphi, An, Anp1, Uh, vin, iterate=False, want_J=True, level_in=None):
         """One frozen-field pass; level_in (iterate only) sets the refinement level each
-        particle starts at.  Returns v_out, P^{n+1}, J, per-particle evaluations and levels,
-        the converged v_in and the unwrapped end positions."""
+        particle starts at.  Returns v_out, P^{n+1}, J, per-particle evaluations and levels
+        (refine_levels + 1 where every level failed), the converged v_in and the unwrapped
+        end positions."""
         ip = C.POINTER(C.c_int32)
         vout = np.zeros((3, self.np))
         Pn1 = np.zeros((3, self.np))

@@ -634,7 +634,8 @@ struct SubStep {
 struct ParticleSolve {
   bool ok = false;
   int evals = 0;              // orbit evaluations, failed attempts included
-  int level = 0;              // level of the last attempt (K = 2^level sub-steps)
+  int level = 0;              // level of the accepted solve (K = 2^level sub-steps); after a
+                              // failure at every level, refine_levels + 1
   std::vector<SubStep> sub;   // sub-steps of a refined solve (empty at level 0)
   double vin[3] = {0, 0, 0};  // level 0: converged v_in; refined: mean over sub-steps
   double vout[3] = {0, 0, 0}; // level 0: its v_out; refined: mean over sub-steps
@@ -741,6 +742,8 @@ void solve_particle(const Sim& S, const std::vector<std::array<const double*, 3>
     ps.ok = ok;
     if (ok) return;
   }
+  // failed at every level: reported one past the finest (0 without refinement)
+  ps.level = top > 0 ? top + 1 : 0;
 }
 
 // A^n, A^{n+1} and, with refinement, the interpolant A(j / kmax) = (1 - s) A^n + s A^{n+1}

@@ -15,6 +15,7 @@
 using namespace gmhc;
 
 static_assert(GMHC_MAX_ORBIT_CELLS == kMaxCross - 1, "the orbit pass supports |dt v / h| < kMaxCross - 1");
+static_assert(kMaxRefine == 3, "gmhc_config.refine_levels is documented as 0..3");
 
 struct gmhc_ctx {
   gmhc_config cfg;
@@ -53,6 +54,12 @@ struct gmhc_ctx {
   int32_t* ridx = nullptr;
   int32_t* ridx2 = nullptr;
   int32_t* rcount = nullptr;
+  // refinement (refine_levels > 0): per-particle level within the step, per-workgroup
+  // flags of the orbit pass, and the interpolated vector potentials of the sub-steps
+  int32_t* rstate = nullptr;
+  int32_t* rblock = nullptr;
+  double* Ab = nullptr;
+  bool pass_levels = false;  // the last frozen pass ran with refinement (rstate holds its levels)
   // mesh
   double* tacc = nullptr;   // [d+6][Ng] block in the trial layout whose A part is A^n; at
                             // commit it trades places with the converged trial block
@@ -222,6 +229,8 @@ size_t carve(gmhc_ctx* c, char* base, int64_t np) {
   c->ridx = cv.take<int32_t>(N);
   c->ridx2 = cv.take<int32_t>(N);
   c->rcount = cv.take<int32_t>((size_t)radix_count_ints(np));
+  const int rl = c->cfg.refine_levels;
+  if (rl > 0) c->rstate = cv.take<int32_t>(N);
   c->tacc = cv.take<double>((size_t)(d + 6) * Ng);
   c->An = c->tacc + (size_t)d * Ng;
   for (int p = 0; p < 2; ++p) c->trial[p] = cv.take<double>((size_t)(d + 6) * Ng);
@@ -244,7 +253,11 @@ size_t carve(gmhc_ctx* c, char* base, int64_t np) {
   // orbit partials, then residual / diagnostic partials: at most one block per axis-0
   // line (the residual folded into the last FFT pass) or 1024
   const int64_t res_cap = std::max<int64_t>(1024, c->M.Ng / c->M.n[0]);
-  c->partials = cv.take<double>((size_t)(c->max_blocks + res_cap) * 8);
+  c->partials = cv.take<double>((size_t)c->max_blocks * kOrbitParts + (size_t)res_cap * 8);
+  if (rl > 0) {
+    c->rblock = cv.take<int32_t>((size_t)c->max_blocks);
+    c->Ab = cv.take<double>((size_t)((1 << rl) - 1) * 3 * Ng);
+  }
   c->pchunk = cv.take<double>((size_t)kOrbitParts * kReduceChunks);
   c->dres = cv.take<double>(64);
   c->ddot = cv.take<double>(kMaxDots);
@@ -313,8 +326,17 @@ OrbitArgs orbit_args(gmhc_ctx* c, int iterate, int par = 0) {
   a.iters = c->iters;
   a.partials = c->partials;
   a.pstride = c->max_blocks;
+  if (c->cfg.refine_levels > 0 && iterate) {
+    a.refine_levels = c->cfg.refine_levels;
+    a.rstate = c->rstate;
+    a.rblock = c->rblock;
+    a.Ab = c->Ab;
+  }
   return a;
 }
+
+// Residual and diagnostic partials, after the orbit pass's.
+double* res_partials(const gmhc_ctx* c) { return c->partials + (size_t)c->max_blocks * kOrbitParts; }
 
 int orbit_blocks(const gmhc_ctx* c) { return (int)((c->np + kOrbitBlock - 1) / kOrbitBlock); }
 
@@ -322,6 +344,8 @@ int orbit_blocks(const gmhc_ctx* c) { return (int)((c->np + kOrbitBlock - 1) / k
 int32_t run_orbit(gmhc_ctx* ctx, int iterate, double* ms) {
   OrbitArgs a = orbit_args(ctx, iterate);
   HIPCK(launch_zero(reinterpret_cast<double*>(ctx->Jdep), 6 * ctx->M.Ng, ctx->stream));
+  if (a.rstate) HIPCK(launch_refine_reset(ctx->rstate, ctx->np, ctx->stream));
+  ctx->pass_levels = a.rstate != nullptr;
   const bool timed = ctx->timed_now;
   HIPCK(launch_orbit(a, ctx->ngl, ctx->stream, timed ? ctx->ev0 : nullptr, timed ? ctx->ev1 : nullptr));
   const int nb = (int)((ctx->np + kOrbitBlock - 1) / kOrbitBlock);
@@ -535,6 +559,7 @@ bool config_ok(const gmhc_config& c) {
   if (c.max_outer < 1 || c.max_inner < 1 || !(c.beta > 0.0 && c.beta <= 1.0)) return false;
   if (c.timing < 0) return false;
   if (c.deterministic != 0 && c.deterministic != 1) return false;
+  if (c.refine_levels < 0 || c.refine_levels > kMaxRefine) return false;
   if (c.outer_scheme != 0 && c.outer_scheme != 1) return false;
   if (c.outer_scheme == 1 &&
       (c.anderson_m < 1 || c.anderson_m > 8 || c.anderson_start < 1 || c.ls_halvings < 0 || c.ls_halvings > 30 ||
@@ -891,7 +916,7 @@ int32_t enqueue_outer(gmhc_ctx* ctx, int cur, int hs, int part, const int32_t* s
     ra.j = ctx->jr[cur];
     ra.gphi = ctx->trial[par];
     ra.Uh = ctx->trial[par] + (int64_t)(d + 3) * Ng;
-    ra.partials = ctx->partials + (size_t)ctx->max_blocks * 8;  // disjoint from orbit partials
+    ra.partials = res_partials(ctx);  // disjoint from orbit partials
     ra.stop = stop;
     const bool proj = ctx->cfg.project_nyquist != 0;
     // pass and residual sums, then (device control) the outer test
@@ -1034,6 +1059,7 @@ int32_t eval_outer(gmhc_ctx* ctx, int cur, int hs, gmhc_step_report& R, bool& us
   R.segments += (int64_t)llround(h[OP_SEGS]);
   R.inner_max = (int32_t)llround(h[OP_ITMAX]);
   R.inner_mean = np ? h[OP_ITERS] / (double)np : 0.0;
+  R.refined = (int32_t)llround(h[OP_REFINED]);
   if (h[OP_FAIL] > 0.0) return fail(ctx, GMHC_EINNER, inner_fail_msg(h[OP_FAIL], h[OP_XLIM]));
   const double* r = ctx->hres + kResOff;
   const double n3 = 3.0 * (double)Ng;
@@ -1090,11 +1116,14 @@ int32_t commit_host(gmhc_ctx* ctx, int cur, double rr, double mr) {
 // already queued return at once.  The host synchronizes once per batch, so the GPU does
 // not idle between outer iterations.
 // Per-step flags: the first orbit pass reads the accepted v from vb, and the orbit
-// launches of every timing-th step are timed.
-void begin_step(gmhc_ctx* ctx) {
+// launches of every timing-th step are timed.  With refinement every particle starts
+// the step at the full step again.
+int32_t begin_step(gmhc_ctx* ctx) {
   ctx->vin_first = true;
   const int tk = ctx->cfg.timing;
   ctx->timed_now = tk == 1 || (tk > 1 && ctx->step % tk == 0);
+  if (ctx->rstate) HIPCK(launch_refine_reset(ctx->rstate, ctx->np, ctx->stream));
+  return GMHC_OK;
 }
 
 // Enqueue outer iteration k (1-based) of a device-controlled Picard step from current
@@ -1136,9 +1165,10 @@ bool can_run_ahead(const gmhc_ctx* ctx) {
 // it (drop_ahead), and the next step then starts afresh.
 int32_t run_ahead(gmhc_ctx* ctx) {
   if (!can_run_ahead(ctx)) return GMHC_OK;
-  begin_step(ctx);
+  int32_t st = begin_step(ctx);
+  if (st) return st;
   ctx->ctl_clean = false;
-  int32_t st = enqueue_picard_iter(ctx, 1, 0);
+  st = enqueue_picard_iter(ctx, 1, 0);
   if (st) return st;
   ctx->ahead = true;
   return GMHC_OK;
@@ -1204,6 +1234,7 @@ int32_t run_picard(gmhc_ctx* ctx, gmhc_step_report& R) {
     R.segments = (int64_t)llround(acc[1]);
     R.inner_max = (int32_t)llround(acc[2]);
     R.inner_mean = np ? acc[10] / (double)np : 0.0;
+    R.refined = (int32_t)llround(acc[12]);
     R.res_rms_ratio = acc[5];
     R.res_max_ratio = acc[6];
     if (c[0]) {
@@ -1370,7 +1401,8 @@ int32_t gmhc_step(gmhc_ctx* ctx, gmhc_step_report* rep) {
       int32_t st = sort_particles(ctx);
       if (st) return done(st);
     }
-    begin_step(ctx);
+    int32_t st = begin_step(ctx);
+    if (st) return done(st);
   }
   bool use_graph = ctx->cfg.graphs != 0 && ctx->stream != nullptr && !ctx->graphs_off;
   if (ctx->cfg.outer_scheme == 1) return done(step_anderson(ctx, R, use_graph));
@@ -1425,7 +1457,7 @@ int32_t gmhc_diagnostics(gmhc_ctx* ctx, gmhc_diag* out) {
   sa.rho = ctx->S0 + 2 * Ng;
   sa.A = ctx->S0 + 3 * Ng;
   sa.U = ctx->S0 + 6 * Ng;
-  sa.partials = ctx->partials + (size_t)ctx->max_blocks * 8;
+  sa.partials = res_partials(ctx);
   const int sb = res_blocks(ctx);
   HIPCK(launch_spec_diag(sa, sb, s));
   HIPCK(launch_reduce(sa.partials, sb, kDiagParts, 1, kDiagParts, 0u, ctx->dres + kResOff, s));
@@ -1615,6 +1647,7 @@ int32_t gmhc_orbit_pass_frozen(gmhc_ctx* ctx, int32_t iterate, gmhc_pass_report*
   R.evaluations = (int64_t)llround(h[OP_ITERS]);
   R.segments = (int64_t)llround(h[OP_SEGS]);
   R.inner_mean = np ? h[OP_ITERS] / (double)np : 0.0;
+  R.refined = (int64_t)llround(h[OP_REFINED]);
   R.orbit_ms = oms;
   ctx->last_pass = R;
   ctx->pass_done = true;
@@ -1622,7 +1655,8 @@ int32_t gmhc_orbit_pass_frozen(gmhc_ctx* ctx, int32_t iterate, gmhc_pass_report*
   return GMHC_OK;
 }
 
-int32_t gmhc_read_pass(gmhc_ctx* ctx, double* vout, double* Pnp1, double* J, int32_t* iters, int32_t ptr_kind) {
+int32_t gmhc_read_pass(gmhc_ctx* ctx, double* vout, double* Pnp1, double* J, int32_t* iters, int32_t* levels,
+                       int32_t ptr_kind) {
   if (!ctx) return GMHC_EINVAL;
   drop_ahead(ctx);
   if (!ctx->pass_done) return fail(ctx, GMHC_ESTATE, "no frozen pass has run");
@@ -1644,6 +1678,15 @@ int32_t gmhc_read_pass(gmhc_ctx* ctx, double* vout, double* Pnp1, double* J, int
     int32_t* tmp = reinterpret_cast<int32_t*>(ctx->pscr[0]);
     HIPCK(launch_unpermute_i32(ctx->iters, tmp, ctx->id, np, s));
     HIPCK(hipMemcpyAsync(iters, tmp, sizeof(int32_t) * np, kind_of(ptr_kind, false), s));
+    HIPCK(hipStreamSynchronize(s));
+  }
+  if (levels && np) {
+    int32_t* tmp = reinterpret_cast<int32_t*>(ctx->pscr[0]);
+    if (ctx->pass_levels)
+      HIPCK(launch_unpermute_i32(ctx->rstate, tmp, ctx->id, np, s));
+    else
+      HIPCK(hipMemsetAsync(tmp, 0, sizeof(int32_t) * np, s));
+    HIPCK(hipMemcpyAsync(levels, tmp, sizeof(int32_t) * np, kind_of(ptr_kind, false), s));
     HIPCK(hipStreamSynchronize(s));
   }
   if (J) {

@@ -13,7 +13,8 @@ constexpr int kBlock = 256;       // threads per workgroup (4 wave64)
 constexpr int kOrbitBlock = 64;   // threads per orbit-pass workgroup (one wave64)
 constexpr int kMaxGL = 8;         // Gauss-Legendre points per segment supported
 constexpr int kMaxCross = 8;      // knot crossings per axis per step supported
-constexpr int kOrbitParts = 8;    // per-block partial values written by the orbit pass
+constexpr int kOrbitParts = 9;    // per-block partial values written by the orbit pass
+constexpr int kMaxRefine = 3;     // particle refinement: at most 2^3 sub-steps per step
 constexpr int kResParts = 8;      // per-block partial values written by the residual pass
 constexpr int kDiagParts = 8;
 
@@ -26,7 +27,8 @@ enum OrbitPart {
   OP_WORK = 4,    // sum q v_out . E-bar
   OP_RA2 = 5,     // sum |R_A|^2
   OP_SEGS = 6,    // knot-split segments over all evaluations (sum)
-  OP_XLIM = 7     // failed solves whose orbit reached the knot-crossing limit (sum)
+  OP_XLIM = 7,    // failed solves whose orbit reached the knot-crossing limit (sum)
+  OP_REFINED = 8  // particles solved with sub-steps (sum)
 };
 
 // Particle momenta, charges and orbit velocities are stored in the bulk type: FP64
@@ -90,12 +92,26 @@ struct OrbitArgs {
   double* partials;      // [kOrbitParts][pstride]: value v of block b at v * pstride + b
   int64_t pstride;       // >= gridDim.x
   const int32_t* stop;   // optional device flag: nonzero = skip the pass
+  // Convergence-triggered particle refinement (refine_levels > 0 and iterate = 1; else
+  // rstate is null).  rstate[i]: bits 0-7 the particle's level within the step (K = 2^level
+  // sub-steps; 0 the full step), bits 8-31 the evaluations of a full-step attempt of this
+  // pass that failed.  rblock[b]: workgroup b of the pass holds a particle to refine.  Ab:
+  // the vector potential A(j / 2^refine_levels) = (1 - s) A^n + s A^{n+1} at the interior
+  // fractions, [j - 1][3][Ng].
+  int refine_levels;
+  int32_t* rstate;
+  int32_t* rblock;
+  double* Ab;
 };
 
 // With events e0 and e1, the launch itself records its start and stop in them (no
 // separate marker packets on the stream); with no particles both are recorded at once.
+// With refinement (a.rstate set) the refinement pass follows the main pass in the same
+// call, and the events span both.
 hipError_t launch_orbit(const OrbitArgs& a, int ngl, hipStream_t s, hipEvent_t e0 = nullptr,
                         hipEvent_t e1 = nullptr);
+// Every particle back to the full step (refinement level 0), at the start of a step.
+hipError_t launch_refine_reset(int32_t* rstate, int64_t np, hipStream_t s);
 
 // ---- spectral field step ---------------------------------------------------------
 

@@ -54,6 +54,15 @@ __device__ __forceinline__ int wrapi(int i, int n) { return i & (n - 1); }
 
 __device__ __forceinline__ int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
+// A position less than one period outside [lo, lo + len) brought back into it.
+__device__ __forceinline__ double wrap_pos(double xv, double lo, double len) {
+  const double top = lo + len;
+  if (xv >= top) xv -= len;
+  if (xv < lo) xv += len;
+  if (xv >= top) xv -= len;
+  return xv;
+}
+
 // Reciprocal and square roots: hardware estimates refined by Newton / Goldschmidt
 // steps to full FP64 precision; single hardware instructions in FP32.
 __device__ __forceinline__ double rcp_(double x) {
@@ -949,7 +958,9 @@ __device__ __forceinline__ int tile_to_global(const Mesh& M, const Tile& t, int 
 template <int D, class R>
 constexpr int orbit_waves() { return (sizeof(R) == 4 && D <= 2) ? 3 : 2; }
 
-template <int D, int SH, int NGL, class R>
+// REF: refinement is on (a.rstate set); the kernel then hands the particles whose
+// full-step solve fails, and those refined earlier in the step, to the refinement pass.
+template <int D, int SH, int NGL, class R, bool REF>
 __global__ __launch_bounds__(kOrbitBlock)
 __attribute__((amdgpu_waves_per_eu(orbit_waves<D, R>()))) void k_orbit(OrbitArgs a) {
   if (a.stop && *a.stop) return;  // the outer iteration this pass belongs to is done
@@ -1095,7 +1106,9 @@ __attribute__((amdgpu_waves_per_eu(orbit_waves<D, R>()))) void k_orbit(OrbitArgs
   // the kinetic energy of p^{n+1}
   double vout[3] = {0.0, 0.0, 0.0}, wra[3] = {0.0, 0.0, 0.0};
   double wgp = 0.0, kin = 0.0;
-  if (live) {
+  // with refinement, a particle already refined earlier in the step skips the full step
+  const bool solve = live && !(REF && (a.rstate[i] & 0xff) != 0);
+  if (solve) {
     PConst<R> pc;
     pc.q = qv;
     q = pc.q;
@@ -1160,14 +1173,7 @@ __attribute__((amdgpu_waves_per_eu(orbit_waves<D, R>()))) void k_orbit(OrbitArgs
           Pnp[c * ps + i] = o.Pn1[c];
         }
 #pragma unroll
-        for (int l = 0; l < D; ++l) {
-          double xv = a.x[l * ps + i] + a.dt * (double)vin[l];
-          const double top = M.lo[l] + M.len[l];
-          if (xv >= top) xv -= M.len[l];
-          if (xv < M.lo[l]) xv += M.len[l];
-          if (xv >= top) xv -= M.len[l];
-          a.xn[l * ps + i] = xv;
-        }
+        for (int l = 0; l < D; ++l) a.xn[l * ps + i] = wrap_pos(a.x[l * ps + i] + a.dt * (double)vin[l], M.lo[l], M.len[l]);
         break;
       }
 #pragma unroll
@@ -1175,11 +1181,19 @@ __attribute__((amdgpu_waves_per_eu(orbit_waves<D, R>()))) void k_orbit(OrbitArgs
     }
     if (it > maxit) it = maxit;
     if (a.iters) a.iters[i] = it;
-    part[OP_FAIL] = conv ? 0.0 : 1.0;
+    // with refinement a failed full step is handed to the refinement pass, with the
+    // evaluations it took
+    const bool refine = REF && !conv;
+    if (refine) a.rstate[i] = (it << 8) | 1;
+    part[OP_FAIL] = (conv || refine) ? 0.0 : 1.0;
     part[OP_ITERS] = (double)it;
     part[OP_ITMAX] = (double)it;
     part[OP_SEGS] = (double)segs;
-    part[OP_XLIM] = (!conv && xlim) ? 1.0 : 0.0;
+    part[OP_XLIM] = (!conv && !refine && xlim) ? 1.0 : 0.0;
+  }
+  if (REF) {  // flag the workgroup for the refinement pass (its skipped and failed particles)
+    const uint64_t need = __ballot(live && !conv);
+    if (threadIdx.x == 0) a.rblock[blockIdx.x] = need != 0 ? 1 : 0;
   }
 
   // ---- deposit phase (every lane of the workgroup, converged particles contribute)
@@ -1238,13 +1252,351 @@ __attribute__((amdgpu_waves_per_eu(orbit_waves<D, R>()))) void k_orbit(OrbitArgs
     a.partials[(int64_t)idx * a.pstride + blockIdx.x] = idx == OP_ITMAX ? itmax : tot;
 }
 
+// ---- refinement pass (convergence-triggered particle refinement of the spline-degree
+// comparison in the results section)
+//
+// A particle whose full-step solve failed, in this pass or earlier in the step, is solved
+// with K = 2^L equal particle sub-steps of dt/K, for L = its level, ... refine_levels (the
+// level rises when a sub-step solve fails).  Sub-step k is the full-step map with dt/K and
+// the vector potential of the step at the fractions k/K and (k+1)/K of it,
+// A(s) = (1 - s) A^n + s A^{n+1} (the interpolant the orbit discrete gradient uses),
+// grad phi^{n+1/2} and U^{n+1/2} unchanged; it starts where the previous one ended, from
+// the previous v_out.  The particle deposits the mean of its sub-step orbit currents,
+// (1/K) sum_k q v_out,k S-bar_k / dV, which keeps the particle work of the sub-steps equal
+// to the mesh work of the deposit; its accepted orbit velocity is the mean of the sub-step
+// v_out.  Rare work: one wave per flagged workgroup of the main pass (one lane per
+// particle), fields from global memory, fixed-point deposits straight to the accumulator.
+
+// Nearest node j0 (wrapped into [0, n)) and offset f0 of position x, as the main pass
+// takes them; false for a non-finite or far-off position.
+template <int D, class R>
+__device__ __forceinline__ bool locate(const Mesh& M, const double x[3], int j0[3], R f0[3]) {
+  bool ok = true;
+#pragma unroll
+  for (int l = 0; l < 3; ++l) {
+    j0[l] = 0;
+    f0[l] = R(0);
+  }
+#pragma unroll
+  for (int l = 0; l < D; ++l) {
+    const double xi = (x[l] - M.lo[l]) * M.inv_h[l];
+    ok = ok && isfinite(xi) && fabs(xi) < 1.0e8;
+    const double jr = ok ? floor(xi + 0.5) : 0.0;
+    j0[l] = ok ? wrapi((int)jr, M.n[l]) : 0;
+    f0[l] = ok ? (R)(xi - jr) : R(0);
+  }
+  return ok;
+}
+
+// A(j / 2^refine_levels): A^n, A^{n+1}, or an interpolant of the potentials pass.
+__device__ __forceinline__ const double* sub_potential(const OrbitArgs& a, int j) {
+  if (j == 0) return a.An;
+  if (j == (1 << a.refine_levels)) return a.Anp1;
+  return a.Ab + (int64_t)(j - 1) * 3 * a.M.Ng;
+}
+
+// The refinement of the particles of main-pass workgroup b (all 64 lanes call it).
+template <int D, int SH, int NGL, class R>
+__device__ void refine_block(const OrbitArgs& a, int64_t b, int lane, const R* gx, const R* gw) {
+  const Mesh& M = a.M;
+  const int64_t ps = a.ps;
+  const int64_t i = b * kOrbitBlock + lane;
+  const int st = i < a.np ? a.rstate[i] : 0;
+  int lv = st & 0xff;
+  const int ev0 = st >> 8;  // evaluations of a failed full-step attempt in this pass
+  const bool act = lv > 0;
+  const R* Pp = static_cast<const R*>(a.P);
+  const R* qp = static_cast<const R*>(a.q);
+  const R* vinp = static_cast<const R*>(a.vin);
+  R q = R(0), P0[3] = {R(0), R(0), R(0)}, w0[3] = {R(0), R(0), R(0)};
+  double x0[3] = {0.0, 0.0, 0.0};
+  if (act) {
+    q = qp[i];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      P0[c] = Pp[c * ps + i];
+      w0[c] = vinp[c * ps + i];
+    }
+#pragma unroll
+    for (int l = 0; l < D; ++l) x0[l] = a.x[l * ps + i];
+  }
+  Tile t;  // no LDS tile: every gather and deposit goes through global memory
+#pragma unroll
+  for (int l = 0; l < 3; ++l) {
+    t.o[l] = 0;
+    t.E[l] = 1;
+  }
+  t.nodes = 0;
+  t.ok = 0;
+  t.joff = 0;
+  t.goff = 0;
+
+  // per sub-step of the accepted level: v_in, v_out, the chain-rule part
+  // (A^+ - A^-) - dt_k D v_in and -v_out . grad-phi-bar
+  constexpr int KM = 1 << kMaxRefine;
+  R svin[KM][3];
+  double svout[KM][3], swra[KM][3], swgp[KM];
+  bool ok = false, xlim = false;
+  int evals = 0, segs = 0, K = 1;
+  double kin = 0.0, xend[3] = {0.0, 0.0, 0.0};
+  R Pend[3] = {R(0), R(0), R(0)};
+  const R kap2 = R(a.kappa) * R(a.kappa);
+  for (int L = 1; L <= a.refine_levels; ++L) {
+    const bool run = act && !ok && lv <= L;
+    if (__ballot(run) == 0) continue;
+    const int KL = 1 << L;
+    const int stride = (1 << a.refine_levels) >> L;
+    OrbitArgs as = a;
+    as.dt = a.dt / KL;
+    double xk[3] = {x0[0], x0[1], x0[2]};
+    R Pk[3] = {P0[0], P0[1], P0[2]}, warm[3] = {w0[0], w0[1], w0[2]};
+    bool okL = run;
+    xlim = false;
+    for (int k = 0; k < KL; ++k) {
+      as.An = sub_potential(a, k * stride);
+      as.Anp1 = sub_potential(a, (k + 1) * stride);
+      if (!okL) continue;
+      int j0[3];
+      R f0[3];
+      const bool valid = locate<D, R>(M, xk, j0, f0);
+      R Am[3] = {R(0), R(0), R(0)};
+      if (valid) interp3<D, SH, R>(as, t, D, j0, f0, Am);
+      PConst<R> pc;
+      pc.q = q;
+      {
+        R u2 = R(0);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          const R u = (Pk[c] - q * Am[c]) * rcp_(fabs(q) * R(a.kappa));
+          u2 += u * u;
+        }
+        pc.gpn = sqrt_(R(1) + u2);
+      }
+      R vin[3] = {warm[0], warm[1], warm[2]};
+      bool conv = false;
+      for (int it = 1; it <= a.max_inner; ++it) {
+        const R vn2 = vin[0] * vin[0] + vin[1] * vin[1] + vin[2] * vin[2];
+        const bool okv = valid && isfinite(vn2);
+        bool inr = true;
+#pragma unroll
+        for (int l = 0; l < D; ++l) inr = inr && fabs(R(as.dt) * vin[l] * R(M.inv_h[l])) < R(kMaxCross - 1);
+        xlim = okv && !inr;
+        if (!okv || !inr) break;
+        EvalOut<R> o;
+        evaluate<D, SH, NGL, R>(as, t, gx, gw, j0, f0, Pk, pc, Am, vin, o);
+        ++evals;
+        segs += o.nseg;
+        const R vo2 = o.vout[0] * o.vout[0] + o.vout[1] * o.vout[1] + o.vout[2] * o.vout[2];
+        if (!isfinite(vo2) || !(vo2 < kap2)) break;  // finite and subluminal
+        R dmax = R(0), vmax = R(0);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          dmax = fmax(dmax, fabs(o.vout[c] - vin[c]));
+          vmax = fmax(vmax, fabs(o.vout[c]));
+        }
+        if (dmax <= R(a.tol_abs) + R(a.tol_rel) * vmax) {
+          conv = true;
+          double wg = 0.0;
+#pragma unroll
+          for (int c = 0; c < 3; ++c) {
+            double d = 0.0;
+#pragma unroll
+            for (int j = 0; j < D; ++j) d += (double)o.Dm[c][j] * (double)vin[j];
+            svin[k][c] = vin[c];
+            svout[k][c] = (double)o.vout[c];
+            swra[k][c] = ((double)o.Ap[c] - (double)Am[c]) - as.dt * d;
+            wg -= svout[k][c] * (double)o.gp[c];
+            Pk[c] = o.Pn1[c];
+            warm[c] = o.vout[c];
+          }
+          swgp[k] = wg;
+#pragma unroll
+          for (int l = 0; l < D; ++l) xk[l] = xk[l] + as.dt * (double)vin[l];
+          if (k == KL - 1) {
+            const double m = fabs((double)q);
+            const double p2 =
+                (double)o.pn1[0] * o.pn1[0] + (double)o.pn1[1] * o.pn1[1] + (double)o.pn1[2] * o.pn1[2];
+            const double gmm = sqrt(1.0 + p2 / (m * m * a.kappa * a.kappa));
+            kin = p2 / (m * (gmm + 1.0));
+          }
+          break;
+        }
+#pragma unroll
+        for (int c = 0; c < 3; ++c) vin[c] = o.vout[c];
+      }
+      okL = conv;
+    }
+    if (run && okL) {
+      ok = true;
+      K = KL;
+      lv = L;
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        xend[c] = xk[c];
+        Pend[c] = Pk[c];
+      }
+    } else if (run) {
+      lv = L + 1;
+    }
+  }
+
+  // deposit of the accepted sub-steps, with the U-bar gathers of the diagnostics
+  double ra2 = 0.0, wk = 0.0;
+  {
+    double xd[3] = {x0[0], x0[1], x0[2]};
+    const double dtK = a.dt / K;
+    for (int k = 0; k < (1 << a.refine_levels); ++k) {
+      const bool dep = ok && k < K;
+      if (__ballot(dep) == 0) break;
+      int j0[3] = {0, 0, 0};
+      R f0[3] = {R(0), R(0), R(0)}, del[3] = {R(0), R(0), R(0)};
+      double coef[3] = {0.0, 0.0, 0.0};
+      if (dep) {
+        locate<D, R>(M, xd, j0, f0);
+#pragma unroll
+        for (int l = 0; l < D; ++l) del[l] = R(dtK) * svin[k][l] * R(M.inv_h[l]);
+        const double qv = (double)q / (M.dV * K);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) coef[c] = qv * svout[k][c];
+      }
+      R Ub[3];
+      deposit_phase<D, SH, NGL, R>(a, t, gx, gw, j0, f0, del, dep, coef, Ub);
+      if (dep) {
+        double w = swgp[k];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          const double r = swra[k][c] - dtK * (double)Ub[c];
+          ra2 += r * r;
+          w -= svout[k][c] * (double)Ub[c];
+        }
+        wk += w / K;
+#pragma unroll
+        for (int l = 0; l < D; ++l) xd[l] = xd[l] + dtK * (double)svin[k][l];
+      }
+    }
+  }
+  if (act) {
+    if (ok) {
+      R* vp = static_cast<R*>(a.v);
+      R* Pnp = static_cast<R*>(a.Pn);
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        double vs = 0.0;
+        for (int k = 0; k < K; ++k) vs += svout[k][c];
+        vp[c * ps + i] = (R)(vs / K);
+        Pnp[c * ps + i] = Pend[c];
+      }
+#pragma unroll
+      for (int l = 0; l < D; ++l) a.xn[l * ps + i] = wrap_pos(xend[l], M.lo[l], M.len[l]);
+    }
+    a.rstate[i] = lv;  // the settled level (refine_levels + 1 after a failure)
+    if (a.iters) a.iters[i] = ev0 + evals;
+  }
+  // the wave's sums join the main pass's partials of workgroup b, in a fixed order
+  double part[kOrbitParts];
+#pragma unroll
+  for (int v = 0; v < kOrbitParts; ++v) part[v] = 0.0;
+  if (act) {
+    part[OP_FAIL] = ok ? 0.0 : 1.0;
+    part[OP_ITERS] = (double)evals;
+    part[OP_ITMAX] = (double)(ev0 + evals);
+    part[OP_SEGS] = (double)segs;
+    part[OP_XLIM] = (!ok && xlim) ? 1.0 : 0.0;
+    part[OP_REFINED] = ok ? 1.0 : 0.0;
+    if (ok) {
+      part[OP_KIN] = kin;
+      part[OP_WORK] = (double)q * wk;
+      part[OP_RA2] = ra2;
+    }
+  }
+  double v[16];
+#pragma unroll
+  for (int k = 0; k < 16; ++k) v[k] = (k < kOrbitParts && k != OP_ITMAX) ? part[k] : 0.0;
+  const double tot = wave_reduce_scatter<16>(v, lane);
+  const double itmax = wave_reduce_f64<true>(part[OP_ITMAX]);
+  const int idx = wave_slot<16>(lane);
+  if (wave_owner<16>(lane) && idx < kOrbitParts) {
+    double* p = a.partials + (int64_t)idx * a.pstride + b;
+    *p = idx == OP_ITMAX ? fmax(*p, itmax) : *p + tot;
+  }
+}
+
+// One wave per workgroup; each takes 64 block flags of the main pass at a time and
+// refines the flagged blocks one after another.
+template <int D, int SH, int NGL, class R>
+__global__ __launch_bounds__(kOrbitBlock) void k_refine(OrbitArgs a, int64_t nblocks) {
+  if (a.stop && *a.stop) return;
+  const int lane = threadIdx.x;
+  constexpr int NQ = NGL > 0 ? NGL : kMaxGL;
+  R gx[NQ], gw[NQ];
+#pragma unroll
+  for (int k = 0; k < NQ; ++k) {
+    gx[k] = (R)a.glx[k];
+    gw[k] = (R)a.glw[k];
+  }
+  for (int64_t c0 = (int64_t)blockIdx.x * 64; c0 < nblocks; c0 += (int64_t)gridDim.x * 64) {
+    const int64_t bb = c0 + lane;
+    uint64_t m = __ballot(bb < nblocks && a.rblock[bb] != 0);
+    while (m != 0) {
+      const int bit = __ffsll((long long)m) - 1;
+      m &= m - 1;
+      refine_block<D, SH, NGL, R>(a, c0 + bit, lane, gx, gw);
+    }
+  }
+}
+
+// A(j / kmax) = (1 - s) A^n + s A^{n+1} at the interior fractions j = 1 .. kmax - 1.
+__global__ void k_refine_potentials(const double* An, const double* Anp1, double* Ab, int64_t n3, int kmax,
+                                    const int32_t* stop) {
+  if (stop && *stop) return;
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n3) return;
+  const double a0 = An[e], a1 = Anp1[e];
+  for (int j = 1; j < kmax; ++j) {
+    const double s = (double)j / (double)kmax;
+    Ab[(int64_t)(j - 1) * n3 + e] = (1.0 - s) * a0 + s * a1;
+  }
+}
+
+__global__ void k_refine_reset(int32_t* rstate, int64_t np) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < np) rstate[i] = 0;
+}
+
 template <int D, int SH, int NGL, class R>
 hipError_t launch_k(const OrbitArgs& a, unsigned blocks, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
-  if (e0 || e1)
-    hipExtLaunchKernelGGL((k_orbit<D, SH, NGL, R>), dim3(blocks), dim3(kOrbitBlock), tile_bytes<D>(), s, e0, e1, 0u,
-                          a);
+  if (!a.rstate) {
+    if (e0 || e1)
+      hipExtLaunchKernelGGL((k_orbit<D, SH, NGL, R, false>), dim3(blocks), dim3(kOrbitBlock), tile_bytes<D>(), s, e0,
+                            e1, 0u, a);
+    else
+      hipLaunchKernelGGL((k_orbit<D, SH, NGL, R, false>), dim3(blocks), dim3(kOrbitBlock), tile_bytes<D>(), s, a);
+    return hipGetLastError();
+  }
+  // with refinement: the main pass, the interpolated potentials, the refinement pass (a
+  // timed launch spans all three)
+  if (e0)
+    hipExtLaunchKernelGGL((k_orbit<D, SH, NGL, R, true>), dim3(blocks), dim3(kOrbitBlock), tile_bytes<D>(), s, e0,
+                          nullptr, 0u, a);
   else
-    hipLaunchKernelGGL((k_orbit<D, SH, NGL, R>), dim3(blocks), dim3(kOrbitBlock), tile_bytes<D>(), s, a);
+    hipLaunchKernelGGL((k_orbit<D, SH, NGL, R, true>), dim3(blocks), dim3(kOrbitBlock), tile_bytes<D>(), s, a);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const int kmax = 1 << a.refine_levels;
+  if (kmax > 1) {
+    const int64_t n3 = 3 * a.M.Ng;
+    hipLaunchKernelGGL(k_refine_potentials, dim3((unsigned)((n3 + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, a.An,
+                       a.Anp1, a.Ab, n3, kmax, a.stop);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  const int64_t chunks = ((int64_t)blocks + 63) / 64;
+  const unsigned rg = (unsigned)(chunks < 2048 ? chunks : 2048);
+  if (e1)
+    hipExtLaunchKernelGGL((k_refine<D, SH, NGL, R>), dim3(rg), dim3(kOrbitBlock), 0, s, nullptr, e1, 0u, a,
+                          (int64_t)blocks);
+  else
+    hipLaunchKernelGGL((k_refine<D, SH, NGL, R>), dim3(rg), dim3(kOrbitBlock), 0, s, a, (int64_t)blocks);
   return hipGetLastError();
 }
 
@@ -1263,6 +1615,12 @@ hipError_t launch_d(const OrbitArgs& a, unsigned blocks, hipStream_t s, hipEvent
 }
 
 }  // namespace
+
+hipError_t launch_refine_reset(int32_t* rstate, int64_t np, hipStream_t s) {
+  if (np <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_refine_reset, dim3((unsigned)((np + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, rstate, np);
+  return hipGetLastError();
+}
 
 hipError_t launch_orbit(const OrbitArgs& a, int ngl, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
   (void)ngl;

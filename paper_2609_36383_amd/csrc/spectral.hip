@@ -463,6 +463,7 @@ __device__ void outer_test(const OuterTest& t) {
   acc[2] = h[OP_ITMAX];
   acc[3] += 1.0;
   acc[10] = h[OP_ITERS];
+  acc[12] = h[OP_REFINED];
   if (h[OP_FAIL] > 0.0) {
     acc[4] = h[OP_FAIL];
     acc[11] = h[OP_XLIM];

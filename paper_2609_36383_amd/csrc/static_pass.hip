@@ -79,6 +79,8 @@ int32_t gmhc_orbit_pass_static(const gmhc_config* cfg, int64_t n, const double* 
   g_static_err.clear();
   if (!cfg || !config_ok(*cfg)) return static_fail(GMHC_EINVAL, "invalid configuration (see gmhc_create)");
   if (cfg->precision != GMHC_FP64) return static_fail(GMHC_EINVAL, "the static orbit pass runs in FP64 only");
+  if (cfg->refine_levels != 0)
+    return static_fail(GMHC_EINVAL, "the static orbit pass has no particle refinement (refine_levels must be 0)");
   if (n < 0 || n > GMHC_STATIC_MAX_PARTICLES)
     return static_fail(GMHC_EINVAL, "particle count " + std::to_string((long long)n) +
                                         " outside 0..GMHC_STATIC_MAX_PARTICLES (" +

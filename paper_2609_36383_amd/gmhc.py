@@ -15,7 +15,7 @@ LIB_PATH = os.path.join(HERE, "libgmhc.so")
 
 OK, EINVAL, ESTATE, ENOMEM, EDEVICE, EINNER, ENOCONV = 0, -1, -2, -3, -4, -5, -6
 HOST, DEVICE = 0, 1
-ABI_VERSION = 4  # layout of the structures below (include/gmhc.h, GMHC_ABI_VERSION)
+ABI_VERSION = 5  # layout of the structures below (include/gmhc.h, GMHC_ABI_VERSION)
 FP64, FP32_BULK = 0, 1
 PICARD, ANDERSON = 0, 1
 FIELD = {"phi": 0, "psi": 1, "A": 2, "U": 3, "rho": 4, "J": 5, "E": 6, "B": 7}
@@ -48,6 +48,7 @@ class Config(C.Structure):
         ("ls_halvings", C.c_int32), ("shape_order", C.c_int32),
         ("deterministic", C.c_int32),
         ("anderson_lambda", C.c_double), ("ls_decrease", C.c_double), ("ls_growth", C.c_double),
+        ("refine_levels", C.c_int32),
     ]
 
 
@@ -55,7 +56,7 @@ class StepReport(C.Structure):
     _fields_ = [("outer_iters", C.c_int32), ("inner_max", C.c_int32), ("inner_mean", C.c_double),
                 ("evaluations", C.c_int64), ("res_rms_ratio", C.c_double), ("res_max_ratio", C.c_double),
                 ("orbit_ms", C.c_double), ("orbit_launches", C.c_int32), ("graph_replays", C.c_int32),
-                ("segments", C.c_int64), ("outer_updates", C.c_int32), ("reserved", C.c_int32)]
+                ("segments", C.c_int64), ("outer_updates", C.c_int32), ("refined", C.c_int32)]
 
 
 class Diag(C.Structure):
@@ -67,7 +68,7 @@ class Diag(C.Structure):
 class PassReport(C.Structure):
     _fields_ = [("failed", C.c_int64), ("inner_max", C.c_int32), ("over_limit", C.c_int32),
                 ("inner_mean", C.c_double), ("evaluations", C.c_int64), ("orbit_ms", C.c_double),
-                ("segments", C.c_int64)]
+                ("segments", C.c_int64), ("refined", C.c_int64)]
 
 
 def _todict(s):
@@ -109,7 +110,7 @@ def load_library(path=LIB_PATH):
         "gmhc_mode_amplitude": ([vp, i32, i32, C.POINTER(i32), dp], i32),
         "gmhc_set_frozen_fields": ([vp, vp, vp, vp, vp, i32], i32),
         "gmhc_orbit_pass_frozen": ([vp, i32, C.POINTER(PassReport)], i32),
-        "gmhc_read_pass": ([vp, vp, vp, vp, vp, i32], i32),
+        "gmhc_read_pass": ([vp, vp, vp, vp, vp, vp, i32], i32),
         "gmhc_state_bytes": ([vp, C.POINTER(C.c_size_t)], i32),
         "gmhc_save": ([vp, vp, C.c_size_t, i32], i32),
         "gmhc_load": ([vp, vp, C.c_size_t, i32], i32),
@@ -139,7 +140,7 @@ def make_config(dim, n, lo, length, dt, kappa=1.0, sigma1=1.0, sigma2=1.0, gl_or
                 tol_outer_rel=1e-12, tol_inner_abs=1e-14, tol_inner_rel=1e-12, max_outer=80,
                 max_inner=64, beta=1.0, timing=0, graphs=0, outer_scheme=0, anderson_m=4,
                 anderson_start=2, ls_halvings=6, anderson_lambda=1e-12, ls_decrease=1e-4, ls_growth=1.2,
-                shape_order=2, deterministic=1):
+                shape_order=2, deterministic=1, refine_levels=0):
     c = Config()
     c.dim = dim
     for i in range(3):
@@ -155,6 +156,7 @@ def make_config(dim, n, lo, length, dt, kappa=1.0, sigma1=1.0, sigma2=1.0, gl_or
     c.anderson_lambda, c.ls_decrease, c.ls_growth = anderson_lambda, ls_decrease, ls_growth
     c.shape_order = shape_order
     c.deterministic = deterministic
+    c.refine_levels = refine_levels
     return c
 
 
@@ -316,19 +318,18 @@ class Simulation:
             self.stream.wait_stream(self.torch.cuda.current_stream(self.device))
             self._chk(self.lib.gmhc_load(self.h, C.c_void_p(image.data_ptr()), image.numel(), DEVICE), "gmhc_load")
 
-    def read_pass(self, iters=False, current=True):
-        """v_out, P^{n+1} and J (None unless current) of the last frozen pass, and with
-        iters the per-particle evaluation counts."""
+    def read_pass(self, iters=False, current=True, levels=False):
+        """v_out, P^{n+1} and J (None unless current) of the last frozen pass, then with
+        iters the per-particle evaluation counts and with levels the refinement levels."""
         vout = np.zeros((3, self.np))
         Pn1 = np.zeros((3, self.np))
         J = np.zeros((3, self.ng)) if current else None
         it = np.zeros(self.np, dtype=np.int32) if iters else None
-        self._chk(self.lib.gmhc_read_pass(self.h, vout.ctypes.data_as(C.c_void_p),
-                                          Pn1.ctypes.data_as(C.c_void_p),
-                                          J.ctypes.data_as(C.c_void_p) if current else None,
-                                          it.ctypes.data_as(C.c_void_p) if iters else None,
-                                          HOST), "gmhc_read_pass")
-        return (vout, Pn1, J, it) if iters else (vout, Pn1, J)
+        lv = np.zeros(self.np, dtype=np.int32) if levels else None
+        ptr = lambda a: a.ctypes.data_as(C.c_void_p) if a is not None else None
+        self._chk(self.lib.gmhc_read_pass(self.h, ptr(vout), ptr(Pn1), ptr(J), ptr(it), ptr(lv), HOST),
+                  "gmhc_read_pass")
+        return (vout, Pn1, J) + ((it,) if iters else ()) + ((lv,) if levels else ())
 
 
 def orbit_pass_static(cfg, x, P, q, vin, gradphi, An, Anp1, Uh, vout, Pnp1, xnp1, J, iterate=False,

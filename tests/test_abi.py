@@ -52,6 +52,20 @@ def test_host_validation():
         hh = C.c_void_p()
         assert lib.gmhc_create(C.byref(c), C.byref(hh)) == G.OK, det
         lib.gmhc_destroy(hh)
+    # refine_levels closes the structure (the compiler pads it to a multiple of 8)
+    assert G.Config.refine_levels.offset == G.Config.ls_growth.offset + 8
+    assert C.sizeof(G.Config) == G.Config.refine_levels.offset + 8
+    for rl in range(4):
+        c = G.make_config(2, (16, 16), (0, 0), (3.2, 3.2), 0.05, refine_levels=rl)
+        hh = C.c_void_p()
+        assert lib.gmhc_create(C.byref(c), C.byref(hh)) == G.OK, rl
+        n1, n2 = C.c_size_t(), C.c_size_t()
+        assert lib.gmhc_workspace_bytes(hh, 1000, C.byref(n1)) == G.OK
+        lib.gmhc_destroy(hh)
+        if rl:  # the refinement buffers are only taken when it is on
+            assert n1.value > n0.value
+        else:
+            n0 = n1
     bad = [
         dict(sigma1=2.0),                 # sigma1 != kappa^2 sigma2
         dict(dt=0.0),
@@ -68,6 +82,8 @@ def test_host_validation():
         dict(shape_order=3),
         dict(shape_order=-1),
         dict(deterministic=2),
+        dict(refine_levels=-1),
+        dict(refine_levels=4),
     ]
     for over in bad:
         kw = dict(dim=2, n=(16, 16), lo=(0, 0), length=(3.2, 3.2), dt=0.05)

@@ -142,3 +142,14 @@ def test_refined_steps_conserve_energy():
     s0.initialize()
     st, _ = s0.step(raise_on_error=False)
     assert st == O.EINNER
+
+
+def test_failure_at_every_level_is_reported():
+    """1D, an inner limit of 8: some particles fail with two and four sub-steps too; they
+    count as failed and carry level refine_levels + 1, the others their accepted level."""
+    dim, dt = 1, 0.3
+    c = _frozen_case(dim, 2000, 6.0, dt, seed=9)
+    r = _sim(c, dim, dt, refine_levels=2, max_inner=8).orbit_pass(c["gphi"], c["An"], c["Anp1"], c["Uh"], c["v"],
+                                                                   iterate=True)
+    assert r["nfail"] > 0 and np.count_nonzero(r["level"] == 3) == r["nfail"]
+    assert set(np.unique(r["level"])) == {0, 1, 2, 3}
