@@ -274,7 +274,9 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="mixed2d")
-    ap.add_argument("--sort-every", type=int, default=10)
+    ap.add_argument("--sort-every", type=int, default=1,
+                    help="steps between particle sorts (1: every step, which keeps the workgroups' "
+                         "particles within a cell or two and pays for itself at these sizes)")
     ap.add_argument("--gl-order", type=int, default=0)
     ap.add_argument("--shape", type=int, choices=(1, 2), default=2,
                     help="particle-shape B-spline degree: 2 quadratic (the paper's), 1 linear")
@@ -316,7 +318,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"{args.workload}: {'x'.join(map(str, w['n']))} mesh, {r['npart']} particles, "
                                f"{w['ppc']} per cell, dt {w['dt']}, GL{r['ngl']} per knot segment"
-                               + ("" if args.shape == 2 else ", linear B-spline shape"),
+                               + ("" if args.shape == 2 else ", linear B-spline shape")
+                               + f", particles sorted every {args.sort_every} step(s)",
                    "global_batch": r["npart"], "seq_len": None, "parallelism": "single GPU"},
     }
     for k in ("particle_steps_per_s", "outer_iters_mean", "evaluations_per_particle_step", "energy_drift",

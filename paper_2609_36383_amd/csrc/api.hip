@@ -418,6 +418,9 @@ int32_t sort_particles(gmhc_ctx* ctx) {
   a.idx = ctx->ridx;
   a.idx2 = ctx->ridx2;
   a.rcount = ctx->rcount;
+  for (int l = 0; l < 3; ++l) a.v[l] = ctx->vb[l];
+  a.prec = ctx->prec;
+  a.dt = ctx->cfg.dt;
   HIPCK(sort_by_cell(a, ctx->scan_tmp, ctx->scan_tmp_bytes, ctx->stream));
   for (int l = 0; l < d; ++l) std::swap(ctx->x[l], ctx->x2[l]);
   for (int l = 0; l < 3; ++l) {

@@ -386,6 +386,12 @@ struct SortArgs {
   int32_t* idx;           // [np]
   int32_t* idx2;          // [np]
   int32_t* rcount;        // [radix_count_ints(np)] digit counts and scan block sums
+  // radix sort: within a cell, the particles whose orbit under the accepted velocity v
+  // (bulk type, prec) stays inside one knot interval come first, those that cross a knot
+  // after them, so the waves of one cell mostly walk one orbit segment or mostly two
+  const void* v[3];
+  int prec;
+  double dt;
 };
 hipError_t sort_by_cell(const SortArgs& a, void* scan_tmp, size_t scan_tmp_bytes, hipStream_t s);
 size_t sort_scan_tmp_bytes(int64_t Ng);

@@ -220,18 +220,25 @@ __global__ __launch_bounds__(kBlock) void k_radix_scatter(const int32_t* key_in,
   }
 }
 
+// Radix-sort key: 2 * cell + (the orbit x + s dt v, s in [0, 1], crosses a knot of the
+// particle shape: a half-integer node offset for S_2, a node for S_1).
 __global__ __launch_bounds__(kBlock) void k_cell_key_only(SortArgs a) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= a.np) return;
   int64_t mul = 1, gg = 0;
+  bool cross = false;
   for (int l = 0; l < a.M.d; ++l) {
     const double xi = (a.x[l][i] - a.M.lo[l]) * a.M.inv_h[l];
     double r = floor(xi + 0.5);
     if (!(r > -1.0e9 && r < 1.0e9)) r = 0.0;
     gg += (int64_t)wrapi((int)r, a.M.n[l]) * mul;
     mul *= a.M.n[l];
+    const double del = a.dt * ld_bulk(a.v[l], i, a.prec) * a.M.inv_h[l];
+    const double k = a.M.shape == 1 ? floor(xi) : r - 0.5;  // knot at or below the point
+    const double e = xi + del;
+    cross = cross || e < k || e > k + 1.0;
   }
-  a.key[i] = (int32_t)gg;
+  a.key[i] = (int32_t)(2 * gg + (cross ? 1 : 0));
 }
 
 // dst[c][i] = src[c][perm[i]] for every moved array, and the particle ids likewise.
@@ -287,7 +294,7 @@ hipError_t sort_by_cell(const SortArgs& a, void* scan_tmp, size_t scan_tmp_bytes
   if (a.stable) {
     const unsigned pb = (unsigned)((a.np + kBlock - 1) / kBlock);
     hipLaunchKernelGGL(k_cell_key_only, dim3(pb), dim3(kBlock), 0, s, a);
-    const int kb = key_bits(a.M.Ng);
+    const int kb = key_bits(2 * a.M.Ng);
     const int passes = (kb + kRadixMaxBits - 1) / kRadixMaxBits;
     const int per = (kb + passes - 1) / passes;
     const int64_t ntiles = (a.np + kRadixTile - 1) / kRadixTile;

@@ -137,27 +137,31 @@ def test_shape_order_out_of_range_rejected():
 
 def test_linear_tsi_0p1_through_t60():
     """The r = 1 run of the spline-degree comparison: TSI-0.1 at full size (32^3,
-    655,360 particles) with the paper's Anderson controls through T = 60.  Every step's
-    particle solves converge at the full step (the paper's r = 1 run needs its local
-    refinement from t = 53.9 on; the library has no refinement, so a failed solve would
-    fail the step), and the energy change stays within ten outer relative tolerances."""
+    655,360 particles) with the paper's Anderson controls and particle refinement (two and
+    four sub-steps) through T = 60.  The energy change stays within ten outer relative
+    tolerances.  The paper's r = 1 run first refines at t = 53.9; the step of the first
+    refinement here, if any, is printed."""
     import math
     from oracle import closed_forms as CF
     from test_gpu_paper_runs import _load
     G = _gpu()
     w = W.spec("tsi", dt=0.1, eig_gamma=CF.gamma_two_stream(0.25, 0.9, math.pi / 4))
     base = W.config_dict(w)
-    sim = G.Simulation(G.config_from_dict(base, gl_order=0, shape_order=1, outer_scheme=1, beta=0.5),
-                       w["num_particles"])
+    sim = G.Simulation(G.config_from_dict(base, gl_order=0, shape_order=1, outer_scheme=1, beta=0.5,
+                                          refine_levels=2), w["num_particles"])
     _load(sim, w)
-    drift = 0.0
+    drift, first, refined = 0.0, None, 0
     for s in range(600):
-        sim.step()
+        _, rep = sim.step()
+        if rep["refined"] and first is None:
+            first = s + 1
+        refined = max(refined, rep["refined"])
         d = sim.diagnostics()
         drift = max(drift, abs(d["energy_rel"]))
         if (s + 1) % 100 == 0:
             _say(f"linear shape TSI-0.1 step {s + 1}: t {d['t']:.1f} max energy change {drift:.2e} "
-                 f"E_x mode 1 {sim.mode_amplitude('E', 0, (1, 0, 0)):.4e}")
+                 f"E_x mode 1 {sim.mode_amplitude('E', 0, (1, 0, 0)):.4e}; first refined step {first}, "
+                 f"most particles refined in a step {refined}")
     sim.close()
     assert abs(d["t"] - 60.0) < 1e-9
     assert drift <= 10.0 * base["tol_outer_rel"]
