@@ -262,7 +262,7 @@ def run_case(args, w, fp32, parts, tol_of_fp32=None):
             "bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
             "traffic": measured_traffic(args.workload, "fp32" if fp32 else "fp64", sh),
             "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE x2.0 + WRITE_SIZE x1.0)",
-            "kernel": f"k_orbit<{d},{sh},{ngl},{'float' if fp32 else 'double'}>", "launch_ms": launch_s * 1e3,
+            "kernel": f"k_orbit<{d}, {sh}, {ngl}, {'float' if fp32 else 'double'}, false>", "launch_ms": launch_s * 1e3,
             "flops_per_launch": flops_launch, "hbm_bytes_per_launch": bytes_launch,
             "hbm_achieved_gbs": gbs, "hbm_frac": gbs / PEAK_HBM_GBS,
         })

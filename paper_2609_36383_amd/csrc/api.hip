@@ -54,6 +54,7 @@ struct gmhc_ctx {
   int32_t* ridx = nullptr;
   int32_t* ridx2 = nullptr;
   int32_t* rcount = nullptr;
+  int32_t* xcount = nullptr;  // knot-crossing particles counted by the sort
   // refinement (refine_levels > 0): per-particle level within the step, per-workgroup
   // flags of the orbit pass, and the interpolated vector potentials of the sub-steps
   int32_t* rstate = nullptr;
@@ -229,6 +230,7 @@ size_t carve(gmhc_ctx* c, char* base, int64_t np) {
   c->ridx = cv.take<int32_t>(N);
   c->ridx2 = cv.take<int32_t>(N);
   c->rcount = cv.take<int32_t>((size_t)radix_count_ints(np));
+  c->xcount = cv.take<int32_t>((size_t)cross_count_ints());
   const int rl = c->cfg.refine_levels;
   if (rl > 0) c->rstate = cv.take<int32_t>(N);
   c->tacc = cv.take<double>((size_t)(d + 6) * Ng);
@@ -421,6 +423,7 @@ int32_t sort_particles(gmhc_ctx* ctx) {
   for (int l = 0; l < 3; ++l) a.v[l] = ctx->vb[l];
   a.prec = ctx->prec;
   a.dt = ctx->cfg.dt;
+  a.xcount = ctx->xcount;
   HIPCK(sort_by_cell(a, ctx->scan_tmp, ctx->scan_tmp_bytes, ctx->stream));
   for (int l = 0; l < d; ++l) std::swap(ctx->x[l], ctx->x2[l]);
   for (int l = 0; l < 3; ++l) {

@@ -386,15 +386,17 @@ struct SortArgs {
   int32_t* idx;           // [np]
   int32_t* idx2;          // [np]
   int32_t* rcount;        // [radix_count_ints(np)] digit counts and scan block sums
-  // radix sort: within a cell, the particles whose orbit under the accepted velocity v
-  // (bulk type, prec) stays inside one knot interval come first, those that cross a knot
-  // after them, so the waves of one cell mostly walk one orbit segment or mostly two
+  // radix sort: the particles whose orbit under the accepted velocity v (bulk type, prec)
+  // crosses a knot follow the others, within each cell or (where they are dense) after all
+  // of them, so most waves walk one orbit segment and the rest two; xcount [1]: their count
   const void* v[3];
   int prec;
   double dt;
+  int32_t* xcount;         // [cross_count_ints()]
 };
 hipError_t sort_by_cell(const SortArgs& a, void* scan_tmp, size_t scan_tmp_bytes, hipStream_t s);
 size_t sort_scan_tmp_bytes(int64_t Ng);
 int64_t radix_count_ints(int64_t np);
+int cross_count_ints();
 
 }  // namespace gmhc

@@ -220,13 +220,11 @@ __global__ __launch_bounds__(kBlock) void k_radix_scatter(const int32_t* key_in,
   }
 }
 
-// Radix-sort key: 2 * cell + (the orbit x + s dt v, s in [0, 1], crosses a knot of the
-// particle shape: a half-integer node offset for S_2, a node for S_1).
-__global__ __launch_bounds__(kBlock) void k_cell_key_only(SortArgs a) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= a.np) return;
+// Nearest-node cell of particle i, and whether its orbit x + s dt v, s in [0, 1], crosses
+// a knot of the particle shape (a half-integer node offset for S_2, a node for S_1).
+__device__ __forceinline__ int64_t cell_and_cross(const SortArgs& a, int64_t i, bool& cross) {
   int64_t mul = 1, gg = 0;
-  bool cross = false;
+  cross = false;
   for (int l = 0; l < a.M.d; ++l) {
     const double xi = (a.x[l][i] - a.M.lo[l]) * a.M.inv_h[l];
     double r = floor(xi + 0.5);
@@ -238,7 +236,52 @@ __global__ __launch_bounds__(kBlock) void k_cell_key_only(SortArgs a) {
     const double e = xi + del;
     cross = cross || e < k || e > k + 1.0;
   }
-  a.key[i] = (int32_t)(2 * gg + (cross ? 1 : 0));
+  return gg;
+}
+
+// Particles whose orbit crosses a knot: each workgroup adds its count to one of
+// kCrossSlots counters (a.xcount[1 ..]), spread so that the atomics do not queue on one
+// address; k_cross_total sums them into a.xcount[0].
+constexpr int kCrossSlots = 256;
+__global__ __launch_bounds__(kBlock) void k_cross_count(SortArgs a) {
+  __shared__ int32_t wsum[kBlock / 64];
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  bool cross = false;
+  if (i < a.np) (void)cell_and_cross(a, i, cross);
+  const uint64_t m = __ballot(cross);
+  if ((threadIdx.x & 63) == 0) wsum[threadIdx.x / 64] = (int32_t)__popcll(m);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int32_t t = 0;
+    for (int w = 0; w < kBlock / 64; ++w) t += wsum[w];
+    if (t) atomicAdd(a.xcount + 1 + (blockIdx.x % kCrossSlots), t);
+  }
+}
+
+__global__ __launch_bounds__(kCrossSlots) void k_cross_total(int32_t* xcount) {
+  __shared__ int32_t sh[kCrossSlots];
+  sh[threadIdx.x] = xcount[1 + threadIdx.x];
+  __syncthreads();
+  for (int off = kCrossSlots / 2; off > 0; off >>= 1) {
+    if ((int)threadIdx.x < off) sh[threadIdx.x] += sh[threadIdx.x + off];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) xcount[0] = sh[0];
+}
+
+// Radix-sort key.  Where knot-crossing particles are dense (at least kDenseCross per cell
+// on average), they follow all the others: key = cell + Ng (crossing) or cell, so whole
+// waves walk two segments or one, and the crossing waves still hold a cell or two.  Where
+// they are sparse, grouping them would spread a wave over many cells; they follow the
+// others within their own cell instead: key = 2 cell + (crossing).
+constexpr int kDenseCross = 16;
+__global__ __launch_bounds__(kBlock) void k_cell_key_only(SortArgs a) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= a.np) return;
+  bool cross = false;
+  const int64_t gg = cell_and_cross(a, i, cross);
+  const bool dense = (int64_t)*a.xcount >= (int64_t)kDenseCross * a.M.Ng;
+  a.key[i] = (int32_t)(dense ? gg + (cross ? a.M.Ng : 0) : 2 * gg + (cross ? 1 : 0));
 }
 
 // dst[c][i] = src[c][perm[i]] for every moved array, and the particle ids likewise.
@@ -278,6 +321,8 @@ __global__ __launch_bounds__(kBlock) void k_scatter(SortArgs a) {
 
 }  // namespace
 
+int cross_count_ints() { return 1 + kCrossSlots; }
+
 size_t sort_scan_tmp_bytes(int64_t Ng) {
   const int64_t nb = (Ng + kScanBlock - 1) / kScanBlock;
   return sizeof(int32_t) * (size_t)(nb + 1);
@@ -293,6 +338,10 @@ hipError_t sort_by_cell(const SortArgs& a, void* scan_tmp, size_t scan_tmp_bytes
   if (a.np <= 0) return hipSuccess;
   if (a.stable) {
     const unsigned pb = (unsigned)((a.np + kBlock - 1) / kBlock);
+    hipError_t e = hipMemsetAsync(a.xcount, 0, sizeof(int32_t) * (1 + kCrossSlots), s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_cross_count, dim3(pb), dim3(kBlock), 0, s, a);
+    hipLaunchKernelGGL(k_cross_total, dim3(1), dim3(kCrossSlots), 0, s, a.xcount);
     hipLaunchKernelGGL(k_cell_key_only, dim3(pb), dim3(kBlock), 0, s, a);
     const int kb = key_bits(2 * a.M.Ng);
     const int passes = (kb + kRadixMaxBits - 1) / kRadixMaxBits;
