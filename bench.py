@@ -265,6 +265,9 @@ def run_case(args, w, fp32, parts, tol_of_fp32=None):
             "kernel": f"k_orbit<{d}, {sh}, {ngl}, {'float' if fp32 else 'double'}, false>", "launch_ms": launch_s * 1e3,
             "flops_per_launch": flops_launch, "hbm_bytes_per_launch": bytes_launch,
             "hbm_achieved_gbs": gbs, "hbm_frac": gbs / PEAK_HBM_GBS,
+            # the published FP32 peak counts packed instructions, which this build does not
+            # emit; non-packed FP32 issues at the FP64 rate
+            **({"frac_of_nonpacked_fp32": achieved / (PEAK_FP32_VALU_TFLOPS / 2)} if fp32 else {}),
         })
 
 
