@@ -953,16 +953,22 @@ __device__ __forceinline__ int tile_to_global(const Mesh& M, const Tile& t, int 
 }
 
 // Occupancy target (waves per SIMD) the register allocator works to, chosen per
-// instantiation by measurement: the FP32 kernels of 1D and 2D fit three waves with
-// little spilling and gain from it; the others run best at two.
-template <int D, class R>
-constexpr int orbit_waves() { return (sizeof(R) == 4 && D <= 2) ? 3 : 2; }
+// instantiation by measurement: 1D at its least exact Gauss-Legendre order runs short
+// launches whose time is latency, and fits three waves in FP64 and four in FP32 without
+// spilling; the other FP32 kernels of 1D and 2D fit three with little spilling; 2D FP64,
+// 3D and the other 1D FP64 kernels run best at two.
+template <int D, int SH, int NGL, class R>
+constexpr int orbit_waves() {
+  const bool fp32 = sizeof(R) == 4;
+  if (D == 1 && NGL == (SH == 1 ? 1 : 2)) return fp32 ? 4 : 3;
+  return (fp32 && D <= 2) ? 3 : 2;
+}
 
 // REF: refinement is on (a.rstate set); the kernel then hands the particles whose
 // full-step solve fails, and those refined earlier in the step, to the refinement pass.
 template <int D, int SH, int NGL, class R, bool REF>
 __global__ __launch_bounds__(kOrbitBlock)
-__attribute__((amdgpu_waves_per_eu(orbit_waves<D, R>()))) void k_orbit(OrbitArgs a) {
+__attribute__((amdgpu_waves_per_eu(orbit_waves<D, SH, NGL, R>()))) void k_orbit(OrbitArgs a) {
   if (a.stop && *a.stop) return;  // the outer iteration this pass belongs to is done
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const Mesh& M = a.M;
