@@ -36,34 +36,27 @@ PEAK_FP64_VALU_TFLOPS = 78.6
 TIMING_EVERY = 4
 
 
-def _support(shape):
-    """Nodes per axis in the support of the shape at a point, and flops per axis of its
-    1D weights and derivatives: 3 and 10 for the quadratic S_2, 2 and 3 for the linear
-    S_1 (whose derivatives are constants on a knot segment)."""
-    return (3, 10) if shape == 2 else (2, 3)
-
-
 def flops_per_eval(d, seg_mean, ngl, shape=2):
-    """Algorithmic flops of one orbit evaluation (FMA = 2).
+    """Algorithmic flops of one orbit evaluation (FMA = 2, a square root or a divide = 1).
 
-    Per Gauss-Legendre point: 1D weights and derivatives (10 per axis for S_2), the
-    time blend (3), and per support node (3^d for S_2, 2^d for S_1): tensor weights
-    d-1 + d(d-1), grad-phi gather 2d, D gather 3(3 + 2d), quadrature weight 1.  Per
-    evaluation add the endpoint interpolant A^+ (support (d - 1 + 6) + 6d) and the push,
-    HC rotation, secant velocity and inner test (250).
+    Quadratic shape S_2 (3 support nodes per axis), per Gauss-Legendre point:
+    - gathers, per support node: grad phi (d), the D_i A sums of A^n and A^{n+1} (6d) and
+      the S-bar accumulation of the orbit current (1), so 2 * 3^d * (7d + 1);
+    - weights: 1D values and derivatives (20 per axis), their tensor products (0, 27, 120
+      for d = 1, 2, 3) and the time blend (6 per axis).
+    Per evaluation: seg * n_GL points, the endpoint interpolant A^+ (2 * 3 * 3^d gathers
+    plus one point's weights without the blend) and the push, HC rotation, secant
+    velocity and inner test (250).  The deposit is the S-bar term of the gathers.
+
+    The linear shape S_1 counts the same terms over 2 nodes per axis, with 6 flops per
+    axis for its 1D weights (values only; the derivatives are constant on a knot segment)
+    and 0, 12, 44 tensor products.
     """
-    k, wf = _support(shape)
-    node = (d - 1) + d * (d - 1) + 2 * d + 3 * (3 + 2 * d) + 1
-    point = wf * d + 3 + (k ** d) * node
-    endpoint = (k ** d) * (d - 1 + 6) + 6 * d
+    k, w1 = (3, 20) if shape == 2 else (2, 6)
+    tensor = ((0, 27, 120) if shape == 2 else (0, 12, 44))[d - 1]
+    point = 2 * k ** d * (7 * d + 1) + w1 * d + tensor + 6 * d
+    endpoint = 2 * 3 * k ** d + w1 * d + tensor
     return seg_mean * ngl * point + endpoint + 250
-
-
-def deposit_flops(d, seg_mean, ngl, shape=2):
-    """Flops of the deposit sweep (once per converged particle per launch)."""
-    k, wf = _support(shape)
-    point = wf * d + (k ** d) * d
-    return seg_mean * ngl * point + (k ** d) * (3 * 2 + 3 * 2)
 
 
 def bytes_per_particle(d, bulk=8):
@@ -244,8 +237,7 @@ def run_case(args, w, fp32, parts, tol_of_fp32=None):
     ng = int(np.prod(w["n"]))
     seg_mean = segs / max(evals, 1)  # measured knot-split segments per evaluation
     # flops of the timed launches (evaluations per launch of the timed steps)
-    flops_launch = (timed_evals / max(timed_launches, 1)) * flops_per_eval(d, seg_mean, ngl, sh) + \
-        npart * deposit_flops(d, seg_mean, ngl, sh)
+    flops_launch = (timed_evals / max(timed_launches, 1)) * flops_per_eval(d, seg_mean, ngl, sh)
     bytes_launch = npart * bytes_per_particle(d, 4 if fp32 else 8) + ng * bytes_per_node(d)
     launch_s = (orbit_ms / max(timed_launches, 1)) * 1e-3
     peak = PEAK_FP32_VALU_TFLOPS if fp32 else PEAK_FP64_VALU_TFLOPS
