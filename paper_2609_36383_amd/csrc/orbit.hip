@@ -48,6 +48,14 @@ constexpr int kHalo = 1;               // tile halo in nodes (the stencil reach)
 template <int D>
 constexpr int tile_bytes() { return D == 3 ? 18 * 1024 : 8 * 1024; }
 
+// FP64 2D quadratic at its default Gauss order keeps the row-independent quadrature
+// values of each segment (Gauss point offsets and factors, hence its x weights) across
+// the stencil rows; the particle constants then wait in LDS (PARK) instead of registers.
+template <int D, int SH, int NGL, class R>
+constexpr bool orbit_park() {
+  return D == 2 && SH == 2 && NGL == 3 && sizeof(R) == 8;
+}
+
 // i mod n for a mesh size n (a power of two; two's complement makes this the
 // non-negative residue for negative i too)
 __device__ __forceinline__ int wrapi(int i, int n) { return i & (n - 1); }
@@ -180,21 +188,35 @@ __device__ __forceinline__ void bw(R f, R w[3], R dw[3]) {
     dw[1] = R(-1);
     dw[2] = R(1);
   } else {
-    const R a = R(0.5) - f, b = R(0.5) + f;
+    // w2 - w0 = f: one addition instead of a square
+    const R a = R(0.5) - f;
     w[0] = R(0.5) * a * a;
     w[1] = R(0.75) - f * f;
-    w[2] = R(0.5) * b * b;
+    w[2] = w[0] + f;
     dw[0] = -a;
     dw[1] = R(-2.0) * f;
-    dw[2] = b;
+    dw[2] = R(0.5) + f;
   }
 }
-// weight and derivative of the single stencil node c (0, 1, 2)
-template <int SH, class R>
+// weight and derivative of the single stencil node c (0, 1, 2).  SHORT (for stencil rows
+// known at compile time): the S_2 outer nodes take their pieces directly, since f lies
+// within half a node of the base node (|f| <= 1/2 up to rounding) and so the offsets
+// f + 1 and f - 1 of nodes 0 and 2 are positive and negative.  Otherwise the piece is
+// chosen by |offset|, which costs fewer registers when c is a run-time value.
+template <int SH, bool SHORT, class R>
 __device__ __forceinline__ void bw1(R f, int c, R& w, R& dw) {
   if constexpr (SH == 1) {
     w = c == 0 ? R(0) : (c == 1 ? R(1) - f : f);
     dw = c == 0 ? R(0) : (c == 1 ? R(-1) : R(1));
+  } else if constexpr (SHORT) {
+    if (c == 1) {
+      w = R(0.75) - f * f;
+      dw = R(-2.0) * f;
+    } else {
+      const R g = c == 0 ? R(0.5) - f : R(0.5) + f;
+      w = R(0.5) * g * g;
+      dw = c == 0 ? -g : g;
+    }
   } else {
     const R t = f - R(c - 1);  // offset from node j + c - 1
     const R at = fabs(t);
@@ -204,6 +226,10 @@ __device__ __forceinline__ void bw1(R f, int c, R& w, R& dw) {
     dw = c == 1 ? R(-2.0) * t : -sg * o;
   }
 }
+
+// The short form where it does not raise register use: FP64 with rows unrolled (d < 3).
+template <int D, class R>
+constexpr bool kShortW = D < 3 && sizeof(R) == 8;
 
 // Stencil rows and columns that carry weight: all three per axis for S_2, the upper two
 // (nodes j and j+1) for S_1.  Rows of the 3^(d-1) row layout are visited as
@@ -360,6 +386,22 @@ __device__ __forceinline__ void eval_segment(const OrbitArgs& a, const Tile& t, 
   // 1D and 2D rows at a compile-time GL order are unrolled (the y weights specialise
   // per row); 3D and the runtime order keep a loop
   constexpr int kRowUnroll = (D < 3 && NGL > 0) ? NROW : 1;
+  // FP64 2D has registers for the row-independent quadrature factors w_q, w_q (1 - s_q)
+  // and w_q s_q of its unrolled rows; elsewhere they are recomputed per row
+  constexpr bool kHoist = orbit_park<D, SH, NGL, R>();
+  constexpr int NH = kHoist ? NGL : 1;
+  R hw[NH], ha[NH], hb[NH], hx[NH], hy[NH];
+  if (kHoist) {
+#pragma unroll
+    for (int q = 0; q < NH; ++q) {
+      const R s = sa + len * gx[q];
+      hw[q] = len * gw[q];
+      hb[q] = hw[q] * s;
+      ha[q] = hw[q] - hb[q];
+      hx[q] = fs[0] + s * del[0];
+      hy[q] = fs[1] + s * del[1];
+    }
+  }
 #pragma unroll kRowUnroll
   for (int row = 0; row < NROW; ++row) {
     const int cy = D > 1 ? RB + row % RW : 0, cz = D > 2 ? RB + row / RW : 0;
@@ -384,13 +426,21 @@ __device__ __forceinline__ void eval_segment(const OrbitArgs& a, const Tile& t, 
 #pragma unroll
     for (int q = 0; q < nq; ++q) {
       const R s = sar + len * gx[q];
-      const R wq = len * gw[q];
-      const R b1 = wq * s, a1 = wq - b1;  // w_q s and w_q (1 - s)
+      R wq, b1, a1;  // w_q, w_q s and w_q (1 - s)
+      if (kHoist) {
+        wq = hw[q];
+        b1 = hb[q];
+        a1 = ha[q];
+      } else {
+        wq = len * gw[q];
+        b1 = wq * s;
+        a1 = wq - b1;
+      }
       R wx[3], dwx[3];
-      bw<SH>(fs[0] + s * del[0], wx, dwx);
+      bw<SH>(kHoist ? hx[q] : fs[0] + s * del[0], wx, dwx);
       R wy = R(1), dwy = R(0), wz = R(1), dwz = R(0);
-      if (D > 1) bw1<SH>(fs[1] + s * del[1], cy, wy, dwy);
-      if (D > 2) bw1<SH>(fs[2] + s * del[2], cz, wz, dwz);
+      if (D > 1) bw1<SH, kShortW<D, R>>(kHoist ? hy[q] : fs[1] + s * del[1], cy, wy, dwy);
+      if (D > 2) bw1<SH, kShortW<D, R>>(fs[2] + s * del[2], cz, wz, dwz);
       const R wyz = wy * wz;
       const R sw = wq * wyz, xw0 = a1 * wyz, xw1 = b1 * wyz;
       const R yz = dwy * wz, zy = wy * dwz;
@@ -436,6 +486,7 @@ struct EvalOut {
   R Pn1[3];
   R pn1[3];
   R Ap[3];
+  R dA[3];  // A^+ - A^-
   R gp[3];
   R Dm[3][3];
   int nseg;
@@ -450,10 +501,28 @@ struct PConst {
   R gpn;
 };
 
+// Particle constants parked in LDS (PARK): P^n, A^-, q and the gamma of p^n, value k of
+// lane l at s_dyn[park + 64 k] with park = (LDS offset of the block) + l.  They are read
+// back after the segment quadrature, so no registers hold them across it.
+constexpr int kParkVals = 8;
+
+template <class R>
+__device__ __forceinline__ void park_store(int park, const R P[3], const R Am[3], const PConst<R>& pc) {
+  HIP_DYNAMIC_SHARED(double, s_dyn);
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    s_dyn[park + 64 * c] = (double)P[c];
+    s_dyn[park + 64 * (3 + c)] = (double)Am[c];
+  }
+  s_dyn[park + 64 * 6] = (double)pc.q;
+  s_dyn[park + 64 * 7] = (double)pc.gpn;
+}
+
 // One orbit evaluation of one particle.
-template <int D, int SH, int NGL, class R>
+template <int D, int SH, int NGL, class R, bool PARK = false>
 __device__ void evaluate(const OrbitArgs& a, const Tile& t, const R* gx, const R* gw, const int j0[3], const R* f0,
-                         const R P[3], const PConst<R>& pc, const R Am[3], const R vin[3], EvalOut<R>& o) {
+                         const R Pa[3], const PConst<R>& pca, const R Ama[3], const R vin[3], EvalOut<R>& o,
+                         int park = 0) {
   const Mesh& M = a.M;
   R del[3] = {R(0), R(0), R(0)};
 #pragma unroll
@@ -480,6 +549,29 @@ __device__ void evaluate(const OrbitArgs& a, const Tile& t, const R* gx, const R
     const R ih = R(M.inv_h[j]);
 #pragma unroll
     for (int l = 0; l < 3; ++l) Dm[l][j] *= ih;
+  }
+
+  // the particle constants, from LDS when parked (the opaque offset keeps the reads here)
+  R P[3], Am[3];
+  PConst<R> pc;
+  if constexpr (PARK) {
+    HIP_DYNAMIC_SHARED(double, s_dyn);
+    int off = park;
+    asm volatile("" : "+v"(off));
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      P[c] = (R)s_dyn[off + 64 * c];
+      Am[c] = (R)s_dyn[off + 64 * (3 + c)];
+    }
+    pc.q = (R)s_dyn[off + 64 * 6];
+    pc.gpn = (R)s_dyn[off + 64 * 7];
+  } else {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      P[c] = Pa[c];
+      Am[c] = Ama[c];
+    }
+    pc = pca;
   }
 
   // endpoint interpolant A^+ = A_h^{n+1}(x^n + dt v_in)
@@ -555,6 +647,7 @@ __device__ void evaluate(const OrbitArgs& a, const Tile& t, const R* gx, const R
     o.Pn1[c] = Pn1[c];
     o.pn1[c] = pn1[c];
     o.Ap[c] = Ap[c];
+    o.dA[c] = Ap[c] - Am[c];
     o.gp[c] = gp[c];
 #pragma unroll
     for (int j = 0; j < 3; ++j) o.Dm[c][j] = Dm[c][j];
@@ -902,8 +995,8 @@ __device__ void deposit_phase(const OrbitArgs& a, const Tile& t, const R* gx, co
         R wx[3], dwx[3];
         bw<SH>(fs[0] + s * del[0], wx, dwx);
         R wy = R(1), dwy, wz = R(1), dwz;
-        if (D > 1) bw1<SH>(fs[1] + s * del[1], cy, wy, dwy);
-        if (D > 2) bw1<SH>(fs[2] + s * del[2], cz, wz, dwz);
+        if (D > 1) bw1<SH, kShortW<D, R>>(fs[1] + s * del[1], cy, wy, dwy);
+        if (D > 2) bw1<SH, kShortW<D, R>>(fs[2] + s * del[2], cz, wz, dwz);
         const R sw = wq * wy * wz;
 #pragma unroll
         for (int c = kC0<SH>; c < 3; ++c) S[c] += sw * wx[c];
@@ -964,6 +1057,12 @@ constexpr int orbit_waves() {
   return (fp32 && D <= 2) ? 3 : 2;
 }
 
+// dynamic LDS of one orbit-pass workgroup: the tile, then the park block
+template <int D, int SH, int NGL, class R>
+constexpr int orbit_lds() {
+  return tile_bytes<D>() + (orbit_park<D, SH, NGL, R>() ? kParkVals * 64 * 8 : 0);
+}
+
 // REF: refinement is on (a.rstate set); the kernel then hands the particles whose
 // full-step solve fails, and those refined earlier in the step, to the refinement pass.
 template <int D, int SH, int NGL, class R, bool REF>
@@ -975,6 +1074,8 @@ __attribute__((amdgpu_waves_per_eu(orbit_waves<D, SH, NGL, R>()))) void k_orbit(
   const int64_t ps = a.ps;
   HIP_DYNAMIC_SHARED(double, s_dyn);
   constexpr int NF = nfields<D>();
+  constexpr bool kPark = orbit_park<D, SH, NGL, R>();
+  constexpr int kParkBase = tile_bytes<D>() / 8;  // the park block follows the tile
   const R* Pp = static_cast<const R*>(a.P);
   const R* qp = static_cast<const R*>(a.q);
   const R* vinp = static_cast<const R*>(a.vin);
@@ -1132,6 +1233,7 @@ __attribute__((amdgpu_waves_per_eu(orbit_waves<D, SH, NGL, R>()))) void k_orbit(
       }
       pc.gpn = sqrt_(R(1) + u2);
     }
+    if (kPark) park_store<R>(kParkBase + (int)threadIdx.x, P0, Am, pc);
     int it = 0, segs = 0;
     bool xlim = false;  // the orbit reached the supported knot-crossing range
     const int maxit = a.iterate ? a.max_inner : 1;
@@ -1147,7 +1249,7 @@ __attribute__((amdgpu_waves_per_eu(orbit_waves<D, SH, NGL, R>()))) void k_orbit(
       xlim = okv && !inr;
       if (!okv || !inr) break;
       EvalOut<R> o;
-      evaluate<D, SH, NGL, R>(a, t, gx, gw, j0, f0, P, pc, Am, vin, o);
+      evaluate<D, SH, NGL, R, kPark>(a, t, gx, gw, j0, f0, P, pc, Am, vin, o, kParkBase + (int)threadIdx.x);
       segs += o.nseg;
       const R vo2 = o.vout[0] * o.vout[0] + o.vout[1] * o.vout[1] + o.vout[2] * o.vout[2];
       if (!isfinite(vo2) || !(vo2 < kap2)) break;  // finite and subluminal
@@ -1165,11 +1267,11 @@ __attribute__((amdgpu_waves_per_eu(orbit_waves<D, SH, NGL, R>()))) void k_orbit(
           double d = 0.0;
 #pragma unroll
           for (int j = 0; j < D; ++j) d += (double)o.Dm[c][j] * (double)vin[j];
-          wra[c] = ((double)o.Ap[c] - (double)Am[c]) - a.dt * d;
+          wra[c] = (kPark ? (double)o.dA[c] : (double)o.Ap[c] - (double)Am[c]) - a.dt * d;
           vout[c] = (double)o.vout[c];
           wgp -= vout[c] * (double)o.gp[c];
         }
-        const double m = fabs((double)pc.q);
+        const double m = fabs(kPark ? s_dyn[kParkBase + threadIdx.x + 64 * 6] : (double)pc.q);
         const double p2 = (double)o.pn1[0] * o.pn1[0] + (double)o.pn1[1] * o.pn1[1] + (double)o.pn1[2] * o.pn1[2];
         const double gmm = sqrt(1.0 + p2 / (m * m * a.kappa * a.kappa));
         kin = p2 / (m * (gmm + 1.0));
@@ -1571,21 +1673,22 @@ __global__ void k_refine_reset(int32_t* rstate, int64_t np) {
 
 template <int D, int SH, int NGL, class R>
 hipError_t launch_k(const OrbitArgs& a, unsigned blocks, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
+  constexpr unsigned kLds = orbit_lds<D, SH, NGL, R>();
   if (!a.rstate) {
     if (e0 || e1)
-      hipExtLaunchKernelGGL((k_orbit<D, SH, NGL, R, false>), dim3(blocks), dim3(kOrbitBlock), tile_bytes<D>(), s, e0,
+      hipExtLaunchKernelGGL((k_orbit<D, SH, NGL, R, false>), dim3(blocks), dim3(kOrbitBlock), kLds, s, e0,
                             e1, 0u, a);
     else
-      hipLaunchKernelGGL((k_orbit<D, SH, NGL, R, false>), dim3(blocks), dim3(kOrbitBlock), tile_bytes<D>(), s, a);
+      hipLaunchKernelGGL((k_orbit<D, SH, NGL, R, false>), dim3(blocks), dim3(kOrbitBlock), kLds, s, a);
     return hipGetLastError();
   }
   // with refinement: the main pass, the interpolated potentials, the refinement pass (a
   // timed launch spans all three)
   if (e0)
-    hipExtLaunchKernelGGL((k_orbit<D, SH, NGL, R, true>), dim3(blocks), dim3(kOrbitBlock), tile_bytes<D>(), s, e0,
+    hipExtLaunchKernelGGL((k_orbit<D, SH, NGL, R, true>), dim3(blocks), dim3(kOrbitBlock), kLds, s, e0,
                           nullptr, 0u, a);
   else
-    hipLaunchKernelGGL((k_orbit<D, SH, NGL, R, true>), dim3(blocks), dim3(kOrbitBlock), tile_bytes<D>(), s, a);
+    hipLaunchKernelGGL((k_orbit<D, SH, NGL, R, true>), dim3(blocks), dim3(kOrbitBlock), kLds, s, a);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   const int kmax = 1 << a.refine_levels;
