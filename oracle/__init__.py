@@ -111,6 +111,8 @@ def lib():
         L.orc_spd_solve.argtypes = [C.c_int, dp, dp, dp]
         L.orc_num_particles.argtypes = [C.c_void_p]
         L.orc_num_particles.restype = C.c_int64
+        L.orc_tangent_run.argtypes = [cfgp, C.c_int64, dp, dp, dp, C.c_int, dp, dp, dp, C.c_int, dp, dp,
+                                      C.POINTER(C.c_int64)]
         _lib = L
     return _lib
 
@@ -366,3 +368,28 @@ class OracleSim:
             raise OracleError(EINVAL, "orbit_pass: level_in outside 0..refine_levels")
         return {"vout": vout, "Pnp1": Pn1, "J": J, "iters": iters, "nfail": int(nfail), "level": level,
                 "vin": vinc, "xend": xend}
+
+
+def tangent_run(cfg, x, u, q, steps, dx=None, du=None, dq=None):
+    """Forward-mode derivatives of a 1D run (gmhc_tangent.cpp): from the initial particles
+    x [N], u [3][N], q [N] and the seed directions dx [nd][N], du [nd][3][N], dq [nd][N]
+    (None: zero; nd <= 16), run ``steps`` steps.  Returns (E, dE, outer): E = (W0, K0, WT,
+    KT), the field and kinetic energies at the start and at the end, dE [4][nd] their
+    derivatives along each direction, and the outer map evaluations of the run."""
+    x = _f64(x).ravel()
+    n = x.size
+    u = _f64(u).reshape(3, n)
+    q = _f64(q).ravel()
+    nd = max(int(np.shape(a)[0]) for a in (dx, du, dq) if a is not None) if any(
+        a is not None for a in (dx, du, dq)) else 0
+    dx = _f64(np.zeros((nd, n)) if dx is None else dx).reshape(nd, n)
+    du = _f64(np.zeros((nd, 3, n)) if du is None else du).reshape(nd, 3, n)
+    dq = _f64(np.zeros((nd, n)) if dq is None else dq).reshape(nd, n)
+    E = np.zeros(4)
+    dE = np.zeros((4, max(nd, 1)))
+    outer = C.c_int64(0)
+    st = lib().orc_tangent_run(C.byref(cfg), n, _p(x), _p(u), _p(q), nd, _p(dx), _p(du), _p(dq), int(steps),
+                               _p(E), _p(dE), C.byref(outer))
+    if st != OK:
+        raise OracleError(st, "tangent_run")
+    return E, dE[:, :nd], outer.value
