@@ -13,7 +13,8 @@
 // The iterations are differentiated by running them to convergence with the derivatives
 // carried along: the inner Picard loop of each particle and the outer damped-Picard loop
 // on the mesh current stop only when the values pass the run's tests AND the derivative
-// parts have settled to the relative tolerance of the same tests.  The derivative of a
+// parts have settled (to the relative tolerance of the same tests, or to their rounding
+// floor, see settled()).  The derivative of a
 // contracting fixed-point iteration converges to the derivative of its fixed point
 // (implicit-function theorem), so the result is the derivative of the converged step,
 // independent of the iteration history.
@@ -28,6 +29,7 @@
 #include <cmath>
 #include <complex>
 #include <cstdint>
+#include <limits>
 #include <vector>
 
 #include "orc_config.h"
@@ -348,18 +350,25 @@ void orbit_eval(const Ctx& C, const TrialFields& F, const Part& p, const Dn vin[
   for (int c = 0; c < 3; ++c) vout[c] = 0.5 * (vEm[c] + vEp[c]);
 }
 
-// Largest |derivative| over three components, per direction, and the settle test of the
-// derivative parts: max_c |a.d - b.d| <= tol max_c |a.d| for every direction.
-bool settled(const Dn* a, const Dn* b, int n, double tol) {
+// Settle test of the derivative parts of an iteration a = map(b): per direction, the
+// change D = max_c |a.d - b.d| against the scale S = max_c |a.d|.  A direction has settled
+// when D <= tol S, or when D has stopped contracting (D > prev / 2, with prev its change
+// one iteration earlier): the iteration contracts by a fixed factor far below 1/2 until
+// the rounding of the terms that make up the derivative is reached, so a change that no
+// longer halves is that rounding floor (where the derivative is a small difference of
+// larger terms, the floor lies above tol S).  prev holds kMaxDir changes (start: +inf).
+bool settled(const Dn* a, const Dn* b, int n, double tol, double* prev) {
+  bool all = true;
   for (int k = 0; k < ND; ++k) {
     double dmax = 0.0, smax = 0.0;
     for (int c = 0; c < n; ++c) {
       dmax = std::max(dmax, std::fabs(a[c].d[k] - b[c].d[k]));
       smax = std::max(smax, std::fabs(a[c].d[k]));
     }
-    if (dmax > tol * smax) return false;
+    if (!(dmax <= tol * smax || dmax > 0.5 * prev[k])) all = false;
+    prev[k] = dmax;
   }
-  return true;
+  return all;
 }
 
 // Inner Picard loop of one particle (Algorithm 1, inner solve) until the values pass the
@@ -367,6 +376,8 @@ bool settled(const Dn* a, const Dn* b, int n, double tol) {
 // the last evaluation, vout, Pn1 and dep its results.
 bool inner_solve(const Ctx& C, const TrialFields& F, const Part& p, Dn vin[3], Dn vout[3], Dn Pn1[3], Dep& dep) {
   const orc_config& c = C.cfg;
+  double prev[kMaxDir];
+  std::fill(prev, prev + kMaxDir, std::numeric_limits<double>::infinity());
   for (int it = 0; it < 4 * c.max_inner; ++it) {
     dep.w.clear();
     orbit_eval(C, F, p, vin, vout, Pn1, &dep);
@@ -379,7 +390,8 @@ bool inner_solve(const Ctx& C, const TrialFields& F, const Part& p, Dn vin[3], D
       finite = finite && std::isfinite(vout[k].v);
     }
     if (!finite || !(std::sqrt(v2) < c.kappa)) return false;
-    if (dmax <= c.tol_inner_abs + c.tol_inner_rel * vmax && settled(vout, vin, 3, c.tol_inner_rel)) return true;
+    const bool dset = settled(vout, vin, 3, c.tol_inner_rel, prev);
+    if (dmax <= c.tol_inner_abs + c.tol_inner_rel * vmax && dset) return true;
     for (int k = 0; k < 3; ++k) vin[k] = vout[k];
   }
   return false;
@@ -490,6 +502,8 @@ int step(const Ctx& C, State& S, std::vector<Part>& parts, int64_t& outer) {
   std::vector<std::array<Dn, 3>> vw(np);
   for (int64_t i = 0; i < np; ++i)
     for (int c = 0; c < 3; ++c) vw[i][c] = parts[i].vbar[c];
+  double prev[kMaxDir];
+  std::fill(prev, prev + kMaxDir, std::numeric_limits<double>::infinity());
   for (int it = 0; it < 4 * C.cfg.max_outer; ++it) {
     State T;
     TrialFields F;
@@ -522,16 +536,14 @@ int step(const Ctx& C, State& S, std::vector<Part>& parts, int64_t& outer) {
       H[c] = to_real(M, s);
     }
     ++outer;
-    bool conv = outer_pass(C, H, j);
-    if (conv) {
-      std::vector<Dn> hf, jf;
-      for (int c = 0; c < 3; ++c)
-        for (int g = 0; g < M.n; ++g) {
-          hf.push_back(H[c][g]);
-          jf.push_back(j[c][g]);
-        }
-      conv = settled(hf.data(), jf.data(), (int)hf.size(), C.cfg.tol_outer_rel);
-    }
+    std::vector<Dn> hf, jf;
+    for (int c = 0; c < 3; ++c)
+      for (int g = 0; g < M.n; ++g) {
+        hf.push_back(H[c][g]);
+        jf.push_back(j[c][g]);
+      }
+    const bool dset = settled(hf.data(), jf.data(), (int)hf.size(), C.cfg.tol_outer_rel, prev);
+    const bool conv = outer_pass(C, H, j) && dset;
     if (conv) {  // commit (Algorithm 1): fields of j, particles of this evaluation
       S.phi = T.phi;
       S.psi = T.psi;

@@ -12,7 +12,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libgmhc.so")
 BUILD = os.path.join(HERE, "_build")
-SOURCES = ["orbit.hip", "spectral.hip", "sort.hip", "api.hip", "static_pass.hip"]
+SOURCES = ["orbit.hip", "spectral.hip", "sort.hip", "api.hip", "static_pass.hip", "adjoint.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = os.environ.get("GMHC_ARCH", "gfx950")

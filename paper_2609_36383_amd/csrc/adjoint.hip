@@ -1,0 +1,702 @@
+// adjoint.hip -- reverse-mode adjoint of the implicit step and of initialization for
+// one-dimensional runs with the quadratic shape in FP64.
+//
+// The paper defines the step (Algorithm 1) but no derivative of it.  The adjoint here
+// differentiates the converged step, not its iteration history: the step's unknowns
+// (every particle's orbit velocity vbar and the mesh current j) satisfy
+//     vbar_i = F_i(vbar_i; x_i, P_i, q_i, Phi(j))      (inner fixed point, per particle)
+//     j      = H(vbar, x, q)                          (outer fixed point on the mesh)
+// with Phi(j) the trial fields of the CN field step (grad phi^{n+1/2}, A^n, A^{n+1}) and
+// H the projected orbit current.  The outputs are x^{n+1} = x + dt vbar_x, P^{n+1} of
+// the evaluation and the new field state.  By the implicit-function theorem, with
+// cotangents (lx, lP, lf) of the outputs, the adjoint unknowns mu_v (per particle) and
+// mu_j (mesh) solve
+//     mu_v,i = (I - dF_i/dvbar)^-T [ dt lx_i e_x + (dP^{n+1}_i/dvbar)^T lP_i
+//                                    + (dH/dvbar_i)^T mu_j ]
+//     mu_j   = (dState'/dj)^T lf + (dPhi/dj)^T sum_i (dF_i/dPhi)^T mu_v,i
+//                                + (dPhi/dj)^T sum_i (dP^{n+1}_i/dPhi)^T lP_i
+// and the input cotangents follow by one more transposed product.  The per-particle
+// 3x3 system is solved directly (in 1D, F depends on vbar only through vbar_x, so only
+// one column of dF/dvbar is nonzero); the mesh equation is iterated like the outer
+// Picard iteration it transposes, with the same damping, until mu_j settles.
+//
+// Kernels: k_adj_particle (one thread per particle; the hand-written reverse sweep of the
+// orbit gathers, the GM-HC push with its gamma_HC, B_eff and K chain, the secant
+// velocity and the orbit deposit, and the scatter of the field cotangents as exact
+// fixed-point sums), k_adj_field (one thread per Fourier mode; the conjugate transpose of
+// the projected continuity / CN update), k_energy_grad and k_adj_init_field, and small
+// reductions.
+#include <hip/hip_runtime.h>
+#include <math.h>
+
+#include "gmhc_internal.h"
+
+namespace gmhc {
+
+namespace {
+
+// ---- quadratic B-spline S_2 and its first two derivatives --------------------------
+__device__ __forceinline__ double s2(double t) {
+  const double a = fabs(t);
+  if (a < 0.5) return 0.75 - t * t;
+  if (a < 1.5) return 0.5 * (1.5 - a) * (1.5 - a);
+  return 0.0;
+}
+__device__ __forceinline__ double s2d(double t) {
+  const double a = fabs(t);
+  if (a < 0.5) return -2.0 * t;
+  if (a < 1.5) return t > 0.0 ? -(1.5 - a) : (1.5 - a);
+  return 0.0;
+}
+__device__ __forceinline__ double s2dd(double t) {
+  const double a = fabs(t);
+  if (a < 0.5) return -2.0;
+  if (a < 1.5) return 1.0;
+  return 0.0;
+}
+__device__ __forceinline__ int wrapi(int i, int n) { return ((i % n) + n) % n; }
+
+__device__ __forceinline__ void cross3(const double a[3], const double b[3], double o[3]) {
+  o[0] = a[1] * b[2] - a[2] * b[1];
+  o[1] = a[2] * b[0] - a[0] * b[2];
+  o[2] = a[0] * b[1] - a[1] * b[0];
+}
+__device__ __forceinline__ double dot3(const double a[3], const double b[3]) {
+  return a[0] * b[0] + a[1] * b[1] + a[2] * b[2];
+}
+
+// Orbit quantities of one particle: the gathers the evaluation uses, their derivatives
+// with respect to the start x and the displacement dx = dt vbar_x, and the gathers of the
+// adjoint current mu along the orbit (the transpose of the deposit).
+struct Gath {
+  double Gp, D[3], Am[3], Ap[3];
+  double Gp_x, Gp_dx, D_x[3], D_dx[3], Am_x[3], Ap_x[3];
+  double Mc[3], Mx, Mdx;
+};
+
+// Knot-split walk of the orbit xi(s) = xi0 + s dxi, s in [0, 1] (knots of S_2 at
+// half-integer node offsets), calling f(s, wq) at every Gauss-Legendre point.
+template <class Fn>
+__device__ __forceinline__ void walk_orbit(const AdjArgs& a, double xi0, double dxi, Fn&& f) {
+  double sa = 0.0;
+  // next knot strictly ahead of xi0 in the direction of motion
+  double kn = dxi > 0.0 ? floor(xi0 - 0.5) + 1.5 : ceil(xi0 - 0.5) - 0.5;
+  for (int c = 0; c <= kMaxCross + 1; ++c) {
+    double sb = 1.0;
+    if (dxi != 0.0) {
+      const double sk = (kn - xi0) / dxi;
+      if (sk > 0.0 && sk < 1.0) sb = sk;
+    }
+    if (sb > sa) {
+      const double len = sb - sa;
+      for (int k = 0; k < a.ngl; ++k) f(sa + len * a.glx[k], len * a.glw[k]);
+    }
+    if (sb >= 1.0) break;
+    sa = sb;
+    kn += dxi > 0.0 ? 1.0 : -1.0;
+  }
+}
+
+__device__ void gather(const AdjArgs& a, double x, const double v[3], Gath& G) {
+  const Mesh& M = a.M;
+  const int n = M.n[0];
+  const double ih = M.inv_h[0];
+  const double xi0 = (x - M.lo[0]) * ih, dxi = a.dt * v[0] * ih;
+  const int64_t Ng = M.Ng;
+  G = Gath{};
+  walk_orbit(a, xi0, dxi, [&](double s, double wq) {
+    const double xs = xi0 + s * dxi;
+    const int i0 = (int)floor(xs + 0.5);
+    for (int o = -1; o <= 1; ++o) {
+      const double t = xs - (double)(i0 + o);
+      const double S = s2(t), S1 = s2d(t) * ih, S2 = s2dd(t) * ih * ih;
+      const int g = wrapi(i0 + o, n);
+      const double gp = a.gphi[g];
+      G.Gp += wq * S * gp;
+      G.Gp_x += wq * S1 * gp;
+      G.Gp_dx += wq * s * S1 * gp;
+      double vm = 0.0;
+      for (int c = 0; c < 3; ++c) {
+        const double As = (1.0 - s) * a.An[c * Ng + g] + s * a.Anp1[c * Ng + g];
+        G.D[c] += wq * S1 * As;
+        G.D_x[c] += wq * S2 * As;
+        G.D_dx[c] += wq * s * S2 * As;
+        if (a.mu) {
+          const double m = a.mu[c * Ng + g];
+          G.Mc[c] += wq * S * m;
+          vm += v[c] * m;
+        }
+      }
+      G.Mx += wq * S1 * vm;
+      G.Mdx += wq * s * S1 * vm;
+    }
+  });
+  // endpoint interpolants A^n(x) and A^{n+1}(x + dx)
+  for (int e = 0; e < 2; ++e) {
+    const double xs = xi0 + (e ? dxi : 0.0);
+    const double* F = e ? a.Anp1 : a.An;
+    const int i0 = (int)floor(xs + 0.5);
+    for (int o = -1; o <= 1; ++o) {
+      const double t = xs - (double)(i0 + o);
+      const double S = s2(t), S1 = s2d(t) * ih;
+      const int g = wrapi(i0 + o, n);
+      for (int c = 0; c < 3; ++c) {
+        const double f = F[c * Ng + g];
+        (e ? G.Ap : G.Am)[c] += S * f;
+        (e ? G.Ap_x : G.Am_x)[c] += S1 * f;
+      }
+    }
+  }
+}
+
+// Forward values of one evaluation (no-explicit-A_t GM-HC step, mechanical endpoints,
+// electric-work secant velocities) that the reverse sweep needs.
+struct Fwd {
+  double q, m, mk, dt, kappa, v0;
+  double Gp, D[3], Am[3], Ap[3];
+  double Aep[3], kick[3], pm[3], um[3], tau[3], up[3], pp[3], Pn1[3], pn[3], pn1[3];
+  double gm2, sigma, X, R, gHC, t[3], t2, s[3], ustar[3], ut;
+  double vEm[3], vEp[3];
+};
+
+__device__ double gam(const double p[3], double mk) { return sqrt(1.0 + dot3(p, p) / (mk * mk)); }
+
+__device__ void forward(const Gath& G, const double P[3], double q, double m, double v0, double dt, double kappa,
+                        Fwd& f) {
+  f.q = q;
+  f.m = m;
+  f.mk = m * kappa;
+  f.dt = dt;
+  f.kappa = kappa;
+  f.v0 = v0;
+  f.Gp = G.Gp;
+  for (int c = 0; c < 3; ++c) {
+    f.D[c] = G.D[c];
+    f.Am[c] = G.Am[c];
+    f.Ap[c] = G.Ap[c];
+    f.Aep[c] = 0.5 * (G.Am[c] + G.Ap[c]);
+    f.kick[c] = 0.5 * dt * q * G.D[c] * v0 - (c == 0 ? 0.5 * dt * q * G.Gp : 0.0);
+    f.pm[c] = P[c] - q * f.Aep[c] + f.kick[c];
+    f.um[c] = f.pm[c] / f.mk;
+  }
+  const double Beff[3] = {0.0, -G.D[2], G.D[1]};
+  for (int c = 0; c < 3; ++c) f.tau[c] = dt * q / (2.0 * m) * Beff[c];
+  // normalized HC map
+  f.gm2 = 1.0 + dot3(f.um, f.um);
+  const double tau2 = dot3(f.tau, f.tau);
+  f.ut = dot3(f.um, f.tau);
+  f.sigma = f.gm2 - tau2;
+  f.X = tau2 + f.ut * f.ut;
+  f.R = sqrt(f.sigma * f.sigma + 4.0 * f.X);
+  const double g2 = f.sigma >= 0.0 ? 0.5 * (f.sigma + f.R) : 2.0 * f.X / (f.R - f.sigma);
+  f.gHC = sqrt(g2);
+  for (int c = 0; c < 3; ++c) f.t[c] = f.tau[c] / f.gHC;
+  f.t2 = dot3(f.t, f.t);
+  for (int c = 0; c < 3; ++c) f.s[c] = 2.0 * f.t[c] / (1.0 + f.t2);
+  double uxt[3], usxs[3];
+  cross3(f.um, f.t, uxt);
+  for (int c = 0; c < 3; ++c) f.ustar[c] = f.um[c] + uxt[c];
+  cross3(f.ustar, f.s, usxs);
+  for (int c = 0; c < 3; ++c) {
+    f.up[c] = f.um[c] + usxs[c];
+    f.pp[c] = f.mk * f.up[c];
+    f.Pn1[c] = f.pp[c] + q * f.Aep[c] + f.kick[c];
+    f.pn[c] = P[c] - q * f.Am[c];
+    f.pn1[c] = f.Pn1[c] - q * f.Ap[c];
+  }
+  const double gm = gam(f.pm, f.mk), gn = gam(f.pn, f.mk), gn1 = gam(f.pn1, f.mk), gp = gam(f.pp, f.mk);
+  for (int c = 0; c < 3; ++c) {
+    f.vEm[c] = (f.pm[c] + f.pn[c]) / (m * (gm + gn));
+    f.vEp[c] = (f.pn1[c] + f.pp[c]) / (m * (gn1 + gp));
+  }
+}
+
+// Reverse sweep of the secant velocity V(a, b) = (a + b) / (m (gamma(a) + gamma(b))):
+// adds the cotangents of a, b and m for the cotangent fb of V.
+__device__ void vdg_rev(const double pa[3], const double pb[3], const double f[3], double m, double mk,
+                        const double fb[3], double ab[3], double bb[3], double& mb) {
+  const double ga = gam(pa, mk), gb = gam(pb, mk), G = ga + gb;
+  double S[3];
+  for (int c = 0; c < 3; ++c) S[c] = pa[c] + pb[c];
+  const double fs = dot3(fb, S);
+  const double k = fs / (m * G * G);
+  for (int c = 0; c < 3; ++c) {
+    ab[c] += fb[c] / (m * G) - k * pa[c] / (mk * mk * ga);
+    bb[c] += fb[c] / (m * G) - k * pb[c] / (mk * mk * gb);
+  }
+  // m enters through the prefactor 1/m and through gamma: d gamma(a)/dm = -(|a|/mk)^2 / (m gamma(a))
+  const double dga = -dot3(pa, pa) / (mk * mk) / (m * ga), dgb = -dot3(pb, pb) / (mk * mk) / (m * gb);
+  mb += -dot3(fb, f) / m - dot3(fb, f) / G * (dga + dgb);
+}
+
+// Cotangents of the evaluation's inputs for the cotangents wv of v_out and wP of P^{n+1}.
+struct Rev {
+  double Gp, D[3], Am[3], Ap[3];  // gathers
+  double P[3], q, m, v0;          // direct inputs (v0 through the kick only)
+};
+
+__device__ void reverse(const Fwd& f, const double wv[3], const double wP[3], Rev& r) {
+  r = Rev{};
+  const double m = f.m, mk = f.mk, q = f.q, dt = f.dt;
+  double vEb[3], pmb[3] = {}, pnb[3] = {}, pn1b[3] = {}, ppb[3] = {}, Pn1b[3], Aepb[3] = {}, kickb[3] = {};
+  for (int c = 0; c < 3; ++c) {
+    vEb[c] = 0.5 * wv[c];
+    Pn1b[c] = wP[c];
+  }
+  vdg_rev(f.pm, f.pn, f.vEm, m, mk, vEb, pmb, pnb, r.m);
+  vdg_rev(f.pn1, f.pp, f.vEp, m, mk, vEb, pn1b, ppb, r.m);
+  for (int c = 0; c < 3; ++c) {
+    // pn1 = Pn1 - q Ap ; pn = P - q Am
+    Pn1b[c] += pn1b[c];
+    r.Ap[c] -= q * pn1b[c];
+    r.q -= pn1b[c] * f.Ap[c];
+    r.P[c] += pnb[c];
+    r.Am[c] -= q * pnb[c];
+    r.q -= pnb[c] * f.Am[c];
+    // Pn1 = pp + q Aep + kick
+    ppb[c] += Pn1b[c];
+    Aepb[c] += q * Pn1b[c];
+    kickb[c] += Pn1b[c];
+    r.q += Pn1b[c] * f.Aep[c];
+  }
+  // pp = mk up
+  double upb[3];
+  for (int c = 0; c < 3; ++c) upb[c] = mk * ppb[c];
+  r.m += f.kappa * dot3(ppb, f.up);
+  // normalized HC map, reversed: up = um + ustar x s, ustar = um + um x t,
+  // s = 2 t / (1 + |t|^2), t = tau / gamma_HC, gamma_HC^2 = (sigma + R) / 2,
+  // R^2 = sigma^2 + 4 X, X = |tau|^2 + (u.tau)^2, sigma = 1 + |u|^2 - |tau|^2.
+  double umb[3], ustarb[3], sb[3], tb[3], taub[3];
+  for (int c = 0; c < 3; ++c) umb[c] = upb[c];
+  cross3(f.s, upb, ustarb);  // d(ustar x s)/d ustar
+  cross3(upb, f.ustar, sb);  // d(ustar x s)/d s
+  for (int c = 0; c < 3; ++c) umb[c] += ustarb[c];
+  {
+    double a1[3];
+    cross3(f.t, ustarb, a1);  // d(um x t)/d um
+    for (int c = 0; c < 3; ++c) umb[c] += a1[c];
+    cross3(ustarb, f.um, tb);  // d(um x t)/d t
+  }
+  const double den = 1.0 + f.t2, st = dot3(sb, f.t);
+  for (int c = 0; c < 3; ++c) tb[c] += 2.0 * sb[c] / den - 4.0 * st / (den * den) * f.t[c];
+  for (int c = 0; c < 3; ++c) taub[c] = tb[c] / f.gHC;
+  const double gHCb = -dot3(tb, f.t) / f.gHC;
+  const double g2b = gHCb / (2.0 * f.gHC);
+  // d g2 / d sigma = (1 + sigma / R) / 2, written without cancellation for sigma < 0
+  const double dsig = f.sigma >= 0.0 ? 0.5 * (1.0 + f.sigma / f.R) : 2.0 * f.X / (f.R * (f.R - f.sigma));
+  const double sigmab = g2b * dsig;
+  const double Xb = g2b / f.R;
+  double tau2b = Xb - sigmab;
+  const double utb = 2.0 * f.ut * Xb;
+  const double gm2b = sigmab;
+  for (int c = 0; c < 3; ++c) {
+    umb[c] += utb * f.tau[c] + 2.0 * gm2b * f.um[c];
+    taub[c] += utb * f.um[c] + 2.0 * tau2b * f.tau[c];
+  }
+  // tau = (dt q / 2m) B_eff, B_eff = (0, -D_z, D_y)
+  const double Beff[3] = {0.0, -f.D[2], f.D[1]};
+  const double kq = dt * q / (2.0 * m);
+  r.q += dt / (2.0 * m) * dot3(taub, Beff);
+  r.m -= dot3(taub, f.tau) / m;
+  r.D[2] -= kq * taub[1];
+  r.D[1] += kq * taub[2];
+  // um = pm / mk
+  for (int c = 0; c < 3; ++c) pmb[c] += umb[c] / mk;
+  r.m -= dot3(umb, f.um) / m;
+  // pm = P - q Aep + kick
+  for (int c = 0; c < 3; ++c) {
+    r.P[c] += pmb[c];
+    Aepb[c] -= q * pmb[c];
+    kickb[c] += pmb[c];
+    r.q -= pmb[c] * f.Aep[c];
+  }
+  // kick = (dt q / 2) (D v_x - grad-phi-bar e_x)
+  for (int c = 0; c < 3; ++c) {
+    r.D[c] += 0.5 * dt * q * f.v0 * kickb[c];
+    r.v0 += 0.5 * dt * q * f.D[c] * kickb[c];
+    r.q += 0.5 * dt * (f.D[c] * f.v0 - (c == 0 ? f.Gp : 0.0)) * kickb[c];
+  }
+  r.Gp -= 0.5 * dt * q * kickb[0];
+  // Aep = (Am + Ap) / 2
+  for (int c = 0; c < 3; ++c) {
+    r.Am[c] += 0.5 * Aepb[c];
+    r.Ap[c] += 0.5 * Aepb[c];
+  }
+}
+
+// Cotangent of vbar_x (through the kick and through the orbit gathers) and of x.
+__device__ __forceinline__ double rev_v0(const Rev& r, const Gath& G, double dt) {
+  double s = r.Gp * G.Gp_dx;
+  for (int c = 0; c < 3; ++c) s += r.D[c] * G.D_dx[c] + r.Ap[c] * G.Ap_x[c];
+  return r.v0 + dt * s;
+}
+__device__ __forceinline__ double rev_x(const Rev& r, const Gath& G) {
+  double s = r.Gp * G.Gp_x;
+  for (int c = 0; c < 3; ++c) s += r.D[c] * G.D_x[c] + r.Am[c] * G.Am_x[c] + r.Ap[c] * G.Ap_x[c];
+  return s;
+}
+
+}  // namespace
+
+__global__ __launch_bounds__(kBlock) void k_adj_particle(AdjArgs a) {
+  __shared__ double red[kBlock];
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  double bound = 0.0;
+  if (i < a.np) {
+    const Mesh& M = a.M;
+    const int64_t Ng = M.Ng;
+    const double ih = M.inv_h[0];
+    const int64_t li = a.id[i];
+    const double x = a.x[i];
+    const double q = a.q[i], m = fabs(q);
+    double P[3], v[3], lP[3];
+    for (int c = 0; c < 3; ++c) {
+      P[c] = a.P[c * a.ps + i];
+      v[c] = a.vbar[c * a.np + li];
+      lP[c] = a.lP[c * a.np + li];
+    }
+    const double lx = a.lx[li];
+    Gath G;
+    gather(a, x, v, G);
+    Fwd f;
+    forward(G, P, q, m, v[0], a.dt, a.kappa, f);
+    // column x of dF/dvbar (F depends on vbar through vbar_x only)
+    double J[3];
+    Rev r;
+    for (int c = 0; c < 3; ++c) {
+      const double e[3] = {c == 0 ? 1.0 : 0.0, c == 1 ? 1.0 : 0.0, c == 2 ? 1.0 : 0.0}, z[3] = {0.0, 0.0, 0.0};
+      reverse(f, e, z, r);
+      J[c] = rev_v0(r, G, a.dt);
+    }
+    // right side: x^{n+1} = x + dt vbar_x, P^{n+1}(vbar), and the transposed deposit
+    const double z3[3] = {0.0, 0.0, 0.0};
+    reverse(f, z3, lP, r);
+    const double qdv = q / M.dV;
+    double rhs[3];
+    for (int c = 0; c < 3; ++c) rhs[c] = qdv * G.Mc[c];
+    rhs[0] += a.dt * lx + rev_v0(r, G, a.dt) + qdv * a.dt * G.Mdx;
+    double mv[3];
+    mv[1] = rhs[1];
+    mv[2] = rhs[2];
+    mv[0] = (rhs[0] + J[1] * rhs[1] + J[2] * rhs[2]) / (1.0 - J[0]);
+    reverse(f, mv, lP, r);
+    if (a.mode == ADJ_BOUND) {
+      bound = fabs(r.Gp);
+      for (int c = 0; c < 3; ++c) bound += 2.0 * ih * fabs(r.D[c]) + fabs(r.Am[c]) + fabs(r.Ap[c]);
+    } else if (a.mode == ADJ_SCATTER) {
+      const int n = M.n[0];
+      const double xi0 = (x - M.lo[0]) * ih, dxi = a.dt * v[0] * ih;
+      const double up = a.fx_up;
+      walk_orbit(a, xi0, dxi, [&](double s, double wq) {
+        const double xs = xi0 + s * dxi;
+        const int i0 = (int)floor(xs + 0.5);
+        for (int o = -1; o <= 1; ++o) {
+          const double t = xs - (double)(i0 + o);
+          const double S = s2(t), S1 = s2d(t) * ih;
+          const int64_t g = wrapi(i0 + o, n);
+          fix_add(a.acc, g, wq * S * r.Gp, up);
+          for (int c = 0; c < 3; ++c) {
+            fix_add(a.acc, (1 + c) * Ng + g, wq * (1.0 - s) * S1 * r.D[c], up);
+            fix_add(a.acc, (4 + c) * Ng + g, wq * s * S1 * r.D[c], up);
+          }
+        }
+      });
+      for (int e = 0; e < 2; ++e) {
+        const double xs = xi0 + (e ? dxi : 0.0);
+        const int i0 = (int)floor(xs + 0.5);
+        for (int o = -1; o <= 1; ++o) {
+          const double S = s2(xs - (double)(i0 + o));
+          const int64_t g = wrapi(i0 + o, n);
+          for (int c = 0; c < 3; ++c) fix_add(a.acc, ((e ? 4 : 1) + c) * Ng + g, S * (e ? r.Ap[c] : r.Am[c]), up);
+        }
+      }
+    } else {
+      a.gx[li] = lx + rev_x(r, G) + qdv * G.Mx;
+      for (int c = 0; c < 3; ++c) a.gP[c * a.np + li] = r.P[c];
+      a.gq[li] = r.q + (q < 0.0 ? -r.m : r.m) + dot3(v, G.Mc) / M.dV;
+    }
+  }
+  if (a.mode == ADJ_BOUND) {  // per-block sum, fixed order
+    red[threadIdx.x] = bound;
+    __syncthreads();
+    for (int w = kBlock / 2; w > 0; w >>= 1) {
+      if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) a.partials[blockIdx.x] = red[0];
+  }
+}
+
+// ---- mesh side ---------------------------------------------------------------------
+
+namespace {
+__device__ __forceinline__ double2 cadd2(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ double2 csc(double2 a, double s) { return make_double2(a.x * s, a.y * s); }
+// i k * a
+__device__ __forceinline__ double2 cik2(double k, double2 a) { return make_double2(-k * a.y, k * a.x); }
+
+__device__ __forceinline__ void wavevec(const Mesh& M, int64_t g, double k[3], bool& nyq) {
+  int64_t idx[3] = {g & (M.n[0] - 1), (g >> M.ln[0]) & (M.n[1] - 1), g >> (M.ln[0] + M.ln[1])};
+  nyq = false;
+  for (int l = 0; l < 3; ++l) {
+    k[l] = 0.0;
+    if (l >= M.d) continue;
+    const int n = M.n[l];
+    if (idx[l] == n / 2) {
+      nyq = true;
+      continue;
+    }
+    const int64_t ms = idx[l] <= n / 2 ? idx[l] : idx[l] - n;
+    k[l] = M.kf[l] * (double)ms;
+  }
+}
+}  // namespace
+
+
+// Conjugate transpose, mode by mode, of the field step of Algorithm 1: projection of the
+// trial current, continuity rho' = rho - dt i k.jh, the CN pairs
+//   phi' = (c1 phi + dt psi + e1 (rho + rho')) / .. , psi' = 2 (phi' - phi) / dt - psi,
+//   A'   = c1 A + c2 U + e2 jh,                       U'   = 2 (A' - A) / dt - U,
+// and the trial fields i k (phi + phi') / 2, A, A'.  Real coefficients stay; i k becomes -i k.
+__global__ __launch_bounds__(kBlock) void k_adj_field(AdjFieldArgs a) {
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const Mesh& M = a.M;
+  const int64_t Ng = M.Ng;
+  if (g >= Ng) return;
+  const int d = M.d;
+  double k[3];
+  bool nyq;
+  wavevec(M, g, k, nyq);
+  const double h = a.dt;
+  const double av = a.kappa2 * (k[0] * k[0] + k[1] * k[1] + k[2] * k[2]);
+  const double q4 = 0.25 * h * h * av, den = 1.0 + q4;
+  const double c1 = (1.0 - q4) / den, c2 = h / den;
+  const double e1 = 0.25 * h * h * a.kappa2 * a.sigma1 / den, e2 = 0.5 * h * h * a.kappa2 * a.sigma2 / den;
+  const double2 z = make_double2(0.0, 0.0);
+  double2 phb1 = a.Lf[g], psb1 = a.Lf[Ng + g], rhb1 = a.Lf[2 * Ng + g];
+  double2 Ab1[3], Ub1[3], Ab[3] = {z, z, z}, Ub[3] = {z, z, z}, jb[3] = {z, z, z};
+  for (int c = 0; c < 3; ++c) {
+    Ab1[c] = a.Lf[(3 + c) * Ng + g];
+    Ub1[c] = a.Lf[(6 + c) * Ng + g];
+  }
+  double2 phb = z, psb = z, rhb = z;
+  if (a.Pb) {  // trial fields
+    for (int l = 0; l < d; ++l) {
+      const double2 t = csc(cik2(-k[l], a.Pb[l * Ng + g]), 0.5);
+      phb = cadd2(phb, t);
+      phb1 = cadd2(phb1, t);
+    }
+    for (int c = 0; c < 3; ++c) {
+      Ab[c] = cadd2(Ab[c], a.Pb[(d + c) * Ng + g]);
+      Ab1[c] = cadd2(Ab1[c], a.Pb[(d + 3 + c) * Ng + g]);
+    }
+  }
+  for (int c = 0; c < 3; ++c) {  // U' = 2 (A' - A) / h - U
+    Ab1[c] = cadd2(Ab1[c], csc(Ub1[c], 2.0 / h));
+    Ab[c] = cadd2(Ab[c], csc(Ub1[c], -2.0 / h));
+    Ub[c] = cadd2(Ub[c], csc(Ub1[c], -1.0));
+  }
+  for (int c = 0; c < 3; ++c) {  // A' = c1 A + c2 U + e2 jh
+    Ab[c] = cadd2(Ab[c], csc(Ab1[c], c1));
+    Ub[c] = cadd2(Ub[c], csc(Ab1[c], c2));
+    jb[c] = cadd2(jb[c], csc(Ab1[c], e2));
+  }
+  // psi' = 2 (phi' - phi) / h - psi
+  phb1 = cadd2(phb1, csc(psb1, 2.0 / h));
+  phb = cadd2(phb, csc(psb1, -2.0 / h));
+  psb = cadd2(psb, csc(psb1, -1.0));
+  // phi' = c1 phi + c2 psi + e1 (rho + rho')
+  phb = cadd2(phb, csc(phb1, c1));
+  psb = cadd2(psb, csc(phb1, c2));
+  rhb = cadd2(rhb, csc(phb1, e1));
+  rhb1 = cadd2(rhb1, csc(phb1, e1));
+  // rho' = rho - h i k . jh
+  rhb = cadd2(rhb, rhb1);
+  for (int l = 0; l < d; ++l) jb[l] = cadd2(jb[l], csc(cik2(k[l], rhb1), h));
+  // jh = P j
+  if (a.project && nyq)
+    for (int c = 0; c < 3; ++c) jb[c] = z;
+  a.Ls[g] = phb;
+  a.Ls[Ng + g] = psb;
+  a.Ls[2 * Ng + g] = rhb;
+  for (int c = 0; c < 3; ++c) {
+    a.Ls[(3 + c) * Ng + g] = Ab[c];
+    a.Ls[(6 + c) * Ng + g] = Ub[c];
+    a.Lj[c * Ng + g] = jb[c];
+  }
+}
+
+// Spectra of the cotangent of the field energy W = sum (|E|^2 / (2 sigma1) + |B|^2 /
+// (2 sigma2)) dV with respect to the real-space state (phi, psi, rho, A, U):
+// E = -i k phi - U, B = i k x A; phi-bar = (dV / sigma1) i k . E, U-bar = -(dV / sigma1) E,
+// A-bar = (dV / sigma2) i k x B.
+__global__ __launch_bounds__(kBlock) void k_energy_grad(Mesh M, double sigma1, double sigma2, const double2* S,
+                                                        double2* out) {
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t Ng = M.Ng;
+  if (g >= Ng) return;
+  double k[3];
+  bool nyq;
+  wavevec(M, g, k, nyq);
+  const double2 ph = S[g];
+  double2 E[3], A[3], B[3];
+  for (int c = 0; c < 3; ++c) {
+    const double2 gk = cik2(k[c], ph), U = S[(6 + c) * Ng + g];
+    E[c] = make_double2(-gk.x - U.x, -gk.y - U.y);
+    A[c] = S[(3 + c) * Ng + g];
+  }
+  for (int c = 0; c < 3; ++c) {
+    const int c1 = (c + 1) % 3, c2 = (c + 2) % 3;
+    const double2 a1 = cik2(k[c1], A[c2]), a2 = cik2(k[c2], A[c1]);
+    B[c] = make_double2(a1.x - a2.x, a1.y - a2.y);
+  }
+  const double fe = M.dV / sigma1, fb = M.dV / sigma2;
+  double2 phb = make_double2(0.0, 0.0);
+  for (int c = 0; c < 3; ++c) phb = cadd2(phb, cik2(k[c], E[c]));
+  out[g] = csc(phb, fe);
+  out[Ng + g] = make_double2(0.0, 0.0);
+  out[2 * Ng + g] = make_double2(0.0, 0.0);
+  for (int c = 0; c < 3; ++c) {
+    const int c1 = (c + 1) % 3, c2 = (c + 2) % 3;
+    const double2 a1 = cik2(k[c1], B[c2]), a2 = cik2(k[c2], B[c1]);
+    out[(3 + c) * Ng + g] = csc(make_double2(a1.x - a2.x, a1.y - a2.y), fb);
+    out[(6 + c) * Ng + g] = csc(E[c], -fe);
+  }
+}
+
+// Spectrum of the cotangent of the deposited point-shape charge at initialization:
+// rho^0 = P (deposit) with the mean removed, phi^0 = sigma1 rho^0 / |k|^2 (+ terms free of
+// the particles); so rho-bar_total = rho-bar + sigma1 phi-bar / |k|^2, zero at k = 0 and
+// (projected) on the Nyquist planes.
+__global__ __launch_bounds__(kBlock) void k_adj_init_field(Mesh M, double sigma1, int project, const double2* L,
+                                                           double2* out) {
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t Ng = M.Ng;
+  if (g >= Ng) return;
+  double k[3];
+  bool nyq;
+  wavevec(M, g, k, nyq);
+  const double k2 = k[0] * k[0] + k[1] * k[1] + k[2] * k[2];
+  double2 r = L[2 * Ng + g];
+  if (k2 > 0.0) r = cadd2(r, csc(L[g], sigma1 / k2));
+  if (g == 0 || (project && nyq)) r = make_double2(0.0, 0.0);
+  out[g] = r;
+}
+
+
+// Per particle: x -> rho^0 (point shape), u -> P^0 = m kappa u + q A^0(x), q -> both
+// (with m = |q|).
+__global__ __launch_bounds__(kBlock) void k_adj_init_particle(AdjInitArgs a) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= a.np) return;
+  const Mesh& M = a.M;
+  const int64_t Ng = M.Ng;
+  const int n = M.n[0];
+  const double ih = M.inv_h[0];
+  const int64_t li = a.id[i];
+  const double x = a.x[i], q = a.q[i], m = fabs(q), mk = m * a.kappa;
+  const double xs = (x - M.lo[0]) * ih;
+  const int i0 = (int)floor(xs + 0.5);
+  double rS = 0.0, rS1 = 0.0, A[3] = {0.0, 0.0, 0.0}, A1[3] = {0.0, 0.0, 0.0};
+  for (int o = -1; o <= 1; ++o) {
+    const double t = xs - (double)(i0 + o);
+    const double S = s2(t), S1 = s2d(t) * ih;
+    const int g = wrapi(i0 + o, n);
+    rS += S * a.rb[g];
+    rS1 += S1 * a.rb[g];
+    for (int c = 0; c < 3; ++c) {
+      A[c] += S * a.A0[c * Ng + g];
+      A1[c] += S1 * a.A0[c * Ng + g];
+    }
+  }
+  double lP[3], u[3];
+  for (int c = 0; c < 3; ++c) {
+    lP[c] = a.lP[c * a.np + li];
+    u[c] = (a.P[c * a.ps + i] - q * A[c]) / mk;
+  }
+  a.gx[li] = a.lx[li] + q / M.dV * rS1 + q * dot3(lP, A1);
+  for (int c = 0; c < 3; ++c) a.gu[c * a.np + li] = mk * lP[c];
+  a.gq[li] = rS / M.dV + dot3(lP, A) + (q < 0.0 ? -1.0 : 1.0) * a.kappa * dot3(lP, u);
+}
+
+// Settle test of the adjoint current: out[0] = max |new - old|, out[1] = max |new| over
+// n values (one workgroup), and old <- old + beta (new - old).
+__global__ __launch_bounds__(kBlock) void k_adj_update(double* mu, const double* mnew, int64_t n, double beta,
+                                                       double* out) {
+  __shared__ double r0[kBlock], r1[kBlock];
+  double dm = 0.0, mm = 0.0;
+  for (int64_t i = threadIdx.x; i < n; i += kBlock) {
+    const double d = mnew[i] - mu[i];
+    dm = fmax(dm, fabs(d));
+    mm = fmax(mm, fabs(mnew[i]));
+    mu[i] += beta * d;
+  }
+  r0[threadIdx.x] = dm;
+  r1[threadIdx.x] = mm;
+  __syncthreads();
+  for (int w = kBlock / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) {
+      r0[threadIdx.x] = fmax(r0[threadIdx.x], r0[threadIdx.x + w]);
+      r1[threadIdx.x] = fmax(r1[threadIdx.x], r1[threadIdx.x + w]);
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    out[0] = r0[0];
+    out[1] = r1[0];
+  }
+}
+
+// Fixed-order sum of n per-block values (one workgroup).
+__global__ __launch_bounds__(kBlock) void k_adj_sum(const double* p, int64_t n, double* out) {
+  __shared__ double r[kBlock];
+  double s = 0.0;
+  for (int64_t i = threadIdx.x; i < n; i += kBlock) s += p[i];
+  r[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = kBlock / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) r[threadIdx.x] += r[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[0] = r[0];
+}
+
+namespace {
+inline unsigned nblocks(int64_t n) { return (unsigned)std::max<int64_t>((n + kBlock - 1) / kBlock, 1); }
+}  // namespace
+
+hipError_t launch_adj_particle(const AdjArgs& a, hipStream_t s) {
+  if (a.np == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_adj_particle, dim3(nblocks(a.np)), dim3(kBlock), 0, s, a);
+  return hipGetLastError();
+}
+int64_t adj_particle_blocks(int64_t np) { return nblocks(np); }
+hipError_t launch_adj_field(const AdjFieldArgs& a, hipStream_t s) {
+  hipLaunchKernelGGL(k_adj_field, dim3(nblocks(a.M.Ng)), dim3(kBlock), 0, s, a);
+  return hipGetLastError();
+}
+hipError_t launch_energy_grad(const Mesh& M, double sigma1, double sigma2, const double2* S, double2* out,
+                              hipStream_t s) {
+  hipLaunchKernelGGL(k_energy_grad, dim3(nblocks(M.Ng)), dim3(kBlock), 0, s, M, sigma1, sigma2, S, out);
+  return hipGetLastError();
+}
+hipError_t launch_adj_init_field(const Mesh& M, double sigma1, int project, const double2* L, double2* out,
+                                 hipStream_t s) {
+  hipLaunchKernelGGL(k_adj_init_field, dim3(nblocks(M.Ng)), dim3(kBlock), 0, s, M, sigma1, project, L, out);
+  return hipGetLastError();
+}
+hipError_t launch_adj_init_particle(const AdjInitArgs& a, hipStream_t s) {
+  if (a.np == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_adj_init_particle, dim3(nblocks(a.np)), dim3(kBlock), 0, s, a);
+  return hipGetLastError();
+}
+hipError_t launch_adj_update(double* mu, const double* mnew, int64_t n, double beta, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_adj_update, dim3(1), dim3(kBlock), 0, s, mu, mnew, n, beta, out);
+  return hipGetLastError();
+}
+hipError_t launch_adj_sum(const double* p, int64_t n, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_adj_sum, dim3(1), dim3(kBlock), 0, s, p, n, out);
+  return hipGetLastError();
+}
+
+}  // namespace gmhc

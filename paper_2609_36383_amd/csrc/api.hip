@@ -1703,6 +1703,230 @@ int32_t gmhc_read_pass(gmhc_ctx* ctx, double* vout, double* Pnp1, double* J, int
   return GMHC_OK;
 }
 
+}  // extern "C"
+
+// ---- adjoint of the step and of initialization (adjoint.hip) ----------------------
+
+namespace {
+
+// Device scratch of the adjoint calls, carved from the caller's buffer.
+struct AdjScratch {
+  double2* jh;
+  double2* S1;
+  double* trial;
+  double2* work;
+  double2* Lf;
+  unsigned long long* acc;
+  double* Pr;
+  double2* Pb;
+  double2* Lout;
+  double* Lreal;
+  double* mu;
+  double* partials;
+  double* red;
+};
+
+size_t adj_carve(const gmhc_ctx* c, char* base, AdjScratch& a) {
+  Carver cv{base};
+  const int64_t Ng = c->M.Ng;
+  const int d = c->M.d;
+  a.jh = cv.take<double2>(3 * Ng);
+  a.S1 = cv.take<double2>(9 * Ng);
+  a.trial = cv.take<double>((size_t)(d + 6) * Ng);
+  a.work = cv.take<double2>(12 * Ng);
+  a.Lf = cv.take<double2>(9 * Ng);
+  a.acc = cv.take<unsigned long long>((size_t)2 * kAdjVals * Ng);
+  a.Pr = cv.take<double>((size_t)kAdjVals * Ng);
+  a.Pb = cv.take<double2>((size_t)kAdjVals * Ng);
+  a.Lout = cv.take<double2>(12 * Ng);
+  a.Lreal = cv.take<double>(12 * Ng);
+  a.mu = cv.take<double>(3 * Ng);
+  a.partials = cv.take<double>((size_t)adj_particle_blocks(std::max<int64_t>(c->np, 1)));
+  a.red = cv.take<double>(8);
+  return (cv.off + 255) & ~(size_t)255;
+}
+
+// The configurations the adjoint covers: 1D, quadratic shape, FP64, no refinement, a
+// Gauss-Legendre order that integrates the derivative integrands exactly (>= 2).
+int32_t adj_supported(gmhc_ctx* ctx) {
+  if (ctx->M.d != 1 || ctx->M.shape != 2 || ctx->prec != GMHC_FP64 || ctx->cfg.refine_levels != 0 ||
+      ctx->ngl < 2)
+    return fail(ctx, GMHC_EINVAL,
+                "the adjoint covers dim 1, shape_order 2, precision FP64, refine_levels 0 and gl_order 0 or >= 2");
+  return GMHC_OK;
+}
+
+int32_t adj_prepare(gmhc_ctx* ctx, void* scratch, size_t bytes, AdjScratch& a) {
+  if (!ctx->initialized) return fail(ctx, GMHC_ESTATE, "initialize (or load a state) before the adjoint");
+  int32_t st = adj_supported(ctx);
+  if (st) return st;
+  if (!scratch) return fail(ctx, GMHC_EINVAL, "null adjoint scratch");
+  if (reinterpret_cast<uintptr_t>(scratch) & 255) return fail(ctx, GMHC_EINVAL, "adjoint scratch not 256-byte aligned");
+  if (bytes < adj_carve(ctx, nullptr, a)) return fail(ctx, GMHC_ENOMEM, "adjoint scratch smaller than gmhc_adjoint_bytes");
+  adj_carve(ctx, static_cast<char*>(scratch), a);
+  drop_ahead(ctx);
+  return GMHC_OK;
+}
+
+AdjArgs adj_args(const gmhc_ctx* c, const AdjScratch& a, const double* vbar, const double* lx, const double* lP) {
+  AdjArgs r{};
+  r.M = c->M;
+  r.np = c->np;
+  r.dt = c->cfg.dt;
+  r.kappa = c->cfg.kappa;
+  r.ngl = c->ngl;
+  for (int k = 0; k < kMaxGL; ++k) {
+    r.glx[k] = c->glx[k];
+    r.glw[k] = c->glw[k];
+  }
+  r.ps = std::max<int64_t>(c->np, 1);
+  r.x = c->x[0];
+  r.P = static_cast<const double*>(c->P[0]);
+  r.q = static_cast<const double*>(c->q);
+  r.id = c->id;
+  r.vbar = vbar;
+  r.lx = lx;
+  r.lP = lP;
+  r.gphi = a.trial;
+  r.An = c->An;
+  r.Anp1 = a.trial + c->M.Ng;
+  r.partials = a.partials;
+  r.acc = a.acc;
+  return r;
+}
+
+}  // namespace
+
+extern "C" {
+
+int32_t gmhc_adjoint_bytes(const gmhc_ctx* ctx, size_t* bytes) {
+  if (!ctx || !bytes) return GMHC_EINVAL;
+  AdjScratch a{};
+  *bytes = adj_carve(ctx, nullptr, a);
+  return GMHC_OK;
+}
+
+int32_t gmhc_energy_grad(gmhc_ctx* ctx, double* gf, int32_t ptr_kind) {
+  if (!ctx || !gf) return GMHC_EINVAL;
+  if (!ctx->initialized) return fail(ctx, GMHC_ESTATE, "initialize (or load a state) before gmhc_energy_grad");
+  drop_ahead(ctx);
+  DevGuard gd(ctx->device);
+  const Mesh& M = ctx->M;
+  hipStream_t s = ctx->stream;
+  HIPCK(launch_energy_grad(M, ctx->cfg.sigma1, ctx->cfg.sigma2, ctx->S0, ctx->cscr, s));
+  HIPCK(fft_nd(M, ctx->axes, 9, nullptr, ctx->cscr, nullptr, ctx->rscr, ctx->cout, true, false, s));
+  HIPCK(hipMemcpyAsync(gf, ctx->rscr, sizeof(double) * 9 * M.Ng, kind_of(ptr_kind, false), s));
+  HIPCK(hipStreamSynchronize(s));
+  return GMHC_OK;
+}
+
+int32_t gmhc_adjoint_step(gmhc_ctx* ctx, void* scratch, size_t scratch_bytes, const double* j, const double* vbar,
+                          const double* lx, const double* lP, const double* lf, double* gx, double* gP, double* gq,
+                          double* gf, gmhc_adjoint_report* rep) {
+  if (!ctx || !j || !vbar || !lx || !lP || !lf || !gx || !gP || !gq || !gf) return GMHC_EINVAL;
+  AdjScratch a{};
+  int32_t st = adj_prepare(ctx, scratch, scratch_bytes, a);
+  if (st) return st;
+  DevGuard gd(ctx->device);
+  const Mesh& M = ctx->M;
+  const int64_t Ng = M.Ng;
+  hipStream_t s = ctx->stream;
+  const bool proj = ctx->cfg.project_nyquist != 0;
+  // trial fields of the converged current: projected spectrum, CN solve, real fields
+  HIPCK(fft_nd(M, ctx->axes, 3, j, nullptr, a.jh, nullptr, nullptr, false, proj, s));
+  HIPCK(field_trial(M, ctx->axes, cn_args(ctx, a.jh, a.S1, nullptr), a.trial, a.work, nullptr, s));
+  HIPCK(fft_nd(M, ctx->axes, 9, lf, nullptr, a.Lf, nullptr, nullptr, false, false, s));
+  HIPCK(launch_zero(a.mu, 3 * Ng, s));
+  AdjFieldArgs fa{};
+  fa.M = M;
+  fa.dt = ctx->cfg.dt;
+  fa.kappa2 = ctx->cfg.kappa * ctx->cfg.kappa;
+  fa.sigma1 = ctx->cfg.sigma1;
+  fa.sigma2 = ctx->cfg.sigma2;
+  fa.project = proj ? 1 : 0;
+  fa.Lf = a.Lf;
+  fa.Pb = a.Pb;
+  fa.Ls = a.Lout;
+  fa.Lj = a.Lout + 9 * Ng;
+  const double tol = std::max(ctx->cfg.tol_outer_rel, 1e-15);
+  const int64_t nb = adj_particle_blocks(ctx->np);
+  gmhc_adjoint_report R{};
+  double hr[2] = {0.0, 0.0};
+  bool done = false;
+  for (int it = 0; it < ctx->cfg.max_outer && !done; ++it) {
+    AdjArgs pa = adj_args(ctx, a, vbar, lx, lP);
+    pa.mu = it ? a.mu : nullptr;
+    // scale of the exact fixed-point sums from a bound on every scattered value
+    pa.mode = ADJ_BOUND;
+    HIPCK(launch_adj_particle(pa, s));
+    HIPCK(launch_adj_sum(a.partials, ctx->np ? nb : 0, a.red, s));
+    double B = 0.0;
+    HIPCK(hipMemcpyAsync(&B, a.red, sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCK(hipStreamSynchronize(s));
+    const FixScale fx = fix_scale(B);
+    HIPCK(launch_zero(reinterpret_cast<double*>(a.acc), 2 * kAdjVals * Ng, s));
+    pa.mode = ADJ_SCATTER;
+    pa.fx_up = fx.up;
+    HIPCK(launch_adj_particle(pa, s));
+    HIPCK(launch_fix_to_double(a.acc, a.Pr, kAdjVals * Ng, fx, s));
+    HIPCK(fft_nd(M, ctx->axes, kAdjVals, a.Pr, nullptr, a.Pb, nullptr, nullptr, false, false, s));
+    HIPCK(launch_adj_field(fa, s));
+    HIPCK(fft_nd(M, ctx->axes, 12, nullptr, a.Lout, nullptr, a.Lreal, a.work, true, false, s));
+    HIPCK(launch_adj_update(a.mu, a.Lreal + 9 * Ng, 3 * Ng, it ? ctx->cfg.beta : 1.0, a.red, s));
+    HIPCK(hipMemcpyAsync(hr, a.red, sizeof(hr), hipMemcpyDeviceToHost, s));
+    HIPCK(hipStreamSynchronize(s));
+    R.iterations = it + 1;
+    R.change_ratio = hr[1] > 0.0 ? hr[0] / hr[1] : 0.0;
+    done = hr[0] <= tol * hr[1];
+  }
+  if (rep) *rep = R;
+  if (!done) return fail(ctx, GMHC_ENOCONV, "adjoint current did not settle within max_outer iterations");
+  AdjArgs pa = adj_args(ctx, a, vbar, lx, lP);
+  pa.mu = a.mu;
+  pa.mode = ADJ_FINAL;
+  pa.gx = gx;
+  pa.gP = gP;
+  pa.gq = gq;
+  HIPCK(launch_adj_particle(pa, s));
+  HIPCK(hipMemcpyAsync(gf, a.Lreal, sizeof(double) * 9 * Ng, hipMemcpyDeviceToDevice, s));
+  HIPCK(hipStreamSynchronize(s));
+  return GMHC_OK;
+}
+
+int32_t gmhc_adjoint_initialize(gmhc_ctx* ctx, void* scratch, size_t scratch_bytes, const double* lx,
+                                const double* lP, const double* lf, double* gx, double* gu, double* gq) {
+  if (!ctx || !lx || !lP || !lf || !gx || !gu || !gq) return GMHC_EINVAL;
+  AdjScratch a{};
+  int32_t st = adj_prepare(ctx, scratch, scratch_bytes, a);
+  if (st) return st;
+  if (ctx->step != 0) return fail(ctx, GMHC_ESTATE, "gmhc_adjoint_initialize needs the initial state (step 0)");
+  DevGuard gd(ctx->device);
+  const Mesh& M = ctx->M;
+  hipStream_t s = ctx->stream;
+  HIPCK(fft_nd(M, ctx->axes, 9, lf, nullptr, a.Lf, nullptr, nullptr, false, false, s));
+  HIPCK(launch_adj_init_field(M, ctx->cfg.sigma1, ctx->cfg.project_nyquist, a.Lf, a.Lout, s));
+  HIPCK(fft_nd(M, ctx->axes, 1, nullptr, a.Lout, nullptr, a.Lreal, a.work, true, false, s));
+  AdjInitArgs ia{};
+  ia.M = M;
+  ia.np = ctx->np;
+  ia.ps = std::max<int64_t>(ctx->np, 1);
+  ia.kappa = ctx->cfg.kappa;
+  ia.x = ctx->x[0];
+  ia.P = static_cast<const double*>(ctx->P[0]);
+  ia.q = static_cast<const double*>(ctx->q);
+  ia.id = ctx->id;
+  ia.A0 = ctx->An;
+  ia.rb = a.Lreal;
+  ia.lx = lx;
+  ia.lP = lP;
+  ia.gx = gx;
+  ia.gu = gu;
+  ia.gq = gq;
+  HIPCK(launch_adj_init_particle(ia, s));
+  HIPCK(hipStreamSynchronize(s));
+  return GMHC_OK;
+}
+
 int32_t gmhc_state_bytes(const gmhc_ctx* cctx, size_t* bytes) {
   gmhc_ctx* ctx = const_cast<gmhc_ctx*>(cctx);
   if (!ctx || !bytes) return GMHC_EINVAL;

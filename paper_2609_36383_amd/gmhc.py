@@ -15,7 +15,7 @@ LIB_PATH = os.path.join(HERE, "libgmhc.so")
 
 OK, EINVAL, ESTATE, ENOMEM, EDEVICE, EINNER, ENOCONV = 0, -1, -2, -3, -4, -5, -6
 HOST, DEVICE = 0, 1
-ABI_VERSION = 5  # layout of the structures below (include/gmhc.h, GMHC_ABI_VERSION)
+ABI_VERSION = 6  # layout of the structures below (include/gmhc.h, GMHC_ABI_VERSION)
 FP64, FP32_BULK = 0, 1
 PICARD, ANDERSON = 0, 1
 FIELD = {"phi": 0, "psi": 1, "A": 2, "U": 3, "rho": 4, "J": 5, "E": 6, "B": 7}
@@ -28,7 +28,8 @@ SYMBOLS = (
     "gmhc_initialize", "gmhc_step", "gmhc_diagnostics", "gmhc_read_particles",
     "gmhc_set_particle_state", "gmhc_read_field", "gmhc_mode_amplitude", "gmhc_set_frozen_fields",
     "gmhc_orbit_pass_frozen", "gmhc_read_pass", "gmhc_state_bytes", "gmhc_save", "gmhc_load",
-    "gmhc_orbit_pass_static",
+    "gmhc_orbit_pass_static", "gmhc_adjoint_bytes", "gmhc_energy_grad", "gmhc_adjoint_step",
+    "gmhc_adjoint_initialize",
 )
 STATIC_MAX_PARTICLES = 1 << 22  # GMHC_STATIC_MAX_PARTICLES
 STATIC_MAX_NODES = 1 << 18      # GMHC_STATIC_MAX_NODES
@@ -69,6 +70,10 @@ class PassReport(C.Structure):
     _fields_ = [("failed", C.c_int64), ("inner_max", C.c_int32), ("over_limit", C.c_int32),
                 ("inner_mean", C.c_double), ("evaluations", C.c_int64), ("orbit_ms", C.c_double),
                 ("segments", C.c_int64), ("refined", C.c_int64)]
+
+
+class AdjointReport(C.Structure):
+    _fields_ = [("iterations", C.c_int32), ("change_ratio", C.c_double)]
 
 
 def _todict(s):
@@ -116,6 +121,10 @@ def load_library(path=LIB_PATH):
         "gmhc_load": ([vp, vp, C.c_size_t, i32], i32),
         "gmhc_orbit_pass_static": ([C.POINTER(Config), i64] + [vp] * 8 + [i32] + [vp] * 5 +
                                    [C.POINTER(PassReport)], i32),
+        "gmhc_adjoint_bytes": ([vp, C.POINTER(C.c_size_t)], i32),
+        "gmhc_energy_grad": ([vp, vp, i32], i32),
+        "gmhc_adjoint_step": ([vp, vp, C.c_size_t] + [vp] * 9 + [C.POINTER(AdjointReport)], i32),
+        "gmhc_adjoint_initialize": ([vp, vp, C.c_size_t] + [vp] * 6, i32),
     }
     for name, (args, res) in sig.items():
         f = getattr(L, name)
@@ -317,6 +326,56 @@ class Simulation:
         else:
             self.stream.wait_stream(self.torch.cuda.current_stream(self.device))
             self._chk(self.lib.gmhc_load(self.h, C.c_void_p(image.data_ptr()), image.numel(), DEVICE), "gmhc_load")
+
+    # -- device read-outs and the adjoint (torch float64 tensors on this device) ----
+    def _dev(self, t):
+        assert t.dtype == self.torch.float64 and t.is_contiguous() and t.device == self.device
+        return C.c_void_p(t.data_ptr())
+
+    def read_field_into(self, which, out):
+        """Real-space field `which` of the accepted state into the device tensor out."""
+        self.stream.wait_stream(self.torch.cuda.current_stream(self.device))
+        self._chk(self.lib.gmhc_read_field(self.h, FIELD[which], self._dev(out), DEVICE), "gmhc_read_field")
+        return out
+
+    def read_particles_into(self, x=None, P=None, vbar=None):
+        """Particle state (load order) into device tensors; None skips."""
+        self.stream.wait_stream(self.torch.cuda.current_stream(self.device))
+        p = [self._dev(t) if t is not None else None for t in (x, P, vbar)]
+        self._chk(self.lib.gmhc_read_particles(self.h, *p, DEVICE), "gmhc_read_particles")
+
+    def adjoint_bytes(self):
+        n = C.c_size_t()
+        self._chk(self.lib.gmhc_adjoint_bytes(self.h, C.byref(n)), "gmhc_adjoint_bytes")
+        return n.value
+
+    def adjoint_scratch(self):
+        """A 256-byte aligned device scratch tensor for the adjoint calls."""
+        n = self.adjoint_bytes()
+        buf = self.torch.empty(n + 256, dtype=self.torch.uint8, device=self.device)
+        off = (-buf.data_ptr()) % 256
+        return buf[off:off + n]
+
+    def energy_grad(self, out):
+        """out [9][Ng] (device): the cotangent of the field energy of the accepted state."""
+        self.stream.wait_stream(self.torch.cuda.current_stream(self.device))
+        self._chk(self.lib.gmhc_energy_grad(self.h, self._dev(out), DEVICE), "gmhc_energy_grad")
+        return out
+
+    def adjoint_step(self, scratch, j, vbar, lx, lP, lf, gx, gP, gq, gf):
+        """gmhc_adjoint_step on device tensors; returns its report."""
+        self.stream.wait_stream(self.torch.cuda.current_stream(self.device))
+        r = AdjointReport()
+        args = [self._dev(t) for t in (j, vbar, lx, lP, lf, gx, gP, gq, gf)]
+        self._chk(self.lib.gmhc_adjoint_step(self.h, C.c_void_p(scratch.data_ptr()), scratch.numel(), *args,
+                                             C.byref(r)), "gmhc_adjoint_step")
+        return _todict(r)
+
+    def adjoint_initialize(self, scratch, lx, lP, lf, gx, gu, gq):
+        self.stream.wait_stream(self.torch.cuda.current_stream(self.device))
+        args = [self._dev(t) for t in (lx, lP, lf, gx, gu, gq)]
+        self._chk(self.lib.gmhc_adjoint_initialize(self.h, C.c_void_p(scratch.data_ptr()), scratch.numel(), *args),
+                  "gmhc_adjoint_initialize")
 
     def read_pass(self, iters=False, current=True, levels=False):
         """v_out, P^{n+1} and J (None unless current) of the last frozen pass, then with

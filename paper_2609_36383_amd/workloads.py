@@ -236,6 +236,22 @@ def _quiet1d(w):
     return np.ascontiguousarray(x), u, q
 
 
+def quiet1d_parts(w):
+    """Pieces of the quiet 1D two-beam start of a "quiet1d" workload, for callers that
+    build the particles from parameters: the beam positions xj [nb] (both beams share
+    them), and the per-mode weight patterns cos(2 pi m (xj - lo) / L + theta_m)
+    [nmodes][nb] with the workload's seeded phases.  The particles are x = (xj, xj),
+    u_x = (+u_drift, -u_drift), q = -(w, w) with w = (L / nb) / 2 (1 + sum_m eps_m pattern_m)."""
+    L = w["length"][0]
+    lo = w["lo"][0]
+    nb = w["n"][0] * w["ppc"] // 2
+    rng = np.random.default_rng(w["seed"])
+    theta = 2.0 * math.pi * rng.random(len(w["modes"]))
+    xj = lo + (np.arange(nb) + 0.5) * (L / nb)
+    pat = np.stack([np.cos(2.0 * math.pi * m / L * (xj - lo) + th) for m, th in zip(w["modes"], theta)])
+    return xj, pat
+
+
 def _eigen1d(w, xj, u):
     """Cold-fluid growing eigenmode of mode 1 for two equal electron beams (q/m = -1).
 

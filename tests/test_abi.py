@@ -113,4 +113,12 @@ def test_calls_out_of_order_are_rejected():
     assert lib.gmhc_save(h, buf, 64, G.HOST) == G.ESTATE
     assert lib.gmhc_load(h, buf, 64, G.HOST) == G.ESTATE
     assert b"initialize" in lib.gmhc_last_error(h) or lib.gmhc_last_error(h)
+    # the adjoint calls need an initialized (or loaded) state
+    dummy = (C.c_double * 8)()
+    assert lib.gmhc_energy_grad(h, dummy, G.HOST) == G.ESTATE
+    assert lib.gmhc_adjoint_step(h, buf, 64, *([dummy] * 9), None) == G.ESTATE
+    assert lib.gmhc_adjoint_initialize(h, buf, 64, *([dummy] * 6)) == G.ESTATE
+    assert lib.gmhc_adjoint_step(h, buf, 64, *([dummy] * 8), None, None) == G.EINVAL  # null output
+    n = C.c_size_t()
+    assert lib.gmhc_adjoint_bytes(h, C.byref(n)) == G.OK and n.value > 0
     lib.gmhc_destroy(h)

@@ -1,0 +1,136 @@
+"""GPU parity of the adjoint of the implicit step (gradients of the field energy at the
+end of a run with respect to the perturbation amplitudes and the beam momentum of the
+1D two-stream workload), through the C ABI's adjoint calls and the autograd Function.
+
+References: the oracle's forward-mode derivatives (oracle/gmhc_tangent.cpp, pinned on
+the CPU by central differences and the conserved derivative of total energy) on a
+reduced mesh, and central differences of the GPU's own forward runs at full size.
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from paper_2609_36383_amd import adjoint as A
+from paper_2609_36383_amd import gmhc as G
+from paper_2609_36383_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def _gpu_grad(w, steps, every):
+    cfg = G.config_from_dict(W.config_dict(w))
+    eps = torch.full((len(w["modes"]),), w["eps"], dtype=torch.float64, requires_grad=True)
+    u0 = torch.tensor(w["u_drift"], dtype=torch.float64, requires_grad=True)
+    x, u, q = A.quiet1d_inputs(w, eps, u0)
+    Wt = A.field_energy_run(x, u, q, cfg, steps, every, "cuda:0")
+    Wt.backward()
+    return float(Wt.detach()), np.concatenate([eps.grad.numpy(), [u0.grad.item()]])
+
+
+def _seeds(w):
+    """Derivatives of the loaded charges and momenta along eps_1..eps_M and u0."""
+    xj, pat = W.quiet1d_parts(w)
+    nb = xj.size
+    L = w["length"][0]
+    nm = pat.shape[0]
+    dq = np.zeros((nm + 1, 2 * nb))
+    du = np.zeros((nm + 1, 3, 2 * nb))
+    for m in range(nm):
+        dq[m] = -np.concatenate([0.5 * (L / nb) * pat[m]] * 2)
+    du[nm, 0, :nb] = 1.0
+    du[nm, 0, nb:] = -1.0
+    return dq, du
+
+
+def test_adjoint_matches_oracle_tangent_reduced():
+    """64 cells, 2048 particles, 20 steps with checkpoints every 5: dW(T)/d(eps_1..8, u0)
+    from the GPU adjoint against the oracle's forward-mode derivatives."""
+    w = W.spec("tsi1d_big", n=(64,), ppc=32, length=(4.0 * math.pi,))
+    steps, every = 20, 5
+    print(f"adjoint vs oracle tangent: {w['num_particles']} particles, {steps} steps", flush=True)
+    Wg, gg = _gpu_grad(w, steps, every)
+    Wg2, gg2 = _gpu_grad(w, steps, every)
+    x, u, q = W.particles(w)
+    cfg = O.config_from_dict(W.config_dict(w), gl_order=2)
+    dq, du = _seeds(w)
+    E, dE, _ = O.tangent_run(cfg, x[0], u, q, steps, du=du, dq=dq)
+    go = dE[2]
+    err = np.abs(gg - go).max() / np.abs(go).max()
+    print(f"W gpu {Wg:.12e} oracle {E[2]:.12e}; grad rel err {err:.2e}", flush=True)
+    print("gpu   ", gg, "\noracle", go, flush=True)
+    assert Wg == Wg2 and np.array_equal(gg, gg2)  # bitwise reproducible
+    assert abs(Wg - E[2]) <= 1e-10 * E[2]
+    assert err <= 1e-10
+
+
+def test_adjoint_matches_central_differences_full_size():
+    """The full 1D adjoint workload (1024 cells, 1,048,576 particles, 50 steps with
+    checkpoints every 10): GPU adjoint against central differences (h = 1e-6) of GPU runs."""
+    w = W.spec("tsi1d_big")
+    steps, every = 50, 10
+    print(f"adjoint vs central differences: {w['num_particles']} particles, {steps} steps", flush=True)
+    Wg, gg = _gpu_grad(w, steps, every)
+    cfg = G.config_from_dict(W.config_dict(w))
+    nm = len(w["modes"])
+    h = 1e-6
+    fd = np.zeros(nm + 1)
+    for k in range(nm + 1):
+        vals = []
+        for sgn in (1.0, -1.0):
+            eps = torch.full((nm,), w["eps"], dtype=torch.float64)
+            u0 = torch.tensor(w["u_drift"], dtype=torch.float64)
+            if k < nm:
+                eps[k] += sgn * h
+            else:
+                u0 += sgn * h
+            x, u, q = A.quiet1d_inputs(w, eps, u0)
+            sim = G.Simulation(cfg, q.numel(), device="cuda:0")
+            sim.load_particles(x.numpy()[None], u.numpy(), q.numpy())
+            sim.initialize()
+            for _ in range(steps):
+                sim.step()
+            vals.append(sim.diagnostics()["field"])
+            sim.close()
+        fd[k] = (vals[0] - vals[1]) / (2.0 * h)
+    err = np.abs(gg - fd).max() / np.abs(fd).max()
+    print(f"W {Wg:.6e}; grad rel err vs central differences {err:.2e}", flush=True)
+    print("adjoint", gg, "\nFD     ", fd, flush=True)
+    assert err <= 1e-7
+
+
+def test_energy_grad_is_twice_the_energy_along_the_state():
+    """W is a quadratic form of the field state f, so dW/df . f = 2 W (Euler)."""
+    w = W.spec("tsi1d_big", n=(64,), ppc=16, length=(4.0 * math.pi,))
+    cfg = G.config_from_dict(W.config_dict(w))
+    x, u, q = W.particles(w)
+    sim = G.Simulation(cfg, q.size, device="cuda:0")
+    sim.load_particles(x, u, q)
+    sim.initialize()
+    for _ in range(5):
+        sim.step()
+    gf = torch.empty(9, sim.ng, dtype=torch.float64, device=sim.device)
+    sim.energy_grad(gf)
+    f = np.concatenate([np.atleast_2d(sim.read_field(k)) for k in ("phi", "psi", "rho", "A", "U")])
+    Wf = sim.diagnostics()["field"]
+    s = float((gf.cpu().numpy() * f).sum())
+    sim.close()
+    assert abs(s - 2.0 * Wf) <= 1e-12 * Wf
+
+
+def test_adjoint_rejects_unsupported_configurations():
+    w = W.spec("weibel2d", n=(16, 16), ppc=4)
+    cfg = G.config_from_dict(W.config_dict(w))
+    x, u, q = W.particles(w)
+    sim = G.Simulation(cfg, q.size, device="cuda:0")
+    sim.load_particles(x, u, q)
+    sim.initialize()
+    scratch = sim.adjoint_scratch()
+    z = lambda *s: torch.zeros(*s, dtype=torch.float64, device=sim.device)
+    n, ng = sim.np, sim.ng
+    with pytest.raises(G.GmhcError) as e:
+        sim.adjoint_step(scratch, z(3, ng), z(3, n), z(n), z(3, n), z(9, ng), z(n), z(3, n), z(n), z(9, ng))
+    assert e.value.code == G.EINVAL
+    sim.close()
