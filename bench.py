@@ -263,6 +263,49 @@ def run_case(args, w, fp32, parts, tol_of_fp32=None):
         })
 
 
+def adjoint_block():
+    """Gradient of the final field energy with respect to the eight perturbation amplitudes
+    and the beam momentum on the 1D adjoint workload (1024 cells, 1,048,576 particles, 50
+    steps, checkpoints every 10): wall times of the forward run and of the backward pass
+    (re-run of each checkpoint segment, then the adjoint steps)."""
+    import torch
+
+    from paper_2609_36383_amd import adjoint as A
+    from paper_2609_36383_amd import gmhc as G
+    from paper_2609_36383_amd import workloads as W
+
+    w = W.spec("tsi1d_big")
+    steps, every = 50, 10
+    cfg = G.config_from_dict(W.config_dict(w))
+    eps = torch.full((len(w["modes"]),), w["eps"], dtype=torch.float64, requires_grad=True)
+    u0 = torch.tensor(w["u_drift"], dtype=torch.float64, requires_grad=True)
+    x, u, q = A.quiet1d_inputs(w, eps, u0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    Wt = A.field_energy_run(x, u, q, cfg, steps, every, "cuda:0")
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    Wt.backward()
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    fn = Wt.grad_fn
+    its = [r["iterations"] for r in fn.reports]
+    n = w["num_particles"]
+    return {
+        "workload": f"tsi1d_big: 1024 cells, {n} particles, {steps} steps, checkpoints every {every}, FP64",
+        "field_energy": float(Wt.detach()),
+        "grad_eps": [float(v) for v in eps.grad],
+        "grad_u0": float(u0.grad),
+        "forward_s": t1 - t0,
+        "backward_s": t2 - t1,
+        "backward_rerun_s": fn.seconds["rerun"],
+        "backward_adjoint_steps_s": fn.seconds["adjoint_steps"],
+        "ms_per_adjoint_step": 1e3 * fn.seconds["adjoint_steps"] / steps,
+        "adjoint_particle_steps_per_s": n * steps / fn.seconds["adjoint_steps"],
+        "transposed_outer_iterations_mean": float(np.mean(its)),
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -278,6 +321,8 @@ def main():
     ap.add_argument("--precision", choices=("both", "fp64", "fp32"), default="both",
                     help="FP64 (the headline value), FP32-bulk, or both (default)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-adjoint", action="store_true",
+                    help="skip the adjoint block (gradient of the 1D run's final field energy)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a 256 MiB device-to-device copy (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -337,6 +382,8 @@ def main():
         f["speedup_particle_steps_same_tolerances"] = other["particle_steps_per_s"] / matched["particle_steps_per_s"]
         f["speedup_particle_steps_own_tolerances"] = other["particle_steps_per_s"] / r["particle_steps_per_s"]
         f["speedup_per_iteration_vs_fp64"] = other["value"] / r["value"]
+    if not args.no_adjoint:
+        out["adjoint"] = adjoint_block()
     if not args.no_cpu_baseline:
         base = W.config_dict(w, fp32_bulk=main_fp32)
         out["cpu_baseline"] = cpu_baseline(w, base, r["ngl"], parts, shape=args.shape)

@@ -13,6 +13,8 @@ velocities of every step, and the steps are then reversed one by one with
 gmhc_adjoint_step; at the first state gmhc_adjoint_initialize maps the cotangents to the
 loaded inputs.  The charge cotangent sums every step's part and initialization's.
 """
+import time
+
 import numpy as np
 import torch
 
@@ -45,6 +47,7 @@ class FieldEnergyRun(torch.autograd.Function):
         ctx.sim, ctx.ckpt, ctx.steps, ctx.every, ctx.save_fn = sim, ckpt, steps, every, save
         ctx.devices = (x.device, u.device, q.device)
         ctx.reports = []
+        ctx.seconds = {"rerun": 0.0, "adjoint_steps": 0.0}
         return torch.tensor(W, dtype=torch.float64)
 
     @staticmethod
@@ -64,6 +67,7 @@ class FieldEnergyRun(torch.autograd.Function):
         starts = sorted(ctx.ckpt)
         for a in reversed(starts):
             b = min(a + ctx.every, steps)
+            t0 = time.perf_counter()
             sim.load(ctx.ckpt[a])
             images, js, vbars = [], [], []
             for _ in range(a, b):
@@ -75,11 +79,15 @@ class FieldEnergyRun(torch.autograd.Function):
                 sim.read_particles_into(vbar=vb)
                 js.append(j)
                 vbars.append(vb)
+            torch.cuda.synchronize(dev)
+            t1 = time.perf_counter()
+            ctx.seconds["rerun"] += t1 - t0
             for k in reversed(range(len(images))):
                 sim.load(images[k])
                 rep = sim.adjoint_step(scratch, js[k], vbars[k], lx, lP, lf, lx, lP, gq_step, lf)
                 ctx.reports.append(rep)
                 gq += gq_step
+            ctx.seconds["adjoint_steps"] += time.perf_counter() - t1
         sim.load(ctx.ckpt[0])
         gx = torch.empty(n, **f64)
         gu = torch.empty(3, n, **f64)
