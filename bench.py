@@ -323,11 +323,16 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true",
                     help="skip the adjoint block (gradient of the 1D run's final field energy)")
+    ap.add_argument("--adjoint-only", action="store_true",
+                    help="run only the adjoint block and print it as one JSON line (for profiling)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a 256 MiB device-to-device copy (calibrates HBM byte counters)")
     args = ap.parse_args()
     if args.copy_probe:
         copy_probe()
+        return
+    if args.adjoint_only:
+        print(json.dumps({"adjoint": adjoint_block()}), flush=True)
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the library runs the orbit pass on a single MI355X "

@@ -27,6 +27,7 @@
 // the projected continuity / CN update), k_energy_grad and k_adj_init_field, and small
 // reductions.
 #include <hip/hip_runtime.h>
+#include <limits.h>
 #include <math.h>
 
 #include "gmhc_internal.h"
@@ -338,31 +339,63 @@ __device__ __forceinline__ double rev_x(const Rev& r, const Gath& G) {
 
 }  // namespace
 
+// Exact fixed-point accumulation of one workgroup's scattered values: a window of
+// kAdjWin consecutive (unwrapped) nodes from wlo per field array in LDS, summed with 64-bit
+// integer LDS atomics and added to the global accumulator once per workgroup; values at
+// nodes outside the window go to the global accumulator directly.  Integer sums are exact,
+// so the result does not depend on the order of arrival.
+constexpr int kAdjWin = 32;
+
+struct WinAcc {
+  unsigned long long* s;  // [kAdjVals][kAdjWin] pairs
+  unsigned long long* g;  // global [kAdjVals][Ng] pairs
+  int wlo, n;
+  int64_t Ng;
+  double up;
+  __device__ __forceinline__ void put(int f, int node, double v) const {
+    const int rel = node - wlo;
+    if (rel >= 0 && rel < kAdjWin) {
+      long long H, L;
+      fix_split(v, up, H, L);
+      const int k = 2 * (f * kAdjWin + rel);
+      if (H) atomicAdd(s + k, (unsigned long long)H);
+      if (L) atomicAdd(s + k + 1, (unsigned long long)L);
+    } else {
+      fix_add(g, f * Ng + wrapi(node, n), v, up);
+    }
+  }
+};
+
 __global__ __launch_bounds__(kBlock) void k_adj_particle(AdjArgs a) {
   __shared__ double red[kBlock];
+  __shared__ unsigned long long sacc[2 * kAdjVals * kAdjWin];
+  __shared__ int swlo;
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const bool live = i < a.np;
+  const Mesh& M = a.M;
+  const double ih = M.inv_h[0];
   double bound = 0.0;
-  if (i < a.np) {
-    const Mesh& M = a.M;
-    const int64_t Ng = M.Ng;
-    const double ih = M.inv_h[0];
-    const int64_t li = a.id[i];
-    const double x = a.x[i];
-    const double q = a.q[i], m = fabs(q);
-    double P[3], v[3], lP[3];
+  int64_t li = 0;
+  double x = 0.0, q = 0.0, v[3] = {0.0, 0.0, 0.0}, lx = 0.0;
+  Gath G{};
+  Rev r{};
+  if (live) {
+    li = a.id[i];
+    x = a.x[i];
+    q = a.q[i];
+    const double m = fabs(q);
+    double P[3], lP[3];
     for (int c = 0; c < 3; ++c) {
       P[c] = a.P[c * a.ps + i];
       v[c] = a.vbar[c * a.np + li];
       lP[c] = a.lP[c * a.np + li];
     }
-    const double lx = a.lx[li];
-    Gath G;
+    lx = a.lx[li];
     gather(a, x, v, G);
     Fwd f;
     forward(G, P, q, m, v[0], a.dt, a.kappa, f);
     // column x of dF/dvbar (F depends on vbar through vbar_x only)
     double J[3];
-    Rev r;
     for (int c = 0; c < 3; ++c) {
       const double e[3] = {c == 0 ? 1.0 : 0.0, c == 1 ? 1.0 : 0.0, c == 2 ? 1.0 : 0.0}, z[3] = {0.0, 0.0, 0.0};
       reverse(f, e, z, r);
@@ -383,21 +416,34 @@ __global__ __launch_bounds__(kBlock) void k_adj_particle(AdjArgs a) {
     if (a.mode == ADJ_BOUND) {
       bound = fabs(r.Gp);
       for (int c = 0; c < 3; ++c) bound += 2.0 * ih * fabs(r.D[c]) + fabs(r.Am[c]) + fabs(r.Ap[c]);
-    } else if (a.mode == ADJ_SCATTER) {
-      const int n = M.n[0];
-      const double xi0 = (x - M.lo[0]) * ih, dxi = a.dt * v[0] * ih;
-      const double up = a.fx_up;
+    } else if (a.mode == ADJ_FINAL) {
+      a.gx[li] = lx + rev_x(r, G) + qdv * G.Mx;
+      for (int c = 0; c < 3; ++c) a.gP[c * a.np + li] = r.P[c];
+      a.gq[li] = r.q + (q < 0.0 ? -r.m : r.m) + dot3(v, G.Mc) / M.dV;
+    }
+  }
+  if (a.mode == ADJ_SCATTER) {  // uniform over the workgroup
+    const int64_t Ng = M.Ng;
+    const int n = M.n[0];
+    const double xi0 = (x - M.lo[0]) * ih, dxi = a.dt * v[0] * ih;
+    if (threadIdx.x == 0) swlo = INT_MAX;
+    for (int k = threadIdx.x; k < 2 * kAdjVals * kAdjWin; k += kBlock) sacc[k] = 0ull;
+    __syncthreads();
+    if (live) atomicMin(&swlo, (int)floor(fmin(xi0, xi0 + dxi) + 0.5) - 1);
+    __syncthreads();
+    const WinAcc w{sacc, a.acc, swlo, n, Ng, a.fx_up};
+    if (live) {
       walk_orbit(a, xi0, dxi, [&](double s, double wq) {
         const double xs = xi0 + s * dxi;
         const int i0 = (int)floor(xs + 0.5);
         for (int o = -1; o <= 1; ++o) {
           const double t = xs - (double)(i0 + o);
           const double S = s2(t), S1 = s2d(t) * ih;
-          const int64_t g = wrapi(i0 + o, n);
-          fix_add(a.acc, g, wq * S * r.Gp, up);
+          const int node = i0 + o;
+          w.put(0, node, wq * S * r.Gp);
           for (int c = 0; c < 3; ++c) {
-            fix_add(a.acc, (1 + c) * Ng + g, wq * (1.0 - s) * S1 * r.D[c], up);
-            fix_add(a.acc, (4 + c) * Ng + g, wq * s * S1 * r.D[c], up);
+            w.put(1 + c, node, wq * (1.0 - s) * S1 * r.D[c]);
+            w.put(4 + c, node, wq * s * S1 * r.D[c]);
           }
         }
       });
@@ -406,21 +452,26 @@ __global__ __launch_bounds__(kBlock) void k_adj_particle(AdjArgs a) {
         const int i0 = (int)floor(xs + 0.5);
         for (int o = -1; o <= 1; ++o) {
           const double S = s2(xs - (double)(i0 + o));
-          const int64_t g = wrapi(i0 + o, n);
-          for (int c = 0; c < 3; ++c) fix_add(a.acc, ((e ? 4 : 1) + c) * Ng + g, S * (e ? r.Ap[c] : r.Am[c]), up);
+          for (int c = 0; c < 3; ++c) w.put((e ? 4 : 1) + c, i0 + o, S * (e ? r.Ap[c] : r.Am[c]));
         }
       }
-    } else {
-      a.gx[li] = lx + rev_x(r, G) + qdv * G.Mx;
-      for (int c = 0; c < 3; ++c) a.gP[c * a.np + li] = r.P[c];
-      a.gq[li] = r.q + (q < 0.0 ? -r.m : r.m) + dot3(v, G.Mc) / M.dV;
+    }
+    __syncthreads();
+    for (int k = threadIdx.x; k < kAdjVals * kAdjWin; k += kBlock) {
+      const unsigned long long H = sacc[2 * k], L = sacc[2 * k + 1];
+      if (H | L) {
+        const int f = k / kAdjWin, rel = k % kAdjWin;
+        unsigned long long* dst = a.acc + 2 * (f * Ng + wrapi(swlo + rel, n));
+        if (H) atomicAdd(dst, H);
+        if (L) atomicAdd(dst + 1, L);
+      }
     }
   }
   if (a.mode == ADJ_BOUND) {  // per-block sum, fixed order
     red[threadIdx.x] = bound;
     __syncthreads();
-    for (int w = kBlock / 2; w > 0; w >>= 1) {
-      if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    for (int s2w = kBlock / 2; s2w > 0; s2w >>= 1) {
+      if ((int)threadIdx.x < s2w) red[threadIdx.x] += red[threadIdx.x + s2w];
       __syncthreads();
     }
     if (threadIdx.x == 0) a.partials[blockIdx.x] = red[0];
