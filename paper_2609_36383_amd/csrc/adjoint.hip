@@ -22,8 +22,9 @@
 //
 // Kernels: k_adj_particle (one thread per particle; the hand-written reverse sweep of the
 // orbit gathers, the GM-HC push with its gamma_HC, B_eff and K chain, the secant
-// velocity and the orbit deposit, and the scatter of the field cotangents as exact
-// fixed-point sums), k_adj_field (one thread per Fourier mode; the conjugate transpose of
+// velocity and the orbit deposit), k_adj_iter (one transposed outer iteration per launch
+// from the values k_adj_particle cached: the transposed deposit, the per-particle solve
+// and the scatter of the field cotangents as exact fixed-point sums), k_adj_field (one thread per Fourier mode; the conjugate transpose of
 // the projected continuity / CN update), k_energy_grad and k_adj_init_field, and small
 // reductions.
 #include <hip/hip_runtime.h>
@@ -337,8 +338,6 @@ __device__ __forceinline__ double rev_x(const Rev& r, const Gath& G) {
   return s;
 }
 
-}  // namespace
-
 // Exact fixed-point accumulation of one workgroup's scattered values: a window of
 // kAdjWin consecutive (unwrapped) nodes from wlo per field array in LDS, summed with 64-bit
 // integer LDS atomics and added to the global accumulator once per workgroup; values at
@@ -366,7 +365,106 @@ struct WinAcc {
   }
 };
 
+// Gather of the adjoint current mu along the orbit (the transposed deposit): Mc = sum_g
+// mu_g int S_g, Mdx = sum_g (v . mu_g) int s S_g'.
+__device__ __forceinline__ void gather_mu(const AdjArgs& a, double xi0, double dxi, const double v[3], double Mc[3],
+                                         double& Mdx) {
+  const int64_t Ng = a.M.Ng;
+  const int n = a.M.n[0];
+  const double ih = a.M.inv_h[0];
+  Mc[0] = Mc[1] = Mc[2] = 0.0;
+  Mdx = 0.0;
+  walk_orbit(a, xi0, dxi, [&](double s, double wq) {
+    const double xs = xi0 + s * dxi;
+    const int i0 = (int)floor(xs + 0.5);
+    for (int o = -1; o <= 1; ++o) {
+      const double t = xs - (double)(i0 + o);
+      const double S = s2(t), S1 = s2d(t) * ih;
+      const int g = wrapi(i0 + o, n);
+      double vm = 0.0;
+      for (int c = 0; c < 3; ++c) {
+        const double m = a.mu[c * Ng + g];
+        Mc[c] += wq * S * m;
+        vm += v[c] * m;
+      }
+      Mdx += wq * s * S1 * vm;
+    }
+  });
+}
+
+__device__ __forceinline__ void rev_gath(const Rev& r, double g[kAdjGath]) {
+  g[0] = r.Gp;
+  for (int c = 0; c < 3; ++c) {
+    g[1 + c] = r.D[c];
+    g[4 + c] = r.Am[c];
+    g[7 + c] = r.Ap[c];
+  }
+}
+
+}  // namespace
+
+// ADJ_PREP and ADJ_FINAL: the full reverse sweep of one particle's evaluation.
 __global__ __launch_bounds__(kBlock) void k_adj_particle(AdjArgs a) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= a.np) return;
+  const Mesh& M = a.M;
+  const int64_t li = a.id[i];
+  const double x = a.x[i];
+  const double q = a.q[i], m = fabs(q);
+  double P[3], v[3], lP[3];
+  for (int c = 0; c < 3; ++c) {
+    P[c] = a.P[c * a.ps + i];
+    v[c] = a.vbar[c * a.np + li];
+    lP[c] = a.lP[c * a.np + li];
+  }
+  const double lx = a.lx[li];
+  Gath G;
+  gather(a, x, v, G);
+  Fwd f;
+  forward(G, P, q, m, v[0], a.dt, a.kappa, f);
+  Rev r;
+  // column x of dF/dvbar (F depends on vbar through vbar_x only)
+  double J[3];
+  for (int c = 0; c < 3; ++c) {
+    const double e[3] = {c == 0 ? 1.0 : 0.0, c == 1 ? 1.0 : 0.0, c == 2 ? 1.0 : 0.0}, z[3] = {0.0, 0.0, 0.0};
+    reverse(f, e, z, r);
+    J[c] = rev_v0(r, G, a.dt);
+    if (a.mode == ADJ_PREP) {
+      double g[kAdjGath];
+      rev_gath(r, g);
+      for (int k = 0; k < kAdjGath; ++k) a.cache[(4 + c * kAdjGath + k) * a.ps + i] = g[k];
+    }
+  }
+  // right side: x^{n+1} = x + dt vbar_x, P^{n+1}(vbar), and the transposed deposit
+  const double z3[3] = {0.0, 0.0, 0.0};
+  reverse(f, z3, lP, r);
+  const double base = a.dt * lx + rev_v0(r, G, a.dt);
+  if (a.mode == ADJ_PREP) {
+    double g[kAdjGath];
+    rev_gath(r, g);
+    for (int k = 0; k < kAdjGath; ++k) a.cache[(4 + 3 * kAdjGath + k) * a.ps + i] = g[k];
+    for (int c = 0; c < 3; ++c) a.cache[c * a.ps + i] = J[c];
+    a.cache[3 * a.ps + i] = base;
+    return;
+  }
+  const double qdv = q / M.dV;
+  double rhs[3];
+  for (int c = 0; c < 3; ++c) rhs[c] = qdv * G.Mc[c];
+  rhs[0] += base + qdv * a.dt * G.Mdx;
+  double mv[3];
+  mv[1] = rhs[1];
+  mv[2] = rhs[2];
+  mv[0] = (rhs[0] + J[1] * rhs[1] + J[2] * rhs[2]) / (1.0 - J[0]);
+  reverse(f, mv, lP, r);
+  a.gx[li] = lx + rev_x(r, G) + qdv * G.Mx;
+  for (int c = 0; c < 3; ++c) a.gP[c * a.np + li] = r.P[c];
+  a.gq[li] = r.q + (q < 0.0 ? -r.m : r.m) + dot3(v, G.Mc) / M.dV;
+}
+
+// ADJ_BOUND and ADJ_SCATTER: one transposed outer iteration from the cached values.  The
+// reverse sweep is linear in its cotangents, so the gather cotangents for (mu_v, lP) are
+// sum_c mu_v,c (those of e_c) + (those of lP).
+__global__ __launch_bounds__(kBlock) void k_adj_iter(AdjArgs a) {
   __shared__ double red[kBlock];
   __shared__ unsigned long long sacc[2 * kAdjVals * kAdjWin];
   __shared__ int swlo;
@@ -374,107 +472,81 @@ __global__ __launch_bounds__(kBlock) void k_adj_particle(AdjArgs a) {
   const bool live = i < a.np;
   const Mesh& M = a.M;
   const double ih = M.inv_h[0];
-  double bound = 0.0;
-  int64_t li = 0;
-  double x = 0.0, q = 0.0, v[3] = {0.0, 0.0, 0.0}, lx = 0.0;
-  Gath G{};
-  Rev r{};
+  double xi0 = 0.0, dxi = 0.0, g[kAdjGath];
+  for (int k = 0; k < kAdjGath; ++k) g[k] = 0.0;
   if (live) {
-    li = a.id[i];
-    x = a.x[i];
-    q = a.q[i];
-    const double m = fabs(q);
-    double P[3], lP[3];
-    for (int c = 0; c < 3; ++c) {
-      P[c] = a.P[c * a.ps + i];
-      v[c] = a.vbar[c * a.np + li];
-      lP[c] = a.lP[c * a.np + li];
-    }
-    lx = a.lx[li];
-    gather(a, x, v, G);
-    Fwd f;
-    forward(G, P, q, m, v[0], a.dt, a.kappa, f);
-    // column x of dF/dvbar (F depends on vbar through vbar_x only)
-    double J[3];
-    for (int c = 0; c < 3; ++c) {
-      const double e[3] = {c == 0 ? 1.0 : 0.0, c == 1 ? 1.0 : 0.0, c == 2 ? 1.0 : 0.0}, z[3] = {0.0, 0.0, 0.0};
-      reverse(f, e, z, r);
-      J[c] = rev_v0(r, G, a.dt);
-    }
-    // right side: x^{n+1} = x + dt vbar_x, P^{n+1}(vbar), and the transposed deposit
-    const double z3[3] = {0.0, 0.0, 0.0};
-    reverse(f, z3, lP, r);
+    const int64_t li = a.id[i];
+    const double q = a.q[i];
+    double v[3];
+    for (int c = 0; c < 3; ++c) v[c] = a.vbar[c * a.np + li];
+    xi0 = (a.x[i] - M.lo[0]) * ih;
+    dxi = a.dt * v[0] * ih;
+    double rhs[3] = {0.0, 0.0, 0.0}, Mdx = 0.0;
+    if (a.mu) gather_mu(a, xi0, dxi, v, rhs, Mdx);
     const double qdv = q / M.dV;
-    double rhs[3];
-    for (int c = 0; c < 3; ++c) rhs[c] = qdv * G.Mc[c];
-    rhs[0] += a.dt * lx + rev_v0(r, G, a.dt) + qdv * a.dt * G.Mdx;
-    double mv[3];
-    mv[1] = rhs[1];
-    mv[2] = rhs[2];
-    mv[0] = (rhs[0] + J[1] * rhs[1] + J[2] * rhs[2]) / (1.0 - J[0]);
-    reverse(f, mv, lP, r);
-    if (a.mode == ADJ_BOUND) {
-      bound = fabs(r.Gp);
-      for (int c = 0; c < 3; ++c) bound += 2.0 * ih * fabs(r.D[c]) + fabs(r.Am[c]) + fabs(r.Ap[c]);
-    } else if (a.mode == ADJ_FINAL) {
-      a.gx[li] = lx + rev_x(r, G) + qdv * G.Mx;
-      for (int c = 0; c < 3; ++c) a.gP[c * a.np + li] = r.P[c];
-      a.gq[li] = r.q + (q < 0.0 ? -r.m : r.m) + dot3(v, G.Mc) / M.dV;
+    for (int c = 0; c < 3; ++c) rhs[c] *= qdv;
+    rhs[0] += a.cache[3 * a.ps + i] + qdv * a.dt * Mdx;
+    const double J0 = a.cache[i], J1 = a.cache[a.ps + i], J2 = a.cache[2 * a.ps + i];
+    const double mv[3] = {(rhs[0] + J1 * rhs[1] + J2 * rhs[2]) / (1.0 - J0), rhs[1], rhs[2]};
+    for (int k = 0; k < kAdjGath; ++k) {
+      double s = a.cache[(4 + 3 * kAdjGath + k) * a.ps + i];
+      for (int c = 0; c < 3; ++c) s += mv[c] * a.cache[(4 + c * kAdjGath + k) * a.ps + i];
+      g[k] = s;
     }
   }
-  if (a.mode == ADJ_SCATTER) {  // uniform over the workgroup
-    const int64_t Ng = M.Ng;
-    const int n = M.n[0];
-    const double xi0 = (x - M.lo[0]) * ih, dxi = a.dt * v[0] * ih;
-    if (threadIdx.x == 0) swlo = INT_MAX;
-    for (int k = threadIdx.x; k < 2 * kAdjVals * kAdjWin; k += kBlock) sacc[k] = 0ull;
+  if (a.mode == ADJ_BOUND) {  // per-block sum of the bound, fixed order
+    double bound = fabs(g[0]);
+    for (int c = 0; c < 3; ++c) bound += 2.0 * ih * fabs(g[1 + c]) + fabs(g[4 + c]) + fabs(g[7 + c]);
+    red[threadIdx.x] = live ? bound : 0.0;
     __syncthreads();
-    if (live) atomicMin(&swlo, (int)floor(fmin(xi0, xi0 + dxi) + 0.5) - 1);
-    __syncthreads();
-    const WinAcc w{sacc, a.acc, swlo, n, Ng, a.fx_up};
-    if (live) {
-      walk_orbit(a, xi0, dxi, [&](double s, double wq) {
-        const double xs = xi0 + s * dxi;
-        const int i0 = (int)floor(xs + 0.5);
-        for (int o = -1; o <= 1; ++o) {
-          const double t = xs - (double)(i0 + o);
-          const double S = s2(t), S1 = s2d(t) * ih;
-          const int node = i0 + o;
-          w.put(0, node, wq * S * r.Gp);
-          for (int c = 0; c < 3; ++c) {
-            w.put(1 + c, node, wq * (1.0 - s) * S1 * r.D[c]);
-            w.put(4 + c, node, wq * s * S1 * r.D[c]);
-          }
-        }
-      });
-      for (int e = 0; e < 2; ++e) {
-        const double xs = xi0 + (e ? dxi : 0.0);
-        const int i0 = (int)floor(xs + 0.5);
-        for (int o = -1; o <= 1; ++o) {
-          const double S = s2(xs - (double)(i0 + o));
-          for (int c = 0; c < 3; ++c) w.put((e ? 4 : 1) + c, i0 + o, S * (e ? r.Ap[c] : r.Am[c]));
-        }
-      }
-    }
-    __syncthreads();
-    for (int k = threadIdx.x; k < kAdjVals * kAdjWin; k += kBlock) {
-      const unsigned long long H = sacc[2 * k], L = sacc[2 * k + 1];
-      if (H | L) {
-        const int f = k / kAdjWin, rel = k % kAdjWin;
-        unsigned long long* dst = a.acc + 2 * (f * Ng + wrapi(swlo + rel, n));
-        if (H) atomicAdd(dst, H);
-        if (L) atomicAdd(dst + 1, L);
-      }
-    }
-  }
-  if (a.mode == ADJ_BOUND) {  // per-block sum, fixed order
-    red[threadIdx.x] = bound;
-    __syncthreads();
-    for (int s2w = kBlock / 2; s2w > 0; s2w >>= 1) {
-      if ((int)threadIdx.x < s2w) red[threadIdx.x] += red[threadIdx.x + s2w];
+    for (int w = kBlock / 2; w > 0; w >>= 1) {
+      if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
       __syncthreads();
     }
     if (threadIdx.x == 0) a.partials[blockIdx.x] = red[0];
+    return;
+  }
+  const int64_t Ng = M.Ng;
+  const int n = M.n[0];
+  if (threadIdx.x == 0) swlo = INT_MAX;
+  for (int k = threadIdx.x; k < 2 * kAdjVals * kAdjWin; k += kBlock) sacc[k] = 0ull;
+  __syncthreads();
+  if (live) atomicMin(&swlo, (int)floor(fmin(xi0, xi0 + dxi) + 0.5) - 1);
+  __syncthreads();
+  const WinAcc w{sacc, a.acc, swlo, n, Ng, a.fx_up};
+  if (live) {
+    walk_orbit(a, xi0, dxi, [&](double s, double wq) {
+      const double xs = xi0 + s * dxi;
+      const int i0 = (int)floor(xs + 0.5);
+      for (int o = -1; o <= 1; ++o) {
+        const double t = xs - (double)(i0 + o);
+        const double S = s2(t), S1 = s2d(t) * ih;
+        const int node = i0 + o;
+        w.put(0, node, wq * S * g[0]);
+        for (int c = 0; c < 3; ++c) {
+          w.put(1 + c, node, wq * (1.0 - s) * S1 * g[1 + c]);
+          w.put(4 + c, node, wq * s * S1 * g[1 + c]);
+        }
+      }
+    });
+    for (int e = 0; e < 2; ++e) {
+      const double xs = xi0 + (e ? dxi : 0.0);
+      const int i0 = (int)floor(xs + 0.5);
+      for (int o = -1; o <= 1; ++o) {
+        const double S = s2(xs - (double)(i0 + o));
+        for (int c = 0; c < 3; ++c) w.put((e ? 4 : 1) + c, i0 + o, S * g[(e ? 7 : 4) + c]);
+      }
+    }
+  }
+  __syncthreads();
+  for (int k = threadIdx.x; k < kAdjVals * kAdjWin; k += kBlock) {
+    const unsigned long long H = sacc[2 * k], L = sacc[2 * k + 1];
+    if (H | L) {
+      const int f = k / kAdjWin, rel = k % kAdjWin;
+      unsigned long long* dst = a.acc + 2 * (f * Ng + wrapi(swlo + rel, n));
+      if (H) atomicAdd(dst, H);
+      if (L) atomicAdd(dst + 1, L);
+    }
   }
 }
 
@@ -719,6 +791,11 @@ inline unsigned nblocks(int64_t n) { return (unsigned)std::max<int64_t>((n + kBl
 hipError_t launch_adj_particle(const AdjArgs& a, hipStream_t s) {
   if (a.np == 0) return hipSuccess;
   hipLaunchKernelGGL(k_adj_particle, dim3(nblocks(a.np)), dim3(kBlock), 0, s, a);
+  return hipGetLastError();
+}
+hipError_t launch_adj_iter(const AdjArgs& a, hipStream_t s) {
+  if (a.np == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_adj_iter, dim3(nblocks(a.np)), dim3(kBlock), 0, s, a);
   return hipGetLastError();
 }
 int64_t adj_particle_blocks(int64_t np) { return nblocks(np); }

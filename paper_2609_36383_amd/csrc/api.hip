@@ -1724,6 +1724,7 @@ struct AdjScratch {
   double* mu;
   double* partials;
   double* red;
+  double* cache;
 };
 
 size_t adj_carve(const gmhc_ctx* c, char* base, AdjScratch& a) {
@@ -1743,6 +1744,7 @@ size_t adj_carve(const gmhc_ctx* c, char* base, AdjScratch& a) {
   a.mu = cv.take<double>(3 * Ng);
   a.partials = cv.take<double>((size_t)adj_particle_blocks(std::max<int64_t>(c->np, 1)));
   a.red = cv.take<double>(8);
+  a.cache = cv.take<double>((size_t)kAdjCache * std::max<int64_t>(c->np, 1));
   return (cv.off + 255) & ~(size_t)255;
 }
 
@@ -1792,6 +1794,7 @@ AdjArgs adj_args(const gmhc_ctx* c, const AdjScratch& a, const double* vbar, con
   r.Anp1 = a.trial + c->M.Ng;
   r.partials = a.partials;
   r.acc = a.acc;
+  r.cache = a.cache;
   return r;
 }
 
@@ -1853,12 +1856,17 @@ int32_t gmhc_adjoint_step(gmhc_ctx* ctx, void* scratch, size_t scratch_bytes, co
   gmhc_adjoint_report R{};
   double hr[2] = {0.0, 0.0};
   bool done = false;
+  {  // the values of the step that do not depend on the adjoint current
+    AdjArgs pa = adj_args(ctx, a, vbar, lx, lP);
+    pa.mode = ADJ_PREP;
+    HIPCK(launch_adj_particle(pa, s));
+  }
   for (int it = 0; it < ctx->cfg.max_outer && !done; ++it) {
     AdjArgs pa = adj_args(ctx, a, vbar, lx, lP);
     pa.mu = it ? a.mu : nullptr;
     // scale of the exact fixed-point sums from a bound on every scattered value
     pa.mode = ADJ_BOUND;
-    HIPCK(launch_adj_particle(pa, s));
+    HIPCK(launch_adj_iter(pa, s));
     HIPCK(launch_adj_sum(a.partials, ctx->np ? nb : 0, a.red, s));
     double B = 0.0;
     HIPCK(hipMemcpyAsync(&B, a.red, sizeof(double), hipMemcpyDeviceToHost, s));
@@ -1867,7 +1875,7 @@ int32_t gmhc_adjoint_step(gmhc_ctx* ctx, void* scratch, size_t scratch_bytes, co
     HIPCK(launch_zero(reinterpret_cast<double*>(a.acc), 2 * kAdjVals * Ng, s));
     pa.mode = ADJ_SCATTER;
     pa.fx_up = fx.up;
-    HIPCK(launch_adj_particle(pa, s));
+    HIPCK(launch_adj_iter(pa, s));
     HIPCK(launch_fix_to_double(a.acc, a.Pr, kAdjVals * Ng, fx, s));
     HIPCK(fft_nd(M, ctx->axes, kAdjVals, a.Pr, nullptr, a.Pb, nullptr, nullptr, false, false, s));
     HIPCK(launch_adj_field(fa, s));

@@ -356,12 +356,19 @@ hipError_t launch_permute_in(const double* const* src, void* const* dst, int dst
 
 // ---- adjoint of the step and of initialization (adjoint.hip; 1D, quadratic shape, FP64) --
 
-enum AdjMode { ADJ_BOUND = 0, ADJ_SCATTER = 1, ADJ_FINAL = 2 };
+enum AdjMode { ADJ_BOUND = 0, ADJ_SCATTER = 1, ADJ_FINAL = 2, ADJ_PREP = 3 };
 constexpr int kAdjVals = 7;  // scattered field arrays: grad phi, A^n (3), A^{n+1} (3)
+// Per-particle values of the step that do not depend on the adjoint current: the column
+// dv_out/dvbar_x (3), the part of the inner right side from the output cotangents (1), and
+// the gather cotangents (grad-phi-bar, D (3), A^- (3), A^+ (3)) of the reverse sweeps for
+// the unit cotangents of v_out along x, y, z and for the cotangent of P^{n+1} (4 x 10).
+constexpr int kAdjGath = 10;
+constexpr int kAdjCache = 4 + 4 * kAdjGath;
 
-// Per-particle reverse sweep at the converged step.  ADJ_BOUND: per-block sums of a bound
-// on the scattered values (for the fixed-point scale); ADJ_SCATTER: the cotangents of the
-// trial fields into acc; ADJ_FINAL: the cotangents of x, P and q.
+// Per-particle reverse sweep at the converged step.  ADJ_PREP (k_adj_particle): the values
+// above into cache; ADJ_BOUND (k_adj_iter): per-block sums of a bound on the values to be
+// scattered (for the fixed-point scale); ADJ_SCATTER (k_adj_iter): the cotangents of the
+// trial fields into acc; ADJ_FINAL (k_adj_particle): the cotangents of x, P and q.
 struct AdjArgs {
   Mesh M;
   int64_t np;
@@ -387,12 +394,14 @@ struct AdjArgs {
   double* partials;      // ADJ_BOUND: per-block sums of the scatter bound
   unsigned long long* acc;  // ADJ_SCATTER: [kAdjVals][Ng] fixed-point pairs
   double fx_up;
+  double* cache;         // [kAdjCache][ps]: written by ADJ_PREP, read by ADJ_BOUND / ADJ_SCATTER
   double* gx;            // ADJ_FINAL outputs, load order
   double* gP;
   double* gq;
 };
 
-hipError_t launch_adj_particle(const AdjArgs& a, hipStream_t s);
+hipError_t launch_adj_particle(const AdjArgs& a, hipStream_t s);  // ADJ_PREP, ADJ_FINAL
+hipError_t launch_adj_iter(const AdjArgs& a, hipStream_t s);      // ADJ_BOUND, ADJ_SCATTER
 int64_t adj_particle_blocks(int64_t np);
 
 struct AdjFieldArgs {
