@@ -22,13 +22,15 @@ from . import gmhc as G
 
 
 class FieldEnergyRun(torch.autograd.Function):
-    """W(T) = FieldEnergyRun.apply(x, u, q, cfg, steps, every, device)."""
+    """W(T) = FieldEnergyRun.apply(x, u, q, cfg, steps, every, device, potentials)."""
 
     @staticmethod
-    def forward(ctx, x, u, q, cfg, steps, every, device):
+    def forward(ctx, x, u, q, cfg, steps, every, device, potentials=None):
         n = int(q.numel())
         sim = G.Simulation(cfg, n, device=device)
         sim.load_particles(x.detach().cpu().numpy(), u.detach().cpu().numpy(), q.detach().cpu().numpy())
+        if potentials is not None:
+            sim.load_potentials(*potentials)
         sim.initialize()
         nbytes = sim.state_bytes()
         ckpt = {}
@@ -95,13 +97,14 @@ class FieldEnergyRun(torch.autograd.Function):
         gq += gq_step
         torch.cuda.synchronize(dev)
         dx, du, dq = ctx.devices
-        return gx.to(dx), gu.to(du), gq.to(dq), None, None, None, None
+        return gx.to(dx), gu.to(du), gq.to(dq), None, None, None, None, None
 
 
-def field_energy_run(x, u, q, cfg, steps, every=10, device="cuda"):
+def field_energy_run(x, u, q, cfg, steps, every=10, device="cuda", potentials=None):
     """W(T) after `steps` steps from the particles (x [N], u [3][N], q [N], float64 torch
-    tensors, any device), differentiable with respect to x, u and q."""
-    return FieldEnergyRun.apply(x, u, q, cfg, int(steps), int(every), device)
+    tensors, any device), differentiable with respect to x, u and q.  potentials: optional
+    initial (A0, U0) [3][Ng] arrays, held fixed."""
+    return FieldEnergyRun.apply(x, u, q, cfg, int(steps), int(every), device, potentials)
 
 
 def quiet1d_inputs(w, eps, u0, device="cpu"):

@@ -20,14 +20,42 @@ from paper_2609_36383_amd import workloads as W
 pytestmark = pytest.mark.gpu
 
 
-def _gpu_grad(w, steps, every):
-    cfg = G.config_from_dict(W.config_dict(w))
+def _gpu_grad(w, steps, every, potentials=None, **over):
+    cfg = G.config_from_dict(W.config_dict(w), **over)
     eps = torch.full((len(w["modes"]),), w["eps"], dtype=torch.float64, requires_grad=True)
     u0 = torch.tensor(w["u_drift"], dtype=torch.float64, requires_grad=True)
     x, u, q = A.quiet1d_inputs(w, eps, u0)
-    Wt = A.field_energy_run(x, u, q, cfg, steps, every, "cuda:0")
+    Wt = A.field_energy_run(x, u, q, cfg, steps, every, "cuda:0", potentials)
     Wt.backward()
     return float(Wt.detach()), np.concatenate([eps.grad.numpy(), [u0.grad.item()]])
+
+
+def _gpu_fd(w, steps, h=1e-6, potentials=None, **over):
+    """Central differences of GPU runs along eps_1..eps_M and u0."""
+    cfg = G.config_from_dict(W.config_dict(w), **over)
+    nm = len(w["modes"])
+    fd = np.zeros(nm + 1)
+    for k in range(nm + 1):
+        vals = []
+        for sgn in (1.0, -1.0):
+            eps = torch.full((nm,), w["eps"], dtype=torch.float64)
+            u0 = torch.tensor(w["u_drift"], dtype=torch.float64)
+            if k < nm:
+                eps[k] += sgn * h
+            else:
+                u0 += sgn * h
+            x, u, q = A.quiet1d_inputs(w, eps, u0)
+            sim = G.Simulation(cfg, q.numel(), device="cuda:0")
+            sim.load_particles(x.numpy()[None], u.numpy(), q.numpy())
+            if potentials is not None:
+                sim.load_potentials(*potentials)
+            sim.initialize()
+            for _ in range(steps):
+                sim.step()
+            vals.append(sim.diagnostics()["field"])
+            sim.close()
+        fd[k] = (vals[0] - vals[1]) / (2.0 * h)
+    return fd
 
 
 def _seeds(w):
@@ -73,32 +101,46 @@ def test_adjoint_matches_central_differences_full_size():
     steps, every = 50, 10
     print(f"adjoint vs central differences: {w['num_particles']} particles, {steps} steps", flush=True)
     Wg, gg = _gpu_grad(w, steps, every)
-    cfg = G.config_from_dict(W.config_dict(w))
-    nm = len(w["modes"])
-    h = 1e-6
-    fd = np.zeros(nm + 1)
-    for k in range(nm + 1):
-        vals = []
-        for sgn in (1.0, -1.0):
-            eps = torch.full((nm,), w["eps"], dtype=torch.float64)
-            u0 = torch.tensor(w["u_drift"], dtype=torch.float64)
-            if k < nm:
-                eps[k] += sgn * h
-            else:
-                u0 += sgn * h
-            x, u, q = A.quiet1d_inputs(w, eps, u0)
-            sim = G.Simulation(cfg, q.numel(), device="cuda:0")
-            sim.load_particles(x.numpy()[None], u.numpy(), q.numpy())
-            sim.initialize()
-            for _ in range(steps):
-                sim.step()
-            vals.append(sim.diagnostics()["field"])
-            sim.close()
-        fd[k] = (vals[0] - vals[1]) / (2.0 * h)
+    fd = _gpu_fd(w, steps)
     err = np.abs(gg - fd).max() / np.abs(fd).max()
     print(f"W {Wg:.6e}; grad rel err vs central differences {err:.2e}", flush=True)
     print("adjoint", gg, "\nFD     ", fd, flush=True)
     assert err <= 1e-7
+
+
+def test_adjoint_does_not_depend_on_the_outer_solver_or_the_sort():
+    """The adjoint differentiates the converged step: the paper's Anderson outer solver
+    (damping 0.5), and sorting the particles by cell every step, give the gradient of
+    damped Picard on unsorted particles, to the solver tolerance."""
+    w = W.spec("tsi1d_big", n=(64,), ppc=32, length=(4.0 * math.pi,))
+    steps, every = 12, 4
+    _, g_ref = _gpu_grad(w, steps, every)
+    _, g_and = _gpu_grad(w, steps, every, outer_scheme=1, beta=0.5)
+    _, g_srt = _gpu_grad(w, steps, every, sort_every=1)
+    for name, g in (("anderson", g_and), ("sorted", g_srt)):
+        err = np.abs(g - g_ref).max() / np.abs(g_ref).max()
+        print(f"{name}: rel diff {err:.2e}", flush=True)
+        assert err <= 1e-9
+
+
+def test_adjoint_with_initial_potentials():
+    """Nonzero initial potentials A0, U0 (canonical momenta P = m kappa u + q A0(x) at
+    initialization): adjoint against central differences of GPU runs."""
+    w = W.spec("tsi1d_big", n=(64,), ppc=16, length=(4.0 * math.pi,))
+    steps, every = 8, 4
+    ng = w["n"][0]
+    xg = w["lo"][0] + np.arange(ng) * w["length"][0] / ng
+    k = 2.0 * math.pi / w["length"][0]
+    A0 = np.zeros((3, ng))
+    U0 = np.zeros((3, ng))
+    A0[1] = 0.02 * np.cos(k * xg)
+    A0[2] = 0.01 * np.sin(2.0 * k * xg + 0.4)
+    U0[1] = 0.005 * np.sin(k * xg)
+    _, gg = _gpu_grad(w, steps, every, potentials=(A0, U0))
+    fd = _gpu_fd(w, steps, potentials=(A0, U0))
+    err = np.abs(gg - fd).max() / np.abs(fd).max()
+    print(f"with potentials: rel err vs central differences {err:.2e}", flush=True)
+    assert err <= 1e-6
 
 
 def test_energy_grad_is_twice_the_energy_along_the_state():
