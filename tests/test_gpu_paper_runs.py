@@ -12,6 +12,12 @@ Weibel/filamentation (WBI):
   change and of the structural residuals stay within ten times the printed maxima (they
   come out below them), and the outer iterations as the paper counts them (accepted
   updates plus one) within 5% of the printed mean.
+* WBI-0.04 through T = 100 (2500 steps) with the paper's Anderson settings: the energy
+  change and the structural residuals within ten times the printed maxima, the outer
+  mean within 15% of the printed one.  The same run on the default path (undamped
+  Picard under the device outer test) is bounded by ten outer tolerances instead: that
+  iteration accepts each step with its residual just under the tolerance, and the energy
+  change grows by about 1e-15 per step once the instability is nonlinear.
 
 Two-stream (TSI):
 * Parity: the 32 x 4 x 4 reduction with the paper's 10 pairs per cell against the oracle.
@@ -304,3 +310,38 @@ def test_wbi_0p04_through_end_time_on_the_device_controlled_path():
     assert worst["energy_rel"] <= 10.0 * W.config_dict(w)["tol_outer_rel"]
     for k in keys[1:]:
         assert worst[k] <= 10.0 * printed[k], k
+
+
+def test_wbi_0p04_anderson_through_end_time_within_ten_times_printed():
+    """WBI-0.04 through T = 100 (2500 steps) with the paper's outer solver (Anderson, M = 4,
+    beta = 0.5): the energy change and the structural residuals within ten times the
+    printed maxima, and the mean outer iteration count within 15% of the printed one."""
+    G = _gpu()
+    g = GOLD["WBI-0.04"]
+    steps = int(round(g["end_time"] / g["dt"]))
+    w = W.spec("wbi", dt=g["dt"], eig_gamma=GW)
+    sim = G.Simulation(G.config_from_dict(W.config_dict(w), gl_order=0, outer_scheme=1, beta=0.5, sort_every=10),
+                       w["num_particles"])
+    _load(sim, w)
+    keys = ("energy_rel", "gauss_rms", "lorenz_rms", "chain_rms", "work_residual")
+    worst = dict.fromkeys(keys, 0.0)
+    outer = []
+    t0 = time.perf_counter()
+    for s in range(steps):
+        _, rep = sim.step()
+        outer.append(rep["outer_updates"] + 1)
+        d = sim.diagnostics()
+        for k in keys:
+            worst[k] = max(worst[k], abs(d[k]))
+        if (s + 1) % 500 == 0:
+            _say(f"WBI-0.04 Anderson step {s + 1}: t {d['t']:.2f} energy {worst['energy_rel']:.2e} "
+                 f"outer mean {np.mean(outer):.3f} ({time.perf_counter() - t0:.1f} s)")
+    sim.close()
+    printed = dict(energy_rel=g["max_energy_rel"], gauss_rms=g["max_gauss_rms"], lorenz_rms=g["max_lorenz_rms"],
+                   chain_rms=g["max_chain_rms"], work_residual=g["max_work_residual"])
+    for k in keys:
+        _say(f"WBI-0.04 Anderson max {k}: {worst[k]:.3e} (printed {printed[k]:.3e})")
+    assert abs(d["t"] - g["end_time"]) < 1e-9
+    for k in keys:
+        assert worst[k] <= 10.0 * printed[k], k
+    assert abs(np.mean(outer) - g["outer_mean"]) <= 0.15 * g["outer_mean"]
