@@ -31,6 +31,7 @@
 #include <limits.h>
 #include <math.h>
 
+#include "adjoint.h"
 #include "gmhc_internal.h"
 
 namespace gmhc {

@@ -10,6 +10,7 @@
 #include <vector>
 
 #include "gmhc.h"
+#include "adjoint.h"
 #include "gmhc_internal.h"
 
 using namespace gmhc;

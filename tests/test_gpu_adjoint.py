@@ -74,9 +74,10 @@ def _seeds(w):
 
 
 def test_adjoint_matches_oracle_tangent_reduced():
-    """64 cells, 2048 particles, 20 steps with checkpoints every 5: dW(T)/d(eps_1..8, u0)
-    from the GPU adjoint against the oracle's forward-mode derivatives."""
-    w = W.spec("tsi1d_big", n=(64,), ppc=32, length=(4.0 * math.pi,))
+    """64 cells, 2112 particles (eight workgroups of 256 and a ragged tail of 64), 20 steps
+    with checkpoints every 5: dW(T)/d(eps_1..8, u0) from the GPU adjoint against the
+    oracle's forward-mode derivatives."""
+    w = W.spec("tsi1d_big", n=(64,), ppc=33, length=(4.0 * math.pi,))
     steps, every = 20, 5
     print(f"adjoint vs oracle tangent: {w['num_particles']} particles, {steps} steps", flush=True)
     Wg, gg = _gpu_grad(w, steps, every)
