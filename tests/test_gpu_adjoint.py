@@ -144,6 +144,38 @@ def test_adjoint_with_initial_potentials():
     assert err <= 1e-6
 
 
+def test_adjoint_per_particle_directions_with_transverse_momenta():
+    """Beams with a transverse thermal spread (so the potentials A_y, A_z and the HC
+    rotation are active), and random per-particle directions of the positions, all three
+    momentum components and the charges: the directional derivatives from the GPU's
+    per-particle cotangents (gx, gu, gq) against the oracle's forward-mode derivatives
+    along the same directions."""
+    w = W.spec("tsi1d_big", n=(32,), ppc=20, length=(4.0 * math.pi,))
+    steps, every = 10, 4
+    x, u, q = W.particles(w)
+    n = q.size
+    rng = np.random.default_rng(17)
+    u = u + np.vstack([np.zeros(n), 0.1 * rng.standard_normal(n), 0.1 * rng.standard_normal(n)])
+    nd = 3
+    dx = 0.05 * rng.standard_normal((nd, n))
+    du = 0.1 * rng.standard_normal((nd, 3, n))
+    dq = q * rng.standard_normal((nd, n))
+    cfg = G.config_from_dict(W.config_dict(w))
+    xt = torch.tensor(x[0], requires_grad=True)
+    ut = torch.tensor(u, requires_grad=True)
+    qt = torch.tensor(q, requires_grad=True)
+    Wt = A.field_energy_run(xt, ut, qt, cfg, steps, every, "cuda:0")
+    Wt.backward()
+    gx, gu, gq = xt.grad.numpy(), ut.grad.numpy(), qt.grad.numpy()
+    dirs = np.array([(gx * dx[k]).sum() + (gu * du[k]).sum() + (gq * dq[k]).sum() for k in range(nd)])
+    E, dE, _ = O.tangent_run(O.config_from_dict(W.config_dict(w), gl_order=2), x[0], u, q, steps, dx=dx, du=du, dq=dq)
+    err = np.abs(dirs - dE[2]).max() / np.abs(dE[2]).max()
+    print(f"per-particle directions: W gpu {float(Wt.detach()):.10e} oracle {E[2]:.10e}; rel err {err:.2e}", flush=True)
+    print("gpu   ", dirs, "\noracle", dE[2], flush=True)
+    assert abs(float(Wt.detach()) - E[2]) <= 1e-10 * E[2]
+    assert err <= 1e-9
+
+
 def test_energy_grad_is_twice_the_energy_along_the_state():
     """W is a quadratic form of the field state f, so dW/df . f = 2 W (Euler)."""
     w = W.spec("tsi1d_big", n=(64,), ppc=16, length=(4.0 * math.pi,))
