@@ -371,18 +371,19 @@ class OracleSim:
 
 
 def tangent_run(cfg, x, u, q, steps, dx=None, du=None, dq=None):
-    """Forward-mode derivatives of a 1D run (gmhc_tangent.cpp): from the initial particles
-    x [N], u [3][N], q [N] and the seed directions dx [nd][N], du [nd][3][N], dq [nd][N]
-    (None: zero; nd <= 16), run ``steps`` steps.  Returns (E, dE, outer): E = (W0, K0, WT,
+    """Forward-mode derivatives of a 1D or 2D run (gmhc_tangent.cpp): from the initial
+    particles x [dim][N], u [3][N], q [N] and the seed directions dx [nd][dim][N],
+    du [nd][3][N], dq [nd][N] (None: zero; nd <= 16), run ``steps`` steps.  Returns (E, dE, outer): E = (W0, K0, WT,
     KT), the field and kinetic energies at the start and at the end, dE [4][nd] their
     derivatives along each direction, and the outer map evaluations of the run."""
-    x = _f64(x).ravel()
-    n = x.size
-    u = _f64(u).reshape(3, n)
     q = _f64(q).ravel()
+    n = q.size
+    d = cfg.dim
+    x = _f64(x).reshape(d, n)
+    u = _f64(u).reshape(3, n)
     nd = max(int(np.shape(a)[0]) for a in (dx, du, dq) if a is not None) if any(
         a is not None for a in (dx, du, dq)) else 0
-    dx = _f64(np.zeros((nd, n)) if dx is None else dx).reshape(nd, n)
+    dx = _f64(np.zeros((nd, d, n)) if dx is None else dx).reshape(nd, d, n)
     du = _f64(np.zeros((nd, 3, n)) if du is None else du).reshape(nd, 3, n)
     dq = _f64(np.zeros((nd, n)) if dq is None else dq).reshape(nd, n)
     E = np.zeros(4)

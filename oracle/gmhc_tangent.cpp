@@ -1,5 +1,5 @@
 // gmhc_tangent.cpp -- forward-mode derivatives (the tangent-linear model) of a 1D
-// GM-HC-CN run of the CPU oracle.
+// GM-HC-CN run (1D or 2D) of the CPU oracle.
 //
 // TEST INFRASTRUCTURE ONLY, like gmhc_oracle.cpp: the independent reference for the
 // GPU library's reverse-mode adjoint.  The paper defines no derivative of its step;
@@ -19,7 +19,7 @@
 // (implicit-function theorem), so the result is the derivative of the converged step,
 // independent of the iteration history.
 //
-// Scope: dim = 1, the quadratic shape S_2, damped Picard outer iteration, zero initial
+// Scope: dim 1 or 2, the quadratic shape S_2, damped Picard outer iteration, zero initial
 // potentials (A^0 = U^0 = 0), FP64, no refinement.  The output is the field energy W
 // and the kinetic energy K at the start and after `steps` steps, each with its
 // derivatives along the directions seeded on the initial positions, mechanical
@@ -108,11 +108,14 @@ Dn sqrt(const Dn& a) {
 }
 Dn fabs(const Dn& a) { return a.v < 0.0 ? -a : a; }
 
-// ---- 1D mesh -------------------------------------------------------------------
-struct Mesh1 {
-  int n;
-  double lo, L, h, dV;
-  int wrap(int64_t i) const { return (int)(((i % n) + n) % n); }
+// ---- mesh (d = 1 or 2) ---------------------------------------------------------
+// Node g = i0 + n0 i1 at lo + i h (periodic); unresolved axes have n = 1.
+struct Mesh {
+  int d;
+  int n[2];
+  double lo[2], L[2], h[2], dV;
+  int Ng;
+  int wrap(int l, int64_t i) const { return (int)(((i % n[l]) + n[l]) % n[l]); }
 };
 
 // Centered quadratic B-spline S_2 (particle-shape paragraph of the solver section) and
@@ -141,75 +144,100 @@ Dn dS2(const Dn& t) {
 using DVec = std::vector<Dn>;
 using CVec = std::vector<cplx>;
 
-void fft(CVec& a, bool inverse) {  // radix-2, forward unnormalized, inverse scaled 1/n
-  const int n = (int)a.size();
+void fft1(cplx* a, int n, int stride, bool inverse) {  // radix-2, forward unnormalized
+  std::vector<cplx> b(n);
+  for (int i = 0; i < n; ++i) b[i] = a[(int64_t)i * stride];
   for (int i = 1, j = 0; i < n; ++i) {
     int bit = n >> 1;
     for (; j & bit; bit >>= 1) j ^= bit;
     j ^= bit;
-    if (i < j) std::swap(a[i], a[j]);
+    if (i < j) std::swap(b[i], b[j]);
   }
   for (int len = 2; len <= n; len <<= 1) {
     const double ang = 2.0 * kPi / len * (inverse ? 1.0 : -1.0);
     for (int i = 0; i < n; i += len)
       for (int k = 0; k < len / 2; ++k) {
         const cplx w(std::cos(ang * k), std::sin(ang * k));
-        const cplx u = a[i + k], v = a[i + k + len / 2] * w;
-        a[i + k] = u + v;
-        a[i + k + len / 2] = u - v;
+        const cplx u = b[i + k], v = b[i + k + len / 2] * w;
+        b[i + k] = u + v;
+        b[i + k + len / 2] = u - v;
       }
   }
-  if (inverse)
-    for (auto& z : a) z /= (double)n;
+  for (int i = 0; i < n; ++i) a[(int64_t)i * stride] = inverse ? b[i] / (double)n : b[i];
+}
+// Multi-dimensional transform of one layer: along axis 0 for every row, then along axis 1.
+void fft(const Mesh& M, CVec& a, bool inverse) {
+  for (int r = 0; r < M.n[1]; ++r) fft1(a.data() + (int64_t)r * M.n[0], M.n[0], 1, inverse);
+  if (M.d > 1)
+    for (int c = 0; c < M.n[0]; ++c) fft1(a.data() + c, M.n[1], M.n[0], inverse);
 }
 
 // Spectral field of every layer: S[l][m].
 using Spec = std::vector<CVec>;
 
-Spec to_spec(const Mesh1& M, const DVec& r) {
-  Spec s(ND + 1, CVec(M.n));
+Spec to_spec(const Mesh& M, const DVec& r) {
+  Spec s(ND + 1, CVec(M.Ng));
   for (int l = 0; l <= ND; ++l) {
-    for (int g = 0; g < M.n; ++g) s[l][g] = l ? r[g].d[l - 1] : r[g].v;
-    fft(s[l], false);
+    for (int g = 0; g < M.Ng; ++g) s[l][g] = l ? r[g].d[l - 1] : r[g].v;
+    fft(M, s[l], false);
   }
   return s;
 }
-DVec to_real(const Mesh1& M, const Spec& s) {
-  DVec r(M.n);
+DVec to_real(const Mesh& M, const Spec& s) {
+  DVec r(M.Ng);
   for (int l = 0; l <= ND; ++l) {
     CVec a = s[l];
-    fft(a, true);
-    for (int g = 0; g < M.n; ++g) (l ? r[g].d[l - 1] : r[g].v) = a[g].real();
+    fft(M, a, true);
+    for (int g = 0; g < M.Ng; ++g) (l ? r[g].d[l - 1] : r[g].v) = a[g].real();
   }
   return r;
 }
-Spec zero_spec(const Mesh1& M) { return Spec(ND + 1, CVec(M.n, 0.0)); }
+Spec zero_spec(const Mesh& M) { return Spec(ND + 1, CVec(M.Ng, 0.0)); }
 
-// Wavenumber of index m (signed index, zero at the even-grid Nyquist index) and the
-// Nyquist projector.
-double kx(const Mesh1& M, int m) {
-  if (m == M.n / 2) return 0.0;
-  const int ms = m <= M.n / 2 ? m : m - M.n;
-  return 2.0 * kPi * ms / M.L;
+// Wavenumbers of mode g (signed index, zero at an even-grid Nyquist index, as the spectral
+// derivative of the paper's Nyquist paragraph), and whether g lies on a Nyquist plane.
+void kvec(const Mesh& M, int g, double k[2], bool& nyq) {
+  const int idx[2] = {g % M.n[0], g / M.n[0]};
+  nyq = false;
+  for (int l = 0; l < 2; ++l) {
+    k[l] = 0.0;
+    if (l >= M.d) continue;
+    if (idx[l] == M.n[l] / 2) {
+      nyq = true;
+      continue;
+    }
+    const int ms = idx[l] <= M.n[l] / 2 ? idx[l] : idx[l] - M.n[l];
+    k[l] = 2.0 * kPi * ms / M.L[l];
+  }
 }
-void project(const Mesh1& M, Spec& s, bool on) {
+void project(const Mesh& M, Spec& s, bool on) {
   if (!on) return;
-  for (auto& l : s) l[M.n / 2] = 0.0;
+  for (int g = 0; g < M.Ng; ++g) {
+    double k[2];
+    bool nyq;
+    kvec(M, g, k, nyq);
+    if (nyq)
+      for (auto& l : s) l[g] = 0.0;
+  }
 }
-Spec ddx(const Mesh1& M, const Spec& s) {
+Spec dspec(const Mesh& M, const Spec& s, int ax) {  // d/dx_ax: i k_ax
   Spec r = s;
-  for (auto& l : r)
-    for (int m = 0; m < M.n; ++m) l[m] *= cplx(0.0, kx(M, m));
+  for (int g = 0; g < M.Ng; ++g) {
+    double k[2];
+    bool nyq;
+    kvec(M, g, k, nyq);
+    for (auto& l : r) l[g] *= cplx(0.0, ax < M.d ? k[ax] : 0.0);
+  }
   return r;
 }
 
 // ---- particle part -----------------------------------------------------------------
 struct Part {
-  Dn x, P[3], q, m, vbar[3];
+  Dn x[2], P[3], q, m, vbar[3];
 };
 
 struct TrialFields {  // real trial fields of one outer iteration
-  DVec gphi, An[3], Anp1[3];
+  DVec gphi[2], An[3], Anp1[3];
 };
 
 struct Dep {  // one particle's orbit-averaged shape, as (node, weight) pairs
@@ -253,86 +281,118 @@ void hc_map(const Dn um[3], const Dn tau[3], Dn up[3]) {
 
 struct Ctx {
   orc_config cfg;
-  Mesh1 M;
+  Mesh M;
   int ngl;
   double glx[64], glw[64];
 };
 
-// A_h(x) = sum_g F_g S_2((x - x_g)/h) of three real mesh arrays.
-void interp3(const Ctx& C, const DVec F[3], const Dn& x, Dn out[3]) {
-  const Mesh1& M = C.M;
-  Dn xi = (x - M.lo) / M.h;
-  const int64_t b = (int64_t)std::floor(xi.v);
-  for (int c = 0; c < 3; ++c) out[c] = cst(0.0);
-  for (int64_t i = b - 2; i <= b + 2; ++i) {
-    Dn S = S2(xi - (double)i);
-    if (S.v == 0.0) continue;
-    const int g = M.wrap(i);
-    for (int c = 0; c < 3; ++c) out[c] += F[c][g] * S;
+// Shape weights of the candidate nodes around a point with unit offsets xi[l]
+// (five candidates per resolved axis; nodes outside the support get zero) and their
+// derivatives with respect to the position, as (node, S, dS/dx_0, dS/dx_1).
+struct NodeW {
+  int g;
+  Dn S, dS[2];
+};
+void node_weights(const Mesh& M, const Dn xi[2], std::vector<NodeW>& out) {
+  out.clear();
+  int64_t b[2] = {(int64_t)std::floor(xi[0].v), M.d > 1 ? (int64_t)std::floor(xi[1].v) : 0};
+  const int r1 = M.d > 1 ? 2 : 0;
+  for (int64_t j = b[1] - r1; j <= b[1] + r1; ++j) {
+    Dn Sy = cst(1.0), dSy = cst(0.0);
+    if (M.d > 1) {
+      Sy = S2(xi[1] - (double)j);
+      dSy = dS2(xi[1] - (double)j) / M.h[1];
+    }
+    for (int64_t i = b[0] - 2; i <= b[0] + 2; ++i) {
+      Dn Sx = S2(xi[0] - (double)i), dSx = dS2(xi[0] - (double)i) / M.h[0];
+      NodeW w;
+      w.S = Sx * Sy;
+      w.dS[0] = dSx * Sy;
+      w.dS[1] = Sx * dSy;
+      if (w.S.v == 0.0 && w.dS[0].v == 0.0 && w.dS[1].v == 0.0) continue;
+      w.g = M.wrap(0, i) + M.n[0] * (M.d > 1 ? M.wrap(1, j) : 0);
+      out.push_back(w);
+    }
   }
+}
+
+// A_h(x) = sum_g F_g S_g(x) of three real mesh arrays.
+void interp3(const Ctx& C, const DVec F[3], const Dn x[2], Dn out[3]) {
+  const Mesh& M = C.M;
+  Dn xi[2];
+  for (int l = 0; l < 2; ++l) xi[l] = l < M.d ? (x[l] - M.lo[l]) / M.h[l] : cst(0.0);
+  std::vector<NodeW> nw;
+  node_weights(M, xi, nw);
+  for (int c = 0; c < 3; ++c) out[c] = cst(0.0);
+  for (const NodeW& w : nw)
+    for (int c = 0; c < 3; ++c) out[c] += F[c][w.g] * w.S;
 }
 
 // One orbit evaluation v_out = F(v_in) (no-explicit-A_t GM-HC step, mechanical
 // endpoints, electric-work secant velocities and their mean as the orbit velocity), with
-// the knot-split Gauss-Legendre orbit quadrature of the straight orbit x + s dt v_x.
+// the knot-split Gauss-Legendre orbit quadrature of the straight orbit x + s dt v.
 // dep, when given, receives the orbit-averaged shape of the evaluated orbit.
 void orbit_eval(const Ctx& C, const TrialFields& F, const Part& p, const Dn vin[3], Dn vout[3], Dn Pn1[3],
                 Dep* dep) {
-  const Mesh1& M = C.M;
+  const Mesh& M = C.M;
+  const int d = M.d;
   const double dt = C.cfg.dt, kappa = C.cfg.kappa;
-  Dn dx = dt * vin[0];
-  // knot split: S_2 has knots at half-integer node offsets; a crossing counts when
-  // strictly inside the orbit.
-  Dn xi0 = (p.x - M.lo) / M.h, dxi = dx / M.h;
+  // knot split: S_2 has knots at half-integer node offsets on every axis; a crossing
+  // counts when strictly inside the orbit.
+  Dn xi0[2], dxi[2];
   std::vector<Dn> brk{cst(0.0)};
-  const double e0 = xi0.v, e1 = xi0.v + dxi.v;
-  if (e1 > e0) {
-    for (int64_t j = (int64_t)std::floor(e0 - 0.5); j <= (int64_t)std::floor(e1 - 0.5) + 1; ++j) {
-      Dn s = ((double)j + 0.5 - xi0) / dxi;
-      if (s.v > 0.0 && s.v < 1.0) brk.push_back(s);
-    }
-  } else if (e1 < e0) {
-    for (int64_t j = (int64_t)std::floor(e0 - 0.5) + 1; j >= (int64_t)std::floor(e1 - 0.5) - 1; --j) {
-      Dn s = ((double)j + 0.5 - xi0) / dxi;
+  for (int l = 0; l < 2; ++l) {
+    xi0[l] = l < d ? (p.x[l] - M.lo[l]) / M.h[l] : cst(0.0);
+    dxi[l] = l < d ? dt * vin[l] / M.h[l] : cst(0.0);
+    if (l >= d || dxi[l].v == 0.0) continue;
+    const double e0 = xi0[l].v, e1 = xi0[l].v + dxi[l].v;
+    const int64_t ja = (int64_t)std::floor(std::min(e0, e1) - 0.5) - 1, jb = (int64_t)std::floor(std::max(e0, e1) - 0.5) + 1;
+    for (int64_t j = ja; j <= jb; ++j) {
+      Dn s = ((double)j + 0.5 - xi0[l]) / dxi[l];
       if (s.v > 0.0 && s.v < 1.0) brk.push_back(s);
     }
   }
   brk.push_back(cst(1.0));
   std::sort(brk.begin(), brk.end(), [](const Dn& a, const Dn& b) { return a.v < b.v; });
-  Dn gp = cst(0.0), D[3] = {cst(0.0), cst(0.0), cst(0.0)};
+  Dn gp[2] = {cst(0.0), cst(0.0)}, D[3][2];
+  for (int c = 0; c < 3; ++c) D[c][0] = D[c][1] = cst(0.0);
+  std::vector<NodeW> nw;
   for (size_t k = 0; k + 1 < brk.size(); ++k) {
     Dn a = brk[k], b = brk[k + 1];
     if (!(b.v > a.v)) continue;
     for (int qd = 0; qd < C.ngl; ++qd) {
       Dn s = a + (b - a) * C.glx[qd];
       Dn wq = (b - a) * C.glw[qd];
-      Dn xs = xi0 + s * dxi;
-      const int64_t bse = (int64_t)std::floor(xs.v);
-      for (int64_t i = bse - 2; i <= bse + 2; ++i) {
-        Dn t = xs - (double)i;
-        Dn S = S2(t), dS = dS2(t) / M.h;
-        if (S.v == 0.0 && dS.v == 0.0) continue;
-        const int g = M.wrap(i);
-        gp += wq * F.gphi[g] * S;
-        for (int c = 0; c < 3; ++c) D[c] += wq * ((1.0 - s) * F.An[c][g] + s * F.Anp1[c][g]) * dS;
-        if (dep && S.v != 0.0) dep->w.push_back({g, wq * S});
+      Dn xs[2] = {xi0[0] + s * dxi[0], xi0[1] + s * dxi[1]};
+      node_weights(M, xs, nw);
+      for (const NodeW& w : nw) {
+        for (int l = 0; l < d; ++l) gp[l] += wq * F.gphi[l][w.g] * w.S;
+        for (int c = 0; c < 3; ++c) {
+          Dn As = (1.0 - s) * F.An[c][w.g] + s * F.Anp1[c][w.g];
+          for (int l = 0; l < d; ++l) D[c][l] += wq * As * w.dS[l];
+        }
+        if (dep && w.S.v != 0.0) dep->w.push_back({w.g, wq * w.S});
       }
     }
   }
-  Dn Am[3], Ap[3];
+  Dn Am[3], Ap[3], xe[2];
   interp3(C, F.An, p.x, Am);
-  interp3(C, F.Anp1, p.x + dx, Ap);
+  for (int l = 0; l < 2; ++l) xe[l] = l < d ? p.x[l] + dt * vin[l] : cst(0.0);
+  interp3(C, F.Anp1, xe, Ap);
   const Dn& q = p.q;
   const Dn& m = p.m;
   Dn Aep[3], kick[3], pm[3];
   for (int c = 0; c < 3; ++c) {
     Aep[c] = 0.5 * (Am[c] + Ap[c]);
-    kick[c] = 0.5 * dt * q * (D[c] * vin[0]);
-    if (c == 0) kick[c] -= 0.5 * dt * q * gp;
+    Dn Dv = cst(0.0);
+    for (int l = 0; l < d; ++l) Dv += D[c][l] * vin[l];
+    kick[c] = 0.5 * dt * q * Dv;
+    if (c < d) kick[c] -= 0.5 * dt * q * gp[c];
     pm[c] = p.P[c] - q * Aep[c] + kick[c];
   }
-  // B_eff of K = D~^T - D~ (D~ the 3x3 zero-padded 3x1 D): (0, -D_z, D_y).
-  Dn Beff[3] = {cst(0.0), -D[2], D[1]};
+  // B_eff = (K23, -K13, K12) of K = D~^T - D~ with D~ the zero-padded 3x3 D.
+  auto Dz = [&](int c, int l) { return (l < d && l < 2) ? D[c][l] : cst(0.0); };
+  Dn Beff[3] = {Dz(2, 1) - Dz(1, 2), -(Dz(2, 0) - Dz(0, 2)), Dz(1, 0) - Dz(0, 1)};
   Dn um[3], tau[3], up[3], pp[3], pn[3], pn1[3], vEm[3], vEp[3];
   for (int c = 0; c < 3; ++c) {
     um[c] = pm[c] / (m * kappa);
@@ -407,7 +467,7 @@ struct State {
 // charge by continuity, solve the CN potential equations mode by mode).  The step is
 // linear in (state, j), so each layer is advanced on its own.
 void field_step(const Ctx& C, const State& S, const DVec j[3], State& T, TrialFields& F) {
-  const Mesh1& M = C.M;
+  const Mesh& M = C.M;
   const double h = C.cfg.dt, kap2 = C.cfg.kappa * C.cfg.kappa;
   Spec jh[3];
   for (int c = 0; c < 3; ++c) {
@@ -416,24 +476,28 @@ void field_step(const Ctx& C, const State& S, const DVec j[3], State& T, TrialFi
   }
   T.phi = T.psi = T.rho = zero_spec(M);
   for (int c = 0; c < 3; ++c) T.A[c] = T.U[c] = zero_spec(M);
-  Spec phih = zero_spec(M), Uh[3];
-  for (int c = 0; c < 3; ++c) Uh[c] = zero_spec(M);
-  for (int l = 0; l <= ND; ++l)
-    for (int m = 0; m < M.n; ++m) {
-      const double k = kx(M, m), a = kap2 * k * k, den = 1.0 + h * h * a / 4.0;
-      T.rho[l][m] = S.rho[l][m] - h * cplx(0.0, k) * jh[0][l][m];
-      const cplx rh = 0.5 * (S.rho[l][m] + T.rho[l][m]);
-      T.phi[l][m] = ((1.0 - h * h * a / 4.0) * S.phi[l][m] + h * S.psi[l][m] + 0.5 * h * h * kap2 * C.cfg.sigma1 * rh) / den;
-      T.psi[l][m] = 2.0 * (T.phi[l][m] - S.phi[l][m]) / h - S.psi[l][m];
-      phih[l][m] = 0.5 * (S.phi[l][m] + T.phi[l][m]);
+  Spec phih = zero_spec(M);
+  for (int g = 0; g < M.Ng; ++g) {
+    double k[2];
+    bool nyq;
+    kvec(M, g, k, nyq);
+    const double a = kap2 * (k[0] * k[0] + k[1] * k[1]), den = 1.0 + h * h * a / 4.0;
+    for (int l = 0; l <= ND; ++l) {
+      // continuity: rho^{n+1} = rho^n - dt i k . jh
+      const cplx divj = cplx(0.0, k[0]) * jh[0][l][g] + cplx(0.0, k[1]) * jh[1][l][g];
+      T.rho[l][g] = S.rho[l][g] - h * divj;
+      const cplx rh = 0.5 * (S.rho[l][g] + T.rho[l][g]);
+      T.phi[l][g] = ((1.0 - h * h * a / 4.0) * S.phi[l][g] + h * S.psi[l][g] + 0.5 * h * h * kap2 * C.cfg.sigma1 * rh) / den;
+      T.psi[l][g] = 2.0 * (T.phi[l][g] - S.phi[l][g]) / h - S.psi[l][g];
+      phih[l][g] = 0.5 * (S.phi[l][g] + T.phi[l][g]);
       for (int c = 0; c < 3; ++c) {
-        T.A[c][l][m] = ((1.0 - h * h * a / 4.0) * S.A[c][l][m] + h * S.U[c][l][m] +
-                        0.5 * h * h * kap2 * C.cfg.sigma2 * jh[c][l][m]) / den;
-        T.U[c][l][m] = 2.0 * (T.A[c][l][m] - S.A[c][l][m]) / h - S.U[c][l][m];
-        Uh[c][l][m] = 0.5 * (S.U[c][l][m] + T.U[c][l][m]);
+        T.A[c][l][g] = ((1.0 - h * h * a / 4.0) * S.A[c][l][g] + h * S.U[c][l][g] +
+                        0.5 * h * h * kap2 * C.cfg.sigma2 * jh[c][l][g]) / den;
+        T.U[c][l][g] = 2.0 * (T.A[c][l][g] - S.A[c][l][g]) / h - S.U[c][l][g];
       }
     }
-  F.gphi = to_real(M, ddx(M, phih));
+  }
+  for (int l = 0; l < M.d; ++l) F.gphi[l] = to_real(M, dspec(M, phih, l));
   for (int c = 0; c < 3; ++c) {
     F.An[c] = to_real(M, S.A[c]);
     F.Anp1[c] = to_real(M, T.A[c]);
@@ -441,21 +505,22 @@ void field_step(const Ctx& C, const State& S, const DVec j[3], State& T, TrialFi
 }
 
 // Energies of the state: field energy W = sum (|E|^2 / (2 sigma1) + |B|^2 / (2 sigma2)) dV
-// with E = -d_x phi - U, B = curl A = (0, -d_x A_z, d_x A_y); kinetic energy
+// with E = -grad phi - U and B = curl A (no z derivative); kinetic energy
 // sum |p|^2 / (m (gamma + 1)) with p = P - q A_h(x).
 void energies(const Ctx& C, const State& S, const std::vector<Part>& parts, Dn& W, Dn& K) {
-  const Mesh1& M = C.M;
-  DVec dphi = to_real(M, ddx(M, S.phi)), U[3], A[3];
+  const Mesh& M = C.M;
+  DVec gph[2], U[3], A[3], dA[3][2];
+  for (int l = 0; l < 2; ++l) gph[l] = to_real(M, dspec(M, S.phi, l));
   for (int c = 0; c < 3; ++c) {
     U[c] = to_real(M, S.U[c]);
     A[c] = to_real(M, S.A[c]);
+    for (int l = 0; l < 2; ++l) dA[c][l] = to_real(M, dspec(M, S.A[c], l));
   }
-  DVec dAy = to_real(M, ddx(M, S.A[1])), dAz = to_real(M, ddx(M, S.A[2]));
   W = cst(0.0);
-  for (int g = 0; g < M.n; ++g) {
-    Dn Ex = -dphi[g] - U[0][g], Ey = -U[1][g], Ez = -U[2][g];
-    Dn By = -dAz[g], Bz = dAy[g];
-    Dn e2 = Ex * Ex + Ey * Ey + Ez * Ez, b2 = By * By + Bz * Bz;
+  for (int g = 0; g < M.Ng; ++g) {
+    Dn E[3] = {-gph[0][g] - U[0][g], -gph[1][g] - U[1][g], -U[2][g]};
+    Dn B[3] = {dA[2][1][g], -dA[2][0][g], dA[1][0][g] - dA[0][1][g]};
+    Dn e2 = E[0] * E[0] + E[1] * E[1] + E[2] * E[2], b2 = B[0] * B[0] + B[1] * B[1] + B[2] * B[2];
     W += (e2 / (2.0 * C.cfg.sigma1) + b2 / (2.0 * C.cfg.sigma2)) * M.dV;
   }
   K = cst(0.0);
@@ -471,7 +536,7 @@ void energies(const Ctx& C, const State& S, const std::vector<Part>& parts, Dn& 
 // Mixed outer tests of the values (RMS over 3 Ng components, max over nodes of the node
 // norm), as the oracle's step applies them.
 bool outer_pass(const Ctx& C, const DVec H[3], const DVec j[3]) {
-  const int n = C.M.n;
+  const int n = C.M.Ng;
   double sr = 0, sh = 0, sj = 0, mx = 0;
   const double ta = C.cfg.tol_outer_abs, tr = C.cfg.tol_outer_rel;
   for (int g = 0; g < n; ++g) {
@@ -495,7 +560,7 @@ bool outer_pass(const Ctx& C, const DVec H[3], const DVec j[3]) {
 // One implicit step (Algorithm 1) with damped Picard on the mesh current, run until the
 // values pass the outer tests and the derivative parts of H(j) - j have settled.
 int step(const Ctx& C, State& S, std::vector<Part>& parts, int64_t& outer) {
-  const Mesh1& M = C.M;
+  const Mesh& M = C.M;
   const int64_t np = (int64_t)parts.size();
   DVec j[3];
   for (int c = 0; c < 3; ++c) j[c] = S.J[c];
@@ -525,7 +590,7 @@ int step(const Ctx& C, State& S, std::vector<Part>& parts, int64_t& outer) {
       if (!ok[i]) return -5;
     // orbit current deposit J_g = (1/dV) sum_i q_i v_out,i Sbar_ig, particle order
     DVec Jd[3];
-    for (int c = 0; c < 3; ++c) Jd[c].assign(M.n, cst(0.0));
+    for (int c = 0; c < 3; ++c) Jd[c].assign(M.Ng, cst(0.0));
     for (int64_t i = 0; i < np; ++i)
       for (const auto& e : dep[i].w)
         for (int c = 0; c < 3; ++c) Jd[c][e.first] += parts[i].q * vw[i][c] * e.second / M.dV;
@@ -538,7 +603,7 @@ int step(const Ctx& C, State& S, std::vector<Part>& parts, int64_t& outer) {
     ++outer;
     std::vector<Dn> hf, jf;
     for (int c = 0; c < 3; ++c)
-      for (int g = 0; g < M.n; ++g) {
+      for (int g = 0; g < M.Ng; ++g) {
         hf.push_back(H[c][g]);
         jf.push_back(j[c][g]);
       }
@@ -555,11 +620,13 @@ int step(const Ctx& C, State& S, std::vector<Part>& parts, int64_t& outer) {
       }
       for (int64_t i = 0; i < np; ++i) {
         Part& p = parts[i];
-        Dn xe = p.x + C.cfg.dt * vin[i][0];
-        const double k = std::floor((xe.v - M.lo) / M.L);  // periodic image, a constant shift
-        p.x = xe - k * M.L;
-        if (p.x.v >= M.lo + M.L) p.x -= cst(M.L);
-        if (p.x.v < M.lo) p.x += cst(M.L);
+        for (int l = 0; l < M.d; ++l) {
+          Dn xe = p.x[l] + C.cfg.dt * vin[i][l];
+          const double k = std::floor((xe.v - M.lo[l]) / M.L[l]);  // periodic image, a constant shift
+          p.x[l] = xe - k * M.L[l];
+          if (p.x[l].v >= M.lo[l] + M.L[l]) p.x[l] -= cst(M.L[l]);
+          if (p.x[l].v < M.lo[l]) p.x[l] += cst(M.L[l]);
+        }
         for (int c = 0; c < 3; ++c) {
           p.P[c] = Pn1[i][c];
           p.vbar[c] = vw[i][c];
@@ -568,7 +635,7 @@ int step(const Ctx& C, State& S, std::vector<Part>& parts, int64_t& outer) {
       return 0;
     }
     for (int c = 0; c < 3; ++c)
-      for (int g = 0; g < M.n; ++g) j[c][g] += C.cfg.beta * (H[c][g] - j[c][g]);
+      for (int g = 0; g < M.Ng; ++g) j[c][g] += C.cfg.beta * (H[c][g] - j[c][g]);
   }
   return -6;
 }
@@ -578,21 +645,21 @@ int step(const Ctx& C, State& S, std::vector<Part>& parts, int64_t& outer) {
 // neutralizing background cancelling the mean charge, phi from Gauss's law
 // (-Lap phi = sigma1 rho), psi = A = U = 0, canonical momenta P = p.
 void initialize(const Ctx& C, std::vector<Part>& parts, State& S) {
-  const Mesh1& M = C.M;
-  DVec rho(M.n, cst(0.0)), J[3];
-  for (int c = 0; c < 3; ++c) J[c].assign(M.n, cst(0.0));
+  const Mesh& M = C.M;
+  DVec rho(M.Ng, cst(0.0)), J[3];
+  for (int c = 0; c < 3; ++c) J[c].assign(M.Ng, cst(0.0));
+  std::vector<NodeW> nw;
   for (Part& p : parts) {
     Dn g = gamma_of(p.P, p.m, C.cfg.kappa);
     Dn v[3];
     for (int c = 0; c < 3; ++c) v[c] = p.P[c] / (p.m * g);
-    Dn xi = (p.x - M.lo) / M.h;
-    const int64_t b = (int64_t)std::floor(xi.v);
-    for (int64_t i = b - 2; i <= b + 2; ++i) {
-      Dn Sg = S2(xi - (double)i);
-      if (Sg.v == 0.0) continue;
-      const int gi = M.wrap(i);
-      rho[gi] += p.q * Sg / M.dV;
-      for (int c = 0; c < 3; ++c) J[c][gi] += p.q * v[c] * Sg / M.dV;
+    Dn xi[2];
+    for (int l = 0; l < 2; ++l) xi[l] = l < M.d ? (p.x[l] - M.lo[l]) / M.h[l] : cst(0.0);
+    node_weights(M, xi, nw);
+    for (const NodeW& w : nw) {
+      if (w.S.v == 0.0) continue;
+      rho[w.g] += p.q * w.S / M.dV;
+      for (int c = 0; c < 3; ++c) J[c][w.g] += p.q * v[c] * w.S / M.dV;
     }
     for (int c = 0; c < 3; ++c) p.vbar[c] = v[c];
   }
@@ -606,19 +673,22 @@ void initialize(const Ctx& C, std::vector<Part>& parts, State& S) {
     S.A[c] = S.U[c] = zero_spec(M);
   }
   S.phi = S.psi = zero_spec(M);
-  for (int l = 0; l <= ND; ++l)
-    for (int m = 0; m < M.n; ++m) {
-      const double k = kx(M, m);
-      if (k != 0.0) S.phi[l][m] = C.cfg.sigma1 * S.rho[l][m] / (k * k);
-    }
+  for (int g = 0; g < M.Ng; ++g) {
+    double k[2];
+    bool nyq;
+    kvec(M, g, k, nyq);
+    const double k2 = k[0] * k[0] + k[1] * k[1];
+    if (k2 > 0.0)
+      for (int l = 0; l <= ND; ++l) S.phi[l][g] = C.cfg.sigma1 * S.rho[l][g] / k2;
+  }
 }
 
 }  // namespace
 
 extern "C" {
 
-// Tangent-linear run: n particles x [n], u [3][n], q [n] (m = |q|) with nd <= 16 seed
-// directions dx [nd][n], du [nd][3][n], dq [nd][n] (the derivatives of the inputs along
+// Tangent-linear run: n particles x [dim][n], u [3][n], q [n] (m = |q|) with nd <= 16 seed
+// directions dx [nd][dim][n], du [nd][3][n], dq [nd][n] (the derivatives of the inputs along
 // each direction); steps implicit steps.  Out: E[4] = (W^0, K^0, W^T, K^T) and
 // dE[4][nd] their derivatives along each direction; *outer the map evaluations summed
 // over the steps.  Status 0, -1 (unsupported configuration), -5 (a particle solve
@@ -626,29 +696,37 @@ extern "C" {
 int orc_tangent_run(const orc_config* cfg, int64_t n, const double* x, const double* u, const double* q, int nd,
                     const double* dx, const double* du, const double* dq, int steps, double* E, double* dE,
                     int64_t* outer) {
-  if (cfg->dim != 1 || (cfg->shape_order != 0 && cfg->shape_order != 2) || cfg->outer_scheme != 0 ||
+  if (cfg->dim < 1 || cfg->dim > 2 || (cfg->shape_order != 0 && cfg->shape_order != 2) || cfg->outer_scheme != 0 ||
       cfg->refine_levels != 0 || nd < 0 || nd > kMaxDir || cfg->gl_order < 1 || cfg->gl_order > 64)
     return -1;
-  if (cfg->n[0] < 4 || (cfg->n[0] & (cfg->n[0] - 1)) != 0) return -1;
+  const int d = cfg->dim;
   ND = nd;
   Ctx C;
   C.cfg = *cfg;
-  C.M.n = cfg->n[0];
-  C.M.lo = cfg->lo[0];
-  C.M.L = cfg->len[0];
-  C.M.h = C.M.L / C.M.n;
-  C.M.dV = C.M.h;
+  C.M.d = d;
+  C.M.dV = 1.0;
+  for (int l = 0; l < 2; ++l) {
+    C.M.n[l] = l < d ? cfg->n[l] : 1;
+    C.M.lo[l] = l < d ? cfg->lo[l] : 0.0;
+    C.M.L[l] = l < d ? cfg->len[l] : 1.0;
+    C.M.h[l] = C.M.L[l] / C.M.n[l];
+    if (l < d) {
+      if (C.M.n[l] < 4 || (C.M.n[l] & (C.M.n[l] - 1)) != 0) return -1;
+      C.M.dV *= C.M.h[l];
+    }
+  }
+  C.M.Ng = C.M.n[0] * C.M.n[1];
   C.ngl = cfg->gl_order;
   orc_gl_rule(C.ngl, C.glx, C.glw);
   std::vector<Part> parts(n);
   for (int64_t i = 0; i < n; ++i) {
     Part& p = parts[i];
-    p.x = cst(x[i]);
     p.q = cst(q[i]);
     Dn uu[3];
     for (int c = 0; c < 3; ++c) uu[c] = cst(u[c * n + i]);
+    for (int l = 0; l < 2; ++l) p.x[l] = cst(l < d ? x[l * n + i] : 0.0);
     for (int k = 0; k < nd; ++k) {
-      p.x.d[k] = dx[k * n + i];
+      for (int l = 0; l < d; ++l) p.x[l].d[k] = dx[(k * d + l) * n + i];
       p.q.d[k] = dq[k * n + i];
       for (int c = 0; c < 3; ++c) uu[c].d[k] = du[(k * 3 + c) * n + i];
     }

@@ -1,6 +1,6 @@
 """Pins of the oracle's forward-mode derivatives (oracle/gmhc_tangent.cpp), CPU only.
 
-The tangent oracle carries derivatives through a 1D run (Algorithm 1 with the orbit
+The tangent oracle carries derivatives through a 1D or 2D run (Algorithm 1 with the orbit
 maps, the GM-HC step, the secant velocity and the CN field step) by dual-number
 arithmetic.  It is pinned here against what does not depend on it:
   * its values equal the main oracle's run (same step, separately written);
@@ -105,6 +105,44 @@ def test_single_beam_direction_and_zero_direction():
     assert np.all(dE[:, 1] == 0.0)
     assert abs((dE[2, 0] + dE[3, 0]) - (dE[0, 0] + dE[1, 0])) <= 1e-9 * abs(dE[1, 0])
     assert dE[1, 0] > 0.0
+
+
+def _case2d():
+    w = W.spec("weibel2d", n=(16, 16), ppc=4)
+    x, u, q = W.particles(w)
+    cfg = O.config_from_dict(W.config_dict(w), gl_order=3)
+    rng = np.random.default_rng(3)
+    n = q.size
+    dx = 0.05 * rng.standard_normal((3, 2, n))
+    du = 0.1 * rng.standard_normal((3, 3, n))
+    dq = q * rng.standard_normal((3, n))
+    return cfg, x, u, q, dx, du, dq
+
+
+def test_tangent_2d_values_derivatives_and_energy_identity():
+    """2D (16 x 16, 1024 particles, 3 steps): values equal the main oracle's run, the
+    derivatives along random directions of positions, momenta and charges equal central
+    differences of the main oracle, and d(K + W) is conserved."""
+    cfg, x, u, q, dx, du, dq = _case2d()
+    E, dE, _ = O.tangent_run(cfg, x, u, q, STEPS, dx=dx, du=du, dq=dq)
+
+    def run(xx, uu, qq):
+        s = O.OracleSim(cfg)
+        s.load_particles(xx, uu, qq)
+        s.initialize()
+        d0 = s.diagnostics()
+        for _ in range(STEPS):
+            s.step()
+        d = s.diagnostics()
+        return np.array([d0["field"], d0["kinetic"], d["field"], d["kinetic"]])
+
+    np.testing.assert_allclose(E, run(x, u, q), rtol=1e-11, atol=0)
+    h = 1e-6
+    for k in range(3):
+        fd = (run(x + h * dx[k], u + h * du[k], q + h * dq[k]) - run(x - h * dx[k], u - h * du[k], q - h * dq[k])) / (2 * h)
+        assert abs(dE[2, k] - fd[2]) <= 1e-6 * abs(fd[2]), (k, dE[2, k], fd[2])
+    start, end = dE[0] + dE[1], dE[2] + dE[3]
+    assert np.all(np.abs(end - start) <= 1e-9 * np.abs(dE).max(axis=0))
 
 
 def test_tangent_rejects_unsupported_configurations():
