@@ -280,9 +280,41 @@ def adjoint_block():
     eps = torch.full((len(w["modes"]),), w["eps"], dtype=torch.float64, requires_grad=True)
     u0 = torch.tensor(w["u_drift"], dtype=torch.float64, requires_grad=True)
     x, u, q = A.quiet1d_inputs(w, eps, u0)
+    out = _time_adjoint(lambda: A.field_energy_run(x, u, q, cfg, steps, every, "cuda:0"), w["num_particles"], steps)
+    out["workload"] = f"tsi1d_big: 1024 cells, {w['num_particles']} particles, {steps} steps, checkpoints every {every}, FP64"
+    out["grad_eps"] = [float(v) for v in eps.grad]
+    out["grad_u0"] = float(u0.grad)
+    return out
+
+
+def adjoint_block_2d():
+    """The same on the 2D Weibel workload (128 x 128, 1,048,576 particles), 20 steps with
+    checkpoints every 10: gradient of the final field energy with respect to every
+    particle's position, momentum and charge (reported: the derivative along the beam drift)."""
+    import torch
+
+    from paper_2609_36383_amd import adjoint as A
+    from paper_2609_36383_amd import gmhc as G
+    from paper_2609_36383_amd import workloads as W
+
+    w = W.spec("weibel2d")
+    steps, every = 20, 10
+    cfg = G.config_from_dict(W.config_dict(w))
+    x, u, q = W.particles(w)
+    xt = torch.tensor(x, requires_grad=True)
+    ut = torch.tensor(u, requires_grad=True)
+    qt = torch.tensor(q, requires_grad=True)
+    out = _time_adjoint(lambda: A.field_energy_run(xt, ut, qt, cfg, steps, every, "cuda:0"), w["num_particles"], steps)
+    out["workload"] = f"weibel2d: 128x128 mesh, {w['num_particles']} particles, {steps} steps, checkpoints every {every}, FP64"
+    out["grad_drift"] = float((ut.grad[2] * torch.sign(ut.detach()[2])).sum())
+    return out
+
+
+def _time_adjoint(run, n, steps):
+    import torch
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    Wt = A.field_energy_run(x, u, q, cfg, steps, every, "cuda:0")
+    Wt = run()
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     Wt.backward()
@@ -290,12 +322,8 @@ def adjoint_block():
     t2 = time.perf_counter()
     fn = Wt.grad_fn
     its = [r["iterations"] for r in fn.reports]
-    n = w["num_particles"]
     return {
-        "workload": f"tsi1d_big: 1024 cells, {n} particles, {steps} steps, checkpoints every {every}, FP64",
         "field_energy": float(Wt.detach()),
-        "grad_eps": [float(v) for v in eps.grad],
-        "grad_u0": float(u0.grad),
         "forward_s": t1 - t0,
         "backward_s": t2 - t1,
         "backward_rerun_s": fn.seconds["rerun"],
@@ -332,7 +360,7 @@ def main():
         copy_probe()
         return
     if args.adjoint_only:
-        print(json.dumps({"adjoint": adjoint_block()}), flush=True)
+        print(json.dumps({"adjoint": adjoint_block(), "adjoint_2d": adjoint_block_2d()}), flush=True)
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the library runs the orbit pass on a single MI355X "
@@ -389,6 +417,7 @@ def main():
         f["speedup_per_iteration_vs_fp64"] = other["value"] / r["value"]
     if not args.no_adjoint:
         out["adjoint"] = adjoint_block()
+        out["adjoint_2d"] = adjoint_block_2d()
     if not args.no_cpu_baseline:
         base = W.config_dict(w, fp32_bulk=main_fp32)
         out["cpu_baseline"] = cpu_baseline(w, base, r["ngl"], parts, shape=args.shape)

@@ -4,7 +4,8 @@ torch.autograd.Function over the C ABI's adjoint calls (include/gmhc.h).
 Argument marshalling and checkpoint bookkeeping only: the forward steps, the field-energy
 cotangent, every adjoint step and the adjoint of initialization run in libgmhc.
 
-Forward: load the particles (x [N], u = p/(m kappa) [3][N], q [N]; 1D), initialize, run
+Forward: load the particles (x [dim][N], or [N] in 1D; u = p/(m kappa) [3][N]; q [N]; dim 1
+or 2), initialize, run
 `steps` steps and return W(T), saving a checkpoint image of the accepted state every
 `every` steps.  Backward: from dW/d(state) at T, walk the checkpoint segments from last
 to first; each segment is re-run from its checkpoint (bitwise the same steps with
@@ -48,6 +49,7 @@ class FieldEnergyRun(torch.autograd.Function):
         W = sim.diagnostics()["field"]
         ctx.sim, ctx.ckpt, ctx.steps, ctx.every, ctx.save_fn = sim, ckpt, steps, every, save
         ctx.devices = (x.device, u.device, q.device)
+        ctx.xshape = x.shape
         ctx.reports = []
         ctx.seconds = {"rerun": 0.0, "adjoint_steps": 0.0}
         return torch.tensor(W, dtype=torch.float64)
@@ -56,13 +58,13 @@ class FieldEnergyRun(torch.autograd.Function):
     def backward(ctx, gW):
         sim, steps = ctx.sim, ctx.steps
         dev = sim.device
-        n, ng = sim.np, sim.ng
+        n, ng, d = sim.np, sim.ng, sim.d
         f64 = dict(dtype=torch.float64, device=dev)
         scratch = sim.adjoint_scratch()
         lf = torch.empty(9, ng, **f64)
         sim.energy_grad(lf)
         lf *= float(gW)
-        lx = torch.zeros(n, **f64)
+        lx = torch.zeros(d, n, **f64)
         lP = torch.zeros(3, n, **f64)
         gq = torch.zeros(n, **f64)
         gq_step = torch.empty(n, **f64)
@@ -91,18 +93,18 @@ class FieldEnergyRun(torch.autograd.Function):
                 gq += gq_step
             ctx.seconds["adjoint_steps"] += time.perf_counter() - t1
         sim.load(ctx.ckpt[0])
-        gx = torch.empty(n, **f64)
+        gx = torch.empty(d, n, **f64)
         gu = torch.empty(3, n, **f64)
         sim.adjoint_initialize(scratch, lx, lP, lf, gx, gu, gq_step)
         gq += gq_step
         torch.cuda.synchronize(dev)
         dx, du, dq = ctx.devices
-        return gx.to(dx), gu.to(du), gq.to(dq), None, None, None, None, None
+        return gx.reshape(ctx.xshape).to(dx), gu.to(du), gq.to(dq), None, None, None, None, None
 
 
 def field_energy_run(x, u, q, cfg, steps, every=10, device="cuda", potentials=None):
-    """W(T) after `steps` steps from the particles (x [N], u [3][N], q [N], float64 torch
-    tensors, any device), differentiable with respect to x, u and q.  potentials: optional
+    """W(T) after `steps` steps from the particles (x [dim][N] or [N] in 1D, u [3][N], q [N],
+    float64 torch tensors, any device), differentiable with respect to x, u and q.  potentials: optional
     initial (A0, U0) [3][Ng] arrays, held fixed."""
     return FieldEnergyRun.apply(x, u, q, cfg, int(steps), int(every), device, potentials)
 

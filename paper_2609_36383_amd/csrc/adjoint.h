@@ -6,16 +6,19 @@
 
 namespace gmhc {
 
-// ---- adjoint of the step and of initialization (adjoint.hip; 1D, quadratic shape, FP64) --
+// ---- adjoint of the step and of initialization (adjoint.hip; 1D and 2D, quadratic shape,
+// FP64) --
 
 enum AdjMode { ADJ_BOUND = 0, ADJ_SCATTER = 1, ADJ_FINAL = 2, ADJ_PREP = 3 };
-constexpr int kAdjVals = 7;  // scattered field arrays: grad phi, A^n (3), A^{n+1} (3)
-// Per-particle values of the step that do not depend on the adjoint current: the column
-// dv_out/dvbar_x (3), the part of the inner right side from the output cotangents (1), and
-// the gather cotangents (grad-phi-bar, D (3), A^- (3), A^+ (3)) of the reverse sweeps for
-// the unit cotangents of v_out along x, y, z and for the cotangent of P^{n+1} (4 x 10).
-constexpr int kAdjGath = 10;
-constexpr int kAdjCache = 4 + 4 * kAdjGath;
+// scattered field arrays in dimension d: grad phi (d), A^n (3), A^{n+1} (3)
+constexpr int adj_nvals(int d) { return d + 6; }
+// Per-particle values of the step that do not depend on the adjoint current: the columns
+// dv_out/dvbar_j, j < d (3 d), the part of the inner right side from the output
+// cotangents (d), and the gather cotangents (grad-phi-bar (d), D (3 d), A^- (3), A^+ (3))
+// of the reverse sweeps for the unit cotangents of v_out along x, y, z and for the
+// cotangent of P^{n+1} (4 sets).
+constexpr int adj_ngath(int d) { return 4 * d + 6; }
+constexpr int adj_ncache(int d) { return 4 * d + 4 * adj_ngath(d); }
 
 // Per-particle reverse sweep at the converged step.  ADJ_PREP (k_adj_particle): the values
 // above into cache; ADJ_BOUND (k_adj_iter): per-block sums of a bound on the values to be
@@ -35,18 +38,18 @@ struct AdjArgs {
   const int32_t* id;     // internal index -> load order
   // load order, component stride np
   const double* vbar;    // [3] converged orbit velocity of the step
-  const double* lx;      // [1] cotangent of x^{n+1}
+  const double* lx;      // [dim] cotangent of x^{n+1}
   const double* lP;      // [3] cotangent of P^{n+1}
   // trial fields of the converged current (real, stride Ng)
-  const double* gphi;    // [1]
+  const double* gphi;    // [dim]
   const double* An;      // [3]
   const double* Anp1;    // [3]
   const double* mu;      // [3] adjoint current (already projected); null = zero
   int mode;
   double* partials;      // ADJ_BOUND: per-block sums of the scatter bound
-  unsigned long long* acc;  // ADJ_SCATTER: [kAdjVals][Ng] fixed-point pairs
+  unsigned long long* acc;  // ADJ_SCATTER: [dim + 6][Ng] fixed-point pairs
   double fx_up;
-  double* cache;         // [kAdjCache][ps]: written by ADJ_PREP, read by ADJ_BOUND / ADJ_SCATTER
+  double* cache;         // [adj_ncache(dim)][ps]: written by ADJ_PREP, read by ADJ_BOUND / ADJ_SCATTER
   double* gx;            // ADJ_FINAL outputs, load order
   double* gP;
   double* gq;

@@ -1,5 +1,5 @@
 // adjoint.hip -- reverse-mode adjoint of the implicit step and of initialization for
-// one-dimensional runs with the quadratic shape in FP64.
+// one- and two-dimensional runs with the quadratic shape in FP64.
 //
 // The paper defines the step (Algorithm 1) but no derivative of it.  The adjoint here
 // differentiates the converged step, not its iteration history: the step's unknowns
@@ -16,9 +16,10 @@
 //     mu_j   = (dState'/dj)^T lf + (dPhi/dj)^T sum_i (dF_i/dPhi)^T mu_v,i
 //                                + (dPhi/dj)^T sum_i (dP^{n+1}_i/dPhi)^T lP_i
 // and the input cotangents follow by one more transposed product.  The per-particle
-// 3x3 system is solved directly (in 1D, F depends on vbar only through vbar_x, so only
-// one column of dF/dvbar is nonzero); the mesh equation is iterated like the outer
-// Picard iteration it transposes, with the same damping, until mu_j settles.
+// 3x3 system is solved directly (F depends on vbar only through its d resolved
+// components, so only d columns of dF/dvbar are nonzero); the mesh equation is iterated
+// like the outer Picard iteration it transposes, with the same damping, until mu_j
+// settles.
 //
 // Kernels: k_adj_particle (one thread per particle; the hand-written reverse sweep of the
 // orbit gathers, the GM-HC push with its gamma_HC, B_eff and K chain, the secant
@@ -68,85 +69,188 @@ __device__ __forceinline__ double dot3(const double a[3], const double b[3]) {
   return a[0] * b[0] + a[1] * b[1] + a[2] * b[2];
 }
 
-// Orbit quantities of one particle: the gathers the evaluation uses, their derivatives
-// with respect to the start x and the displacement dx = dt vbar_x, and the gathers of the
-// adjoint current mu along the orbit (the transpose of the deposit).
+// Weights of the 3^D stencil nodes around a point xs (unit offsets) and their first and
+// second derivatives with respect to the position: node (o_0, o_1) of the stencil, its
+// mesh index, S, dS/dx_j and d2S/dx_j dx_k.
+template <int D>
+struct NodeWeights {
+  int i0[2];
+  double w[2][3], w1[2][3], w2[2][3];  // per axis and offset -1, 0, +1: S_2, S_2' / h, S_2'' / h^2
+  __device__ __forceinline__ void at(const Mesh& M, const double xs[D]) {
+    int b[D];
+    for (int l = 0; l < D; ++l) b[l] = (int)floor(xs[l] + 0.5);
+    at_base(M, xs, b);
+  }
+  // the same with the stencil's centre node given (a segment's node, taken at its midpoint)
+  __device__ __forceinline__ void at_base(const Mesh& M, const double xs[D], const int b[D]) {
+    for (int l = 0; l < D; ++l) {
+      i0[l] = b[l];
+      const double ih = M.inv_h[l];
+      for (int o = 0; o < 3; ++o) {
+        const double t = xs[l] - (double)(i0[l] + o - 1);
+        w[l][o] = s2(t);
+        w1[l][o] = s2d(t) * ih;
+        w2[l][o] = s2dd(t) * ih * ih;
+      }
+    }
+  }
+  // node k = ox + 3 oy of the stencil
+  __device__ __forceinline__ int node(const Mesh& M, int k) const {
+    const int ox = k % 3;
+    int g = wrapi(i0[0] + ox - 1, M.n[0]);
+    if (D > 1) g += M.n[0] * wrapi(i0[1] + k / 3 - 1, M.n[1]);
+    return g;
+  }
+  __device__ __forceinline__ int unode(int l, int k) const { return i0[l] + (l == 0 ? k % 3 : k / 3) - 1; }
+  __device__ __forceinline__ void vals(int k, double& S, double dS[D], double ddS[D][D]) const {
+    const int o[2] = {k % 3, k / 3};
+    S = 1.0;
+    for (int l = 0; l < D; ++l) S *= w[l][o[l]];
+    for (int j = 0; j < D; ++j) {
+      dS[j] = 1.0;
+      for (int l = 0; l < D; ++l) dS[j] *= l == j ? w1[l][o[l]] : w[l][o[l]];
+      for (int m = 0; m < D; ++m) {
+        ddS[j][m] = 1.0;
+        for (int l = 0; l < D; ++l) {
+          const int ord = (l == j) + (l == m);
+          ddS[j][m] *= ord == 0 ? w[l][o[l]] : (ord == 1 ? w1[l][o[l]] : w2[l][o[l]]);
+        }
+      }
+    }
+  }
+};
+template <int D>
+constexpr int kStencil = D == 1 ? 3 : 9;
+
+// Orbit quantities of one particle: the gathers the evaluation uses (grad-phi-bar, D,
+// A^-, A^+), their derivatives with respect to the start x_j and the displacement
+// dx_j = dt vbar_j, and the gathers of the adjoint current mu along the orbit (the
+// transpose of the deposit).
+template <int D>
 struct Gath {
-  double Gp, D[3], Am[3], Ap[3];
-  double Gp_x, Gp_dx, D_x[3], D_dx[3], Am_x[3], Ap_x[3];
-  double Mc[3], Mx, Mdx;
+  double Gp[D], Dm[3][D], Am[3], Ap[3];
+  double Gp_x[D][D], Gp_dx[D][D], D_x[3][D][D], D_dx[3][D][D], Am_x[3][D], Ap_x[3][D];
+  double Mc[3], Mx[D], Mdx[D];
 };
 
 // Knot-split walk of the orbit xi(s) = xi0 + s dxi, s in [0, 1] (knots of S_2 at
-// half-integer node offsets), calling f(s, wq) at every Gauss-Legendre point.
-template <class Fn>
-__device__ __forceinline__ void walk_orbit(const AdjArgs& a, double xi0, double dxi, Fn&& f) {
+// half-integer node offsets on every axis), calling f(s, wq) at every Gauss-Legendre
+// point of every segment.
+template <int D, class Fn>
+__device__ __forceinline__ void walk_orbit(const AdjArgs& a, const double xi0[D], const double dxi[D], Fn&& f) {
+  double kn[D], sk[D];
+  for (int l = 0; l < D; ++l) {
+    kn[l] = dxi[l] > 0.0 ? floor(xi0[l] - 0.5) + 1.5 : ceil(xi0[l] - 0.5) - 0.5;
+    sk[l] = dxi[l] != 0.0 ? (kn[l] - xi0[l]) / dxi[l] : 2.0;
+  }
   double sa = 0.0;
-  // next knot strictly ahead of xi0 in the direction of motion
-  double kn = dxi > 0.0 ? floor(xi0 - 0.5) + 1.5 : ceil(xi0 - 0.5) - 0.5;
-  for (int c = 0; c <= kMaxCross + 1; ++c) {
+  for (int c = 0; c <= D * (kMaxCross + 1); ++c) {
     double sb = 1.0;
-    if (dxi != 0.0) {
-      const double sk = (kn - xi0) / dxi;
-      if (sk > 0.0 && sk < 1.0) sb = sk;
-    }
+    for (int l = 0; l < D; ++l)
+      if (sk[l] > sa && sk[l] < sb) sb = sk[l];
     if (sb > sa) {
       const double len = sb - sa;
       for (int k = 0; k < a.ngl; ++k) f(sa + len * a.glx[k], len * a.glw[k]);
     }
     if (sb >= 1.0) break;
+    for (int l = 0; l < D; ++l)
+      if (sk[l] <= sb) {
+        kn[l] += dxi[l] > 0.0 ? 1.0 : -1.0;
+        sk[l] = (kn[l] - xi0[l]) / dxi[l];
+      }
     sa = sb;
-    kn += dxi > 0.0 ? 1.0 : -1.0;
   }
 }
 
-__device__ void gather(const AdjArgs& a, double x, const double v[3], Gath& G) {
+// The same walk, calling f(sa, sb) once per knot-split segment [sa, sb].
+template <int D, class Fn>
+__device__ __forceinline__ void walk_segments(const double xi0[D], const double dxi[D], Fn&& f) {
+  double kn[D], sk[D];
+  for (int l = 0; l < D; ++l) {
+    kn[l] = dxi[l] > 0.0 ? floor(xi0[l] - 0.5) + 1.5 : ceil(xi0[l] - 0.5) - 0.5;
+    sk[l] = dxi[l] != 0.0 ? (kn[l] - xi0[l]) / dxi[l] : 2.0;
+  }
+  double sa = 0.0;
+  for (int c = 0; c <= D * (kMaxCross + 1); ++c) {
+    double sb = 1.0;
+    for (int l = 0; l < D; ++l)
+      if (sk[l] > sa && sk[l] < sb) sb = sk[l];
+    if (sb > sa) f(sa, sb);
+    if (sb >= 1.0) break;
+    for (int l = 0; l < D; ++l)
+      if (sk[l] <= sb) {
+        kn[l] += dxi[l] > 0.0 ? 1.0 : -1.0;
+        sk[l] = (kn[l] - xi0[l]) / dxi[l];
+      }
+    sa = sb;
+  }
+}
+
+template <int D>
+__device__ void gather(const AdjArgs& a, const double x[D], const double v[3], Gath<D>& G) {
   const Mesh& M = a.M;
-  const int n = M.n[0];
-  const double ih = M.inv_h[0];
-  const double xi0 = (x - M.lo[0]) * ih, dxi = a.dt * v[0] * ih;
   const int64_t Ng = M.Ng;
-  G = Gath{};
-  walk_orbit(a, xi0, dxi, [&](double s, double wq) {
-    const double xs = xi0 + s * dxi;
-    const int i0 = (int)floor(xs + 0.5);
-    for (int o = -1; o <= 1; ++o) {
-      const double t = xs - (double)(i0 + o);
-      const double S = s2(t), S1 = s2d(t) * ih, S2 = s2dd(t) * ih * ih;
-      const int g = wrapi(i0 + o, n);
-      const double gp = a.gphi[g];
-      G.Gp += wq * S * gp;
-      G.Gp_x += wq * S1 * gp;
-      G.Gp_dx += wq * s * S1 * gp;
+  double xi0[D], dxi[D];
+  for (int l = 0; l < D; ++l) {
+    xi0[l] = (x[l] - M.lo[l]) * M.inv_h[l];
+    dxi[l] = a.dt * v[l] * M.inv_h[l];
+  }
+  G = Gath<D>{};
+  NodeWeights<D> nw;
+  walk_orbit<D>(a, xi0, dxi, [&](double s, double wq) {
+    double xs[D];
+    for (int l = 0; l < D; ++l) xs[l] = xi0[l] + s * dxi[l];
+    nw.at(M, xs);
+    #pragma unroll
+    for (int k = 0; k < kStencil<D>; ++k) {
+      double S, dS[D], ddS[D][D];
+      nw.vals(k, S, dS, ddS);
+      const int g = nw.node(M, k);
+      for (int l = 0; l < D; ++l) {
+        const double gp = a.gphi[l * Ng + g];
+        G.Gp[l] += wq * S * gp;
+        for (int j = 0; j < D; ++j) {
+          G.Gp_x[l][j] += wq * dS[j] * gp;
+          G.Gp_dx[l][j] += wq * s * dS[j] * gp;
+        }
+      }
       double vm = 0.0;
       for (int c = 0; c < 3; ++c) {
         const double As = (1.0 - s) * a.An[c * Ng + g] + s * a.Anp1[c * Ng + g];
-        G.D[c] += wq * S1 * As;
-        G.D_x[c] += wq * S2 * As;
-        G.D_dx[c] += wq * s * S2 * As;
+        for (int l = 0; l < D; ++l) {
+          G.Dm[c][l] += wq * dS[l] * As;
+          for (int j = 0; j < D; ++j) {
+            G.D_x[c][l][j] += wq * ddS[l][j] * As;
+            G.D_dx[c][l][j] += wq * s * ddS[l][j] * As;
+          }
+        }
         if (a.mu) {
           const double m = a.mu[c * Ng + g];
           G.Mc[c] += wq * S * m;
           vm += v[c] * m;
         }
       }
-      G.Mx += wq * S1 * vm;
-      G.Mdx += wq * s * S1 * vm;
+      for (int j = 0; j < D; ++j) {
+        G.Mx[j] += wq * dS[j] * vm;
+        G.Mdx[j] += wq * s * dS[j] * vm;
+      }
     }
   });
   // endpoint interpolants A^n(x) and A^{n+1}(x + dx)
   for (int e = 0; e < 2; ++e) {
-    const double xs = xi0 + (e ? dxi : 0.0);
+    double xs[D];
+    for (int l = 0; l < D; ++l) xs[l] = xi0[l] + (e ? dxi[l] : 0.0);
+    nw.at(M, xs);
     const double* F = e ? a.Anp1 : a.An;
-    const int i0 = (int)floor(xs + 0.5);
-    for (int o = -1; o <= 1; ++o) {
-      const double t = xs - (double)(i0 + o);
-      const double S = s2(t), S1 = s2d(t) * ih;
-      const int g = wrapi(i0 + o, n);
+    #pragma unroll
+    for (int k = 0; k < kStencil<D>; ++k) {
+      double S, dS[D], ddS[D][D];
+      nw.vals(k, S, dS, ddS);
+      const int g = nw.node(M, k);
       for (int c = 0; c < 3; ++c) {
         const double f = F[c * Ng + g];
         (e ? G.Ap : G.Am)[c] += S * f;
-        (e ? G.Ap_x : G.Am_x)[c] += S1 * f;
+        for (int j = 0; j < D; ++j) (e ? G.Ap_x : G.Am_x)[c][j] += dS[j] * f;
       }
     }
   }
@@ -154,35 +258,45 @@ __device__ void gather(const AdjArgs& a, double x, const double v[3], Gath& G) {
 
 // Forward values of one evaluation (no-explicit-A_t GM-HC step, mechanical endpoints,
 // electric-work secant velocities) that the reverse sweep needs.
+template <int D>
 struct Fwd {
-  double q, m, mk, dt, kappa, v0;
-  double Gp, D[3], Am[3], Ap[3];
+  double q, m, mk, dt, kappa, v[D];
+  double Gp[D], Dm[3][D], Am[3], Ap[3];
   double Aep[3], kick[3], pm[3], um[3], tau[3], up[3], pp[3], Pn1[3], pn[3], pn1[3];
   double gm2, sigma, X, R, gHC, t[3], t2, s[3], ustar[3], ut;
   double vEm[3], vEp[3];
+  // B_eff = (K23, -K13, K12) of K = D~^T - D~, D~ the zero-padded 3x3 D
+  __device__ __forceinline__ double dz(int c, int l) const { return l < D ? Dm[c][l] : 0.0; }
 };
 
 __device__ double gam(const double p[3], double mk) { return sqrt(1.0 + dot3(p, p) / (mk * mk)); }
 
-__device__ void forward(const Gath& G, const double P[3], double q, double m, double v0, double dt, double kappa,
-                        Fwd& f) {
+template <int D>
+__device__ void forward(const Gath<D>& G, const double P[3], double q, double m, const double v[3], double dt,
+                        double kappa, Fwd<D>& f) {
   f.q = q;
   f.m = m;
   f.mk = m * kappa;
   f.dt = dt;
   f.kappa = kappa;
-  f.v0 = v0;
-  f.Gp = G.Gp;
+  for (int l = 0; l < D; ++l) {
+    f.v[l] = v[l];
+    f.Gp[l] = G.Gp[l];
+  }
   for (int c = 0; c < 3; ++c) {
-    f.D[c] = G.D[c];
+    double Dv = 0.0;
+    for (int l = 0; l < D; ++l) {
+      f.Dm[c][l] = G.Dm[c][l];
+      Dv += G.Dm[c][l] * v[l];
+    }
     f.Am[c] = G.Am[c];
     f.Ap[c] = G.Ap[c];
     f.Aep[c] = 0.5 * (G.Am[c] + G.Ap[c]);
-    f.kick[c] = 0.5 * dt * q * G.D[c] * v0 - (c == 0 ? 0.5 * dt * q * G.Gp : 0.0);
+    f.kick[c] = 0.5 * dt * q * (Dv - (c < D ? G.Gp[c] : 0.0));
     f.pm[c] = P[c] - q * f.Aep[c] + f.kick[c];
     f.um[c] = f.pm[c] / f.mk;
   }
-  const double Beff[3] = {0.0, -G.D[2], G.D[1]};
+  const double Beff[3] = {f.dz(2, 1) - f.dz(1, 2), -(f.dz(2, 0) - f.dz(0, 2)), f.dz(1, 0) - f.dz(0, 1)};
   for (int c = 0; c < 3; ++c) f.tau[c] = dt * q / (2.0 * m) * Beff[c];
   // normalized HC map
   f.gm2 = 1.0 + dot3(f.um, f.um);
@@ -233,13 +347,15 @@ __device__ void vdg_rev(const double pa[3], const double pb[3], const double f[3
 }
 
 // Cotangents of the evaluation's inputs for the cotangents wv of v_out and wP of P^{n+1}.
+template <int D>
 struct Rev {
-  double Gp, D[3], Am[3], Ap[3];  // gathers
-  double P[3], q, m, v0;          // direct inputs (v0 through the kick only)
+  double Gp[D], Dm[3][D], Am[3], Ap[3];  // gathers
+  double P[3], q, m, v[D];               // direct inputs (v through the kick only)
 };
 
-__device__ void reverse(const Fwd& f, const double wv[3], const double wP[3], Rev& r) {
-  r = Rev{};
+template <int D>
+__device__ void reverse(const Fwd<D>& f, const double wv[3], const double wP[3], Rev<D>& r) {
+  r = Rev<D>{};
   const double m = f.m, mk = f.mk, q = f.q, dt = f.dt;
   double vEb[3], pmb[3] = {}, pnb[3] = {}, pn1b[3] = {}, ppb[3] = {}, Pn1b[3], Aepb[3] = {}, kickb[3] = {};
   for (int c = 0; c < 3; ++c) {
@@ -289,20 +405,25 @@ __device__ void reverse(const Fwd& f, const double wv[3], const double wP[3], Re
   const double dsig = f.sigma >= 0.0 ? 0.5 * (1.0 + f.sigma / f.R) : 2.0 * f.X / (f.R * (f.R - f.sigma));
   const double sigmab = g2b * dsig;
   const double Xb = g2b / f.R;
-  double tau2b = Xb - sigmab;
+  const double tau2b = Xb - sigmab;
   const double utb = 2.0 * f.ut * Xb;
   const double gm2b = sigmab;
   for (int c = 0; c < 3; ++c) {
     umb[c] += utb * f.tau[c] + 2.0 * gm2b * f.um[c];
     taub[c] += utb * f.um[c] + 2.0 * tau2b * f.tau[c];
   }
-  // tau = (dt q / 2m) B_eff, B_eff = (0, -D_z, D_y)
-  const double Beff[3] = {0.0, -f.D[2], f.D[1]};
+  // tau = (dt q / 2m) B_eff, B_eff = (D_zy - D_yz, -(D_zx - D_xz), D_yx - D_xy) (zero-padded D)
+  const double Beff[3] = {f.dz(2, 1) - f.dz(1, 2), -(f.dz(2, 0) - f.dz(0, 2)), f.dz(1, 0) - f.dz(0, 1)};
   const double kq = dt * q / (2.0 * m);
   r.q += dt / (2.0 * m) * dot3(taub, Beff);
   r.m -= dot3(taub, f.tau) / m;
-  r.D[2] -= kq * taub[1];
-  r.D[1] += kq * taub[2];
+  const double Bb[3] = {kq * taub[0], kq * taub[1], kq * taub[2]};
+  r.Dm[2][0] -= Bb[1];
+  r.Dm[1][0] += Bb[2];
+  if (D > 1) {
+    r.Dm[2][D > 1 ? 1 : 0] += Bb[0];
+    r.Dm[0][D > 1 ? 1 : 0] -= Bb[2];
+  }
   // um = pm / mk
   for (int c = 0; c < 3; ++c) pmb[c] += umb[c] / mk;
   r.m -= dot3(umb, f.um) / m;
@@ -313,13 +434,17 @@ __device__ void reverse(const Fwd& f, const double wv[3], const double wP[3], Re
     kickb[c] += pmb[c];
     r.q -= pmb[c] * f.Aep[c];
   }
-  // kick = (dt q / 2) (D v_x - grad-phi-bar e_x)
+  // kick = (dt q / 2) (D v - grad-phi-bar)
   for (int c = 0; c < 3; ++c) {
-    r.D[c] += 0.5 * dt * q * f.v0 * kickb[c];
-    r.v0 += 0.5 * dt * q * f.D[c] * kickb[c];
-    r.q += 0.5 * dt * (f.D[c] * f.v0 - (c == 0 ? f.Gp : 0.0)) * kickb[c];
+    double Dv = 0.0;
+    for (int l = 0; l < D; ++l) {
+      r.Dm[c][l] += 0.5 * dt * q * f.v[l] * kickb[c];
+      r.v[l] += 0.5 * dt * q * f.Dm[c][l] * kickb[c];
+      Dv += f.Dm[c][l] * f.v[l];
+    }
+    r.q += 0.5 * dt * (Dv - (c < D ? f.Gp[c] : 0.0)) * kickb[c];
   }
-  r.Gp -= 0.5 * dt * q * kickb[0];
+  for (int l = 0; l < D; ++l) r.Gp[l] -= 0.5 * dt * q * kickb[l];
   // Aep = (Am + Ap) / 2
   for (int c = 0; c < 3; ++c) {
     r.Am[c] += 0.5 * Aepb[c];
@@ -327,137 +452,187 @@ __device__ void reverse(const Fwd& f, const double wv[3], const double wP[3], Re
   }
 }
 
-// Cotangent of vbar_x (through the kick and through the orbit gathers) and of x.
-__device__ __forceinline__ double rev_v0(const Rev& r, const Gath& G, double dt) {
-  double s = r.Gp * G.Gp_dx;
-  for (int c = 0; c < 3; ++c) s += r.D[c] * G.D_dx[c] + r.Ap[c] * G.Ap_x[c];
-  return r.v0 + dt * s;
+// Cotangent of vbar_j (through the kick and through the orbit gathers) and of x_j.
+template <int D>
+__device__ __forceinline__ double rev_v(const Rev<D>& r, const Gath<D>& G, double dt, int j) {
+  double s = 0.0;
+  for (int l = 0; l < D; ++l) s += r.Gp[l] * G.Gp_dx[l][j];
+  for (int c = 0; c < 3; ++c) {
+    for (int l = 0; l < D; ++l) s += r.Dm[c][l] * G.D_dx[c][l][j];
+    s += r.Ap[c] * G.Ap_x[c][j];
+  }
+  return r.v[j] + dt * s;
 }
-__device__ __forceinline__ double rev_x(const Rev& r, const Gath& G) {
-  double s = r.Gp * G.Gp_x;
-  for (int c = 0; c < 3; ++c) s += r.D[c] * G.D_x[c] + r.Am[c] * G.Am_x[c] + r.Ap[c] * G.Ap_x[c];
+template <int D>
+__device__ __forceinline__ double rev_x(const Rev<D>& r, const Gath<D>& G, int j) {
+  double s = 0.0;
+  for (int l = 0; l < D; ++l) s += r.Gp[l] * G.Gp_x[l][j];
+  for (int c = 0; c < 3; ++c) {
+    for (int l = 0; l < D; ++l) s += r.Dm[c][l] * G.D_x[c][l][j];
+    s += r.Am[c] * G.Am_x[c][j] + r.Ap[c] * G.Ap_x[c][j];
+  }
   return s;
 }
 
-// Exact fixed-point accumulation of one workgroup's scattered values: a window of
-// kAdjWin consecutive (unwrapped) nodes from wlo per field array in LDS, summed with 64-bit
-// integer LDS atomics and added to the global accumulator once per workgroup; values at
-// nodes outside the window go to the global accumulator directly.  Integer sums are exact,
-// so the result does not depend on the order of arrival.
-constexpr int kAdjWin = 32;
+// Solve (I - J^T) mu = rhs for the transposed inner system, with J[c][j] = dv_out,c /
+// dvbar_j nonzero for j < D only (Cramer's rule on the 3x3 matrix).
+template <int D>
+__device__ __forceinline__ void inner_solve(const double J[3][D], const double rhs[3], double mu[3]) {
+  double A[3][3];
+  for (int j = 0; j < 3; ++j)
+    for (int c = 0; c < 3; ++c) A[j][c] = (j == c ? 1.0 : 0.0) - (j < D ? J[c][j < D ? j : 0] : 0.0);
+  const double det = A[0][0] * (A[1][1] * A[2][2] - A[1][2] * A[2][1]) - A[0][1] * (A[1][0] * A[2][2] - A[1][2] * A[2][0]) +
+                     A[0][2] * (A[1][0] * A[2][1] - A[1][1] * A[2][0]);
+  for (int k = 0; k < 3; ++k) {
+    double B[3][3];
+    for (int j = 0; j < 3; ++j)
+      for (int c = 0; c < 3; ++c) B[j][c] = c == k ? rhs[j] : A[j][c];
+    mu[k] = (B[0][0] * (B[1][1] * B[2][2] - B[1][2] * B[2][1]) - B[0][1] * (B[1][0] * B[2][2] - B[1][2] * B[2][0]) +
+             B[0][2] * (B[1][0] * B[2][1] - B[1][1] * B[2][0])) / det;
+  }
+}
 
+// Gather cotangents of one reverse sweep as a flat list: grad-phi-bar (D), D (3 D),
+// A^- (3), A^+ (3).
+template <int D>
+__device__ __forceinline__ void rev_gath(const Rev<D>& r, double g[adj_ngath(D)]) {
+  for (int l = 0; l < D; ++l) g[l] = r.Gp[l];
+  for (int c = 0; c < 3; ++c) {
+    for (int l = 0; l < D; ++l) g[D + c * D + l] = r.Dm[c][l];
+    g[4 * D + c] = r.Am[c];
+    g[4 * D + 3 + c] = r.Ap[c];
+  }
+}
+
+// Exact fixed-point accumulation of one workgroup's scattered values: a window of
+// kWinX x kWinY (1D: kWinX) consecutive unwrapped nodes from wlo per field array in LDS,
+// summed with 64-bit integer LDS atomics and added to the global accumulator once per
+// workgroup; values at nodes outside the window go to the global accumulator directly.
+// Integer sums are exact, so the result does not depend on the order of arrival.
+template <int D>
+constexpr int kWinX = D == 1 ? 32 : 16;
+template <int D>
+constexpr int kWinY = D == 1 ? 1 : 8;
+template <int D>
+constexpr int kWinNodes = kWinX<D> * kWinY<D>;
+
+template <int D>
 struct WinAcc {
-  unsigned long long* s;  // [kAdjVals][kAdjWin] pairs
-  unsigned long long* g;  // global [kAdjVals][Ng] pairs
-  int wlo, n;
-  int64_t Ng;
+  unsigned long long* s;  // [D + 6][kWinNodes] pairs
+  unsigned long long* g;  // global [D + 6][Ng] pairs
+  int wlo[2];
+  const Mesh* M;
   double up;
-  __device__ __forceinline__ void put(int f, int node, double v) const {
-    const int rel = node - wlo;
-    if (rel >= 0 && rel < kAdjWin) {
+  __device__ __forceinline__ void put(int f, const int node[D], double v) const {
+    int rel = 0;
+    bool in = true;
+    for (int l = 0; l < D; ++l) {
+      const int r = node[l] - wlo[l];
+      const int e = l == 0 ? kWinX<D> : kWinY<D>;
+      in = in && r >= 0 && r < e;
+      rel += l == 0 ? r : r * kWinX<D>;
+    }
+    if (in) {
       long long H, L;
       fix_split(v, up, H, L);
-      const int k = 2 * (f * kAdjWin + rel);
+      const int k = 2 * (f * kWinNodes<D> + rel);
       if (H) atomicAdd(s + k, (unsigned long long)H);
       if (L) atomicAdd(s + k + 1, (unsigned long long)L);
     } else {
-      fix_add(g, f * Ng + wrapi(node, n), v, up);
+      int gi = wrapi(node[0], M->n[0]);
+      if (D > 1) gi += M->n[0] * wrapi(node[D > 1 ? 1 : 0], M->n[1]);
+      fix_add(g, f * M->Ng + gi, v, up);
     }
   }
 };
 
 // Gather of the adjoint current mu along the orbit (the transposed deposit): Mc = sum_g
-// mu_g int S_g, Mdx = sum_g (v . mu_g) int s S_g'.
-__device__ __forceinline__ void gather_mu(const AdjArgs& a, double xi0, double dxi, const double v[3], double Mc[3],
-                                         double& Mdx) {
-  const int64_t Ng = a.M.Ng;
-  const int n = a.M.n[0];
-  const double ih = a.M.inv_h[0];
+// mu_g int S_g, Mdx_j = sum_g (v . mu_g) int s dS_g/dx_j.
+template <int D>
+__device__ __forceinline__ void gather_mu(const AdjArgs& a, const double xi0[D], const double dxi[D],
+                                         const double v[3], double Mc[3], double Mdx[D]) {
+  const Mesh& M = a.M;
+  const int64_t Ng = M.Ng;
   Mc[0] = Mc[1] = Mc[2] = 0.0;
-  Mdx = 0.0;
-  walk_orbit(a, xi0, dxi, [&](double s, double wq) {
-    const double xs = xi0 + s * dxi;
-    const int i0 = (int)floor(xs + 0.5);
-    for (int o = -1; o <= 1; ++o) {
-      const double t = xs - (double)(i0 + o);
-      const double S = s2(t), S1 = s2d(t) * ih;
-      const int g = wrapi(i0 + o, n);
+  for (int j = 0; j < D; ++j) Mdx[j] = 0.0;
+  NodeWeights<D> nw;
+  walk_orbit<D>(a, xi0, dxi, [&](double s, double wq) {
+    double xs[D];
+    for (int l = 0; l < D; ++l) xs[l] = xi0[l] + s * dxi[l];
+    nw.at(M, xs);
+    #pragma unroll
+    for (int k = 0; k < kStencil<D>; ++k) {
+      double S, dS[D], ddS[D][D];
+      nw.vals(k, S, dS, ddS);
+      const int g = nw.node(M, k);
       double vm = 0.0;
       for (int c = 0; c < 3; ++c) {
         const double m = a.mu[c * Ng + g];
         Mc[c] += wq * S * m;
         vm += v[c] * m;
       }
-      Mdx += wq * s * S1 * vm;
+      for (int j = 0; j < D; ++j) Mdx[j] += wq * s * dS[j] * vm;
     }
   });
 }
 
-__device__ __forceinline__ void rev_gath(const Rev& r, double g[kAdjGath]) {
-  g[0] = r.Gp;
-  for (int c = 0; c < 3; ++c) {
-    g[1 + c] = r.D[c];
-    g[4 + c] = r.Am[c];
-    g[7 + c] = r.Ap[c];
-  }
-}
-
-}  // namespace
-
 // ADJ_PREP and ADJ_FINAL: the full reverse sweep of one particle's evaluation.
+template <int D>
 __global__ __launch_bounds__(kBlock) void k_adj_particle(AdjArgs a) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= a.np) return;
   const Mesh& M = a.M;
+  constexpr int NG = adj_ngath(D);
   const int64_t li = a.id[i];
-  const double x = a.x[i];
   const double q = a.q[i], m = fabs(q);
-  double P[3], v[3], lP[3];
+  double x[D], P[3], v[3], lP[3], lx[D];
+  for (int l = 0; l < D; ++l) {
+    x[l] = a.x[l * a.ps + i];
+    lx[l] = a.lx[l * a.np + li];
+  }
   for (int c = 0; c < 3; ++c) {
     P[c] = a.P[c * a.ps + i];
     v[c] = a.vbar[c * a.np + li];
     lP[c] = a.lP[c * a.np + li];
   }
-  const double lx = a.lx[li];
-  Gath G;
-  gather(a, x, v, G);
-  Fwd f;
-  forward(G, P, q, m, v[0], a.dt, a.kappa, f);
-  Rev r;
-  // column x of dF/dvbar (F depends on vbar through vbar_x only)
-  double J[3];
+  Gath<D> G;
+  gather<D>(a, x, v, G);
+  Fwd<D> f;
+  forward<D>(G, P, q, m, v, a.dt, a.kappa, f);
+  Rev<D> r;
+  // the nonzero columns j < D of dF/dvbar
+  double J[3][D];
   for (int c = 0; c < 3; ++c) {
     const double e[3] = {c == 0 ? 1.0 : 0.0, c == 1 ? 1.0 : 0.0, c == 2 ? 1.0 : 0.0}, z[3] = {0.0, 0.0, 0.0};
-    reverse(f, e, z, r);
-    J[c] = rev_v0(r, G, a.dt);
+    reverse<D>(f, e, z, r);
+    for (int j = 0; j < D; ++j) J[c][j] = rev_v<D>(r, G, a.dt, j);
     if (a.mode == ADJ_PREP) {
-      double g[kAdjGath];
-      rev_gath(r, g);
-      for (int k = 0; k < kAdjGath; ++k) a.cache[(4 + c * kAdjGath + k) * a.ps + i] = g[k];
+      double g[NG];
+      rev_gath<D>(r, g);
+      for (int k = 0; k < NG; ++k) a.cache[(4 * D + c * NG + k) * a.ps + i] = g[k];
     }
   }
-  // right side: x^{n+1} = x + dt vbar_x, P^{n+1}(vbar), and the transposed deposit
+  // right side: x^{n+1} = x + dt vbar, P^{n+1}(vbar), and the transposed deposit
   const double z3[3] = {0.0, 0.0, 0.0};
-  reverse(f, z3, lP, r);
-  const double base = a.dt * lx + rev_v0(r, G, a.dt);
+  reverse<D>(f, z3, lP, r);
+  double base[D];
+  for (int j = 0; j < D; ++j) base[j] = a.dt * lx[j] + rev_v<D>(r, G, a.dt, j);
   if (a.mode == ADJ_PREP) {
-    double g[kAdjGath];
-    rev_gath(r, g);
-    for (int k = 0; k < kAdjGath; ++k) a.cache[(4 + 3 * kAdjGath + k) * a.ps + i] = g[k];
-    for (int c = 0; c < 3; ++c) a.cache[c * a.ps + i] = J[c];
-    a.cache[3 * a.ps + i] = base;
+    double g[NG];
+    rev_gath<D>(r, g);
+    for (int k = 0; k < NG; ++k) a.cache[(4 * D + 3 * NG + k) * a.ps + i] = g[k];
+    for (int c = 0; c < 3; ++c)
+      for (int j = 0; j < D; ++j) a.cache[(c * D + j) * a.ps + i] = J[c][j];
+    for (int j = 0; j < D; ++j) a.cache[(3 * D + j) * a.ps + i] = base[j];
     return;
   }
   const double qdv = q / M.dV;
-  double rhs[3];
+  double rhs[3], mv[3];
   for (int c = 0; c < 3; ++c) rhs[c] = qdv * G.Mc[c];
-  rhs[0] += base + qdv * a.dt * G.Mdx;
-  double mv[3];
-  mv[1] = rhs[1];
-  mv[2] = rhs[2];
-  mv[0] = (rhs[0] + J[1] * rhs[1] + J[2] * rhs[2]) / (1.0 - J[0]);
-  reverse(f, mv, lP, r);
-  a.gx[li] = lx + rev_x(r, G) + qdv * G.Mx;
+  for (int j = 0; j < D; ++j) rhs[j] += base[j] + qdv * a.dt * G.Mdx[j];
+  inner_solve<D>(J, rhs, mv);
+  reverse<D>(f, mv, lP, r);
+  for (int j = 0; j < D; ++j) a.gx[j * a.np + li] = lx[j] + rev_x<D>(r, G, j) + qdv * G.Mx[j];
   for (int c = 0; c < 3; ++c) a.gP[c * a.np + li] = r.P[c];
   a.gq[li] = r.q + (q < 0.0 ? -r.m : r.m) + dot3(v, G.Mc) / M.dV;
 }
@@ -465,39 +640,51 @@ __global__ __launch_bounds__(kBlock) void k_adj_particle(AdjArgs a) {
 // ADJ_BOUND and ADJ_SCATTER: one transposed outer iteration from the cached values.  The
 // reverse sweep is linear in its cotangents, so the gather cotangents for (mu_v, lP) are
 // sum_c mu_v,c (those of e_c) + (those of lP).
+template <int D>
 __global__ __launch_bounds__(kBlock) void k_adj_iter(AdjArgs a) {
+  constexpr int NG = adj_ngath(D);
+  constexpr int NV = D + 6;
   __shared__ double red[kBlock];
-  __shared__ unsigned long long sacc[2 * kAdjVals * kAdjWin];
-  __shared__ int swlo;
+  __shared__ unsigned long long sacc[2 * NV * kWinNodes<D>];
+  __shared__ int swlo[2];
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const bool live = i < a.np;
   const Mesh& M = a.M;
-  const double ih = M.inv_h[0];
-  double xi0 = 0.0, dxi = 0.0, g[kAdjGath];
-  for (int k = 0; k < kAdjGath; ++k) g[k] = 0.0;
+  double xi0[D], dxi[D], g[NG];
+  for (int l = 0; l < D; ++l) xi0[l] = dxi[l] = 0.0;
+  for (int k = 0; k < NG; ++k) g[k] = 0.0;
   if (live) {
     const int64_t li = a.id[i];
     const double q = a.q[i];
     double v[3];
     for (int c = 0; c < 3; ++c) v[c] = a.vbar[c * a.np + li];
-    xi0 = (a.x[i] - M.lo[0]) * ih;
-    dxi = a.dt * v[0] * ih;
-    double rhs[3] = {0.0, 0.0, 0.0}, Mdx = 0.0;
-    if (a.mu) gather_mu(a, xi0, dxi, v, rhs, Mdx);
+    for (int l = 0; l < D; ++l) {
+      xi0[l] = (a.x[l * a.ps + i] - M.lo[l]) * M.inv_h[l];
+      dxi[l] = a.dt * v[l] * M.inv_h[l];
+    }
+    double rhs[3] = {0.0, 0.0, 0.0}, Mdx[D];
+    for (int j = 0; j < D; ++j) Mdx[j] = 0.0;
+    if (a.mu) gather_mu<D>(a, xi0, dxi, v, rhs, Mdx);
     const double qdv = q / M.dV;
     for (int c = 0; c < 3; ++c) rhs[c] *= qdv;
-    rhs[0] += a.cache[3 * a.ps + i] + qdv * a.dt * Mdx;
-    const double J0 = a.cache[i], J1 = a.cache[a.ps + i], J2 = a.cache[2 * a.ps + i];
-    const double mv[3] = {(rhs[0] + J1 * rhs[1] + J2 * rhs[2]) / (1.0 - J0), rhs[1], rhs[2]};
-    for (int k = 0; k < kAdjGath; ++k) {
-      double s = a.cache[(4 + 3 * kAdjGath + k) * a.ps + i];
-      for (int c = 0; c < 3; ++c) s += mv[c] * a.cache[(4 + c * kAdjGath + k) * a.ps + i];
+    for (int j = 0; j < D; ++j) rhs[j] += a.cache[(3 * D + j) * a.ps + i] + qdv * a.dt * Mdx[j];
+    double J[3][D], mv[3];
+    for (int c = 0; c < 3; ++c)
+      for (int j = 0; j < D; ++j) J[c][j] = a.cache[(c * D + j) * a.ps + i];
+    inner_solve<D>(J, rhs, mv);
+    for (int k = 0; k < NG; ++k) {
+      double s = a.cache[(4 * D + 3 * NG + k) * a.ps + i];
+      for (int c = 0; c < 3; ++c) s += mv[c] * a.cache[(4 * D + c * NG + k) * a.ps + i];
       g[k] = s;
     }
   }
   if (a.mode == ADJ_BOUND) {  // per-block sum of the bound, fixed order
-    double bound = fabs(g[0]);
-    for (int c = 0; c < 3; ++c) bound += 2.0 * ih * fabs(g[1 + c]) + fabs(g[4 + c]) + fabs(g[7 + c]);
+    double bound = 0.0;
+    for (int l = 0; l < D; ++l) bound += fabs(g[l]);
+    for (int c = 0; c < 3; ++c) {
+      for (int l = 0; l < D; ++l) bound += 2.0 * M.inv_h[l] * fabs(g[D + c * D + l]);
+      bound += fabs(g[4 * D + c]) + fabs(g[4 * D + 3 + c]);
+    }
     red[threadIdx.x] = live ? bound : 0.0;
     __syncthreads();
     for (int w = kBlock / 2; w > 0; w >>= 1) {
@@ -507,49 +694,89 @@ __global__ __launch_bounds__(kBlock) void k_adj_iter(AdjArgs a) {
     if (threadIdx.x == 0) a.partials[blockIdx.x] = red[0];
     return;
   }
-  const int64_t Ng = M.Ng;
-  const int n = M.n[0];
-  if (threadIdx.x == 0) swlo = INT_MAX;
-  for (int k = threadIdx.x; k < 2 * kAdjVals * kAdjWin; k += kBlock) sacc[k] = 0ull;
+  if (threadIdx.x < 2) swlo[threadIdx.x] = INT_MAX;
+  for (int k = threadIdx.x; k < 2 * NV * kWinNodes<D>; k += kBlock) sacc[k] = 0ull;
   __syncthreads();
-  if (live) atomicMin(&swlo, (int)floor(fmin(xi0, xi0 + dxi) + 0.5) - 1);
+  if (live)
+    for (int l = 0; l < D; ++l) atomicMin(&swlo[l], (int)floor(fmin(xi0[l], xi0[l] + dxi[l]) + 0.5) - 1);
   __syncthreads();
-  const WinAcc w{sacc, a.acc, swlo, n, Ng, a.fx_up};
+  WinAcc<D> w{sacc, a.acc, {swlo[0], swlo[1]}, &M, a.fx_up};
   if (live) {
-    walk_orbit(a, xi0, dxi, [&](double s, double wq) {
-      const double xs = xi0 + s * dxi;
-      const int i0 = (int)floor(xs + 0.5);
-      for (int o = -1; o <= 1; ++o) {
-        const double t = xs - (double)(i0 + o);
-        const double S = s2(t), S1 = s2d(t) * ih;
-        const int node = i0 + o;
-        w.put(0, node, wq * S * g[0]);
+    NodeWeights<D> nw;
+    // Within a knot-split segment the stencil nodes stay the same, so each node's weights
+    // are integrated over the segment's Gauss points first (int S, int (1 - s) dS/dx_l,
+    // int s dS/dx_l) and scattered once per segment.
+    walk_segments<D>(xi0, dxi, [&](double sa, double sb) {
+      const double len = sb - sa;
+      int base[D];
+      for (int l = 0; l < D; ++l) base[l] = (int)floor(xi0[l] + 0.5 * (sa + sb) * dxi[l] + 0.5);
+      double I0[kStencil<D>], Ia[kStencil<D>][D], Ib[kStencil<D>][D];
+#pragma unroll
+      for (int k = 0; k < kStencil<D>; ++k) {
+        I0[k] = 0.0;
+        for (int l = 0; l < D; ++l) Ia[k][l] = Ib[k][l] = 0.0;
+      }
+      for (int q = 0; q < a.ngl; ++q) {
+        const double s = sa + len * a.glx[q], wq = len * a.glw[q];
+        double xs[D];
+        for (int l = 0; l < D; ++l) xs[l] = xi0[l] + s * dxi[l];
+        nw.at_base(M, xs, base);
+#pragma unroll
+        for (int k = 0; k < kStencil<D>; ++k) {
+          double S, dS[D], ddS[D][D];
+          nw.vals(k, S, dS, ddS);
+          I0[k] += wq * S;
+          for (int l = 0; l < D; ++l) {
+            Ia[k][l] += wq * (1.0 - s) * dS[l];
+            Ib[k][l] += wq * s * dS[l];
+          }
+        }
+      }
+#pragma unroll
+      for (int k = 0; k < kStencil<D>; ++k) {
+        int node[D];
+        for (int l = 0; l < D; ++l) node[l] = nw.unode(l, k);
+        for (int l = 0; l < D; ++l) w.put(l, node, I0[k] * g[l]);
         for (int c = 0; c < 3; ++c) {
-          w.put(1 + c, node, wq * (1.0 - s) * S1 * g[1 + c]);
-          w.put(4 + c, node, wq * s * S1 * g[1 + c]);
+          double va = 0.0, vb = 0.0;
+          for (int l = 0; l < D; ++l) {
+            va += Ia[k][l] * g[D + c * D + l];
+            vb += Ib[k][l] * g[D + c * D + l];
+          }
+          w.put(D + c, node, va);
+          w.put(D + 3 + c, node, vb);
         }
       }
     });
     for (int e = 0; e < 2; ++e) {
-      const double xs = xi0 + (e ? dxi : 0.0);
-      const int i0 = (int)floor(xs + 0.5);
-      for (int o = -1; o <= 1; ++o) {
-        const double S = s2(xs - (double)(i0 + o));
-        for (int c = 0; c < 3; ++c) w.put((e ? 4 : 1) + c, i0 + o, S * g[(e ? 7 : 4) + c]);
+      double xs[D];
+      for (int l = 0; l < D; ++l) xs[l] = xi0[l] + (e ? dxi[l] : 0.0);
+      nw.at(M, xs);
+    #pragma unroll
+    for (int k = 0; k < kStencil<D>; ++k) {
+        double S, dS[D], ddS[D][D];
+        nw.vals(k, S, dS, ddS);
+        int node[D];
+        for (int l = 0; l < D; ++l) node[l] = nw.unode(l, k);
+        for (int c = 0; c < 3; ++c) w.put((e ? D + 3 : D) + c, node, S * g[4 * D + (e ? 3 : 0) + c]);
       }
     }
   }
   __syncthreads();
-  for (int k = threadIdx.x; k < kAdjVals * kAdjWin; k += kBlock) {
+  for (int k = threadIdx.x; k < NV * kWinNodes<D>; k += kBlock) {
     const unsigned long long H = sacc[2 * k], L = sacc[2 * k + 1];
     if (H | L) {
-      const int f = k / kAdjWin, rel = k % kAdjWin;
-      unsigned long long* dst = a.acc + 2 * (f * Ng + wrapi(swlo + rel, n));
+      const int f = k / kWinNodes<D>, rel = k % kWinNodes<D>;
+      int gi = wrapi(swlo[0] + rel % kWinX<D>, M.n[0]);
+      if (D > 1) gi += M.n[0] * wrapi(swlo[1] + rel / kWinX<D>, M.n[1]);
+      unsigned long long* dst = a.acc + 2 * ((int64_t)f * M.Ng + gi);
       if (H) atomicAdd(dst, H);
       if (L) atomicAdd(dst + 1, L);
     }
   }
 }
+
+}  // namespace
 
 // ---- mesh side ---------------------------------------------------------------------
 
@@ -710,27 +937,33 @@ __global__ __launch_bounds__(kBlock) void k_adj_init_field(Mesh M, double sigma1
 
 // Per particle: x -> rho^0 (point shape), u -> P^0 = m kappa u + q A^0(x), q -> both
 // (with m = |q|).
+template <int D>
 __global__ __launch_bounds__(kBlock) void k_adj_init_particle(AdjInitArgs a) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= a.np) return;
   const Mesh& M = a.M;
   const int64_t Ng = M.Ng;
-  const int n = M.n[0];
-  const double ih = M.inv_h[0];
   const int64_t li = a.id[i];
-  const double x = a.x[i], q = a.q[i], m = fabs(q), mk = m * a.kappa;
-  const double xs = (x - M.lo[0]) * ih;
-  const int i0 = (int)floor(xs + 0.5);
-  double rS = 0.0, rS1 = 0.0, A[3] = {0.0, 0.0, 0.0}, A1[3] = {0.0, 0.0, 0.0};
-  for (int o = -1; o <= 1; ++o) {
-    const double t = xs - (double)(i0 + o);
-    const double S = s2(t), S1 = s2d(t) * ih;
-    const int g = wrapi(i0 + o, n);
+  const double q = a.q[i], m = fabs(q), mk = m * a.kappa;
+  double xs[D];
+  for (int l = 0; l < D; ++l) xs[l] = (a.x[l * a.ps + i] - M.lo[l]) * M.inv_h[l];
+  NodeWeights<D> nw;
+  nw.at(M, xs);
+  double rS = 0.0, rS1[D], A[3] = {0.0, 0.0, 0.0}, A1[3][D];
+  for (int j = 0; j < D; ++j) {
+    rS1[j] = 0.0;
+    for (int c = 0; c < 3; ++c) A1[c][j] = 0.0;
+  }
+  #pragma unroll
+  for (int k = 0; k < kStencil<D>; ++k) {
+    double S, dS[D], ddS[D][D];
+    nw.vals(k, S, dS, ddS);
+    const int g = nw.node(M, k);
     rS += S * a.rb[g];
-    rS1 += S1 * a.rb[g];
+    for (int j = 0; j < D; ++j) rS1[j] += dS[j] * a.rb[g];
     for (int c = 0; c < 3; ++c) {
       A[c] += S * a.A0[c * Ng + g];
-      A1[c] += S1 * a.A0[c * Ng + g];
+      for (int j = 0; j < D; ++j) A1[c][j] += dS[j] * a.A0[c * Ng + g];
     }
   }
   double lP[3], u[3];
@@ -738,7 +971,11 @@ __global__ __launch_bounds__(kBlock) void k_adj_init_particle(AdjInitArgs a) {
     lP[c] = a.lP[c * a.np + li];
     u[c] = (a.P[c * a.ps + i] - q * A[c]) / mk;
   }
-  a.gx[li] = a.lx[li] + q / M.dV * rS1 + q * dot3(lP, A1);
+  for (int j = 0; j < D; ++j) {
+    double pa = 0.0;
+    for (int c = 0; c < 3; ++c) pa += lP[c] * A1[c][j];
+    a.gx[j * a.np + li] = a.lx[j * a.np + li] + q / M.dV * rS1[j] + q * pa;
+  }
   for (int c = 0; c < 3; ++c) a.gu[c * a.np + li] = mk * lP[c];
   a.gq[li] = rS / M.dV + dot3(lP, A) + (q < 0.0 ? -1.0 : 1.0) * a.kappa * dot3(lP, u);
 }
@@ -791,12 +1028,18 @@ inline unsigned nblocks(int64_t n) { return (unsigned)std::max<int64_t>((n + kBl
 
 hipError_t launch_adj_particle(const AdjArgs& a, hipStream_t s) {
   if (a.np == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_adj_particle, dim3(nblocks(a.np)), dim3(kBlock), 0, s, a);
+  if (a.M.d == 1)
+    hipLaunchKernelGGL(k_adj_particle<1>, dim3(nblocks(a.np)), dim3(kBlock), 0, s, a);
+  else
+    hipLaunchKernelGGL(k_adj_particle<2>, dim3(nblocks(a.np)), dim3(kBlock), 0, s, a);
   return hipGetLastError();
 }
 hipError_t launch_adj_iter(const AdjArgs& a, hipStream_t s) {
   if (a.np == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_adj_iter, dim3(nblocks(a.np)), dim3(kBlock), 0, s, a);
+  if (a.M.d == 1)
+    hipLaunchKernelGGL(k_adj_iter<1>, dim3(nblocks(a.np)), dim3(kBlock), 0, s, a);
+  else
+    hipLaunchKernelGGL(k_adj_iter<2>, dim3(nblocks(a.np)), dim3(kBlock), 0, s, a);
   return hipGetLastError();
 }
 int64_t adj_particle_blocks(int64_t np) { return nblocks(np); }
@@ -816,7 +1059,10 @@ hipError_t launch_adj_init_field(const Mesh& M, double sigma1, int project, cons
 }
 hipError_t launch_adj_init_particle(const AdjInitArgs& a, hipStream_t s) {
   if (a.np == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_adj_init_particle, dim3(nblocks(a.np)), dim3(kBlock), 0, s, a);
+  if (a.M.d == 1)
+    hipLaunchKernelGGL(k_adj_init_particle<1>, dim3(nblocks(a.np)), dim3(kBlock), 0, s, a);
+  else
+    hipLaunchKernelGGL(k_adj_init_particle<2>, dim3(nblocks(a.np)), dim3(kBlock), 0, s, a);
   return hipGetLastError();
 }
 hipError_t launch_adj_update(double* mu, const double* mnew, int64_t n, double beta, double* out, hipStream_t s) {

@@ -1737,25 +1737,27 @@ size_t adj_carve(const gmhc_ctx* c, char* base, AdjScratch& a) {
   a.trial = cv.take<double>((size_t)(d + 6) * Ng);
   a.work = cv.take<double2>(12 * Ng);
   a.Lf = cv.take<double2>(9 * Ng);
-  a.acc = cv.take<unsigned long long>((size_t)2 * kAdjVals * Ng);
-  a.Pr = cv.take<double>((size_t)kAdjVals * Ng);
-  a.Pb = cv.take<double2>((size_t)kAdjVals * Ng);
+  const int nv = adj_nvals(d);
+  a.acc = cv.take<unsigned long long>((size_t)2 * nv * Ng);
+  a.Pr = cv.take<double>((size_t)nv * Ng);
+  a.Pb = cv.take<double2>((size_t)nv * Ng);
   a.Lout = cv.take<double2>(12 * Ng);
   a.Lreal = cv.take<double>(12 * Ng);
   a.mu = cv.take<double>(3 * Ng);
   a.partials = cv.take<double>((size_t)adj_particle_blocks(std::max<int64_t>(c->np, 1)));
   a.red = cv.take<double>(8);
-  a.cache = cv.take<double>((size_t)kAdjCache * std::max<int64_t>(c->np, 1));
+  a.cache = cv.take<double>((size_t)adj_ncache(d) * std::max<int64_t>(c->np, 1));
   return (cv.off + 255) & ~(size_t)255;
 }
 
-// The configurations the adjoint covers: 1D, quadratic shape, FP64, no refinement, a
-// Gauss-Legendre order that integrates the derivative integrands exactly (>= 2).
+// The configurations the adjoint covers: 1D and 2D, quadratic shape, FP64, no refinement,
+// a Gauss-Legendre order that integrates the derivative integrands exactly (>= dim + 1).
 int32_t adj_supported(gmhc_ctx* ctx) {
-  if (ctx->M.d != 1 || ctx->M.shape != 2 || ctx->prec != GMHC_FP64 || ctx->cfg.refine_levels != 0 ||
-      ctx->ngl < 2)
+  if (ctx->M.d > 2 || ctx->M.shape != 2 || ctx->prec != GMHC_FP64 || ctx->cfg.refine_levels != 0 ||
+      ctx->ngl < ctx->M.d + 1)
     return fail(ctx, GMHC_EINVAL,
-                "the adjoint covers dim 1, shape_order 2, precision FP64, refine_levels 0 and gl_order 0 or >= 2");
+                "the adjoint covers dim 1 and 2, shape_order 2, precision FP64, refine_levels 0 and gl_order 0 or "
+                ">= dim + 1");
   return GMHC_OK;
 }
 
@@ -1792,7 +1794,7 @@ AdjArgs adj_args(const gmhc_ctx* c, const AdjScratch& a, const double* vbar, con
   r.lP = lP;
   r.gphi = a.trial;
   r.An = c->An;
-  r.Anp1 = a.trial + c->M.Ng;
+  r.Anp1 = a.trial + (int64_t)c->M.d * c->M.Ng;
   r.partials = a.partials;
   r.acc = a.acc;
   r.cache = a.cache;
@@ -1873,12 +1875,12 @@ int32_t gmhc_adjoint_step(gmhc_ctx* ctx, void* scratch, size_t scratch_bytes, co
     HIPCK(hipMemcpyAsync(&B, a.red, sizeof(double), hipMemcpyDeviceToHost, s));
     HIPCK(hipStreamSynchronize(s));
     const FixScale fx = fix_scale(B);
-    HIPCK(launch_zero(reinterpret_cast<double*>(a.acc), 2 * kAdjVals * Ng, s));
+    HIPCK(launch_zero(reinterpret_cast<double*>(a.acc), 2 * adj_nvals(M.d) * Ng, s));
     pa.mode = ADJ_SCATTER;
     pa.fx_up = fx.up;
     HIPCK(launch_adj_iter(pa, s));
-    HIPCK(launch_fix_to_double(a.acc, a.Pr, kAdjVals * Ng, fx, s));
-    HIPCK(fft_nd(M, ctx->axes, kAdjVals, a.Pr, nullptr, a.Pb, nullptr, nullptr, false, false, s));
+    HIPCK(launch_fix_to_double(a.acc, a.Pr, adj_nvals(M.d) * Ng, fx, s));
+    HIPCK(fft_nd(M, ctx->axes, adj_nvals(M.d), a.Pr, nullptr, a.Pb, nullptr, nullptr, false, false, s));
     HIPCK(launch_adj_field(fa, s));
     HIPCK(fft_nd(M, ctx->axes, 12, nullptr, a.Lout, nullptr, a.Lreal, a.work, true, false, s));
     HIPCK(launch_adj_update(a.mu, a.Lreal + 9 * Ng, 3 * Ng, it ? ctx->cfg.beta : 1.0, a.red, s));

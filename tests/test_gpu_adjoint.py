@@ -176,6 +176,80 @@ def test_adjoint_per_particle_directions_with_transverse_momenta():
     assert err <= 1e-9
 
 
+def _dir_derivs(grads, dirs):
+    gx, gu, gq = grads
+    dx, du, dq = dirs
+    return np.array([(gx * dx[k]).sum() + (gu * du[k]).sum() + (gq * dq[k]).sum() for k in range(dq.shape[0])])
+
+
+def _torch_grads(x, u, q, cfg, steps, every):
+    xt = torch.tensor(x, requires_grad=True)
+    ut = torch.tensor(u, requires_grad=True)
+    qt = torch.tensor(q, requires_grad=True)
+    Wt = A.field_energy_run(xt, ut, qt, cfg, steps, every, "cuda:0")
+    Wt.backward()
+    return float(Wt.detach()), (xt.grad.numpy(), ut.grad.numpy(), qt.grad.numpy())
+
+
+def test_adjoint_2d_per_particle_directions():
+    """2D Weibel beams (16 x 16 mesh, 1024 particles, thermal spread in all three momentum
+    components), 5 steps with checkpoints every 2: directional derivatives from the GPU's
+    per-particle cotangents along random directions of positions (both axes), momenta and
+    charges, against the oracle's forward-mode derivatives."""
+    w = W.spec("weibel2d", n=(16, 16), ppc=4)
+    steps, every = 5, 2
+    x, u, q = W.particles(w)
+    n = q.size
+    rng = np.random.default_rng(23)
+    dx = 0.05 * rng.standard_normal((3, 2, n))
+    du = 0.1 * rng.standard_normal((3, 3, n))
+    dq = q * rng.standard_normal((3, n))
+    Wg, grads = _torch_grads(x, u, q, G.config_from_dict(W.config_dict(w)), steps, every)
+    dirs = _dir_derivs(grads, (dx, du, dq))
+    E, dE, _ = O.tangent_run(O.config_from_dict(W.config_dict(w), gl_order=3), x, u, q, steps, dx=dx, du=du, dq=dq)
+    err = np.abs(dirs - dE[2]).max() / np.abs(dE[2]).max()
+    print(f"2D per-particle directions: W gpu {Wg:.10e} oracle {E[2]:.10e}; rel err {err:.2e}", flush=True)
+    print("gpu   ", dirs, "\noracle", dE[2], flush=True)
+    assert abs(Wg - E[2]) <= 1e-10 * E[2]
+    assert err <= 1e-9
+
+
+def test_adjoint_2d_full_size_central_differences():
+    """The 2D Weibel workload at full size (128 x 128 mesh, 1,048,576 particles), 10 steps
+    with checkpoints every 5: the derivatives along the beam drift momentum and along a
+    mode-(1, 2) weight perturbation against central differences (h = 1e-6) of GPU runs."""
+    w = W.spec("weibel2d")
+    steps, every = 10, 5
+    x, u, q = W.particles(w)
+    n = q.size
+    cfg = G.config_from_dict(W.config_dict(w))
+    L = w["length"]
+    du = np.zeros((2, 3, n))
+    du[0, 2] = np.sign(u[2])
+    dq = np.zeros((2, n))
+    dq[1] = q * np.cos(2.0 * math.pi * (x[0] / L[0] + 2.0 * x[1] / L[1]) + 0.7)
+    dx = np.zeros((2, 2, n))
+    print(f"2D adjoint vs central differences: {n} particles, {steps} steps", flush=True)
+    Wg, grads = _torch_grads(x, u, q, cfg, steps, every)
+    dirs = _dir_derivs(grads, (dx, du, dq))
+    h = 1e-6
+    fd = np.zeros(2)
+    for k in range(2):
+        vals = []
+        for sgn in (1.0, -1.0):
+            sim = G.Simulation(cfg, n, device="cuda:0")
+            sim.load_particles(x, u + sgn * h * du[k], q + sgn * h * dq[k])
+            sim.initialize()
+            for _ in range(steps):
+                sim.step()
+            vals.append(sim.diagnostics()["field"])
+            sim.close()
+        fd[k] = (vals[0] - vals[1]) / (2.0 * h)
+    err = np.abs(dirs - fd) / np.abs(fd)
+    print(f"W {Wg:.6e}; adjoint {dirs}, FD {fd}, rel err {err}", flush=True)
+    assert np.all(err <= 1e-6)
+
+
 def test_energy_grad_is_twice_the_energy_along_the_state():
     """W is a quadratic form of the field state f, so dW/df . f = 2 W (Euler)."""
     w = W.spec("tsi1d_big", n=(64,), ppc=16, length=(4.0 * math.pi,))
@@ -196,7 +270,7 @@ def test_energy_grad_is_twice_the_energy_along_the_state():
 
 
 def test_adjoint_rejects_unsupported_configurations():
-    w = W.spec("weibel2d", n=(16, 16), ppc=4)
+    w = W.spec("weibel3d", n=(8, 8, 8), ppc=2)
     cfg = G.config_from_dict(W.config_dict(w))
     x, u, q = W.particles(w)
     sim = G.Simulation(cfg, q.size, device="cuda:0")
