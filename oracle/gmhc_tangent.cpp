@@ -1,5 +1,5 @@
 // gmhc_tangent.cpp -- forward-mode derivatives (the tangent-linear model) of a 1D
-// GM-HC-CN run (1D or 2D) of the CPU oracle.
+// GM-HC-CN run (1D, 2D or 3D) of the CPU oracle.
 //
 // TEST INFRASTRUCTURE ONLY, like gmhc_oracle.cpp: the independent reference for the
 // GPU library's reverse-mode adjoint.  The paper defines no derivative of its step;
@@ -19,7 +19,7 @@
 // (implicit-function theorem), so the result is the derivative of the converged step,
 // independent of the iteration history.
 //
-// Scope: dim 1 or 2, the quadratic shape S_2, damped Picard outer iteration, zero initial
+// Scope: dim 1, 2 or 3, the quadratic shape S_2, damped Picard outer iteration, zero initial
 // potentials (A^0 = U^0 = 0), FP64, no refinement.  The output is the field energy W
 // and the kinetic energy K at the start and after `steps` steps, each with its
 // derivatives along the directions seeded on the initial positions, mechanical
@@ -108,12 +108,12 @@ Dn sqrt(const Dn& a) {
 }
 Dn fabs(const Dn& a) { return a.v < 0.0 ? -a : a; }
 
-// ---- mesh (d = 1 or 2) ---------------------------------------------------------
-// Node g = i0 + n0 i1 at lo + i h (periodic); unresolved axes have n = 1.
+// ---- mesh (d = 1, 2 or 3) ------------------------------------------------------
+// Node g = i0 + n0 (i1 + n1 i2) at lo + i h (periodic); unresolved axes have n = 1.
 struct Mesh {
   int d;
-  int n[2];
-  double lo[2], L[2], h[2], dV;
+  int n[3];
+  double lo[3], L[3], h[3], dV;
   int Ng;
   int wrap(int l, int64_t i) const { return (int)(((i % n[l]) + n[l]) % n[l]); }
 };
@@ -165,11 +165,15 @@ void fft1(cplx* a, int n, int stride, bool inverse) {  // radix-2, forward unnor
   }
   for (int i = 0; i < n; ++i) a[(int64_t)i * stride] = inverse ? b[i] / (double)n : b[i];
 }
-// Multi-dimensional transform of one layer: along axis 0 for every row, then along axis 1.
+// Multi-dimensional transform of one layer, one axis after the other.
 void fft(const Mesh& M, CVec& a, bool inverse) {
-  for (int r = 0; r < M.n[1]; ++r) fft1(a.data() + (int64_t)r * M.n[0], M.n[0], 1, inverse);
+  const int n0 = M.n[0], n1 = M.n[1], n2 = M.n[2];
+  for (int r = 0; r < n1 * n2; ++r) fft1(a.data() + (int64_t)r * n0, n0, 1, inverse);
   if (M.d > 1)
-    for (int c = 0; c < M.n[0]; ++c) fft1(a.data() + c, M.n[1], M.n[0], inverse);
+    for (int z = 0; z < n2; ++z)
+      for (int c = 0; c < n0; ++c) fft1(a.data() + (int64_t)z * n0 * n1 + c, n1, n0, inverse);
+  if (M.d > 2)
+    for (int c = 0; c < n0 * n1; ++c) fft1(a.data() + c, n2, n0 * n1, inverse);
 }
 
 // Spectral field of every layer: S[l][m].
@@ -196,10 +200,10 @@ Spec zero_spec(const Mesh& M) { return Spec(ND + 1, CVec(M.Ng, 0.0)); }
 
 // Wavenumbers of mode g (signed index, zero at an even-grid Nyquist index, as the spectral
 // derivative of the paper's Nyquist paragraph), and whether g lies on a Nyquist plane.
-void kvec(const Mesh& M, int g, double k[2], bool& nyq) {
-  const int idx[2] = {g % M.n[0], g / M.n[0]};
+void kvec(const Mesh& M, int g, double k[3], bool& nyq) {
+  const int idx[3] = {g % M.n[0], (g / M.n[0]) % M.n[1], g / (M.n[0] * M.n[1])};
   nyq = false;
-  for (int l = 0; l < 2; ++l) {
+  for (int l = 0; l < 3; ++l) {
     k[l] = 0.0;
     if (l >= M.d) continue;
     if (idx[l] == M.n[l] / 2) {
@@ -213,7 +217,7 @@ void kvec(const Mesh& M, int g, double k[2], bool& nyq) {
 void project(const Mesh& M, Spec& s, bool on) {
   if (!on) return;
   for (int g = 0; g < M.Ng; ++g) {
-    double k[2];
+    double k[3];
     bool nyq;
     kvec(M, g, k, nyq);
     if (nyq)
@@ -223,7 +227,7 @@ void project(const Mesh& M, Spec& s, bool on) {
 Spec dspec(const Mesh& M, const Spec& s, int ax) {  // d/dx_ax: i k_ax
   Spec r = s;
   for (int g = 0; g < M.Ng; ++g) {
-    double k[2];
+    double k[3];
     bool nyq;
     kvec(M, g, k, nyq);
     for (auto& l : r) l[g] *= cplx(0.0, ax < M.d ? k[ax] : 0.0);
@@ -233,11 +237,11 @@ Spec dspec(const Mesh& M, const Spec& s, int ax) {  // d/dx_ax: i k_ax
 
 // ---- particle part -----------------------------------------------------------------
 struct Part {
-  Dn x[2], P[3], q, m, vbar[3];
+  Dn x[3], P[3], q, m, vbar[3];
 };
 
 struct TrialFields {  // real trial fields of one outer iteration
-  DVec gphi[2], An[3], Anp1[3];
+  DVec gphi[3], An[3], Anp1[3];
 };
 
 struct Dep {  // one particle's orbit-averaged shape, as (node, weight) pairs
@@ -291,36 +295,44 @@ struct Ctx {
 // derivatives with respect to the position, as (node, S, dS/dx_0, dS/dx_1).
 struct NodeW {
   int g;
-  Dn S, dS[2];
+  Dn S, dS[3];
 };
-void node_weights(const Mesh& M, const Dn xi[2], std::vector<NodeW>& out) {
+void node_weights(const Mesh& M, const Dn xi[3], std::vector<NodeW>& out) {
   out.clear();
-  int64_t b[2] = {(int64_t)std::floor(xi[0].v), M.d > 1 ? (int64_t)std::floor(xi[1].v) : 0};
-  const int r1 = M.d > 1 ? 2 : 0;
-  for (int64_t j = b[1] - r1; j <= b[1] + r1; ++j) {
-    Dn Sy = cst(1.0), dSy = cst(0.0);
-    if (M.d > 1) {
-      Sy = S2(xi[1] - (double)j);
-      dSy = dS2(xi[1] - (double)j) / M.h[1];
-    }
-    for (int64_t i = b[0] - 2; i <= b[0] + 2; ++i) {
-      Dn Sx = S2(xi[0] - (double)i), dSx = dS2(xi[0] - (double)i) / M.h[0];
-      NodeW w;
-      w.S = Sx * Sy;
-      w.dS[0] = dSx * Sy;
-      w.dS[1] = Sx * dSy;
-      if (w.S.v == 0.0 && w.dS[0].v == 0.0 && w.dS[1].v == 0.0) continue;
-      w.g = M.wrap(0, i) + M.n[0] * (M.d > 1 ? M.wrap(1, j) : 0);
-      out.push_back(w);
+  int64_t b[3];
+  Dn S1[3][5], dS1[3][5];  // per axis: the five candidates around floor(xi)
+  for (int l = 0; l < 3; ++l) {
+    b[l] = l < M.d ? (int64_t)std::floor(xi[l].v) : 0;
+    for (int o = 0; o < 5; ++o) {
+      if (l < M.d) {
+        S1[l][o] = S2(xi[l] - (double)(b[l] + o - 2));
+        dS1[l][o] = dS2(xi[l] - (double)(b[l] + o - 2)) / M.h[l];
+      } else {
+        S1[l][o] = cst(o == 2 ? 1.0 : 0.0);
+        dS1[l][o] = cst(0.0);
+      }
     }
   }
+  const int z0 = M.d > 2 ? 0 : 2, z1 = M.d > 2 ? 5 : 3, y0 = M.d > 1 ? 0 : 2, y1 = M.d > 1 ? 5 : 3;
+  for (int oz = z0; oz < z1; ++oz)
+    for (int oy = y0; oy < y1; ++oy)
+      for (int ox = 0; ox < 5; ++ox) {
+        NodeW w;
+        w.S = S1[0][ox] * S1[1][oy] * S1[2][oz];
+        w.dS[0] = dS1[0][ox] * S1[1][oy] * S1[2][oz];
+        w.dS[1] = S1[0][ox] * dS1[1][oy] * S1[2][oz];
+        w.dS[2] = S1[0][ox] * S1[1][oy] * dS1[2][oz];
+        if (w.S.v == 0.0 && w.dS[0].v == 0.0 && w.dS[1].v == 0.0 && w.dS[2].v == 0.0) continue;
+        w.g = M.wrap(0, b[0] + ox - 2) + M.n[0] * (M.wrap(1, b[1] + oy - 2) + M.n[1] * M.wrap(2, b[2] + oz - 2));
+        out.push_back(w);
+      }
 }
 
 // A_h(x) = sum_g F_g S_g(x) of three real mesh arrays.
-void interp3(const Ctx& C, const DVec F[3], const Dn x[2], Dn out[3]) {
+void interp3(const Ctx& C, const DVec F[3], const Dn x[3], Dn out[3]) {
   const Mesh& M = C.M;
-  Dn xi[2];
-  for (int l = 0; l < 2; ++l) xi[l] = l < M.d ? (x[l] - M.lo[l]) / M.h[l] : cst(0.0);
+  Dn xi[3];
+  for (int l = 0; l < 3; ++l) xi[l] = l < M.d ? (x[l] - M.lo[l]) / M.h[l] : cst(0.0);
   std::vector<NodeW> nw;
   node_weights(M, xi, nw);
   for (int c = 0; c < 3; ++c) out[c] = cst(0.0);
@@ -339,9 +351,9 @@ void orbit_eval(const Ctx& C, const TrialFields& F, const Part& p, const Dn vin[
   const double dt = C.cfg.dt, kappa = C.cfg.kappa;
   // knot split: S_2 has knots at half-integer node offsets on every axis; a crossing
   // counts when strictly inside the orbit.
-  Dn xi0[2], dxi[2];
+  Dn xi0[3], dxi[3];
   std::vector<Dn> brk{cst(0.0)};
-  for (int l = 0; l < 2; ++l) {
+  for (int l = 0; l < 3; ++l) {
     xi0[l] = l < d ? (p.x[l] - M.lo[l]) / M.h[l] : cst(0.0);
     dxi[l] = l < d ? dt * vin[l] / M.h[l] : cst(0.0);
     if (l >= d || dxi[l].v == 0.0) continue;
@@ -354,8 +366,8 @@ void orbit_eval(const Ctx& C, const TrialFields& F, const Part& p, const Dn vin[
   }
   brk.push_back(cst(1.0));
   std::sort(brk.begin(), brk.end(), [](const Dn& a, const Dn& b) { return a.v < b.v; });
-  Dn gp[2] = {cst(0.0), cst(0.0)}, D[3][2];
-  for (int c = 0; c < 3; ++c) D[c][0] = D[c][1] = cst(0.0);
+  Dn gp[3] = {cst(0.0), cst(0.0), cst(0.0)}, D[3][3];
+  for (int c = 0; c < 3; ++c) D[c][0] = D[c][1] = D[c][2] = cst(0.0);
   std::vector<NodeW> nw;
   for (size_t k = 0; k + 1 < brk.size(); ++k) {
     Dn a = brk[k], b = brk[k + 1];
@@ -363,7 +375,7 @@ void orbit_eval(const Ctx& C, const TrialFields& F, const Part& p, const Dn vin[
     for (int qd = 0; qd < C.ngl; ++qd) {
       Dn s = a + (b - a) * C.glx[qd];
       Dn wq = (b - a) * C.glw[qd];
-      Dn xs[2] = {xi0[0] + s * dxi[0], xi0[1] + s * dxi[1]};
+      Dn xs[3] = {xi0[0] + s * dxi[0], xi0[1] + s * dxi[1], xi0[2] + s * dxi[2]};
       node_weights(M, xs, nw);
       for (const NodeW& w : nw) {
         for (int l = 0; l < d; ++l) gp[l] += wq * F.gphi[l][w.g] * w.S;
@@ -375,9 +387,9 @@ void orbit_eval(const Ctx& C, const TrialFields& F, const Part& p, const Dn vin[
       }
     }
   }
-  Dn Am[3], Ap[3], xe[2];
+  Dn Am[3], Ap[3], xe[3];
   interp3(C, F.An, p.x, Am);
-  for (int l = 0; l < 2; ++l) xe[l] = l < d ? p.x[l] + dt * vin[l] : cst(0.0);
+  for (int l = 0; l < 3; ++l) xe[l] = l < d ? p.x[l] + dt * vin[l] : cst(0.0);
   interp3(C, F.Anp1, xe, Ap);
   const Dn& q = p.q;
   const Dn& m = p.m;
@@ -391,7 +403,7 @@ void orbit_eval(const Ctx& C, const TrialFields& F, const Part& p, const Dn vin[
     pm[c] = p.P[c] - q * Aep[c] + kick[c];
   }
   // B_eff = (K23, -K13, K12) of K = D~^T - D~ with D~ the zero-padded 3x3 D.
-  auto Dz = [&](int c, int l) { return (l < d && l < 2) ? D[c][l] : cst(0.0); };
+  auto Dz = [&](int c, int l) { return l < d ? D[c][l] : cst(0.0); };
   Dn Beff[3] = {Dz(2, 1) - Dz(1, 2), -(Dz(2, 0) - Dz(0, 2)), Dz(1, 0) - Dz(0, 1)};
   Dn um[3], tau[3], up[3], pp[3], pn[3], pn1[3], vEm[3], vEp[3];
   for (int c = 0; c < 3; ++c) {
@@ -478,13 +490,13 @@ void field_step(const Ctx& C, const State& S, const DVec j[3], State& T, TrialFi
   for (int c = 0; c < 3; ++c) T.A[c] = T.U[c] = zero_spec(M);
   Spec phih = zero_spec(M);
   for (int g = 0; g < M.Ng; ++g) {
-    double k[2];
+    double k[3];
     bool nyq;
     kvec(M, g, k, nyq);
-    const double a = kap2 * (k[0] * k[0] + k[1] * k[1]), den = 1.0 + h * h * a / 4.0;
+    const double a = kap2 * (k[0] * k[0] + k[1] * k[1] + k[2] * k[2]), den = 1.0 + h * h * a / 4.0;
     for (int l = 0; l <= ND; ++l) {
       // continuity: rho^{n+1} = rho^n - dt i k . jh
-      const cplx divj = cplx(0.0, k[0]) * jh[0][l][g] + cplx(0.0, k[1]) * jh[1][l][g];
+      const cplx divj = cplx(0.0, k[0]) * jh[0][l][g] + cplx(0.0, k[1]) * jh[1][l][g] + cplx(0.0, k[2]) * jh[2][l][g];
       T.rho[l][g] = S.rho[l][g] - h * divj;
       const cplx rh = 0.5 * (S.rho[l][g] + T.rho[l][g]);
       T.phi[l][g] = ((1.0 - h * h * a / 4.0) * S.phi[l][g] + h * S.psi[l][g] + 0.5 * h * h * kap2 * C.cfg.sigma1 * rh) / den;
@@ -505,21 +517,21 @@ void field_step(const Ctx& C, const State& S, const DVec j[3], State& T, TrialFi
 }
 
 // Energies of the state: field energy W = sum (|E|^2 / (2 sigma1) + |B|^2 / (2 sigma2)) dV
-// with E = -grad phi - U and B = curl A (no z derivative); kinetic energy
+// with E = -grad phi - U and B = curl A; kinetic energy
 // sum |p|^2 / (m (gamma + 1)) with p = P - q A_h(x).
 void energies(const Ctx& C, const State& S, const std::vector<Part>& parts, Dn& W, Dn& K) {
   const Mesh& M = C.M;
-  DVec gph[2], U[3], A[3], dA[3][2];
-  for (int l = 0; l < 2; ++l) gph[l] = to_real(M, dspec(M, S.phi, l));
+  DVec gph[3], U[3], A[3], dA[3][3];
+  for (int l = 0; l < 3; ++l) gph[l] = to_real(M, dspec(M, S.phi, l));
   for (int c = 0; c < 3; ++c) {
     U[c] = to_real(M, S.U[c]);
     A[c] = to_real(M, S.A[c]);
-    for (int l = 0; l < 2; ++l) dA[c][l] = to_real(M, dspec(M, S.A[c], l));
+    for (int l = 0; l < 3; ++l) dA[c][l] = to_real(M, dspec(M, S.A[c], l));
   }
   W = cst(0.0);
   for (int g = 0; g < M.Ng; ++g) {
-    Dn E[3] = {-gph[0][g] - U[0][g], -gph[1][g] - U[1][g], -U[2][g]};
-    Dn B[3] = {dA[2][1][g], -dA[2][0][g], dA[1][0][g] - dA[0][1][g]};
+    Dn E[3] = {-gph[0][g] - U[0][g], -gph[1][g] - U[1][g], -gph[2][g] - U[2][g]};
+    Dn B[3] = {dA[2][1][g] - dA[1][2][g], dA[0][2][g] - dA[2][0][g], dA[1][0][g] - dA[0][1][g]};
     Dn e2 = E[0] * E[0] + E[1] * E[1] + E[2] * E[2], b2 = B[0] * B[0] + B[1] * B[1] + B[2] * B[2];
     W += (e2 / (2.0 * C.cfg.sigma1) + b2 / (2.0 * C.cfg.sigma2)) * M.dV;
   }
@@ -653,8 +665,8 @@ void initialize(const Ctx& C, std::vector<Part>& parts, State& S) {
     Dn g = gamma_of(p.P, p.m, C.cfg.kappa);
     Dn v[3];
     for (int c = 0; c < 3; ++c) v[c] = p.P[c] / (p.m * g);
-    Dn xi[2];
-    for (int l = 0; l < 2; ++l) xi[l] = l < M.d ? (p.x[l] - M.lo[l]) / M.h[l] : cst(0.0);
+    Dn xi[3];
+    for (int l = 0; l < 3; ++l) xi[l] = l < M.d ? (p.x[l] - M.lo[l]) / M.h[l] : cst(0.0);
     node_weights(M, xi, nw);
     for (const NodeW& w : nw) {
       if (w.S.v == 0.0) continue;
@@ -674,10 +686,10 @@ void initialize(const Ctx& C, std::vector<Part>& parts, State& S) {
   }
   S.phi = S.psi = zero_spec(M);
   for (int g = 0; g < M.Ng; ++g) {
-    double k[2];
+    double k[3];
     bool nyq;
     kvec(M, g, k, nyq);
-    const double k2 = k[0] * k[0] + k[1] * k[1];
+    const double k2 = k[0] * k[0] + k[1] * k[1] + k[2] * k[2];
     if (k2 > 0.0)
       for (int l = 0; l <= ND; ++l) S.phi[l][g] = C.cfg.sigma1 * S.rho[l][g] / k2;
   }
@@ -696,7 +708,7 @@ extern "C" {
 int orc_tangent_run(const orc_config* cfg, int64_t n, const double* x, const double* u, const double* q, int nd,
                     const double* dx, const double* du, const double* dq, int steps, double* E, double* dE,
                     int64_t* outer) {
-  if (cfg->dim < 1 || cfg->dim > 2 || (cfg->shape_order != 0 && cfg->shape_order != 2) || cfg->outer_scheme != 0 ||
+  if (cfg->dim < 1 || cfg->dim > 3 || (cfg->shape_order != 0 && cfg->shape_order != 2) || cfg->outer_scheme != 0 ||
       cfg->refine_levels != 0 || nd < 0 || nd > kMaxDir || cfg->gl_order < 1 || cfg->gl_order > 64)
     return -1;
   const int d = cfg->dim;
@@ -705,7 +717,7 @@ int orc_tangent_run(const orc_config* cfg, int64_t n, const double* x, const dou
   C.cfg = *cfg;
   C.M.d = d;
   C.M.dV = 1.0;
-  for (int l = 0; l < 2; ++l) {
+  for (int l = 0; l < 3; ++l) {
     C.M.n[l] = l < d ? cfg->n[l] : 1;
     C.M.lo[l] = l < d ? cfg->lo[l] : 0.0;
     C.M.L[l] = l < d ? cfg->len[l] : 1.0;
@@ -715,7 +727,7 @@ int orc_tangent_run(const orc_config* cfg, int64_t n, const double* x, const dou
       C.M.dV *= C.M.h[l];
     }
   }
-  C.M.Ng = C.M.n[0] * C.M.n[1];
+  C.M.Ng = C.M.n[0] * C.M.n[1] * C.M.n[2];
   C.ngl = cfg->gl_order;
   orc_gl_rule(C.ngl, C.glx, C.glw);
   std::vector<Part> parts(n);
@@ -724,7 +736,7 @@ int orc_tangent_run(const orc_config* cfg, int64_t n, const double* x, const dou
     p.q = cst(q[i]);
     Dn uu[3];
     for (int c = 0; c < 3; ++c) uu[c] = cst(u[c * n + i]);
-    for (int l = 0; l < 2; ++l) p.x[l] = cst(l < d ? x[l * n + i] : 0.0);
+    for (int l = 0; l < 3; ++l) p.x[l] = cst(l < d ? x[l * n + i] : 0.0);
     for (int k = 0; k < nd; ++k) {
       for (int l = 0; l < d; ++l) p.x[l].d[k] = dx[(k * d + l) * n + i];
       p.q.d[k] = dq[k * n + i];

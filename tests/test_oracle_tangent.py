@@ -1,6 +1,6 @@
 """Pins of the oracle's forward-mode derivatives (oracle/gmhc_tangent.cpp), CPU only.
 
-The tangent oracle carries derivatives through a 1D or 2D run (Algorithm 1 with the orbit
+The tangent oracle carries derivatives through a 1D, 2D or 3D run (Algorithm 1 with the orbit
 maps, the GM-HC step, the secant velocity and the CN field step) by dual-number
 arithmetic.  It is pinned here against what does not depend on it:
   * its values equal the main oracle's run (same step, separately written);
@@ -107,31 +107,37 @@ def test_single_beam_direction_and_zero_direction():
     assert dE[1, 0] > 0.0
 
 
-def _case2d():
-    w = W.spec("weibel2d", n=(16, 16), ppc=4)
+def _case_nd(dim):
+    if dim == 2:
+        w = W.spec("weibel2d", n=(16, 16), ppc=4)
+    else:
+        w = W.spec("weibel3d", n=(8, 8, 8), ppc=2)
     x, u, q = W.particles(w)
-    cfg = O.config_from_dict(W.config_dict(w), gl_order=3)
+    cfg = O.config_from_dict(W.config_dict(w), gl_order=dim + 1)
     rng = np.random.default_rng(3)
     n = q.size
-    dx = 0.05 * rng.standard_normal((3, 2, n))
+    dx = 0.05 * rng.standard_normal((3, dim, n))
     du = 0.1 * rng.standard_normal((3, 3, n))
     dq = q * rng.standard_normal((3, n))
     return cfg, x, u, q, dx, du, dq
 
 
-def test_tangent_2d_values_derivatives_and_energy_identity():
-    """2D (16 x 16, 1024 particles, 3 steps): values equal the main oracle's run, the
-    derivatives along random directions of positions, momenta and charges equal central
-    differences of the main oracle, and d(K + W) is conserved."""
-    cfg, x, u, q, dx, du, dq = _case2d()
-    E, dE, _ = O.tangent_run(cfg, x, u, q, STEPS, dx=dx, du=du, dq=dq)
+@pytest.mark.parametrize("dim", [2, 3])
+def test_tangent_multid_values_derivatives_and_energy_identity(dim):
+    """2D (16 x 16, 1024 particles) and 3D (8^3, 1024 particles), 3 and 2 steps: values
+    equal the main oracle's run, the derivatives along random directions of positions,
+    momenta and charges equal central differences of the main oracle, and d(K + W) is
+    conserved."""
+    cfg, x, u, q, dx, du, dq = _case_nd(dim)
+    steps = STEPS if dim == 2 else 2
+    E, dE, _ = O.tangent_run(cfg, x, u, q, steps, dx=dx, du=du, dq=dq)
 
     def run(xx, uu, qq):
         s = O.OracleSim(cfg)
         s.load_particles(xx, uu, qq)
         s.initialize()
         d0 = s.diagnostics()
-        for _ in range(STEPS):
+        for _ in range(steps):
             s.step()
         d = s.diagnostics()
         return np.array([d0["field"], d0["kinetic"], d["field"], d["kinetic"]])
