@@ -6,8 +6,7 @@
 
 namespace gmhc {
 
-// ---- adjoint of the step and of initialization (adjoint.hip; 1D and 2D, quadratic shape,
-// FP64) --
+// ---- adjoint of the step and of initialization (adjoint.hip; quadratic shape, FP64) --
 
 enum AdjMode { ADJ_BOUND = 0, ADJ_SCATTER = 1, ADJ_FINAL = 2, ADJ_PREP = 3 };
 // scattered field arrays in dimension d: grad phi (d), A^n (3), A^{n+1} (3)

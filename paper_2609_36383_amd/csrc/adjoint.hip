@@ -1,5 +1,5 @@
 // adjoint.hip -- reverse-mode adjoint of the implicit step and of initialization for
-// one- and two-dimensional runs with the quadratic shape in FP64.
+// runs in one, two or three dimensions with the quadratic shape in FP64.
 //
 // The paper defines the step (Algorithm 1) but no derivative of it.  The adjoint here
 // differentiates the converged step, not its iteration history: the step's unknowns
@@ -74,8 +74,8 @@ __device__ __forceinline__ double dot3(const double a[3], const double b[3]) {
 // mesh index, S, dS/dx_j and d2S/dx_j dx_k.
 template <int D>
 struct NodeWeights {
-  int i0[2];
-  double w[2][3], w1[2][3], w2[2][3];  // per axis and offset -1, 0, +1: S_2, S_2' / h, S_2'' / h^2
+  int i0[3];
+  double w[3][3], w1[3][3], w2[3][3];  // per axis and offset -1, 0, +1: S_2, S_2' / h, S_2'' / h^2
   __device__ __forceinline__ void at(const Mesh& M, const double xs[D]) {
     int b[D];
     for (int l = 0; l < D; ++l) b[l] = (int)floor(xs[l] + 0.5);
@@ -94,16 +94,17 @@ struct NodeWeights {
       }
     }
   }
-  // node k = ox + 3 oy of the stencil
+  // node k = ox + 3 (oy + 3 oz) of the stencil
+  __device__ __forceinline__ static int off(int l, int k) { return l == 0 ? k % 3 : (l == 1 ? (k / 3) % 3 : k / 9); }
   __device__ __forceinline__ int node(const Mesh& M, int k) const {
-    const int ox = k % 3;
-    int g = wrapi(i0[0] + ox - 1, M.n[0]);
-    if (D > 1) g += M.n[0] * wrapi(i0[1] + k / 3 - 1, M.n[1]);
+    int g = wrapi(i0[0] + off(0, k) - 1, M.n[0]);
+    if (D > 1) g += M.n[0] * wrapi(i0[D > 1 ? 1 : 0] + off(1, k) - 1, M.n[1]);
+    if (D > 2) g += M.n[0] * M.n[1] * wrapi(i0[D > 2 ? 2 : 0] + off(2, k) - 1, M.n[2]);
     return g;
   }
-  __device__ __forceinline__ int unode(int l, int k) const { return i0[l] + (l == 0 ? k % 3 : k / 3) - 1; }
+  __device__ __forceinline__ int unode(int l, int k) const { return i0[l] + off(l, k) - 1; }
   __device__ __forceinline__ void vals(int k, double& S, double dS[D], double ddS[D][D]) const {
-    const int o[2] = {k % 3, k / 3};
+    const int o[3] = {k % 3, (k / 3) % 3, k / 9};
     S = 1.0;
     for (int l = 0; l < D; ++l) S *= w[l][o[l]];
     for (int j = 0; j < D; ++j) {
@@ -120,7 +121,7 @@ struct NodeWeights {
   }
 };
 template <int D>
-constexpr int kStencil = D == 1 ? 3 : 9;
+constexpr int kStencil = D == 1 ? 3 : (D == 2 ? 9 : 27);
 
 // Orbit quantities of one particle: the gathers the evaluation uses (grad-phi-bar, D,
 // A^-, A^+), their derivatives with respect to the start x_j and the displacement
@@ -424,6 +425,10 @@ __device__ void reverse(const Fwd<D>& f, const double wv[3], const double wP[3],
     r.Dm[2][D > 1 ? 1 : 0] += Bb[0];
     r.Dm[0][D > 1 ? 1 : 0] -= Bb[2];
   }
+  if (D > 2) {
+    r.Dm[1][D > 2 ? 2 : 0] -= Bb[0];
+    r.Dm[0][D > 2 ? 2 : 0] += Bb[1];
+  }
   // um = pm / mk
   for (int c = 0; c < 3; ++c) pmb[c] += umb[c] / mk;
   r.m -= dot3(umb, f.um) / m;
@@ -512,15 +517,17 @@ __device__ __forceinline__ void rev_gath(const Rev<D>& r, double g[adj_ngath(D)]
 template <int D>
 constexpr int kWinX = D == 1 ? 32 : 16;
 template <int D>
-constexpr int kWinY = D == 1 ? 1 : 8;
+constexpr int kWinY = D == 1 ? 1 : (D == 2 ? 8 : 4);
 template <int D>
-constexpr int kWinNodes = kWinX<D> * kWinY<D>;
+constexpr int kWinZ = D == 3 ? 4 : 1;
+template <int D>
+constexpr int kWinNodes = kWinX<D> * kWinY<D> * kWinZ<D>;
 
 template <int D>
 struct WinAcc {
   unsigned long long* s;  // [D + 6][kWinNodes] pairs
   unsigned long long* g;  // global [D + 6][Ng] pairs
-  int wlo[2];
+  int wlo[3];
   const Mesh* M;
   double up;
   __device__ __forceinline__ void put(int f, const int node[D], double v) const {
@@ -528,9 +535,9 @@ struct WinAcc {
     bool in = true;
     for (int l = 0; l < D; ++l) {
       const int r = node[l] - wlo[l];
-      const int e = l == 0 ? kWinX<D> : kWinY<D>;
+      const int e = l == 0 ? kWinX<D> : (l == 1 ? kWinY<D> : kWinZ<D>);
       in = in && r >= 0 && r < e;
-      rel += l == 0 ? r : r * kWinX<D>;
+      rel += l == 0 ? r : (l == 1 ? r * kWinX<D> : r * kWinX<D> * kWinY<D>);
     }
     if (in) {
       long long H, L;
@@ -541,6 +548,7 @@ struct WinAcc {
     } else {
       int gi = wrapi(node[0], M->n[0]);
       if (D > 1) gi += M->n[0] * wrapi(node[D > 1 ? 1 : 0], M->n[1]);
+      if (D > 2) gi += M->n[0] * M->n[1] * wrapi(node[D > 2 ? 2 : 0], M->n[2]);
       fix_add(g, f * M->Ng + gi, v, up);
     }
   }
@@ -646,7 +654,7 @@ __global__ __launch_bounds__(kBlock) void k_adj_iter(AdjArgs a) {
   constexpr int NV = D + 6;
   __shared__ double red[kBlock];
   __shared__ unsigned long long sacc[2 * NV * kWinNodes<D>];
-  __shared__ int swlo[2];
+  __shared__ int swlo[3];
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const bool live = i < a.np;
   const Mesh& M = a.M;
@@ -694,13 +702,13 @@ __global__ __launch_bounds__(kBlock) void k_adj_iter(AdjArgs a) {
     if (threadIdx.x == 0) a.partials[blockIdx.x] = red[0];
     return;
   }
-  if (threadIdx.x < 2) swlo[threadIdx.x] = INT_MAX;
+  if (threadIdx.x < 3) swlo[threadIdx.x] = INT_MAX;
   for (int k = threadIdx.x; k < 2 * NV * kWinNodes<D>; k += kBlock) sacc[k] = 0ull;
   __syncthreads();
   if (live)
     for (int l = 0; l < D; ++l) atomicMin(&swlo[l], (int)floor(fmin(xi0[l], xi0[l] + dxi[l]) + 0.5) - 1);
   __syncthreads();
-  WinAcc<D> w{sacc, a.acc, {swlo[0], swlo[1]}, &M, a.fx_up};
+  WinAcc<D> w{sacc, a.acc, {swlo[0], swlo[1], swlo[2]}, &M, a.fx_up};
   if (live) {
     NodeWeights<D> nw;
     // Within a knot-split segment the stencil nodes stay the same, so each node's weights
@@ -768,7 +776,8 @@ __global__ __launch_bounds__(kBlock) void k_adj_iter(AdjArgs a) {
     if (H | L) {
       const int f = k / kWinNodes<D>, rel = k % kWinNodes<D>;
       int gi = wrapi(swlo[0] + rel % kWinX<D>, M.n[0]);
-      if (D > 1) gi += M.n[0] * wrapi(swlo[1] + rel / kWinX<D>, M.n[1]);
+      if (D > 1) gi += M.n[0] * wrapi(swlo[1] + (rel / kWinX<D>) % kWinY<D>, M.n[1]);
+      if (D > 2) gi += M.n[0] * M.n[1] * wrapi(swlo[2] + rel / (kWinX<D> * kWinY<D>), M.n[2]);
       unsigned long long* dst = a.acc + 2 * ((int64_t)f * M.Ng + gi);
       if (H) atomicAdd(dst, H);
       if (L) atomicAdd(dst + 1, L);
@@ -1030,16 +1039,20 @@ hipError_t launch_adj_particle(const AdjArgs& a, hipStream_t s) {
   if (a.np == 0) return hipSuccess;
   if (a.M.d == 1)
     hipLaunchKernelGGL(k_adj_particle<1>, dim3(nblocks(a.np)), dim3(kBlock), 0, s, a);
-  else
+  else if (a.M.d == 2)
     hipLaunchKernelGGL(k_adj_particle<2>, dim3(nblocks(a.np)), dim3(kBlock), 0, s, a);
+  else
+    hipLaunchKernelGGL(k_adj_particle<3>, dim3(nblocks(a.np)), dim3(kBlock), 0, s, a);
   return hipGetLastError();
 }
 hipError_t launch_adj_iter(const AdjArgs& a, hipStream_t s) {
   if (a.np == 0) return hipSuccess;
   if (a.M.d == 1)
     hipLaunchKernelGGL(k_adj_iter<1>, dim3(nblocks(a.np)), dim3(kBlock), 0, s, a);
-  else
+  else if (a.M.d == 2)
     hipLaunchKernelGGL(k_adj_iter<2>, dim3(nblocks(a.np)), dim3(kBlock), 0, s, a);
+  else
+    hipLaunchKernelGGL(k_adj_iter<3>, dim3(nblocks(a.np)), dim3(kBlock), 0, s, a);
   return hipGetLastError();
 }
 int64_t adj_particle_blocks(int64_t np) { return nblocks(np); }
@@ -1061,8 +1074,10 @@ hipError_t launch_adj_init_particle(const AdjInitArgs& a, hipStream_t s) {
   if (a.np == 0) return hipSuccess;
   if (a.M.d == 1)
     hipLaunchKernelGGL(k_adj_init_particle<1>, dim3(nblocks(a.np)), dim3(kBlock), 0, s, a);
-  else
+  else if (a.M.d == 2)
     hipLaunchKernelGGL(k_adj_init_particle<2>, dim3(nblocks(a.np)), dim3(kBlock), 0, s, a);
+  else
+    hipLaunchKernelGGL(k_adj_init_particle<3>, dim3(nblocks(a.np)), dim3(kBlock), 0, s, a);
   return hipGetLastError();
 }
 hipError_t launch_adj_update(double* mu, const double* mnew, int64_t n, double beta, double* out, hipStream_t s) {

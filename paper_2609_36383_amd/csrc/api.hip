@@ -1750,14 +1750,13 @@ size_t adj_carve(const gmhc_ctx* c, char* base, AdjScratch& a) {
   return (cv.off + 255) & ~(size_t)255;
 }
 
-// The configurations the adjoint covers: 1D and 2D, quadratic shape, FP64, no refinement,
-// a Gauss-Legendre order that integrates the derivative integrands exactly (>= dim + 1).
+// The configurations the adjoint covers: quadratic shape, FP64, no refinement, a
+// Gauss-Legendre order that integrates the derivative integrands exactly (>= dim + 1).
 int32_t adj_supported(gmhc_ctx* ctx) {
-  if (ctx->M.d > 2 || ctx->M.shape != 2 || ctx->prec != GMHC_FP64 || ctx->cfg.refine_levels != 0 ||
+  if (ctx->M.shape != 2 || ctx->prec != GMHC_FP64 || ctx->cfg.refine_levels != 0 ||
       ctx->ngl < ctx->M.d + 1)
     return fail(ctx, GMHC_EINVAL,
-                "the adjoint covers dim 1 and 2, shape_order 2, precision FP64, refine_levels 0 and gl_order 0 or "
-                ">= dim + 1");
+                "the adjoint covers shape_order 2, precision FP64, refine_levels 0 and gl_order 0 or >= dim + 1");
   return GMHC_OK;
 }
 
