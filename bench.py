@@ -310,6 +310,29 @@ def adjoint_block_2d():
     return out
 
 
+def adjoint_block_3d():
+    """The same on the paper's 3D two-stream run TSI-0.1 (32^3 mesh, 655,360 particles,
+    eigenmode start), 10 steps with checkpoints every 5 (reported: the derivative along the
+    beam speed)."""
+    import torch
+
+    from paper_2609_36383_amd import adjoint as A
+    from paper_2609_36383_amd import gmhc as G
+    from paper_2609_36383_amd import workloads as W
+
+    w = W.spec("tsi")
+    steps, every = 10, 5
+    cfg = G.config_from_dict(W.config_dict(w))
+    x, u, q = W.particles(w)
+    xt = torch.tensor(x, requires_grad=True)
+    ut = torch.tensor(u, requires_grad=True)
+    qt = torch.tensor(q, requires_grad=True)
+    out = _time_adjoint(lambda: A.field_energy_run(xt, ut, qt, cfg, steps, every, "cuda:0"), w["num_particles"], steps)
+    out["workload"] = f"tsi (TSI-0.1): 32^3 mesh, {w['num_particles']} particles, {steps} steps, checkpoints every {every}, FP64"
+    out["grad_beam_speed"] = float((ut.grad[0] * torch.sign(ut.detach()[0])).sum())
+    return out
+
+
 def _time_adjoint(run, n, steps):
     import torch
     torch.cuda.synchronize()
@@ -360,7 +383,8 @@ def main():
         copy_probe()
         return
     if args.adjoint_only:
-        print(json.dumps({"adjoint": adjoint_block(), "adjoint_2d": adjoint_block_2d()}), flush=True)
+        print(json.dumps({"adjoint": adjoint_block(), "adjoint_2d": adjoint_block_2d(),
+                          "adjoint_3d": adjoint_block_3d()}), flush=True)
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the library runs the orbit pass on a single MI355X "
@@ -418,6 +442,7 @@ def main():
     if not args.no_adjoint:
         out["adjoint"] = adjoint_block()
         out["adjoint_2d"] = adjoint_block_2d()
+        out["adjoint_3d"] = adjoint_block_3d()
     if not args.no_cpu_baseline:
         base = W.config_dict(w, fp32_bulk=main_fp32)
         out["cpu_baseline"] = cpu_baseline(w, base, r["ngl"], parts, shape=args.shape)

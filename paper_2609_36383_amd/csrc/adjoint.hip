@@ -718,41 +718,45 @@ __global__ __launch_bounds__(kBlock) void k_adj_iter(AdjArgs a) {
       const double len = sb - sa;
       int base[D];
       for (int l = 0; l < D; ++l) base[l] = (int)floor(xi0[l] + 0.5 * (sa + sb) * dxi[l] + 0.5);
-      double I0[kStencil<D>], Ia[kStencil<D>][D], Ib[kStencil<D>][D];
+      // one z-plane of the stencil at a time (3D), which keeps 9 nodes' integrals live
+      constexpr int NP = D == 3 ? 3 : 1, NK = kStencil<D> / NP;
+      for (int pl = 0; pl < NP; ++pl) {
+        double I0[NK], Ia[NK][D], Ib[NK][D];
 #pragma unroll
-      for (int k = 0; k < kStencil<D>; ++k) {
-        I0[k] = 0.0;
-        for (int l = 0; l < D; ++l) Ia[k][l] = Ib[k][l] = 0.0;
-      }
-      for (int q = 0; q < a.ngl; ++q) {
-        const double s = sa + len * a.glx[q], wq = len * a.glw[q];
-        double xs[D];
-        for (int l = 0; l < D; ++l) xs[l] = xi0[l] + s * dxi[l];
-        nw.at_base(M, xs, base);
+        for (int k = 0; k < NK; ++k) {
+          I0[k] = 0.0;
+          for (int l = 0; l < D; ++l) Ia[k][l] = Ib[k][l] = 0.0;
+        }
+        for (int q = 0; q < a.ngl; ++q) {
+          const double s = sa + len * a.glx[q], wq = len * a.glw[q];
+          double xs[D];
+          for (int l = 0; l < D; ++l) xs[l] = xi0[l] + s * dxi[l];
+          nw.at_base(M, xs, base);
 #pragma unroll
-        for (int k = 0; k < kStencil<D>; ++k) {
-          double S, dS[D], ddS[D][D];
-          nw.vals(k, S, dS, ddS);
-          I0[k] += wq * S;
-          for (int l = 0; l < D; ++l) {
-            Ia[k][l] += wq * (1.0 - s) * dS[l];
-            Ib[k][l] += wq * s * dS[l];
+          for (int k = 0; k < NK; ++k) {
+            double S, dS[D], ddS[D][D];
+            nw.vals(k + NK * pl, S, dS, ddS);
+            I0[k] += wq * S;
+            for (int l = 0; l < D; ++l) {
+              Ia[k][l] += wq * (1.0 - s) * dS[l];
+              Ib[k][l] += wq * s * dS[l];
+            }
           }
         }
-      }
 #pragma unroll
-      for (int k = 0; k < kStencil<D>; ++k) {
-        int node[D];
-        for (int l = 0; l < D; ++l) node[l] = nw.unode(l, k);
-        for (int l = 0; l < D; ++l) w.put(l, node, I0[k] * g[l]);
-        for (int c = 0; c < 3; ++c) {
-          double va = 0.0, vb = 0.0;
-          for (int l = 0; l < D; ++l) {
-            va += Ia[k][l] * g[D + c * D + l];
-            vb += Ib[k][l] * g[D + c * D + l];
+        for (int k = 0; k < NK; ++k) {
+          int node[D];
+          for (int l = 0; l < D; ++l) node[l] = nw.unode(l, k + NK * pl);
+          for (int l = 0; l < D; ++l) w.put(l, node, I0[k] * g[l]);
+          for (int c = 0; c < 3; ++c) {
+            double va = 0.0, vb = 0.0;
+            for (int l = 0; l < D; ++l) {
+              va += Ia[k][l] * g[D + c * D + l];
+              vb += Ib[k][l] * g[D + c * D + l];
+            }
+            w.put(D + c, node, va);
+            w.put(D + 3 + c, node, vb);
           }
-          w.put(D + c, node, va);
-          w.put(D + 3 + c, node, vb);
         }
       }
     });
