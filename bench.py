@@ -276,7 +276,7 @@ def adjoint_block():
 
     w = W.spec("tsi1d_big")
     steps, every = 50, 10
-    cfg = G.config_from_dict(W.config_dict(w))
+    cfg = G.config_from_dict(W.config_dict(w), sort_every=1)  # sorted every step, as the forward line
     eps = torch.full((len(w["modes"]),), w["eps"], dtype=torch.float64, requires_grad=True)
     u0 = torch.tensor(w["u_drift"], dtype=torch.float64, requires_grad=True)
     x, u, q = A.quiet1d_inputs(w, eps, u0)
@@ -299,7 +299,7 @@ def adjoint_block_2d():
 
     w = W.spec("weibel2d")
     steps, every = 20, 10
-    cfg = G.config_from_dict(W.config_dict(w))
+    cfg = G.config_from_dict(W.config_dict(w), sort_every=1)  # sorted every step, as the forward line
     x, u, q = W.particles(w)
     xt = torch.tensor(x, requires_grad=True)
     ut = torch.tensor(u, requires_grad=True)
@@ -322,7 +322,7 @@ def adjoint_block_3d():
 
     w = W.spec("tsi")
     steps, every = 10, 5
-    cfg = G.config_from_dict(W.config_dict(w))
+    cfg = G.config_from_dict(W.config_dict(w), sort_every=1)  # sorted every step, as the forward line
     x, u, q = W.particles(w)
     xt = torch.tensor(x, requires_grad=True)
     ut = torch.tensor(u, requires_grad=True)

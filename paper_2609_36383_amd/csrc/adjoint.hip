@@ -83,9 +83,11 @@ struct NodeWeights {
   }
   // the same with the stencil's centre node given (a segment's node, taken at its midpoint)
   __device__ __forceinline__ void at_base(const Mesh& M, const double xs[D], const int b[D]) {
+#pragma unroll
     for (int l = 0; l < D; ++l) {
       i0[l] = b[l];
       const double ih = M.inv_h[l];
+#pragma unroll
       for (int o = 0; o < 3; ++o) {
         const double t = xs[l] - (double)(i0[l] + o - 1);
         w[l][o] = s2(t);
@@ -163,21 +165,34 @@ __device__ __forceinline__ void walk_orbit(const AdjArgs& a, const double xi0[D]
   }
 }
 
-// The same walk, calling f(sa, sb) once per knot-split segment [sa, sb].
-template <int D, class Fn>
-__device__ __forceinline__ void walk_segments(const double xi0[D], const double dxi[D], Fn&& f) {
-  double kn[D], sk[D];
-  for (int l = 0; l < D; ++l) {
-    kn[l] = dxi[l] > 0.0 ? floor(xi0[l] - 0.5) + 1.5 : ceil(xi0[l] - 0.5) - 0.5;
-    sk[l] = dxi[l] != 0.0 ? (kn[l] - xi0[l]) / dxi[l] : 2.0;
+// The knot-split segments [sa, sb] of the same walk, one step at a time, so that the
+// lanes of a wave can take their segments in lockstep: step() gives the lane's segment of
+// this step (false for a step of zero length or a finished walk), advance() moves past it.
+template <int D>
+struct SegWalk {
+  double kn[D], sk[D], sa, sb;
+  bool live;
+  __device__ __forceinline__ void init(const double xi0[D], const double dxi[D], bool on) {
+    for (int l = 0; l < D; ++l) {
+      kn[l] = dxi[l] > 0.0 ? floor(xi0[l] - 0.5) + 1.5 : ceil(xi0[l] - 0.5) - 0.5;
+      sk[l] = dxi[l] != 0.0 ? (kn[l] - xi0[l]) / dxi[l] : 2.0;
+    }
+    sa = sb = 0.0;
+    live = on;
   }
-  double sa = 0.0;
-  for (int c = 0; c <= D * (kMaxCross + 1); ++c) {
-    double sb = 1.0;
+  __device__ __forceinline__ bool step() {
+    if (!live) return false;
+    sb = 1.0;
     for (int l = 0; l < D; ++l)
       if (sk[l] > sa && sk[l] < sb) sb = sk[l];
-    if (sb > sa) f(sa, sb);
-    if (sb >= 1.0) break;
+    return sb > sa;
+  }
+  __device__ __forceinline__ void advance(const double xi0[D], const double dxi[D]) {
+    if (!live) return;
+    if (sb >= 1.0) {
+      live = false;
+      return;
+    }
     for (int l = 0; l < D; ++l)
       if (sk[l] <= sb) {
         kn[l] += dxi[l] > 0.0 ? 1.0 : -1.0;
@@ -185,7 +200,7 @@ __device__ __forceinline__ void walk_segments(const double xi0[D], const double 
       }
     sa = sb;
   }
-}
+};
 
 template <int D>
 __device__ void gather(const AdjArgs& a, const double x[D], const double v[3], Gath<D>& G) {
@@ -523,6 +538,88 @@ constexpr int kWinZ = D == 3 ? 4 : 1;
 template <int D>
 constexpr int kWinNodes = kWinX<D> * kWinY<D> * kWinZ<D>;
 
+// Sum of a 64-bit integer over the 64 lanes of a wave (all lanes active), left on every
+// lane: partners lane ^ 1 and lane ^ 2 (quad permutations), lane ^ 7 within eight lanes
+// (half-row mirror), lane ^ 8 (row rotation by eight), then the row swaps lane ^ 16 and
+// lane ^ 32.  Integer addition is exact, so the total does not depend on the order.
+template <int CTRL>
+__device__ __forceinline__ long long dpp_i64(long long x) {
+  const uint64_t u = (uint64_t)x;
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_mov_dpp((int)(uint32_t)u, CTRL, 0xF, 0xF, false);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_mov_dpp((int)(uint32_t)(u >> 32), CTRL, 0xF, 0xF, false);
+  return (long long)(((uint64_t)hi << 32) | lo);
+}
+template <bool ROW16>
+__device__ __forceinline__ long long swap_i64(long long x) {
+  const uint64_t u = (uint64_t)x;
+  const uint32_t lo = (uint32_t)u, hi = (uint32_t)(u >> 32);
+  // the swap exchanges half the rows of its two operands; given the value twice, one
+  // result is the lane's own value and the other its partner's, and their sum is the pair's
+  if (ROW16) {
+    const auto l = __builtin_amdgcn_permlane16_swap(lo, lo, false, false);
+    const auto h = __builtin_amdgcn_permlane16_swap(hi, hi, false, false);
+    return (long long)((((uint64_t)h[0] << 32) | l[0]) + (((uint64_t)h[1] << 32) | l[1]));
+  } else {
+    const auto l = __builtin_amdgcn_permlane32_swap(lo, lo, false, false);
+    const auto h = __builtin_amdgcn_permlane32_swap(hi, hi, false, false);
+    return (long long)((((uint64_t)h[0] << 32) | l[0]) + (((uint64_t)h[1] << 32) | l[1]));
+  }
+}
+__device__ __forceinline__ long long wave_sum_i64(long long x) {
+  x += dpp_i64<0xB1>(x);   // quad_perm [1, 0, 3, 2]: lane ^ 1
+  x += dpp_i64<0x4E>(x);   // quad_perm [2, 3, 0, 1]: lane ^ 2
+  x += dpp_i64<0x141>(x);  // row_half_mirror: lane ^ 7
+  x += dpp_i64<0x128>(x);  // row_ror:8: lane ^ 8
+  x = swap_i64<true>(x);   // lane ^ 16
+  return swap_i64<false>(x);  // lane ^ 32
+}
+
+// Reduce-scatter of 32 64-bit integers per lane over the wave (all lanes active): after
+// it, lane l holds the wave total of value slot32(l), and the lanes with l even hold one
+// copy of each of the 32 totals.  Each step halves the values a lane holds: it keeps one
+// half and adds its partner's copy of that half (partners lane ^ 32 and lane ^ 16 by the
+// row swaps, lane ^ 8, lane ^ 7 and lane ^ 2 by DPP); the last step adds the lane ^ 1
+// partner's copy of the one value left.  The six partners span the wave.
+template <bool ROW16>
+__device__ __forceinline__ long long swap2_i64(long long A, long long B) {
+  // the lower rows of the swap keep A and receive the partner's A, the upper rows keep B
+  // and receive the partner's B
+  const uint64_t a = (uint64_t)A, b = (uint64_t)B;
+  const uint32_t alo = (uint32_t)a, ahi = (uint32_t)(a >> 32), blo = (uint32_t)b, bhi = (uint32_t)(b >> 32);
+  if (ROW16) {
+    const auto l = __builtin_amdgcn_permlane16_swap(alo, blo, false, false);
+    const auto h = __builtin_amdgcn_permlane16_swap(ahi, bhi, false, false);
+    return (long long)((((uint64_t)h[0] << 32) | l[0]) + (((uint64_t)h[1] << 32) | l[1]));
+  } else {
+    const auto l = __builtin_amdgcn_permlane32_swap(alo, blo, false, false);
+    const auto h = __builtin_amdgcn_permlane32_swap(ahi, bhi, false, false);
+    return (long long)((((uint64_t)h[0] << 32) | l[0]) + (((uint64_t)h[1] << 32) | l[1]));
+  }
+}
+template <int H, int CTRL>
+__device__ __forceinline__ void dpp_half_i64(long long* v, bool up) {
+#pragma unroll
+  for (int j = 0; j < H; ++j) {
+    const long long send = up ? v[j] : v[j + H];
+    const long long keep = up ? v[j + H] : v[j];
+    v[j] = keep + dpp_i64<CTRL>(send);
+  }
+}
+__device__ __forceinline__ long long rs32_i64(long long (&v)[32], int lane) {
+#pragma unroll
+  for (int j = 0; j < 16; ++j) v[j] = swap2_i64<false>(v[j], v[j + 16]);
+#pragma unroll
+  for (int j = 0; j < 8; ++j) v[j] = swap2_i64<true>(v[j], v[j + 8]);
+  dpp_half_i64<4, 0x128>(v, (lane & 8) != 0);  // row_ror:8
+  dpp_half_i64<2, 0x141>(v, (lane & 4) != 0);  // row_half_mirror
+  dpp_half_i64<1, 0x4E>(v, (lane & 2) != 0);   // quad_perm [2, 3, 0, 1]
+  return v[0] + dpp_i64<0xB1>(v[0]);           // quad_perm [1, 0, 3, 2]
+}
+__device__ __forceinline__ int slot32(int lane) {
+  return 16 * ((lane >> 5) & 1) + 8 * ((lane >> 4) & 1) + 4 * ((lane >> 3) & 1) + 2 * ((lane >> 2) & 1) +
+         ((lane >> 1) & 1);
+}
+
 template <int D>
 struct WinAcc {
   unsigned long long* s;  // [D + 6][kWinNodes] pairs
@@ -530,26 +627,78 @@ struct WinAcc {
   int wlo[3];
   const Mesh* M;
   double up;
-  __device__ __forceinline__ void put(int f, const int node[D], double v) const {
-    int rel = 0;
+  // window-relative index of an unwrapped node, -1 outside the window
+  __device__ __forceinline__ int rel(const int node[D]) const {
+    int r = 0;
     bool in = true;
     for (int l = 0; l < D; ++l) {
-      const int r = node[l] - wlo[l];
+      const int o = node[l] - wlo[l];
       const int e = l == 0 ? kWinX<D> : (l == 1 ? kWinY<D> : kWinZ<D>);
-      in = in && r >= 0 && r < e;
-      rel += l == 0 ? r : (l == 1 ? r * kWinX<D> : r * kWinX<D> * kWinY<D>);
+      in = in && o >= 0 && o < e;
+      r += l == 0 ? o : (l == 1 ? o * kWinX<D> : o * kWinX<D> * kWinY<D>);
     }
-    if (in) {
-      long long H, L;
-      fix_split(v, up, H, L);
-      const int k = 2 * (f * kWinNodes<D> + rel);
-      if (H) atomicAdd(s + k, (unsigned long long)H);
-      if (L) atomicAdd(s + k + 1, (unsigned long long)L);
-    } else {
+    return in ? r : -1;
+  }
+  // The put of NE entries by a whole wave whose lanes all target the same window nodes
+  // (every lane active; a lane without a value passes zeros): entry e has the value
+  // val(e) on each lane and the window entry ent(e) (field * window nodes + node, the
+  // same on every lane).  The limbs are summed over the wave by reduce-scatters of 16
+  // entries at a time, and the lane holding a total adds it: one LDS atomic per entry
+  // and limb instead of one per lane.
+  template <int NE, class Val, class Ent>
+  __device__ __forceinline__ void put_all(Val&& val, Ent&& ent, int lane) const {
+#pragma unroll
+    for (int c0 = 0; c0 < NE; c0 += 16) {
+      long long v[32];
+#pragma unroll
+      for (int i = 0; i < 16; ++i) {
+        long long H = 0, L = 0;
+        if (c0 + i < NE) fix_split(val(c0 + i), up, H, L);
+        v[2 * i] = H;
+        v[2 * i + 1] = L;
+      }
+      const long long tot = rs32_i64(v, lane);
+      const int slot = slot32(lane), e = c0 + slot / 2;
+      if ((lane & 1) == 0 && e < NE && tot != 0) atomicAdd(s + 2 * ent(e) + (slot & 1), (unsigned long long)tot);
+    }
+  }
+  // The put of a whole wave (every lane active; a lane without a value passes v = 0).
+  // Lanes whose limbs go to the same window entry are summed across the wave first and
+  // added by one lane, which takes the 64-way same-address serialization off the LDS
+  // atomics; up to two such groups are taken, the rest add their own limbs.  Integer sums
+  // do not depend on the grouping, so every entry ends with the same bits as when each
+  // lane adds its own limbs.
+  __device__ __forceinline__ void put_wave(int f, int r, const int node[D], double v, int lane) const {
+    long long H, L;
+    fix_split(v, up, H, L);
+    const bool c = (H | L) != 0;
+    if (c && r < 0) {
       int gi = wrapi(node[0], M->n[0]);
       if (D > 1) gi += M->n[0] * wrapi(node[D > 1 ? 1 : 0], M->n[1]);
       if (D > 2) gi += M->n[0] * M->n[1] * wrapi(node[D > 2 ? 2 : 0], M->n[2]);
-      fix_add(g, f * M->Ng + gi, v, up);
+      if (H) atomicAdd(g + 2 * ((int64_t)f * M->Ng + gi), (unsigned long long)H);
+      if (L) atomicAdd(g + 2 * ((int64_t)f * M->Ng + gi) + 1, (unsigned long long)L);
+    }
+    bool pend = c && r >= 0;
+    uint64_t act = __ballot(pend);
+#pragma unroll 1
+    for (int round = 0; round < 2 && act != 0; ++round) {
+      const int lead = __ffsll((long long)act) - 1;  // wave-uniform
+      const int rl = __builtin_amdgcn_readlane(r, lead);
+      const bool mine = pend && r == rl;
+      const long long hs = wave_sum_i64(mine ? H : 0ll), ls = wave_sum_i64(mine ? L : 0ll);
+      if (lane == lead) {
+        const int k = 2 * (f * kWinNodes<D> + rl);
+        if (hs) atomicAdd(s + k, (unsigned long long)hs);
+        if (ls) atomicAdd(s + k + 1, (unsigned long long)ls);
+      }
+      pend = pend && !mine;
+      act = __ballot(pend);
+    }
+    if (pend) {
+      const int k = 2 * (f * kWinNodes<D> + r);
+      if (H) atomicAdd(s + k, (unsigned long long)H);
+      if (L) atomicAdd(s + k + 1, (unsigned long long)L);
     }
   }
 };
@@ -680,6 +829,7 @@ __global__ __launch_bounds__(kBlock) void k_adj_iter(AdjArgs a) {
     for (int c = 0; c < 3; ++c)
       for (int j = 0; j < D; ++j) J[c][j] = a.cache[(c * D + j) * a.ps + i];
     inner_solve<D>(J, rhs, mv);
+#pragma unroll
     for (int k = 0; k < NG; ++k) {
       double s = a.cache[(4 * D + 3 * NG + k) * a.ps + i];
       for (int c = 0; c < 3; ++c) s += mv[c] * a.cache[(4 * D + c * NG + k) * a.ps + i];
@@ -702,76 +852,203 @@ __global__ __launch_bounds__(kBlock) void k_adj_iter(AdjArgs a) {
     if (threadIdx.x == 0) a.partials[blockIdx.x] = red[0];
     return;
   }
+  // The window is taken periodically: each lane's nodes are moved by whole periods to lie
+  // within half a period of the block's first particle (always live), so a block whose
+  // particles straddle the periodic seam (a cell-sorted block at node 0 holds particles
+  // just below the top of the box) still shares one window.  The shift sh only relabels
+  // the nodes; the weights and the wrapped mesh indices are unchanged.
+  __shared__ double sref[3];
   if (threadIdx.x < 3) swlo[threadIdx.x] = INT_MAX;
+  if (threadIdx.x == 0)
+    for (int l = 0; l < D; ++l) sref[l] = xi0[l];
   for (int k = threadIdx.x; k < 2 * NV * kWinNodes<D>; k += kBlock) sacc[k] = 0ull;
   __syncthreads();
+  int sh[D];
+  for (int l = 0; l < D; ++l) {
+    const double nl = (double)M.n[l];
+    sh[l] = live ? -M.n[l] * (int)rint((xi0[l] - sref[l]) / nl) : 0;
+  }
   if (live)
-    for (int l = 0; l < D; ++l) atomicMin(&swlo[l], (int)floor(fmin(xi0[l], xi0[l] + dxi[l]) + 0.5) - 1);
+    for (int l = 0; l < D; ++l) atomicMin(&swlo[l], (int)floor(fmin(xi0[l], xi0[l] + dxi[l]) + 0.5) - 1 + sh[l]);
   __syncthreads();
   WinAcc<D> w{sacc, a.acc, {swlo[0], swlo[1], swlo[2]}, &M, a.fx_up};
-  if (live) {
-    NodeWeights<D> nw;
-    // Within a knot-split segment the stencil nodes stay the same, so each node's weights
-    // are integrated over the segment's Gauss points first (int S, int (1 - s) dS/dx_l,
-    // int s dS/dx_l) and scattered once per segment.
-    walk_segments<D>(xi0, dxi, [&](double sa, double sb) {
-      const double len = sb - sa;
-      int base[D];
-      for (int l = 0; l < D; ++l) base[l] = (int)floor(xi0[l] + 0.5 * (sa + sb) * dxi[l] + 0.5);
-      // one z-plane of the stencil at a time (3D), which keeps 9 nodes' integrals live
-      constexpr int NP = D == 3 ? 3 : 1, NK = kStencil<D> / NP;
-      for (int pl = 0; pl < NP; ++pl) {
-        double I0[NK], Ia[NK][D], Ib[NK][D];
+  const int lane = threadIdx.x & 63;
+  // Every lane of the wave takes part (a lane with no particle, or no segment at a step,
+  // puts zeros), so the puts can sum across the wave.  Within a knot-split segment the
+  // stencil nodes stay the same, so each node's weights are integrated over the segment's
+  // Gauss points first (int S, int (1 - s) dS/dx_l, int s dS/dx_l) and scattered once per
+  // segment.
+  SegWalk<D> sw;
+  sw.init(xi0, dxi, live);
+#pragma unroll 1
+  for (int step = 0; step <= D * (kMaxCross + 1); ++step) {
+    if (__ballot(sw.live) == 0) break;
+    const bool has = sw.step();
+    const double sa = has ? sw.sa : 0.0, sb = has ? sw.sb : 0.0, len = sb - sa;
+    int base[D];
+    for (int l = 0; l < D; ++l) base[l] = (int)floor(xi0[l] + 0.5 * (sa + sb) * dxi[l] + 0.5);
+    // NP parts of the stencil at a time, which bounds the nodes' integrals held live
+    constexpr int NP = (D == 3 ? 9 : (D == 2 ? 3 : 1)), NK = kStencil<D> / NP;
+#pragma unroll 1
+    for (int pl = 0; pl < NP; ++pl) {
+      double I0[NK], Ia[NK][D], Ib[NK][D];
+#pragma unroll
+      for (int k = 0; k < NK; ++k) {
+        I0[k] = 0.0;
+        for (int l = 0; l < D; ++l) Ia[k][l] = Ib[k][l] = 0.0;
+      }
+      for (int q = 0; q < a.ngl; ++q) {
+        const double s = sa + len * a.glx[q], wq = len * a.glw[q];
+        double xs[D];
+        for (int l = 0; l < D; ++l) xs[l] = xi0[l] + s * dxi[l];
 #pragma unroll
         for (int k = 0; k < NK; ++k) {
-          I0[k] = 0.0;
-          for (int l = 0; l < D; ++l) Ia[k][l] = Ib[k][l] = 0.0;
-        }
-        for (int q = 0; q < a.ngl; ++q) {
-          const double s = sa + len * a.glx[q], wq = len * a.glw[q];
-          double xs[D];
-          for (int l = 0; l < D; ++l) xs[l] = xi0[l] + s * dxi[l];
-          nw.at_base(M, xs, base);
+          // node offsets from the base (x at compile time; y and z depend on the part) and
+          // the node's weight and derivative per axis, evaluated at the offset itself
+          const int o[3] = {k % 3, NK >= 9 ? (k / 3) % 3 : (D == 2 ? pl : pl % 3),
+                            NK == 27 ? k / 9 : (NK == 9 ? pl : pl / 3)};
+          double wv[3], dv[3];
 #pragma unroll
-          for (int k = 0; k < NK; ++k) {
-            double S, dS[D], ddS[D][D];
-            nw.vals(k + NK * pl, S, dS, ddS);
-            I0[k] += wq * S;
-            for (int l = 0; l < D; ++l) {
-              Ia[k][l] += wq * (1.0 - s) * dS[l];
-              Ib[k][l] += wq * s * dS[l];
-            }
+          for (int l = 0; l < D; ++l) {
+            const double t = xs[l] - (double)(base[l] + o[l] - 1);
+            wv[l] = s2(t);
+            dv[l] = s2d(t) * M.inv_h[l];
+          }
+          double S = 1.0, dS[D];
+          for (int l = 0; l < D; ++l) S *= wv[l];
+          for (int j = 0; j < D; ++j) {
+            dS[j] = 1.0;
+            for (int l = 0; l < D; ++l) dS[j] *= l == j ? dv[l] : wv[l];
+          }
+          I0[k] += wq * S;
+          for (int l = 0; l < D; ++l) {
+            Ia[k][l] += wq * (1.0 - s) * dS[l];
+            Ib[k][l] += wq * s * dS[l];
           }
         }
+      }
+      // Sorted particles: the lanes of a wave fall in a few groups that share their base
+      // node, and a group whose part nodes lie in the window has all its entries summed
+      // over the wave at once.  Lanes left over put each entry on their own.
+      bool pend = has;
+#pragma unroll 1
+      for (int grp = 0; grp < (D < 3 ? 4 : 0); ++grp) {
+        const uint64_t pm = __ballot(pend);
+        if (pm == 0) break;
+        const int lead = __ffsll((long long)pm) - 1;
+        int bl[D];
+        bool mine = pend;
+        for (int l = 0; l < D; ++l) {
+          bl[l] = __builtin_amdgcn_readlane(base[l] + sh[l], lead);
+          mine = mine && base[l] + sh[l] == bl[l];
+        }
+        bool inwin = true;
 #pragma unroll
         for (int k = 0; k < NK; ++k) {
           int node[D];
-          for (int l = 0; l < D; ++l) node[l] = nw.unode(l, k + NK * pl);
-          for (int l = 0; l < D; ++l) w.put(l, node, I0[k] * g[l]);
-          for (int c = 0; c < 3; ++c) {
-            double va = 0.0, vb = 0.0;
-            for (int l = 0; l < D; ++l) {
-              va += Ia[k][l] * g[D + c * D + l];
-              vb += Ib[k][l] * g[D + c * D + l];
-            }
-            w.put(D + c, node, va);
-            w.put(D + 3 + c, node, vb);
+          for (int l = 0; l < D; ++l) node[l] = bl[l] + NodeWeights<D>::off(l, k + NK * pl) - 1;
+          inwin = inwin && w.rel(node) >= 0;
+        }
+        if (!inwin) break;
+        // entry e = k NV + f: I0_k g_f (f < D), then the A^n and A^{n+1} integrals
+        w.template put_all<NK * NV>(
+            [&](int e) -> double {
+              const int k = e / NV, f = e % NV;
+              if (!mine) return 0.0;
+              if (f < D) return I0[k] * g[f];
+              const int c = f < D + 3 ? f - D : f - D - 3;
+              double v = 0.0;
+              for (int l = 0; l < D; ++l) v += (f < D + 3 ? Ia[k][l] : Ib[k][l]) * g[D + c * D + l];
+              return v;
+            },
+            [&](int e) -> int {
+              const int k = e / NV, f = e % NV;
+              int node[D];
+              for (int l = 0; l < D; ++l) node[l] = bl[l] + NodeWeights<D>::off(l, k + NK * pl) - 1;
+              return f * kWinNodes<D> + w.rel(node);
+            },
+            lane);
+        pend = pend && !mine;
+      }
+      if (__ballot(pend) == 0) continue;
+#pragma unroll
+      for (int k = 0; k < NK; ++k) {
+        int node[D];
+        for (int l = 0; l < D; ++l) node[l] = base[l] + NodeWeights<D>::off(l, k + NK * pl) - 1 + sh[l];
+        const int r = w.rel(node);
+        for (int l = 0; l < D; ++l) w.put_wave(l, r, node, pend ? I0[k] * g[l] : 0.0, lane);
+        for (int c = 0; c < 3; ++c) {
+          double va = 0.0, vb = 0.0;
+          for (int l = 0; l < D; ++l) {
+            va += Ia[k][l] * g[D + c * D + l];
+            vb += Ib[k][l] * g[D + c * D + l];
           }
+          w.put_wave(D + c, r, node, pend ? va : 0.0, lane);
+          w.put_wave(D + 3 + c, r, node, pend ? vb : 0.0, lane);
         }
       }
-    });
-    for (int e = 0; e < 2; ++e) {
-      double xs[D];
-      for (int l = 0; l < D; ++l) xs[l] = xi0[l] + (e ? dxi[l] : 0.0);
-      nw.at(M, xs);
-    #pragma unroll
-    for (int k = 0; k < kStencil<D>; ++k) {
-        double S, dS[D], ddS[D][D];
-        nw.vals(k, S, dS, ddS);
-        int node[D];
-        for (int l = 0; l < D; ++l) node[l] = nw.unode(l, k);
-        for (int c = 0; c < 3; ++c) w.put((e ? D + 3 : D) + c, node, S * g[4 * D + (e ? 3 : 0) + c]);
+    }
+    sw.advance(xi0, dxi);
+  }
+  // the endpoint interpolants A^- (at x) and A^+ (at x + dt vbar)
+#pragma unroll 1
+  for (int e = 0; e < 2; ++e) {
+    double xs[D], ge[3];
+    int b[D];
+    for (int l = 0; l < D; ++l) {
+      xs[l] = xi0[l] + (e ? dxi[l] : 0.0);
+      b[l] = (int)floor(xs[l] + 0.5);
+    }
+    for (int c = 0; c < 3; ++c) ge[c] = live ? (e ? g[4 * D + 3 + c] : g[4 * D + c]) : 0.0;
+    if (__ballot(live) == 0) break;
+    // the stencil weights per axis; entry e = 3 k + c holds S_k ge_c
+    double ax[D][3];
+    for (int l = 0; l < D; ++l)
+      for (int o = 0; o < 3; ++o) ax[l][o] = s2(xs[l] - (double)(b[l] + o - 1));
+    bool pend = live;
+#pragma unroll 1
+    for (int grp = 0; grp < (D < 3 ? 4 : 0); ++grp) {
+      const uint64_t pm = __ballot(pend);
+      if (pm == 0) break;
+      const int lead = __ffsll((long long)pm) - 1;
+      int bl[D], lo[D], hi[D];
+      bool mine = pend;
+      for (int l = 0; l < D; ++l) {
+        bl[l] = __builtin_amdgcn_readlane(b[l] + sh[l], lead);
+        mine = mine && b[l] + sh[l] == bl[l];
+        lo[l] = bl[l] - 1;
+        hi[l] = bl[l] + 1;
       }
+      if (w.rel(lo) < 0 || w.rel(hi) < 0) break;
+      w.template put_all<3 * kStencil<D>>(
+          [&](int en) -> double {
+            const int k = en / 3, c = en % 3;
+            double S = 1.0;
+            for (int l = 0; l < D; ++l) S *= ax[l][NodeWeights<D>::off(l, k)];
+            return mine ? S * ge[c] : 0.0;
+          },
+          [&](int en) -> int {
+            const int k = en / 3, c = en % 3;
+            int node[D];
+            for (int l = 0; l < D; ++l) node[l] = bl[l] + NodeWeights<D>::off(l, k) - 1;
+            return ((e ? D + 3 : D) + c) * kWinNodes<D> + w.rel(node);
+          },
+          lane);
+      pend = pend && !mine;
+    }
+    if (__ballot(pend) == 0) continue;
+#pragma unroll 1
+    for (int k = 0; k < kStencil<D>; ++k) {
+      int node[D];
+      double S = 1.0;
+#pragma unroll
+      for (int l = 0; l < D; ++l) {
+        node[l] = b[l] + NodeWeights<D>::off(l, k) - 1;
+        S *= s2(xs[l] - (double)node[l]);
+        node[l] += sh[l];
+      }
+      const int r = w.rel(node);
+      for (int c = 0; c < 3; ++c) w.put_wave((e ? D + 3 : D) + c, r, node, pend ? S * ge[c] : 0.0, lane);
     }
   }
   __syncthreads();
