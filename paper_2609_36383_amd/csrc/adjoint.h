@@ -48,7 +48,7 @@ struct AdjArgs {
   double* partials;      // ADJ_BOUND: per-block sums of the scatter bound
   unsigned long long* acc;  // ADJ_SCATTER: [dim + 6][Ng] fixed-point pairs
   double fx_up;
-  double* cache;         // [adj_ncache(dim)][ps]: written by ADJ_PREP, read by ADJ_BOUND / ADJ_SCATTER
+  double* cache;         // [adj_ncache(dim)][ps]: written by ADJ_PREP, read by ADJ_BOUND, ADJ_SCATTER, ADJ_FINAL
   double* gx;            // ADJ_FINAL outputs, load order
   double* gP;
   double* gq;

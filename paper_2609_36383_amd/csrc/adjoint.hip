@@ -733,7 +733,8 @@ __device__ __forceinline__ void gather_mu(const AdjArgs& a, const double xi0[D],
   });
 }
 
-// ADJ_PREP and ADJ_FINAL: the full reverse sweep of one particle's evaluation.
+// ADJ_PREP: the reverse sweeps of one particle's evaluation for the unit cotangents and lP;
+// ADJ_FINAL: the sweep for the converged (mu_v, lP), which gives the input cotangents.
 template <int D>
 __global__ __launch_bounds__(kBlock) void k_adj_particle(AdjArgs a) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -757,23 +758,28 @@ __global__ __launch_bounds__(kBlock) void k_adj_particle(AdjArgs a) {
   Fwd<D> f;
   forward<D>(G, P, q, m, v, a.dt, a.kappa, f);
   Rev<D> r;
-  // the nonzero columns j < D of dF/dvbar
-  double J[3][D];
-  for (int c = 0; c < 3; ++c) {
-    const double e[3] = {c == 0 ? 1.0 : 0.0, c == 1 ? 1.0 : 0.0, c == 2 ? 1.0 : 0.0}, z[3] = {0.0, 0.0, 0.0};
-    reverse<D>(f, e, z, r);
-    for (int j = 0; j < D; ++j) J[c][j] = rev_v<D>(r, G, a.dt, j);
-    if (a.mode == ADJ_PREP) {
+  // the nonzero columns j < D of dF/dvbar, and the part of the right side that does not
+  // depend on the adjoint current; the final sweep reads both back from the cache the
+  // preparing sweep of the same step wrote
+  double J[3][D], base[D];
+  if (a.mode == ADJ_FINAL) {
+    for (int c = 0; c < 3; ++c)
+      for (int j = 0; j < D; ++j) J[c][j] = a.cache[(c * D + j) * a.ps + i];
+    for (int j = 0; j < D; ++j) base[j] = a.cache[(3 * D + j) * a.ps + i];
+  } else {
+    for (int c = 0; c < 3; ++c) {
+      const double e[3] = {c == 0 ? 1.0 : 0.0, c == 1 ? 1.0 : 0.0, c == 2 ? 1.0 : 0.0}, z[3] = {0.0, 0.0, 0.0};
+      reverse<D>(f, e, z, r);
+      for (int j = 0; j < D; ++j) J[c][j] = rev_v<D>(r, G, a.dt, j);
       double g[NG];
       rev_gath<D>(r, g);
       for (int k = 0; k < NG; ++k) a.cache[(4 * D + c * NG + k) * a.ps + i] = g[k];
     }
+    // right side: x^{n+1} = x + dt vbar, P^{n+1}(vbar), and the transposed deposit
+    const double z3[3] = {0.0, 0.0, 0.0};
+    reverse<D>(f, z3, lP, r);
+    for (int j = 0; j < D; ++j) base[j] = a.dt * lx[j] + rev_v<D>(r, G, a.dt, j);
   }
-  // right side: x^{n+1} = x + dt vbar, P^{n+1}(vbar), and the transposed deposit
-  const double z3[3] = {0.0, 0.0, 0.0};
-  reverse<D>(f, z3, lP, r);
-  double base[D];
-  for (int j = 0; j < D; ++j) base[j] = a.dt * lx[j] + rev_v<D>(r, G, a.dt, j);
   if (a.mode == ADJ_PREP) {
     double g[NG];
     rev_gath<D>(r, g);
