@@ -44,16 +44,19 @@ namespace {
 constexpr int kHalo = 1;               // tile halo in nodes (the stencil reach)
 // LDS per workgroup for the field and current tiles.  A one-wave workgroup of sorted
 // particles spans one or two cells; the budgets let eight workgroups share a CU's
-// 160 KB in every dimension (3D: a 6 x 5 x 5 box of 12 FP64 values per node).
+// 160 KB in every dimension, with the park block below where there is one (3D: a
+// 5 x 5 x 5 box of 12 FP64 values per node; a larger box takes the global path).
 template <int D>
-constexpr int tile_bytes() { return D == 3 ? 18 * 1024 : 8 * 1024; }
+constexpr int tile_bytes() { return D == 3 ? 16 * 1024 : 8 * 1024; }
 
-// FP64 2D quadratic at its default Gauss order keeps the row-independent quadrature
-// values of each segment (Gauss point offsets and factors, hence its x weights) across
-// the stencil rows; the particle constants then wait in LDS (PARK) instead of registers.
+// The particle constants wait in LDS (PARK) instead of registers across the segment
+// quadrature where registers are short: FP64 2D quadratic at its default Gauss order,
+// which keeps the row-independent quadrature values of each segment (Gauss point offsets
+// and factors, hence its x weights) across the stencil rows, and FP64 3D quadratic at its
+// default order, whose 27-node quadrature otherwise spills.
 template <int D, int SH, int NGL, class R>
 constexpr bool orbit_park() {
-  return D == 2 && SH == 2 && NGL == 3 && sizeof(R) == 8;
+  return SH == 2 && sizeof(R) == 8 && ((D == 2 && NGL == 3) || (D == 3 && NGL == 4));
 }
 
 // i mod n for a mesh size n (a power of two; two's complement makes this the
@@ -388,7 +391,7 @@ __device__ __forceinline__ void eval_segment(const OrbitArgs& a, const Tile& t, 
   constexpr int kRowUnroll = (D < 3 && NGL > 0) ? NROW : 1;
   // FP64 2D has registers for the row-independent quadrature factors w_q, w_q (1 - s_q)
   // and w_q s_q of its unrolled rows; elsewhere they are recomputed per row
-  constexpr bool kHoist = orbit_park<D, SH, NGL, R>();
+  constexpr bool kHoist = D == 2 && orbit_park<D, SH, NGL, R>();
   constexpr int NH = kHoist ? NGL : 1;
   R hw[NH], ha[NH], hb[NH], hx[NH], hy[NH];
   if (kHoist) {
