@@ -32,6 +32,8 @@
 #include <limits.h>
 #include <math.h>
 
+#include <type_traits>
+
 #include "adjoint.h"
 #include "gmhc_internal.h"
 
@@ -574,46 +576,62 @@ __device__ __forceinline__ long long wave_sum_i64(long long x) {
   return swap_i64<false>(x);  // lane ^ 32
 }
 
-// Reduce-scatter of 32 64-bit integers per lane over the wave (all lanes active): after
-// it, lane l holds the wave total of value slot32(l), and the lanes with l even hold one
-// copy of each of the 32 totals.  Each step halves the values a lane holds: it keeps one
-// half and adds its partner's copy of that half (partners lane ^ 32 and lane ^ 16 by the
-// row swaps, lane ^ 8, lane ^ 7 and lane ^ 2 by DPP); the last step adds the lane ^ 1
-// partner's copy of the one value left.  The six partners span the wave.
-template <bool ROW16>
-__device__ __forceinline__ long long swap2_i64(long long A, long long B) {
+// Reduce-scatter of 32 64-bit values (integers or FP64) per lane over the wave (all lanes
+// active): after it, lane l holds the wave total of value slot32(l), and the lanes with l
+// even hold one copy of each of the 32 totals.  Each step halves the values a lane holds:
+// it keeps one half and adds its partner's copy of that half (partners lane ^ 32 and
+// lane ^ 16 by the row swaps, lane ^ 8, lane ^ 7 and lane ^ 2 by DPP); the last step adds
+// the lane ^ 1 partner's copy of the one value left.  The six partners span the wave, and
+// the order of the additions is fixed, so FP64 totals are the same on every run.
+__device__ __forceinline__ uint64_t bits64(long long x) { return (uint64_t)x; }
+__device__ __forceinline__ uint64_t bits64(double x) { return (uint64_t)__double_as_longlong(x); }
+template <class T>
+__device__ __forceinline__ T from64(uint64_t u) {
+  if constexpr (std::is_floating_point<T>::value) return __longlong_as_double((long long)u);
+  else return (T)u;
+}
+template <bool ROW16, class T>
+__device__ __forceinline__ T swap2(T A, T B) {
   // the lower rows of the swap keep A and receive the partner's A, the upper rows keep B
   // and receive the partner's B
-  const uint64_t a = (uint64_t)A, b = (uint64_t)B;
+  const uint64_t a = bits64(A), b = bits64(B);
   const uint32_t alo = (uint32_t)a, ahi = (uint32_t)(a >> 32), blo = (uint32_t)b, bhi = (uint32_t)(b >> 32);
   if (ROW16) {
     const auto l = __builtin_amdgcn_permlane16_swap(alo, blo, false, false);
     const auto h = __builtin_amdgcn_permlane16_swap(ahi, bhi, false, false);
-    return (long long)((((uint64_t)h[0] << 32) | l[0]) + (((uint64_t)h[1] << 32) | l[1]));
+    return from64<T>(((uint64_t)h[0] << 32) | l[0]) + from64<T>(((uint64_t)h[1] << 32) | l[1]);
   } else {
     const auto l = __builtin_amdgcn_permlane32_swap(alo, blo, false, false);
     const auto h = __builtin_amdgcn_permlane32_swap(ahi, bhi, false, false);
-    return (long long)((((uint64_t)h[0] << 32) | l[0]) + (((uint64_t)h[1] << 32) | l[1]));
+    return from64<T>(((uint64_t)h[0] << 32) | l[0]) + from64<T>(((uint64_t)h[1] << 32) | l[1]);
   }
 }
-template <int H, int CTRL>
-__device__ __forceinline__ void dpp_half_i64(long long* v, bool up) {
+template <int CTRL, class T>
+__device__ __forceinline__ T dpp64(T x) {
+  const uint64_t u = bits64(x);
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_mov_dpp((int)(uint32_t)u, CTRL, 0xF, 0xF, false);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_mov_dpp((int)(uint32_t)(u >> 32), CTRL, 0xF, 0xF, false);
+  return from64<T>(((uint64_t)hi << 32) | lo);
+}
+template <int H, int CTRL, class T>
+__device__ __forceinline__ void dpp_half(T* v, bool up) {
 #pragma unroll
   for (int j = 0; j < H; ++j) {
-    const long long send = up ? v[j] : v[j + H];
-    const long long keep = up ? v[j + H] : v[j];
-    v[j] = keep + dpp_i64<CTRL>(send);
+    const T send = up ? v[j] : v[j + H];
+    const T keep = up ? v[j + H] : v[j];
+    v[j] = keep + dpp64<CTRL>(send);
   }
 }
-__device__ __forceinline__ long long rs32_i64(long long (&v)[32], int lane) {
+template <class T>
+__device__ __forceinline__ T rs32(T (&v)[32], int lane) {
 #pragma unroll
-  for (int j = 0; j < 16; ++j) v[j] = swap2_i64<false>(v[j], v[j + 16]);
+  for (int j = 0; j < 16; ++j) v[j] = swap2<false>(v[j], v[j + 16]);
 #pragma unroll
-  for (int j = 0; j < 8; ++j) v[j] = swap2_i64<true>(v[j], v[j + 8]);
-  dpp_half_i64<4, 0x128>(v, (lane & 8) != 0);  // row_ror:8
-  dpp_half_i64<2, 0x141>(v, (lane & 4) != 0);  // row_half_mirror
-  dpp_half_i64<1, 0x4E>(v, (lane & 2) != 0);   // quad_perm [2, 3, 0, 1]
-  return v[0] + dpp_i64<0xB1>(v[0]);           // quad_perm [1, 0, 3, 2]
+  for (int j = 0; j < 8; ++j) v[j] = swap2<true>(v[j], v[j + 8]);
+  dpp_half<4, 0x128>(v, (lane & 8) != 0);  // row_ror:8
+  dpp_half<2, 0x141>(v, (lane & 4) != 0);  // row_half_mirror
+  dpp_half<1, 0x4E>(v, (lane & 2) != 0);   // quad_perm [2, 3, 0, 1]
+  return v[0] + dpp64<0xB1>(v[0]);         // quad_perm [1, 0, 3, 2]
 }
 __device__ __forceinline__ int slot32(int lane) {
   return 16 * ((lane >> 5) & 1) + 8 * ((lane >> 4) & 1) + 4 * ((lane >> 3) & 1) + 2 * ((lane >> 2) & 1) +
@@ -642,24 +660,26 @@ struct WinAcc {
   // The put of NE entries by a whole wave whose lanes all target the same window nodes
   // (every lane active; a lane without a value passes zeros): entry e has the value
   // val(e) on each lane and the window entry ent(e) (field * window nodes + node, the
-  // same on every lane).  The limbs are summed over the wave by reduce-scatters of 16
-  // entries at a time, and the lane holding a total adds it: one LDS atomic per entry
-  // and limb instead of one per lane.
+  // same on every lane).  The values are summed over the wave in FP64 by reduce-scatters
+  // of 32 entries at a time (a fixed order of additions), and the lane holding a total
+  // splits it into limbs and adds them: one LDS atomic per entry and limb instead of one
+  // per lane, and one split per entry instead of one per lane.
   template <int NE, class Val, class Ent>
   __device__ __forceinline__ void put_all(Val&& val, Ent&& ent, int lane) const {
 #pragma unroll
-    for (int c0 = 0; c0 < NE; c0 += 16) {
-      long long v[32];
+    for (int c0 = 0; c0 < NE; c0 += 32) {
+      double v[32];
 #pragma unroll
-      for (int i = 0; i < 16; ++i) {
-        long long H = 0, L = 0;
-        if (c0 + i < NE) fix_split(val(c0 + i), up, H, L);
-        v[2 * i] = H;
-        v[2 * i + 1] = L;
+      for (int i = 0; i < 32; ++i) v[i] = c0 + i < NE ? val(c0 + i) : 0.0;
+      const double tot = rs32(v, lane);
+      const int e = c0 + slot32(lane);
+      if ((lane & 1) == 0 && e < NE && tot != 0.0) {
+        long long H, L;
+        fix_split(tot, up, H, L);
+        const int k = 2 * ent(e);
+        if (H) atomicAdd(s + k, (unsigned long long)H);
+        if (L) atomicAdd(s + k + 1, (unsigned long long)L);
       }
-      const long long tot = rs32_i64(v, lane);
-      const int slot = slot32(lane), e = c0 + slot / 2;
-      if ((lane & 1) == 0 && e < NE && tot != 0) atomicAdd(s + 2 * ent(e) + (slot & 1), (unsigned long long)tot);
     }
   }
   // The put of a whole wave (every lane active; a lane without a value passes v = 0).
