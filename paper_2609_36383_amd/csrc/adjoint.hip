@@ -25,9 +25,10 @@
 // orbit gathers, the GM-HC push with its gamma_HC, B_eff and K chain, the secant
 // velocity and the orbit deposit), k_adj_iter (one transposed outer iteration per launch
 // from the values k_adj_particle cached: the transposed deposit, the per-particle solve
-// and the scatter of the field cotangents as exact fixed-point sums), k_adj_field (one thread per Fourier mode; the conjugate transpose of
-// the projected continuity / CN update), k_energy_grad and k_adj_init_field, and small
-// reductions.
+// and the scatter of the field cotangents, summed in a fixed order within each wave and
+// as exact fixed-point sums across waves), k_adj_field (one thread per Fourier mode; the
+// conjugate transpose of the projected continuity / CN update), k_energy_grad and
+// k_adj_init_field, and small reductions.
 #include <hip/hip_runtime.h>
 #include <limits.h>
 #include <math.h>
