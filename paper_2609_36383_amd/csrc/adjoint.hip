@@ -955,11 +955,12 @@ __global__ __launch_bounds__(kBlock) void k_adj_iter(AdjArgs a) {
         }
       }
       // Sorted particles: the lanes of a wave fall in a few groups that share their base
-      // node, and a group whose part nodes lie in the window has all its entries summed
-      // over the wave at once.  Lanes left over put each entry on their own.
+      // node (one to three in 2D, three or four in 3D at 20 particles per cell), and a
+      // group whose part nodes lie in the window has all its entries summed over the wave
+      // at once.  Lanes left over put each entry on their own.
       bool pend = has;
 #pragma unroll 1
-      for (int grp = 0; grp < (D < 3 ? 4 : 0); ++grp) {
+      for (int grp = 0; grp < 8; ++grp) {
         const uint64_t pm = __ballot(pend);
         if (pm == 0) break;
         const int lead = __ffsll((long long)pm) - 1;
@@ -1032,6 +1033,8 @@ __global__ __launch_bounds__(kBlock) void k_adj_iter(AdjArgs a) {
     double ax[D][3];
     for (int l = 0; l < D; ++l)
       for (int o = 0; o < 3; ++o) ax[l][o] = s2(xs[l] - (double)(b[l] + o - 1));
+    // the groups of lanes sharing their nearest node, as for the segments (in 3D the
+    // 81 entries of a group cost more than putting each value on its own: measured)
     bool pend = live;
 #pragma unroll 1
     for (int grp = 0; grp < (D < 3 ? 4 : 0); ++grp) {
