@@ -205,7 +205,7 @@ struct SegWalk {
   }
 };
 
-template <int D>
+template <int D, bool MU>
 __device__ void gather(const AdjArgs& a, const double x[D], const double v[3], Gath<D>& G) {
   const Mesh& M = a.M;
   const int64_t Ng = M.Ng;
@@ -243,16 +243,17 @@ __device__ void gather(const AdjArgs& a, const double x[D], const double v[3], G
             G.D_dx[c][l][j] += wq * s * ddS[l][j] * As;
           }
         }
-        if (a.mu) {
+        if (MU) {
           const double m = a.mu[c * Ng + g];
           G.Mc[c] += wq * S * m;
           vm += v[c] * m;
         }
       }
-      for (int j = 0; j < D; ++j) {
-        G.Mx[j] += wq * dS[j] * vm;
-        G.Mdx[j] += wq * s * dS[j] * vm;
-      }
+      if (MU)
+        for (int j = 0; j < D; ++j) {
+          G.Mx[j] += wq * dS[j] * vm;
+          G.Mdx[j] += wq * s * dS[j] * vm;
+        }
     }
   });
   // endpoint interpolants A^n(x) and A^{n+1}(x + dx)
@@ -756,7 +757,7 @@ __device__ __forceinline__ void gather_mu(const AdjArgs& a, const double xi0[D],
 
 // ADJ_PREP: the reverse sweeps of one particle's evaluation for the unit cotangents and lP;
 // ADJ_FINAL: the sweep for the converged (mu_v, lP), which gives the input cotangents.
-template <int D>
+template <int D, bool FINAL>
 __global__ __launch_bounds__(kBlock) void k_adj_particle(AdjArgs a) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= a.np) return;
@@ -775,7 +776,7 @@ __global__ __launch_bounds__(kBlock) void k_adj_particle(AdjArgs a) {
     lP[c] = a.lP[c * a.np + li];
   }
   Gath<D> G;
-  gather<D>(a, x, v, G);
+  gather<D, FINAL>(a, x, v, G);
   Fwd<D> f;
   forward<D>(G, P, q, m, v, a.dt, a.kappa, f);
   Rev<D> r;
@@ -783,7 +784,7 @@ __global__ __launch_bounds__(kBlock) void k_adj_particle(AdjArgs a) {
   // depend on the adjoint current; the final sweep reads both back from the cache the
   // preparing sweep of the same step wrote
   double J[3][D], base[D];
-  if (a.mode == ADJ_FINAL) {
+  if (FINAL) {
     for (int c = 0; c < 3; ++c)
       for (int j = 0; j < D; ++j) J[c][j] = a.cache[(c * D + j) * a.ps + i];
     for (int j = 0; j < D; ++j) base[j] = a.cache[(3 * D + j) * a.ps + i];
@@ -801,7 +802,7 @@ __global__ __launch_bounds__(kBlock) void k_adj_particle(AdjArgs a) {
     reverse<D>(f, z3, lP, r);
     for (int j = 0; j < D; ++j) base[j] = a.dt * lx[j] + rev_v<D>(r, G, a.dt, j);
   }
-  if (a.mode == ADJ_PREP) {
+  if (!FINAL) {
     double g[NG];
     rev_gath<D>(r, g);
     for (int k = 0; k < NG; ++k) a.cache[(4 * D + 3 * NG + k) * a.ps + i] = g[k];
@@ -1346,14 +1347,22 @@ namespace {
 inline unsigned nblocks(int64_t n) { return (unsigned)std::max<int64_t>((n + kBlock - 1) / kBlock, 1); }
 }  // namespace
 
+template <int D>
+void launch_adj_particle_d(const AdjArgs& a, hipStream_t s) {
+  if (a.mode == ADJ_FINAL)
+    hipLaunchKernelGGL((k_adj_particle<D, true>), dim3(nblocks(a.np)), dim3(kBlock), 0, s, a);
+  else
+    hipLaunchKernelGGL((k_adj_particle<D, false>), dim3(nblocks(a.np)), dim3(kBlock), 0, s, a);
+}
 hipError_t launch_adj_particle(const AdjArgs& a, hipStream_t s) {
   if (a.np == 0) return hipSuccess;
+  if (a.mode != ADJ_PREP && a.mode != ADJ_FINAL) return hipErrorInvalidValue;
   if (a.M.d == 1)
-    hipLaunchKernelGGL(k_adj_particle<1>, dim3(nblocks(a.np)), dim3(kBlock), 0, s, a);
+    launch_adj_particle_d<1>(a, s);
   else if (a.M.d == 2)
-    hipLaunchKernelGGL(k_adj_particle<2>, dim3(nblocks(a.np)), dim3(kBlock), 0, s, a);
+    launch_adj_particle_d<2>(a, s);
   else
-    hipLaunchKernelGGL(k_adj_particle<3>, dim3(nblocks(a.np)), dim3(kBlock), 0, s, a);
+    launch_adj_particle_d<3>(a, s);
   return hipGetLastError();
 }
 hipError_t launch_adj_iter(const AdjArgs& a, hipStream_t s) {
