@@ -371,7 +371,7 @@ class OracleSim:
 
 
 def tangent_run(cfg, x, u, q, steps, dx=None, du=None, dq=None):
-    """Forward-mode derivatives of a 1D or 2D run (gmhc_tangent.cpp): from the initial
+    """Forward-mode derivatives of a 1D, 2D or 3D run (gmhc_tangent.cpp): from the initial
     particles x [dim][N], u [3][N], q [N] and the seed directions dx [nd][dim][N],
     du [nd][3][N], dq [nd][N] (None: zero; nd <= 16), run ``steps`` steps.  Returns (E, dE, outer): E = (W0, K0, WT,
     KT), the field and kinetic energies at the start and at the end, dE [4][nd] their

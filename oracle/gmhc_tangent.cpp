@@ -1,5 +1,5 @@
-// gmhc_tangent.cpp -- forward-mode derivatives (the tangent-linear model) of a 1D
-// GM-HC-CN run (1D, 2D or 3D) of the CPU oracle.
+// gmhc_tangent.cpp -- forward-mode derivatives (the tangent-linear model) of a GM-HC-CN
+// run (1D, 2D or 3D) of the CPU oracle.
 //
 // TEST INFRASTRUCTURE ONLY, like gmhc_oracle.cpp: the independent reference for the
 // GPU library's reverse-mode adjoint.  The paper defines no derivative of its step;
