@@ -757,8 +757,11 @@ __device__ __forceinline__ void gather_mu(const AdjArgs& a, const double xi0[D],
 
 // ADJ_PREP: the reverse sweeps of one particle's evaluation for the unit cotangents and lP;
 // ADJ_FINAL: the sweep for the converged (mu_v, lP), which gives the input cotangents.
+// Occupancy target by measurement: two waves per SIMD in 1D (the final sweep then spills
+// 60 B per lane), the register file of one wave in 2D and 3D.
 template <int D, bool FINAL>
-__global__ __launch_bounds__(kBlock) void k_adj_particle(AdjArgs a) {
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(D == 1 ? 2 : 1))) void k_adj_particle(
+    AdjArgs a) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= a.np) return;
   const Mesh& M = a.M;
