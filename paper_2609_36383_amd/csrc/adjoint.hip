@@ -828,9 +828,10 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(D == 1 ?
 // ADJ_BOUND and ADJ_SCATTER: one transposed outer iteration from the cached values.  The
 // reverse sweep is linear in its cotangents, so the gather cotangents for (mu_v, lP) are
 // sum_c mu_v,c (those of e_c) + (those of lP).  Occupancy target by measurement: three
-// waves per SIMD in 2D (68 B of spill per lane, 5% faster than two).
+// waves per SIMD in 2D and 3D (68 and 240 B of spill per lane; 5% and 7% faster than
+// two), and 1D's own three (four was slower).
 template <int D>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(D == 2 ? 3 : 1))) void k_adj_iter(
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(D == 1 ? 1 : 3))) void k_adj_iter(
     AdjArgs a) {
   constexpr int NG = adj_ngath(D);
   constexpr int NV = D + 6;
