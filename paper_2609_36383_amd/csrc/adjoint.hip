@@ -1310,10 +1310,13 @@ __global__ __launch_bounds__(kBlock) void k_adj_init_particle(AdjInitArgs a) {
 // Settle test of the adjoint current: out[0] = max |new - old|, out[1] = max |new| over
 // n values (one workgroup), and old <- old + beta (new - old).
 __global__ __launch_bounds__(kBlock) void k_adj_update(double* mu, const double* mnew, int64_t n, double beta,
-                                                       double* out) {
+                                                       unsigned long long* out) {
+  // mu += beta (mnew - mu), and max |mnew - mu| and max |mnew| into out[0], out[1]: each
+  // block reduces its share, then an integer atomic max of the bit patterns (non-negative
+  // doubles order as their bits; a maximum does not depend on the order of arrival)
   __shared__ double r0[kBlock], r1[kBlock];
   double dm = 0.0, mm = 0.0;
-  for (int64_t i = threadIdx.x; i < n; i += kBlock) {
+  for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock) {
     const double d = mnew[i] - mu[i];
     dm = fmax(dm, fabs(d));
     mm = fmax(mm, fabs(mnew[i]));
@@ -1330,9 +1333,12 @@ __global__ __launch_bounds__(kBlock) void k_adj_update(double* mu, const double*
     __syncthreads();
   }
   if (threadIdx.x == 0) {
-    out[0] = r0[0];
-    out[1] = r1[0];
+    atomicMax(out, (unsigned long long)__double_as_longlong(r0[0]));
+    atomicMax(out + 1, (unsigned long long)__double_as_longlong(r1[0]));
   }
+}
+__global__ void k_adj_update_init(unsigned long long* out) {
+  if (threadIdx.x < 2) out[threadIdx.x] = 0ull;
 }
 
 // Fixed-order sum of n per-block values (one workgroup).
@@ -1407,7 +1413,10 @@ hipError_t launch_adj_init_particle(const AdjInitArgs& a, hipStream_t s) {
   return hipGetLastError();
 }
 hipError_t launch_adj_update(double* mu, const double* mnew, int64_t n, double beta, double* out, hipStream_t s) {
-  hipLaunchKernelGGL(k_adj_update, dim3(1), dim3(kBlock), 0, s, mu, mnew, n, beta, out);
+  unsigned long long* o = reinterpret_cast<unsigned long long*>(out);
+  hipLaunchKernelGGL(k_adj_update_init, dim3(1), dim3(64), 0, s, o);
+  const unsigned blocks = (unsigned)std::min<int64_t>((n + kBlock - 1) / kBlock, 512);
+  hipLaunchKernelGGL(k_adj_update, dim3(std::max(blocks, 1u)), dim3(kBlock), 0, s, mu, mnew, n, beta, o);
   return hipGetLastError();
 }
 hipError_t launch_adj_sum(const double* p, int64_t n, double* out, hipStream_t s) {
