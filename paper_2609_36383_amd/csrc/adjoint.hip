@@ -825,19 +825,19 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(D == 1 ?
   a.gq[li] = r.q + (q < 0.0 ? -r.m : r.m) + dot3(v, G.Mc) / M.dV;
 }
 
-// ADJ_BOUND and ADJ_SCATTER: one transposed outer iteration from the cached values.  The
-// reverse sweep is linear in its cotangents, so the gather cotangents for (mu_v, lP) are
-// sum_c mu_v,c (those of e_c) + (those of lP).  Occupancy target by measurement: three
-// waves per SIMD in 2D and 3D (68 and 240 B of spill per lane; 5% and 7% faster than
-// two), and 1D's own three (four was slower).
-template <int D>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(D == 1 ? 1 : 3))) void k_adj_iter(
+// ADJ_BOUND (SCAT false) and ADJ_SCATTER (SCAT true): one transposed outer iteration from
+// the cached values.  The reverse sweep is linear in its cotangents, so the gather
+// cotangents for (mu_v, lP) are sum_c mu_v,c (those of e_c) + (those of lP).  The two
+// modes are separate instantiations, so the bound pass carries none of the scatter's
+// registers or LDS.  Occupancy target of the scatter by measurement: three waves per SIMD
+// in 2D and 3D (68 and 240 B of spill per lane; 5% and 7% faster than two), and 1D's own
+// three (four was slower).
+template <int D, bool SCAT>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(SCAT && D > 1 ? 3 : 1))) void k_adj_iter(
     AdjArgs a) {
   constexpr int NG = adj_ngath(D);
   constexpr int NV = D + 6;
   __shared__ double red[kBlock];
-  __shared__ unsigned long long sacc[2 * NV * kWinNodes<D>];
-  __shared__ int swlo[3];
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const bool live = i < a.np;
   const Mesh& M = a.M;
@@ -870,7 +870,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(D == 1 ?
       g[k] = s;
     }
   }
-  if (a.mode == ADJ_BOUND) {  // per-block sum of the bound, fixed order
+  if (!SCAT) {  // per-block sum of the bound, fixed order
     double bound = 0.0;
     for (int l = 0; l < D; ++l) bound += fabs(g[l]);
     for (int c = 0; c < 3; ++c) {
@@ -886,6 +886,8 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(D == 1 ?
     if (threadIdx.x == 0) a.partials[blockIdx.x] = red[0];
     return;
   }
+  __shared__ unsigned long long sacc[2 * NV * kWinNodes<D>];
+  __shared__ int swlo[3];
   // The window is taken periodically: each lane's nodes are moved by whole periods to lie
   // within half a period of the block's first particle (always live), so a block whose
   // particles straddle the periodic seam (a cell-sorted block at node 0 holds particles
@@ -1377,14 +1379,22 @@ hipError_t launch_adj_particle(const AdjArgs& a, hipStream_t s) {
     launch_adj_particle_d<3>(a, s);
   return hipGetLastError();
 }
+template <int D>
+void launch_adj_iter_d(const AdjArgs& a, hipStream_t s) {
+  if (a.mode == ADJ_SCATTER)
+    hipLaunchKernelGGL((k_adj_iter<D, true>), dim3(nblocks(a.np)), dim3(kBlock), 0, s, a);
+  else
+    hipLaunchKernelGGL((k_adj_iter<D, false>), dim3(nblocks(a.np)), dim3(kBlock), 0, s, a);
+}
 hipError_t launch_adj_iter(const AdjArgs& a, hipStream_t s) {
   if (a.np == 0) return hipSuccess;
+  if (a.mode != ADJ_BOUND && a.mode != ADJ_SCATTER) return hipErrorInvalidValue;
   if (a.M.d == 1)
-    hipLaunchKernelGGL(k_adj_iter<1>, dim3(nblocks(a.np)), dim3(kBlock), 0, s, a);
+    launch_adj_iter_d<1>(a, s);
   else if (a.M.d == 2)
-    hipLaunchKernelGGL(k_adj_iter<2>, dim3(nblocks(a.np)), dim3(kBlock), 0, s, a);
+    launch_adj_iter_d<2>(a, s);
   else
-    hipLaunchKernelGGL(k_adj_iter<3>, dim3(nblocks(a.np)), dim3(kBlock), 0, s, a);
+    launch_adj_iter_d<3>(a, s);
   return hipGetLastError();
 }
 int64_t adj_particle_blocks(int64_t np) { return nblocks(np); }
