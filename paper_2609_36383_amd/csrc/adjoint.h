@@ -47,7 +47,7 @@ struct AdjArgs {
   int mode;
   double* partials;      // ADJ_BOUND: per-block sums of the scatter bound
   unsigned long long* acc;  // ADJ_SCATTER: [dim + 6][Ng] fixed-point pairs
-  double fx_up;
+  const double* fx;      // ADJ_SCATTER: the fixed-point scale (up, hi, lo) in device memory
   double* cache;         // [adj_ncache(dim)][ps]: written by ADJ_PREP, read by ADJ_BOUND, ADJ_SCATTER, ADJ_FINAL
   double* gx;            // ADJ_FINAL outputs, load order
   double* gP;
@@ -97,5 +97,10 @@ hipError_t launch_adj_init_particle(const AdjInitArgs& a, hipStream_t s);
 hipError_t launch_adj_update(double* mu, const double* mnew, int64_t n, double beta, double* out, hipStream_t s);
 // out[0] = fixed-order sum of p[0..n).
 hipError_t launch_adj_sum(const double* p, int64_t n, double* out, hipStream_t s);
+// The fixed-point scale (up, hi, lo) of sums bounded by bound[0] (fix_scale, on the device),
+// and the conversion of fixed-point pairs to doubles with a scale in device memory.
+hipError_t launch_adj_scale(const double* bound, double* fx, hipStream_t s);
+hipError_t launch_adj_fix_to_double(const unsigned long long* acc, double* out, int64_t n, const double* fx,
+                                    hipStream_t s);
 
 }  // namespace gmhc

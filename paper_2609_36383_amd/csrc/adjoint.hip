@@ -907,7 +907,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(SCAT && 
   if (live)
     for (int l = 0; l < D; ++l) atomicMin(&swlo[l], (int)floor(fmin(xi0[l], xi0[l] + dxi[l]) + 0.5) - 1 + sh[l]);
   __syncthreads();
-  WinAcc<D> w{sacc, a.acc, {swlo[0], swlo[1], swlo[2]}, &M, a.fx_up};
+  WinAcc<D> w{sacc, a.acc, {swlo[0], swlo[1], swlo[2]}, &M, a.fx[0]};
   const int lane = threadIdx.x & 63;
   // Every lane of the wave takes part (a lane with no particle, or no segment at a step,
   // puts zeros), so the puts can sum across the wave.  Within a knot-split segment the
@@ -1343,6 +1343,27 @@ __global__ void k_adj_update_init(unsigned long long* out) {
   if (threadIdx.x < 2) out[threadIdx.x] = 0ull;
 }
 
+// fix_scale on the device, so the scatter needs no round trip to the host: the exponent
+// ceil(log2 B) from frexp (B = m 2^e with m in [1/2, 1)), exact for every B.
+__global__ void k_adj_scale(const double* bound, double* fx) {
+  if (threadIdx.x != 0) return;
+  double B = bound[0];
+  if (!(B > 0.0) || !isfinite(B)) B = 1.0;
+  int e = 0;
+  const double m = frexp(B, &e);
+  const int eb = m == 0.5 ? e - 1 : e;
+  const int sc = kFixK + 61 - eb;  // B 2^(sc-K) <= 2^61
+  fx[0] = ldexp(1.0, sc - kFixK);
+  fx[1] = ldexp(1.0, kFixK - sc);
+  fx[2] = ldexp(1.0, -sc);
+}
+__global__ __launch_bounds__(kBlock) void k_adj_fix_to_double(const unsigned long long* acc, double* out, int64_t n,
+                                                              const double* fx) {
+  const double hi = fx[1], lo = fx[2];
+  for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock)
+    out[i] = fix_value(acc, i, hi, lo);
+}
+
 // Fixed-order sum of n per-block values (one workgroup).
 __global__ __launch_bounds__(kBlock) void k_adj_sum(const double* p, int64_t n, double* out) {
   __shared__ double r[kBlock];
@@ -1427,6 +1448,16 @@ hipError_t launch_adj_update(double* mu, const double* mnew, int64_t n, double b
   hipLaunchKernelGGL(k_adj_update_init, dim3(1), dim3(64), 0, s, o);
   const unsigned blocks = (unsigned)std::min<int64_t>((n + kBlock - 1) / kBlock, 512);
   hipLaunchKernelGGL(k_adj_update, dim3(std::max(blocks, 1u)), dim3(kBlock), 0, s, mu, mnew, n, beta, o);
+  return hipGetLastError();
+}
+hipError_t launch_adj_scale(const double* bound, double* fx, hipStream_t s) {
+  hipLaunchKernelGGL(k_adj_scale, dim3(1), dim3(64), 0, s, bound, fx);
+  return hipGetLastError();
+}
+hipError_t launch_adj_fix_to_double(const unsigned long long* acc, double* out, int64_t n, const double* fx,
+                                    hipStream_t s) {
+  const unsigned blocks = (unsigned)std::max<int64_t>(std::min<int64_t>((n + kBlock - 1) / kBlock, 4096), 1);
+  hipLaunchKernelGGL(k_adj_fix_to_double, dim3(blocks), dim3(kBlock), 0, s, acc, out, n, fx);
   return hipGetLastError();
 }
 hipError_t launch_adj_sum(const double* p, int64_t n, double* out, hipStream_t s) {

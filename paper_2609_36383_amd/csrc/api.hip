@@ -1866,19 +1866,17 @@ int32_t gmhc_adjoint_step(gmhc_ctx* ctx, void* scratch, size_t scratch_bytes, co
   for (int it = 0; it < ctx->cfg.max_outer && !done; ++it) {
     AdjArgs pa = adj_args(ctx, a, vbar, lx, lP);
     pa.mu = it ? a.mu : nullptr;
-    // scale of the exact fixed-point sums from a bound on every scattered value
+    // scale of the exact fixed-point sums from a bound on every scattered value, computed
+    // on the device (red[4..6]), so no host round trip sits between the two passes
     pa.mode = ADJ_BOUND;
     HIPCK(launch_adj_iter(pa, s));
     HIPCK(launch_adj_sum(a.partials, ctx->np ? nb : 0, a.red, s));
-    double B = 0.0;
-    HIPCK(hipMemcpyAsync(&B, a.red, sizeof(double), hipMemcpyDeviceToHost, s));
-    HIPCK(hipStreamSynchronize(s));
-    const FixScale fx = fix_scale(B);
+    HIPCK(launch_adj_scale(a.red, a.red + 4, s));
     HIPCK(launch_zero(reinterpret_cast<double*>(a.acc), 2 * adj_nvals(M.d) * Ng, s));
     pa.mode = ADJ_SCATTER;
-    pa.fx_up = fx.up;
+    pa.fx = a.red + 4;
     HIPCK(launch_adj_iter(pa, s));
-    HIPCK(launch_fix_to_double(a.acc, a.Pr, adj_nvals(M.d) * Ng, fx, s));
+    HIPCK(launch_adj_fix_to_double(a.acc, a.Pr, adj_nvals(M.d) * Ng, a.red + 4, s));
     HIPCK(fft_nd(M, ctx->axes, adj_nvals(M.d), a.Pr, nullptr, a.Pb, nullptr, nullptr, false, false, s));
     HIPCK(launch_adj_field(fa, s));
     HIPCK(fft_nd(M, ctx->axes, 12, nullptr, a.Lout, nullptr, a.Lreal, a.work, true, false, s));
