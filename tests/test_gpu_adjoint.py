@@ -191,11 +191,14 @@ def _torch_grads(x, u, q, cfg, steps, every):
     return float(Wt.detach()), (xt.grad.numpy(), ut.grad.numpy(), qt.grad.numpy())
 
 
-def test_adjoint_2d_per_particle_directions():
+@pytest.mark.parametrize("sort_every", [0, 1])
+def test_adjoint_2d_per_particle_directions(sort_every):
     """2D Weibel beams (16 x 16 mesh, 1024 particles, thermal spread in all three momentum
     components), 5 steps with checkpoints every 2: directional derivatives from the GPU's
     per-particle cotangents along random directions of positions (both axes), momenta and
-    charges, against the oracle's forward-mode derivatives."""
+    charges, against the oracle's forward-mode derivatives.  Sorted every step, the waves
+    hold particles of neighbouring cells (and of both sides of the periodic seam), which the
+    scatter sums by groups of lanes sharing a base node."""
     w = W.spec("weibel2d", n=(16, 16), ppc=4)
     steps, every = 5, 2
     x, u, q = W.particles(w)
@@ -204,7 +207,7 @@ def test_adjoint_2d_per_particle_directions():
     dx = 0.05 * rng.standard_normal((3, 2, n))
     du = 0.1 * rng.standard_normal((3, 3, n))
     dq = q * rng.standard_normal((3, n))
-    Wg, grads = _torch_grads(x, u, q, G.config_from_dict(W.config_dict(w)), steps, every)
+    Wg, grads = _torch_grads(x, u, q, G.config_from_dict(W.config_dict(w), sort_every=sort_every), steps, every)
     dirs = _dir_derivs(grads, (dx, du, dq))
     E, dE, _ = O.tangent_run(O.config_from_dict(W.config_dict(w), gl_order=3), x, u, q, steps, dx=dx, du=du, dq=dq)
     err = np.abs(dirs - dE[2]).max() / np.abs(dE[2]).max()
@@ -250,10 +253,12 @@ def test_adjoint_2d_full_size_central_differences():
     assert np.all(err <= 1e-6)
 
 
-def test_adjoint_3d_per_particle_directions():
+@pytest.mark.parametrize("sort_every", [0, 1])
+def test_adjoint_3d_per_particle_directions(sort_every):
     """3D Weibel beams (8^3 mesh, 1024 particles), 2 steps: directional derivatives from the
     GPU's per-particle cotangents along random directions of positions (three axes),
-    momenta and charges, against the oracle's forward-mode derivatives (GL4)."""
+    momenta and charges, against the oracle's forward-mode derivatives (GL4); unsorted and
+    sorted every step, as in 2D."""
     w = W.spec("weibel3d", n=(8, 8, 8), ppc=2)
     steps, every = 2, 1
     x, u, q = W.particles(w)
@@ -262,7 +267,7 @@ def test_adjoint_3d_per_particle_directions():
     dx = 0.05 * rng.standard_normal((3, 3, n))
     du = 0.1 * rng.standard_normal((3, 3, n))
     dq = q * rng.standard_normal((3, n))
-    Wg, grads = _torch_grads(x, u, q, G.config_from_dict(W.config_dict(w)), steps, every)
+    Wg, grads = _torch_grads(x, u, q, G.config_from_dict(W.config_dict(w), sort_every=sort_every), steps, every)
     dirs = _dir_derivs(grads, (dx, du, dq))
     E, dE, _ = O.tangent_run(O.config_from_dict(W.config_dict(w), gl_order=4), x, u, q, steps, dx=dx, du=du, dq=dq)
     err = np.abs(dirs - dE[2]).max() / np.abs(dE[2]).max()
